@@ -1,0 +1,447 @@
+/*
+ * mpd_oracle.c -- CPU oracle for the synchronous 2D message-passing automaton
+ * decoder of E. Lake, "Fast offline decoding with local message-passing
+ * automata" (arXiv:2506.03266).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain definition that the
+ * GPU path is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header, table
+ * or helper with the HIP library and includes nothing from it.
+ *
+ * Everything here follows the paper's notation and order of operations:
+ *   - qubits on the 2L^2 links of a periodic L x L square lattice, i.i.d. X
+ *     noise of strength p on every link (Sec. 2.1, Sec. 2.2, Sec. 7);
+ *   - syndrome sigma_r = -1 at a vertex touched by an odd number of flipped
+ *     links (Def. "synchronous automaton decoder");
+ *   - four message registers m^{+x}, m^{-x}, m^{+y}, m^{-y} per vertex,
+ *     updated v times per decoder step by the rule A^{(D)} of
+ *     Def. "message passing automaton, general dimensions" (Sec. 3.2), all
+ *     sites simultaneously;
+ *   - then one application of the feedback operators F^{(D)} of the same
+ *     definition, with the degeneracy-breaking argmin' of eq. (degbreak) and
+ *     the OR function of Def. "message passing automaton, 1D";
+ *   - decoding time T_dec = number of decoder steps until no anyon is left
+ *     (Def. "logical failure rate, expected decoding time, and thresholds");
+ *   - logical failure = error + correction winds a non-trivial cycle of the
+ *     torus (Sec. 7.2: either or both of the two cycles).
+ *
+ * Readings taken where the text is garbled or silent (each is listed with
+ * its justification in the design notes of the repository):
+ *   R1  C^{(a)}_r is the 3-site line through r normal to a.
+ *   R2  the "min + 1" branch of A^{(D)} takes the minimum over NONZERO
+ *       registers only (0 means "no message", Sec. 3.1).
+ *   R3  in f^a = sgn(m^{-a} - m^{+a}) an absent message (0) counts as
+ *       +infinity, i.e. an anyon moves toward the source of the smallest
+ *       message it holds, and does not move on an exact tie along that axis.
+ *   R4  only anyon sites (sigma = -1) apply feedback; f := 0 elsewhere.
+ *   R5  axis a = 1 is x (first coordinate), a = 2 is y.
+ *   R6  within one step the v message updates come first, then feedback;
+ *       sigma is fixed during the message updates.
+ *   R7  T_dec and T_max count decoder steps (feedback applications).
+ *   R8  no truncation of message values (m_max = infinity).
+ *   R9  periodic boundary conditions, L >= 3.
+ *   R10 a sample still holding anyons after T_max steps is reported as a
+ *       timeout, counted as a failure, with T_dec = T_max.
+ *   R11 failure iff either winding parity of E + C is odd.
+ *   R12 noise: Philox4x32-10 keyed by the 64-bit seed, counter = site-pair
+ *       index; word 2(i&1) drives the x-link and word 2(i&1)+1 the y-link of
+ *       site i; a link flips iff the word is below floor(p * 2^32).
+ *
+ * Site index i = y*L + x.  The x-link of site (x,y) joins (x,y) and
+ * (x+1,y); its y-link joins (x,y) and (x,y+1) (indices mod L).
+ * Register order in every array: d = 0: +x, 1: -x, 2: +y, 3: -y, i.e.
+ * (s,a) = (+1,1), (-1,1), (+1,2), (-1,2).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EBADARG -1
+#define ORC_ENOMEM -2
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10: the counter-based generator of Salmon, Moraes, Dror and    */
+/* Shaw, "Parallel random numbers: as easy as 1, 2, 3" (SC'11).  Ten rounds  */
+/* of the multiply-hi/lo S-box with the Weyl-sequence key schedule.          */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4]) {
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k[2] = {key_in[0], key_in[1]};
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k[0] += W0;
+      k[1] += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)c[0];
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    uint32_t n3 = lo0;
+    c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+  }
+  out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+/* Flip threshold: a 32-bit uniform word u flips its link iff u < thr. */
+static uint64_t orc_threshold(double p) {
+  double t = floor(p * 4294967296.0);
+  if (t < 0.0) t = 0.0;
+  if (t > 4294967296.0) t = 4294967296.0;
+  return (uint64_t)t;
+}
+
+/* i.i.d. bit-flip noise N on the 2L^2 links (R12).  ex/ey: L*L bytes. */
+int orc_noise(int L, double p, uint64_t seed, uint8_t *ex, uint8_t *ey) {
+  if (L < 3 || !(p >= 0.0 && p <= 1.0)) return ORC_EBADARG;
+  uint64_t thr = orc_threshold(p);
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  int64_t nsite = (int64_t)L * L;
+  for (int64_t i = 0; i < nsite; ++i) {
+    uint32_t ctr[4] = {(uint32_t)(i >> 1), 0u, 0u, 0u};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    int half = (int)(i & 1);
+    ex[i] = ((uint64_t)w[2 * half] < thr) ? 1 : 0;
+    ey[i] = ((uint64_t)w[2 * half + 1] < thr) ? 1 : 0;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decoder state                                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int L, v;
+  int64_t n;          /* number of sites L*L */
+  int32_t *m[4];      /* m^{sa}_r, registers after the last update */
+  int32_t *mnew[4];   /* scratch for the synchronous update */
+  int8_t *sigma;      /* +1 / -1 */
+  uint8_t *cx, *cy;   /* correction chain C (links flipped by feedback) */
+  int8_t *fx, *fy;    /* f^x_r, f^y_r of the current step */
+  uint8_t *flx, *fly; /* link exponents of the current step */
+} orc_state;
+
+static const int DIR_S[4] = {+1, -1, +1, -1};
+static const int DIR_A[4] = {1, 1, 2, 2};
+
+static int wrap(int c, int L) {
+  c %= L;
+  return c < 0 ? c + L : c;
+}
+
+static void orc_free(orc_state *st) {
+  for (int d = 0; d < 4; ++d) {
+    free(st->m[d]);
+    free(st->mnew[d]);
+  }
+  free(st->sigma); free(st->cx); free(st->cy);
+  free(st->fx); free(st->fy); free(st->flx); free(st->fly);
+  memset(st, 0, sizeof(*st));
+}
+
+static int orc_alloc(orc_state *st, int L, int v) {
+  memset(st, 0, sizeof(*st));
+  st->L = L; st->v = v; st->n = (int64_t)L * L;
+  size_t n = (size_t)st->n;
+  int ok = 1;
+  for (int d = 0; d < 4; ++d) {
+    st->m[d] = (int32_t *)calloc(n, sizeof(int32_t));
+    st->mnew[d] = (int32_t *)calloc(n, sizeof(int32_t));
+    ok = ok && st->m[d] && st->mnew[d];
+  }
+  st->sigma = (int8_t *)calloc(n, 1);
+  st->cx = (uint8_t *)calloc(n, 1); st->cy = (uint8_t *)calloc(n, 1);
+  st->fx = (int8_t *)calloc(n, 1); st->fy = (int8_t *)calloc(n, 1);
+  st->flx = (uint8_t *)calloc(n, 1); st->fly = (uint8_t *)calloc(n, 1);
+  ok = ok && st->sigma && st->cx && st->cy && st->fx && st->fy && st->flx && st->fly;
+  if (!ok) { orc_free(st); return ORC_ENOMEM; }
+  return ORC_OK;
+}
+
+/* sigma = boundary of the error chain: -1 where an odd number of the four
+ * incident links carry an error (Def. "synchronous automaton decoder"). */
+static void orc_syndrome(orc_state *st, const uint8_t *ex, const uint8_t *ey) {
+  int L = st->L;
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      int i = y * L + x;
+      int par = ex[i] ^ ex[y * L + wrap(x - 1, L)] ^ ey[i] ^ ey[wrap(y - 1, L) * L + x];
+      st->sigma[i] = par ? -1 : +1;
+    }
+}
+
+/* One application of A^{(D)}, D = 2, to every register simultaneously.
+ * For direction (s,a) the register at r reads the line C^{(a)}_{r - s a}:
+ *   1                                  if an anyon sits on the line,
+ *   0                                  if every register on it is 0,
+ *   (min of the nonzero registers) + 1 otherwise (R1, R2). */
+static void orc_message_update(orc_state *st) {
+  int L = st->L;
+  for (int d = 0; d < 4; ++d) {
+    int s = DIR_S[d], a = DIR_A[d];
+    int ax = (a == 1), ay = (a == 2);       /* unit vector a-hat */
+    int bx = ay, by = ax;                   /* unit vector normal to a */
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        int cxp = x - s * ax, cyp = y - s * ay;   /* centre r - s a-hat */
+        int anyon = 0;
+        int32_t minnz = 0;
+        for (int k = -1; k <= 1; ++k) {
+          int qx = wrap(cxp + k * bx, L), qy = wrap(cyp + k * by, L);
+          int q = qy * L + qx;
+          if (st->sigma[q] == -1) anyon = 1;
+          int32_t mv = st->m[d][q];
+          if (mv > 0 && (minnz == 0 || mv < minnz)) minnz = mv;
+        }
+        int32_t out;
+        if (anyon) out = 1;
+        else if (minnz == 0) out = 0;
+        else out = minnz + 1;
+        st->mnew[d][y * L + x] = out;
+      }
+  }
+  for (int d = 0; d < 4; ++d) {
+    int32_t *t = st->m[d];
+    st->m[d] = st->mnew[d];
+    st->mnew[d] = t;
+  }
+}
+
+/* sgn(mm - mp) with an absent message (0) read as +infinity (R3). */
+static int orc_force(int32_t mp, int32_t mm) {
+  if (mp == 0 && mm == 0) return 0;
+  if (mp == 0) return -1;   /* only m^{-a}: source on the +a side */
+  if (mm == 0) return +1;   /* only m^{+a}: source on the -a side */
+  return (mm > mp) - (mm < mp);
+}
+
+/* x OR y for x, y in {-1, 0, +1}: 1 iff either equals 1. */
+static int orc_or(int x, int y) { return (x == 1 || y == 1) ? 1 : 0; }
+
+/* Feedback F^{(D)}: per-site force f^a_r from argmin' over the nonzero
+ * registers (ties broken by m + s a / (D+1), eq. (degbreak)), then the link
+ * exponent sigma_r f^a_r OR sigma_{r+a}(-f^a_{r+a}) of eq. (ddfeedback).
+ * Returns the number of anyons after the step. */
+static int64_t orc_feedback(orc_state *st) {
+  int L = st->L;
+  int64_t n = st->n;
+  for (int64_t i = 0; i < n; ++i) {
+    st->fx[i] = 0; st->fy[i] = 0;
+    if (st->sigma[i] != -1) continue;           /* R4 */
+    int best = -1;
+    int32_t bestkey = 0;
+    for (int d = 0; d < 4; ++d) {
+      int32_t mv = st->m[d][i];
+      if (mv <= 0) continue;
+      /* (D+1) * (m + s a / (D+1)) = 3 m + s a, an exact integer key */
+      int32_t key = 3 * mv + DIR_S[d] * DIR_A[d];
+      if (best < 0 || key < bestkey) { best = d; bestkey = key; }
+    }
+    if (best < 0) continue;                     /* M_r empty: no feedback */
+    if (DIR_A[best] == 1) st->fx[i] = (int8_t)orc_force(st->m[0][i], st->m[1][i]);
+    else st->fy[i] = (int8_t)orc_force(st->m[2][i], st->m[3][i]);
+  }
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      int i = y * L + x;
+      int ix = y * L + wrap(x + 1, L), iy = wrap(y + 1, L) * L + x;
+      st->flx[i] = (uint8_t)orc_or(st->sigma[i] * st->fx[i], st->sigma[ix] * (-st->fx[ix]));
+      st->fly[i] = (uint8_t)orc_or(st->sigma[i] * st->fy[i], st->sigma[iy] * (-st->fy[iy]));
+    }
+  int64_t anyons = 0;
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      int i = y * L + x;
+      int par = st->flx[i] ^ st->flx[y * L + wrap(x - 1, L)] ^ st->fly[i] ^
+                st->fly[wrap(y - 1, L) * L + x];
+      st->cx[i] ^= st->flx[i];
+      st->cy[i] ^= st->fly[i];
+      if (par) st->sigma[i] = (int8_t)(-st->sigma[i]);
+    }
+  for (int64_t i = 0; i < n; ++i) anyons += (st->sigma[i] == -1);
+  return anyons;
+}
+
+static int64_t orc_count_anyons(const orc_state *st) {
+  int64_t a = 0;
+  for (int64_t i = 0; i < st->n; ++i) a += (st->sigma[i] == -1);
+  return a;
+}
+
+/* Winding parity of a chain across the fixed cuts: x-links leaving column
+ * L-1 and y-links leaving row L-1. */
+static void orc_winding(int L, const uint8_t *cx, const uint8_t *cy, int *wx, int *wy) {
+  int a = 0, b = 0;
+  for (int y = 0; y < L; ++y) a ^= cx[y * L + (L - 1)];
+  for (int x = 0; x < L; ++x) b ^= cy[(L - 1) * L + x];
+  *wx = a; *wy = b;
+}
+
+static void orc_pack_sigma(const orc_state *st, uint32_t *words) {
+  int64_t nw = (st->n + 31) / 32;
+  memset(words, 0, (size_t)nw * 4);
+  for (int64_t i = 0; i < st->n; ++i)
+    if (st->sigma[i] == -1) words[i >> 5] |= 1u << (i & 31);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public entry points (used through ctypes by the tests)                    */
+/* ------------------------------------------------------------------------ */
+
+/* Decode one explicit error pattern.  Outputs T_dec, flags (bit0 = logical
+ * failure, bit1 = timeout) and the final syndrome, packed as bit i%32 of
+ * word i/32 for site i = y*L + x.  Optional outputs may be NULL:
+ *   m_out     [4][L*L] int32 registers at the end,
+ *   cx_out, cy_out  [L*L] correction chain,
+ *   wind_out  [4] = (Wx_E, Wy_E, Wx_C, Wy_C). */
+int orc_decode_errors(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_max,
+                      int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words,
+                      int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out, int32_t *wind_out) {
+  if (L < 3 || v < 1 || T_max < 0) return ORC_EBADARG;
+  orc_state st;
+  if (orc_alloc(&st, L, v) != ORC_OK) return ORC_ENOMEM;
+  orc_syndrome(&st, ex, ey);
+  int64_t anyons = orc_count_anyons(&st);
+  int t = 0;
+  while (anyons > 0 && t < T_max) {
+    for (int j = 0; j < v; ++j) orc_message_update(&st);
+    anyons = orc_feedback(&st);
+    ++t;
+  }
+  int wxe, wye, wxc, wyc;
+  orc_winding(L, ex, ey, &wxe, &wye);
+  orc_winding(L, st.cx, st.cy, &wxc, &wyc);
+  int timeout = anyons > 0;
+  int fail = timeout || ((wxe ^ wxc) | (wye ^ wyc));
+  *T_dec = t;
+  *flags = (uint8_t)((fail ? 1 : 0) | (timeout ? 2 : 0));
+  if (sigma_words) orc_pack_sigma(&st, sigma_words);
+  if (m_out)
+    for (int d = 0; d < 4; ++d) memcpy(m_out + (size_t)d * st.n, st.m[d], (size_t)st.n * 4);
+  if (cx_out) memcpy(cx_out, st.cx, (size_t)st.n);
+  if (cy_out) memcpy(cy_out, st.cy, (size_t)st.n);
+  if (wind_out) { wind_out[0] = wxe; wind_out[1] = wye; wind_out[2] = wxc; wind_out[3] = wyc; }
+  orc_free(&st);
+  return ORC_OK;
+}
+
+/* Run exactly t_exact decoder steps (no early exit) from the noise pattern,
+ * starting from m = 0.  Outputs the registers, the syndrome (+1/-1 bytes)
+ * and the correction chain after the last step.  With record != NULL, the
+ * anyon indicator after every step k = 0..t_exact is written to
+ * record[k*L*L + i] (k = 0 is the initial syndrome). */
+int orc_run_steps(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exact,
+                  int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out, uint8_t *cy_out,
+                  uint8_t *record) {
+  if (L < 3 || v < 1 || t_exact < 0) return ORC_EBADARG;
+  orc_state st;
+  if (orc_alloc(&st, L, v) != ORC_OK) return ORC_ENOMEM;
+  orc_syndrome(&st, ex, ey);
+  if (record)
+    for (int64_t i = 0; i < st.n; ++i) record[i] = st.sigma[i] == -1;
+  for (int t = 0; t < t_exact; ++t) {
+    for (int j = 0; j < v; ++j) orc_message_update(&st);
+    orc_feedback(&st);
+    if (record)
+      for (int64_t i = 0; i < st.n; ++i)
+        record[(size_t)(t + 1) * st.n + i] = st.sigma[i] == -1;
+  }
+  if (m_out)
+    for (int d = 0; d < 4; ++d) memcpy(m_out + (size_t)d * st.n, st.m[d], (size_t)st.n * 4);
+  if (sigma_out) memcpy(sigma_out, st.sigma, (size_t)st.n);
+  if (cx_out) memcpy(cx_out, st.cx, (size_t)st.n);
+  if (cy_out) memcpy(cy_out, st.cy, (size_t)st.n);
+  orc_free(&st);
+  return ORC_OK;
+}
+
+/* Noise + decode for a batch of seeds; samples are spread over nthreads
+ * OpenMP threads (nthreads <= 0: the OpenMP default).  Returns the number
+ * of threads actually used through *threads_used. */
+int orc_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds,
+                     int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
+                     uint32_t *sigma_words, int *threads_used) {
+  if (L < 3 || v < 1 || T_max < 0 || n < 0) return ORC_EBADARG;
+  int64_t nsite = (int64_t)L * L;
+  int64_t nw = (nsite + 31) / 32;
+  int err = ORC_OK;
+  int used = 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+  {
+#pragma omp single
+    used = omp_get_num_threads();
+  }
+#else
+  (void)nthreads;
+#endif
+  if (threads_used) *threads_used = used;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n; ++k) {
+    uint8_t *ex = (uint8_t *)malloc((size_t)nsite);
+    uint8_t *ey = (uint8_t *)malloc((size_t)nsite);
+    int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
+    if (rc == ORC_OK) rc = orc_noise(L, p[p_stride ? k : 0], seeds[k], ex, ey);
+    if (rc == ORC_OK)
+      rc = orc_decode_errors(L, v, ex, ey, T_max, &T_dec[k], &flags[k],
+                             sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+    if (rc != ORC_OK) {
+#pragma omp critical
+      err = rc;
+    }
+    free(ex);
+    free(ey);
+  }
+  return err;
+}
+
+/* Decode a batch of explicit error chains given as link bits: link id
+ * l = 2*i + dir (dir 0: x-link of site i, dir 1: y-link), bit l%32 of word
+ * l/32, ceil(2*L*L/32) words per sample. */
+int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, int nthreads,
+                     int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words) {
+  if (L < 3 || v < 1 || T_max < 0 || n < 0) return ORC_EBADARG;
+  int64_t nsite = (int64_t)L * L;
+  int64_t lw = (2 * nsite + 31) / 32, nw = (nsite + 31) / 32;
+  int err = ORC_OK;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < n; ++k) {
+    uint8_t *ex = (uint8_t *)malloc((size_t)nsite);
+    uint8_t *ey = (uint8_t *)malloc((size_t)nsite);
+    int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
+    if (rc == ORC_OK) {
+      const uint32_t *w = links + k * lw;
+      for (int64_t i = 0; i < nsite; ++i) {
+        int64_t lx = 2 * i, ly = 2 * i + 1;
+        ex[i] = (uint8_t)((w[lx >> 5] >> (lx & 31)) & 1u);
+        ey[i] = (uint8_t)((w[ly >> 5] >> (ly & 31)) & 1u);
+      }
+      rc = orc_decode_errors(L, v, ex, ey, T_max, &T_dec[k], &flags[k],
+                             sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+    }
+    if (rc != ORC_OK) {
+#pragma omp critical
+      err = rc;
+    }
+    free(ex);
+    free(ey);
+  }
+  return err;
+}

@@ -1,0 +1,196 @@
+"""ctypes binding of the C oracle ``mpd_oracle.c`` plus its build step.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Arrays are numpy; the
+C side is plain scalar loops written from the paper's definitions:
+Def. "synchronous automaton decoder" (Sec. 2.1), Def. "message passing
+automaton, general dimensions" (Sec. 3.2) and Def. "logical failure rate,
+expected decoding time, and thresholds" (Sec. 5.1), with i.i.d. noise as in
+Sec. 7.  Direction order of register arrays: +x, -x, +y, -y.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mpd_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_BUILD, "libmpd_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP over samples).  Returns the .so path."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    os.makedirs(_BUILD, exist_ok=True)
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    lib.orc_philox4x32_10.argtypes = [P, P, P]
+    lib.orc_philox4x32_10.restype = None
+    lib.orc_noise.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P]
+    lib.orc_noise.restype = ctypes.c_int
+    lib.orc_decode_errors.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
+                                      P, P, P, P, P, P, P]
+    lib.orc_decode_errors.restype = ctypes.c_int
+    lib.orc_run_steps.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
+                                  P, P, P, P, P]
+    lib.orc_run_steps.restype = ctypes.c_int
+    lib.orc_decode_seeds.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
+                                     ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P, P, P]
+    lib.orc_decode_seeds.restype = ctypes.c_int
+    lib.orc_decode_links.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int64, ctypes.c_int,
+                                     ctypes.c_int, P, P, P]
+    lib.orc_decode_links.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block (Salmon et al., SC'11): 4 counter words, 2 key words."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def noise(L: int, p: float, seed: int):
+    """i.i.d. link flips (ex, ey) as uint8 [L, L] arrays indexed [y, x]."""
+    ex = np.zeros(L * L, dtype=np.uint8)
+    ey = np.zeros(L * L, dtype=np.uint8)
+    _check(_load().orc_noise(L, float(p), int(seed) & (2**64 - 1), _ptr(ex), _ptr(ey)), "noise")
+    return ex.reshape(L, L), ey.reshape(L, L)
+
+
+def syndrome_of(L: int, ex, ey):
+    """Anyon indicator (1 = sigma -1) of an error chain, via a zero-step run."""
+    _, sig, _, _ = run_steps(L, ex, ey, 0)
+    return (sig == -1).astype(np.uint8)
+
+
+def pack_bits(bits):
+    """Pack a flat 0/1 array as bit i%32 of uint32 word i/32."""
+    b = np.asarray(bits, dtype=np.uint8).reshape(-1)
+    nw = (b.size + 31) // 32
+    pad = np.zeros(nw * 32, dtype=np.uint64)
+    pad[: b.size] = b
+    w = pad.reshape(nw, 32) << np.arange(32, dtype=np.uint64)
+    return w.sum(axis=1).astype(np.uint32)
+
+
+def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = False):
+    """Decode one explicit error chain.
+
+    Returns dict(T_dec, flags, sigma_words) and, with want_state, also
+    m [4, L, L] int32, cx, cy [L, L] and wind (Wx_E, Wy_E, Wx_C, Wy_C).
+    """
+    ex = np.ascontiguousarray(np.asarray(ex, dtype=np.uint8).reshape(-1))
+    ey = np.ascontiguousarray(np.asarray(ey, dtype=np.uint8).reshape(-1))
+    assert ex.size == L * L and ey.size == L * L
+    T = np.zeros(1, dtype=np.int32)
+    fl = np.zeros(1, dtype=np.uint8)
+    sw = np.zeros((L * L + 31) // 32, dtype=np.uint32)
+    m = np.zeros(4 * L * L, dtype=np.int32) if want_state else None
+    cx = np.zeros(L * L, dtype=np.uint8) if want_state else None
+    cy = np.zeros(L * L, dtype=np.uint8) if want_state else None
+    wind = np.zeros(4, dtype=np.int32) if want_state else None
+    _check(_load().orc_decode_errors(L, v, _ptr(ex), _ptr(ey), int(T_max), _ptr(T), _ptr(fl),
+                                     _ptr(sw), _ptr(m), _ptr(cx), _ptr(cy), _ptr(wind)),
+           "decode_errors")
+    out = dict(T_dec=int(T[0]), flags=int(fl[0]), sigma_words=sw)
+    if want_state:
+        out.update(m=m.reshape(4, L, L), cx=cx.reshape(L, L), cy=cy.reshape(L, L),
+                   wind=tuple(int(w) for w in wind))
+    return out
+
+
+def run_steps(L: int, ex, ey, t_exact: int, v: int = 3, record: bool = False):
+    """Run exactly t_exact steps.  Returns (m [4,L,L], sigma [L,L] (+1/-1),
+    (cx, cy), history) with history [t_exact+1, L, L] anyon indicators or None."""
+    ex = np.ascontiguousarray(np.asarray(ex, dtype=np.uint8).reshape(-1))
+    ey = np.ascontiguousarray(np.asarray(ey, dtype=np.uint8).reshape(-1))
+    m = np.zeros(4 * L * L, dtype=np.int32)
+    sig = np.zeros(L * L, dtype=np.int8)
+    cx = np.zeros(L * L, dtype=np.uint8)
+    cy = np.zeros(L * L, dtype=np.uint8)
+    hist = np.zeros((t_exact + 1) * L * L, dtype=np.uint8) if record else None
+    _check(_load().orc_run_steps(L, v, _ptr(ex), _ptr(ey), int(t_exact), _ptr(m), _ptr(sig),
+                                 _ptr(cx), _ptr(cy), _ptr(hist)), "run_steps")
+    return (m.reshape(4, L, L), sig.reshape(L, L), (cx.reshape(L, L), cy.reshape(L, L)),
+            None if hist is None else hist.reshape(t_exact + 1, L, L))
+
+
+def decode_seeds(L: int, p, seeds, T_max: int, v: int = 3, threads: int = 0,
+                 want_sigma: bool = True):
+    """Noise from each seed (one p, or one p per seed) and decode.
+
+    Returns dict(T_dec int32[n], flags uint8[n], sigma_words uint32[n, W] or
+    None, threads) where threads is the number of OpenMP threads used.
+    """
+    seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
+    n = seeds.size
+    pa = np.ascontiguousarray(np.atleast_1d(np.asarray(p, dtype=np.float64)))
+    stride = 1 if pa.size > 1 else 0
+    if stride:
+        assert pa.size == n
+    T = np.zeros(n, dtype=np.int32)
+    fl = np.zeros(n, dtype=np.uint8)
+    W = (L * L + 31) // 32
+    sw = np.zeros((n, W), dtype=np.uint32) if want_sigma else None
+    used = ctypes.c_int(0)
+    _check(_load().orc_decode_seeds(L, v, _ptr(pa), stride, _ptr(seeds), n, int(T_max),
+                                    int(threads), _ptr(T), _ptr(fl), _ptr(sw),
+                                    ctypes.byref(used)), "decode_seeds")
+    return dict(T_dec=T, flags=fl, sigma_words=sw, threads=int(used.value))
+
+
+def links_from_chains(L: int, ex, ey):
+    """Pack (ex, ey) chains of shape [..., L, L] into link words
+    (link id 2*i + dir, bit l%32 of word l/32)."""
+    ex = np.asarray(ex, dtype=np.uint8).reshape(-1, L * L)
+    ey = np.asarray(ey, dtype=np.uint8).reshape(-1, L * L)
+    n = ex.shape[0]
+    bits = np.zeros((n, 2 * L * L), dtype=np.uint8)
+    bits[:, 0::2] = ex
+    bits[:, 1::2] = ey
+    return np.stack([pack_bits(b) for b in bits]) if n else np.zeros((0, (2 * L * L + 31) // 32), np.uint32)
+
+
+def decode_links(L: int, links, T_max: int, v: int = 3, threads: int = 0):
+    """Decode explicit error chains given as packed link words [n, W]."""
+    lw = (2 * L * L + 31) // 32
+    links = np.ascontiguousarray(np.asarray(links, dtype=np.uint32).reshape(-1, lw))
+    n = links.shape[0]
+    T = np.zeros(n, dtype=np.int32)
+    fl = np.zeros(n, dtype=np.uint8)
+    sw = np.zeros((n, (L * L + 31) // 32), dtype=np.uint32)
+    _check(_load().orc_decode_links(L, v, _ptr(links), n, int(T_max), int(threads), _ptr(T),
+                                    _ptr(fl), _ptr(sw)), "decode_links")
+    return dict(T_dec=T, flags=fl, sigma_words=sw)
