@@ -34,7 +34,12 @@
  *       +infinity, i.e. an anyon moves toward the source of the smallest
  *       message it holds, and does not move on an exact tie along that axis.
  *   R4  only anyon sites (sigma = -1) apply feedback; f := 0 elsewhere.
- *   R5  axis a = 1 is x (first coordinate), a = 2 is y.
+ *   R5  argmin' compares the messages first and uses the offset s a/(D+1)
+ *       only between equal messages (axis a = 1 is x, a = 2 is y), giving
+ *       the order -y < -x < +x < +y on ties.  Read literally, m + s a/(D+1)
+ *       would leave (-x, m+1) and (+y, m) tied, and (-y, m+1) tied with
+ *       (+x, m), so it would not remove the degeneracies it is introduced to
+ *       remove; the anyon is meant to follow its smallest message.
  *   R6  within one step the v message updates come first, then feedback;
  *       sigma is fixed during the message updates.
  *   R7  T_dec and T_max count decoder steps (feedback applications).
@@ -240,13 +245,18 @@ static int64_t orc_feedback(orc_state *st) {
     st->fx[i] = 0; st->fy[i] = 0;
     if (st->sigma[i] != -1) continue;           /* R4 */
     int best = -1;
-    int32_t bestkey = 0;
+    int32_t bestm = 0, bestoff = 0;
     for (int d = 0; d < 4; ++d) {
       int32_t mv = st->m[d][i];
       if (mv <= 0) continue;
-      /* (D+1) * (m + s a / (D+1)) = 3 m + s a, an exact integer key */
-      int32_t key = 3 * mv + DIR_S[d] * DIR_A[d];
-      if (best < 0 || key < bestkey) { best = d; bestkey = key; }
+      /* argmin' of eq. (degbreak): the offset s a / (D+1) only breaks ties
+       * between equal messages (R5): smallest m first, then smallest s*a. */
+      int32_t off = DIR_S[d] * DIR_A[d];
+      if (best < 0 || mv < bestm || (mv == bestm && off < bestoff)) {
+        best = d;
+        bestm = mv;
+        bestoff = off;
+      }
     }
     if (best < 0) continue;                     /* M_r empty: no feedback */
     if (DIR_A[best] == 1) st->fx[i] = (int8_t)orc_force(st->m[0][i], st->m[1][i]);
