@@ -1,0 +1,140 @@
+/*
+ * mpd.h -- C ABI of the MI355X message-passing decoder for the 2D toric code.
+ *
+ * The decoder is the synchronous automaton decoder of E. Lake, "Fast offline
+ * decoding with local message-passing automata" (arXiv:2506.03266):
+ *   - noise: i.i.d. bit flips of strength p on the 2L^2 links of an L x L
+ *     periodic lattice (Sec. 2.2, eq. (final_channel); numerics of Sec. 7);
+ *   - syndrome sigma measured once, then per decoder step v = 3 applications
+ *     of the message rule A^{(D)} followed by one application of the feedback
+ *     operators F^{(D)} (Def. "synchronous automaton decoder", Sec. 2.1;
+ *     Def. "message passing automaton, general dimensions", Sec. 3.2);
+ *   - stop at the first step with no anyon: T_dec (Def. "logical failure
+ *     rate, expected decoding time, and thresholds", Sec. 5.1);
+ *   - logical failure iff error + correction winds either cycle of the torus
+ *     (Sec. 7.2).
+ *
+ * Conventions shared by every entry point
+ *   - Site index i = y*L + x, 0 <= x, y < L.  The x-link of site (x,y) joins
+ *     (x,y)-(x+1,y), its y-link joins (x,y)-(x,y+1), indices mod L.
+ *   - Noise (seeded entry points): for site i, Philox4x32-10 (Salmon et al.,
+ *     SC'11) with key = (seed & 0xffffffff, seed >> 32) and counter
+ *     (i >> 1, 0, 0, 0); word 2*(i&1) drives the x-link and word 2*(i&1)+1 the
+ *     y-link; a link flips iff word < floor(p * 2^32) (computed in double).
+ *   - Link bit arrays: link id l = 2*i + dir (dir 0: x-link, 1: y-link), bit
+ *     l % 32 of word l / 32, ceil(2*L*L/32) words per sample.
+ *   - Syndrome bit arrays: bit i % 32 of word i / 32 set iff site i holds an
+ *     anyon, ceil(L*L/32) words per sample.
+ *   - flags: bit 0 (MPD_FLAG_FAIL) logical failure, bit 1 (MPD_FLAG_TIMEOUT)
+ *     anyons left after T_max steps (then T_dec = T_max and the failure bit is
+ *     also set).
+ *   - Readings of the paper where it is silent or garbled: the message rule
+ *     takes the minimum over nonzero registers only; an anyon moves toward the
+ *     source of its smallest message, ties broken in the order
+ *     -y < -x < +x < +y, and does not move on an exact tie along the chosen
+ *     axis; only anyon sites apply feedback; messages are never truncated.
+ *
+ * Ownership and execution
+ *   - Every pointer named d_* is caller-owned device memory on the current
+ *     HIP device; the library never allocates, frees or keeps it.  Host
+ *     memory is never read or written except the scalar arguments.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *     stream).  Outputs are valid once the stream has reached the point after
+ *     the call.  Calls that share a workspace must be ordered on one stream.
+ *   - The large-lattice path reads a small per-block counter back to the host
+ *     between decoder passes, so those calls synchronize `stream`.
+ *   - Return value 0 on success, a negative MPD_ERR_* code otherwise; the
+ *     message of the last failing call on this host thread is returned by
+ *     mpd_last_error().  On an error nothing has been enqueued unless the
+ *     code is MPD_ERR_HIP.
+ */
+#ifndef MPD_H
+#define MPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPD_OK 0
+#define MPD_ERR_L (-1)         /* L outside [3, 1024] or unsupported for the call */
+#define MPD_ERR_P (-2)         /* p is NaN or outside [0, 1] */
+#define MPD_ERR_TMAX (-3)      /* T_max (or t_exact) outside [0, MPD_T_MAX_LIMIT] */
+#define MPD_ERR_PTR (-4)       /* a required pointer is NULL or misaligned */
+#define MPD_ERR_WORKSPACE (-5) /* ws_bytes < mpd_workspace_bytes(...) */
+#define MPD_ERR_HIP (-6)       /* a HIP runtime call failed */
+#define MPD_ERR_N (-7)         /* n < 0 or too large */
+
+#define MPD_FLAG_FAIL 1u
+#define MPD_FLAG_TIMEOUT 2u
+
+/* Message registers are kept as 16-bit emission times of sub-steps, so that
+ * v * T_max <= 32767 keeps every register exact (no truncation). */
+#define MPD_T_MAX_LIMIT 10922
+
+/* Library version string. */
+const char *mpd_version(void);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char *mpd_last_error(void);
+
+/* Bytes of device workspace that a decode of n samples of size L needs
+ * (0 if none).  Lattices up to L = 128 decode entirely on chip; larger ones
+ * keep two copies of the per-site state (8 B of registers + 1 bit of
+ * syndrome per site) plus per-sample bookkeeping. */
+size_t mpd_workspace_bytes(int L, int64_t n);
+
+/* Decode n seeded noise samples of size L at noise strength p.
+ *   d_seeds            [n] uint64 seeds (device)
+ *   T_max              step budget, 0 <= T_max <= MPD_T_MAX_LIMIT
+ *   d_T_dec            [n] int32  decoding time (steps) or T_max on timeout
+ *   d_flags            [n] uint8  MPD_FLAG_* bits
+ *   d_final_syndrome   [n][ceil(L*L/32)] uint32 anyons after the last step
+ *                      (all zero for a decoded sample); may be NULL
+ *   d_workspace        >= mpd_workspace_bytes(L, n) bytes, 256-byte aligned
+ *                      (may be NULL when that size is 0)
+ * Supported L: 3 <= L <= 128 (any), and L = 256. */
+int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max,
+                     int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
+                     void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Decode n explicit error patterns (hand-built cases, exhaustive checks).
+ *   d_links            [n][ceil(2*L*L/32)] uint32 link bits (see above)
+ * Other arguments as mpd_decode_batch.  Supported L: 3 <= L <= 128. */
+int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec,
+                      uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace,
+                      size_t ws_bytes, void *stream);
+
+/* Run exactly t_exact decoder steps on explicit error patterns, with no early
+ * exit, and export the full decoder state (checkpoint / parity debugging).
+ *   d_m_out            [n][4][L*L] int16 message registers m^{+x}, m^{-x},
+ *                      m^{+y}, m^{-y} after step t_exact (distance form of the
+ *                      paper: 0 = no message)
+ *   d_sigma_out        [n][ceil(L*L/32)] uint32 anyon bits after step t_exact
+ *   d_wind_out         [n] uint8: bit 0 Wx(E), bit 1 Wy(E), bit 2 Wx(C),
+ *                      bit 3 Wy(C), winding parities of the error and of the
+ *                      correction applied so far, across the cuts x = L-1 and
+ *                      y = L-1
+ * Supported L: 3 <= L <= 128. */
+int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
+                  uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
+/* Kernel timing for measurement (not needed for decoding).
+ * mpd_profile(1) clears earlier records and starts recording a pair of HIP
+ * events on the launch stream around every kernel launch of the library;
+ * mpd_profile(0) stops recording (records are kept).  Names: "k_tile"
+ * (one pass of k decoder steps over the L = 256 bands) and "k_resident"
+ * (whole decode of small lattices).  Not thread-safe. */
+int mpd_profile(int enable);
+
+/* Sum of the recorded durations (ms) and number of launches of `kernel`;
+ * waits for the recorded events to complete. */
+int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPD_H */

@@ -1,0 +1,162 @@
+"""ctypes binding of libmpd.so (C ABI in include/mpd.h) for torch tensors.
+
+Argument marshalling only: every step of a decode runs in the HIP kernels of
+the library.  PyTorch supplies device memory and the stream.  There is no
+CPU fallback: if the library is missing, the import of a decode function
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libmpd.so")
+
+MPD_FLAG_FAIL = 1
+MPD_FLAG_TIMEOUT = 2
+MPD_T_MAX_LIMIT = 10922
+
+_lib = None
+
+
+class MPDError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libmpd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MPDError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, SZ, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    L.mpd_version.restype = ctypes.c_char_p
+    L.mpd_last_error.restype = ctypes.c_char_p
+    L.mpd_workspace_bytes.argtypes = [I, I64]
+    L.mpd_workspace_bytes.restype = SZ
+    L.mpd_decode_batch.argtypes = [I, D, P, I64, I, P, P, P, P, SZ, P]
+    L.mpd_decode_batch.restype = I
+    L.mpd_decode_errors.argtypes = [I, P, I64, I, P, P, P, P, SZ, P]
+    L.mpd_decode_errors.restype = I
+    L.mpd_run_steps.argtypes = [I, P, I64, I, P, P, P, P]
+    L.mpd_run_steps.restype = I
+    L.mpd_profile.argtypes = [I]
+    L.mpd_profile.restype = I
+    L.mpd_profile_read.argtypes = [ctypes.c_char_p, P, P]
+    L.mpd_profile_read.restype = I
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().mpd_last_error().decode()
+        raise MPDError(f"{what} failed ({rc}): {msg}")
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _seeds_tensor(seeds, device):
+    if isinstance(seeds, torch.Tensor):
+        assert seeds.dtype in (torch.int64, torch.uint64)
+        return seeds.to(device).contiguous()
+    a = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64)).view(np.int64)
+    return torch.from_numpy(a).to(device)
+
+
+def syndrome_words(L: int) -> int:
+    return (L * L + 31) // 32
+
+
+def link_words(L: int) -> int:
+    return (2 * L * L + 31) // 32
+
+
+def workspace_bytes(L: int, n: int) -> int:
+    return int(lib().mpd_workspace_bytes(L, n))
+
+
+def alloc_workspace(L: int, n: int, device="cuda"):
+    nb = workspace_bytes(L, n)
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+
+
+def decode_batch(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True,
+                 workspace=None, out=None, stream=None):
+    """Decode len(seeds) seeded noise samples.
+
+    Returns (T_dec int32[n], flags uint8[n], syndrome int32[n, W] or None) on
+    the device.  `out` may pass preallocated (T_dec, flags, syndrome).
+    """
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    else:
+        T, F, S = out
+    ws = workspace if workspace is not None else alloc_workspace(L, n)
+    rc = lib().mpd_decode_batch(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws),
+                                ws.numel(), _stream_ptr(stream))
+    _check(rc, "mpd_decode_batch")
+    return T, F, S
+
+
+def decode_errors(L: int, links, T_max: int = 4096, want_syndrome: bool = True, stream=None):
+    """Decode explicit error patterns given as link words [n, link_words(L)]."""
+    dev = torch.device("cuda")
+    if not isinstance(links, torch.Tensor):
+        links = torch.from_numpy(np.ascontiguousarray(np.asarray(links, dtype=np.uint32)).view(np.int32))
+    links = links.to(dev).contiguous().view(-1, link_words(L))
+    n = links.shape[0]
+    T = torch.empty(n, dtype=torch.int32, device=dev)
+    F = torch.empty(n, dtype=torch.uint8, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    ws = alloc_workspace(L, n)
+    rc = lib().mpd_decode_errors(L, _ptr(links), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws), ws.numel(),
+                                 _stream_ptr(stream))
+    _check(rc, "mpd_decode_errors")
+    return T, F, S
+
+
+def run_steps(L: int, links, t_exact: int, stream=None):
+    """Run exactly t_exact steps; returns (m int16[n,4,L,L], syndrome int32[n,W], wind uint8[n])."""
+    dev = torch.device("cuda")
+    if not isinstance(links, torch.Tensor):
+        links = torch.from_numpy(np.ascontiguousarray(np.asarray(links, dtype=np.uint32)).view(np.int32))
+    links = links.to(dev).contiguous().view(-1, link_words(L))
+    n = links.shape[0]
+    M = torch.empty((n, 4, L, L), dtype=torch.int16, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
+    W = torch.empty(n, dtype=torch.uint8, device=dev)
+    rc = lib().mpd_run_steps(L, _ptr(links), n, int(t_exact), _ptr(M), _ptr(S), _ptr(W), _stream_ptr(stream))
+    _check(rc, "mpd_run_steps")
+    return M, S, W
+
+
+def profile(enable: bool):
+    """Start (clearing old records) or stop per-launch kernel timing."""
+    _check(lib().mpd_profile(1 if enable else 0), "mpd_profile")
+
+
+def profile_read(kernel: str):
+    """(total_ms, launches) recorded for a kernel name."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().mpd_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "mpd_profile_read")
+    return ms.value, cnt.value

@@ -1,0 +1,716 @@
+// mpd.hip -- kernels and C ABI of the MI355X decoder (see include/mpd.h).
+//
+// Two execution shapes share the device engine of engine.h:
+//  * resident: one workgroup holds a whole L x L sample in LDS/VGPRs and runs
+//    it from noise to termination with no HBM traffic for the state
+//    (L <= 128 with a strip height dividing L);
+//  * tiled (L = 256): each workgroup owns a full-height band of columns plus
+//    a halo of 4k columns on each side (k = decoder steps per pass: a step
+//    moves information by v = 3 sites for the messages plus 1 for the
+//    feedback), runs k steps on chip, and writes its band back to HBM.  The
+//    first pass generates the noise for its band in place.  Between passes a
+//    small kernel turns the per-step "anyons left" bits into T_dec and
+//    compacts the list of unfinished samples.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "mpd.h"
+
+namespace mpd {
+
+// ---------------------------------------------------------------------------
+// Resident kernel: one workgroup per sample.
+// ---------------------------------------------------------------------------
+
+struct ResidentArgs {
+  int L;
+  int64_t n;
+  const uint64_t *seeds;   // seeded mode when links == nullptr
+  uint64_t thr;
+  const uint32_t *links;   // explicit error patterns
+  int T_max;
+  int t_exact;             // >= 0: run exactly this many steps (state export)
+  int32_t *T_dec;
+  uint8_t *flags;
+  uint32_t *syn;           // final syndrome bits (may be null)
+  int16_t *m_out;          // state export (t_exact >= 0)
+  uint8_t *wind_out;
+};
+
+__device__ __forceinline__ uint32_t parity32(uint32_t x) { return __popc(x) & 1u; }
+
+template <int H>
+__global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = a.L, RX = L, NS = L / H;
+  uint2 *F = reinterpret_cast<uint2 *>(smem);
+  uint4 *MV = reinterpret_cast<uint4 *>(smem + (size_t)RX * L * sizeof(uint2));
+  uint32_t *red = reinterpret_cast<uint32_t *>(MV + (size_t)RX * NS);
+  const int64_t sample = blockIdx.x;
+  const int tid = threadIdx.x;
+
+  Geo g;
+  g.RX = RX;
+  g.c = tid % RX;
+  g.j = tid / RX;
+  g.y0 = g.j * H;
+  g.cl = g.c == 0 ? RX - 1 : g.c - 1;
+  g.cr = g.c == RX - 1 ? 0 : g.c + 1;
+  g.jd = g.j == 0 ? NS - 1 : g.j - 1;
+  g.ju = g.j == NS - 1 ? 0 : g.j + 1;
+  g.rowDn = g.y0 == 0 ? L - 1 : g.y0 - 1;
+  g.rowUp = g.y0 + H == L ? 0 : g.y0 + H;
+
+  if (tid == 0) red[0] = 0u;
+
+  // ---- noise / error pattern -> link bits of the strip
+  uint32_t exb = 0u, eyb = 0u;
+  if (a.links == nullptr) {
+    const uint64_t seed = a.seeds[sample];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      bool fx, fy;
+      site_noise((uint32_t)((g.y0 + h) * L + g.c), k0, k1, a.thr, fx, fy);
+      exb |= (uint32_t)fx << h;
+      eyb |= (uint32_t)fy << h;
+      if (h & 1) __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    const int64_t lw = (2 * (int64_t)L * L + 31) / 32;
+    const uint32_t *w = a.links + sample * lw;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint32_t lx = 2u * (uint32_t)((g.y0 + h) * L + g.c), ly = lx + 1u;
+      exb |= ((w[lx >> 5] >> (lx & 31u)) & 1u) << h;
+      eyb |= ((w[ly >> 5] >> (ly & 31u)) & 1u) << h;
+    }
+  }
+  uint32_t wind = 0u;  // bit0 Wx(E), bit1 Wy(E), bit2 Wx(C), bit3 Wy(C)
+  if (g.c == L - 1) wind ^= parity32(exb);
+  if (g.j == NS - 1) wind ^= ((eyb >> (H - 1)) & 1u) << 1;
+  uint32_t sig = syndrome_from_links<H>(exb, eyb, MV, g);
+
+  uint32_t P[H], Q[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    P[h] = 0u;
+    Q[h] = 0u;
+  }
+
+  int alive = __syncthreads_or(sig != 0u);
+  const bool exact = a.t_exact >= 0;
+  const int steps = exact ? a.t_exact : a.T_max;
+  int t = 0;
+  while (t < steps && (exact || alive)) {
+#pragma unroll 1
+    for (int sub = 1; sub <= 3; ++sub) {
+      const uint32_t s = (uint32_t)(3 * t + sub);
+      substep<H>(P, Q, sig, s | (s << 16), F, g);
+    }
+    uint32_t xo, yo;
+    sig = feedback<H>(P, Q, sig, MV, g, xo, yo);
+    if (g.c == L - 1) wind ^= parity32(xo) << 2;
+    if (g.j == NS - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
+    ++t;
+    alive = __syncthreads_or(sig != 0u);
+  }
+
+  // ---- reduce the winding bits of the block
+  if (wind) atomicXor(&red[0], wind);
+  __syncthreads();
+  const uint32_t W = red[0];
+
+  const int64_t nw = ((int64_t)L * L + 31) / 32;
+  uint32_t *out_bits = exact ? a.syn : a.syn;
+  if (out_bits != nullptr) {
+    uint32_t *SW = reinterpret_cast<uint32_t *>(F);  // F is free now
+    for (int w = tid; w < nw; w += blockDim.x) SW[w] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      if ((sig >> h) & 1u) {
+        const uint32_t i = (uint32_t)((g.y0 + h) * L + g.c);
+        atomicOr(&SW[i >> 5], 1u << (i & 31u));
+      }
+    __syncthreads();
+    for (int w = tid; w < nw; w += blockDim.x) out_bits[sample * nw + w] = SW[w];
+  }
+
+  if (exact) {
+    if (a.m_out != nullptr) {
+      const uint32_t snow = 3u * (uint32_t)a.t_exact;
+      const int64_t n2 = (int64_t)L * L;
+      int16_t *mo = a.m_out + sample * 4 * n2;
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int64_t i = (int64_t)(g.y0 + h) * L + g.c;
+        const uint32_t e[4] = {P[h] & 0xFFFFu, P[h] >> 16, Q[h] & 0xFFFFu, Q[h] >> 16};
+#pragma unroll
+        for (int d = 0; d < 4; ++d) mo[d * n2 + i] = (int16_t)(e[d] ? (snow - e[d] + 1u) : 0u);
+      }
+    }
+    if (tid == 0 && a.wind_out != nullptr) a.wind_out[sample] = (uint8_t)W;
+  } else if (tid == 0) {
+    const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
+    const uint32_t timeout = alive ? 1u : 0u;
+    a.T_dec[sample] = t;
+    a.flags[sample] = (uint8_t)((fail | timeout) | (timeout << 1));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled path for L = 256: full-height bands, k steps per pass.
+// ---------------------------------------------------------------------------
+
+constexpr int TILE_H = 16;    // rows per thread strip
+constexpr int TILE_RX = 64;   // region width including both halos
+
+struct TileArgs {
+  int L;
+  int first;        // 1: generate noise in place, 0: load state from src
+  int k;            // decoder steps in this pass
+  int t0;           // steps already done
+  int halo;         // columns of halo on each side
+  int tx;           // owned columns per tile
+  const uint64_t *seeds;
+  uint64_t thr;
+  const int32_t *active;  // sample index per grid.x
+  const uint2 *Esrc;
+  const uint16_t *Ssrc;
+  uint2 *Edst;
+  uint16_t *Sdst;
+  uint32_t *alive;  // per sample: bit 0 anyons at pass start, bit j after step t0+j
+  uint32_t *wind;   // per sample winding bits (see k_resident)
+  int *zero_count;  // counter to clear for the following compaction
+};
+
+template <int H>
+__global__ __launch_bounds__(1024) void k_tile(TileArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = a.L, RX = TILE_RX, NS = L / H;
+  uint2 *F = reinterpret_cast<uint2 *>(smem);
+  uint4 *MV = reinterpret_cast<uint4 *>(smem + (size_t)RX * L * sizeof(uint2));
+  uint32_t *red = reinterpret_cast<uint32_t *>(MV + (size_t)RX * NS);
+  const int sample = a.active[blockIdx.x];
+  const int tile = blockIdx.y;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tile == 0 && tid == 0) *a.zero_count = 0;
+
+  Geo g;
+  g.RX = RX;
+  g.c = tid % RX;
+  g.j = tid / RX;
+  g.y0 = g.j * H;
+  g.cl = g.c == 0 ? 0 : g.c - 1;           // clamped: the halo absorbs the edge
+  g.cr = g.c == RX - 1 ? RX - 1 : g.c + 1;
+  g.jd = g.j == 0 ? NS - 1 : g.j - 1;      // full height: rows wrap
+  g.ju = g.j == NS - 1 ? 0 : g.j + 1;
+  g.rowDn = g.y0 == 0 ? L - 1 : g.y0 - 1;
+  g.rowUp = g.y0 + H == L ? 0 : g.y0 + H;
+
+  const int tx0 = tile * a.tx;
+  int gx = tx0 - a.halo + g.c;
+  gx = gx < 0 ? gx + L : (gx >= L ? gx - L : gx);
+  const int owned_w = min(a.tx, L - tx0);
+  const bool own = g.c >= a.halo && g.c < a.halo + owned_w;
+
+  if (tid == 0) red[0] = 0u;
+  uint32_t wind = 0u;
+  uint32_t P[H], Q[H];
+  uint32_t sig;
+  const size_t base = (size_t)sample * L * L;
+  if (a.first) {
+    const uint64_t seed = a.seeds[sample];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t exb = 0u, eyb = 0u;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      bool fx, fy;
+      site_noise((uint32_t)((g.y0 + h) * L + gx), k0, k1, a.thr, fx, fy);
+      exb |= (uint32_t)fx << h;
+      eyb |= (uint32_t)fy << h;
+      P[h] = 0u;
+      Q[h] = 0u;
+      if (h & 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (own && gx == L - 1) wind ^= parity32(exb);
+    if (own && g.j == NS - 1) wind ^= ((eyb >> (H - 1)) & 1u) << 1;
+    sig = syndrome_from_links<H>(exb, eyb, MV, g);
+  } else {
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint2 e = a.Esrc[base + (size_t)(g.y0 + h) * L + gx];
+      P[h] = e.x;
+      Q[h] = e.y;
+    }
+    sig = a.Ssrc[((size_t)sample * NS + g.j) * L + gx];
+  }
+
+  uint32_t bits = __syncthreads_or(own && sig != 0u) ? 1u : 0u;
+  for (int st = 0; st < a.k; ++st) {
+    const int t = a.t0 + st;
+#pragma unroll 1
+    for (int sub = 1; sub <= 3; ++sub) {
+      const uint32_t s = (uint32_t)(3 * t + sub);
+      substep<H>(P, Q, sig, s | (s << 16), F, g);
+    }
+    uint32_t xo, yo;
+    sig = feedback<H>(P, Q, sig, MV, g, xo, yo);
+    if (own && gx == L - 1) wind ^= parity32(xo) << 2;
+    if (own && g.j == NS - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
+    if (__syncthreads_or(own && sig != 0u)) bits |= 2u << st;
+  }
+
+  if (own) {
+#pragma unroll
+    for (int h = 0; h < H; ++h) a.Edst[base + (size_t)(g.y0 + h) * L + gx] = make_uint2(P[h], Q[h]);
+    a.Sdst[((size_t)sample * NS + g.j) * L + gx] = (uint16_t)sig;
+  }
+  if (wind) atomicXor(&red[0], wind);
+  __syncthreads();
+  if (tid == 0) {
+    if (bits) atomicOr(&a.alive[sample], bits);
+    if (red[0]) atomicXor(&a.wind[sample], red[0]);
+  }
+}
+
+// Per-pass bookkeeping: T_dec from the per-step bits, compaction of the
+// samples that still hold anyons.  status: 0 running, 1 decoded, 2 timeout.
+__global__ void k_finalize(int first, int k, int t0, int T_max, const int32_t *active, int nact,
+                           uint32_t *alive, int32_t *T_dec, uint8_t *status, int32_t *next,
+                           int *next_count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nact) return;
+  const int s = active[i];
+  const uint32_t bits = alive[s] | (first ? 0u : 1u);
+  alive[s] = 0u;
+  int td = -1;
+  for (int j = 0; j <= k; ++j)
+    if (!((bits >> j) & 1u)) {
+      td = t0 + j;
+      break;
+    }
+  if (td >= 0) {
+    T_dec[s] = td;
+    status[s] = 1;
+  } else if (t0 + k >= T_max) {
+    T_dec[s] = T_max;
+    status[s] = 2;
+  } else {
+    next[atomicAdd(next_count, 1)] = s;
+  }
+}
+
+__global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t *status,
+                            int32_t *active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  alive[i] = 0u;
+  wind[i] = 0u;
+  status[i] = 0;
+  active[i] = (int32_t)i;
+}
+
+// flags and final syndrome (row-major bits) from the tiled state.
+__global__ void k_tile_export(int L, int64_t n, const uint8_t *status, const uint32_t *wind,
+                              const uint16_t *Slast, uint8_t *flags, uint32_t *syn) {
+  const int64_t s = blockIdx.x;
+  const int NS = L / TILE_H;
+  const int64_t nw = (int64_t)L * L / 32;
+  const bool timeout = status[s] == 2;
+  if (threadIdx.x == 0) {
+    const uint32_t W = wind[s];
+    const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
+    flags[s] = (uint8_t)((fail | (timeout ? 1u : 0u)) | (timeout ? 2u : 0u));
+  }
+  if (syn == nullptr) return;
+  for (int64_t w = threadIdx.x; w < nw; w += blockDim.x) {
+    uint32_t word = 0u;
+    if (timeout) {
+      const int64_t i0 = w * 32;
+      const int y = (int)(i0 / L), x0 = (int)(i0 % L);
+      const uint16_t *col = Slast + ((size_t)s * NS + y / TILE_H) * L;
+      for (int b = 0; b < 32; ++b) word |= (uint32_t)((col[x0 + b] >> (y % TILE_H)) & 1u) << b;
+    }
+    syn[s * nw + w] = word;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+thread_local std::string g_last_error;
+
+int fail_with(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail_with(MPD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));       \
+  } while (0)
+
+// Optional per-kernel timing with HIP events on the launch stream.
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler g_prof;
+
+// Records events around one launch when profiling is on.
+struct ProfScope {
+  ProfRec r{nullptr, nullptr, nullptr};
+  hipStream_t st;
+  ProfScope(const char *name, hipStream_t s) : st(s) {
+    if (!g_prof.on) return;
+    r.name = name;
+    r.a = g_prof.get();
+    r.b = g_prof.get();
+    if (r.a) (void)hipEventRecord(r.a, st);
+  }
+  ~ProfScope() {
+    if (!g_prof.on || !r.a || !r.b) return;
+    (void)hipEventRecord(r.b, st);
+    g_prof.recs.push_back(r);
+  }
+};
+
+uint64_t threshold_of(double p) {
+  double t = floor(p * 4294967296.0);
+  if (t < 0.0) t = 0.0;
+  if (t > 4294967296.0) t = 4294967296.0;
+  return (uint64_t)t;
+}
+
+// Strip height for the resident kernel: the divisor H <= 16 of L giving the
+// block size L*L/H closest to 256 threads without exceeding 1024.
+int resident_H(int L) {
+  int best = 0;
+  long bestd = 1L << 40;
+  for (int H = 1; H <= 16; ++H) {
+    if (L % H) continue;
+    const long th = (long)L * L / H;
+    if (th > 1024) continue;
+    const long d = th > 256 ? th - 256 : 256 - th;
+    if (d < bestd) {
+      bestd = d;
+      best = H;
+    }
+  }
+  return best;
+}
+
+size_t resident_lds(int L, int H) {
+  return (size_t)L * L * sizeof(uint2) + (size_t)L * (L / H) * sizeof(uint4) + 64;
+}
+
+size_t tile_lds(int L) {
+  return (size_t)TILE_RX * L * sizeof(uint2) + (size_t)TILE_RX * (L / TILE_H) * sizeof(uint4) + 64;
+}
+
+template <int H>
+int launch_resident_h(const ResidentArgs &a, hipStream_t stream) {
+  const size_t lds = resident_lds(a.L, H);
+  const int threads = a.L * a.L / H;
+  ProfScope ps("k_resident", stream);
+  hipLaunchKernelGGL(k_resident<H>, dim3((unsigned)a.n), dim3(threads), lds, stream, a);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+int launch_resident(const ResidentArgs &a, hipStream_t stream) {
+  switch (resident_H(a.L)) {
+    case 1: return launch_resident_h<1>(a, stream);
+    case 2: return launch_resident_h<2>(a, stream);
+    case 3: return launch_resident_h<3>(a, stream);
+    case 4: return launch_resident_h<4>(a, stream);
+    case 5: return launch_resident_h<5>(a, stream);
+    case 6: return launch_resident_h<6>(a, stream);
+    case 7: return launch_resident_h<7>(a, stream);
+    case 8: return launch_resident_h<8>(a, stream);
+    case 9: return launch_resident_h<9>(a, stream);
+    case 10: return launch_resident_h<10>(a, stream);
+    case 11: return launch_resident_h<11>(a, stream);
+    case 12: return launch_resident_h<12>(a, stream);
+    case 13: return launch_resident_h<13>(a, stream);
+    case 14: return launch_resident_h<14>(a, stream);
+    case 15: return launch_resident_h<15>(a, stream);
+    case 16: return launch_resident_h<16>(a, stream);
+    default: return fail_with(MPD_ERR_L, "L=%d has no strip height for the resident kernel", a.L);
+  }
+}
+
+bool resident_ok(int L) {
+  if (L < 3 || L > 128) return false;
+  const int H = resident_H(L);
+  return H > 0 && resident_lds(L, H) <= 160 * 1024;
+}
+
+bool tiled_ok(int L) { return L == 256; }
+
+struct TileWorkspace {
+  uint2 *E[2];
+  uint16_t *S[2];
+  uint32_t *alive, *wind;
+  uint8_t *status;
+  int32_t *active[2];
+  int *count;  // [2]
+  size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+TileWorkspace tile_layout(int L, int64_t n, void *base) {
+  TileWorkspace w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void *p = base ? (void *)((char *)base + off) : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const size_t sites = (size_t)n * L * L;
+  for (int b = 0; b < 2; ++b) w.E[b] = (uint2 *)take(sites * sizeof(uint2));
+  for (int b = 0; b < 2; ++b) w.S[b] = (uint16_t *)take((size_t)n * (L / TILE_H) * L * sizeof(uint16_t));
+  w.alive = (uint32_t *)take((size_t)n * 4);
+  w.wind = (uint32_t *)take((size_t)n * 4);
+  w.status = (uint8_t *)take((size_t)n);
+  for (int b = 0; b < 2; ++b) w.active[b] = (int32_t *)take((size_t)n * 4);
+  w.count = (int *)take(2 * sizeof(int));
+  w.bytes = off;
+  return w;
+}
+
+// Decoder steps per pass: the first pass also generates the noise.
+constexpr int K_FIRST = 4;
+constexpr int K_NEXT = 2;
+
+int decode_tiled(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                 uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+  TileWorkspace w = tile_layout(L, n, ws);
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive,
+                     w.wind, w.status, w.active[0]);
+  HIP_TRY(hipGetLastError());
+  const size_t lds = tile_lds(L);
+  const int threads = TILE_RX * (L / TILE_H);
+  int t0 = 0, cur = 0, nact = (int)n;
+  bool first = true;
+  for (;;) {
+    const int k = first ? min(K_FIRST, T_max) : min(K_NEXT, T_max - t0);
+    TileArgs ta;
+    ta.L = L;
+    ta.first = first ? 1 : 0;
+    ta.k = k;
+    ta.t0 = t0;
+    ta.halo = 4 * k + (first ? 1 : 0);
+    ta.tx = TILE_RX - 2 * ta.halo;
+    ta.seeds = d_seeds;
+    ta.thr = thr;
+    ta.active = w.active[cur];
+    ta.Esrc = w.E[cur];
+    ta.Ssrc = w.S[cur];
+    ta.Edst = w.E[cur ^ 1];
+    ta.Sdst = w.S[cur ^ 1];
+    ta.alive = w.alive;
+    ta.wind = w.wind;
+    ta.zero_count = &w.count[cur ^ 1];
+    const int ntiles = (L + ta.tx - 1) / ta.tx;
+    {
+      ProfScope ps("k_tile", stream);
+      hipLaunchKernelGGL(k_tile<TILE_H>, dim3((unsigned)nact, (unsigned)ntiles), dim3(threads), lds, stream, ta);
+    }
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, ta.first, k,
+                       t0, T_max, w.active[cur], nact, w.alive, d_T_dec, w.status, w.active[cur ^ 1],
+                       &w.count[cur ^ 1]);
+    HIP_TRY(hipGetLastError());
+    t0 += k;
+    cur ^= 1;
+    first = false;
+    if (t0 >= T_max) break;
+    int h_count = 0;
+    HIP_TRY(hipMemcpyAsync(&h_count, &w.count[cur], sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    nact = h_count;
+    if (nact == 0) break;
+  }
+  // state of the last pass is in buffer `cur`
+  hipLaunchKernelGGL(k_tile_export, dim3((unsigned)n), dim3(256), 0, stream, L, n, w.status, w.wind, w.S[cur],
+                     d_flags, d_syn);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+int check_common(int L, int64_t n, int T_max, const void *T_dec, const void *flags) {
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n=%lld out of range", (long long)n);
+  if (T_max < 0 || T_max > MPD_T_MAX_LIMIT)
+    return fail_with(MPD_ERR_TMAX, "T_max=%d outside [0, %d]", T_max, MPD_T_MAX_LIMIT);
+  if (n > 0 && (T_dec == nullptr || flags == nullptr))
+    return fail_with(MPD_ERR_PTR, "T_dec and flags must not be NULL");
+  if (((uintptr_t)T_dec & 3u) != 0) return fail_with(MPD_ERR_PTR, "T_dec must be 4-byte aligned");
+  (void)L;
+  return MPD_OK;
+}
+
+}  // namespace mpd
+
+using namespace mpd;
+
+extern "C" {
+
+const char *mpd_version(void) { return "mpd 0.1 gfx950"; }
+
+const char *mpd_last_error(void) { return g_last_error.c_str(); }
+
+size_t mpd_workspace_bytes(int L, int64_t n) {
+  if (n <= 0) return 0;
+  if (resident_ok(L)) return 0;
+  if (tiled_ok(L)) return tile_layout(L, n, nullptr).bytes;
+  return 0;
+}
+
+int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                     uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes,
+                     void *stream) {
+  g_last_error.clear();
+  if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
+  int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (!resident_ok(L) && !tiled_ok(L))
+    return fail_with(MPD_ERR_L, "L=%d unsupported (3..128 with a strip height, or 256)", L);
+  if (n == 0) return MPD_OK;
+  if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u)) return fail_with(MPD_ERR_PTR, "seeds NULL or misaligned");
+  if (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u))
+    return fail_with(MPD_ERR_PTR, "final_syndrome misaligned");
+  const uint64_t thr = threshold_of(p);
+  hipStream_t st = (hipStream_t)stream;
+  if (resident_ok(L)) {
+    ResidentArgs a = {};
+    a.L = L;
+    a.n = n;
+    a.seeds = d_seeds;
+    a.thr = thr;
+    a.links = nullptr;
+    a.T_max = T_max;
+    a.t_exact = -1;
+    a.T_dec = d_T_dec;
+    a.flags = d_flags;
+    a.syn = d_final_syndrome;
+    return launch_resident(a, st);
+  }
+  const size_t need = mpd_workspace_bytes(L, n);
+  if (ws_bytes < need || d_workspace == nullptr)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  return decode_tiled(L, thr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
+}
+
+int mpd_profile(int enable) {
+  g_last_error.clear();
+  if (enable) {
+    for (auto &r : g_prof.recs) {
+      g_prof.pool.push_back(r.a);
+      g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+  }
+  g_prof.on = enable != 0;
+  return MPD_OK;
+}
+
+int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
+  g_last_error.clear();
+  if (kernel == nullptr || total_ms == nullptr || launches == nullptr)
+    return fail_with(MPD_ERR_PTR, "profile_read arguments must not be NULL");
+  double ms = 0.0;
+  int64_t cnt = 0;
+  for (auto &r : g_prof.recs) {
+    if (strcmp(r.name, kernel) != 0) continue;
+    HIP_TRY(hipEventSynchronize(r.b));
+    float e = 0.f;
+    HIP_TRY(hipEventElapsedTime(&e, r.a, r.b));
+    ms += e;
+    ++cnt;
+  }
+  *total_ms = ms;
+  *launches = cnt;
+  return MPD_OK;
+}
+
+int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
+                      uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  (void)d_workspace;
+  (void)ws_bytes;
+  int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (!resident_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported for explicit errors (3..128)", L);
+  if (n == 0) return MPD_OK;
+  if (d_links == nullptr || ((uintptr_t)d_links & 3u)) return fail_with(MPD_ERR_PTR, "links NULL or misaligned");
+  ResidentArgs a = {};
+  a.L = L;
+  a.n = n;
+  a.links = d_links;
+  a.T_max = T_max;
+  a.t_exact = -1;
+  a.T_dec = d_T_dec;
+  a.flags = d_flags;
+  a.syn = d_final_syndrome;
+  return launch_resident(a, (hipStream_t)stream);
+}
+
+int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out, uint32_t *d_sigma_out,
+                  uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
+  if (t_exact < 0 || t_exact > MPD_T_MAX_LIMIT) return fail_with(MPD_ERR_TMAX, "t_exact out of range");
+  if (!resident_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported for run_steps (3..128)", L);
+  if (n == 0) return MPD_OK;
+  if (d_links == nullptr || ((uintptr_t)d_links & 3u)) return fail_with(MPD_ERR_PTR, "links NULL or misaligned");
+  if (d_m_out == nullptr || d_sigma_out == nullptr || d_wind_out == nullptr)
+    return fail_with(MPD_ERR_PTR, "state outputs must not be NULL");
+  ResidentArgs a = {};
+  a.L = L;
+  a.n = n;
+  a.links = d_links;
+  a.T_max = t_exact;
+  a.t_exact = t_exact;
+  a.syn = d_sigma_out;
+  a.m_out = d_m_out;
+  a.wind_out = d_wind_out;
+  return launch_resident(a, (hipStream_t)stream);
+}
+
+}  // extern "C"

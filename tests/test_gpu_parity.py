@@ -1,0 +1,197 @@
+"""GPU path (through the C ABI) against the CPU oracle, bit for bit.
+
+Every comparison is exact: T_dec, failure/timeout flags and the final
+syndrome bits (integer work), plus the full decoder state of run_steps.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2506_03266_amd.workloads import seeds, CONFIGS
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03266_amd.binding as b
+    b.lib()
+    return b
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def compare(tag, gT, gF, gS, ref):
+    T = _np(gT)
+    F = _np(gF)
+    bad = np.nonzero((T != ref["T_dec"]) | (F != ref["flags"]))[0]
+    assert bad.size == 0, f"{tag}: {bad.size} mismatches, first {bad[:5]} gpu T={T[bad[:5]]} F={F[bad[:5]]} " \
+                          f"oracle T={ref['T_dec'][bad[:5]]} F={ref['flags'][bad[:5]]}"
+    if gS is not None:
+        S = _np(gS).view(np.uint32)
+        rows = np.nonzero(np.any(S != ref["sigma_words"], axis=1))[0]
+        assert rows.size == 0, f"{tag}: final syndrome differs for samples {rows[:5]}"
+
+
+def chains(L, x_links, y_links):
+    ex = np.zeros((L, L), np.uint8)
+    ey = np.zeros((L, L), np.uint8)
+    for x, y in x_links:
+        ex[y % L, x % L] ^= 1
+    for x, y in y_links:
+        ey[y % L, x % L] ^= 1
+    return ex, ey
+
+
+def test_hand_cases(gpu, orc):
+    with open(os.path.join(GOLDEN, "hand_cases.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        L = c["L"]
+        ex, ey = chains(L, c["x_links"], c["y_links"])
+        links = orc.links_from_chains(L, ex, ey)
+        T, F, S = gpu.decode_errors(L, links, c["T_max"])
+        e = c["expect"]
+        assert int(_np(T)[0]) == e["T_dec"], c["name"]
+        assert int(_np(F)[0]) == e["fail"] | (e["timeout"] << 1) | e["timeout"], c["name"]
+        ref = orc.decode_links(L, links, c["T_max"])
+        compare(c["name"], T, F, S, ref)
+
+
+def test_exhaustive_L3(gpu, orc):
+    n = 1 << 18
+    links = np.arange(n, dtype=np.uint32).reshape(n, 1)
+    ref = orc.decode_links(3, links, 64, threads=8)
+    T, F, S = gpu.decode_errors(3, links, 64)
+    compare("L=3 exhaustive", T, F, S, ref)
+
+
+@pytest.mark.parametrize("L", [3, 4, 5, 6, 7, 8, 9, 12, 16, 20, 24, 31, 32, 48, 64, 96, 100, 128])
+@pytest.mark.parametrize("p", [0.02, 0.08])
+def test_sizes(gpu, orc, L, p):
+    """Every strip height of the resident kernel, odd and ragged sizes."""
+    n = 96 if L <= 64 else 24
+    s = seeds(40, int(p * 1000), n, start=L * 1000)
+    T_max = 512
+    T, F, S = gpu.decode_batch(L, p, s, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    compare(f"L={L} p={p}", T, F, S, ref)
+
+
+def test_config1_full(gpu, orc):
+    cfg = CONFIGS[1]
+    s = seeds(1, 0, cfg["n"])
+    T, F, S = gpu.decode_batch(cfg["L"], cfg["p"][0], s, cfg["T_max"])
+    ref = orc.decode_seeds(cfg["L"], cfg["p"][0], s, cfg["T_max"], threads=8)
+    compare("config 1", T, F, S, ref)
+
+
+def test_config2_full(gpu, orc):
+    cfg = CONFIGS[2]
+    for k, p in enumerate(cfg["p"]):
+        s = seeds(2, k, cfg["n"])
+        T, F, S = gpu.decode_batch(cfg["L"], p, s, cfg["T_max"])
+        ref = orc.decode_seeds(cfg["L"], p, s, cfg["T_max"], threads=8)
+        compare(f"config 2 p={p}", T, F, S, ref)
+
+
+def test_config3_sampled(gpu, orc):
+    """Full L=256 batch in the benchmark's launch shape; the oracle recomputes
+    a spread of samples one by one."""
+    cfg = CONFIGS[3]
+    n = cfg["n"]
+    s = seeds(3, 0, n)
+    T, F, S = gpu.decode_batch(cfg["L"], cfg["p"][0], s, cfg["T_max"])
+    pick = np.unique(np.concatenate([np.arange(0, n, 37), [n - 1]]))
+    ref = orc.decode_seeds(cfg["L"], cfg["p"][0], s[pick], cfg["T_max"], threads=8)
+    compare("config 3 sampled", T[pick], F[pick], S[pick], ref)
+
+
+@pytest.mark.parametrize("T_max", [0, 1, 2, 3, 5, 6, 7])
+def test_tiled_pass_boundaries(gpu, orc, T_max):
+    """L=256 at high p with budgets that end inside and at the end of passes."""
+    L, p, n = 256, 0.06, 12
+    s = seeds(41, T_max, n)
+    T, F, S = gpu.decode_batch(L, p, s, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    compare(f"tiled T_max={T_max}", T, F, S, ref)
+
+
+def test_tiled_long_decodes(gpu, orc):
+    """L=256 near threshold: many passes, timeouts and failures."""
+    L, p, n, T_max = 256, 0.07, 8, 64
+    s = seeds(42, 0, n)
+    T, F, S = gpu.decode_batch(L, p, s, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    compare("tiled long", T, F, S, ref)
+
+
+@pytest.mark.parametrize("L", [16, 256])
+def test_extreme_p(gpu, orc, L):
+    """p = 0 decodes in zero steps; p = 1 flips every link (no anyon, winding L mod 2)."""
+    s = seeds(43, 0, 8)
+    for p in (0.0, 1.0):
+        T, F, S = gpu.decode_batch(L, p, s, 64)
+        ref = orc.decode_seeds(L, p, s, 64)
+        compare(f"L={L} p={p}", T, F, S, ref)
+        assert np.all(_np(T) == 0)
+
+
+def test_threshold_boundary_word(gpu, orc):
+    """A link whose Philox word equals floor(p 2^32) must not flip."""
+    seed = 777
+    w = orc.philox4x32_10([0, 0, 0, 0], [seed, 0])
+    p = int(w[0]) / 2**32
+    for L in (16, 256):
+        T, F, S = gpu.decode_batch(L, p, [seed], 64)
+        ref = orc.decode_seeds(L, p, [seed], 64)
+        compare(f"boundary L={L}", T, F, S, ref)
+
+
+def test_permutation_invariance(gpu):
+    """Results per seed do not depend on batch order or batch size."""
+    for L in (64, 256):
+        s = seeds(44, 0, 200)
+        T, F, S = gpu.decode_batch(L, 0.02, s, 256)
+        perm = np.random.default_rng(0).permutation(200)
+        T2, F2, S2 = gpu.decode_batch(L, 0.02, s[perm], 256)
+        assert np.array_equal(_np(T)[perm], _np(T2))
+        assert np.array_equal(_np(F)[perm], _np(F2))
+        assert np.array_equal(_np(S)[perm], _np(S2))
+        T3, F3, S3 = gpu.decode_batch(L, 0.02, s[:7], 256)
+        assert np.array_equal(_np(T)[:7], _np(T3))
+
+
+@pytest.mark.parametrize("L,p", [(8, 0.08), (16, 0.05), (64, 0.03)])
+def test_run_steps_state(gpu, orc, L, p):
+    """Full decoder state after exactly t steps: registers (distance form),
+    syndrome and winding bits, against the oracle."""
+    for k, sd in enumerate(seeds(45, 0, 4)):
+        ex, ey = orc.noise(L, p, int(sd))
+        links = orc.links_from_chains(L, ex, ey)
+        for t in (0, 1, 2, 5, 9):
+            M, S, W = gpu.run_steps(L, links, t)
+            m, sig, (cx, cy), _ = orc.run_steps(L, ex, ey, t)
+            assert np.array_equal(_np(M)[0].astype(np.int32), m), (L, k, t)
+            want = orc.pack_bits((sig == -1).astype(np.uint8).reshape(-1))
+            assert np.array_equal(_np(S)[0].view(np.uint32), want), (L, k, t)
+            wx = lambda a: int(a[:, L - 1].sum() % 2)
+            wy = lambda a: int(a[L - 1, :].sum() % 2)
+            wb = wx(ex) | (wy(ey) << 1) | (wx(cx) << 2) | (wy(cy) << 3)
+            assert int(_np(W)[0]) == wb, (L, k, t)
+
+
+def test_empty_batch(gpu):
+    T, F, S = gpu.decode_batch(64, 0.01, np.zeros(0, dtype=np.uint64), 16)
+    assert T.numel() == 0
+    T, F, S = gpu.decode_batch(256, 0.01, np.zeros(0, dtype=np.uint64), 16)
+    assert T.numel() == 0
