@@ -24,6 +24,21 @@ L, P, N_SAMPLES, T_MAX = 256, 0.01, 4096, 4096
 BYTES_PER_SITE_UPDATE = 16.25   # 4 x int16 registers + 1 syndrome bit, read and written once per step
 HBM_PEAK_GBS = 8000.0
 METRIC = "decoded samples/s & site-updates/s at L=256, p=0.01 (plain vs learned-sched)"
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_tile_L256_p001.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_03266_amd", "csrc", f) for f in ("mpd.hip", "engine.h")]
+
+
+def measured_traffic():
+    """HBM bytes per k_tile launch from the committed rocprofv3 counter summary,
+    or None if the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(PROFILE_SUMMARY) as f:
+            summ = json.load(f)
+        sha = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()[:16]
+    except OSError:
+        return None
+    return summ["traffic_bytes_per_launch"] if summ.get("kernel_source_sha16") == sha else None
 
 
 def main():
@@ -32,7 +47,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=512)
+    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
@@ -51,6 +68,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.copy_calib:
+        nbytes = args.copy_calib << 20
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes, "copies": 3}))
+        return
 
     n, K, W = N_SAMPLES, args.steps, args.warmup
     batches = [torch.from_numpy(seeds(3, i % 256, n).view(np.int64)).to(dev) for i in range(W + K)]
@@ -115,7 +143,7 @@ def main():
         "timeouts": int(((F_all & 2) > 0).sum()),
         "roofline": {"bound": "hbm", "kernel": "k_tile",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE,
                      "launches": tile_launches, "avg_launch_ms": avg_launch_s * 1e3},
         "cpu_baseline": cpu,
