@@ -24,8 +24,8 @@ L, P, N_SAMPLES, T_MAX = 256, 0.01, 4096, 4096
 BYTES_PER_SITE_UPDATE = 16.25   # 4 x int16 registers + 1 syndrome bit, read and written once per step
 HBM_PEAK_GBS = 8000.0
 METRIC = "decoded samples/s & site-updates/s at L=256, p=0.01 (plain vs learned-sched)"
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_tile_L256_p001.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_03266_amd", "csrc", f) for f in ("mpd.hip", "engine.h")]
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_band_L256_p001.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_03266_amd", "csrc", f) for f in ("mpd.hip", "engine.h", "band.h")]
 
 
 def measured_traffic():
@@ -97,7 +97,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     b.profile(False)
-    tile_ms, tile_launches = b.profile_read("k_tile")
+    tile_ms, tile_launches = b.profile_read("k_band")
 
     T_all = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
     F_all = torch.cat([outs[i][1] for i in range(W, W + K)]).cpu().numpy()
@@ -141,7 +141,7 @@ def main():
         "max_T_dec": int(T_all.max()),
         "fail_rate": float((F_all & 1).mean()),
         "timeouts": int(((F_all & 2) > 0).sum()),
-        "roofline": {"bound": "hbm", "kernel": "k_tile",
+        "roofline": {"bound": "hbm", "kernel": "k_band",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE,

@@ -124,7 +124,7 @@ int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_
 /* Kernel timing for measurement (not needed for decoding).
  * mpd_profile(1) clears earlier records and starts recording a pair of HIP
  * events on the launch stream around every kernel launch of the library;
- * mpd_profile(0) stops recording (records are kept).  Names: "k_tile"
+ * mpd_profile(0) stops recording (records are kept).  Names: "k_band"
  * (one pass of k decoder steps over the L = 256 bands) and "k_resident"
  * (whole decode of small lattices).  Not thread-safe. */
 int mpd_profile(int enable);

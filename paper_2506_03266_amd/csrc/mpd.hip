@@ -4,13 +4,14 @@
 //  * resident: one workgroup holds a whole L x L sample in LDS/VGPRs and runs
 //    it from noise to termination with no HBM traffic for the state
 //    (L <= 128 with a strip height dividing L);
-//  * tiled (L = 256): each workgroup owns a full-height band of columns plus
-//    a halo of 4k columns on each side (k = decoder steps per pass: a step
-//    moves information by v = 3 sites for the messages plus 1 for the
-//    feedback), runs k steps on chip, and writes its band back to HBM.  The
-//    first pass generates the noise for its band in place.  Between passes a
-//    small kernel turns the per-step "anyons left" bits into T_dec and
-//    compacts the list of unfinished samples.
+//  * band (L = 256): each workgroup holds a full-height band of 128 columns
+//    in VGPRs (band.h), of which all but a halo of 4k columns on each side
+//    are its own (k = decoder steps per pass: a step moves information by
+//    v = 3 sites for the messages plus 1 for the feedback); it runs k steps
+//    on chip and writes its own columns back to HBM.  The first pass
+//    generates the noise for its band in place.  Between passes a small
+//    kernel turns the per-step "anyons left" bits into T_dec and compacts
+//    the list of unfinished samples.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -21,6 +22,7 @@
 #include <string>
 #include <vector>
 
+#include "band.h"
 #include "engine.h"
 #include "mpd.h"
 
@@ -168,116 +170,134 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Tiled path for L = 256: full-height bands, k steps per pass.
+// Band path: regions of 128 columns x 256 rows, k steps per pass.
 // ---------------------------------------------------------------------------
 
-constexpr int TILE_H = 16;    // rows per thread strip
-constexpr int TILE_RX = 64;   // region width including both halos
+constexpr int BAND_H = 16;                 // rows per wave
+constexpr int BAND_NW = 16;                // waves per workgroup
+constexpr int BAND_RX = 128;               // region columns (2 per lane)
+constexpr int BAND_RY = BAND_NW * BAND_H;  // region rows
+constexpr int TILE_H = BAND_H;             // rows per syndrome word pair in HBM
 
-struct TileArgs {
+struct BandArgs {
   int L;
   int first;        // 1: generate noise in place, 0: load state from src
   int k;            // decoder steps in this pass
   int t0;           // steps already done
-  int halo;         // columns of halo on each side
-  int tx;           // owned columns per tile
+  int hx, tx;       // column halo, owned columns per tile
+  int ntx;          // tiles along x
   const uint64_t *seeds;
   uint64_t thr;
-  const int32_t *active;  // sample index per grid.x
-  const uint2 *Esrc;
-  const uint16_t *Ssrc;
-  uint2 *Edst;
-  uint16_t *Sdst;
+  const int32_t *active;  // sample index per grid.y
+  const uint4 *Esrc;      // [n][L][L/2] site pairs (P0, Q0, P1, Q1)
+  const uint2 *Ssrc;      // [n][L/32][L/2] syndrome masks (s0, s1) of column pairs
+  uint4 *Edst;
+  uint2 *Sdst;
   uint32_t *alive;  // per sample: bit 0 anyons at pass start, bit j after step t0+j
-  uint32_t *wind;   // per sample winding bits (see k_resident)
+  uint32_t *wind;   // per sample winding bits: Wx(E), Wy(E), Wx(C), Wy(C)
   int *zero_count;  // counter to clear for the following compaction
 };
 
-template <int H>
-__global__ __launch_bounds__(1024) void k_tile(TileArgs a) {
+// The region spans the full height of the lattice (rows wrap), L == BAND_RY.
+__global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int L = a.L, RX = TILE_RX, NS = L / H;
-  uint2 *F = reinterpret_cast<uint2 *>(smem);
-  uint4 *MV = reinterpret_cast<uint4 *>(smem + (size_t)RX * L * sizeof(uint2));
-  uint32_t *red = reinterpret_cast<uint32_t *>(MV + (size_t)RX * NS);
-  const int sample = a.active[blockIdx.x];
-  const int tile = blockIdx.y;
-  const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tile == 0 && tid == 0) *a.zero_count = 0;
+  uint4 *BND = reinterpret_cast<uint4 *>(smem);        // [2][NW*2*64]
+  uint4 *MB = BND + 2 * BAND_NW * 2 * 64;              // [NW*64]
+  uint32_t *red = reinterpret_cast<uint32_t *>(MB + BAND_NW * 64);
+  constexpr int H = BAND_H;
+  const int L = a.L;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (scalar)
+  const int sample = a.active[blockIdx.y];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  if (threadIdx.x == 0) red[0] = 0u;
 
-  Geo g;
-  g.RX = RX;
-  g.c = tid % RX;
-  g.j = tid / RX;
-  g.y0 = g.j * H;
-  g.cl = g.c == 0 ? 0 : g.c - 1;           // clamped: the halo absorbs the edge
-  g.cr = g.c == RX - 1 ? RX - 1 : g.c + 1;
-  g.jd = g.j == 0 ? NS - 1 : g.j - 1;      // full height: rows wrap
-  g.ju = g.j == NS - 1 ? 0 : g.j + 1;
-  g.rowDn = g.y0 == 0 ? L - 1 : g.y0 - 1;
-  g.rowUp = g.y0 + H == L ? 0 : g.y0 + H;
-
-  const int tx0 = tile * a.tx;
-  int gx = tx0 - a.halo + g.c;
+  const int wdn = w == 0 ? BAND_NW - 1 : w - 1;
+  const int wup = w == BAND_NW - 1 ? 0 : w + 1;
+  // global column of this lane's first column, global row of the wave's first row
+  const int tx0 = blockIdx.x * a.tx;
+  int gx = tx0 - a.hx + 2 * lane;
   gx = gx < 0 ? gx + L : (gx >= L ? gx - L : gx);
+  const int gy = w * H;
   const int owned_w = min(a.tx, L - tx0);
-  const bool own = g.c >= a.halo && g.c < a.halo + owned_w;
+  const bool own = 2 * lane >= a.hx && 2 * lane < a.hx + owned_w;
+  const bool top = w == BAND_NW - 1;      // holds row L-1 (bit H-1)
+  const bool last_col = own && gx == L - 2;  // column L-1 is this lane's second column
 
-  if (tid == 0) red[0] = 0u;
+  BandLane<H> b;
   uint32_t wind = 0u;
-  uint32_t P[H], Q[H];
-  uint32_t sig;
-  const size_t base = (size_t)sample * L * L;
+  const size_t half_row = (size_t)L / 2;
+  const size_t sidx = ((size_t)sample * (L / TILE_H) + w) * half_row + (gx >> 1);
   if (a.first) {
     const uint64_t seed = a.seeds[sample];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    uint32_t exb = 0u, eyb = 0u;
+    uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      bool fx, fy;
-      site_noise((uint32_t)((g.y0 + h) * L + gx), k0, k1, a.thr, fx, fy);
-      exb |= (uint32_t)fx << h;
-      eyb |= (uint32_t)fy << h;
-      P[h] = 0u;
-      Q[h] = 0u;
+      const uint32_t i = (uint32_t)((gy + h) * L + gx);  // even: one block covers both columns
+      const Words4 r = philox4x32_10(i >> 1, k0, k1);
+      ex0 |= (uint32_t)((uint64_t)r.w0 < a.thr) << h;
+      ey0 |= (uint32_t)((uint64_t)r.w1 < a.thr) << h;
+      ex1 |= (uint32_t)((uint64_t)r.w2 < a.thr) << h;
+      ey1 |= (uint32_t)((uint64_t)r.w3 < a.thr) << h;
+      b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
       if (h & 1) __builtin_amdgcn_sched_barrier(0);
     }
-    if (own && gx == L - 1) wind ^= parity32(exb);
-    if (own && g.j == NS - 1) wind ^= ((eyb >> (H - 1)) & 1u) << 1;
-    sig = syndrome_from_links<H>(exb, eyb, MV, g);
+    if (last_col) wind ^= __popc(ex1) & 1u;
+    if (own && top) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;
+    MB[w * 64 + lane] = make_uint4(ey0, ey1, 0u, 0u);
+    __syncthreads();
+    const uint4 dn = MB[wdn * 64 + lane];  // y-links of the row below the strip
+    __syncthreads();
+    constexpr uint32_t F = full_mask<H>();
+    b.s0 = (ex0 ^ from_left(ex1) ^ ey0 ^ ((ey0 << 1) | (dn.x >> (H - 1)))) & F;
+    b.s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | (dn.y >> (H - 1)))) & F;
   } else {
+    const uint4 *E = a.Esrc + (size_t)sample * L * half_row;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      const uint2 e = a.Esrc[base + (size_t)(g.y0 + h) * L + gx];
-      P[h] = e.x;
-      Q[h] = e.y;
+      const uint4 e = E[(size_t)(gy + h) * half_row + (gx >> 1)];
+      b.P0[h] = e.x;
+      b.Q0[h] = e.y;
+      b.P1[h] = e.z;
+      b.Q1[h] = e.w;
     }
-    sig = a.Ssrc[((size_t)sample * NS + g.j) * L + gx];
+    const uint2 sv = a.Ssrc[sidx];
+    b.s0 = sv.x;
+    b.s1 = sv.y;
   }
 
-  uint32_t bits = __syncthreads_or(own && sig != 0u) ? 1u : 0u;
+  uint32_t bits = __syncthreads_or(own && (b.s0 | b.s1) != 0u) ? 1u : 0u;
+  uint4 *BND0 = BND, *BND1 = BND + BAND_NW * 2 * 64;
   for (int st = 0; st < a.k; ++st) {
-    const int t = a.t0 + st;
-#pragma unroll 1
-    for (int sub = 1; sub <= 3; ++sub) {
-      const uint32_t s = (uint32_t)(3 * t + sub);
-      substep<H>(P, Q, sig, s | (s << 16), F, g);
-    }
-    uint32_t xo, yo;
-    sig = feedback<H>(P, Q, sig, MV, g, xo, yo);
-    if (own && gx == L - 1) wind ^= parity32(xo) << 2;
-    if (own && g.j == NS - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
-    if (__syncthreads_or(own && sig != 0u)) bits |= 2u << st;
+    const uint32_t t3 = (uint32_t)(3 * (a.t0 + st));
+    const uint32_t rows = wave_rows<H>(b.s0, b.s1);
+    Moves mv = {{0u, 0u}, {0u, 0u}, {0u, 0u}, {0u, 0u}};
+    // three message updates; LDS boundary slots alternate between sub-steps
+    uint4 *slot_a = (st & 1) ? BND1 : BND0, *slot_b = (st & 1) ? BND0 : BND1;
+    if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16));
+    band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, mv);
+    if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16));
+    band_substep<H, false>(b, slot_b, w, wdn, wup, lane, rows, mv);
+    if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16));
+    band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, mv);
+    uint32_t xo[2], yo[2];
+    band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);
+    if (last_col) wind ^= (__popc(xo[1]) & 1u) << 2;
+    if (own && top) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
+    if (__syncthreads_or(own && (b.s0 | b.s1) != 0u)) bits |= 2u << st;
   }
 
   if (own) {
+    uint4 *E = a.Edst + (size_t)sample * L * half_row;
 #pragma unroll
-    for (int h = 0; h < H; ++h) a.Edst[base + (size_t)(g.y0 + h) * L + gx] = make_uint2(P[h], Q[h]);
-    a.Sdst[((size_t)sample * NS + g.j) * L + gx] = (uint16_t)sig;
+    for (int h = 0; h < H; ++h)
+      E[(size_t)(gy + h) * half_row + (gx >> 1)] = make_uint4(b.P0[h], b.Q0[h], b.P1[h], b.Q1[h]);
+    a.Sdst[sidx] = make_uint2(b.s0, b.s1);
   }
   if (wind) atomicXor(&red[0], wind);
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     if (bits) atomicOr(&a.alive[sample], bits);
     if (red[0]) atomicXor(&a.wind[sample], red[0]);
   }
@@ -320,28 +340,32 @@ __global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t 
   active[i] = (int32_t)i;
 }
 
-// flags and final syndrome (row-major bits) from the tiled state.
-__global__ void k_tile_export(int L, int64_t n, const uint8_t *status, const uint32_t *wind,
-                              const uint16_t *Slast, uint8_t *flags, uint32_t *syn) {
-  const int64_t s = blockIdx.x;
-  const int NS = L / TILE_H;
+// flags and final syndrome (row-major bits) from the band state.
+__global__ void k_band_export(int L, int64_t n, const uint8_t *status, const uint32_t *wind,
+                              const uint2 *Slast, uint8_t *flags, uint32_t *syn) {
+  const int64_t smp = blockIdx.x;
   const int64_t nw = (int64_t)L * L / 32;
-  const bool timeout = status[s] == 2;
+  const bool timeout = status[smp] == 2;
   if (threadIdx.x == 0) {
-    const uint32_t W = wind[s];
+    const uint32_t W = wind[smp];
     const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
-    flags[s] = (uint8_t)((fail | (timeout ? 1u : 0u)) | (timeout ? 2u : 0u));
+    flags[smp] = (uint8_t)((fail | (timeout ? 1u : 0u)) | (timeout ? 2u : 0u));
   }
   if (syn == nullptr) return;
-  for (int64_t w = threadIdx.x; w < nw; w += blockDim.x) {
+  const size_t half_row = (size_t)L / 2;
+  for (int64_t wd = threadIdx.x; wd < nw; wd += blockDim.x) {
     uint32_t word = 0u;
     if (timeout) {
-      const int64_t i0 = w * 32;
+      const int64_t i0 = wd * 32;
       const int y = (int)(i0 / L), x0 = (int)(i0 % L);
-      const uint16_t *col = Slast + ((size_t)s * NS + y / TILE_H) * L;
-      for (int b = 0; b < 32; ++b) word |= (uint32_t)((col[x0 + b] >> (y % TILE_H)) & 1u) << b;
+      const uint2 *row = Slast + ((size_t)smp * (L / TILE_H) + y / TILE_H) * half_row;
+      for (int bt = 0; bt < 32; ++bt) {
+        const int x = x0 + bt;
+        const uint2 m = row[x >> 1];
+        word |= (((x & 1) ? m.y : m.x) >> (y % TILE_H) & 1u) << bt;
+      }
     }
-    syn[s * nw + w] = word;
+    syn[smp * nw + wd] = word;
   }
 }
 
@@ -437,8 +461,8 @@ size_t resident_lds(int L, int H) {
   return (size_t)L * L * sizeof(uint2) + (size_t)L * (L / H) * sizeof(uint4) + 64;
 }
 
-size_t tile_lds(int L) {
-  return (size_t)TILE_RX * L * sizeof(uint2) + (size_t)TILE_RX * (L / TILE_H) * sizeof(uint4) + 64;
+size_t band_lds() {
+  return (size_t)2 * BAND_NW * 2 * 64 * sizeof(uint4) + (size_t)BAND_NW * 64 * sizeof(uint4) + 64;
 }
 
 template <int H>
@@ -479,11 +503,12 @@ bool resident_ok(int L) {
   return H > 0 && resident_lds(L, H) <= 160 * 1024;
 }
 
-bool tiled_ok(int L) { return L == 256; }
+// The band path covers the full height of the lattice with one region.
+bool tiled_ok(int L) { return L == BAND_RY; }
 
-struct TileWorkspace {
-  uint2 *E[2];
-  uint16_t *S[2];
+struct BandWorkspace {
+  uint4 *E[2];      // [n][L][L/2] register pairs
+  uint2 *S[2];      // [n][L/32][L/2] syndrome masks of column pairs
   uint32_t *alive, *wind;
   uint8_t *status;
   int32_t *active[2];
@@ -493,8 +518,8 @@ struct TileWorkspace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-TileWorkspace tile_layout(int L, int64_t n, void *base) {
-  TileWorkspace w;
+BandWorkspace band_layout(int L, int64_t n, void *base) {
+  BandWorkspace w;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     void *p = base ? (void *)((char *)base + off) : nullptr;
@@ -502,8 +527,8 @@ TileWorkspace tile_layout(int L, int64_t n, void *base) {
     return p;
   };
   const size_t sites = (size_t)n * L * L;
-  for (int b = 0; b < 2; ++b) w.E[b] = (uint2 *)take(sites * sizeof(uint2));
-  for (int b = 0; b < 2; ++b) w.S[b] = (uint16_t *)take((size_t)n * (L / TILE_H) * L * sizeof(uint16_t));
+  for (int b = 0; b < 2; ++b) w.E[b] = (uint4 *)take(sites * sizeof(uint2));
+  for (int b = 0; b < 2; ++b) w.S[b] = (uint2 *)take((size_t)n * (L / TILE_H) * (L / 2) * sizeof(uint2));
   w.alive = (uint32_t *)take((size_t)n * 4);
   w.wind = (uint32_t *)take((size_t)n * 4);
   w.status = (uint8_t *)take((size_t)n);
@@ -513,46 +538,47 @@ TileWorkspace tile_layout(int L, int64_t n, void *base) {
   return w;
 }
 
-// Decoder steps per pass: the first pass also generates the noise.
+// Decoder steps per pass.  With 128-column regions a halo of 4k (+2 in the
+// noise pass) leaves 92-96 owned columns, so L = 256 takes 3 tiles for k = 4
+// and k = 5.
 constexpr int K_FIRST = 4;
-constexpr int K_NEXT = 2;
+constexpr int K_NEXT = 5;
 
-int decode_tiled(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
-                 uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
-  TileWorkspace w = tile_layout(L, n, ws);
+int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+  BandWorkspace w = band_layout(L, n, ws);
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive,
                      w.wind, w.status, w.active[0]);
   HIP_TRY(hipGetLastError());
-  const size_t lds = tile_lds(L);
-  const int threads = TILE_RX * (L / TILE_H);
+  const size_t lds = band_lds();
   int t0 = 0, cur = 0, nact = (int)n;
   bool first = true;
   for (;;) {
     const int k = first ? min(K_FIRST, T_max) : min(K_NEXT, T_max - t0);
-    TileArgs ta;
-    ta.L = L;
-    ta.first = first ? 1 : 0;
-    ta.k = k;
-    ta.t0 = t0;
-    ta.halo = 4 * k + (first ? 1 : 0);
-    ta.tx = TILE_RX - 2 * ta.halo;
-    ta.seeds = d_seeds;
-    ta.thr = thr;
-    ta.active = w.active[cur];
-    ta.Esrc = w.E[cur];
-    ta.Ssrc = w.S[cur];
-    ta.Edst = w.E[cur ^ 1];
-    ta.Sdst = w.S[cur ^ 1];
-    ta.alive = w.alive;
-    ta.wind = w.wind;
-    ta.zero_count = &w.count[cur ^ 1];
-    const int ntiles = (L + ta.tx - 1) / ta.tx;
+    BandArgs ba;
+    ba.L = L;
+    ba.first = first ? 1 : 0;
+    ba.k = k;
+    ba.t0 = t0;
+    ba.hx = 4 * k + (first ? 2 : 0);
+    ba.tx = BAND_RX - 2 * ba.hx;
+    ba.ntx = (L + ba.tx - 1) / ba.tx;
+    ba.seeds = d_seeds;
+    ba.thr = thr;
+    ba.active = w.active[cur];
+    ba.Esrc = w.E[cur];
+    ba.Ssrc = w.S[cur];
+    ba.Edst = w.E[cur ^ 1];
+    ba.Sdst = w.S[cur ^ 1];
+    ba.alive = w.alive;
+    ba.wind = w.wind;
+    ba.zero_count = &w.count[cur ^ 1];
     {
-      ProfScope ps("k_tile", stream);
-      hipLaunchKernelGGL(k_tile<TILE_H>, dim3((unsigned)nact, (unsigned)ntiles), dim3(threads), lds, stream, ta);
+      ProfScope ps("k_band", stream);
+      hipLaunchKernelGGL(k_band, dim3((unsigned)ba.ntx, (unsigned)nact), dim3(BAND_NW * 64), lds, stream, ba);
     }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, ta.first, k,
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, ba.first, k,
                        t0, T_max, w.active[cur], nact, w.alive, d_T_dec, w.status, w.active[cur ^ 1],
                        &w.count[cur ^ 1]);
     HIP_TRY(hipGetLastError());
@@ -566,8 +592,7 @@ int decode_tiled(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_
     nact = h_count;
     if (nact == 0) break;
   }
-  // state of the last pass is in buffer `cur`
-  hipLaunchKernelGGL(k_tile_export, dim3((unsigned)n), dim3(256), 0, stream, L, n, w.status, w.wind, w.S[cur],
+  hipLaunchKernelGGL(k_band_export, dim3((unsigned)n), dim3(256), 0, stream, L, n, w.status, w.wind, w.S[cur],
                      d_flags, d_syn);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
@@ -597,7 +622,7 @@ const char *mpd_last_error(void) { return g_last_error.c_str(); }
 size_t mpd_workspace_bytes(int L, int64_t n) {
   if (n <= 0) return 0;
   if (resident_ok(L)) return 0;
-  if (tiled_ok(L)) return tile_layout(L, n, nullptr).bytes;
+  if (tiled_ok(L)) return band_layout(L, n, nullptr).bytes;
   return 0;
 }
 
@@ -634,7 +659,7 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
   if (ws_bytes < need || d_workspace == nullptr)
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
   if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
-  return decode_tiled(L, thr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
+  return decode_band(L, thr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
 }
 
 int mpd_profile(int enable) {
