@@ -121,6 +121,13 @@ int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int3
 int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
+/* Temporal blocking of the band path (L = 256): decoder steps run on chip per
+ * pass over HBM, in the first pass (which also generates the noise) and in
+ * later passes.  Results do not depend on it; speed does.  Each value in
+ * [1, 15]; defaults 4 and 2.  Process-wide, not thread-safe. */
+int mpd_set_band_schedule(int k_first, int k_next);
+int mpd_get_band_schedule(int *k_first, int *k_next);
+
 /* Kernel timing for measurement (not needed for decoding).
  * mpd_profile(1) clears earlier records and starts recording a pair of HIP
  * events on the launch stream around every kernel launch of the library;

@@ -46,6 +46,10 @@ def lib():
     L.mpd_decode_errors.restype = I
     L.mpd_run_steps.argtypes = [I, P, I64, I, P, P, P, P]
     L.mpd_run_steps.restype = I
+    L.mpd_set_band_schedule.argtypes = [I, I]
+    L.mpd_set_band_schedule.restype = I
+    L.mpd_get_band_schedule.argtypes = [P, P]
+    L.mpd_get_band_schedule.restype = I
     L.mpd_profile.argtypes = [I]
     L.mpd_profile.restype = I
     L.mpd_profile_read.argtypes = [ctypes.c_char_p, P, P]
@@ -160,3 +164,14 @@ def profile_read(kernel: str):
     cnt = ctypes.c_int64(0)
     _check(lib().mpd_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "mpd_profile_read")
     return ms.value, cnt.value
+
+
+def set_band_schedule(k_first: int, k_next: int):
+    """Decoder steps per pass of the band path (first pass with noise, later)."""
+    _check(lib().mpd_set_band_schedule(int(k_first), int(k_next)), "mpd_set_band_schedule")
+
+
+def get_band_schedule():
+    a, c = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().mpd_get_band_schedule(ctypes.byref(a), ctypes.byref(c)), "mpd_get_band_schedule")
+    return a.value, c.value

@@ -17,16 +17,17 @@
 
 namespace mpd {
 
-// Wave-wide DPP controls (GFX9): a lane whose source lies outside the wave
-// keeps its own value.
+// Wave-wide DPP controls (GFX9).  Lanes whose source lies outside the wave
+// read 0 (bound_ctrl), which lets the compiler fold the shift into the
+// consuming instruction; those edge lanes only feed the halo.
 constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i <- lane i+1
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i <- lane i-1
 
 __device__ __forceinline__ uint32_t from_left(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_WAVE_SHR1, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, DPP_WAVE_SHR1, 0xF, 0xF, true);
 }
 __device__ __forceinline__ uint32_t from_right(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_WAVE_SHL1, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, DPP_WAVE_SHL1, 0xF, 0xF, true);
 }
 
 // low 16 bits from a, high 16 bits from b
@@ -40,34 +41,30 @@ struct BandLane {
   uint32_t s0, s1;
 };
 
-// Moves of a strip's anyons: bit h of px[c] = the anyon in column c, row h
-// moves +x (likewise -x, +y, -y).
+// Moves of a strip's anyons: bit h + 16c of px = the anyon in column c
+// (0/1), row h moves +x (likewise -x, +y, -y).  H <= 16.
 struct Moves {
-  uint32_t px[2], mx[2], py[2], my[2];
+  uint32_t px, mx, py, my;
 };
 
-// Move decision of one site from its registers, branch-free (see engine.h).
-// Returns the moves as bits (bit 0 +x, bit 1 -x, bit 2 +y, bit 3 -y): the
-// largest emission time wins (smallest message), ties in the order -y, -x,
-// +x, +y, and no move if the opposite register on that axis ties.  `anyon`
-// is 0 or 1; non-anyon sites return 0.
-__device__ __forceinline__ uint32_t decide_site(uint32_t P, uint32_t Q, uint32_t anyon) {
-  const uint32_t vpx = P & 0xFFFFu, vmx = P >> 16, vpy = Q & 0xFFFFu, vmy = Q >> 16;
-  const uint32_t M = max(max(vpx, vmx), max(vpy, vmy));
-  const uint32_t ty = vmy == M, tx = vmx == M, sx = vpx == M, sy = vpy == M;
-  const uint32_t go_py = ty & (sy ^ 1u);
-  const uint32_t go_px = (ty ^ 1u) & tx & (sx ^ 1u);
-  const uint32_t go_mx = (ty ^ 1u) & (tx ^ 1u) & sx;
-  const uint32_t go_my = (ty ^ 1u) & (tx ^ 1u) & (sx ^ 1u);
-  const uint32_t code = go_px | (go_mx << 1) | (go_py << 2) | (go_my << 3);
-  return code & (0u - (anyon & (uint32_t)(M != 0u)));
-}
-
-__device__ __forceinline__ void add_moves(Moves &mv, int c, int h, uint32_t code) {
-  mv.px[c] |= (code & 1u) << h;
-  mv.mx[c] |= ((code >> 1) & 1u) << h;
-  mv.py[c] |= ((code >> 2) & 1u) << h;
-  mv.my[c] |= ((code >> 3) & 1u) << h;
+// Move decision of one site from its registers (see engine.h): the largest
+// emission time wins (smallest message), ties in the order -y, -x, +x, +y,
+// and no move if the opposite register on that axis ties.  Sets bit `bit`
+// of the mask of the chosen move; `anyon` gates it.
+__device__ __forceinline__ void decide_site(uint32_t P, uint32_t Q, bool anyon, uint32_t bit, Moves &mv) {
+  const uint32_t T = pmax(P, Q);  // (max(+x, +y), max(-x, -y))
+  const uint16_t M = max((uint16_t)T, (uint16_t)(T >> 16));
+  const bool sx = (uint16_t)P == M, tx = (uint16_t)(P >> 16) == M;
+  const bool sy = (uint16_t)Q == M, ty = (uint16_t)(Q >> 16) == M;
+  const bool ok = anyon && M != 0;
+  const bool go_py = ok && ty && !sy;
+  const bool go_px = ok && !ty && tx && !sx;
+  const bool go_mx = ok && !ty && !tx && sx;
+  const bool go_my = ok && !ty && !tx && !sx;
+  mv.py |= go_py ? bit : 0u;
+  mv.px |= go_px ? bit : 0u;
+  mv.mx |= go_mx ? bit : 0u;
+  mv.my |= go_my ? bit : 0u;
 }
 
 // Rows of the wave that hold an anyon in any lane (wave-uniform).
@@ -90,11 +87,13 @@ __device__ __forceinline__ void band_fold(BandLane<H> &b, uint32_t ss) {
   asm volatile("" : "+v"(b.s0), "+v"(b.s1));
 #pragma unroll
   for (int h = 0; h < H; ++h) {
-    const bool a0 = (b.s0 >> h) & 1u, a1 = (b.s1 >> h) & 1u;
-    b.P0[h] = a0 ? ss : b.P0[h];
-    b.Q0[h] = a0 ? ss : b.Q0[h];
-    b.P1[h] = a1 ? ss : b.P1[h];
-    b.Q1[h] = a1 ? ss : b.Q1[h];
+    // all-ones where row h holds an anyon (sign extension of bit h)
+    const uint32_t m0 = (uint32_t)((int32_t)(b.s0 << (31 - h)) >> 31);
+    const uint32_t m1 = (uint32_t)((int32_t)(b.s1 << (31 - h)) >> 31);
+    b.P0[h] = (ss & m0) | (b.P0[h] & ~m0);
+    b.Q0[h] = (ss & m0) | (b.Q0[h] & ~m0);
+    b.P1[h] = (ss & m1) | (b.P1[h] & ~m1);
+    b.Q1[h] = (ss & m1) | (b.Q1[h] & ~m1);
   }
 }
 
@@ -153,8 +152,8 @@ __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, 
     hq0c = hq0n;
     hq1c = hq1n;
     if (DECIDE && ((rows >> h) & 1u)) {  // wave-uniform: rows holding an anyon
-      add_moves(mv, 0, h, decide_site(b.P0[h], b.Q0[h], (b.s0 >> h) & 1u));
-      add_moves(mv, 1, h, decide_site(b.P1[h], b.Q1[h], (b.s1 >> h) & 1u));
+      decide_site(b.P0[h], b.Q0[h], (b.s0 >> h) & 1u, 1u << h, mv);
+      decide_site(b.P1[h], b.Q1[h], (b.s1 >> h) & 1u, 1u << (16 + h), mv);
     }
   }
 }
@@ -165,25 +164,28 @@ __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, 
 // flipped x-links to the right of column c, yo[c] the flipped y-links above
 // each row of column c.
 template <int H>
-__device__ __forceinline__ void band_feedback(BandLane<H> &b, const Moves &mv, uint4 *MB, int w, int wdn,
+__device__ __forceinline__ void band_feedback(BandLane<H> &b, const Moves &mv, uint2 *MB, int w, int wdn,
                                               int wup, int lane, uint32_t (&xo)[2], uint32_t (&yo)[2]) {
-  MB[w * 64 + lane] = make_uint4(mv.py[0], mv.py[1], mv.my[0], mv.my[1]);
+  static_assert(H <= 16, "move masks hold 16 rows per column");
+  MB[w * 64 + lane] = make_uint2(mv.py, mv.my);
   __syncthreads();
-  const uint4 upm = MB[wup * 64 + lane];  // wave above: bit 0 of its my = its first row moves -y
-  const uint4 dnm = MB[wdn * 64 + lane];  // wave below: bit H-1 of its py = its last row moves +y
+  const uint32_t upmy = MB[wup * 64 + lane].y;  // wave above: bit 16c = its first row moves -y
+  const uint32_t dnpy = MB[wdn * 64 + lane].x;  // wave below: bit 16c+H-1 = its last row moves +y
   constexpr uint32_t F = full_mask<H>();
   // x-links: column 2i -> 2i+1 and column 2i+1 -> 2i+2 (next lane's column 2i)
-  xo[0] = mv.px[0] | mv.mx[1];
-  xo[1] = mv.px[1] | from_right(mv.mx[0]);
+  xo[0] = (mv.px | (mv.mx >> 16)) & F;
+  xo[1] = ((mv.px >> 16) | from_right(mv.mx)) & F;
   const uint32_t xl0 = from_left(xo[1]), xl1 = xo[0];
   {
-    const uint32_t yd = ((mv.py[0] << 1) | ((dnm.x >> (H - 1)) & 1u) | mv.my[0]) & F;
-    yo[0] = (mv.py[0] | (mv.my[0] >> 1) | ((upm.z & 1u) << (H - 1))) & F;
+    const uint32_t py = mv.py & F, my = mv.my & F;
+    const uint32_t yd = ((py << 1) | ((dnpy >> (H - 1)) & 1u) | my) & F;
+    yo[0] = (py | (my >> 1) | ((upmy & 1u) << (H - 1))) & F;
     b.s0 = (b.s0 ^ xo[0] ^ xl0 ^ yo[0] ^ yd) & F;
   }
   {
-    const uint32_t yd = ((mv.py[1] << 1) | ((dnm.y >> (H - 1)) & 1u) | mv.my[1]) & F;
-    yo[1] = (mv.py[1] | (mv.my[1] >> 1) | ((upm.w & 1u) << (H - 1))) & F;
+    const uint32_t py = (mv.py >> 16) & F, my = (mv.my >> 16) & F;
+    const uint32_t yd = ((py << 1) | ((dnpy >> (16 + H - 1)) & 1u) | my) & F;
+    yo[1] = (py | (my >> 1) | (((upmy >> 16) & 1u) << (H - 1))) & F;
     b.s1 = (b.s1 ^ xo[1] ^ xl1 ^ yo[1] ^ yd) & F;
   }
 }

@@ -202,7 +202,7 @@ struct BandArgs {
 __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint4 *BND = reinterpret_cast<uint4 *>(smem);        // [2][NW*2*64]
-  uint4 *MB = BND + 2 * BAND_NW * 2 * 64;              // [NW*64]
+  uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * BAND_NW * 2 * 64);  // [NW*64]
   uint32_t *red = reinterpret_cast<uint32_t *>(MB + BAND_NW * 64);
   constexpr int H = BAND_H;
   const int L = a.L;
@@ -245,9 +245,9 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
     }
     if (last_col) wind ^= __popc(ex1) & 1u;
     if (own && top) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;
-    MB[w * 64 + lane] = make_uint4(ey0, ey1, 0u, 0u);
+    MB[w * 64 + lane] = make_uint2(ey0, ey1);
     __syncthreads();
-    const uint4 dn = MB[wdn * 64 + lane];  // y-links of the row below the strip
+    const uint2 dn = MB[wdn * 64 + lane];  // y-links of the row below the strip
     __syncthreads();
     constexpr uint32_t F = full_mask<H>();
     b.s0 = (ex0 ^ from_left(ex1) ^ ey0 ^ ((ey0 << 1) | (dn.x >> (H - 1)))) & F;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   for (int st = 0; st < a.k; ++st) {
     const uint32_t t3 = (uint32_t)(3 * (a.t0 + st));
     const uint32_t rows = wave_rows<H>(b.s0, b.s1);
-    Moves mv = {{0u, 0u}, {0u, 0u}, {0u, 0u}, {0u, 0u}};
+    Moves mv = {0u, 0u, 0u, 0u};
     // three message updates; LDS boundary slots alternate between sub-steps
     uint4 *slot_a = (st & 1) ? BND1 : BND0, *slot_b = (st & 1) ? BND0 : BND1;
     if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16));
@@ -462,7 +462,7 @@ size_t resident_lds(int L, int H) {
 }
 
 size_t band_lds() {
-  return (size_t)2 * BAND_NW * 2 * 64 * sizeof(uint4) + (size_t)BAND_NW * 64 * sizeof(uint4) + 64;
+  return (size_t)2 * BAND_NW * 2 * 64 * sizeof(uint4) + (size_t)BAND_NW * 64 * sizeof(uint2) + 64;
 }
 
 template <int H>
@@ -538,11 +538,15 @@ BandWorkspace band_layout(int L, int64_t n, void *base) {
   return w;
 }
 
-// Decoder steps per pass.  With 128-column regions a halo of 4k (+2 in the
-// noise pass) leaves 92-96 owned columns, so L = 256 takes 3 tiles for k = 4
-// and k = 5.
-constexpr int K_FIRST = 4;
-constexpr int K_NEXT = 5;
+// Decoder steps per pass (first pass with the noise, later passes).  With
+// 128-column regions a halo of 4k (+2 in the noise pass) leaves 128 - 2*halo
+// owned columns per tile: L = 256 takes 3 tiles for k <= 4 in the noise
+// pass and k <= 5 later.
+struct BandSchedule {
+  int k_first = 4;
+  int k_next = 2;
+};
+BandSchedule g_band_schedule;
 
 int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
                 uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
@@ -554,7 +558,7 @@ int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_m
   int t0 = 0, cur = 0, nact = (int)n;
   bool first = true;
   for (;;) {
-    const int k = first ? min(K_FIRST, T_max) : min(K_NEXT, T_max - t0);
+    const int k = first ? min(g_band_schedule.k_first, T_max) : min(g_band_schedule.k_next, T_max - t0);
     BandArgs ba;
     ba.L = L;
     ba.first = first ? 1 : 0;
@@ -691,6 +695,24 @@ int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
   }
   *total_ms = ms;
   *launches = cnt;
+  return MPD_OK;
+}
+
+int mpd_set_band_schedule(int k_first, int k_next) {
+  g_last_error.clear();
+  // the halo 4k (+2) must leave owned columns in a 128-column region
+  if (k_first < 1 || k_next < 1 || 4 * k_first + 2 >= BAND_RX / 2 || 4 * k_next >= BAND_RX / 2)
+    return fail_with(MPD_ERR_TMAX, "steps per pass must be in [1, 15]");
+  g_band_schedule.k_first = k_first;
+  g_band_schedule.k_next = k_next;
+  return MPD_OK;
+}
+
+int mpd_get_band_schedule(int *k_first, int *k_next) {
+  g_last_error.clear();
+  if (k_first == nullptr || k_next == nullptr) return fail_with(MPD_ERR_PTR, "NULL output");
+  *k_first = g_band_schedule.k_first;
+  *k_next = g_band_schedule.k_next;
   return MPD_OK;
 }
 
