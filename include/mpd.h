@@ -59,7 +59,7 @@ extern "C" {
 #endif
 
 #define MPD_OK 0
-#define MPD_ERR_L (-1)         /* L outside [3, 1024] or unsupported for the call */
+#define MPD_ERR_L (-1)         /* L unsupported for the call */
 #define MPD_ERR_P (-2)         /* p is NaN or outside [0, 1] */
 #define MPD_ERR_TMAX (-3)      /* T_max (or t_exact) outside [0, MPD_T_MAX_LIMIT] */
 #define MPD_ERR_PTR (-4)       /* a required pointer is NULL or misaligned */
@@ -81,7 +81,7 @@ const char *mpd_version(void);
 const char *mpd_last_error(void);
 
 /* Bytes of device workspace that a decode of n samples of size L needs
- * (0 if none).  Lattices up to L = 128 decode entirely on chip; larger ones
+ * (0 if none).  Lattices up to L = 128 decode entirely on chip; from 256 on
  * keep two copies of the per-site state (8 B of registers + 1 bit of
  * syndrome per site) plus per-sample bookkeeping. */
 size_t mpd_workspace_bytes(int L, int64_t n);
@@ -95,7 +95,9 @@ size_t mpd_workspace_bytes(int L, int64_t n);
  *                      (all zero for a decoded sample); may be NULL
  *   d_workspace        >= mpd_workspace_bytes(L, n) bytes, 256-byte aligned
  *                      (may be NULL when that size is 0)
- * Supported L: 3 <= L <= 128 (any), and L = 256. */
+ * Supported L: 3 <= L <= 128 when a strip height H <= 16 divides L with
+ * L*L/H <= 1024 threads (every L <= 32, and e.g. 48, 64, 96, 100, 128), and
+ * multiples of 16 from 256 to 16384. */
 int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max,
                      int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
                      void *d_workspace, size_t ws_bytes, void *stream);

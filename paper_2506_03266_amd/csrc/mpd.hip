@@ -185,6 +185,7 @@ struct BandArgs {
   int k;            // decoder steps in this pass
   int t0;           // steps already done
   int hx, tx;       // column halo, owned columns per tile
+  int hy, ty;       // row halo, owned rows per tile (ty == L: one full-height region, rows wrap)
   int ntx;          // tiles along x
   const uint64_t *seeds;
   uint64_t thr;
@@ -198,13 +199,15 @@ struct BandArgs {
   int *zero_count;  // counter to clear for the following compaction
 };
 
-// The region spans the full height of the lattice (rows wrap), L == BAND_RY.
+// With ty == L the region spans the full height (L == BAND_RY, rows wrap);
+// otherwise regions overlap by hy rows (a multiple of 16) above and below.
 __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint4 *BND = reinterpret_cast<uint4 *>(smem);        // [2][NW*2*64]
+  uint4 *BND = reinterpret_cast<uint4 *>(smem);                        // [2][NW*2*64]
   uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * BAND_NW * 2 * 64);  // [NW*64]
   uint32_t *red = reinterpret_cast<uint32_t *>(MB + BAND_NW * 64);
   constexpr int H = BAND_H;
+  constexpr uint32_t F = full_mask<H>();
   const int L = a.L;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (scalar)
@@ -212,22 +215,34 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
   if (threadIdx.x == 0) red[0] = 0u;
 
-  const int wdn = w == 0 ? BAND_NW - 1 : w - 1;
-  const int wup = w == BAND_NW - 1 ? 0 : w + 1;
+  const bool wrapY = a.ty == L;
+  const int tix = blockIdx.x % a.ntx, tiy = blockIdx.x / a.ntx;
+  const int wdn = w == 0 ? (wrapY ? BAND_NW - 1 : 0) : w - 1;
+  const int wup = w == BAND_NW - 1 ? (wrapY ? 0 : BAND_NW - 1) : w + 1;
   // global column of this lane's first column, global row of the wave's first row
-  const int tx0 = blockIdx.x * a.tx;
+  const int tx0 = tix * a.tx, ty0 = tiy * a.ty;
   int gx = tx0 - a.hx + 2 * lane;
   gx = gx < 0 ? gx + L : (gx >= L ? gx - L : gx);
-  const int gy = w * H;
+  int gy = (wrapY ? 0 : ty0 - a.hy) + w * H;
+  gy = gy < 0 ? gy + L : (gy >= L ? gy - L : gy);
   const int owned_w = min(a.tx, L - tx0);
-  const bool own = 2 * lane >= a.hx && 2 * lane < a.hx + owned_w;
-  const bool top = w == BAND_NW - 1;      // holds row L-1 (bit H-1)
-  const bool last_col = own && gx == L - 2;  // column L-1 is this lane's second column
+  const bool own_col = 2 * lane >= a.hx && 2 * lane < a.hx + owned_w;
+  // owned rows of this wave (wave-uniform); a strip never straddles row L-1 -> 0
+  const int owned_h = wrapY ? L : min(a.ty, L - ty0);
+  const int r0 = w * H - (wrapY ? 0 : a.hy);  // region row offset of the strip from the owned block
+  uint32_t own_rows = 0u;
+  if (r0 >= 0 && r0 + H <= owned_h) own_rows = F;
+  else if (r0 + H > 0 && r0 < owned_h)
+    for (int h = 0; h < H; ++h) own_rows |= (uint32_t)(r0 + h >= 0 && r0 + h < owned_h) << h;
+  own_rows = __builtin_amdgcn_readfirstlane(own_rows);
+  const bool own = own_col && own_rows != 0u;
+  const bool top = gy == L - H && ((own_rows >> (H - 1)) & 1u);  // owns row L-1 (bit H-1)
+  const bool last_col = own_col && gx == L - 2;                   // column L-1 is the second column
 
   BandLane<H> b;
   uint32_t wind = 0u;
   const size_t half_row = (size_t)L / 2;
-  const size_t sidx = ((size_t)sample * (L / TILE_H) + w) * half_row + (gx >> 1);
+  const size_t sidx = ((size_t)sample * (L / TILE_H) + gy / TILE_H) * half_row + (gx >> 1);
   if (a.first) {
     const uint64_t seed = a.seeds[sample];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -243,8 +258,8 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
       b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
       if (h & 1) __builtin_amdgcn_sched_barrier(0);
     }
-    if (last_col) wind ^= __popc(ex1) & 1u;
-    if (own && top) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;
+    if (last_col) wind ^= __popc(ex1 & own_rows) & 1u;
+    if (own_col && top) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;
     MB[w * 64 + lane] = make_uint2(ey0, ey1);
     __syncthreads();
     const uint2 dn = MB[wdn * 64 + lane];  // y-links of the row below the strip
@@ -267,7 +282,8 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
     b.s1 = sv.y;
   }
 
-  uint32_t bits = __syncthreads_or(own && (b.s0 | b.s1) != 0u) ? 1u : 0u;
+  const uint32_t own_mask = own_col ? own_rows : 0u;
+  uint32_t bits = __syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u) ? 1u : 0u;
   uint4 *BND0 = BND, *BND1 = BND + BAND_NW * 2 * 64;
   for (int st = 0; st < a.k; ++st) {
     const uint32_t t3 = (uint32_t)(3 * (a.t0 + st));
@@ -283,16 +299,18 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
     band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, mv);
     uint32_t xo[2], yo[2];
     band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);
-    if (last_col) wind ^= (__popc(xo[1]) & 1u) << 2;
-    if (own && top) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
-    if (__syncthreads_or(own && (b.s0 | b.s1) != 0u)) bits |= 2u << st;
+    if (last_col) wind ^= (__popc(xo[1] & own_rows) & 1u) << 2;
+    if (own_col && top) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
+    if (__syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u)) bits |= 2u << st;
   }
 
   if (own) {
     uint4 *E = a.Edst + (size_t)sample * L * half_row;
 #pragma unroll
     for (int h = 0; h < H; ++h)
-      E[(size_t)(gy + h) * half_row + (gx >> 1)] = make_uint4(b.P0[h], b.Q0[h], b.P1[h], b.Q1[h]);
+      if ((own_rows >> h) & 1u)
+        E[(size_t)(gy + h) * half_row + (gx >> 1)] = make_uint4(b.P0[h], b.Q0[h], b.P1[h], b.Q1[h]);
+    // hy and ty are multiples of 16, so an owned strip is always whole
     a.Sdst[sidx] = make_uint2(b.s0, b.s1);
   }
   if (wind) atomicXor(&red[0], wind);
@@ -344,7 +362,7 @@ __global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t 
 __global__ void k_band_export(int L, int64_t n, const uint8_t *status, const uint32_t *wind,
                               const uint2 *Slast, uint8_t *flags, uint32_t *syn) {
   const int64_t smp = blockIdx.x;
-  const int64_t nw = (int64_t)L * L / 32;
+  const int64_t nw = ((int64_t)L * L + 31) / 32;
   const bool timeout = status[smp] == 2;
   if (threadIdx.x == 0) {
     const uint32_t W = wind[smp];
@@ -356,12 +374,10 @@ __global__ void k_band_export(int L, int64_t n, const uint8_t *status, const uin
   for (int64_t wd = threadIdx.x; wd < nw; wd += blockDim.x) {
     uint32_t word = 0u;
     if (timeout) {
-      const int64_t i0 = wd * 32;
-      const int y = (int)(i0 / L), x0 = (int)(i0 % L);
-      const uint2 *row = Slast + ((size_t)smp * (L / TILE_H) + y / TILE_H) * half_row;
       for (int bt = 0; bt < 32; ++bt) {
-        const int x = x0 + bt;
-        const uint2 m = row[x >> 1];
+        const int64_t i = wd * 32 + bt;
+        const int y = (int)(i / L), x = (int)(i % L);
+        const uint2 m = Slast[((size_t)smp * (L / TILE_H) + y / TILE_H) * half_row + (x >> 1)];
         word |= (((x & 1) ? m.y : m.x) >> (y % TILE_H) & 1u) << bt;
       }
     }
@@ -503,8 +519,8 @@ bool resident_ok(int L) {
   return H > 0 && resident_lds(L, H) <= 160 * 1024;
 }
 
-// The band path covers the full height of the lattice with one region.
-bool tiled_ok(int L) { return L == BAND_RY; }
+// The band path: L = 256 (one full-height region) or larger multiples of 16.
+bool tiled_ok(int L) { return L >= BAND_RY && L % TILE_H == 0 && L <= 16384; }
 
 struct BandWorkspace {
   uint4 *E[2];      // [n][L][L/2] register pairs
@@ -566,7 +582,15 @@ int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_m
     ba.t0 = t0;
     ba.hx = 4 * k + (first ? 2 : 0);
     ba.tx = BAND_RX - 2 * ba.hx;
+    if (L == BAND_RY) {
+      ba.hy = 0;
+      ba.ty = L;
+    } else {  // row halo of 4k (+1 in the noise pass), rounded up to whole 16-row strips
+      ba.hy = (4 * k + (first ? 1 : 0) + TILE_H - 1) / TILE_H * TILE_H;
+      ba.ty = BAND_RY - 2 * ba.hy;
+    }
     ba.ntx = (L + ba.tx - 1) / ba.tx;
+    const int nty = (L + ba.ty - 1) / ba.ty;
     ba.seeds = d_seeds;
     ba.thr = thr;
     ba.active = w.active[cur];
@@ -579,7 +603,8 @@ int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_m
     ba.zero_count = &w.count[cur ^ 1];
     {
       ProfScope ps("k_band", stream);
-      hipLaunchKernelGGL(k_band, dim3((unsigned)ba.ntx, (unsigned)nact), dim3(BAND_NW * 64), lds, stream, ba);
+      hipLaunchKernelGGL(k_band, dim3((unsigned)(ba.ntx * nty), (unsigned)nact), dim3(BAND_NW * 64), lds, stream,
+                         ba);
     }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, ba.first, k,

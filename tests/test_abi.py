@@ -45,7 +45,8 @@ def test_version_and_workspace(lib):
 
 
 @pytest.mark.parametrize("L,p,n,T,code", [
-    (2, 0.1, 1, 8, -1), (1025, 0.1, 1, 8, -1), (200, 0.1, 1, 8, -1),
+    (2, 0.1, 1, 8, -1), (1025, 0.1, 1, 8, -1), (200, 0.1, 1, 8, -1), (127, 0.1, 1, 8, -1),
+    (16400, 0.1, 1, 8, -1),
     (16, -0.1, 1, 8, -2), (16, 1.5, 1, 8, -2), (16, float("nan"), 1, 8, -2),
     (16, 0.1, 1, -1, -3), (16, 0.1, 1, 10923, -3),
     (16, 0.1, -1, 8, -7),

@@ -135,7 +135,18 @@ def test_tiled_long_decodes(gpu, orc):
     compare("tiled long", T, F, S, ref)
 
 
-@pytest.mark.parametrize("L", [16, 256])
+@pytest.mark.parametrize("L,p,n,T_max", [(272, 0.03, 6, 64), (320, 0.06, 4, 40), (512, 0.02, 4, 64),
+                                         (512, 0.07, 3, 9), (1024, 0.01, 3, 64)])
+def test_band_2d_tiles(gpu, orc, L, p, n, T_max):
+    """Lattices taller than one region: tiles with row halos, ragged last tiles,
+    widths that are not multiples of 32, budgets ending inside a pass."""
+    s = seeds(46, L, n)
+    T, F, S = gpu.decode_batch(L, p, s, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    compare(f"L={L} p={p}", T, F, S, ref)
+
+
+@pytest.mark.parametrize("L", [16, 256, 512])
 def test_extreme_p(gpu, orc, L):
     """p = 0 decodes in zero steps; p = 1 flips every link (no anyon, winding L mod 2)."""
     s = seeds(43, 0, 8)
