@@ -123,12 +123,43 @@ int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int3
 int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
-/* Temporal blocking of the band path (L = 256): decoder steps run on chip per
+/* Temporal blocking of the band path (L >= 256): decoder steps run on chip per
  * pass over HBM, in the first pass (which also generates the noise) and in
  * later passes.  Results do not depend on it; speed does.  Each value in
- * [1, 15]; defaults 4 and 2.  Process-wide, not thread-safe. */
-int mpd_set_band_schedule(int k_first, int k_next);
-int mpd_get_band_schedule(int *k_first, int *k_next);
+ * [1, 15].  L = 0 sets the default for every L and forgets per-L settings;
+ * otherwise the setting applies to that L only (defaults 4 and 2).
+ * Process-wide, guarded by a mutex. */
+int mpd_set_band_schedule(int L, int k_first, int k_next);
+int mpd_get_band_schedule(int L, int *k_first, int *k_next);
+
+/* Autotuner for the band path: decodes the probe batch (same arguments as
+ * mpd_decode_batch, outputs overwritten) once per candidate schedule
+ * k_first in [2, 6] x k_next in [1, 4], timing each with HIP events on
+ * `stream`, and keeps the fastest for this L (mpd_get_band_schedule then
+ * returns it).  *k_first, *k_next and *best_ms receive the choice.
+ * Synchronizes `stream`. */
+int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                      uint8_t *d_flags, void *d_workspace, size_t ws_bytes, void *stream, int *k_first,
+                      int *k_next, float *best_ms);
+
+/* Mixed batch: samples of several lattice sizes and per-sample noise
+ * strengths in one call.
+ *   n_classes, h_L, h_count   host arrays: class c has h_count[c] samples of
+ *                             size h_L[c]; samples are ordered by class
+ *   d_p, d_seeds              [n] per-sample noise strength and seed
+ *   d_T_dec, d_flags          [n] as in mpd_decode_batch
+ *   d_final_syndrome          concatenation over classes of
+ *                             [h_count[c]][ceil(L_c^2/32)] words; may be NULL
+ *   d_workspace               >= mpd_mixed_workspace_bytes(...)
+ * Classes up to L = 128 run as one launch each on a library-owned side
+ * stream forked from `stream` (one workgroup per sample, early exit per
+ * sample); larger classes run the band path on `stream`; the call returns
+ * after both have been joined into `stream` (the band path synchronizes
+ * `stream`).  Every p in [0, 1]; errors as mpd_decode_batch. */
+size_t mpd_mixed_workspace_bytes(int n_classes, const int32_t *h_L, const int64_t *h_count);
+int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, const double *d_p,
+                     const uint64_t *d_seeds, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
+                     uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream);
 
 /* Kernel timing for measurement (not needed for decoding).
  * mpd_profile(1) clears earlier records and starts recording a pair of HIP

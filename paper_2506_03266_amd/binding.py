@@ -46,10 +46,16 @@ def lib():
     L.mpd_decode_errors.restype = I
     L.mpd_run_steps.argtypes = [I, P, I64, I, P, P, P, P]
     L.mpd_run_steps.restype = I
-    L.mpd_set_band_schedule.argtypes = [I, I]
+    L.mpd_set_band_schedule.argtypes = [I, I, I]
     L.mpd_set_band_schedule.restype = I
-    L.mpd_get_band_schedule.argtypes = [P, P]
+    L.mpd_get_band_schedule.argtypes = [I, P, P]
     L.mpd_get_band_schedule.restype = I
+    L.mpd_autotune_band.argtypes = [I, D, P, I64, I, P, P, P, SZ, P, P, P, P]
+    L.mpd_autotune_band.restype = I
+    L.mpd_mixed_workspace_bytes.argtypes = [I, P, P]
+    L.mpd_mixed_workspace_bytes.restype = SZ
+    L.mpd_decode_mixed.argtypes = [I, P, P, P, P, I, P, P, P, P, SZ, P]
+    L.mpd_decode_mixed.restype = I
     L.mpd_profile.argtypes = [I]
     L.mpd_profile.restype = I
     L.mpd_profile_read.argtypes = [ctypes.c_char_p, P, P]
@@ -166,12 +172,58 @@ def profile_read(kernel: str):
     return ms.value, cnt.value
 
 
-def set_band_schedule(k_first: int, k_next: int):
-    """Decoder steps per pass of the band path (first pass with noise, later)."""
-    _check(lib().mpd_set_band_schedule(int(k_first), int(k_next)), "mpd_set_band_schedule")
+def set_band_schedule(k_first: int, k_next: int, L: int = 0):
+    """Decoder steps per pass of the band path (first pass with noise, later);
+    L = 0 sets the default for every L."""
+    _check(lib().mpd_set_band_schedule(int(L), int(k_first), int(k_next)), "mpd_set_band_schedule")
 
 
-def get_band_schedule():
+def get_band_schedule(L: int = 0):
     a, c = ctypes.c_int(0), ctypes.c_int(0)
-    _check(lib().mpd_get_band_schedule(ctypes.byref(a), ctypes.byref(c)), "mpd_get_band_schedule")
+    _check(lib().mpd_get_band_schedule(int(L), ctypes.byref(a), ctypes.byref(c)), "mpd_get_band_schedule")
     return a.value, c.value
+
+
+def autotune_band(L: int, p: float, seeds, T_max: int = 4096, stream=None):
+    """Time the band-path schedules on a probe batch and keep the fastest for L.
+    Returns (k_first, k_next, best_ms)."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    T = torch.empty(n, dtype=torch.int32, device=dev)
+    F = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = alloc_workspace(L, n)
+    kf, kn, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0.0)
+    rc = lib().mpd_autotune_band(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(ws), ws.numel(),
+                                 _stream_ptr(stream), ctypes.byref(kf), ctypes.byref(kn), ctypes.byref(ms))
+    _check(rc, "mpd_autotune_band")
+    return kf.value, kn.value, ms.value
+
+
+def decode_mixed(classes, p, seeds, T_max: int = 4096, want_syndrome: bool = True, workspace=None, out=None,
+                 stream=None):
+    """Decode a batch ordered by class: classes = [(L, count), ...], p and seeds
+    per sample.  Returns (T_dec, flags, syndrome words concatenated by class)."""
+    dev = torch.device("cuda")
+    hL = np.ascontiguousarray([c[0] for c in classes], dtype=np.int32)
+    hC = np.ascontiguousarray([c[1] for c in classes], dtype=np.int64)
+    n = int(hC.sum())
+    s = _seeds_tensor(seeds, dev)
+    pt = p if isinstance(p, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(p, dtype=np.float64))
+    pt = pt.to(dev, dtype=torch.float64).contiguous()
+    assert s.numel() == n and pt.numel() == n
+    W = int(sum(c * syndrome_words(L) for L, c in zip(hL, hC)))
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        S = torch.empty(W, dtype=torch.int32, device=dev) if want_syndrome else None
+    else:
+        T, F, S = out
+    nb = int(lib().mpd_mixed_workspace_bytes(len(hL), hL.ctypes.data_as(ctypes.c_void_p),
+                                             hC.ctypes.data_as(ctypes.c_void_p)))
+    ws = workspace if workspace is not None else torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    rc = lib().mpd_decode_mixed(len(hL), hL.ctypes.data_as(ctypes.c_void_p), hC.ctypes.data_as(ctypes.c_void_p),
+                                _ptr(pt), _ptr(s), int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws), ws.numel(),
+                                _stream_ptr(stream))
+    _check(rc, "mpd_decode_mixed")
+    return T, F, S

@@ -19,6 +19,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,7 +39,8 @@ struct ResidentArgs {
   int L;
   int64_t n;
   const uint64_t *seeds;   // seeded mode when links == nullptr
-  uint64_t thr;
+  uint64_t thr;            // flip threshold floor(p 2^32) when p_arr == nullptr
+  const double *p_arr;     // per-sample noise strength (mixed batches) or nullptr
   const uint32_t *links;   // explicit error patterns
   int T_max;
   int t_exact;             // >= 0: run exactly this many steps (state export)
@@ -48,6 +52,14 @@ struct ResidentArgs {
 };
 
 __device__ __forceinline__ uint32_t parity32(uint32_t x) { return __popc(x) & 1u; }
+
+// floor(p 2^32) clamped to [0, 2^32]; exact in double, so identical to the
+// host's value for the same p.
+__device__ __forceinline__ uint64_t device_threshold(double p) {
+  double t = floor(p * 4294967296.0);
+  t = t < 0.0 ? 0.0 : (t > 4294967296.0 ? 4294967296.0 : t);
+  return (uint64_t)t;
+}
 
 template <int H>
 __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
@@ -78,10 +90,11 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   if (a.links == nullptr) {
     const uint64_t seed = a.seeds[sample];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       bool fx, fy;
-      site_noise((uint32_t)((g.y0 + h) * L + g.c), k0, k1, a.thr, fx, fy);
+      site_noise((uint32_t)((g.y0 + h) * L + g.c), k0, k1, thr, fx, fy);
       exb |= (uint32_t)fx << h;
       eyb |= (uint32_t)fy << h;
       if (h & 1) __builtin_amdgcn_sched_barrier(0);
@@ -188,7 +201,8 @@ struct BandArgs {
   int hy, ty;       // row halo, owned rows per tile (ty == L: one full-height region, rows wrap)
   int ntx;          // tiles along x
   const uint64_t *seeds;
-  uint64_t thr;
+  uint64_t thr;           // flip threshold when p_arr == nullptr
+  const double *p_arr;    // per-sample noise strength or nullptr
   const int32_t *active;  // sample index per grid.y
   const uint4 *Esrc;      // [n][L][L/2] site pairs (P0, Q0, P1, Q1)
   const uint2 *Ssrc;      // [n][L/32][L/2] syndrome masks (s0, s1) of column pairs
@@ -246,15 +260,16 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   if (a.first) {
     const uint64_t seed = a.seeds[sample];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
     uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const uint32_t i = (uint32_t)((gy + h) * L + gx);  // even: one block covers both columns
       const Words4 r = philox4x32_10(i >> 1, k0, k1);
-      ex0 |= (uint32_t)((uint64_t)r.w0 < a.thr) << h;
-      ey0 |= (uint32_t)((uint64_t)r.w1 < a.thr) << h;
-      ex1 |= (uint32_t)((uint64_t)r.w2 < a.thr) << h;
-      ey1 |= (uint32_t)((uint64_t)r.w3 < a.thr) << h;
+      ex0 |= (uint32_t)((uint64_t)r.w0 < thr) << h;
+      ey0 |= (uint32_t)((uint64_t)r.w1 < thr) << h;
+      ex1 |= (uint32_t)((uint64_t)r.w2 < thr) << h;
+      ey1 |= (uint32_t)((uint64_t)r.w3 < thr) << h;
       b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
       if (h & 1) __builtin_amdgcn_sched_barrier(0);
     }
@@ -562,11 +577,20 @@ struct BandSchedule {
   int k_first = 4;
   int k_next = 2;
 };
-BandSchedule g_band_schedule;
+std::mutex g_sched_mu;
+BandSchedule g_sched_default;
+std::map<int, BandSchedule> g_sched_by_L;  // set by the autotuner or the caller
 
-int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
-                uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+BandSchedule schedule_for(int L) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  auto it = g_sched_by_L.find(L);
+  return it == g_sched_by_L.end() ? g_sched_default : it->second;
+}
+
+int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
+                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
   BandWorkspace w = band_layout(L, n, ws);
+  const BandSchedule sched = schedule_for(L);
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive,
                      w.wind, w.status, w.active[0]);
   HIP_TRY(hipGetLastError());
@@ -574,7 +598,7 @@ int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_m
   int t0 = 0, cur = 0, nact = (int)n;
   bool first = true;
   for (;;) {
-    const int k = first ? min(g_band_schedule.k_first, T_max) : min(g_band_schedule.k_next, T_max - t0);
+    const int k = first ? min(sched.k_first, T_max) : min(sched.k_next, T_max - t0);
     BandArgs ba;
     ba.L = L;
     ba.first = first ? 1 : 0;
@@ -593,6 +617,7 @@ int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_m
     const int nty = (L + ba.ty - 1) / ba.ty;
     ba.seeds = d_seeds;
     ba.thr = thr;
+    ba.p_arr = d_p;
     ba.active = w.active[cur];
     ba.Esrc = w.E[cur];
     ba.Ssrc = w.S[cur];
@@ -625,6 +650,28 @@ int decode_band(int L, uint64_t thr, const uint64_t *d_seeds, int64_t n, int T_m
                      d_flags, d_syn);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
+}
+
+// Library-owned side stream per device (default priority, non-blocking) with
+// fork/join events, created on first use and kept for the process.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+std::map<int, SideStream> g_side;
+
+SideStream *side_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  auto it = g_side.find(dev);
+  if (it != g_side.end()) return &it->second;
+  SideStream s;
+  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return &(g_side[dev] = s);
 }
 
 int check_common(int L, int64_t n, int T_max, const void *T_dec, const void *flags) {
@@ -676,6 +723,7 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
     a.n = n;
     a.seeds = d_seeds;
     a.thr = thr;
+    a.p_arr = nullptr;
     a.links = nullptr;
     a.T_max = T_max;
     a.t_exact = -1;
@@ -688,7 +736,7 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
   if (ws_bytes < need || d_workspace == nullptr)
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
   if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
-  return decode_band(L, thr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
+  return decode_band(L, thr, nullptr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
 }
 
 int mpd_profile(int enable) {
@@ -723,21 +771,163 @@ int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
   return MPD_OK;
 }
 
-int mpd_set_band_schedule(int k_first, int k_next) {
+int mpd_set_band_schedule(int L, int k_first, int k_next) {
   g_last_error.clear();
   // the halo 4k (+2) must leave owned columns in a 128-column region
   if (k_first < 1 || k_next < 1 || 4 * k_first + 2 >= BAND_RX / 2 || 4 * k_next >= BAND_RX / 2)
     return fail_with(MPD_ERR_TMAX, "steps per pass must be in [1, 15]");
-  g_band_schedule.k_first = k_first;
-  g_band_schedule.k_next = k_next;
+  BandSchedule b;
+  b.k_first = k_first;
+  b.k_next = k_next;
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  if (L == 0) {
+    g_sched_default = b;
+    g_sched_by_L.clear();
+  } else {
+    g_sched_by_L[L] = b;
+  }
   return MPD_OK;
 }
 
-int mpd_get_band_schedule(int *k_first, int *k_next) {
+int mpd_get_band_schedule(int L, int *k_first, int *k_next) {
   g_last_error.clear();
   if (k_first == nullptr || k_next == nullptr) return fail_with(MPD_ERR_PTR, "NULL output");
-  *k_first = g_band_schedule.k_first;
-  *k_next = g_band_schedule.k_next;
+  const BandSchedule b = schedule_for(L);
+  *k_first = b.k_first;
+  *k_next = b.k_next;
+  return MPD_OK;
+}
+
+int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                      uint8_t *d_flags, void *d_workspace, size_t ws_bytes, void *stream, int *k_first,
+                      int *k_next, float *best_ms) {
+  g_last_error.clear();
+  if (!tiled_ok(L)) return fail_with(MPD_ERR_L, "autotuning applies to the band path (L >= 256)");
+  if (k_first == nullptr || k_next == nullptr || best_ms == nullptr) return fail_with(MPD_ERR_PTR, "NULL output");
+  if (n <= 0) return fail_with(MPD_ERR_N, "autotuning needs a non-empty probe batch");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const BandSchedule saved = schedule_for(L);
+  bool had = false;
+  {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    had = g_sched_by_L.count(L) != 0;
+  }
+  float best = 1e30f;
+  BandSchedule pick = saved;
+  int rc = MPD_OK;
+  for (int kf = 2; kf <= 6 && rc == MPD_OK; ++kf)
+    for (int kn = 1; kn <= 4 && rc == MPD_OK; ++kn) {
+      {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_sched_by_L[L] = BandSchedule{kf, kn};
+      }
+      // warm-up run, then a timed run
+      rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
+      if (rc) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail_with(MPD_ERR_HIP, "event record"); break; }
+      rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
+      if (rc) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail_with(MPD_ERR_HIP, "event timing");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        pick = BandSchedule{kf, kn};
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    if (rc == MPD_OK) g_sched_by_L[L] = pick;
+    else if (had) g_sched_by_L[L] = saved;
+    else g_sched_by_L.erase(L);
+  }
+  if (rc) return rc;
+  *k_first = pick.k_first;
+  *k_next = pick.k_next;
+  *best_ms = best;
+  return MPD_OK;
+}
+
+size_t mpd_mixed_workspace_bytes(int n_classes, const int32_t *h_L, const int64_t *h_count) {
+  size_t need = 0;
+  if (n_classes <= 0 || h_L == nullptr || h_count == nullptr) return 0;
+  for (int c = 0; c < n_classes; ++c)
+    if (!resident_ok(h_L[c]) && tiled_ok(h_L[c])) need = std::max(need, mpd_workspace_bytes(h_L[c], h_count[c]));
+  return need;
+}
+
+int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, const double *d_p,
+                     const uint64_t *d_seeds, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
+                     uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  if (n_classes < 0 || (n_classes > 0 && (h_L == nullptr || h_count == nullptr)))
+    return fail_with(MPD_ERR_PTR, "class arrays must not be NULL");
+  int64_t n = 0;
+  for (int c = 0; c < n_classes; ++c) {
+    if (!resident_ok(h_L[c]) && !tiled_ok(h_L[c])) return fail_with(MPD_ERR_L, "class %d: L=%d unsupported", c, h_L[c]);
+    if (h_count[c] < 0) return fail_with(MPD_ERR_N, "class %d: negative count", c);
+    n += h_count[c];
+  }
+  int rc = check_common(4, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (n == 0) return MPD_OK;
+  if (d_p == nullptr || d_seeds == nullptr || ((uintptr_t)d_seeds & 7u) || ((uintptr_t)d_p & 7u))
+    return fail_with(MPD_ERR_PTR, "p and seeds must be non-NULL and 8-byte aligned");
+  const size_t need = mpd_mixed_workspace_bytes(n_classes, h_L, h_count);
+  if (need > 0 && (ws_bytes < need || d_workspace == nullptr))
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  SideStream *side = side_stream();
+  if (side == nullptr) return fail_with(MPD_ERR_HIP, "could not create the side stream");
+  // fork: resident classes on the side stream
+  HIP_TRY(hipEventRecord(side->fork, st));
+  HIP_TRY(hipStreamWaitEvent(side->stream, side->fork, 0));
+  int64_t off = 0, syn_off = 0;
+  for (int c = 0; c < n_classes; ++c) {
+    const int L = h_L[c];
+    const int64_t cnt = h_count[c];
+    if (cnt > 0 && resident_ok(L)) {
+      ResidentArgs a = {};
+      a.L = L;
+      a.n = cnt;
+      a.seeds = d_seeds + off;
+      a.p_arr = d_p + off;
+      a.links = nullptr;
+      a.T_max = T_max;
+      a.t_exact = -1;
+      a.T_dec = d_T_dec + off;
+      a.flags = d_flags + off;
+      a.syn = d_final_syndrome ? d_final_syndrome + syn_off : nullptr;
+      rc = launch_resident(a, side->stream);
+      if (rc) return rc;
+    }
+    off += cnt;
+    syn_off += cnt * (((int64_t)L * L + 31) / 32);
+  }
+  HIP_TRY(hipEventRecord(side->join, side->stream));
+  // band classes on the caller's stream
+  off = 0;
+  syn_off = 0;
+  for (int c = 0; c < n_classes; ++c) {
+    const int L = h_L[c];
+    const int64_t cnt = h_count[c];
+    if (cnt > 0 && !resident_ok(L)) {
+      rc = decode_band(L, 0, d_p + off, d_seeds + off, cnt, T_max, d_T_dec + off, d_flags + off,
+                       d_final_syndrome ? d_final_syndrome + syn_off : nullptr, d_workspace, st);
+      if (rc) return rc;
+    }
+    off += cnt;
+    syn_off += cnt * (((int64_t)L * L + 31) / 32);
+  }
+  HIP_TRY(hipStreamWaitEvent(st, side->join, 0));
   return MPD_OK;
 }
 

@@ -206,3 +206,46 @@ def test_empty_batch(gpu):
     assert T.numel() == 0
     T, F, S = gpu.decode_batch(256, 0.01, np.zeros(0, dtype=np.uint64), 16)
     assert T.numel() == 0
+
+
+def test_config4_mixed_full(gpu, orc):
+    """Mixed batch (L in {32..512}, counts proportional to 1/L^2, p_i ~ U[0.001, 0.03])
+    in one call, every sample against the oracle."""
+    from paper_2506_03266_amd.workloads import mixed_batch
+    Ls, ps, ss = mixed_batch()
+    classes = []
+    for L in dict.fromkeys(Ls.tolist()):
+        classes.append((L, int((Ls == L).sum())))
+    T, F, S = gpu.decode_mixed(classes, ps, ss, 4096)
+    T, F, S = _np(T), _np(F), _np(S).view(np.uint32)
+    off = woff = 0
+    for L, c in classes:
+        ref = orc.decode_seeds(L, ps[off:off + c], ss[off:off + c], 4096, threads=8)
+        W = (L * L + 31) // 32
+        assert np.array_equal(T[off:off + c], ref["T_dec"]), L
+        assert np.array_equal(F[off:off + c], ref["flags"]), L
+        assert np.array_equal(S[woff:woff + c * W].reshape(c, W), ref["sigma_words"]), L
+        off += c
+        woff += c * W
+
+
+def test_per_sample_p_matches_single_p(gpu):
+    """A mixed call with one class and a constant p equals decode_batch."""
+    s = seeds(47, 0, 64)
+    for L in (64, 256):
+        T1, F1, S1 = gpu.decode_batch(L, 0.02, s, 256)
+        T2, F2, S2 = gpu.decode_mixed([(L, 64)], np.full(64, 0.02), s, 256)
+        assert np.array_equal(_np(T1), _np(T2)) and np.array_equal(_np(F1), _np(F2))
+        assert np.array_equal(_np(S1).reshape(-1), _np(S2))
+
+
+def test_autotune_keeps_results(gpu):
+    """The autotuner picks a schedule for L; decoding with it is unchanged."""
+    s = seeds(48, 0, 256)
+    T0, F0, _ = gpu.decode_batch(256, 0.01, s, 4096)
+    kf, kn, ms = gpu.autotune_band(256, 0.01, s, 4096)
+    assert 2 <= kf <= 6 and 1 <= kn <= 4 and ms > 0
+    assert gpu.get_band_schedule(256) == (kf, kn)
+    T1, F1, _ = gpu.decode_batch(256, 0.01, s, 4096)
+    assert np.array_equal(_np(T0), _np(T1)) and np.array_equal(_np(F0), _np(F1))
+    gpu.set_band_schedule(4, 2)  # restore the defaults for the other tests
