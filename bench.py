@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4"], default="c3",
+                    help="c3 (default) is the headline line; c1/c2/c4 print a line for that configuration")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -79,6 +81,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes, "copies": 3}))
         return
+
+    if args.workload != "c3":
+        return other_workload(args, b, seeds, torch, np)
 
     n, K, W = N_SAMPLES, args.steps, args.warmup
     batches = [torch.from_numpy(seeds(3, i % 256, n).view(np.int64)).to(dev) for i in range(W + K)]
@@ -149,6 +154,51 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def other_workload(args, b, seeds, torch, np):
+    """Throughput of configurations 1, 2 (per p) and 4 (mixed sizes), fresh seeds per step."""
+    from paper_2506_03266_amd.workloads import CONFIGS, mixed_batch
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    if args.workload == "c4":
+        Ls, ps, ss = mixed_batch()
+        classes = [(L, int((Ls == L).sum())) for L in dict.fromkeys(Ls.tolist())]
+        pt = torch.from_numpy(ps).to(dev)
+        st = torch.from_numpy(ss.view(np.int64)).to(dev)
+        for _ in range(W):
+            b.decode_mixed(classes, pt, st, 4096)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = [b.decode_mixed(classes, pt, st, 4096) for _ in range(K)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        T = outs[-1][0].cpu().numpy().astype(np.int64)
+        su = float((Ls.astype(np.int64) ** 2 * T).sum())
+        print(json.dumps({"workload": "config 4: mixed L in {32,64,128,256,512}, counts ~ 1/L^2, "
+                                      "p ~ U[0.001,0.03]", "samples_per_s": K * len(Ls) / dt,
+                          "site_updates_per_s": K * su / dt, "ms_per_batch": dt / K * 1e3,
+                          "samples": int(len(Ls))}))
+        return
+    cfg = CONFIGS[1 if args.workload == "c1" else 2]
+    L, n = cfg["L"], cfg["n"]
+    for k, p in enumerate(cfg["p"]):
+        batches = [torch.from_numpy(seeds(int(args.workload[1]), k, n, start=i * n).view(np.int64)).to(dev)
+                   for i in range(W + K)]
+        out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None)
+        for i in range(W):
+            b.decode_batch(L, p, batches[i], cfg["T_max"], want_syndrome=False, out=out)
+        torch.cuda.synchronize()
+        tsum = 0
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            b.decode_batch(L, p, batches[i], cfg["T_max"], want_syndrome=False, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        T = out[0].cpu().numpy().astype(np.int64)
+        print(json.dumps({"workload": f"config {args.workload[1]}: L={L} p={p} {n} samples",
+                          "samples_per_s": K * n / dt, "site_updates_per_s_last_batch_est": L * L * T.sum() * K / dt,
+                          "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean())}))
 
 
 if __name__ == "__main__":

@@ -124,8 +124,8 @@ int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
 /* Temporal blocking of the band path (L >= 256): decoder steps run on chip per
- * pass over HBM, in the first pass (which also generates the noise) and in
- * later passes.  Results do not depend on it; speed does.  Each value in
+ * pass over HBM, in the first pass (registers still empty) and in later
+ * passes.  Results do not depend on it; speed does.  Each value in
  * [1, 15].  L = 0 sets the default for every L and forgets per-L settings;
  * otherwise the setting applies to that L only (defaults 4 and 2).
  * Process-wide, guarded by a mutex. */
@@ -164,9 +164,10 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
 /* Kernel timing for measurement (not needed for decoding).
  * mpd_profile(1) clears earlier records and starts recording a pair of HIP
  * events on the launch stream around every kernel launch of the library;
- * mpd_profile(0) stops recording (records are kept).  Names: "k_band"
- * (one pass of k decoder steps over the L = 256 bands) and "k_resident"
- * (whole decode of small lattices).  Not thread-safe. */
+ * mpd_profile(0) stops recording (records are kept).  Names: "k_band_noise"
+ * (noise and initial syndrome of a band-path batch), "k_band" (one pass of k
+ * decoder steps over the bands of L >= 256) and "k_resident" (whole decode of
+ * small lattices).  Not thread-safe. */
 int mpd_profile(int enable);
 
 /* Sum of the recorded durations (ms) and number of launches of `kernel`;

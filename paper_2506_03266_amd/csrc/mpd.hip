@@ -194,15 +194,13 @@ constexpr int TILE_H = BAND_H;             // rows per syndrome word pair in HBM
 
 struct BandArgs {
   int L;
-  int first;        // 1: generate noise in place, 0: load state from src
+  int first;        // 1: registers start at zero (syndrome from k_band_noise), 0: load state
+  int write_state;  // 0: do not store the state (samples expected to finish in this pass)
   int k;            // decoder steps in this pass
   int t0;           // steps already done
   int hx, tx;       // column halo, owned columns per tile
   int hy, ty;       // row halo, owned rows per tile (ty == L: one full-height region, rows wrap)
   int ntx;          // tiles along x
-  const uint64_t *seeds;
-  uint64_t thr;           // flip threshold when p_arr == nullptr
-  const double *p_arr;    // per-sample noise strength or nullptr
   const int32_t *active;  // sample index per grid.y
   const uint4 *Esrc;      // [n][L][L/2] site pairs (P0, Q0, P1, Q1)
   const uint2 *Ssrc;      // [n][L/32][L/2] syndrome masks (s0, s1) of column pairs
@@ -257,31 +255,9 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   uint32_t wind = 0u;
   const size_t half_row = (size_t)L / 2;
   const size_t sidx = ((size_t)sample * (L / TILE_H) + gy / TILE_H) * half_row + (gx >> 1);
-  if (a.first) {
-    const uint64_t seed = a.seeds[sample];
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
-    uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
+  if (a.first) {  // registers start empty; the syndrome comes from k_band_noise
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-      const uint32_t i = (uint32_t)((gy + h) * L + gx);  // even: one block covers both columns
-      const Words4 r = philox4x32_10(i >> 1, k0, k1);
-      ex0 |= (uint32_t)((uint64_t)r.w0 < thr) << h;
-      ey0 |= (uint32_t)((uint64_t)r.w1 < thr) << h;
-      ex1 |= (uint32_t)((uint64_t)r.w2 < thr) << h;
-      ey1 |= (uint32_t)((uint64_t)r.w3 < thr) << h;
-      b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
-      if (h & 1) __builtin_amdgcn_sched_barrier(0);
-    }
-    if (last_col) wind ^= __popc(ex1 & own_rows) & 1u;
-    if (own_col && top) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;
-    MB[w * 64 + lane] = make_uint2(ey0, ey1);
-    __syncthreads();
-    const uint2 dn = MB[wdn * 64 + lane];  // y-links of the row below the strip
-    __syncthreads();
-    constexpr uint32_t F = full_mask<H>();
-    b.s0 = (ex0 ^ from_left(ex1) ^ ey0 ^ ((ey0 << 1) | (dn.x >> (H - 1)))) & F;
-    b.s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | (dn.y >> (H - 1)))) & F;
+    for (int h = 0; h < H; ++h) b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
   } else {
     const uint4 *E = a.Esrc + (size_t)sample * L * half_row;
 #pragma unroll
@@ -292,6 +268,8 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
       b.P1[h] = e.z;
       b.Q1[h] = e.w;
     }
+  }
+  {
     const uint2 sv = a.Ssrc[sidx];
     b.s0 = sv.x;
     b.s1 = sv.y;
@@ -319,7 +297,7 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
     if (__syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u)) bits |= 2u << st;
   }
 
-  if (own) {
+  if (own && a.write_state) {
     uint4 *E = a.Edst + (size_t)sample * L * half_row;
 #pragma unroll
     for (int h = 0; h < H; ++h)
@@ -333,6 +311,85 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   if (threadIdx.x == 0) {
     if (bits) atomicOr(&a.alive[sample], bits);
     if (red[0]) atomicXor(&a.wind[sample], red[0]);
+  }
+}
+
+// Noise and initial syndrome of the band path, once per site.  A thread owns
+// one column pair over one 16-row strip (the band's HBM word); a workgroup
+// holds `CP` consecutive column pairs of `S` consecutive strips of one
+// sample.  Writes the syndrome words, the error winding bits (Wx(E), Wy(E))
+// and, if `counts` is set, the number of anyons in every 8x8 block as uint8
+// [n][L/8][L/8].  Links that cross into another workgroup (the y-links of
+// the row below the group, the x-links left of its first column when the
+// group is narrower than the lattice) are drawn again from the generator.
+__global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const uint64_t *seeds, uint64_t thr,
+                                                     const double *p_arr, uint2 *Sout, uint32_t *wind,
+                                                     uint8_t *counts) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int P = L / 2;                                  // column pairs of the lattice
+  const int NB = CP / 4;                                // 8-column blocks of the group
+  uint32_t *ex1s = reinterpret_cast<uint32_t *>(smem);  // [S][CP] x-links right of the second column
+  uint32_t *eyts = ex1s + S * CP;                       // [S][CP] top-row y-links (bit 0 col 0, bit 1 col 1)
+  uint32_t *cnt = eyts + S * CP;                        // [2S][NB] anyon counts of the group's blocks
+  uint32_t *red = cnt + 2 * S * NB;
+  const int gxn = P / CP, gyn = (L / TILE_H) / S;
+  const int64_t sample = blockIdx.x / (gxn * gyn);
+  const int grp = (int)(blockIdx.x % (gxn * gyn));
+  const int cx = grp % gxn, cy = grp / gxn;
+  const int tid = threadIdx.x, ql = tid % CP, jl = tid / CP;
+  const int q = cx * CP + ql, j = cy * S + jl, y0 = j * TILE_H, gx = 2 * q;
+  for (int i = tid; i < 2 * S * NB; i += blockDim.x) cnt[i] = 0u;
+  if (tid == 0) red[0] = 0u;
+  const uint64_t seed = seeds[sample];
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const uint64_t t = p_arr ? device_threshold(p_arr[sample]) : thr;
+  uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
+#pragma unroll 4
+  for (int h = 0; h < TILE_H; ++h) {
+    const Words4 r = philox4x32_10((uint32_t)((y0 + h) * L + gx) >> 1, k0, k1);
+    ex0 |= (uint32_t)((uint64_t)r.w0 < t) << h;
+    ey0 |= (uint32_t)((uint64_t)r.w1 < t) << h;
+    ex1 |= (uint32_t)((uint64_t)r.w2 < t) << h;
+    ey1 |= (uint32_t)((uint64_t)r.w3 < t) << h;
+  }
+  uint32_t eyd = 0u;  // y-links of the row below the strip (bit 0 col 0, bit 1 col 1)
+  if (jl == 0) {      // that row belongs to another workgroup
+    const int yb = y0 == 0 ? L - 1 : y0 - 1;
+    const Words4 r = philox4x32_10((uint32_t)(yb * L + gx) >> 1, k0, k1);
+    eyd = (uint32_t)((uint64_t)r.w1 < t) | ((uint32_t)((uint64_t)r.w3 < t) << 1);
+  }
+  uint32_t exl = 0u;  // x-links entering column 2q from the left
+  if (ql == 0 && CP < P) {
+    const int xl = gx == 0 ? L - 2 : gx - 2;  // pair holding column 2q-1 as its second column
+#pragma unroll 4
+    for (int h = 0; h < TILE_H; ++h) {
+      const Words4 r = philox4x32_10((uint32_t)((y0 + h) * L + xl) >> 1, k0, k1);
+      exl |= (uint32_t)((uint64_t)r.w2 < t) << h;
+    }
+  }
+  ex1s[jl * CP + ql] = ex1;
+  eyts[jl * CP + ql] = ((ey0 >> (TILE_H - 1)) & 1u) | (((ey1 >> (TILE_H - 1)) & 1u) << 1);
+  __syncthreads();
+  if (ql > 0 || CP == P) exl = ex1s[jl * CP + (ql == 0 ? CP - 1 : ql - 1)];
+  if (jl > 0) eyd = eyts[(jl - 1) * CP + ql];
+  constexpr uint32_t F = full_mask<TILE_H>();
+  const uint32_t s0 = (ex0 ^ exl ^ ey0 ^ ((ey0 << 1) | (eyd & 1u))) & F;
+  const uint32_t s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | (eyd >> 1))) & F;
+  Sout[((size_t)sample * (L / TILE_H) + j) * P + q] = make_uint2(s0, s1);
+  uint32_t wd = 0u;
+  if (q == P - 1) wd ^= __popc(ex1) & 1u;                                  // x-links leaving column L-1
+  if (j == L / TILE_H - 1) wd ^= (((ey0 ^ ey1) >> (TILE_H - 1)) & 1u) << 1;  // y-links leaving row L-1
+  if (wd) atomicXor(&red[0], wd);
+  if (counts != nullptr) {
+    const int bx = ql / 4;  // 8 columns = 4 pairs per block
+    atomicAdd(&cnt[(2 * jl) * NB + bx], __popc(s0 & 0xFFu) + __popc(s1 & 0xFFu));
+    atomicAdd(&cnt[(2 * jl + 1) * NB + bx], __popc(s0 >> 8) + __popc(s1 >> 8));
+  }
+  __syncthreads();
+  if (tid == 0 && red[0]) atomicXor(&wind[sample], red[0]);
+  if (counts != nullptr) {
+    uint8_t *out = counts + (size_t)sample * (L / 8) * (L / 8) + (size_t)(2 * cy * S) * (L / 8) + cx * NB;
+    for (int i = tid; i < 2 * S * NB; i += blockDim.x) out[(i / NB) * (L / 8) + i % NB] = (uint8_t)cnt[i];
   }
 }
 
@@ -569,10 +626,9 @@ BandWorkspace band_layout(int L, int64_t n, void *base) {
   return w;
 }
 
-// Decoder steps per pass (first pass with the noise, later passes).  With
-// 128-column regions a halo of 4k (+2 in the noise pass) leaves 128 - 2*halo
-// owned columns per tile: L = 256 takes 3 tiles for k <= 4 in the noise
-// pass and k <= 5 later.
+// Decoder steps per pass (first pass, later passes).  With 128-column
+// regions a halo of 4k leaves 128 - 8k owned columns per tile: L = 256
+// takes 3 tiles for k <= 5.
 struct BandSchedule {
   int k_first = 4;
   int k_next = 2;
@@ -587,12 +643,41 @@ BandSchedule schedule_for(int L) {
   return it == g_sched_by_L.end() ? g_sched_default : it->second;
 }
 
+// Launch shape of k_band_noise: whole rows of column pairs when they fit in
+// one workgroup, else the widest divisor of L/2 (a multiple of 4, so that
+// 8x8 blocks stay inside a group); then as many strips as fit.
+struct NoiseShape {
+  int CP, S, groups;
+  size_t lds;
+};
+NoiseShape noise_shape(int L) {
+  NoiseShape g;
+  const int P = L / 2;
+  g.CP = P;
+  if (P > 1024)
+    for (g.CP = 1024; g.CP > 4 && (P % g.CP || g.CP % 4); --g.CP) {
+    }
+  g.S = 1024 / g.CP;
+  while (g.S > 1 && (L / TILE_H) % g.S) --g.S;
+  g.groups = (P / g.CP) * ((L / TILE_H) / g.S);
+  g.lds = (size_t)(2 * g.S * g.CP + 2 * g.S * (g.CP / 4) + 4) * sizeof(uint32_t);
+  return g;
+}
+
 int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
-                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream,
+                uint8_t *d_counts = nullptr) {
   BandWorkspace w = band_layout(L, n, ws);
   const BandSchedule sched = schedule_for(L);
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive,
                      w.wind, w.status, w.active[0]);
+  HIP_TRY(hipGetLastError());
+  {
+    const NoiseShape g = noise_shape(L);
+    ProfScope ps("k_band_noise", stream);
+    hipLaunchKernelGGL(k_band_noise, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, stream, L, g.CP, g.S,
+                       d_seeds, thr, d_p, w.S[0], w.wind, d_counts);
+  }
   HIP_TRY(hipGetLastError());
   const size_t lds = band_lds();
   int t0 = 0, cur = 0, nact = (int)n;
@@ -602,22 +687,20 @@ int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds,
     BandArgs ba;
     ba.L = L;
     ba.first = first ? 1 : 0;
+    ba.write_state = 1;
     ba.k = k;
     ba.t0 = t0;
-    ba.hx = 4 * k + (first ? 2 : 0);
+    ba.hx = 4 * k;
     ba.tx = BAND_RX - 2 * ba.hx;
     if (L == BAND_RY) {
       ba.hy = 0;
       ba.ty = L;
-    } else {  // row halo of 4k (+1 in the noise pass), rounded up to whole 16-row strips
-      ba.hy = (4 * k + (first ? 1 : 0) + TILE_H - 1) / TILE_H * TILE_H;
+    } else {  // row halo of 4k, rounded up to whole 16-row strips
+      ba.hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
       ba.ty = BAND_RY - 2 * ba.hy;
     }
     ba.ntx = (L + ba.tx - 1) / ba.tx;
     const int nty = (L + ba.ty - 1) / ba.ty;
-    ba.seeds = d_seeds;
-    ba.thr = thr;
-    ba.p_arr = d_p;
     ba.active = w.active[cur];
     ba.Esrc = w.E[cur];
     ba.Ssrc = w.S[cur];
@@ -773,8 +856,8 @@ int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
 
 int mpd_set_band_schedule(int L, int k_first, int k_next) {
   g_last_error.clear();
-  // the halo 4k (+2) must leave owned columns in a 128-column region
-  if (k_first < 1 || k_next < 1 || 4 * k_first + 2 >= BAND_RX / 2 || 4 * k_next >= BAND_RX / 2)
+  // the halo 4k must leave owned columns in a 128-column region
+  if (k_first < 1 || k_next < 1 || 4 * k_first >= BAND_RX / 2 || 4 * k_next >= BAND_RX / 2)
     return fail_with(MPD_ERR_TMAX, "steps per pass must be in [1, 15]");
   BandSchedule b;
   b.k_first = k_first;
