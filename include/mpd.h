@@ -166,13 +166,91 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
  * events on the launch stream around every kernel launch of the library;
  * mpd_profile(0) stops recording (records are kept).  Names: "k_band_noise"
  * (noise and initial syndrome of a band-path batch), "k_band" (one pass of k
- * decoder steps over the bands of L >= 256) and "k_resident" (whole decode of
- * small lattices).  Not thread-safe. */
+ * decoder steps over the bands of L >= 256), "k_resident" (whole decode of
+ * small lattices), "k_cnn_forward" and "k_cnn_backward" (decode-time
+ * predictor).  Not thread-safe. */
 int mpd_profile(int enable);
 
 /* Sum of the recorded durations (ms) and number of launches of `kernel`;
  * waits for the recorded events to complete. */
 int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* ---------------------------------------------------------------------------
+ * Learned scheduling (an addition to the paper's method).
+ *
+ * A small convolutional network predicts ln(1 + T_dec) of a sample from the
+ * anyon counts of its 8 x 8 blocks; a decode can use the prediction to give
+ * groups of samples first passes of different depth.  Decoding results never
+ * depend on the network: mpd_decode_learned returns exactly what
+ * mpd_decode_batch returns for the same seeds.
+ *
+ * Network, on an M x M map (M = L / 8) of inputs x = count / 8:
+ *   layer 1     conv 3x3, 1 -> 16 channels, circular padding, bias, ReLU
+ *   layers 2-4  conv 3x3, 16 -> 16, circular padding, bias, ReLU
+ *   pooling     global maximum per channel (lowest row-major index on ties)
+ *   head        pred = bl + sum_c Wl[c] * feat[c]
+ * Convolutions: z[co][y][x] = b[co] + sum over dy, dx in {-1, 0, 1} and ci
+ * of W[co][3(dy+1) + (dx+1)][ci] * a[ci][(y+dy) mod M][(x+dx) mod M].
+ * Parameters: one float32 vector of MPD_CNN_PARAMS values, in this order:
+ *   W1 [16][9] | b1 [16] | W2 [16][9][16] | b2 [16] | W3 | b3 | W4 | b4 |
+ *   Wl [16] | bl [1].
+ * Arithmetic: conv weights and the activations of layers 1-3 are rounded to
+ * bfloat16 (nearest, ties to even), products accumulate in float32 (matrix
+ * cores); biases, layer-4 activations, pooling and head are float32.
+ * ------------------------------------------------------------------------- */
+#define MPD_CNN_PARAMS 7137
+
+/* Anyon counts per 8 x 8 block of seeded samples, uint8 [n][L/8][L/8]
+ * (row = block row y/8), for the noise of mpd_decode_batch.  p applies to
+ * every sample unless d_p (per-sample [n] double) is given.  L: a multiple
+ * of 16 in [16, 16384]. */
+int mpd_syndrome_counts(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, uint8_t *d_counts,
+                        void *stream);
+
+/* Initial parameters: weights uniform in +-sqrt(6 / fan_in) (He et al.,
+ * 2015; fan_in 9, 144, 144, 144, 16), biases 0.  Weight j is
+ * (2u - 1) * bound with u = (w + 1/2) / 2^32 in double, rounded to float,
+ * where w is word 0 of Philox4x32-10 at counter (j, 0x636e6e31, 0, 0) under
+ * key (seed & 0xffffffff, seed >> 32). */
+int mpd_cnn_init(float *d_params, uint64_t seed, void *stream);
+
+/* Forward pass on count maps d_counts [n][M][M] (2 <= M <= 2048): d_pred [n]
+ * and, if not NULL, d_feat [n][16] (pooled maxima) and d_argmax [n][16]
+ * (their row-major positions; NaN and -1 for a channel without a number).
+ * Workspace: mpd_cnn_forward_workspace_bytes(M, n) bytes, 256-byte aligned
+ * (weights packed for the matrix cores; per-sample maxima when M > 32). */
+size_t mpd_cnn_forward_workspace_bytes(int M, int64_t n);
+int mpd_cnn_forward(const uint8_t *d_counts, int M, int64_t n, const float *d_params, float *d_pred, float *d_feat,
+                    int32_t *d_argmax, void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Training step, part 1: loss = mean over the batch of (pred - target)^2
+ * (d_loss [1]) and its gradient with respect to the parameters (d_grad
+ * [MPD_CNN_PARAMS], the rounding to bfloat16 taken as the identity); d_pred
+ * [n] receives the predictions if not NULL.  2 <= M <= 32, n >= 1.
+ * Workspace: mpd_cnn_train_workspace_bytes(M, n) bytes, 256-byte aligned. */
+size_t mpd_cnn_train_workspace_bytes(int M, int64_t n);
+int mpd_cnn_loss_grad(const uint8_t *d_counts, int M, int64_t n, const float *d_params, const float *d_target,
+                      float *d_grad, float *d_loss, float *d_pred, void *d_workspace, size_t ws_bytes,
+                      void *stream);
+
+/* Training step, part 2: one Adam update (Kingma and Ba, 2015) of d_params
+ * with moments d_m, d_v (all [MPD_CNN_PARAMS] float, zero before step 1);
+ * step counts from 1. */
+int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int step, float lr, float beta1,
+                      float beta2, float eps, void *stream);
+
+/* Decode with learned scheduling: noise and block counts, the network's
+ * predictions, then samples with h_edges[b-1] <= pred < h_edges[b] (n_bins
+ * groups, 1 <= n_bins <= 8, edges ascending) start with a pass of
+ * h_depth[b] steps (1..15); later passes run every survivor at the band
+ * schedule's k_next.  Outputs as mpd_decode_batch, plus d_pred [n] if not
+ * NULL.  L: a multiple of 16 in [256, 16384].  Workspace:
+ * mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.  Synchronizes
+ * `stream`. */
+size_t mpd_learned_workspace_bytes(int L, int64_t n);
+int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const float *d_params,
+                       int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec, uint8_t *d_flags,
+                       uint32_t *d_final_syndrome, float *d_pred, void *d_workspace, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

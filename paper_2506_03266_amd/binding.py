@@ -60,6 +60,25 @@ def lib():
     L.mpd_profile.restype = I
     L.mpd_profile_read.argtypes = [ctypes.c_char_p, P, P]
     L.mpd_profile_read.restype = I
+    L.mpd_syndrome_counts.argtypes = [I, D, P, P, I64, P, P]
+    L.mpd_syndrome_counts.restype = I
+    L.mpd_cnn_init.argtypes = [P, ctypes.c_uint64, P]
+    L.mpd_cnn_init.restype = I
+    L.mpd_cnn_forward_workspace_bytes.argtypes = [I, I64]
+    L.mpd_cnn_forward_workspace_bytes.restype = SZ
+    L.mpd_cnn_forward.argtypes = [P, I, I64, P, P, P, P, P, SZ, P]
+    L.mpd_cnn_forward.restype = I
+    L.mpd_cnn_train_workspace_bytes.argtypes = [I, I64]
+    L.mpd_cnn_train_workspace_bytes.restype = SZ
+    L.mpd_cnn_loss_grad.argtypes = [P, I, I64, P, P, P, P, P, P, SZ, P]
+    L.mpd_cnn_loss_grad.restype = I
+    F = ctypes.c_float
+    L.mpd_cnn_adam_step.argtypes = [P, P, P, P, I, F, F, F, F, P]
+    L.mpd_cnn_adam_step.restype = I
+    L.mpd_learned_workspace_bytes.argtypes = [I, I64]
+    L.mpd_learned_workspace_bytes.restype = SZ
+    L.mpd_decode_learned.argtypes = [I, D, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
+    L.mpd_decode_learned.restype = I
     _lib = L
     return L
 
@@ -227,3 +246,119 @@ def decode_mixed(classes, p, seeds, T_max: int = 4096, want_syndrome: bool = Tru
                                 _stream_ptr(stream))
     _check(rc, "mpd_decode_mixed")
     return T, F, S
+
+
+# ---------------------------------------------------------------------------
+# Learned scheduling: block counts, the decode-time predictor, scheduled decode
+# ---------------------------------------------------------------------------
+
+CNN_PARAMS = 7137
+
+
+def _p_tensor(p, n, dev):
+    if isinstance(p, (float, int)):
+        return None
+    pt = p if isinstance(p, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(p, dtype=np.float64))
+    pt = pt.to(dev, dtype=torch.float64).contiguous()
+    assert pt.numel() == n
+    return pt
+
+
+def syndrome_counts(L: int, p, seeds, out=None, stream=None):
+    """Anyons per 8x8 block, uint8 [n, L/8, L/8]; p is a number or per-sample values."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    pt = _p_tensor(p, n, dev)
+    c = out if out is not None else torch.empty((n, L // 8, L // 8), dtype=torch.uint8, device=dev)
+    rc = lib().mpd_syndrome_counts(L, float(p) if pt is None else 0.0, _ptr(pt), _ptr(s), n, _ptr(c),
+                                   _stream_ptr(stream))
+    _check(rc, "mpd_syndrome_counts")
+    return c
+
+
+def cnn_init(seed: int, stream=None):
+    """Fresh parameter vector (float32 [7137]) on the device."""
+    prm = torch.empty(CNN_PARAMS, dtype=torch.float32, device="cuda")
+    _check(lib().mpd_cnn_init(_ptr(prm), int(seed) & (2**64 - 1), _stream_ptr(stream)), "mpd_cnn_init")
+    return prm
+
+
+def cnn_forward(counts, params, want_feat: bool = False, stream=None):
+    """Predictions (float32 [n]) for count maps [n, M, M]; with want_feat also
+    the pooled maxima [n, 16] and their positions [n, 16]."""
+    counts = counts.contiguous()
+    n, M = counts.shape[0], counts.shape[-1]
+    dev = counts.device
+    pred = torch.empty(n, dtype=torch.float32, device=dev)
+    feat = torch.empty((n, 16), dtype=torch.float32, device=dev) if want_feat else None
+    amax = torch.empty((n, 16), dtype=torch.int32, device=dev) if want_feat else None
+    nb = int(lib().mpd_cnn_forward_workspace_bytes(M, n))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    rc = lib().mpd_cnn_forward(_ptr(counts), M, n, _ptr(params), _ptr(pred), _ptr(feat), _ptr(amax), _ptr(ws),
+                               ws.numel(), _stream_ptr(stream))
+    _check(rc, "mpd_cnn_forward")
+    return (pred, feat, amax) if want_feat else pred
+
+
+def train_workspace(M: int, n: int, device="cuda"):
+    nb = int(lib().mpd_cnn_train_workspace_bytes(M, n))
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+
+
+def cnn_loss_grad(counts, params, target, workspace=None, out=None, stream=None):
+    """Mean squared error and its gradient: returns (loss [1], grad [7137], pred [n])."""
+    counts = counts.contiguous()
+    n, M = counts.shape[0], counts.shape[-1]
+    dev = counts.device
+    if out is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        grad = torch.empty(CNN_PARAMS, dtype=torch.float32, device=dev)
+        pred = torch.empty(n, dtype=torch.float32, device=dev)
+    else:
+        loss, grad, pred = out
+    ws = workspace if workspace is not None else train_workspace(M, n, dev)
+    target = target.to(dev, dtype=torch.float32).contiguous()
+    rc = lib().mpd_cnn_loss_grad(_ptr(counts), M, n, _ptr(params), _ptr(target), _ptr(grad),
+                                 _ptr(loss), _ptr(pred), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc, "mpd_cnn_loss_grad")
+    return loss, grad, pred
+
+
+def cnn_adam_step(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, stream=None):
+    """In-place Adam update of params (and its moments m, v)."""
+    rc = lib().mpd_cnn_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                                 float(beta2), float(eps), _stream_ptr(stream))
+    _check(rc, "mpd_cnn_adam_step")
+
+
+def learned_workspace(L: int, n: int, device="cuda"):
+    nb = int(lib().mpd_learned_workspace_bytes(L, n))
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+
+
+def decode_learned(L: int, p: float, seeds, params, edges, depths, T_max: int = 4096, want_syndrome: bool = True,
+                   workspace=None, out=None, stream=None):
+    """Decode with learned scheduling: samples with edges[b-1] <= pred < edges[b]
+    start with a pass of depths[b] steps.  Returns (T_dec, flags, syndrome,
+    pred), results identical to decode_batch."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+        pred = torch.empty(n, dtype=torch.float32, device=dev)
+    else:
+        T, F, S, pred = out
+    he = np.ascontiguousarray(edges, dtype=np.float32)
+    hd = np.ascontiguousarray(depths, dtype=np.int32)
+    assert hd.size == he.size + 1
+    ws = workspace if workspace is not None else learned_workspace(L, n)
+    rc = lib().mpd_decode_learned(L, float(p), _ptr(s), n, int(T_max), _ptr(params), int(hd.size),
+                                  he.ctypes.data_as(ctypes.c_void_p), hd.ctypes.data_as(ctypes.c_void_p), _ptr(T),
+                                  _ptr(F), _ptr(S), _ptr(pred), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc, "mpd_decode_learned")
+    return T, F, S, pred

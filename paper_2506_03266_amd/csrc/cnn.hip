@@ -1,0 +1,826 @@
+// cnn.hip -- decode-time predictor for learned scheduling (gfx950).
+//
+// A small convolutional network estimates ln(1 + T_dec) of a noise sample
+// from the anyon counts of its 8x8 blocks (an M x M map, M = L / 8); T_dec
+// is the decoding time of Def. "logical failure rate, expected decoding
+// time, and thresholds" (Sec. 5.1).  The network is not part of the paper:
+// it only groups samples by predicted decoding time, and no decoder state or
+// result depends on it.
+//
+// Network (parameter vector of 7137 float32, offsets below):
+//   x = count / 8
+//   4 x [conv 3x3 with circular padding, bias, ReLU]  (1 -> 16, then 16 -> 16)
+//   global max over positions per channel (lowest row-major index on ties)
+//   pred = bl + sum_c Wl[c] feat[c]
+// Conv weights W[co][tap][ci], tap = 3 (dy + 1) + (dx + 1), read the input
+// at (y + dy, x + dx) (a cross-correlation).
+//
+// Precision: conv weights and the activations of layers 1-3 are bfloat16
+// (round to nearest even); products accumulate in float32 on the matrix
+// cores; biases, layer-4 activations, the pooling and the head are float32.
+//
+// Forward: positions form the N dimension of v_mfma_f32_16x16x32_bf16 (16
+// positions per instruction), output channels the M dimension and (tap,
+// input channel) pairs the K dimension (two taps of 16 channels per
+// instruction, five instructions per 3x3 layer).  Activations live in LDS as
+// [position][16 channels] bfloat16, so a lane's K slice is one 16-byte read
+// and its result (4 channels of one position) one 8-byte write.  Maps up to
+// 32 x 32 are processed whole by one workgroup with wrapped indexing; wider
+// maps in 32 x 32 output tiles with a 4-position halo (valid convolutions
+// shrinking the region by one position per layer and side), the per-channel
+// maxima meeting in a 64-bit atomic max.
+//
+// Backward (training, maps up to 32 x 32): the global max routes each
+// channel's gradient to a single layer-4 position, so the gradient of a
+// sample is the sum of 16 back-propagations through receptive fields of
+// 3x3, 5x5, 7x7 and 9x9 positions around those maxima.  One workgroup per
+// sample walks them with the layer-1..3 activations stored by the forward
+// pass (float32 arithmetic on the vector units) and writes its gradient;
+// a reduction kernel sums over the batch in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "engine.h"
+#include "host.h"
+#include "mpd.h"
+
+namespace mpd {
+namespace {
+
+constexpr int CH = 16;
+constexpr int OFF_W1 = 0, OFF_B1 = 144;  // W1 [16 co][9 tap]
+constexpr int OFF_W2 = 160, OFF_B2 = 2464;
+constexpr int OFF_W3 = 2480, OFF_B3 = 4784;
+constexpr int OFF_W4 = 4800, OFF_B4 = 7104;
+constexpr int OFF_WL = 7120, OFF_BL = 7136;
+constexpr int NPARAM = MPD_CNN_PARAMS;
+constexpr uint32_t INIT_TAG = 0x636E6E31u;  // second counter word of the initializer
+constexpr int WRAP_MAX = 32;                // largest map held whole by one workgroup
+constexpr int TILE = 32;                    // output tile of wider maps
+constexpr int THREADS_WRAP = 512, THREADS_TILE = 1024;
+constexpr int BWD_THREADS = 256;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {  // nearest, ties to even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint32_t h) { return __uint_as_float(h << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// two floats to packed bfloat16 (lo | hi << 16), nearest-even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
+__device__ __forceinline__ float relu(float z) { return z > 0.f ? z : 0.f; }
+
+// Packed bfloat16 weights in MFMA operand order, built once per forward call
+// by k_cnn_prep: Aop[layer][jj][lane] holds the 8 K values of lane `lane`
+// for the K block jj (A operand of v_mfma_f32_16x16x32_bf16: row co = lane
+// % 16, K = 8 (lane / 16) + 0..7).  Layers 2-4: K block jj covers taps 2jj
+// (lane groups 0, 1) and 2jj + 1 (groups 2, 3), 16 input channels each;
+// layer 1: K = tap (< 9) in block 0.
+constexpr int AOP_UINT4 = 4 * 5 * 64;
+
+__global__ void k_cnn_prep(const float *__restrict__ params, uint4 *__restrict__ Aop) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= AOP_UINT4) return;
+  const int layer = t / 320, jj = (t / 64) % 5, lane = t % 64;
+  const int co = lane & 15, g = lane >> 4;
+  float v[8];
+  if (layer == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = jj == 0 ? 8 * g + j : 99;
+      v[j] = k < 9 ? params[OFF_W1 + co * 9 + k] : 0.f;
+    }
+  } else {
+    const int off = layer == 1 ? OFF_W2 : (layer == 2 ? OFF_W3 : OFF_W4);
+    const int tap = 2 * jj + (g >> 1), ci0 = 8 * (g & 1);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = tap < 9 ? params[off + (co * 9 + tap) * CH + ci0 + j] : 0.f;
+  }
+  uint32_t w[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w[j] = pack_bf16(v[2 * j], v[2 * j + 1]);
+  Aop[t] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Running maximum with the lowest index on ties.
+__device__ __forceinline__ void keep_max(float v, int i, float &best, int &bi) {
+  if (v > best || (v == best && i < bi)) {
+    best = v;
+    bi = i;
+  }
+}
+
+struct Pool {
+  float best[4];
+  int idx[4];
+};
+
+// One 3x3 layer.  The input buffer has row stride S_in and holds, for
+// output position (y, x) (0 <= y, x < R_out), the 3x3 window at rows
+// y..y+2 and columns x..x+2 (a border or halo of one position on each
+// side).  CIN1: single-channel input [..]; otherwise [..][16].  Outputs go
+// to out[(y + o) S_out + x + o][16] (o = out_off); LAST folds them into the
+// pooling state instead, with global position ((oy + y) mod M, (ox + x) mod M).
+template <bool CIN1, bool LAST>
+__device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out, int S_in,
+                                           int R_out, int S_out, int out_off, const uint4 *__restrict__ Aop,
+                                           const float *__restrict__ b, int M, int oy, int ox, Pool &pool) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  bf16x8 A[5];
+#pragma unroll
+  for (int jj = 0; jj < (CIN1 ? 1 : 5); ++jj) A[jj] = __builtin_bit_cast(bf16x8, Aop[jj * 64 + lane]);
+  float bias[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bias[r] = b[4 * g + r];
+  // this lane's input offset (positions) of each K block: tap 2jj or 2jj + 1
+  // (block 4 of lane groups 2, 3 has no tap: it reads tap 8 and zeroes it)
+  int toff[5];
+#pragma unroll
+  for (int jj = 0; jj < 5; ++jj) {
+    const int tap = min(2 * jj + (g >> 1), 8);
+    toff[jj] = (tap / 3) * S_in + tap % 3;
+  }
+  const int npos = R_out * R_out, ngroups = (npos + 15) >> 4;
+  const float inv = 1.f / (float)R_out;
+  for (int grp = wave; grp < ngroups; grp += nwaves) {
+    int p = (grp << 4) + li;
+    const bool valid = p < npos;
+    p = valid ? p : npos - 1;  // spare lanes repeat the last position, not stored
+    const int y = (int)(((float)p + 0.5f) * inv);
+    const int x = p - y * R_out;
+    const int base = y * S_in + x;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (CIN1) {
+      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (g == 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = in[base + (j / 3) * S_in + j % 3];
+      } else if (g == 1) {
+        v[0] = in[base + 2 * S_in + 2];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], __builtin_bit_cast(bf16x8, v), acc, 0, 0, 0);
+    } else {
+      uint4 v[5];
+#pragma unroll
+      for (int jj = 0; jj < 5; ++jj) v[jj] = *reinterpret_cast<const uint4 *>(in + (base + toff[jj]) * CH + 8 * (g & 1));
+      if (g >= 2) v[4] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int jj = 0; jj < 5; ++jj)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[jj], __builtin_bit_cast(bf16x8, v[jj]), acc, 0, 0, 0);
+    }
+    // lane holds channels 4g..4g+3 of position p
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = relu(acc[r] + bias[r]);
+    if (!LAST) {
+      if (valid)
+        *reinterpret_cast<uint2 *>(out + ((y + out_off) * S_out + x + out_off) * CH + 4 * g) =
+            make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+    } else {
+      const int gi = ((oy + y) % M) * M + (ox + x) % M;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) keep_max(v[r], gi, pool.best[r], pool.idx[r]);
+    }
+  }
+}
+
+// Wrapped border of a [(M+2)^2][16] buffer: row 0 / M+1 and column 0 / M+1
+// copy the opposite interior edge.
+__device__ __forceinline__ void fill_border(uint16_t *buf, int M) {
+  const int S = M + 2, nb = 4 * (M + 1);
+  uint4 *u = reinterpret_cast<uint4 *>(buf);
+  for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) {
+    const int c = i >> 1, half = i & 1;
+    int r, q;  // border cell (r, q)
+    if (c < M + 2) {
+      r = 0;
+      q = c;
+    } else if (c < 2 * (M + 2)) {
+      r = M + 1;
+      q = c - (M + 2);
+    } else if (c < 2 * (M + 2) + M) {
+      r = c - 2 * (M + 2) + 1;
+      q = 0;
+    } else {
+      r = c - 2 * (M + 2) - M + 1;
+      q = M + 1;
+    }
+    const int sr = r == 0 ? M : (r == M + 1 ? 1 : r), sq = q == 0 ? M : (q == M + 1 ? 1 : q);
+    u[(r * S + q) * 2 + half] = u[(sr * S + sq) * 2 + half];
+  }
+}
+
+struct FwdArgs {
+  const uint8_t *counts;  // [n][M][M]
+  int M;
+  int ntile;              // tiles per side (tiled mode)
+  const uint4 *Aop;       // packed weights (k_cnn_prep)
+  const float *params;
+  float *pred;            // [n]
+  float *feat;            // [n][16] or null
+  int32_t *argmax;        // [n][16] or null
+  uint16_t *store;        // [3][n][M*M][16] layer 1-3 activations, or null (whole maps only)
+  unsigned long long *pool;  // tiled mode: [n][16] packed maxima, zero on entry
+  int64_t n;
+};
+
+// Interior of a bordered [(M+2)^2][16] buffer to [M*M][16] in HBM.
+__device__ __forceinline__ void store_interior(const uint16_t *src, uint16_t *dst, int M) {
+  const uint4 *s = reinterpret_cast<const uint4 *>(src);
+  uint4 *d = reinterpret_cast<uint4 *>(dst);
+  for (int i = threadIdx.x; i < 2 * M * M; i += blockDim.x) {
+    const int pos = i >> 1, y = pos / M, x = pos - y * M;
+    d[i] = s[((y + 1) * (M + 2) + x + 1) * 2 + (i & 1)];
+  }
+}
+
+// Reduction of the per-lane pooling state to per-channel (max, index) in
+// threads 0..15 (returned through `best`, `bi`).
+__device__ __forceinline__ void pool_reduce(Pool &pool, float *red_v, int *red_i, float &best, int &bi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+#pragma unroll
+  for (int s = 1; s < 16; s <<= 1)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float ov = __shfl_xor(pool.best[r], s);
+      const int oi = __shfl_xor(pool.idx[r], s);
+      keep_max(ov, oi, pool.best[r], pool.idx[r]);
+    }
+  if ((lane & 15) == 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red_v[wave * CH + 4 * (lane >> 4) + r] = pool.best[r];
+      red_i[wave * CH + 4 * (lane >> 4) + r] = pool.idx[r];
+    }
+  __syncthreads();
+  best = -1.f;
+  bi = 0x7FFFFFFF;
+  if (threadIdx.x < CH)
+    for (int w = 0; w < nwaves; ++w) keep_max(red_v[w * CH + threadIdx.x], red_i[w * CH + threadIdx.x], best, bi);
+  if (bi == 0x7FFFFFFF) {  // no number in the channel (NaN activations)
+    best = __builtin_nanf("");
+    bi = -1;
+  }
+}
+
+__device__ __forceinline__ float head(const float *__restrict__ params, const float *feat) {
+  float acc = params[OFF_BL];
+  for (int c = 0; c < CH; ++c) acc = fmaf(params[OFF_WL + c], feat[c], acc);
+  return acc;
+}
+
+__device__ __forceinline__ void pool_init(Pool &pool) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    pool.best[r] = -1.f;
+    pool.idx[r] = 0x7FFFFFFF;
+  }
+}
+
+// Whole map per workgroup (M <= 32), buffers with a wrapped border of one
+// position.  LDS: x [(M+2)^2] | A, B [(M+2)^2][16] | pooling.
+__global__ __launch_bounds__(THREADS_WRAP) void k_cnn_forward_wrap(FwdArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int M = a.M, S = M + 2, SS = S * S;
+  uint16_t *xin = reinterpret_cast<uint16_t *>(smem);
+  uint16_t *bufA = xin + ((SS + 7) & ~7);
+  uint16_t *bufB = bufA + SS * CH;
+  float *red_v = reinterpret_cast<float *>(bufB + SS * CH);
+  int *red_i = reinterpret_cast<int *>(red_v + (blockDim.x >> 6) * CH);
+  __shared__ float feat_s[CH];
+  const int64_t s = blockIdx.x;
+  const uint8_t *cnt = a.counts + s * M * M;
+  for (int i = threadIdx.x; i < SS; i += blockDim.x) {
+    const int r = i / S, q = i - r * S;
+    const int y = r == 0 ? M - 1 : (r == M + 1 ? 0 : r - 1), x = q == 0 ? M - 1 : (q == M + 1 ? 0 : q - 1);
+    xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
+  }
+  __syncthreads();
+  const float *P = a.params;
+  Pool pool;
+  pool_init(pool);
+  const size_t act = (size_t)M * M * CH;
+  conv_layer<true, false>(xin, bufA, S, M, S, 1, a.Aop, P + OFF_B1, M, 0, 0, pool);
+  __syncthreads();
+  fill_border(bufA, M);
+  if (a.store) store_interior(bufA, a.store + (size_t)s * act, M);
+  __syncthreads();
+  conv_layer<false, false>(bufA, bufB, S, M, S, 1, a.Aop + 320, P + OFF_B2, M, 0, 0, pool);
+  __syncthreads();
+  fill_border(bufB, M);
+  if (a.store) store_interior(bufB, a.store + ((size_t)a.n + s) * act, M);
+  __syncthreads();
+  conv_layer<false, false>(bufB, bufA, S, M, S, 1, a.Aop + 640, P + OFF_B3, M, 0, 0, pool);
+  __syncthreads();
+  fill_border(bufA, M);
+  if (a.store) store_interior(bufA, a.store + ((size_t)2 * a.n + s) * act, M);
+  __syncthreads();
+  conv_layer<false, true>(bufA, nullptr, S, M, 0, 0, a.Aop + 960, P + OFF_B4, M, 0, 0, pool);
+  float best;
+  int bi;
+  pool_reduce(pool, red_v, red_i, best, bi);
+  if (threadIdx.x < CH) {
+    feat_s[threadIdx.x] = best;
+    if (a.feat) a.feat[s * CH + threadIdx.x] = best;
+    if (a.argmax) a.argmax[s * CH + threadIdx.x] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.pred[s] = head(P, feat_s);
+}
+
+// One 32 x 32 output tile per workgroup; each layer shrinks the region by
+// one position per side.  LDS: x [40^2] | A [38^2][16] | B [36^2][16] | pooling.
+__global__ __launch_bounds__(THREADS_TILE) void k_cnn_forward_tile(FwdArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4, R3 = TILE + 2;
+  const int M = a.M;
+  uint16_t *xin = reinterpret_cast<uint16_t *>(smem);
+  uint16_t *bufA = xin + R0 * R0;
+  uint16_t *bufB = bufA + R1 * R1 * CH;
+  float *red_v = reinterpret_cast<float *>(bufB + R2 * R2 * CH);
+  int *red_i = reinterpret_cast<int *>(red_v + (blockDim.x >> 6) * CH);
+  const int nt = a.ntile;
+  const int64_t s = blockIdx.x / (nt * nt);
+  const int t = (int)(blockIdx.x % (nt * nt));
+  const int ty0 = (t / nt) * TILE, tx0 = (t % nt) * TILE;
+  const uint8_t *cnt = a.counts + s * M * M;
+  for (int i = threadIdx.x; i < R0 * R0; i += blockDim.x) {
+    const int y = (ty0 - 4 + i / R0 + M) % M, x = (tx0 - 4 + i % R0 + M) % M;
+    xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
+  }
+  __syncthreads();
+  const float *P = a.params;
+  Pool pool;
+  pool_init(pool);
+  conv_layer<true, false>(xin, bufA, R0, R1, R1, 0, a.Aop, P + OFF_B1, M, 0, 0, pool);
+  __syncthreads();
+  conv_layer<false, false>(bufA, bufB, R1, R2, R2, 0, a.Aop + 320, P + OFF_B2, M, 0, 0, pool);
+  __syncthreads();
+  conv_layer<false, false>(bufB, bufA, R2, R3, R3, 0, a.Aop + 640, P + OFF_B3, M, 0, 0, pool);
+  __syncthreads();
+  conv_layer<false, true>(bufA, nullptr, R3, TILE, 0, 0, a.Aop + 960, P + OFF_B4, M, ty0, tx0, pool);
+  float best;
+  int bi;
+  pool_reduce(pool, red_v, red_i, best, bi);
+  if (threadIdx.x < CH && bi >= 0) {
+    // non-negative floats order as their bit patterns; ties keep the lowest index
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)bi);
+    atomicMax(&a.pool[s * CH + threadIdx.x], key);
+  }
+}
+
+__global__ void k_cnn_head(FwdArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  float feat[CH];
+  for (int c = 0; c < CH; ++c) {
+    const unsigned long long key = a.pool[s * CH + c];  // 0: no tile had a number
+    feat[c] = key ? __uint_as_float((uint32_t)(key >> 32)) : __builtin_nanf("");
+    if (a.feat) a.feat[s * CH + c] = feat[c];
+    if (a.argmax) a.argmax[s * CH + c] = key ? (int32_t)(0xFFFFFFFFu - (uint32_t)key) : -1;
+  }
+  a.pred[s] = head(a.params, feat);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Backward (maps up to 32 x 32)
+// ---------------------------------------------------------------------------
+
+struct BwdArgs {
+  const uint8_t *counts;   // [n][M][M]
+  int M;
+  int64_t n;
+  const float *params;
+  const uint16_t *store;   // [3][n][M*M][16]
+  const float *feat;       // [n][16]
+  const int32_t *argmax;   // [n][16]
+  const float *pred;       // [n]
+  const float *target;     // [n]
+  float *part;             // [n][NPARAM] per-sample gradient of the batch-mean loss
+};
+
+// window of radius R around P (offsets -R..R), position index of offset (oy, ox)
+__device__ __forceinline__ int wpos(int P, int oy, int ox, int M) {
+  int y = P / M + oy, x = P % M + ox;
+  y += y < 0 ? M : 0;
+  y -= y >= M ? M : 0;
+  x += x < 0 ? M : 0;
+  x -= x >= M ? M : 0;
+  return y * M + x;
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_cnn_backward(BwdArgs a) {
+  // LDS (float): W2, W3, W4 [16][9][16]; W1 [16][9]; windows; dz; accumulators
+  __shared__ float W2[2304], W3[2304], W4[2304], W1[144];
+  __shared__ float a3w[9 * CH], a2w[25 * CH], a1w[49 * CH], xw[81];
+  __shared__ float dz3[9 * CH], dz2[25 * CH], dz1[49 * CH];
+  __shared__ float gW1[144], gB1[CH], gW2[2304], gB2[CH], gW3[2304], gB3[CH], gW4[2304], gB4[CH];
+  const int tid = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const int M = a.M, MM = M * M;
+  const float *P = a.params;
+  for (int i = tid; i < 2304; i += BWD_THREADS) {  // weights as the forward used them (bfloat16)
+    W2[i] = from_bf16(to_bf16(P[OFF_W2 + i]));
+    W3[i] = from_bf16(to_bf16(P[OFF_W3 + i]));
+    W4[i] = from_bf16(to_bf16(P[OFF_W4 + i]));
+    gW2[i] = gW3[i] = gW4[i] = 0.f;
+  }
+  if (tid < 144) {
+    W1[tid] = from_bf16(to_bf16(P[OFF_W1 + tid]));
+    gW1[tid] = 0.f;
+  }
+  if (tid < CH) gB1[tid] = gB2[tid] = gB3[tid] = gB4[tid] = 0.f;
+  const float dpred = 2.f * (a.pred[s] - a.target[s]) / (float)a.n;
+  const size_t act = (size_t)MM * CH;
+  const uint16_t *A1 = a.store + (size_t)s * act;
+  const uint16_t *A2 = a.store + ((size_t)a.n + s) * act;
+  const uint16_t *A3 = a.store + ((size_t)2 * a.n + s) * act;
+  const uint8_t *cnt = a.counts + s * MM;
+  __syncthreads();
+
+  for (int co = 0; co < CH; ++co) {
+    const float f = a.feat[s * CH + co];
+    const float gz = f > 0.f ? dpred * P[OFF_WL + co] : 0.f;  // d loss / d z4 at the maximum
+    if (gz == 0.f) continue;                                   // uniform over the workgroup
+    const int Pc = a.argmax[s * CH + co];
+    if (Pc < 0 || Pc >= MM) continue;  // only with NaN activations (then gz is not 0)
+    for (int i = tid; i < 9 * CH; i += BWD_THREADS) {
+      const int q = i / CH, c = i % CH;
+      a3w[i] = from_bf16(A3[(size_t)wpos(Pc, q / 3 - 1, q % 3 - 1, M) * CH + c]);
+    }
+    for (int i = tid; i < 25 * CH; i += BWD_THREADS) {
+      const int q = i / CH, c = i % CH;
+      a2w[i] = from_bf16(A2[(size_t)wpos(Pc, q / 5 - 2, q % 5 - 2, M) * CH + c]);
+    }
+    for (int i = tid; i < 49 * CH; i += BWD_THREADS) {
+      const int q = i / CH, c = i % CH;
+      a1w[i] = from_bf16(A1[(size_t)wpos(Pc, q / 7 - 3, q % 7 - 3, M) * CH + c]);
+    }
+    for (int i = tid; i < 81; i += BWD_THREADS) xw[i] = (float)cnt[wpos(Pc, i / 9 - 4, i % 9 - 4, M)] * 0.125f;
+    __syncthreads();
+    // layer 4: weight gradient of channel co and the layer-3 window
+    if (tid < 9 * CH) {
+      const int d = tid / CH, ci = tid % CH;
+      gW4[(co * 9 + d) * CH + ci] += gz * a3w[d * CH + ci];
+      dz3[d * CH + ci] = a3w[d * CH + ci] > 0.f ? gz * W4[(co * 9 + d) * CH + ci] : 0.f;
+    }
+    if (tid == 0) gB4[co] += gz;
+    __syncthreads();
+    // layer 3: weights from dz3 (3x3) and a2 (5x5); dz2 on the 5x5 window
+    for (int e = tid; e < 2304; e += BWD_THREADS) {
+      const int c = e / 144, d = (e / CH) % 9, ci = e % CH;
+      const int dy = d / 3 - 1, dx = d % 3 - 1;
+      float acc = 0.f;
+      for (int q = 0; q < 9; ++q) {
+        const int qy = q / 3 - 1, qx = q % 3 - 1;
+        acc = fmaf(dz3[q * CH + c], a2w[((qy + dy + 2) * 5 + (qx + dx + 2)) * CH + ci], acc);
+      }
+      gW3[e] += acc;
+    }
+    if (tid < CH) {
+      float acc = 0.f;
+      for (int q = 0; q < 9; ++q) acc += dz3[q * CH + tid];
+      gB3[tid] += acc;
+    }
+    for (int e = tid; e < 25 * CH; e += BWD_THREADS) {
+      const int r = e / CH, ci = e % CH;
+      const int ry = r / 5 - 2, rx = r % 5 - 2;
+      float acc = 0.f;
+      for (int d = 0; d < 9; ++d) {
+        const int qy = ry - (d / 3 - 1), qx = rx - (d % 3 - 1);
+        if (qy < -1 || qy > 1 || qx < -1 || qx > 1) continue;
+        const int q = (qy + 1) * 3 + (qx + 1);
+        for (int c = 0; c < CH; ++c) acc = fmaf(dz3[q * CH + c], W3[(c * 9 + d) * CH + ci], acc);
+      }
+      dz2[e] = a2w[e] > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    // layer 2: weights from dz2 (5x5) and a1 (7x7); dz1 on the 7x7 window
+    for (int e = tid; e < 2304; e += BWD_THREADS) {
+      const int c = e / 144, d = (e / CH) % 9, ci = e % CH;
+      const int dy = d / 3 - 1, dx = d % 3 - 1;
+      float acc = 0.f;
+      for (int r = 0; r < 25; ++r) {
+        const int ry = r / 5 - 2, rx = r % 5 - 2;
+        acc = fmaf(dz2[r * CH + c], a1w[((ry + dy + 3) * 7 + (rx + dx + 3)) * CH + ci], acc);
+      }
+      gW2[e] += acc;
+    }
+    if (tid < CH) {
+      float acc = 0.f;
+      for (int r = 0; r < 25; ++r) acc += dz2[r * CH + tid];
+      gB2[tid] += acc;
+    }
+    for (int e = tid; e < 49 * CH; e += BWD_THREADS) {
+      const int u = e / CH, ci = e % CH;
+      const int uy = u / 7 - 3, ux = u % 7 - 3;
+      float acc = 0.f;
+      for (int d = 0; d < 9; ++d) {
+        const int ry = uy - (d / 3 - 1), rx = ux - (d % 3 - 1);
+        if (ry < -2 || ry > 2 || rx < -2 || rx > 2) continue;
+        const int r = (ry + 2) * 5 + (rx + 2);
+        for (int c = 0; c < CH; ++c) acc = fmaf(dz2[r * CH + c], W2[(c * 9 + d) * CH + ci], acc);
+      }
+      dz1[e] = a1w[e] > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    // layer 1: weights from dz1 (7x7) and the input (9x9)
+    if (tid < 144) {
+      const int c = tid / 9, d = tid % 9;
+      const int dy = d / 3 - 1, dx = d % 3 - 1;
+      float acc = 0.f;
+      for (int u = 0; u < 49; ++u) {
+        const int uy = u / 7 - 3, ux = u % 7 - 3;
+        acc = fmaf(dz1[u * CH + c], xw[(uy + dy + 4) * 9 + (ux + dx + 4)], acc);
+      }
+      gW1[tid] += acc;
+    }
+    if (tid < CH) {
+      float acc = 0.f;
+      for (int u = 0; u < 49; ++u) acc += dz1[u * CH + tid];
+      gB1[tid] += acc;
+    }
+    __syncthreads();
+  }
+  float *out = a.part + s * NPARAM;
+  for (int i = tid; i < 2304; i += BWD_THREADS) {
+    out[OFF_W2 + i] = gW2[i];
+    out[OFF_W3 + i] = gW3[i];
+    out[OFF_W4 + i] = gW4[i];
+  }
+  if (tid < 144) out[OFF_W1 + tid] = gW1[tid];
+  if (tid < CH) {
+    out[OFF_B1 + tid] = gB1[tid];
+    out[OFF_B2 + tid] = gB2[tid];
+    out[OFF_B3 + tid] = gB3[tid];
+    out[OFF_B4 + tid] = gB4[tid];
+    out[OFF_WL + tid] = dpred * a.feat[s * CH + tid];
+  }
+  if (tid == 0) out[OFF_BL] = dpred;
+}
+
+// grad[j] = sum over samples (in order) of part[s][j]; loss = mean squared error
+__global__ void k_cnn_reduce(const float *part, int64_t n, float *grad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= NPARAM) return;
+  float acc = 0.f;
+  for (int64_t s = 0; s < n; ++s) acc += part[s * NPARAM + j];
+  grad[j] = acc;
+}
+
+__global__ void k_cnn_loss(const float *pred, const float *target, int64_t n, float *loss) {
+  __shared__ float red[256];
+  float acc = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float d = pred[i] - target[i];
+    acc = fmaf(d, d, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] / (float)n;
+}
+
+__global__ void k_cnn_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
+                           float c1, float c2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= NPARAM) return;
+  const float gj = g[j];
+  const float mj = b1 * m[j] + (1.f - b1) * gj;
+  const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+  m[j] = mj;
+  v[j] = vj;
+  p[j] -= lr * (mj * c1) / (sqrtf(vj * c2) + eps);
+}
+
+struct InitBounds {
+  double b[5];  // W1, W2, W3, W4, head
+};
+
+__global__ void k_cnn_init(float *p, uint32_t k0, uint32_t k1, InitBounds ib) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= NPARAM) return;
+  double bound = 0.0;
+  if (j < OFF_B1) bound = ib.b[0];
+  else if (j >= OFF_W2 && j < OFF_B2) bound = ib.b[1];
+  else if (j >= OFF_W3 && j < OFF_B3) bound = ib.b[2];
+  else if (j >= OFF_W4 && j < OFF_B4) bound = ib.b[3];
+  else if (j >= OFF_WL && j < OFF_BL) bound = ib.b[4];
+  float w = 0.f;
+  if (bound > 0.0) {
+    const Words4 r = philox4x32_10((uint32_t)j, k0, k1, INIT_TAG);
+    const double u = ((double)r.w0 + 0.5) / 4294967296.0;
+    w = (float)((2.0 * u - 1.0) * bound);
+  }
+  p[j] = w;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t wrap_lds(int M, int threads) {
+  const size_t SS = (size_t)(M + 2) * (M + 2);
+  return ((SS + 7) & ~(size_t)7) * 2 + 2 * SS * CH * 2 + (size_t)(threads / 64) * CH * 8;
+}
+size_t tile_lds(int threads) {
+  constexpr size_t R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4;
+  return R0 * R0 * 2 + (R1 * R1 + R2 * R2) * CH * 2 + (size_t)(threads / 64) * CH * 8;
+}
+
+// Workspace of the training step: stored activations, feat, argmax, pred,
+// per-sample gradients.
+struct BwdLayout {
+  uint16_t *store;
+  float *feat, *pred, *part;
+  int32_t *argmax;
+  void *fwd_ws;
+  size_t bytes;
+};
+BwdLayout bwd_layout(int M, int64_t n, void *base) {
+  BwdLayout l;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    void *p = base ? (void *)((char *)base + off) : nullptr;
+    off += align256(b);
+    return p;
+  };
+  l.store = (uint16_t *)take((size_t)3 * n * M * M * CH * 2);
+  l.feat = (float *)take((size_t)n * CH * 4);
+  l.argmax = (int32_t *)take((size_t)n * CH * 4);
+  l.pred = (float *)take((size_t)n * 4);
+  l.part = (float *)take((size_t)n * NPARAM * 4);
+  l.fwd_ws = take(cnn_forward_ws(M, n));
+  l.bytes = off;
+  return l;
+}
+
+int check_map(int M, int64_t n) {
+  if (M < 2 || M > 2048) return fail_with(MPD_ERR_L, "map size M=%d outside [2, 2048]", M);
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "batch size %lld out of range", (long long)n);
+  return MPD_OK;
+}
+
+}  // namespace
+
+// Forward workspace: packed weights, then (maps wider than 32) the pooled maxima.
+size_t cnn_forward_ws(int M, int64_t n) {
+  return align256(AOP_UINT4 * sizeof(uint4)) + (M <= WRAP_MAX ? 0 : align256((size_t)n * CH * sizeof(unsigned long long)));
+}
+
+int cnn_forward_run(const uint8_t *counts, int M, int64_t n, const float *params, float *pred, float *feat,
+                    int32_t *argmax, uint16_t *store, void *ws, hipStream_t stream) {
+  if (n == 0) return MPD_OK;
+  FwdArgs a;
+  a.counts = counts;
+  a.M = M;
+  a.ntile = (M + TILE - 1) / TILE;
+  a.params = params;
+  a.pred = pred;
+  a.feat = feat;
+  a.argmax = argmax;
+  a.store = store;
+  a.pool = nullptr;
+  a.n = n;
+  uint4 *Aop = (uint4 *)ws;
+  a.Aop = Aop;
+  hipLaunchKernelGGL(k_cnn_prep, dim3((AOP_UINT4 + 255) / 256), dim3(256), 0, stream, params, Aop);
+  HIP_TRY(hipGetLastError());
+  ProfScope ps("k_cnn_forward", stream);
+  if (M <= WRAP_MAX) {
+    hipLaunchKernelGGL(k_cnn_forward_wrap, dim3((unsigned)n), dim3(THREADS_WRAP), wrap_lds(M, THREADS_WRAP), stream,
+                       a);
+    HIP_TRY(hipGetLastError());
+    return MPD_OK;
+  }
+  if (store != nullptr) return fail_with(MPD_ERR_L, "stored activations need M <= %d", WRAP_MAX);
+  a.pool = (unsigned long long *)((char *)ws + align256(AOP_UINT4 * sizeof(uint4)));
+  const int64_t cnt = n * CH;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.pool, cnt);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cnn_forward_tile, dim3((unsigned)(n * a.ntile * a.ntile)), dim3(THREADS_TILE),
+                     tile_lds(THREADS_TILE), stream, a);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cnn_head, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+}  // namespace mpd
+
+using namespace mpd;
+
+extern "C" {
+
+int mpd_cnn_init(float *d_params, uint64_t seed, void *stream) {
+  g_last_error.clear();
+  if (d_params == nullptr || ((uintptr_t)d_params & 3u)) return fail_with(MPD_ERR_PTR, "params NULL or misaligned");
+  InitBounds ib;
+  const int fan[5] = {9, 144, 144, 144, 16};
+  for (int i = 0; i < 5; ++i) ib.b[i] = sqrt(6.0 / fan[i]);
+  hipLaunchKernelGGL(k_cnn_init, dim3((NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_params,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), ib);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+size_t mpd_cnn_forward_workspace_bytes(int M, int64_t n) { return n > 0 ? cnn_forward_ws(M, n) : 0; }
+
+int mpd_cnn_forward(const uint8_t *d_counts, int M, int64_t n, const float *d_params, float *d_pred, float *d_feat,
+                    int32_t *d_argmax, void *d_workspace, size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  int rc = check_map(M, n);
+  if (rc != MPD_OK) return rc;
+  if (n == 0) return MPD_OK;
+  if (d_counts == nullptr || d_params == nullptr || d_pred == nullptr) return fail_with(MPD_ERR_PTR, "NULL argument");
+  if (((uintptr_t)d_params | (uintptr_t)d_pred | (uintptr_t)d_feat | (uintptr_t)d_argmax) & 3u)
+    return fail_with(MPD_ERR_PTR, "float/int arrays must be 4-byte aligned");
+  const size_t need = cnn_forward_ws(M, n);
+  if (d_workspace == nullptr || ws_bytes < need)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  return cnn_forward_run(d_counts, M, n, d_params, d_pred, d_feat, d_argmax, nullptr, d_workspace,
+                         (hipStream_t)stream);
+}
+
+size_t mpd_cnn_train_workspace_bytes(int M, int64_t n) {
+  if (M < 2 || M > WRAP_MAX || n <= 0) return 0;
+  return bwd_layout(M, n, nullptr).bytes;
+}
+
+int mpd_cnn_loss_grad(const uint8_t *d_counts, int M, int64_t n, const float *d_params, const float *d_target,
+                      float *d_grad, float *d_loss, float *d_pred, void *d_workspace, size_t ws_bytes,
+                      void *stream) {
+  g_last_error.clear();
+  if (M < 2 || M > WRAP_MAX) return fail_with(MPD_ERR_L, "training needs 2 <= M <= %d (got %d)", WRAP_MAX, M);
+  if (n <= 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "batch size %lld out of range", (long long)n);
+  if (d_counts == nullptr || d_params == nullptr || d_target == nullptr || d_grad == nullptr || d_loss == nullptr)
+    return fail_with(MPD_ERR_PTR, "NULL argument");
+  if (((uintptr_t)d_params | (uintptr_t)d_target | (uintptr_t)d_grad | (uintptr_t)d_loss | (uintptr_t)d_pred) & 3u)
+    return fail_with(MPD_ERR_PTR, "float arrays must be 4-byte aligned");
+  const BwdLayout l = bwd_layout(M, n, d_workspace);
+  if (d_workspace == nullptr || ws_bytes < l.bytes)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, l.bytes);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = cnn_forward_run(d_counts, M, n, d_params, l.pred, l.feat, l.argmax, l.store, l.fwd_ws, st);
+  if (rc != MPD_OK) return rc;
+  BwdArgs b;
+  b.counts = d_counts;
+  b.M = M;
+  b.n = n;
+  b.params = d_params;
+  b.store = l.store;
+  b.feat = l.feat;
+  b.argmax = l.argmax;
+  b.pred = l.pred;
+  b.target = d_target;
+  b.part = l.part;
+  {
+    ProfScope ps("k_cnn_backward", st);
+    hipLaunchKernelGGL(k_cnn_backward, dim3((unsigned)n), dim3(BWD_THREADS), 0, st, b);
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cnn_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, l.part, n, d_grad);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cnn_loss, dim3(1), dim3(256), 0, st, l.pred, d_target, n, d_loss);
+  HIP_TRY(hipGetLastError());
+  if (d_pred != nullptr) HIP_TRY(hipMemcpyAsync(d_pred, l.pred, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+  return MPD_OK;
+}
+
+int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d_v, int step, float lr, float beta1,
+                      float beta2, float eps, void *stream) {
+  g_last_error.clear();
+  if (d_params == nullptr || d_grad == nullptr || d_m == nullptr || d_v == nullptr)
+    return fail_with(MPD_ERR_PTR, "NULL argument");
+  if (step < 1) return fail_with(MPD_ERR_N, "step counts from 1 (got %d)", step);
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail_with(MPD_ERR_P, "Adam hyper-parameters out of range");
+  const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, step)));
+  hipLaunchKernelGGL(k_cnn_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_params, d_grad,
+                     d_m, d_v, lr, beta1, beta2, eps, c1, c2);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+}  // extern "C"

@@ -37,13 +37,13 @@ __device__ __forceinline__ uint32_t pmax3(uint32_t a, uint32_t b, uint32_t c) {
   return pmax(pmax(a, b), c);
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter (c0, 0, 0, 0).
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter (c0, c1, 0, 0).
 struct Words4 {
   uint32_t w0, w1, w2, w3;
 };
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t k0, uint32_t k1) {
-  uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t k0, uint32_t k1, uint32_t c1 = 0u) {
+  uint32_t c2 = 0u, c3 = 0u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);

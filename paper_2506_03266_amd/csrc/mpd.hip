@@ -4,14 +4,17 @@
 //  * resident: one workgroup holds a whole L x L sample in LDS/VGPRs and runs
 //    it from noise to termination with no HBM traffic for the state
 //    (L <= 128 with a strip height dividing L);
-//  * band (L = 256): each workgroup holds a full-height band of 128 columns
-//    in VGPRs (band.h), of which all but a halo of 4k columns on each side
-//    are its own (k = decoder steps per pass: a step moves information by
-//    v = 3 sites for the messages plus 1 for the feedback); it runs k steps
-//    on chip and writes its own columns back to HBM.  The first pass
-//    generates the noise for its band in place.  Between passes a small
-//    kernel turns the per-step "anyons left" bits into T_dec and compacts
-//    the list of unfinished samples.
+//  * band (L >= 256, multiples of 16): each workgroup holds a region of 128
+//    columns x 256 rows in VGPRs (band.h), of which all but a halo of 4k
+//    columns (and 4k rows rounded up to 16, unless the region spans the
+//    lattice height) on each side are its own (k = decoder steps per pass:
+//    a step moves information by v = 3 sites for the messages plus 1 for
+//    the feedback); it runs k steps on chip and writes its own sites back to
+//    HBM.  A separate kernel draws the noise and the initial syndrome once.
+//    Between passes a small kernel turns the per-step "anyons left" bits
+//    into T_dec and compacts the list of unfinished samples; each sample
+//    keeps its own step count, so groups of samples may start with passes
+//    of different depth (learned scheduling, cnn.hip).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -27,6 +30,7 @@
 
 #include "band.h"
 #include "engine.h"
+#include "host.h"
 #include "mpd.h"
 
 namespace mpd {
@@ -194,10 +198,10 @@ constexpr int TILE_H = BAND_H;             // rows per syndrome word pair in HBM
 
 struct BandArgs {
   int L;
-  int first;        // 1: registers start at zero (syndrome from k_band_noise), 0: load state
   int write_state;  // 0: do not store the state (samples expected to finish in this pass)
-  int k;            // decoder steps in this pass
-  int t0;           // steps already done
+  int k;            // decoder steps in this pass (fewer for a sample that reaches T_max)
+  int T_max;
+  const int32_t *t_done;  // per sample: steps already done (0: registers start empty)
   int hx, tx;       // column halo, owned columns per tile
   int hy, ty;       // row halo, owned rows per tile (ty == L: one full-height region, rows wrap)
   int ntx;          // tiles along x
@@ -206,9 +210,9 @@ struct BandArgs {
   const uint2 *Ssrc;      // [n][L/32][L/2] syndrome masks (s0, s1) of column pairs
   uint4 *Edst;
   uint2 *Sdst;
-  uint32_t *alive;  // per sample: bit 0 anyons at pass start, bit j after step t0+j
+  uint32_t *alive;  // per sample: bit 0 anyons at pass start, bit j after step t_done+j
   uint32_t *wind;   // per sample winding bits: Wx(E), Wy(E), Wx(C), Wy(C)
-  int *zero_count;  // counter to clear for the following compaction
+  int *zero_count;  // counter to clear for the following compaction, or nullptr
 };
 
 // With ty == L the region spans the full height (L == BAND_RY, rows wrap);
@@ -224,7 +228,9 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (scalar)
   const int sample = a.active[blockIdx.y];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
+  const int ks = min(a.k, a.T_max - t0);  // steps of this sample in this pass
   if (threadIdx.x == 0) red[0] = 0u;
 
   const bool wrapY = a.ty == L;
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   uint32_t wind = 0u;
   const size_t half_row = (size_t)L / 2;
   const size_t sidx = ((size_t)sample * (L / TILE_H) + gy / TILE_H) * half_row + (gx >> 1);
-  if (a.first) {  // registers start empty; the syndrome comes from k_band_noise
+  if (t0 == 0) {  // registers start empty; the syndrome comes from k_band_noise
 #pragma unroll
     for (int h = 0; h < H; ++h) b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
   } else {
@@ -278,8 +284,8 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
   const uint32_t own_mask = own_col ? own_rows : 0u;
   uint32_t bits = __syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u) ? 1u : 0u;
   uint4 *BND0 = BND, *BND1 = BND + BAND_NW * 2 * 64;
-  for (int st = 0; st < a.k; ++st) {
-    const uint32_t t3 = (uint32_t)(3 * (a.t0 + st));
+  for (int st = 0; st < ks; ++st) {
+    const uint32_t t3 = (uint32_t)(3 * (t0 + st));
     const uint32_t rows = wave_rows<H>(b.s0, b.s1);
     Moves mv = {0u, 0u, 0u, 0u};
     // three message updates; LDS boundary slots alternate between sub-steps
@@ -317,9 +323,9 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
 // Noise and initial syndrome of the band path, once per site.  A thread owns
 // one column pair over one 16-row strip (the band's HBM word); a workgroup
 // holds `CP` consecutive column pairs of `S` consecutive strips of one
-// sample.  Writes the syndrome words, the error winding bits (Wx(E), Wy(E))
-// and, if `counts` is set, the number of anyons in every 8x8 block as uint8
-// [n][L/8][L/8].  Links that cross into another workgroup (the y-links of
+// sample.  Writes the syndrome words and the error winding bits (Wx(E),
+// Wy(E)) unless their pointers are null, and, if `counts` is set, the number
+// of anyons in every 8x8 block as uint8 [n][L/8][L/8].  Links that cross into another workgroup (the y-links of
 // the row below the group, the x-links left of its first column when the
 // group is narrower than the lattice) are drawn again from the generator.
 __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const uint64_t *seeds, uint64_t thr,
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
   constexpr uint32_t F = full_mask<TILE_H>();
   const uint32_t s0 = (ex0 ^ exl ^ ey0 ^ ((ey0 << 1) | (eyd & 1u))) & F;
   const uint32_t s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | (eyd >> 1))) & F;
-  Sout[((size_t)sample * (L / TILE_H) + j) * P + q] = make_uint2(s0, s1);
+  if (Sout != nullptr) Sout[((size_t)sample * (L / TILE_H) + j) * P + q] = make_uint2(s0, s1);
   uint32_t wd = 0u;
   if (q == P - 1) wd ^= __popc(ex1) & 1u;                                  // x-links leaving column L-1
   if (j == L / TILE_H - 1) wd ^= (((ey0 ^ ey1) >> (TILE_H - 1)) & 1u) << 1;  // y-links leaving row L-1
@@ -386,7 +392,7 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
     atomicAdd(&cnt[(2 * jl + 1) * NB + bx], __popc(s0 >> 8) + __popc(s1 >> 8));
   }
   __syncthreads();
-  if (tid == 0 && red[0]) atomicXor(&wind[sample], red[0]);
+  if (wind != nullptr && tid == 0 && red[0]) atomicXor(&wind[sample], red[0]);
   if (counts != nullptr) {
     uint8_t *out = counts + (size_t)sample * (L / 8) * (L / 8) + (size_t)(2 * cy * S) * (L / 8) + cx * NB;
     for (int i = tid; i < 2 * S * NB; i += blockDim.x) out[(i / NB) * (L / 8) + i % NB] = (uint8_t)cnt[i];
@@ -395,16 +401,19 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
 
 // Per-pass bookkeeping: T_dec from the per-step bits, compaction of the
 // samples that still hold anyons.  status: 0 running, 1 decoded, 2 timeout.
-__global__ void k_finalize(int first, int k, int t0, int T_max, const int32_t *active, int nact,
+__global__ void k_finalize(int k, int T_max, const int32_t *active, int nact, int32_t *t_done,
                            uint32_t *alive, int32_t *T_dec, uint8_t *status, int32_t *next,
                            int *next_count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nact) return;
   const int s = active[i];
-  const uint32_t bits = alive[s] | (first ? 0u : 1u);
+  const int t0 = t_done[s];
+  const int ks = min(k, T_max - t0);
+  const uint32_t bits = alive[s] | (t0 == 0 ? 0u : 1u);
   alive[s] = 0u;
+  t_done[s] = t0 + ks;
   int td = -1;
-  for (int j = 0; j <= k; ++j)
+  for (int j = 0; j <= ks; ++j)
     if (!((bits >> j) & 1u)) {
       td = t0 + j;
       break;
@@ -412,7 +421,7 @@ __global__ void k_finalize(int first, int k, int t0, int T_max, const int32_t *a
   if (td >= 0) {
     T_dec[s] = td;
     status[s] = 1;
-  } else if (t0 + k >= T_max) {
+  } else if (t0 + ks >= T_max) {
     T_dec[s] = T_max;
     status[s] = 2;
   } else {
@@ -420,13 +429,14 @@ __global__ void k_finalize(int first, int k, int t0, int T_max, const int32_t *a
   }
 }
 
-__global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t *status,
+__global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t *status, int32_t *t_done,
                             int32_t *active) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   alive[i] = 0u;
   wind[i] = 0u;
   status[i] = 0;
+  t_done[i] = 0;
   active[i] = (int32_t)i;
 }
 
@@ -473,52 +483,7 @@ int fail_with(int code, const char *fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t _e = (expr);                                                               \
-    if (_e != hipSuccess)                                                                 \
-      return fail_with(MPD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));       \
-  } while (0)
-
-// Optional per-kernel timing with HIP events on the launch stream.
-struct ProfRec {
-  const char *name;
-  hipEvent_t a, b;
-};
-struct Profiler {
-  bool on = false;
-  std::vector<ProfRec> recs;
-  std::vector<hipEvent_t> pool;
-  hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-};
 Profiler g_prof;
-
-// Records events around one launch when profiling is on.
-struct ProfScope {
-  ProfRec r{nullptr, nullptr, nullptr};
-  hipStream_t st;
-  ProfScope(const char *name, hipStream_t s) : st(s) {
-    if (!g_prof.on) return;
-    r.name = name;
-    r.a = g_prof.get();
-    r.b = g_prof.get();
-    if (r.a) (void)hipEventRecord(r.a, st);
-  }
-  ~ProfScope() {
-    if (!g_prof.on || !r.a || !r.b) return;
-    (void)hipEventRecord(r.b, st);
-    g_prof.recs.push_back(r);
-  }
-};
 
 uint64_t threshold_of(double p) {
   double t = floor(p * 4294967296.0);
@@ -599,6 +564,7 @@ struct BandWorkspace {
   uint2 *S[2];      // [n][L/32][L/2] syndrome masks of column pairs
   uint32_t *alive, *wind;
   uint8_t *status;
+  int32_t *t_done;
   int32_t *active[2];
   int *count;  // [2]
   size_t bytes;
@@ -620,6 +586,7 @@ BandWorkspace band_layout(int L, int64_t n, void *base) {
   w.alive = (uint32_t *)take((size_t)n * 4);
   w.wind = (uint32_t *)take((size_t)n * 4);
   w.status = (uint8_t *)take((size_t)n);
+  w.t_done = (int32_t *)take((size_t)n * 4);
   for (int b = 0; b < 2; ++b) w.active[b] = (int32_t *)take((size_t)n * 4);
   w.count = (int *)take(2 * sizeof(int));
   w.bytes = off;
@@ -664,75 +631,109 @@ NoiseShape noise_shape(int L) {
   return g;
 }
 
-int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
-                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream,
-                uint8_t *d_counts = nullptr) {
-  BandWorkspace w = band_layout(L, n, ws);
-  const BandSchedule sched = schedule_for(L);
-  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive,
-                     w.wind, w.status, w.active[0]);
+// Noise, syndrome and bookkeeping of a band-path batch (before the passes).
+int band_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, const BandWorkspace &w,
+               uint8_t *d_counts, hipStream_t stream) {
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
+                     w.status, w.t_done, w.active[0]);
   HIP_TRY(hipGetLastError());
+  const NoiseShape g = noise_shape(L);
+  ProfScope ps("k_band_noise", stream);
+  hipLaunchKernelGGL(k_band_noise, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, stream, L, g.CP, g.S,
+                     d_seeds, thr, d_p, w.S[0], w.wind, d_counts);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+// One pass of up to k steps over the samples in `active` (state in buffers
+// cur, written to cur ^ 1), then T_dec bookkeeping and compaction of the
+// survivors into w.active[cur ^ 1].  `zero` clears the survivor counter
+// first (the first launch of a pass).
+int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *active, int nact, int cur, bool zero,
+              int32_t *d_T_dec, hipStream_t stream) {
+  BandArgs ba;
+  ba.L = L;
+  ba.write_state = 1;
+  ba.k = k;
+  ba.T_max = T_max;
+  ba.t_done = w.t_done;
+  ba.hx = 4 * k;
+  ba.tx = BAND_RX - 2 * ba.hx;
+  if (L == BAND_RY) {
+    ba.hy = 0;
+    ba.ty = L;
+  } else {  // row halo of 4k, rounded up to whole 16-row strips
+    ba.hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
+    ba.ty = BAND_RY - 2 * ba.hy;
+  }
+  ba.ntx = (L + ba.tx - 1) / ba.tx;
+  const int nty = (L + ba.ty - 1) / ba.ty;
+  ba.active = active;
+  ba.Esrc = w.E[cur];
+  ba.Ssrc = w.S[cur];
+  ba.Edst = w.E[cur ^ 1];
+  ba.Sdst = w.S[cur ^ 1];
+  ba.alive = w.alive;
+  ba.wind = w.wind;
+  ba.zero_count = zero ? &w.count[cur ^ 1] : nullptr;
   {
-    const NoiseShape g = noise_shape(L);
-    ProfScope ps("k_band_noise", stream);
-    hipLaunchKernelGGL(k_band_noise, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, stream, L, g.CP, g.S,
-                       d_seeds, thr, d_p, w.S[0], w.wind, d_counts);
+    ProfScope ps("k_band", stream);
+    hipLaunchKernelGGL(k_band, dim3((unsigned)(ba.ntx * nty), (unsigned)nact), dim3(BAND_NW * 64), band_lds(),
+                       stream, ba);
   }
   HIP_TRY(hipGetLastError());
-  const size_t lds = band_lds();
-  int t0 = 0, cur = 0, nact = (int)n;
-  bool first = true;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, active, nact,
+                     w.t_done, w.alive, d_T_dec, w.status, w.active[cur ^ 1], &w.count[cur ^ 1]);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+// First pass of a batch: groups of samples (device lists) with their own
+// depth.  Every later pass runs all survivors at the schedule's k_next.
+struct FirstPass {
+  int nb = 0;
+  const int32_t *list[8];
+  int count[8];
+  int k[8];
+};
+
+int band_passes(int L, int64_t n, int T_max, const BandWorkspace &w, const FirstPass &fp, int32_t *d_T_dec,
+                uint8_t *d_flags, uint32_t *d_syn, hipStream_t stream) {
+  const BandSchedule sched = schedule_for(L);
+  bool zero = true;
+  for (int b = 0; b < fp.nb; ++b) {
+    if (fp.count[b] == 0) continue;
+    const int rc = band_pass(L, min(fp.k[b], T_max), T_max, w, fp.list[b], fp.count[b], 0, zero, d_T_dec, stream);
+    if (rc != MPD_OK) return rc;
+    zero = false;
+  }
+  int cur = 1;
   for (;;) {
-    const int k = first ? min(sched.k_first, T_max) : min(sched.k_next, T_max - t0);
-    BandArgs ba;
-    ba.L = L;
-    ba.first = first ? 1 : 0;
-    ba.write_state = 1;
-    ba.k = k;
-    ba.t0 = t0;
-    ba.hx = 4 * k;
-    ba.tx = BAND_RX - 2 * ba.hx;
-    if (L == BAND_RY) {
-      ba.hy = 0;
-      ba.ty = L;
-    } else {  // row halo of 4k, rounded up to whole 16-row strips
-      ba.hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
-      ba.ty = BAND_RY - 2 * ba.hy;
-    }
-    ba.ntx = (L + ba.tx - 1) / ba.tx;
-    const int nty = (L + ba.ty - 1) / ba.ty;
-    ba.active = w.active[cur];
-    ba.Esrc = w.E[cur];
-    ba.Ssrc = w.S[cur];
-    ba.Edst = w.E[cur ^ 1];
-    ba.Sdst = w.S[cur ^ 1];
-    ba.alive = w.alive;
-    ba.wind = w.wind;
-    ba.zero_count = &w.count[cur ^ 1];
-    {
-      ProfScope ps("k_band", stream);
-      hipLaunchKernelGGL(k_band, dim3((unsigned)(ba.ntx * nty), (unsigned)nact), dim3(BAND_NW * 64), lds, stream,
-                         ba);
-    }
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, ba.first, k,
-                       t0, T_max, w.active[cur], nact, w.alive, d_T_dec, w.status, w.active[cur ^ 1],
-                       &w.count[cur ^ 1]);
-    HIP_TRY(hipGetLastError());
-    t0 += k;
-    cur ^= 1;
-    first = false;
-    if (t0 >= T_max) break;
     int h_count = 0;
     HIP_TRY(hipMemcpyAsync(&h_count, &w.count[cur], sizeof(int), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    nact = h_count;
-    if (nact == 0) break;
+    if (h_count == 0) break;
+    const int rc = band_pass(L, sched.k_next, T_max, w, w.active[cur], h_count, cur, true, d_T_dec, stream);
+    if (rc != MPD_OK) return rc;
+    cur ^= 1;
   }
   hipLaunchKernelGGL(k_band_export, dim3((unsigned)n), dim3(256), 0, stream, L, n, w.status, w.wind, w.S[cur],
                      d_flags, d_syn);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
+}
+
+int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
+                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+  BandWorkspace w = band_layout(L, n, ws);
+  int rc = band_start(L, thr, d_p, d_seeds, n, w, nullptr, stream);
+  if (rc != MPD_OK) return rc;
+  FirstPass fp;
+  fp.nb = 1;
+  fp.list[0] = w.active[0];
+  fp.count[0] = (int)n;
+  fp.k[0] = schedule_for(L).k_first;
+  return band_passes(L, n, T_max, w, fp, d_T_dec, d_flags, d_syn, stream);
 }
 
 // Library-owned side stream per device (default priority, non-blocking) with
@@ -768,6 +769,61 @@ int check_common(int L, int64_t n, int T_max, const void *T_dec, const void *fla
   return MPD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned scheduling: predicted decode time -> first-pass depth per group
+// ---------------------------------------------------------------------------
+
+constexpr int MAX_BINS = 8;
+struct BinEdges {
+  float v[MAX_BINS - 1];
+};
+
+// Sample i goes to bin b with edges[b-1] <= pred[i] < edges[b] (bin 0 below
+// the first edge, NaN included); lists [nb][n], counts [nb] zero on entry.
+__global__ void k_bin(const float *pred, int64_t n, int nb, BinEdges e, int32_t *lists, int *counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = pred[i];
+  int b = 0;
+  while (b < nb - 1 && v >= e.v[b]) ++b;
+  lists[(int64_t)b * n + atomicAdd(&counts[b], 1)] = (int32_t)i;
+}
+
+__global__ void k_zero_i32(int *p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+// Workspace of a learned-schedule decode: the band workspace followed by the
+// block counts, predictions, bin lists and the predictor's own workspace.
+struct LearnedLayout {
+  BandWorkspace band;
+  uint8_t *counts;
+  float *pred;
+  int32_t *lists;
+  int *bin_count;
+  void *cnn_ws;
+  size_t bytes;
+};
+LearnedLayout learned_layout(int L, int64_t n, void *base) {
+  LearnedLayout l;
+  l.band = band_layout(L, n, base);
+  size_t off = l.band.bytes;
+  auto take = [&](size_t bytes) {
+    void *p = base ? (void *)((char *)base + off) : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const int M = L / 8;
+  l.counts = (uint8_t *)take((size_t)n * M * M);
+  l.pred = (float *)take((size_t)n * 4);
+  l.lists = (int32_t *)take((size_t)MAX_BINS * n * 4);
+  l.bin_count = (int *)take(MAX_BINS * sizeof(int));
+  l.cnn_ws = take(cnn_forward_ws(M, n));
+  l.bytes = off;
+  return l;
+}
+
 }  // namespace mpd
 
 using namespace mpd;
@@ -793,7 +849,7 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
   int rc = check_common(L, n, T_max, d_T_dec, d_flags);
   if (rc) return rc;
   if (!resident_ok(L) && !tiled_ok(L))
-    return fail_with(MPD_ERR_L, "L=%d unsupported (3..128 with a strip height, or 256)", L);
+    return fail_with(MPD_ERR_L, "L=%d unsupported (3..128 with a strip height, or a multiple of 16 in [256, 16384])", L);
   if (n == 0) return MPD_OK;
   if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u)) return fail_with(MPD_ERR_PTR, "seeds NULL or misaligned");
   if (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u))
@@ -820,6 +876,77 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
   if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
   return decode_band(L, thr, nullptr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
+}
+
+int mpd_syndrome_counts(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, uint8_t *d_counts,
+                        void *stream) {
+  g_last_error.clear();
+  if (L < 16 || L > 16384 || L % 16) return fail_with(MPD_ERR_L, "L=%d: need a multiple of 16 in [16, 16384]", L);
+  if (d_p == nullptr && !(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n=%lld out of range", (long long)n);
+  if (n == 0) return MPD_OK;
+  if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u) || d_counts == nullptr || ((uintptr_t)d_p & 7u))
+    return fail_with(MPD_ERR_PTR, "seeds/counts NULL or misaligned");
+  const NoiseShape g = noise_shape(L);
+  hipLaunchKernelGGL(k_band_noise, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, (hipStream_t)stream, L,
+                     g.CP, g.S, d_seeds, threshold_of(d_p ? 0.0 : p), d_p, (uint2 *)nullptr, (uint32_t *)nullptr,
+                     d_counts);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+size_t mpd_learned_workspace_bytes(int L, int64_t n) {
+  if (n <= 0 || !tiled_ok(L)) return 0;
+  return learned_layout(L, n, nullptr).bytes;
+}
+
+int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const float *d_params,
+                       int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec, uint8_t *d_flags,
+                       uint32_t *d_final_syndrome, float *d_pred, void *d_workspace, size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
+  int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (!tiled_ok(L)) return fail_with(MPD_ERR_L, "L=%d: learned scheduling needs a multiple of 16 in [256, 16384]", L);
+  if (n_bins < 1 || n_bins > MAX_BINS) return fail_with(MPD_ERR_N, "n_bins=%d outside [1, %d]", n_bins, MAX_BINS);
+  if (h_depth == nullptr || (n_bins > 1 && h_edges == nullptr)) return fail_with(MPD_ERR_PTR, "NULL policy");
+  BinEdges e;
+  for (int b = 0; b < n_bins; ++b) {
+    if (h_depth[b] < 1 || 4 * h_depth[b] >= BAND_RX / 2)
+      return fail_with(MPD_ERR_TMAX, "bin depth %d outside [1, 15]", h_depth[b]);
+    if (b + 1 < n_bins) {
+      e.v[b] = h_edges[b];
+      if (!(e.v[b] == e.v[b]) || (b > 0 && e.v[b] < e.v[b - 1]))
+        return fail_with(MPD_ERR_P, "bin edges must be ascending numbers");
+    }
+  }
+  if (n == 0) return MPD_OK;
+  if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u) || d_params == nullptr || ((uintptr_t)d_params & 3u) ||
+      ((uintptr_t)d_pred & 3u) || ((uintptr_t)d_final_syndrome & 3u))
+    return fail_with(MPD_ERR_PTR, "seeds/params/pred/syndrome NULL or misaligned");
+  const LearnedLayout l = learned_layout(L, n, d_workspace);
+  if (d_workspace == nullptr || ws_bytes < l.bytes)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, l.bytes);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  rc = band_start(L, threshold_of(p), nullptr, d_seeds, n, l.band, l.counts, st);
+  if (rc != MPD_OK) return rc;
+  rc = cnn_forward_run(l.counts, L / 8, n, d_params, l.pred, nullptr, nullptr, nullptr, l.cnn_ws, st);
+  if (rc != MPD_OK) return rc;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, l.bin_count, MAX_BINS);
+  hipLaunchKernelGGL(k_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, l.pred, n, n_bins, e, l.lists,
+                     l.bin_count);
+  HIP_TRY(hipGetLastError());
+  if (d_pred != nullptr) HIP_TRY(hipMemcpyAsync(d_pred, l.pred, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+  FirstPass fp;
+  fp.nb = n_bins;
+  HIP_TRY(hipMemcpyAsync(fp.count, l.bin_count, n_bins * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int b = 0; b < n_bins; ++b) {
+    fp.list[b] = l.lists + (int64_t)b * n;
+    fp.k[b] = h_depth[b];
+  }
+  return band_passes(L, n, T_max, l.band, fp, d_T_dec, d_flags, d_final_syndrome, st);
 }
 
 int mpd_profile(int enable) {

@@ -1,0 +1,131 @@
+"""Learned scheduling on the GPU: training data from the decoder itself, training
+of the decode-time predictor with the library's kernels, and the choice of a
+binning policy by timing.
+
+Every step runs in libmpd's HIP kernels (noise, decoding, block counts,
+forward, loss gradient, Adam); this module only sequences the calls and
+moves a few scalars.  The predictor never changes what a decode returns.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import binding as b
+from .workloads import seeds as make_seeds
+
+TRAIN_CONFIG = 5            # seed stream of the training samples (evaluation uses others)
+P_RANGE = (0.005, 0.02)     # noise strengths of the training samples
+
+
+def make_dataset(n: int, L: int = 256, p_range=P_RANGE, config: int = TRAIN_CONFIG, p_index: int = 1,
+                 T_max: int = 4096, chunk: int = 16384, rng_seed: int = 5):
+    """(counts uint8 [n, L/8, L/8], target float32 [n] = ln(1 + T_dec), T_dec int32 [n],
+    p float64 [n]) on the device: p_i uniform in p_range, seeds from the
+    workload generator, T_dec measured by the decoder."""
+    dev = torch.device("cuda")
+    p = np.random.default_rng(rng_seed).uniform(p_range[0], p_range[1], n)
+    s = make_seeds(config, p_index, n)
+    counts = torch.empty((n, L // 8, L // 8), dtype=torch.uint8, device=dev)
+    T = torch.empty(n, dtype=torch.int32, device=dev)
+    for a in range(0, n, chunk):
+        e = min(n, a + chunk)
+        pt = torch.from_numpy(p[a:e]).to(dev)
+        st = torch.from_numpy(s[a:e].view(np.int64)).to(dev)
+        b.syndrome_counts(L, pt, st, out=counts[a:e])
+        Tc, _, _ = b.decode_mixed([(L, e - a)], pt, st, T_max, want_syndrome=False)
+        T[a:e] = Tc
+    target = torch.log1p(T.double()).float()
+    return counts, target, T, p
+
+
+def train(counts, target, epochs: int = 8, batch: int = 256, lr: float = 2e-3, seed: int = 1,
+          lr_final: float = 2e-4, log=None):
+    """Adam on the mean squared error of ln(1 + T_dec); cosine learning-rate
+    decay from lr to lr_final.  Returns (params, history of epoch losses)."""
+    n, M = counts.shape[0], counts.shape[-1]
+    dev = counts.device
+    params = b.cnn_init(seed)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    ws = b.train_workspace(M, batch, dev)
+    out = (torch.empty(1, dtype=torch.float32, device=dev), torch.empty(b.CNN_PARAMS, dtype=torch.float32, device=dev),
+           torch.empty(batch, dtype=torch.float32, device=dev))
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    steps_per_epoch = n // batch
+    total = epochs * steps_per_epoch
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(dev)
+        acc = torch.zeros(1, dtype=torch.float32, device=dev)
+        for i in range(steps_per_epoch):
+            idx = perm[i * batch:(i + 1) * batch]
+            c = counts.index_select(0, idx)
+            y = target.index_select(0, idx)
+            loss, grad, _ = b.cnn_loss_grad(c, params, y, workspace=ws, out=out)
+            acc += loss
+            step += 1
+            lr_t = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * step / total))
+            b.cnn_adam_step(params, grad, m, v, step, lr_t)
+        hist.append(float(acc.item()) / steps_per_epoch)
+        if log:
+            log(f"epoch {ep}: train mse {hist[-1]:.5f}")
+    return params, hist
+
+
+def predict(counts, params, chunk: int = 16384):
+    return torch.cat([b.cnn_forward(counts[a:a + chunk], params) for a in range(0, counts.shape[0], chunk)])
+
+
+def candidate_policies(pred: np.ndarray, k_first: int):
+    """Binning policies to try: one bin at the default depth (no use of the
+    prediction), and splits at prediction quantiles that give the samples
+    predicted shortest one step less and/or the longest one step more."""
+    qs = np.quantile(pred, [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
+    pol = [((), (k_first,))]
+    for a in qs:
+        pol.append(((float(a),), (k_first - 1, k_first)))
+        pol.append(((float(a),), (k_first, k_first + 1)))
+    for i, a in enumerate(qs):
+        for c in qs[i + 1:]:
+            pol.append(((float(a), float(c)), (k_first - 1, k_first, k_first + 1)))
+    return pol
+
+
+def time_policy(L, p, seeds_t, params, policy, T_max, reps: int = 3, ws=None, out=None):
+    """Median wall time (s) of decode_learned with this policy on a resident seed batch."""
+    edges, depths = policy
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.decode_learned(L, p, seeds_t, params, edges, depths, T_max, want_syndrome=False, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def tune_policy(L, p, seeds_t, params, T_max: int = 4096, k_first: int | None = None, reps: int = 3, log=None):
+    """Time every candidate policy on a tuning batch; returns (best policy,
+    its time, time of the single-bin policy, all timings)."""
+    n = seeds_t.numel()
+    if k_first is None:
+        k_first = b.get_band_schedule(L)[0]
+    dev = seeds_t.device
+    ws = b.learned_workspace(L, n, dev)
+    out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None,
+           torch.empty(n, dtype=torch.float32, device=dev))
+    b.decode_learned(L, p, seeds_t, params, (), (k_first,), T_max, want_syndrome=False, workspace=ws, out=out)
+    pred = out[3].cpu().numpy()
+    res = []
+    for pol in candidate_policies(pred, k_first):
+        t = time_policy(L, p, seeds_t, params, pol, T_max, reps, ws, out)
+        res.append((t, pol))
+        if log:
+            log(f"policy {pol}: {t * 1e3:.3f} ms")
+    best = min(res, key=lambda r: r[0])
+    return best[1], best[0], res[0][0], res

@@ -1,0 +1,196 @@
+"""GPU kernels of the decode-time predictor and the learned-schedule decode
+(through the C ABI) against the CPU oracles.
+
+Block counts, initial parameters and every decode result are compared
+exactly; the network's floating-point outputs within the tolerances below
+(float32 accumulation in a different order than the oracle's float64 sums,
+with bfloat16 rounding at the same points on both sides):
+  forward  |pred_gpu - pred_oracle| <= 1e-2 * max(1, |pred_oracle|)
+  gradient cosine >= 0.999 and relative L2 error <= 2e-2
+  Adam     parameters within 1e-6 relative (+ 1e-9 absolute)
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import cnn_oracle as co
+from paper_2506_03266_amd.workloads import seeds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03266_amd.binding as b
+    b.lib()
+    return b
+
+
+def realistic_counts(seed, n, M, lam=2.6):
+    """Block counts like an L = 8M lattice near p = 0.01 (Poisson, with a few dense blocks)."""
+    r = np.random.default_rng(seed)
+    c = r.poisson(lam, size=(n, M, M))
+    hot = r.random((n, M, M)) < 0.01
+    c[hot] += r.integers(4, 12, size=hot.sum())
+    return np.minimum(c, 64).astype(np.uint8)
+
+
+def trained_like_params(seed):
+    """Initial parameters plus a perturbation, with a head that mixes channels."""
+    p = co.init_params(seed, oracle.philox4x32_10).astype(np.float64)
+    r = np.random.default_rng(seed)
+    p += r.standard_normal(p.size) * 0.02
+    p[co.OFF_BL] = 1.5
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("L", [16, 64, 256, 272, 1024])
+def test_syndrome_counts(gpu, orc, L):
+    n = 6 if L < 1024 else 2
+    s = seeds(50, L, n)
+    p = 0.03
+    got = gpu.syndrome_counts(L, p, s).cpu().numpy()
+    for i in range(n):
+        ex, ey = orc.noise(L, p, int(s[i]))
+        want = co.block_counts(orc.syndrome_of(L, ex, ey), 8)
+        assert np.array_equal(got[i], want), (L, i)
+
+
+def test_syndrome_counts_per_sample_p(gpu, orc):
+    L, n = 256, 8
+    s = seeds(51, 0, n)
+    ps = np.linspace(0.0, 0.05, n)
+    got = gpu.syndrome_counts(L, ps, s).cpu().numpy()
+    for i in range(n):
+        ex, ey = orc.noise(L, ps[i], int(s[i]))
+        assert np.array_equal(got[i], co.block_counts(orc.syndrome_of(L, ex, ey), 8)), i
+    assert got[0].sum() == 0
+
+
+def test_init_matches_oracle(gpu):
+    for seed in (0, 12345, 2**40 + 7):
+        got = gpu.cnn_init(seed).cpu().numpy()
+        want = co.init_params(seed, oracle.philox4x32_10)
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), seed
+
+
+@pytest.mark.parametrize("M,n", [(32, 24), (8, 16), (5, 8), (2, 4), (64, 4), (34, 3), (128, 2)])
+def test_forward_matches_oracle(gpu, M, n):
+    """Whole-map kernel (M <= 32, incl. odd and tiny maps) and tiled kernel
+    (M = 64, ragged M = 34, M = 128 as for L = 1024)."""
+    counts = realistic_counts(M * 100 + n, n, M)
+    params = trained_like_params(M)
+    dev = torch.device("cuda")
+    pred, feat, amax = gpu.cnn_forward(torch.from_numpy(counts).to(dev), torch.from_numpy(params).to(dev),
+                                       want_feat=True)
+    ref = co.forward(counts, params, "bf16")
+    want = ref["pred"].detach().numpy()
+    got = pred.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= 1e-2 * np.maximum(1.0, np.abs(want))), (got, want)
+    wf = ref["feat"].detach().numpy()
+    gf = feat.cpu().numpy()
+    assert np.all(np.abs(gf - wf) <= 1e-2 * np.maximum(1.0, np.abs(wf)))
+    agree = (amax.cpu().numpy() == ref["argmax"]).mean()
+    assert agree >= 0.9, agree
+
+
+def test_forward_translation_invariance(gpu):
+    """Circular convolutions and a global maximum: shifting the map leaves the
+    predictions unchanged (exactly on the whole-map kernel up to summation
+    order, so within float32 rounding)."""
+    counts = realistic_counts(7, 4, 32)
+    params = torch.from_numpy(trained_like_params(3)).cuda()
+    base = gpu.cnn_forward(torch.from_numpy(counts).cuda(), params).cpu().numpy()
+    sh = np.roll(counts, (5, 11), axis=(1, 2))
+    got = gpu.cnn_forward(torch.from_numpy(np.ascontiguousarray(sh)).cuda(), params).cpu().numpy()
+    assert np.allclose(got, base, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("M,n", [(32, 16), (8, 32)])
+def test_gradient_matches_oracle(gpu, M, n):
+    counts = realistic_counts(M + 1, n, M)
+    params = trained_like_params(M + 2)
+    target = np.log1p(np.random.default_rng(M).integers(2, 8, size=n)).astype(np.float32)
+    dev = torch.device("cuda")
+    loss, grad, pred = gpu.cnn_loss_grad(torch.from_numpy(counts).to(dev), torch.from_numpy(params).to(dev),
+                                         torch.from_numpy(target).to(dev))
+    wl, wg, ref = co.loss_and_grad(counts, params, target, "bf16")
+    g = grad.cpu().numpy().astype(np.float64)
+    cos = g @ wg / (np.linalg.norm(g) * np.linalg.norm(wg))
+    rel = np.linalg.norm(g - wg) / np.linalg.norm(wg)
+    assert cos >= 0.999 and rel <= 2e-2, (cos, rel)
+    assert float(loss.item()) == pytest.approx(wl, rel=1e-2)
+    # every layer's block individually
+    for lo, hi in ((co.OFF_W1, co.OFF_W2), (co.OFF_W2, co.OFF_W3), (co.OFF_W3, co.OFF_W4), (co.OFF_W4, co.OFF_WL),
+                   (co.OFF_WL, co.CNN_PARAMS)):
+        a, w = g[lo:hi], wg[lo:hi]
+        if np.linalg.norm(w) > 0:
+            assert np.linalg.norm(a - w) / np.linalg.norm(w) <= 5e-2, (lo, hi)
+
+
+def test_adam_matches_oracle(gpu):
+    r = np.random.default_rng(3)
+    p0 = r.standard_normal(co.CNN_PARAMS).astype(np.float32)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(p0.copy()).to(dev)
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    pr, mr, vr = p0.astype(np.float64), np.zeros(co.CNN_PARAMS), np.zeros(co.CNN_PARAMS)
+    for t in range(1, 4):
+        g = (r.standard_normal(co.CNN_PARAMS) * 10.0 ** r.integers(-6, 1, co.CNN_PARAMS)).astype(np.float32)
+        gpu.cnn_adam_step(P, torch.from_numpy(g).to(dev), m, v, t, 1e-3)
+        pr, mr, vr = co.adam_step(pr, g, mr, vr, t, 1e-3)
+    got = P.cpu().numpy().astype(np.float64)
+    assert np.allclose(got, pr, rtol=1e-6, atol=1e-9)
+
+
+def test_training_lowers_loss(gpu):
+    """A few hundred Adam steps on decoder-labelled L = 256 samples lower the
+    training loss well below that of the initial network."""
+    from paper_2506_03266_amd import learned
+    counts, target, T, _ = learned.make_dataset(8192, p_range=(0.005, 0.02), p_index=9)
+    params, hist = learned.train(counts, target, epochs=4, batch=256)
+    assert hist[-1] < 0.5 * hist[0], hist
+    assert np.isfinite(params.cpu().numpy()).all()
+
+
+POLICIES = [((), (4,)), ((), (1,)), ((1.4,), (3, 4)), ((1.0, 1.6), (2, 5, 6)), ((-1e9, 1e9), (3, 6, 1)),
+            ((0.0,), (7, 2))]
+
+
+@pytest.mark.parametrize("policy", POLICIES)
+def test_learned_decode_equals_plain(gpu, orc, policy):
+    """Any binning policy returns exactly the plain decode's results (and the
+    oracle's), at L = 256."""
+    L, p, n = 256, 0.02, 192
+    s = seeds(52, 0, n)
+    params = torch.from_numpy(trained_like_params(9)).cuda()
+    T0, F0, S0 = gpu.decode_batch(L, p, s, 4096)
+    edges, depths = policy
+    T1, F1, S1, pred = gpu.decode_learned(L, p, s, params, edges, depths, 4096)
+    assert np.array_equal(T0.cpu().numpy(), T1.cpu().numpy())
+    assert np.array_equal(F0.cpu().numpy(), F1.cpu().numpy())
+    assert np.array_equal(S0.cpu().numpy(), S1.cpu().numpy())
+    pick = np.arange(0, n, 23)
+    ref = orc.decode_seeds(L, p, s[pick], 4096, threads=8)
+    assert np.array_equal(T1.cpu().numpy()[pick], ref["T_dec"])
+    assert np.array_equal(F1.cpu().numpy()[pick], ref["flags"])
+    assert np.isfinite(pred.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("L,p,n,T_max", [(256, 0.07, 8, 5), (256, 0.06, 8, 0), (512, 0.02, 4, 64),
+                                         (1024, 0.01, 2, 64)])
+def test_learned_decode_budgets_and_sizes(gpu, orc, L, p, n, T_max):
+    """Bins deeper than T_max, timeouts, and tiled lattices (L = 512, 1024:
+    the predictor's tiled kernel), against the oracle."""
+    s = seeds(53, L + T_max, n)
+    params = torch.from_numpy(trained_like_params(10)).cuda()
+    med = float(np.median(gpu.cnn_forward(gpu.syndrome_counts(L, p, s), params).cpu().numpy()))
+    T, F, S, pred = gpu.decode_learned(L, p, s, params, (med,), (2, 6), T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    assert np.array_equal(T.cpu().numpy(), ref["T_dec"])
+    assert np.array_equal(F.cpu().numpy(), ref["flags"])
+    assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"])
