@@ -9,6 +9,12 @@ winding and classification, final syndrome export.  Each step uses a fresh
 batch of seeds (same distribution); the seeds are already in HBM when the
 timed region starts.
 
+The headline value is plain (FIFO) batching.  The learned-scheduling leg
+trains the decode-time predictor on the GPU (200000 decoder-labelled L = 256
+samples, p ~ U[0.005, 0.02]), picks its binning policy by timing on a
+separate batch, then times the same K batches with inference and binning
+inside the timed region, and checks that the results are identical.
+
 Prints one JSON line on stdout.
 """
 import argparse
@@ -48,8 +54,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1024)
-    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4"], default="c3",
-                    help="c3 (default) is the headline line; c1/c2/c4 print a line for that configuration")
+    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn"], default="c3",
+                    help="c3 (default) is the headline line; c1/c2/c4/c5 print a line for that configuration, "
+                         "cnn times the predictor's kernels")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduling leg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -104,6 +112,8 @@ def main():
     b.profile(False)
     tile_ms, tile_launches = b.profile_read("k_band")
 
+    learned_leg = None if args.no_learned else learned_scheduling(b, batches, outs, W, K, n, elapsed, torch, np)
+
     T_all = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
     F_all = torch.cat([outs[i][1] for i in range(W, W + K)]).cpu().numpy()
     site_updates = float(L * L * T_all.sum())
@@ -152,8 +162,49 @@ def main():
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE,
                      "launches": tile_launches, "avg_launch_ms": avg_launch_s * 1e3},
         "cpu_baseline": cpu,
+        "learned_sched": learned_leg,
     }
     print(json.dumps(line), flush=True)
+
+
+def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, L_eval=L):
+    """Train, tune and time the learned-scheduling decode on the benchmark's batches."""
+    from paper_2506_03266_amd import learned
+    from paper_2506_03266_amd.workloads import seeds
+    from scipy.stats import spearmanr
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    counts, target, _, _ = learned.make_dataset(200000)
+    params, hist = learned.train(counts, target, epochs=6)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    tune = torch.from_numpy(seeds(3, 201, n).view(np.int64)).to(dev)
+    policy, t_best, t_single, _ = learned.tune_policy(L_eval, P, tune, params, reps=2)
+    lws = b.learned_workspace(L_eval, n)
+    louts = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+              torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev),
+              torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
+    for i in range(W):
+        b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lws, out=louts[i])
+    b.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(W, W + K):
+        b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lws, out=louts[i])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    b.profile(False)
+    cnn_ms, cnn_n = b.profile_read("k_cnn_forward")
+    same = all(torch.equal(outs[i][j], louts[i][j]) for i in range(W, W + K) for j in range(3))
+    T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy()
+    pred = torch.cat([louts[i][3] for i in range(W, W + K)]).cpu().numpy()
+    y = np.log1p(T)
+    return {"samples_per_s": K * n / el, "ms_per_step": el / K * 1e3, "ratio_vs_fifo": fifo_elapsed / el,
+            "identical_results": bool(same), "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])},
+            "cnn_forward_ms_per_step": cnn_ms / max(cnn_n, 1), "train_s": t_train,
+            "train_mse_last_epoch": hist[-1], "eval_mae_ln": float(np.abs(pred - y).mean()),
+            "eval_spearman": float(spearmanr(pred, T).correlation),
+            "tuning_ms": {"best": t_best * 1e3, "single_bin": t_single * 1e3}}
 
 
 def other_workload(args, b, seeds, torch, np):
@@ -180,6 +231,10 @@ def other_workload(args, b, seeds, torch, np):
                           "site_updates_per_s": K * su / dt, "ms_per_batch": dt / K * 1e3,
                           "samples": int(len(Ls))}))
         return
+    if args.workload == "c5":
+        return learned_c5(args, b, seeds, torch, np)
+    if args.workload == "cnn":
+        return cnn_kernels(args, b, seeds, torch, np)
     cfg = CONFIGS[1 if args.workload == "c1" else 2]
     L, n = cfg["L"], cfg["n"]
     for k, p in enumerate(cfg["p"]):
@@ -199,6 +254,80 @@ def other_workload(args, b, seeds, torch, np):
         print(json.dumps({"workload": f"config {args.workload[1]}: L={L} p={p} {n} samples",
                           "samples_per_s": K * n / dt, "site_updates_per_s_last_batch_est": L * L * T.sum() * K / dt,
                           "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean())}))
+
+
+
+def learned_c5(args, b, seeds, torch, np):
+    """Configuration 5: plain vs learned scheduling at L = 256 (4096 samples)
+    and L = 1024 (1024 samples), p = 0.01, with one predictor trained at L = 256."""
+    from paper_2506_03266_amd import learned
+    dev = torch.device("cuda")
+    K, W = args.steps, args.warmup
+    counts, target, _, _ = learned.make_dataset(200000)
+    params, _ = learned.train(counts, target, epochs=6)
+    for Lc, n, pidx in ((256, 4096, 0), (1024, 1024, 1)):
+        batches = [torch.from_numpy(seeds(5, 100 + pidx, n, start=i * n).view(np.int64)).to(dev)
+                   for i in range(W + K)]
+        tune = torch.from_numpy(seeds(5, 200 + pidx, n).view(np.int64)).to(dev)
+        policy, _, _, _ = learned.tune_policy(Lc, P, tune, params, reps=2)
+        ws = b.alloc_workspace(Lc, n)
+        lws = b.learned_workspace(Lc, n)
+        res = {}
+        for name, fn in (("fifo", lambda s: b.decode_batch(Lc, P, s, T_MAX, want_syndrome=False, workspace=ws)),
+                         ("learned", lambda s: b.decode_learned(Lc, P, s, params, policy[0], policy[1], T_MAX,
+                                                                want_syndrome=False, workspace=lws))):
+            for i in range(W):
+                fn(batches[i])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = [fn(batches[i])[:2] for i in range(W, W + K)]
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0, o)
+        same = all(torch.equal(x, y) for a, c in zip(res["fifo"][1], res["learned"][1]) for x, y in zip(a, c))
+        print(json.dumps({"workload": f"config 5: L={Lc} p={P} {n} samples, plain vs learned scheduling",
+                          "fifo_samples_per_s": K * n / res["fifo"][0],
+                          "learned_samples_per_s": K * n / res["learned"][0],
+                          "ratio": res["fifo"][0] / res["learned"][0], "identical_results": same,
+                          "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])}}), flush=True)
+
+
+def cnn_kernels(args, b, seeds, torch, np):
+    """Forward pass of the decode-time predictor on one decode batch of block-count
+    maps (4096 at L = 256, 1024 at L = 1024) and training steps of 256 maps."""
+    dev = torch.device("cuda")
+    K, W = args.steps, args.warmup
+    prm = b.cnn_init(1)
+    for Lc, n in ((256, 4096), (1024, 1024)):
+        c = b.syndrome_counts(Lc, P, torch.from_numpy(seeds(3, 300, n).view(np.int64)).to(dev))
+        for _ in range(W):
+            b.cnn_forward(c, prm)
+        torch.cuda.synchronize()
+        b.profile(True)
+        for _ in range(K):
+            b.cnn_forward(c, prm)
+        torch.cuda.synchronize()
+        b.profile(False)
+        ms, k = b.profile_read("k_cnn_forward")
+        flop = 14112.0 * (Lc // 8) ** 2 * n
+        print(json.dumps({"kernel": "k_cnn_forward", "L": Lc, "maps": n, "ms": ms / k,
+                          "TFLOP_per_s": flop / (ms / k) / 1e9, "bf16_dense_peak_frac": flop / (ms / k) / 1e9 / 2500}),
+              flush=True)
+    c = b.syndrome_counts(256, P, torch.from_numpy(seeds(3, 301, 256).view(np.int64)).to(dev))
+    y = torch.full((256,), 1.6, device=dev)
+    ws = b.train_workspace(32, 256)
+    for _ in range(W):
+        b.cnn_loss_grad(c, prm, y, workspace=ws)
+    torch.cuda.synchronize()
+    b.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        b.cnn_loss_grad(c, prm, y, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    b.profile(False)
+    print(json.dumps({"kernel": "training step (256 maps)", "ms": dt * 1e3,
+                      "forward_ms": b.profile_read("k_cnn_forward")[0] / K,
+                      "backward_ms": b.profile_read("k_cnn_backward")[0] / K}), flush=True)
 
 
 if __name__ == "__main__":

@@ -576,12 +576,24 @@ __global__ __launch_bounds__(BWD_THREADS) void k_cnn_backward(BwdArgs a) {
   if (tid == 0) out[OFF_BL] = dpred;
 }
 
-// grad[j] = sum over samples (in order) of part[s][j]; loss = mean squared error
-__global__ void k_cnn_reduce(const float *part, int64_t n, float *grad) {
+// grad[j] = sum over samples of part[s][j] in a fixed order: chunks of
+// RED_CHUNK samples in order (k_cnn_reduce_chunks, one thread per (chunk,
+// j)), then the chunk sums in order (k_cnn_reduce).
+constexpr int RED_CHUNK = 16;
+__global__ void k_cnn_reduce_chunks(const float *part, int64_t n, float *chunks) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (j >= NPARAM) return;
+  const int64_t s1 = min(n, (c + 1) * RED_CHUNK);
+  float acc = 0.f;
+  for (int64_t s = c * RED_CHUNK; s < s1; ++s) acc += part[s * NPARAM + j];
+  chunks[c * NPARAM + j] = acc;
+}
+__global__ void k_cnn_reduce(const float *chunks, int64_t nchunks, float *grad) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= NPARAM) return;
   float acc = 0.f;
-  for (int64_t s = 0; s < n; ++s) acc += part[s * NPARAM + j];
+  for (int64_t c = 0; c < nchunks; ++c) acc += chunks[c * NPARAM + j];
   grad[j] = acc;
 }
 
@@ -650,7 +662,7 @@ size_t tile_lds(int threads) {
 // per-sample gradients.
 struct BwdLayout {
   uint16_t *store;
-  float *feat, *pred, *part;
+  float *feat, *pred, *part, *chunks;
   int32_t *argmax;
   void *fwd_ws;
   size_t bytes;
@@ -668,6 +680,7 @@ BwdLayout bwd_layout(int M, int64_t n, void *base) {
   l.argmax = (int32_t *)take((size_t)n * CH * 4);
   l.pred = (float *)take((size_t)n * 4);
   l.part = (float *)take((size_t)n * NPARAM * 4);
+  l.chunks = (float *)take((size_t)((n + RED_CHUNK - 1) / RED_CHUNK) * NPARAM * 4);
   l.fwd_ws = take(cnn_forward_ws(M, n));
   l.bytes = off;
   return l;
@@ -799,7 +812,11 @@ int mpd_cnn_loss_grad(const uint8_t *d_counts, int M, int64_t n, const float *d_
     hipLaunchKernelGGL(k_cnn_backward, dim3((unsigned)n), dim3(BWD_THREADS), 0, st, b);
   }
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_cnn_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, l.part, n, d_grad);
+  const int64_t nch = (n + RED_CHUNK - 1) / RED_CHUNK;
+  hipLaunchKernelGGL(k_cnn_reduce_chunks, dim3((NPARAM + 255) / 256, (unsigned)nch), dim3(256), 0, st, l.part, n,
+                     l.chunks);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_cnn_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, l.chunks, nch, d_grad);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_cnn_loss, dim3(1), dim3(256), 0, st, l.pred, d_target, n, d_loss);
   HIP_TRY(hipGetLastError());

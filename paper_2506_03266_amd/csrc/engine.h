@@ -46,8 +46,10 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t k0, uint32
   uint32_t c2 = 0u, c3 = 0u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    // one 32x32 -> 64-bit product each (v_mad_u64_u32) instead of separate lo/hi multiplies
+    const uint64_t m0 = (uint64_t)0xD2511F53u * c0, m1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)m0, hi0 = (uint32_t)(m0 >> 32);
+    const uint32_t lo1 = (uint32_t)m1, hi1 = (uint32_t)(m1 >> 32);
     const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);  // 3-way XOR
     const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
     c0 = n0;

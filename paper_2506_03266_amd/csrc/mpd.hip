@@ -782,11 +782,24 @@ struct BinEdges {
 // the first edge, NaN included); lists [nb][n], counts [nb] zero on entry.
 __global__ void k_bin(const float *pred, int64_t n, int nb, BinEdges e, int32_t *lists, int *counts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float v = pred[i];
-  int b = 0;
-  while (b < nb - 1 && v >= e.v[b]) ++b;
-  lists[(int64_t)b * n + atomicAdd(&counts[b], 1)] = (int32_t)i;
+  const bool in = i < n;
+  int b = -1;
+  if (in) {
+    const float v = pred[i];
+    b = 0;
+    while (b < nb - 1 && v >= e.v[b]) ++b;
+  }
+  // one atomic per wave and bin: the wave's members of bin c take consecutive slots
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < nb; ++c) {
+    const uint64_t m = __ballot(b == c);
+    if (m == 0) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[c], __popcll(m));
+    base = __shfl(base, leader);
+    if (b == c) lists[(int64_t)c * n + base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+  }
 }
 
 __global__ void k_zero_i32(int *p, int count) {

@@ -194,3 +194,48 @@ def test_learned_decode_budgets_and_sizes(gpu, orc, L, p, n, T_max):
     assert np.array_equal(T.cpu().numpy(), ref["T_dec"])
     assert np.array_equal(F.cpu().numpy(), ref["flags"])
     assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"])
+
+
+def test_learned_vs_fifo_L256(gpu, capsys):
+    """What the trained network gains (or loses) over plain FIFO batching at
+    L = 256, p = 0.01 (4096 samples per batch), end to end (noise, inference,
+    binning, decoding).  Trains on 200000 decoder-labelled samples with
+    p ~ U[0.005, 0.02], picks the binning policy by timing on a tuning batch,
+    then times both on fresh batches.  Results must be identical; the measured
+    ratio is reported, and the network must beat the best constant predictor
+    of the training labels on the evaluation samples."""
+    import time
+    from paper_2506_03266_amd import learned
+    counts, target, _, _ = learned.make_dataset(200000)
+    params, hist = learned.train(counts, target, epochs=6)
+    L, p, n = 256, 0.01, 4096
+    tune = torch.from_numpy(seeds(3, 201, n).view(np.int64)).cuda()
+    policy, _, _, _ = learned.tune_policy(L, p, tune, params, reps=2)
+    batches = [torch.from_numpy(seeds(3, 210 + i, n).view(np.int64)).cuda() for i in range(6)]
+    ws = gpu.alloc_workspace(L, n)
+    lws = gpu.learned_workspace(L, n)
+
+    def run(fn):
+        fn(batches[0])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        outs = [fn(s) for s in batches[1:]]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / (len(batches) - 1), outs
+
+    t_fifo, o_fifo = run(lambda s: gpu.decode_batch(L, p, s, 4096, workspace=ws))
+    t_lrn, o_lrn = run(lambda s: gpu.decode_learned(L, p, s, params, policy[0], policy[1], 4096, workspace=lws))
+    for a, c in zip(o_fifo, o_lrn):
+        for x, y in zip(a[:3], c[:3]):
+            assert torch.equal(x, y)
+    T = torch.cat([o[0] for o in o_fifo]).double()
+    y = torch.log1p(T)
+    pred = torch.cat([o[3] for o in o_lrn]).double()
+    mse_net = float(((pred - y) ** 2).mean())
+    mse_const = float(((float(target.double().mean()) - y) ** 2).mean())
+    with capsys.disabled():
+        print(f"\nlearned vs FIFO at L=256 p=0.01: fifo {n / t_fifo:.4g} samples/s, learned {n / t_lrn:.4g} "
+              f"samples/s (ratio {t_fifo / t_lrn:.3f}), policy {policy}, mse net {mse_net:.4f} "
+              f"vs training-mean constant {mse_const:.4f}")
+    assert mse_net < mse_const
+    assert t_lrn < 1.5 * t_fifo
