@@ -37,12 +37,17 @@
  * Ownership and execution
  *   - Every pointer named d_* is caller-owned device memory on the current
  *     HIP device; the library never allocates, frees or keeps it.  Host
- *     memory is never read or written except the scalar arguments.
+ *     memory is never read or written except the scalar arguments.  The
+ *     library keeps, per device, a few streams and events of its own, and per
+ *     host thread a small pinned host block for the pass counters (created
+ *     on first use, kept until the process ends).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default
  *     stream).  Outputs are valid once the stream has reached the point after
  *     the call.  Calls that share a workspace must be ordered on one stream.
- *   - The large-lattice path reads a small per-block counter back to the host
- *     between decoder passes, so those calls synchronize `stream`.
+ *   - The large-lattice (band) path reads a survivor counter back to the host
+ *     between decoder passes, so those calls synchronize `stream` (they cannot
+ *     be captured into a HIP graph).  Lattices up to L = 128 decode in a
+ *     single launch with no host synchronization and can be captured.
  *   - Return value 0 on success, a negative MPD_ERR_* code otherwise; the
  *     message of the last failing call on this host thread is returned by
  *     mpd_last_error().  On an error nothing has been enqueued unless the
@@ -150,12 +155,14 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
  *   d_T_dec, d_flags          [n] as in mpd_decode_batch
  *   d_final_syndrome          concatenation over classes of
  *                             [h_count[c]][ceil(L_c^2/32)] words; may be NULL
- *   d_workspace               >= mpd_mixed_workspace_bytes(...)
+ *   d_workspace               >= mpd_mixed_workspace_bytes(...), 256-byte
+ *                             aligned (the sum of the band classes' parts)
  * Classes up to L = 128 run as one launch each on a library-owned side
  * stream forked from `stream` (one workgroup per sample, early exit per
- * sample); larger classes run the band path on `stream`; the call returns
- * after both have been joined into `stream` (the band path synchronizes
- * `stream`).  Every p in [0, 1]; errors as mpd_decode_batch. */
+ * sample); larger classes run the band path, each on a library-owned stream
+ * with its own part of the workspace, their passes in lockstep (one host wait
+ * per round of passes); the call returns after all of them have been joined
+ * into `stream`.  Every p in [0, 1]; errors as mpd_decode_batch. */
 size_t mpd_mixed_workspace_bytes(int n_classes, const int32_t *h_L, const int64_t *h_count);
 int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, const double *d_p,
                      const uint64_t *d_seeds, int T_max, int32_t *d_T_dec, uint8_t *d_flags,

@@ -697,50 +697,119 @@ struct FirstPass {
   int k[8];
 };
 
-int band_passes(int L, int64_t n, int T_max, const BandWorkspace &w, const FirstPass &fp, int32_t *d_T_dec,
-                uint8_t *d_flags, uint32_t *d_syn, hipStream_t stream) {
-  const BandSchedule sched = schedule_for(L);
-  bool zero = true;
-  for (int b = 0; b < fp.nb; ++b) {
-    if (fp.count[b] == 0) continue;
-    const int rc = band_pass(L, min(fp.k[b], T_max), T_max, w, fp.list[b], fp.count[b], 0, zero, d_T_dec, stream);
-    if (rc != MPD_OK) return rc;
-    zero = false;
-  }
+// One batch on the band path: workspace, stream, outputs and first pass.
+struct BandRun {
+  int L = 0;
+  int64_t n = 0;
+  int T_max = 0;
+  BandWorkspace w;
+  FirstPass fp;
+  int32_t *T_dec = nullptr;
+  uint8_t *flags = nullptr;
+  uint32_t *syn = nullptr;
+  hipStream_t stream = nullptr;
   int cur = 1;
-  for (;;) {
-    int h_count = 0;
-    HIP_TRY(hipMemcpyAsync(&h_count, &w.count[cur], sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    if (h_count == 0) break;
-    const int rc = band_pass(L, sched.k_next, T_max, w, w.active[cur], h_count, cur, true, d_T_dec, stream);
-    if (rc != MPD_OK) return rc;
-    cur ^= 1;
+  bool done = false;
+};
+
+// Pinned host words for the survivor counts, one block per host thread,
+// allocated on first use and kept for the life of the process.
+int *pinned_counts(int need) {
+  thread_local int *buf = nullptr;
+  thread_local int cap = 0;
+  if (need > cap) {
+    int *p = nullptr;
+    const int c = std::max(need, 16);
+    if (hipHostMalloc((void **)&p, c * sizeof(int), hipHostMallocDefault) != hipSuccess) return nullptr;
+    buf = p;  // an older, smaller block stays allocated (a few bytes)
+    cap = c;
   }
-  hipLaunchKernelGGL(k_band_export, dim3((unsigned)n), dim3(256), 0, stream, L, n, w.status, w.wind, w.S[cur],
-                     d_flags, d_syn);
-  HIP_TRY(hipGetLastError());
+  return buf;
+}
+
+// Runs the passes of several band-path batches in lockstep: the first passes
+// of every batch, then rounds of one survivor-count readback per batch (one
+// host wait per round) and one pass for each batch with survivors.  Batches
+// on different streams overlap on the device.
+int band_passes(BandRun *runs, int nr) {
+  for (int i = 0; i < nr; ++i) {
+    BandRun &r = runs[i];
+    bool zero = true;
+    for (int b = 0; b < r.fp.nb; ++b) {
+      if (r.fp.count[b] == 0) continue;
+      const int rc = band_pass(r.L, min(r.fp.k[b], r.T_max), r.T_max, r.w, r.fp.list[b], r.fp.count[b], 0, zero,
+                               r.T_dec, r.stream);
+      if (rc != MPD_OK) return rc;
+      zero = false;
+    }
+    r.cur = 1;
+    r.done = false;
+  }
+  int *hc = pinned_counts(nr);
+  if (hc == nullptr) return fail_with(MPD_ERR_HIP, "could not allocate pinned host memory for the pass counters");
+  for (;;) {
+    bool any = false;
+    for (int i = 0; i < nr; ++i)
+      if (!runs[i].done)
+        HIP_TRY(hipMemcpyAsync(&hc[i], &runs[i].w.count[runs[i].cur], sizeof(int), hipMemcpyDeviceToHost,
+                               runs[i].stream));
+    for (int i = 0; i < nr; ++i)
+      if (!runs[i].done) HIP_TRY(hipStreamSynchronize(runs[i].stream));
+    for (int i = 0; i < nr; ++i) {
+      BandRun &r = runs[i];
+      if (r.done) continue;
+      if (hc[i] == 0) {
+        hipLaunchKernelGGL(k_band_export, dim3((unsigned)r.n), dim3(256), 0, r.stream, r.L, r.n, r.w.status, r.w.wind,
+                           r.w.S[r.cur], r.flags, r.syn);
+        HIP_TRY(hipGetLastError());
+        r.done = true;
+        continue;
+      }
+      const int rc = band_pass(r.L, schedule_for(r.L).k_next, r.T_max, r.w, r.w.active[r.cur], hc[i], r.cur, true,
+                               r.T_dec, r.stream);
+      if (rc != MPD_OK) return rc;
+      r.cur ^= 1;
+      any = true;
+    }
+    if (!any) break;
+  }
   return MPD_OK;
+}
+
+// Noise and first-pass setup of a plain (single-group) band batch.
+int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
+               int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+  r.L = L;
+  r.n = n;
+  r.T_max = T_max;
+  r.w = band_layout(L, n, ws);
+  r.T_dec = d_T_dec;
+  r.flags = d_flags;
+  r.syn = d_syn;
+  r.stream = stream;
+  r.fp.nb = 1;
+  r.fp.list[0] = r.w.active[0];
+  r.fp.count[0] = (int)n;
+  r.fp.k[0] = schedule_for(L).k_first;
+  return band_start(L, thr, d_p, d_seeds, n, r.w, nullptr, stream);
 }
 
 int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
                 int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
-  BandWorkspace w = band_layout(L, n, ws);
-  int rc = band_start(L, thr, d_p, d_seeds, n, w, nullptr, stream);
+  BandRun r;
+  const int rc = band_setup(r, L, thr, d_p, d_seeds, n, T_max, d_T_dec, d_flags, d_syn, ws, stream);
   if (rc != MPD_OK) return rc;
-  FirstPass fp;
-  fp.nb = 1;
-  fp.list[0] = w.active[0];
-  fp.count[0] = (int)n;
-  fp.k[0] = schedule_for(L).k_first;
-  return band_passes(L, n, T_max, w, fp, d_T_dec, d_flags, d_syn, stream);
+  return band_passes(&r, 1);
 }
 
 // Library-owned side stream per device (default priority, non-blocking) with
 // fork/join events, created on first use and kept for the process.
+constexpr int BAND_STREAMS = 4;
 struct SideStream {
   hipStream_t stream = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t band[BAND_STREAMS] = {};   // band-path classes of a mixed batch
+  hipEvent_t band_join[BAND_STREAMS] = {};
 };
 std::mutex g_side_mu;
 std::map<int, SideStream> g_side;
@@ -755,6 +824,10 @@ SideStream *side_stream() {
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
   if (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
   if (hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess) return nullptr;
+  for (int i = 0; i < BAND_STREAMS; ++i) {
+    if (hipStreamCreateWithFlags(&s.band[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&s.band_join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
+  }
   return &(g_side[dev] = s);
 }
 
@@ -951,15 +1024,26 @@ int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int 
                      l.bin_count);
   HIP_TRY(hipGetLastError());
   if (d_pred != nullptr) HIP_TRY(hipMemcpyAsync(d_pred, l.pred, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
-  FirstPass fp;
-  fp.nb = n_bins;
-  HIP_TRY(hipMemcpyAsync(fp.count, l.bin_count, n_bins * sizeof(int), hipMemcpyDeviceToHost, st));
+  BandRun r;
+  r.L = L;
+  r.n = n;
+  r.T_max = T_max;
+  r.w = l.band;
+  r.T_dec = d_T_dec;
+  r.flags = d_flags;
+  r.syn = d_final_syndrome;
+  r.stream = st;
+  r.fp.nb = n_bins;
+  int *hc = pinned_counts(n_bins);
+  if (hc == nullptr) return fail_with(MPD_ERR_HIP, "could not allocate pinned host memory for the bin counters");
+  HIP_TRY(hipMemcpyAsync(hc, l.bin_count, n_bins * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int b = 0; b < n_bins; ++b) {
-    fp.list[b] = l.lists + (int64_t)b * n;
-    fp.k[b] = h_depth[b];
+    r.fp.count[b] = hc[b];
+    r.fp.list[b] = l.lists + (int64_t)b * n;
+    r.fp.k[b] = h_depth[b];
   }
-  return band_passes(L, n, T_max, l.band, fp, d_T_dec, d_flags, d_final_syndrome, st);
+  return band_passes(&r, 1);
 }
 
 int mpd_profile(int enable) {
@@ -1082,8 +1166,8 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
 size_t mpd_mixed_workspace_bytes(int n_classes, const int32_t *h_L, const int64_t *h_count) {
   size_t need = 0;
   if (n_classes <= 0 || h_L == nullptr || h_count == nullptr) return 0;
-  for (int c = 0; c < n_classes; ++c)
-    if (!resident_ok(h_L[c]) && tiled_ok(h_L[c])) need = std::max(need, mpd_workspace_bytes(h_L[c], h_count[c]));
+  for (int c = 0; c < n_classes; ++c)  // band classes run concurrently, each with its own part
+    if (!resident_ok(h_L[c]) && tiled_ok(h_L[c])) need += align256(mpd_workspace_bytes(h_L[c], h_count[c]));
   return need;
 }
 
@@ -1107,6 +1191,7 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
   const size_t need = mpd_mixed_workspace_bytes(n_classes, h_L, h_count);
   if (need > 0 && (ws_bytes < need || d_workspace == nullptr))
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  if (need > 0 && ((uintptr_t)d_workspace & 255u)) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   SideStream *side = side_stream();
   if (side == nullptr) return fail_with(MPD_ERR_HIP, "could not create the side stream");
@@ -1136,19 +1221,35 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
     syn_off += cnt * (((int64_t)L * L + 31) / 32);
   }
   HIP_TRY(hipEventRecord(side->join, side->stream));
-  // band classes on the caller's stream
+  // band classes: each on a stream of the pool with its own workspace part,
+  // passes in lockstep
+  std::vector<BandRun> runs;
   off = 0;
   syn_off = 0;
+  size_t ws_off = 0;
   for (int c = 0; c < n_classes; ++c) {
     const int L = h_L[c];
     const int64_t cnt = h_count[c];
     if (cnt > 0 && !resident_ok(L)) {
-      rc = decode_band(L, 0, d_p + off, d_seeds + off, cnt, T_max, d_T_dec + off, d_flags + off,
-                       d_final_syndrome ? d_final_syndrome + syn_off : nullptr, d_workspace, st);
+      const int si = (int)(runs.size() % BAND_STREAMS);
+      HIP_TRY(hipStreamWaitEvent(side->band[si], side->fork, 0));
+      runs.emplace_back();
+      rc = band_setup(runs.back(), L, 0, d_p + off, d_seeds + off, cnt, T_max, d_T_dec + off, d_flags + off,
+                      d_final_syndrome ? d_final_syndrome + syn_off : nullptr, (char *)d_workspace + ws_off,
+                      side->band[si]);
       if (rc) return rc;
+      ws_off += align256(mpd_workspace_bytes(L, cnt));
     }
     off += cnt;
     syn_off += cnt * (((int64_t)L * L + 31) / 32);
+  }
+  if (!runs.empty()) {
+    rc = band_passes(runs.data(), (int)runs.size());
+    if (rc) return rc;
+    for (int i = 0; i < std::min((int)runs.size(), BAND_STREAMS); ++i) {
+      HIP_TRY(hipEventRecord(side->band_join[i], side->band[i]));
+      HIP_TRY(hipStreamWaitEvent(st, side->band_join[i], 0));
+    }
   }
   HIP_TRY(hipStreamWaitEvent(st, side->join, 0));
   return MPD_OK;

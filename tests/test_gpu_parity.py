@@ -249,3 +249,25 @@ def test_autotune_keeps_results(gpu):
     T1, F1, _ = gpu.decode_batch(256, 0.01, s, 4096)
     assert np.array_equal(_np(T0), _np(T1)) and np.array_equal(_np(F0), _np(F1))
     gpu.set_band_schedule(4, 2)  # restore the defaults for the other tests
+
+
+def test_mixed_many_band_classes(gpu, orc):
+    """Six band-path classes (more than the library's stream pool, repeated
+    sizes) plus resident classes in one mixed call, every sample against the
+    oracle: passes of different classes run interleaved on several streams."""
+    classes = [(256, 3), (64, 5), (272, 2), (256, 2), (512, 1), (320, 2), (32, 4), (256, 1)]
+    n = sum(c for _, c in classes)
+    r = np.random.default_rng(11)
+    ps = r.uniform(0.005, 0.05, n)
+    ss = seeds(49, 0, n)
+    T, F, S = gpu.decode_mixed(classes, ps, ss, 256)
+    T, F, S = _np(T), _np(F), _np(S).view(np.uint32)
+    off = woff = 0
+    for L, c in classes:
+        ref = orc.decode_seeds(L, ps[off:off + c], ss[off:off + c], 256, threads=8)
+        W = (L * L + 31) // 32
+        assert np.array_equal(T[off:off + c], ref["T_dec"]), L
+        assert np.array_equal(F[off:off + c], ref["flags"]), L
+        assert np.array_equal(S[woff:woff + c * W].reshape(c, W), ref["sigma_words"]), L
+        off += c
+        woff += c * W
