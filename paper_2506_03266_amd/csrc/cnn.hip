@@ -41,6 +41,11 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <type_traits>
+
 #include "engine.h"
 #include "host.h"
 #include "mpd.h"
@@ -112,6 +117,13 @@ __global__ void k_cnn_prep(const float *__restrict__ params, uint4 *__restrict__
   Aop[t] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// p / R: a constant division when R is a compile-time constant, else an
+// exact float reciprocal (p < 2^20).
+__device__ __forceinline__ int row_of(int p, int R) {
+  if (__builtin_constant_p(R)) return p / R;
+  return (int)(((float)p + 0.5f) * (1.f / (float)R));
+}
+
 // Running maximum with the lowest index on ties.
 __device__ __forceinline__ void keep_max(float v, int i, float &best, int &bi) {
   if (v > best || (v == best && i < bi)) {
@@ -125,21 +137,49 @@ struct Pool {
   int idx[4];
 };
 
+// Layer geometry: input row stride, output side, output row stride and
+// offset.  RtGeom holds them at run time; CtGeom makes them compile-time
+// constants (tap offsets then fold into the LDS instructions).
+struct RtGeom {
+  int S_in, R_out, S_out, out_off;
+};
+template <int SI, int RO, int SO, int OO>
+struct CtGeom {
+  static constexpr int S_in = SI, R_out = RO, S_out = SO, out_off = OO;
+};
+
+// A operands of one layer for this lane (layer 1 uses block 0 only).  A
+// workgroup keeps the current layer's in registers and loads the next
+// layer's while it computes (the loads complete during the layer).
+struct LayerA {
+  bf16x8 A[5];
+};
+__device__ __forceinline__ void load_layer(const uint4 *__restrict__ Aop, int layer, LayerA &W) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int jj = 0; jj < 5; ++jj)
+    W.A[jj] = (layer > 0 || jj == 0) ? __builtin_bit_cast(bf16x8, Aop[layer * 320 + jj * 64 + lane]) : W.A[0];
+}
+__device__ __forceinline__ void load_biases(const float *__restrict__ P, float *bias_s) {
+  if (threadIdx.x < 4 * CH) {
+    const int l = threadIdx.x / CH, c = threadIdx.x % CH;
+    bias_s[threadIdx.x] = P[(l == 0 ? OFF_B1 : l == 1 ? OFF_B2 : l == 2 ? OFF_B3 : OFF_B4) + c];
+  }
+}
+
 // One 3x3 layer.  The input buffer has row stride S_in and holds, for
 // output position (y, x) (0 <= y, x < R_out), the 3x3 window at rows
 // y..y+2 and columns x..x+2 (a border or halo of one position on each
 // side).  CIN1: single-channel input [..]; otherwise [..][16].  Outputs go
 // to out[(y + o) S_out + x + o][16] (o = out_off); LAST folds them into the
 // pooling state instead, with global position ((oy + y) mod M, (ox + x) mod M).
-template <bool CIN1, bool LAST>
-__device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out, int S_in,
-                                           int R_out, int S_out, int out_off, const uint4 *__restrict__ Aop,
-                                           const float *__restrict__ b, int M, int oy, int ox, Pool &pool) {
+template <bool CIN1, bool LAST, class G>
+__device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out, const G &geo,
+                                           const bf16x8 *A, const float *__restrict__ b, int M, int oy, int ox,
+                                           Pool &pool) {
+  const int S_in = geo.S_in, R_out = geo.R_out, S_out = geo.S_out, out_off = geo.out_off;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int g = lane >> 4, li = lane & 15;
-  bf16x8 A[5];
-#pragma unroll
-  for (int jj = 0; jj < (CIN1 ? 1 : 5); ++jj) A[jj] = __builtin_bit_cast(bf16x8, Aop[jj * 64 + lane]);
   float bias[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) bias[r] = b[4 * g + r];
@@ -152,14 +192,11 @@ __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint
     toff[jj] = (tap / 3) * S_in + tap % 3;
   }
   const int npos = R_out * R_out, ngroups = (npos + 15) >> 4;
-  const float inv = 1.f / (float)R_out;
-  for (int grp = wave; grp < ngroups; grp += nwaves) {
-    int p = (grp << 4) + li;
-    const bool valid = p < npos;
-    p = valid ? p : npos - 1;  // spare lanes repeat the last position, not stored
-    const int y = (int)(((float)p + 0.5f) * inv);
-    const int x = p - y * R_out;
-    const int base = y * S_in + x;
+  // Accumulators of one 16-position group (the lane's K slices of its input
+  // window times the weights).
+  auto group_acc = [&](int p) {
+    const int y = row_of(p, R_out);
+    const int base = y * S_in + (p - y * R_out);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     if (CIN1) {
       u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -179,7 +216,11 @@ __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint
       for (int jj = 0; jj < 5; ++jj)
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[jj], __builtin_bit_cast(bf16x8, v[jj]), acc, 0, 0, 0);
     }
-    // lane holds channels 4g..4g+3 of position p
+    return acc;
+  };
+  // Bias, ReLU, then store (or pool) the lane's 4 channels of position p.
+  auto finish = [&](const f32x4 &acc, int p, bool valid) {
+    const int y = row_of(p, R_out), x = p - y * R_out;
     float v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) v[r] = relu(acc[r] + bias[r]);
@@ -192,6 +233,13 @@ __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint
 #pragma unroll
       for (int r = 0; r < 4; ++r) keep_max(v[r], gi, pool.best[r], pool.idx[r]);
     }
+  };
+  // Spare lanes (past the last position) repeat the last position and store nothing.
+  for (int grp = wave; grp < ngroups; grp += nwaves) {
+    int p1 = (grp << 4) + li;
+    const bool v1 = p1 < npos;
+    p1 = v1 ? p1 : npos - 1;
+    finish(group_acc(p1), p1, v1);
   }
 }
 
@@ -289,58 +337,83 @@ __device__ __forceinline__ void pool_init(Pool &pool) {
 }
 
 // Whole map per workgroup (M <= 32), buffers with a wrapped border of one
-// position.  LDS: x [(M+2)^2] | A, B [(M+2)^2][16] | pooling.
-__global__ __launch_bounds__(THREADS_WRAP) void k_cnn_forward_wrap(FwdArgs a) {
+// position.  LDS: x [(M+2)^2] | A, B [(M+2)^2][16] | pooling.  MC > 0: the
+// map side as a compile-time constant (L = 256 maps), 0: at run time.
+template <int MC>
+__global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4))) void k_cnn_forward_wrap(
+    FwdArgs a) {  // 4 waves per SIMD: two workgroups per CU, as the LDS allows
   extern __shared__ __align__(16) unsigned char smem[];
-  const int M = a.M, S = M + 2, SS = S * S;
+  const int M = MC > 0 ? MC : a.M, S = M + 2, SS = S * S;
+  using Geo = typename std::conditional<(MC > 0), CtGeom<MC + 2, MC, MC + 2, 1>, RtGeom>::type;
+  using GeoL = typename std::conditional<(MC > 0), CtGeom<MC + 2, MC, 0, 0>, RtGeom>::type;
+  Geo geo;
+  GeoL geol;
+  if constexpr (MC == 0) {
+    geo = RtGeom{S, M, S, 1};
+    geol = RtGeom{S, M, 0, 0};
+  }
   uint16_t *xin = reinterpret_cast<uint16_t *>(smem);
   uint16_t *bufA = xin + ((SS + 7) & ~7);
   uint16_t *bufB = bufA + SS * CH;
   float *red_v = reinterpret_cast<float *>(bufB + SS * CH);
   int *red_i = reinterpret_cast<int *>(red_v + (blockDim.x >> 6) * CH);
   __shared__ float feat_s[CH];
-  const int64_t s = blockIdx.x;
-  const uint8_t *cnt = a.counts + s * M * M;
-  for (int i = threadIdx.x; i < SS; i += blockDim.x) {
-    const int r = i / S, q = i - r * S;
-    const int y = r == 0 ? M - 1 : (r == M + 1 ? 0 : r - 1), x = q == 0 ? M - 1 : (q == M + 1 ? 0 : q - 1);
-    xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
-  }
-  __syncthreads();
+  __shared__ float bias_s[4 * CH];
   const float *P = a.params;
-  Pool pool;
-  pool_init(pool);
+  load_biases(P, bias_s);
+  LayerA Wc, Wn;  // current and next layer's operands
+  load_layer(a.Aop, 0, Wc);
   const size_t act = (size_t)M * M * CH;
-  conv_layer<true, false>(xin, bufA, S, M, S, 1, a.Aop, P + OFF_B1, M, 0, 0, pool);
-  __syncthreads();
-  fill_border(bufA, M);
-  if (a.store) store_interior(bufA, a.store + (size_t)s * act, M);
-  __syncthreads();
-  conv_layer<false, false>(bufA, bufB, S, M, S, 1, a.Aop + 320, P + OFF_B2, M, 0, 0, pool);
-  __syncthreads();
-  fill_border(bufB, M);
-  if (a.store) store_interior(bufB, a.store + ((size_t)a.n + s) * act, M);
-  __syncthreads();
-  conv_layer<false, false>(bufB, bufA, S, M, S, 1, a.Aop + 640, P + OFF_B3, M, 0, 0, pool);
-  __syncthreads();
-  fill_border(bufA, M);
-  if (a.store) store_interior(bufA, a.store + ((size_t)2 * a.n + s) * act, M);
-  __syncthreads();
-  conv_layer<false, true>(bufA, nullptr, S, M, 0, 0, a.Aop + 960, P + OFF_B4, M, 0, 0, pool);
-  float best;
-  int bi;
-  pool_reduce(pool, red_v, red_i, best, bi);
-  if (threadIdx.x < CH) {
-    feat_s[threadIdx.x] = best;
-    if (a.feat) a.feat[s * CH + threadIdx.x] = best;
-    if (a.argmax) a.argmax[s * CH + threadIdx.x] = bi;
+  // a fixed grid walks the samples
+  for (int64_t s = blockIdx.x; s < a.n; s += gridDim.x) {
+    const uint8_t *cnt = a.counts + s * M * M;
+    for (int i = threadIdx.x; i < SS; i += blockDim.x) {
+      const int r = i / S, q = i - r * S;
+      const int y = r == 0 ? M - 1 : (r == M + 1 ? 0 : r - 1), x = q == 0 ? M - 1 : (q == M + 1 ? 0 : q - 1);
+      xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
+    }
+    __syncthreads();
+    Pool pool;
+    pool_init(pool);
+    load_layer(a.Aop, 1, Wn);
+    conv_layer<true, false>(xin, bufA, geo, Wc.A, bias_s, M, 0, 0, pool);
+    Wc = Wn;
+    load_layer(a.Aop, 2, Wn);
+    __syncthreads();
+    fill_border(bufA, M);
+    if (a.store) store_interior(bufA, a.store + (size_t)s * act, M);
+    __syncthreads();
+    conv_layer<false, false>(bufA, bufB, geo, Wc.A, bias_s + CH, M, 0, 0, pool);
+    Wc = Wn;
+    load_layer(a.Aop, 3, Wn);
+    __syncthreads();
+    fill_border(bufB, M);
+    if (a.store) store_interior(bufB, a.store + ((size_t)a.n + s) * act, M);
+    __syncthreads();
+    conv_layer<false, false>(bufB, bufA, geo, Wc.A, bias_s + 2 * CH, M, 0, 0, pool);
+    Wc = Wn;
+    load_layer(a.Aop, 0, Wn);
+    __syncthreads();
+    fill_border(bufA, M);
+    if (a.store) store_interior(bufA, a.store + ((size_t)2 * a.n + s) * act, M);
+    __syncthreads();
+    conv_layer<false, true>(bufA, nullptr, geol, Wc.A, bias_s + 3 * CH, M, 0, 0, pool);
+    Wc = Wn;
+    float best;
+    int bi;
+    pool_reduce(pool, red_v, red_i, best, bi);
+    if (threadIdx.x < CH) {
+      feat_s[threadIdx.x] = best;
+      if (a.feat) a.feat[s * CH + threadIdx.x] = best;
+      if (a.argmax) a.argmax[s * CH + threadIdx.x] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.pred[s] = head(P, feat_s);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) a.pred[s] = head(P, feat_s);
 }
 
-// One 32 x 32 output tile per workgroup; each layer shrinks the region by
-// one position per side.  LDS: x [40^2] | A [38^2][16] | B [36^2][16] | pooling.
+// 32 x 32 output tiles; each layer shrinks the region by one position per
+// side.  LDS: x [40^2] | A [38^2][16] | B [36^2][16] | pooling.
 __global__ __launch_bounds__(THREADS_TILE) void k_cnn_forward_tile(FwdArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4, R3 = TILE + 2;
@@ -350,34 +423,49 @@ __global__ __launch_bounds__(THREADS_TILE) void k_cnn_forward_tile(FwdArgs a) {
   uint16_t *bufB = bufA + R1 * R1 * CH;
   float *red_v = reinterpret_cast<float *>(bufB + R2 * R2 * CH);
   int *red_i = reinterpret_cast<int *>(red_v + (blockDim.x >> 6) * CH);
+  __shared__ float bias_s[4 * CH];
+  load_biases(a.params, bias_s);
+  LayerA Wc, Wn;  // current and next layer's operands
+  load_layer(a.Aop, 0, Wc);
   const int nt = a.ntile;
-  const int64_t s = blockIdx.x / (nt * nt);
-  const int t = (int)(blockIdx.x % (nt * nt));
-  const int ty0 = (t / nt) * TILE, tx0 = (t % nt) * TILE;
-  const uint8_t *cnt = a.counts + s * M * M;
-  for (int i = threadIdx.x; i < R0 * R0; i += blockDim.x) {
-    const int y = (ty0 - 4 + i / R0 + M) % M, x = (tx0 - 4 + i % R0 + M) % M;
-    xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
-  }
-  __syncthreads();
-  const float *P = a.params;
-  Pool pool;
-  pool_init(pool);
-  conv_layer<true, false>(xin, bufA, R0, R1, R1, 0, a.Aop, P + OFF_B1, M, 0, 0, pool);
-  __syncthreads();
-  conv_layer<false, false>(bufA, bufB, R1, R2, R2, 0, a.Aop + 320, P + OFF_B2, M, 0, 0, pool);
-  __syncthreads();
-  conv_layer<false, false>(bufB, bufA, R2, R3, R3, 0, a.Aop + 640, P + OFF_B3, M, 0, 0, pool);
-  __syncthreads();
-  conv_layer<false, true>(bufA, nullptr, R3, TILE, 0, 0, a.Aop + 960, P + OFF_B4, M, ty0, tx0, pool);
-  float best;
-  int bi;
-  pool_reduce(pool, red_v, red_i, best, bi);
-  if (threadIdx.x < CH && bi >= 0) {
-    // non-negative floats order as their bit patterns; ties keep the lowest index
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)bi);
-    atomicMax(&a.pool[s * CH + threadIdx.x], key);
+  // a fixed grid walks the (sample, tile) items: weights stay in registers
+  for (int64_t it = blockIdx.x; it < a.n * nt * nt; it += gridDim.x) {
+    const int64_t s = it / (nt * nt);
+    const int t = (int)(it % (nt * nt));
+    const int ty0 = (t / nt) * TILE, tx0 = (t % nt) * TILE;
+    const uint8_t *cnt = a.counts + s * M * M;
+    for (int i = threadIdx.x; i < R0 * R0; i += blockDim.x) {
+      const int y = (ty0 - 4 + i / R0 + M) % M, x = (tx0 - 4 + i % R0 + M) % M;
+      xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
+    }
+    __syncthreads();
+    Pool pool;
+    pool_init(pool);
+    load_layer(a.Aop, 1, Wn);
+    conv_layer<true, false>(xin, bufA, CtGeom<R0, R1, R1, 0>{}, Wc.A, bias_s, M, 0, 0, pool);
+    Wc = Wn;
+    load_layer(a.Aop, 2, Wn);
+    __syncthreads();
+    conv_layer<false, false>(bufA, bufB, CtGeom<R1, R2, R2, 0>{}, Wc.A, bias_s + CH, M, 0, 0, pool);
+    Wc = Wn;
+    load_layer(a.Aop, 3, Wn);
+    __syncthreads();
+    conv_layer<false, false>(bufB, bufA, CtGeom<R2, R3, R3, 0>{}, Wc.A, bias_s + 2 * CH, M, 0, 0, pool);
+    Wc = Wn;
+    load_layer(a.Aop, 0, Wn);
+    __syncthreads();
+    conv_layer<false, true>(bufA, nullptr, CtGeom<R3, TILE, 0, 0>{}, Wc.A, bias_s + 3 * CH, M, ty0, tx0, pool);
+    Wc = Wn;
+    float best;
+    int bi;
+    pool_reduce(pool, red_v, red_i, best, bi);
+    if (threadIdx.x < CH && bi >= 0) {
+      // non-negative floats order as their bit patterns; ties keep the lowest index
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)bi);
+      atomicMax(&a.pool[s * CH + threadIdx.x], key);
+    }
+    __syncthreads();  // LDS reused by the next item
   }
 }
 
@@ -695,6 +783,20 @@ int check_map(int M, int64_t n) {
 }  // namespace
 
 // Forward workspace: packed weights, then (maps wider than 32) the pooled maxima.
+// Compute units of the current device (cached per device).
+int cu_count() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  return cache[dev] = cus;
+}
+
 size_t cnn_forward_ws(int M, int64_t n) {
   return align256(AOP_UINT4 * sizeof(uint4)) + (M <= WRAP_MAX ? 0 : align256((size_t)n * CH * sizeof(unsigned long long)));
 }
@@ -719,8 +821,12 @@ int cnn_forward_run(const uint8_t *counts, int M, int64_t n, const float *params
   HIP_TRY(hipGetLastError());
   ProfScope ps("k_cnn_forward", stream);
   if (M <= WRAP_MAX) {
-    hipLaunchKernelGGL(k_cnn_forward_wrap, dim3((unsigned)n), dim3(THREADS_WRAP), wrap_lds(M, THREADS_WRAP), stream,
-                       a);
+    // two workgroups per CU fit in LDS; each walks its share of the maps
+    const unsigned grid = (unsigned)std::min<int64_t>(n, 2 * (int64_t)cu_count());
+    if (M == 32)
+      hipLaunchKernelGGL(k_cnn_forward_wrap<32>, dim3(grid), dim3(THREADS_WRAP), wrap_lds(M, THREADS_WRAP), stream, a);
+    else
+      hipLaunchKernelGGL(k_cnn_forward_wrap<0>, dim3(grid), dim3(THREADS_WRAP), wrap_lds(M, THREADS_WRAP), stream, a);
     HIP_TRY(hipGetLastError());
     return MPD_OK;
   }
@@ -729,8 +835,8 @@ int cnn_forward_run(const uint8_t *counts, int M, int64_t n, const float *params
   const int64_t cnt = n * CH;
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.pool, cnt);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_cnn_forward_tile, dim3((unsigned)(n * a.ntile * a.ntile)), dim3(THREADS_TILE),
-                     tile_lds(THREADS_TILE), stream, a);
+  const unsigned tgrid = (unsigned)std::min<int64_t>(n * a.ntile * a.ntile, cu_count());
+  hipLaunchKernelGGL(k_cnn_forward_tile, dim3(tgrid), dim3(THREADS_TILE), tile_lds(THREADS_TILE), stream, a);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_cnn_head, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   HIP_TRY(hipGetLastError());
