@@ -783,20 +783,6 @@ int check_map(int M, int64_t n) {
 }  // namespace
 
 // Forward workspace: packed weights, then (maps wider than 32) the pooled maxima.
-// Compute units of the current device (cached per device).
-int cu_count() {
-  static std::mutex mu;
-  static std::map<int, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(dev);
-  if (it != cache.end()) return it->second;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-  return cache[dev] = cus;
-}
-
 size_t cnn_forward_ws(int M, int64_t n) {
   return align256(AOP_UINT4 * sizeof(uint4)) + (M <= WRAP_MAX ? 0 : align256((size_t)n * CH * sizeof(unsigned long long)));
 }

@@ -191,9 +191,10 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
 // ---------------------------------------------------------------------------
 
 constexpr int BAND_H = 16;                 // rows per wave
-constexpr int BAND_NW = 16;                // waves per workgroup
+constexpr int BAND_NW = 16;                // waves per workgroup (full-size regions)
+constexpr int BAND_NW_SMALL = 4;           // waves per workgroup for passes that underfill the GPU
 constexpr int BAND_RX = 128;               // region columns (2 per lane)
-constexpr int BAND_RY = BAND_NW * BAND_H;  // region rows
+constexpr int BAND_RY = BAND_NW * BAND_H;  // region rows (full-size regions)
 constexpr int TILE_H = BAND_H;             // rows per syndrome word pair in HBM
 
 struct BandArgs {
@@ -215,13 +216,15 @@ struct BandArgs {
   int *zero_count;  // counter to clear for the following compaction, or nullptr
 };
 
-// With ty == L the region spans the full height (L == BAND_RY, rows wrap);
-// otherwise regions overlap by hy rows (a multiple of 16) above and below.
-__global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
+// A region has NW * 16 rows.  With ty == L it spans the full height
+// (L == NW * 16, rows wrap); otherwise regions overlap by hy rows (a
+// multiple of 16) above and below.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint4 *BND = reinterpret_cast<uint4 *>(smem);                        // [2][NW*2*64]
-  uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * BAND_NW * 2 * 64);  // [NW*64]
-  uint32_t *red = reinterpret_cast<uint32_t *>(MB + BAND_NW * 64);
+  uint4 *BND = reinterpret_cast<uint4 *>(smem);                   // [2][NW*2*64]
+  uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * NW * 2 * 64);  // [NW*64]
+  uint32_t *red = reinterpret_cast<uint32_t *>(MB + NW * 64);
   constexpr int H = BAND_H;
   constexpr uint32_t F = full_mask<H>();
   const int L = a.L;
@@ -235,8 +238,8 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
 
   const bool wrapY = a.ty == L;
   const int tix = blockIdx.x % a.ntx, tiy = blockIdx.x / a.ntx;
-  const int wdn = w == 0 ? (wrapY ? BAND_NW - 1 : 0) : w - 1;
-  const int wup = w == BAND_NW - 1 ? (wrapY ? 0 : BAND_NW - 1) : w + 1;
+  const int wdn = w == 0 ? (wrapY ? NW - 1 : 0) : w - 1;
+  const int wup = w == NW - 1 ? (wrapY ? 0 : NW - 1) : w + 1;
   // global column of this lane's first column, global row of the wave's first row
   const int tx0 = tix * a.tx, ty0 = tiy * a.ty;
   int gx = tx0 - a.hx + 2 * lane;
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(BAND_NW * 64) void k_band(BandArgs a) {
 
   const uint32_t own_mask = own_col ? own_rows : 0u;
   uint32_t bits = __syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u) ? 1u : 0u;
-  uint4 *BND0 = BND, *BND1 = BND + BAND_NW * 2 * 64;
+  uint4 *BND0 = BND, *BND1 = BND + NW * 2 * 64;
   for (int st = 0; st < ks; ++st) {
     const uint32_t t3 = (uint32_t)(3 * (t0 + st));
     const uint32_t rows = wave_rows<H>(b.s0, b.s1);
@@ -485,6 +488,19 @@ int fail_with(int code, const char *fmt, ...) {
 
 Profiler g_prof;
 
+int cu_count() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  return cache[dev] = cus;
+}
+
 uint64_t threshold_of(double p) {
   double t = floor(p * 4294967296.0);
   if (t < 0.0) t = 0.0;
@@ -514,8 +530,8 @@ size_t resident_lds(int L, int H) {
   return (size_t)L * L * sizeof(uint2) + (size_t)L * (L / H) * sizeof(uint4) + 64;
 }
 
-size_t band_lds() {
-  return (size_t)2 * BAND_NW * 2 * 64 * sizeof(uint4) + (size_t)BAND_NW * 64 * sizeof(uint2) + 64;
+size_t band_lds(int nw) {
+  return (size_t)2 * nw * 2 * 64 * sizeof(uint4) + (size_t)nw * 64 * sizeof(uint2) + 64;
 }
 
 template <int H>
@@ -659,14 +675,23 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   ba.t_done = w.t_done;
   ba.hx = 4 * k;
   ba.tx = BAND_RX - 2 * ba.hx;
-  if (L == BAND_RY) {
+  ba.ntx = (L + ba.tx - 1) / ba.tx;
+  const int hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;  // row halo of 4k in whole 16-row strips
+  // Full-size regions (16 waves, 256 rows) unless their grid would leave
+  // compute units idle: then 4-wave regions of 64 rows, which need more
+  // (overlapping) tiles but take about a quarter of the time per step.
+  const int ty16 = L == BAND_RY ? L : BAND_RY - 2 * hy;
+  const int64_t wg16 = (int64_t)ba.ntx * ((L + ty16 - 1) / ty16) * nact;
+  const int ry4 = BAND_NW_SMALL * BAND_H;
+  const bool small = wg16 < cu_count() && ry4 - 2 * hy >= TILE_H;
+  const int ry = small ? ry4 : BAND_RY;
+  if (L == ry) {
     ba.hy = 0;
     ba.ty = L;
-  } else {  // row halo of 4k, rounded up to whole 16-row strips
-    ba.hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
-    ba.ty = BAND_RY - 2 * ba.hy;
+  } else {
+    ba.hy = hy;
+    ba.ty = ry - 2 * hy;
   }
-  ba.ntx = (L + ba.tx - 1) / ba.tx;
   const int nty = (L + ba.ty - 1) / ba.ty;
   ba.active = active;
   ba.Esrc = w.E[cur];
@@ -678,8 +703,12 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   ba.zero_count = zero ? &w.count[cur ^ 1] : nullptr;
   {
     ProfScope ps("k_band", stream);
-    hipLaunchKernelGGL(k_band, dim3((unsigned)(ba.ntx * nty), (unsigned)nact), dim3(BAND_NW * 64), band_lds(),
-                       stream, ba);
+    if (small)
+      hipLaunchKernelGGL(k_band<BAND_NW_SMALL>, dim3((unsigned)(ba.ntx * nty), (unsigned)nact),
+                         dim3(BAND_NW_SMALL * 64), band_lds(BAND_NW_SMALL), stream, ba);
+    else
+      hipLaunchKernelGGL(k_band<BAND_NW>, dim3((unsigned)(ba.ntx * nty), (unsigned)nact), dim3(BAND_NW * 64),
+                         band_lds(BAND_NW), stream, ba);
   }
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, active, nact,

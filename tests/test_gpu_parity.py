@@ -271,3 +271,13 @@ def test_mixed_many_band_classes(gpu, orc):
         assert np.array_equal(S[woff:woff + c * W].reshape(c, W), ref["sigma_words"]), L
         off += c
         woff += c * W
+
+
+@pytest.mark.parametrize("L,p,n,T_max", [(512, 0.02, 24, 64), (256, 0.03, 100, 64)])
+def test_band_full_and_small_regions(gpu, orc, L, p, n, T_max):
+    """Enough samples that the first passes use 16-wave (256-row) regions and
+    the last ones, with few survivors, 4-wave (64-row) regions."""
+    s = seeds(54, L, n)
+    T, F, S = gpu.decode_batch(L, p, s, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    compare(f"L={L} p={p} n={n}", T, F, S, ref)
