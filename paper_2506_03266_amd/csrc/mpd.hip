@@ -224,7 +224,8 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint4 *BND = reinterpret_cast<uint4 *>(smem);                   // [2][NW*2*64]
   uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * NW * 2 * 64);  // [NW*64]
-  uint32_t *red = reinterpret_cast<uint32_t *>(MB + NW * 64);
+  uint32_t *red = reinterpret_cast<uint32_t *>(MB + NW * 64);      // [16]
+  uint32_t *AW = red + 16;  // [16] per step of the pass: nonzero if anyons are left after it
   constexpr int H = BAND_H;
   constexpr uint32_t F = full_mask<H>();
   const int L = a.L;
@@ -234,6 +235,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
   const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
   const int ks = min(a.k, a.T_max - t0);  // steps of this sample in this pass
+  if (threadIdx.x < 16) AW[threadIdx.x] = 0u;
   if (threadIdx.x == 0) red[0] = 0u;
 
   const bool wrapY = a.ty == L;
@@ -303,7 +305,10 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
     band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);
     if (last_col) wind ^= (__popc(xo[1] & own_rows) & 1u) << 2;
     if (own_col && top) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
-    if (__syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u)) bits |= 2u << st;
+    // anyons left after this step: waves OR into the step's flag, read after
+    // the pass (no barrier of its own)
+    const bool left = __ballot(((b.s0 | b.s1) & own_mask) != 0u) != 0ull;
+    if (lane == 0 && left) atomicOr(&AW[st], 1u);
   }
 
   if (own && a.write_state) {
@@ -317,6 +322,8 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   }
   if (wind) atomicXor(&red[0], wind);
   __syncthreads();
+  if (threadIdx.x == 0)
+    for (int st = 0; st < ks; ++st) bits |= AW[st] ? 2u << st : 0u;
   if (threadIdx.x == 0) {
     if (bits) atomicOr(&a.alive[sample], bits);
     if (red[0]) atomicXor(&a.wind[sample], red[0]);
@@ -531,7 +538,7 @@ size_t resident_lds(int L, int H) {
 }
 
 size_t band_lds(int nw) {
-  return (size_t)2 * nw * 2 * 64 * sizeof(uint4) + (size_t)nw * 64 * sizeof(uint2) + 64;
+  return (size_t)2 * nw * 2 * 64 * sizeof(uint4) + (size_t)nw * 64 * sizeof(uint2) + 64 + 64;
 }
 
 template <int H>
