@@ -79,14 +79,16 @@ __device__ __forceinline__ uint32_t wave_rows(uint32_t s0, uint32_t s1) {
 }
 
 // Anyon sites publish "emits now": their registers read as the sub-step time.
-// Branch-free per row; the caller skips it for waves without anyons.
+// Only rows flagged in `rows` (wave-uniform: rows holding an anyon in some
+// lane) are touched -- after the first decoder step most rows hold none.
 template <int H>
-__device__ __forceinline__ void band_fold(BandLane<H> &b, uint32_t ss) {
+__device__ __forceinline__ void band_fold(BandLane<H> &b, uint32_t ss, uint32_t rows) {
   // The masks do not change between the sub-steps of a step; keep the
   // compiler from hoisting 2*H lane masks out of the sub-step loop.
   asm volatile("" : "+v"(b.s0), "+v"(b.s1));
 #pragma unroll
   for (int h = 0; h < H; ++h) {
+    if (!((rows >> h) & 1u)) continue;
     // all-ones where row h holds an anyon (sign extension of bit h)
     const uint32_t m0 = (uint32_t)((int32_t)(b.s0 << (31 - h)) >> 31);
     const uint32_t m1 = (uint32_t)((int32_t)(b.s1 << (31 - h)) >> 31);

@@ -295,11 +295,11 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
     Moves mv = {0u, 0u, 0u, 0u};
     // three message updates; LDS boundary slots alternate between sub-steps
     uint4 *slot_a = (st & 1) ? BND1 : BND0, *slot_b = (st & 1) ? BND0 : BND1;
-    if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16));
+    if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16), rows);
     band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, mv);
-    if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16));
+    if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), rows);
     band_substep<H, false>(b, slot_b, w, wdn, wup, lane, rows, mv);
-    if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16));
+    if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), rows);
     band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, mv);
     uint32_t xo[2], yo[2];
     band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);
