@@ -31,18 +31,28 @@ BYTES_PER_SITE_UPDATE = 16.25   # 4 x int16 registers + 1 syndrome bit, read and
 HBM_PEAK_GBS = 8000.0
 METRIC = "decoded samples/s & site-updates/s at L=256, p=0.01 (plain vs learned-sched)"
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_band_L256_p001.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_03266_amd", "csrc", f) for f in ("mpd.hip", "engine.h", "band.h")]
+CSRC = os.path.join(ROOT, "paper_2506_03266_amd", "csrc")
+
+
+def kernel_source_sha():
+    """sha256[:16] of the band kernel's device code: engine.h, band.h and the
+    k_band section of mpd.hip (from its banner to the noise kernel)."""
+    import hashlib
+    src = open(os.path.join(CSRC, "mpd.hip")).read()
+    a = src.index("// Band path: regions")
+    b = src.index("// Noise and initial syndrome of the band path")
+    parts = [open(os.path.join(CSRC, f), "rb").read() for f in ("engine.h", "band.h")] + [src[a:b].encode()]
+    return hashlib.sha256(b"".join(parts)).hexdigest()[:16]
 
 
 def measured_traffic():
-    """HBM bytes per k_tile launch from the committed rocprofv3 counter summary,
-    or None if the kernel sources changed since the counters were taken."""
-    import hashlib
+    """HBM bytes per k_band launch from the committed rocprofv3 counter summary,
+    or None if the kernel's code changed since the counters were taken."""
     try:
         with open(PROFILE_SUMMARY) as f:
             summ = json.load(f)
-        sha = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SOURCES)).hexdigest()[:16]
-    except OSError:
+        sha = kernel_source_sha()
+    except (OSError, ValueError):
         return None
     return summ["traffic_bytes_per_launch"] if summ.get("kernel_source_sha16") == sha else None
 
@@ -58,9 +68,14 @@ def main():
                     help="c3 (default) is the headline line; c1/c2/c4/c5 print a line for that configuration, "
                          "cnn times the predictor's kernels")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduling leg")
+    ap.add_argument("--streams", type=int, default=None,
+                    help="batches in flight, each on its own stream, host thread and workspace (default 3 for "
+                         "the L = 256 workloads c3/c5, 1 for the short batches of c1/c2/c4)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     args = ap.parse_args()
+    if args.streams is None:
+        args.streams = 3 if args.workload in ("c3", "c5") else 1
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
               "the decoder shards by samples, see DESIGN.md", file=sys.stderr)
@@ -93,26 +108,34 @@ def main():
     if args.workload != "c3":
         return other_workload(args, b, seeds, torch, np)
 
-    n, K, W = N_SAMPLES, args.steps, args.warmup
+    n, K, W, S = N_SAMPLES, args.steps, args.warmup, max(1, args.streams)
     batches = [torch.from_numpy(seeds(3, i % 256, n).view(np.int64)).to(dev) for i in range(W + K)]
-    ws = b.alloc_workspace(L, n)
     outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
              torch.empty((n, b.syndrome_words(L)), dtype=torch.int32, device=dev)) for _ in range(W + K)]
-    for i in range(W):
-        b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=outs[i])
-    torch.cuda.synchronize()
+    runner = Runner(S, torch)
+    wss = [b.alloc_workspace(L, n) for _ in range(S)]
 
-    b.profile(True)
+    def fifo(i, j, stream):
+        b.decode_batch(L, P, batches[i], T_MAX, workspace=wss[j], out=outs[i], stream=stream)
+
+    # one stream, with per-launch kernel timing: the roofline figures
+    for i in range(W):
+        fifo(i, 0, runner.streams[0])
     torch.cuda.synchronize()
+    b.profile(True)
     t0 = time.perf_counter()
     for i in range(W, W + K):
-        b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=outs[i])
+        fifo(i, 0, runner.streams[0])
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed_1 = time.perf_counter() - t0
     b.profile(False)
     tile_ms, tile_launches = b.profile_read("k_band")
+    # S batches in flight: the throughput figure
+    runner.run(fifo, range(W))
+    elapsed = runner.run(fifo, range(W, W + K))
 
-    learned_leg = None if args.no_learned else learned_scheduling(b, batches, outs, W, K, n, elapsed, torch, np)
+    learned_leg = None if args.no_learned else learned_scheduling(b, batches, outs, W, K, n, elapsed, torch, np,
+                                                                  runner)
 
     T_all = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
     F_all = torch.cat([outs[i][1] for i in range(W, W + K)]).cpu().numpy()
@@ -149,8 +172,10 @@ def main():
         "dtype": "u16",
         "data": "synthetic",
         "config": {"workload": "toric code L=256, p=0.01, 4096 seeded i.i.d. bit-flip samples per step, "
-                               "T_max=4096, v=3, plain FIFO batch",
-                   "L": L, "p": P, "samples_per_step": n, "T_max": T_MAX, "v": 3, "scheduling": "fifo"},
+                               f"T_max=4096, v=3, plain FIFO batch, {S} batches in flight on separate streams",
+                   "L": L, "p": P, "samples_per_step": n, "T_max": T_MAX, "v": 3, "scheduling": "fifo",
+                   "concurrent_batches": S},
+        "single_stream": {"samples_per_s": K * n / elapsed_1, "ms_per_step": elapsed_1 / K * 1e3},
         "site_updates_per_s": su_per_s,
         "mean_T_dec": float(T_all.mean()),
         "max_T_dec": int(T_all.max()),
@@ -167,8 +192,56 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, L_eval=L):
-    """Train, tune and time the learned-scheduling decode on the benchmark's batches."""
+class Runner:
+    """Runs batch i of a list on one of S streams (batch i on stream i mod S),
+    one host thread per stream; the library calls release the interpreter
+    lock, so up to S batches are in flight on the device."""
+
+    def __init__(self, S, torch):
+        self.torch = torch
+        # one batch in flight: the caller's stream, no extra thread
+        self.streams = [torch.cuda.current_stream()] if S == 1 else [torch.cuda.Stream() for _ in range(S)]
+
+    def run(self, fn, idxs):
+        """fn(i, j, stream) for every i in idxs; returns the wall time (s)."""
+        import threading
+        torch = self.torch
+        idxs = list(idxs)
+        S = len(self.streams)
+        errs = []
+        if S == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in idxs:
+                fn(i, 0, self.streams[0])
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        def worker(j):
+            try:
+                with torch.cuda.stream(self.streams[j]):
+                    for i in idxs[j::S]:
+                        fn(i, j, self.streams[j])
+            except BaseException as e:  # re-raised below
+                errs.append(e)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        threads = [threading.Thread(target=worker, args=(j,)) for j in range(S)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if errs:
+            raise errs[0]
+        return dt
+
+
+def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, runner, L_eval=L):
+    """Train, tune and time the learned-scheduling decode on the benchmark's batches
+    (same streams and batches in flight as the plain run)."""
     from paper_2506_03266_amd import learned
     from paper_2506_03266_amd.workloads import seeds
     from scipy.stats import spearmanr
@@ -180,19 +253,22 @@ def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, L_eva
     t_train = time.perf_counter() - t0
     tune = torch.from_numpy(seeds(3, 201, n).view(np.int64)).to(dev)
     policy, t_best, t_single, _ = learned.tune_policy(L_eval, P, tune, params, reps=2)
-    lws = b.learned_workspace(L_eval, n)
+    lwss = [b.learned_workspace(L_eval, n) for _ in runner.streams]
     louts = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
               torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev),
               torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
-    for i in range(W):
-        b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lws, out=louts[i])
+
+    def learned(i, j, stream):
+        b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lwss[j],
+                         out=louts[i], stream=stream)
+
+    runner.run(learned, range(W))
+    el = runner.run(learned, range(W, W + K))
+    # inference time per batch, one stream (no overlap with other batches)
     b.profile(True)
+    for i in range(W):
+        learned(i, 0, runner.streams[0])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(W, W + K):
-        b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lws, out=louts[i])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
     b.profile(False)
     cnn_ms, cnn_n = b.profile_read("k_cnn_forward")
     same = all(torch.equal(outs[i][j], louts[i][j]) for i in range(W, W + K) for j in range(3))
@@ -208,61 +284,68 @@ def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, L_eva
 
 
 def other_workload(args, b, seeds, torch, np):
-    """Throughput of configurations 1, 2 (per p) and 4 (mixed sizes), fresh seeds per step."""
+    """Throughput of configurations 1, 2 (per p), 4 (mixed sizes) and 5 (learned
+    scheduling), fresh seeds per step, --streams batches in flight."""
     from paper_2506_03266_amd.workloads import CONFIGS, mixed_batch
     dev = torch.device("cuda:0")
-    K, W = args.steps, args.warmup
+    K, W, S = args.steps, args.warmup, max(1, args.streams)
+    runner = Runner(S, torch)
+    if args.workload == "c5":
+        return learned_c5(args, b, seeds, torch, np, runner)
+    if args.workload == "cnn":
+        return cnn_kernels(args, b, seeds, torch, np)
     if args.workload == "c4":
         Ls, ps, ss = mixed_batch()
         classes = [(L, int((Ls == L).sum())) for L in dict.fromkeys(Ls.tolist())]
+        nb = len(Ls)
         pt = torch.from_numpy(ps).to(dev)
         st = torch.from_numpy(ss.view(np.int64)).to(dev)
-        for _ in range(W):
-            b.decode_mixed(classes, pt, st, 4096)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        outs = [b.decode_mixed(classes, pt, st, 4096) for _ in range(K)]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        W_syn = int(sum(c * b.syndrome_words(L) for L, c in classes))
+        hL = np.ascontiguousarray([c[0] for c in classes], dtype=np.int32)
+        hC = np.ascontiguousarray([c[1] for c in classes], dtype=np.int64)
+        wsz = int(b.lib().mpd_mixed_workspace_bytes(len(hL), hL.ctypes.data, hC.ctypes.data))
+        wss = [torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev) for _ in range(S)]
+        outs = [(torch.empty(nb, dtype=torch.int32, device=dev), torch.empty(nb, dtype=torch.uint8, device=dev),
+                 torch.empty(W_syn, dtype=torch.int32, device=dev)) for _ in range(W + K)]
+
+        def mixed(i, j, stream):
+            b.decode_mixed(classes, pt, st, 4096, workspace=wss[j], out=outs[i], stream=stream)
+
+        runner.run(mixed, range(W))
+        dt = runner.run(mixed, range(W, W + K))
         T = outs[-1][0].cpu().numpy().astype(np.int64)
         su = float((Ls.astype(np.int64) ** 2 * T).sum())
         print(json.dumps({"workload": "config 4: mixed L in {32,64,128,256,512}, counts ~ 1/L^2, "
-                                      "p ~ U[0.001,0.03]", "samples_per_s": K * len(Ls) / dt,
+                                      "p ~ U[0.001,0.03]", "samples_per_s": K * nb / dt,
                           "site_updates_per_s": K * su / dt, "ms_per_batch": dt / K * 1e3,
-                          "samples": int(len(Ls))}))
+                          "samples": int(nb), "concurrent_batches": S}))
         return
-    if args.workload == "c5":
-        return learned_c5(args, b, seeds, torch, np)
-    if args.workload == "cnn":
-        return cnn_kernels(args, b, seeds, torch, np)
     cfg = CONFIGS[1 if args.workload == "c1" else 2]
     L, n = cfg["L"], cfg["n"]
     for k, p in enumerate(cfg["p"]):
         batches = [torch.from_numpy(seeds(int(args.workload[1]), k, n, start=i * n).view(np.int64)).to(dev)
                    for i in range(W + K)]
-        out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None)
-        for i in range(W):
-            b.decode_batch(L, p, batches[i], cfg["T_max"], want_syndrome=False, out=out)
-        torch.cuda.synchronize()
-        tsum = 0
-        t0 = time.perf_counter()
-        for i in range(W, W + K):
-            b.decode_batch(L, p, batches[i], cfg["T_max"], want_syndrome=False, out=out)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        T = out[0].cpu().numpy().astype(np.int64)
+        outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None)
+                for _ in range(W + K)]
+
+        def resident(i, j, stream):
+            b.decode_batch(L, p, batches[i], cfg["T_max"], want_syndrome=False, out=outs[i], stream=stream)
+
+        runner.run(resident, range(W))
+        dt = runner.run(resident, range(W, W + K))
+        T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
         print(json.dumps({"workload": f"config {args.workload[1]}: L={L} p={p} {n} samples",
-                          "samples_per_s": K * n / dt, "site_updates_per_s_last_batch_est": L * L * T.sum() * K / dt,
-                          "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean())}))
+                          "samples_per_s": K * n / dt, "site_updates_per_s": L * L * T.sum() / dt,
+                          "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean()), "concurrent_batches": S}))
 
 
-
-def learned_c5(args, b, seeds, torch, np):
+def learned_c5(args, b, seeds, torch, np, runner):
     """Configuration 5: plain vs learned scheduling at L = 256 (4096 samples)
     and L = 1024 (1024 samples), p = 0.01, with one predictor trained at L = 256."""
     from paper_2506_03266_amd import learned
     dev = torch.device("cuda")
     K, W = args.steps, args.warmup
+    S = len(runner.streams)
     counts, target, _, _ = learned.make_dataset(200000)
     params, _ = learned.train(counts, target, epochs=6)
     for Lc, n, pidx in ((256, 4096, 0), (1024, 1024, 1)):
@@ -270,25 +353,31 @@ def learned_c5(args, b, seeds, torch, np):
                    for i in range(W + K)]
         tune = torch.from_numpy(seeds(5, 200 + pidx, n).view(np.int64)).to(dev)
         policy, _, _, _ = learned.tune_policy(Lc, P, tune, params, reps=2)
-        ws = b.alloc_workspace(Lc, n)
-        lws = b.learned_workspace(Lc, n)
+        wss = [b.alloc_workspace(Lc, n) for _ in range(S)]
+        lwss = [b.learned_workspace(Lc, n) for _ in range(S)]
         res = {}
-        for name, fn in (("fifo", lambda s: b.decode_batch(Lc, P, s, T_MAX, want_syndrome=False, workspace=ws)),
-                         ("learned", lambda s: b.decode_learned(Lc, P, s, params, policy[0], policy[1], T_MAX,
-                                                                want_syndrome=False, workspace=lws))):
-            for i in range(W):
-                fn(batches[i])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            o = [fn(batches[i])[:2] for i in range(W, W + K)]
-            torch.cuda.synchronize()
-            res[name] = (time.perf_counter() - t0, o)
-        same = all(torch.equal(x, y) for a, c in zip(res["fifo"][1], res["learned"][1]) for x, y in zip(a, c))
+        for name in ("fifo", "learned"):
+            outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+                     None, torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
+
+            def fn(i, j, stream, name=name, outs=outs):
+                if name == "fifo":
+                    b.decode_batch(Lc, P, batches[i], T_MAX, want_syndrome=False, workspace=wss[j],
+                                   out=outs[i][:3], stream=stream)
+                else:
+                    b.decode_learned(Lc, P, batches[i], params, policy[0], policy[1], T_MAX, want_syndrome=False,
+                                     workspace=lwss[j], out=outs[i], stream=stream)
+
+            runner.run(fn, range(W))
+            res[name] = (runner.run(fn, range(W, W + K)), outs)
+        same = all(torch.equal(a[0], c[0]) and torch.equal(a[1], c[1])
+                   for a, c in zip(res["fifo"][1][W:], res["learned"][1][W:]))
         print(json.dumps({"workload": f"config 5: L={Lc} p={P} {n} samples, plain vs learned scheduling",
                           "fifo_samples_per_s": K * n / res["fifo"][0],
                           "learned_samples_per_s": K * n / res["learned"][0],
                           "ratio": res["fifo"][0] / res["learned"][0], "identical_results": same,
-                          "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])}}), flush=True)
+                          "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])},
+                          "concurrent_batches": S}), flush=True)
 
 
 def cnn_kernels(args, b, seeds, torch, np):

@@ -38,12 +38,15 @@
  *   - Every pointer named d_* is caller-owned device memory on the current
  *     HIP device; the library never allocates, frees or keeps it.  Host
  *     memory is never read or written except the scalar arguments.  The
- *     library keeps, per device, a few streams and events of its own, and per
- *     host thread a small pinned host block for the pass counters (created
- *     on first use, kept until the process ends).
+ *     library keeps, per host thread and device, a few streams and events of
+ *     its own, and per host thread a small pinned host block for the pass
+ *     counters (created on first use, kept until the process ends).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default
  *     stream).  Outputs are valid once the stream has reached the point after
  *     the call.  Calls that share a workspace must be ordered on one stream.
+ *     Calls on different streams with separate workspaces may run
+ *     concurrently from several host threads; their kernels then overlap on
+ *     the device (one batch's short final passes fill in around another's).
  *   - The large-lattice (band) path reads a survivor counter back to the host
  *     between decoder passes, so those calls synchronize `stream` (they cannot
  *     be captured into a HIP graph).  Lattices up to L = 128 decode in a
@@ -175,7 +178,7 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
  * (noise and initial syndrome of a band-path batch), "k_band" (one pass of k
  * decoder steps over the bands of L >= 256), "k_resident" (whole decode of
  * small lattices), "k_cnn_forward" and "k_cnn_backward" (decode-time
- * predictor).  Not thread-safe. */
+ * predictor).  Records from several host threads are kept together. */
 int mpd_profile(int enable);
 
 /* Sum of the recorded durations (ms) and number of launches of `kernel`;

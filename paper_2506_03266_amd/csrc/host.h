@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,16 +26,19 @@ int fail_with(int code, const char *fmt, ...);
       return fail_with(MPD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));       \
   } while (0)
 
-// Optional per-kernel timing with HIP events on the launch stream.
+// Optional per-kernel timing with HIP events on the launch stream.  Safe
+// to use from several host threads (records are guarded by a mutex).
 struct ProfRec {
   const char *name;
   hipEvent_t a, b;
 };
 struct Profiler {
   bool on = false;
+  std::mutex mu;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   hipEvent_t get() {
+    std::lock_guard<std::mutex> lk(mu);
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
       pool.pop_back();
@@ -61,6 +65,7 @@ struct ProfScope {
   ~ProfScope() {
     if (!g_prof.on || !r.a || !r.b) return;
     (void)hipEventRecord(r.b, st);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.recs.push_back(r);
   }
 };

@@ -838,7 +838,7 @@ int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds,
   return band_passes(&r, 1);
 }
 
-// Library-owned side stream per device (default priority, non-blocking) with
+// Library-owned side streams (default priority, non-blocking) with
 // fork/join events, created on first use and kept for the process.
 constexpr int BAND_STREAMS = 4;
 struct SideStream {
@@ -847,15 +847,15 @@ struct SideStream {
   hipStream_t band[BAND_STREAMS] = {};   // band-path classes of a mixed batch
   hipEvent_t band_join[BAND_STREAMS] = {};
 };
-std::mutex g_side_mu;
-std::map<int, SideStream> g_side;
+// Per host thread and device, so that concurrent calls from several threads
+// never share streams or fork/join events.
+thread_local std::map<int, SideStream> t_side;
 
 SideStream *side_stream() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_side_mu);
-  auto it = g_side.find(dev);
-  if (it != g_side.end()) return &it->second;
+  auto it = t_side.find(dev);
+  if (it != t_side.end()) return &it->second;
   SideStream s;
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
   if (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
@@ -864,7 +864,7 @@ SideStream *side_stream() {
     if (hipStreamCreateWithFlags(&s.band[i], hipStreamNonBlocking) != hipSuccess) return nullptr;
     if (hipEventCreateWithFlags(&s.band_join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
   }
-  return &(g_side[dev] = s);
+  return &(t_side[dev] = s);
 }
 
 int check_common(int L, int64_t n, int T_max, const void *T_dec, const void *flags) {
@@ -1084,6 +1084,7 @@ int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int 
 
 int mpd_profile(int enable) {
   g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   if (enable) {
     for (auto &r : g_prof.recs) {
       g_prof.pool.push_back(r.a);
@@ -1101,6 +1102,7 @@ int mpd_profile_read(const char *kernel, double *total_ms, int64_t *launches) {
     return fail_with(MPD_ERR_PTR, "profile_read arguments must not be NULL");
   double ms = 0.0;
   int64_t cnt = 0;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   for (auto &r : g_prof.recs) {
     if (strcmp(r.name, kernel) != 0) continue;
     HIP_TRY(hipEventSynchronize(r.b));

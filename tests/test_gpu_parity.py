@@ -281,3 +281,49 @@ def test_band_full_and_small_regions(gpu, orc, L, p, n, T_max):
     T, F, S = gpu.decode_batch(L, p, s, T_max)
     ref = orc.decode_seeds(L, p, s, T_max, threads=8)
     compare(f"L={L} p={p} n={n}", T, F, S, ref)
+
+
+def test_concurrent_calls_from_threads(gpu):
+    """Several host threads, each with its own stream and workspace, decoding
+    plain, mixed and learned batches at once: every result equals the
+    sequential one."""
+    import threading
+    import torch
+    from paper_2506_03266_amd.workloads import mixed_batch
+    Ls, ps, ss = mixed_batch()
+    classes = [(L, int((Ls == L).sum())) for L in dict.fromkeys(Ls.tolist())]
+    params = gpu.cnn_init(5)
+    jobs = []
+    for i in range(6):
+        s = seeds(55, i, 512)
+        if i % 3 == 0:
+            jobs.append(lambda st, s=s: gpu.decode_batch(256, 0.02, s, 256, stream=st))
+        elif i % 3 == 1:
+            jobs.append(lambda st: gpu.decode_mixed(classes, ps, ss, 256, stream=st))
+        else:
+            jobs.append(lambda st, s=s: gpu.decode_learned(256, 0.02, s, params, (1.5,), (3, 5), 256,
+                                                           stream=st)[:3])
+    want = [[t.clone() for t in job(torch.cuda.current_stream())] for job in jobs]
+    torch.cuda.synchronize()
+    got = [None] * len(jobs)
+    errs = []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                got[k] = [t.clone() for t in jobs[k](st)]
+            st.synchronize()
+        except BaseException as e:
+            errs.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(len(jobs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errs, errs
+    for k in range(len(jobs)):
+        for a, c in zip(want[k], got[k]):
+            assert torch.equal(a, c), k
