@@ -109,7 +109,7 @@ def test_forward_translation_invariance(gpu):
     assert np.allclose(got, base, rtol=1e-5, atol=1e-5)
 
 
-@pytest.mark.parametrize("M,n", [(32, 16), (8, 32)])
+@pytest.mark.parametrize("M,n", [(32, 16), (8, 32), (8, 21)])
 def test_gradient_matches_oracle(gpu, M, n):
     counts = realistic_counts(M + 1, n, M)
     params = trained_like_params(M + 2)

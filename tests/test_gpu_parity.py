@@ -327,3 +327,32 @@ def test_concurrent_calls_from_threads(gpu):
     for k in range(len(jobs)):
         for a, c in zip(want[k], got[k]):
             assert torch.equal(a, c), k
+
+
+@pytest.mark.parametrize("L,n,T_max", [(2080, 1, 12), (4096, 1, 6)])
+def test_wide_lattices(gpu, orc, L, n, T_max):
+    """Rows wider than one noise workgroup (L/2 > 1024 column pairs: the
+    x-links left of a group are drawn again) and many 2D band tiles."""
+    from oracle import cnn_oracle as co
+    s = seeds(56, L, n)
+    p = 0.02
+    c = gpu.syndrome_counts(L, p, s).cpu().numpy()
+    for i in range(n):
+        ex, ey = orc.noise(L, p, int(s[i]))
+        assert np.array_equal(c[i], co.block_counts(orc.syndrome_of(L, ex, ey), 8))
+    T, F, S = gpu.decode_batch(L, p, s, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    compare(f"L={L}", T, F, S, ref)
+
+
+def test_resident_max_budget(gpu, orc):
+    """A pair that chases itself around the torus (antipodal tie) runs to the
+    largest budget the 16-bit registers allow, with results equal to the oracle's."""
+    L = 16
+    ex = np.zeros((L, L), np.uint8)
+    ey = np.zeros((L, L), np.uint8)
+    ex[3, 2:10] = 1  # a straight chain of 8 links: anyons at x = 2 and x = 10 on row 3
+    links = orc.links_from_chains(L, ex, ey)
+    T, F, S = gpu.decode_errors(L, links, gpu.MPD_T_MAX_LIMIT)
+    ref = orc.decode_links(L, links, gpu.MPD_T_MAX_LIMIT)
+    compare("max budget", T, F, S, ref)
