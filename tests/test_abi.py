@@ -68,3 +68,77 @@ def test_null_pointers_rejected(lib):
 
 def test_empty_batch_is_a_noop(lib):
     assert lib.mpd_decode_batch(16, 0.1, None, 0, 8, None, None, None, None, 0, None) == 0
+
+
+def test_counts_and_predictor_arguments(lib):
+    d = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    lib.mpd_syndrome_counts.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.mpd_syndrome_counts(8, 0.1, None, d, 4, d, None) == -1
+    assert lib.mpd_syndrome_counts(24, 0.1, None, d, 4, d, None) == -1
+    assert lib.mpd_syndrome_counts(32, -0.5, None, d, 4, d, None) == -2
+    assert lib.mpd_syndrome_counts(32, 0.1, None, d, -1, d, None) == -7
+    assert lib.mpd_syndrome_counts(32, 0.1, None, None, 4, d, None) == -4
+    assert lib.mpd_syndrome_counts(32, 0.1, None, d, 0, d, None) == 0
+    P, I, I64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    lib.mpd_cnn_forward.argtypes = [P, I, I64, P, P, P, P, P, SZ, P]
+    lib.mpd_cnn_forward_workspace_bytes.argtypes = [I, I64]
+    lib.mpd_cnn_forward_workspace_bytes.restype = SZ
+    assert lib.mpd_cnn_forward(d, 1, 4, d, d, None, None, d, 1 << 20, None) == -1
+    assert lib.mpd_cnn_forward(d, 32, -1, d, d, None, None, d, 1 << 20, None) == -7
+    assert lib.mpd_cnn_forward(d, 32, 4, None, d, None, None, d, 1 << 20, None) == -4
+    need = lib.mpd_cnn_forward_workspace_bytes(128, 4)
+    assert need > lib.mpd_cnn_forward_workspace_bytes(32, 4) > 0
+    assert lib.mpd_cnn_forward(d, 128, 4, d, d, None, None, d, need - 1, None) == -5
+    assert lib.mpd_cnn_forward(d, 32, 0, None, None, None, None, None, 0, None) == 0
+    lib.mpd_cnn_loss_grad.argtypes = [P, I, I64, P, P, P, P, P, P, SZ, P]
+    lib.mpd_cnn_train_workspace_bytes.argtypes = [I, I64]
+    lib.mpd_cnn_train_workspace_bytes.restype = SZ
+    assert lib.mpd_cnn_train_workspace_bytes(33, 16) == 0
+    assert lib.mpd_cnn_loss_grad(d, 33, 16, d, d, d, d, None, d, 1 << 30, None) == -1
+    assert lib.mpd_cnn_loss_grad(d, 32, 0, d, d, d, d, None, d, 1 << 30, None) == -7
+    assert lib.mpd_cnn_loss_grad(d, 32, 16, d, d, d, d, None, d, 16, None) == -5
+    F = ctypes.c_float
+    lib.mpd_cnn_adam_step.argtypes = [P, P, P, P, I, F, F, F, F, P]
+    assert lib.mpd_cnn_adam_step(d, d, d, d, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -7
+    assert lib.mpd_cnn_adam_step(d, d, d, d, 1, float("nan"), 0.9, 0.999, 1e-8, None) == -2
+    assert lib.mpd_cnn_adam_step(d, d, d, d, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -2
+    assert lib.mpd_cnn_adam_step(None, d, d, d, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -4
+    lib.mpd_cnn_init.argtypes = [P, ctypes.c_uint64, P]
+    assert lib.mpd_cnn_init(None, 1, None) == -4
+
+
+def test_learned_decode_arguments(lib):
+    d = ctypes.c_void_p(4096)
+    P, I, I64, SZ, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    lib.mpd_decode_learned.argtypes = [I, D, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
+    lib.mpd_learned_workspace_bytes.argtypes = [I, I64]
+    lib.mpd_learned_workspace_bytes.restype = SZ
+    assert lib.mpd_learned_workspace_bytes(128, 10) == 0
+    assert lib.mpd_learned_workspace_bytes(256, 10) > lib.mpd_workspace_bytes(256, 10)
+    edges = (ctypes.c_float * 2)(1.0, 2.0)
+    bad_edges = (ctypes.c_float * 2)(2.0, 1.0)
+    depths = (ctypes.c_int * 3)(3, 4, 5)
+    deep = (ctypes.c_int * 3)(3, 4, 16)
+
+    def call(L=256, p=0.01, n=8, T=64, nb=3, e=edges, k=depths, ws_bytes=1 << 40):
+        return lib.mpd_decode_learned(L, p, d, n, T, d, nb, e, k, d, d, None, None, d, ws_bytes, None)
+
+    assert call(L=128) == -1
+    assert call(p=2.0) == -2
+    assert call(T=-1) == -3
+    assert call(nb=0) == -7 and call(nb=9) == -7
+    assert call(k=deep) == -3
+    assert call(e=bad_edges) == -2
+    assert call(e=None) == -4 and call(k=None) == -4
+    assert call(ws_bytes=1024) == -5
+    assert call(n=0) == 0
+
+
+def test_mixed_workspace_is_per_band_class(lib):
+    lib.mpd_mixed_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.mpd_mixed_workspace_bytes.restype = ctypes.c_size_t
+    Ls = (ctypes.c_int32 * 3)(64, 256, 256)
+    cs = (ctypes.c_int64 * 3)(10, 4, 2)
+    total = lib.mpd_mixed_workspace_bytes(3, Ls, cs)
+    assert total >= lib.mpd_workspace_bytes(256, 4) + lib.mpd_workspace_bytes(256, 2)
