@@ -192,7 +192,7 @@ def profile_read(kernel: str):
 
 
 def set_band_schedule(k_first: int, k_next: int, L: int = 0):
-    """Decoder steps per pass of the band path (first pass with noise, later);
+    """Decoder steps per pass of the band path (first pass, later passes);
     L = 0 sets the default for every L."""
     _check(lib().mpd_set_band_schedule(int(L), int(k_first), int(k_next)), "mpd_set_band_schedule")
 
