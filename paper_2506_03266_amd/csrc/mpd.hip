@@ -410,8 +410,11 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
 }
 
 // Per-pass bookkeeping: T_dec from the per-step bits, compaction of the
-// samples that still hold anyons.  status: 0 running, 1 decoded, 2 timeout.
-__global__ void k_finalize(int k, int T_max, const int32_t *active, int nact, int32_t *t_done,
+// samples that still hold anyons.  status: 0 running, 1 decoded, 2 timeout;
+// bit 2 of a timeout: the state buffer (0/1) that holds its final syndrome
+// (samples of first-pass groups of different depth time out in different
+// passes).  `dst` is the buffer this pass wrote.
+__global__ void k_finalize(int k, int T_max, int dst, const int32_t *active, int nact, int32_t *t_done,
                            uint32_t *alive, int32_t *T_dec, uint8_t *status, int32_t *next,
                            int *next_count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -433,7 +436,7 @@ __global__ void k_finalize(int k, int T_max, const int32_t *active, int nact, in
     status[s] = 1;
   } else if (t0 + ks >= T_max) {
     T_dec[s] = T_max;
-    status[s] = 2;
+    status[s] = (uint8_t)(2 | (dst << 2));
   } else {
     next[atomicAdd(next_count, 1)] = s;
   }
@@ -452,10 +455,11 @@ __global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t 
 
 // flags and final syndrome (row-major bits) from the band state.
 __global__ void k_band_export(int L, int64_t n, const uint8_t *status, const uint32_t *wind,
-                              const uint2 *Slast, uint8_t *flags, uint32_t *syn) {
+                              const uint2 *S0, const uint2 *S1, uint8_t *flags, uint32_t *syn) {
   const int64_t smp = blockIdx.x;
   const int64_t nw = ((int64_t)L * L + 31) / 32;
-  const bool timeout = status[smp] == 2;
+  const bool timeout = (status[smp] & 3) == 2;
+  const uint2 *Slast = (status[smp] >> 2) & 1 ? S1 : S0;
   if (threadIdx.x == 0) {
     const uint32_t W = wind[smp];
     const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
@@ -672,6 +676,25 @@ int band_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, 
 // cur, written to cur ^ 1), then T_dec bookkeeping and compaction of the
 // survivors into w.active[cur ^ 1].  `zero` clears the survivor counter
 // first (the first launch of a pass).
+// Would a pass of k steps over nact samples in full-size regions leave
+// compute units idle?
+bool small_pass(int L, int k, int nact) {
+  const int tx = BAND_RX - 8 * k;
+  const int hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
+  const int ty16 = L == BAND_RY ? L : BAND_RY - 2 * hy;
+  const int64_t wg16 = (int64_t)((L + tx - 1) / tx) * ((L + ty16 - 1) / ty16) * nact;
+  return wg16 < cu_count();
+}
+
+// Steps of a later pass: the schedule's k_next, but at least K_SMALL when the
+// pass is small -- it then runs in 4-wave regions at a fraction of the time
+// per step, and a round trip to the host costs more than a few extra steps.
+constexpr int K_SMALL = 4;
+int later_pass_k(int L, int nact) {
+  const int kn = schedule_for(L).k_next;
+  return (kn < K_SMALL && small_pass(L, kn, nact)) ? K_SMALL : kn;
+}
+
 int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *active, int nact, int cur, bool zero,
               int32_t *d_T_dec, hipStream_t stream) {
   BandArgs ba;
@@ -687,10 +710,8 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   // Full-size regions (16 waves, 256 rows) unless their grid would leave
   // compute units idle: then 4-wave regions of 64 rows, which need more
   // (overlapping) tiles but take about a quarter of the time per step.
-  const int ty16 = L == BAND_RY ? L : BAND_RY - 2 * hy;
-  const int64_t wg16 = (int64_t)ba.ntx * ((L + ty16 - 1) / ty16) * nact;
   const int ry4 = BAND_NW_SMALL * BAND_H;
-  const bool small = wg16 < cu_count() && ry4 - 2 * hy >= TILE_H;
+  const bool small = small_pass(L, k, nact) && ry4 - 2 * hy >= TILE_H;
   const int ry = small ? ry4 : BAND_RY;
   if (L == ry) {
     ba.hy = 0;
@@ -718,8 +739,8 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
                          band_lds(BAND_NW), stream, ba);
   }
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, active, nact,
-                     w.t_done, w.alive, d_T_dec, w.status, w.active[cur ^ 1], &w.count[cur ^ 1]);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, cur ^ 1, active,
+                     nact, w.t_done, w.alive, d_T_dec, w.status, w.active[cur ^ 1], &w.count[cur ^ 1]);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -796,12 +817,12 @@ int band_passes(BandRun *runs, int nr) {
       if (r.done) continue;
       if (hc[i] == 0) {
         hipLaunchKernelGGL(k_band_export, dim3((unsigned)r.n), dim3(256), 0, r.stream, r.L, r.n, r.w.status, r.w.wind,
-                           r.w.S[r.cur], r.flags, r.syn);
+                           r.w.S[0], r.w.S[1], r.flags, r.syn);
         HIP_TRY(hipGetLastError());
         r.done = true;
         continue;
       }
-      const int rc = band_pass(r.L, schedule_for(r.L).k_next, r.T_max, r.w, r.w.active[r.cur], hc[i], r.cur, true,
+      const int rc = band_pass(r.L, later_pass_k(r.L, hc[i]), r.T_max, r.w, r.w.active[r.cur], hc[i], r.cur, true,
                                r.T_dec, r.stream);
       if (rc != MPD_OK) return rc;
       r.cur ^= 1;

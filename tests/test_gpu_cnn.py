@@ -239,3 +239,21 @@ def test_learned_vs_fifo_L256(gpu, capsys):
               f"vs training-mean constant {mse_const:.4f}")
     assert mse_net < mse_const
     assert t_lrn < 1.5 * t_fifo
+
+
+@pytest.mark.parametrize("depths,T_max", [((2, 6), 5), ((1, 7), 6), ((3, 5), 7), ((1, 2, 9), 9)])
+def test_learned_timeouts_in_different_passes(gpu, orc, depths, T_max):
+    """Groups of different first-pass depth reach the step budget in different
+    passes, so their final states sit in different ping-pong buffers: the
+    exported final syndromes of the timeouts must still be the oracle's."""
+    L, p, n = 256, 0.08, 9
+    s = seeds(57, 10 * T_max + len(depths), n)
+    params = torch.from_numpy(trained_like_params(11)).cuda()
+    pr = np.sort(gpu.cnn_forward(gpu.syndrome_counts(L, p, s), params).cpu().numpy())
+    edges = tuple(float(e) for e in pr[np.linspace(0, n, len(depths) + 1).astype(int)[1:-1]])
+    T, F, S, _ = gpu.decode_learned(L, p, s, params, edges, depths, T_max)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=8)
+    assert np.array_equal(T.cpu().numpy(), ref["T_dec"])
+    assert np.array_equal(F.cpu().numpy(), ref["flags"])
+    assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"])
+    assert (F.cpu().numpy() & 2).sum() > 0  # some timeouts
