@@ -12,14 +12,13 @@ tensors to it.  :mod:`.workloads` holds the seeded input recipes.  The
 binding is imported lazily so that the input recipes load without a GPU.
 """
 
-__all__ = ["binding", "workloads"]
+__all__ = ["binding", "workloads", "learned", "sweep"]
 
 
 def __getattr__(name):
-    if name == "binding":
-        from . import binding
-        return binding
-    if name == "workloads":
-        from . import workloads
-        return workloads
+    # import_module loads the submodule itself; "from . import name" would ask
+    # this hook again for the attribute before importing and recurse.
+    if name in __all__:
+        import importlib
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

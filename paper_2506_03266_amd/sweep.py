@@ -1,0 +1,222 @@
+"""Monte Carlo sweeps of the 2D numerics (Sec. 7.2) on the GPU decoder.
+
+Three measurements, all on i.i.d. bit-flip noise, periodic L x L lattices, v = 3:
+
+* logical failure rate p_log against p at several L, and the crossing points
+  of consecutive sizes (the threshold p_c);
+* the slope gamma of p_log = C (p / p_c)^(gamma L) below threshold, from
+  p_log at two sizes: gamma = ln(p_log(L2) / p_log(L1)) / ((L2 - L1) ln(p / p_c));
+* the mean decoding time T_dec against ln L below threshold, fitted by
+  T_dec = A ln L + B.
+
+Every sample is decoded by libmpd (noise, decoding and classification run in
+the HIP kernels); this module chooses seeds, sums the per-sample results on
+the device and fits the sums.  A sample that is still not anyon-free after
+T_max steps is counted as a logical failure, as the decoder's flags say, and
+is left out of the mean decoding time.
+
+Run as ``python -m paper_2506_03266_amd.sweep [--quick] [--json PATH]``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+SWEEP_CONFIG = 7    # seed stream of the sweeps (disjoint from the benchmark workloads)
+
+# Grids: (L, samples) per size, and the noise strengths.
+THRESHOLD_P = [0.06, 0.065, 0.07, 0.0725, 0.075, 0.0775, 0.08, 0.085, 0.09]
+THRESHOLD_L = [(16, 200000), (32, 100000), (64, 50000), (128, 20000), (256, 8000), (512, 4000)]
+SLOPE_P = [0.03, 0.04, 0.05]
+SLOPE_L = [(8, 4000000), (12, 4000000), (16, 4000000), (24, 4000000), (32, 4000000)]
+TDEC_P = [0.01, 0.02, 0.03, 0.05]
+TDEC_L = [(16, 100000), (32, 100000), (64, 50000), (128, 20000), (256, 8000), (512, 2000), (1024, 512)]
+
+
+def seed_block(L: int, p_index: int, n: int, start: int = 0) -> np.ndarray:
+    """Seeds of one sweep point: stream SWEEP_CONFIG, index (L << 8) | p_index."""
+    from .workloads import seeds
+    return seeds(SWEEP_CONFIG, (L << 8) | p_index, n, start)
+
+
+def _chunk(L: int) -> int:
+    # Enough samples per call to fill the GPU; for the band path (L >= 256,
+    # about 16.5 workspace bytes per site and sample) few enough to keep the
+    # workspace near 8 GB.
+    return 262144 if L <= 128 else int(max(64, min(8192, (8 << 30) // (17 * L * L))))
+
+
+def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096) -> dict:
+    """Decode n seeded samples at (L, p); returns the counts and sums of the point.
+
+    fails counts flag bit 0 (timeouts included), timeouts flag bit 1; T_sum
+    and T_sq sum T_dec over the samples that finished.
+    """
+    import torch
+    from . import binding as b
+    dev = torch.device("cuda")
+    c = min(n, _chunk(L))
+    ws = b.alloc_workspace(L, c, dev)
+    T = torch.empty(c, dtype=torch.int32, device=dev)
+    F = torch.empty(c, dtype=torch.uint8, device=dev)
+    acc = torch.zeros(5, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a in range(0, n, c):
+        m = min(c, n - a)
+        s = torch.from_numpy(seed_block(L, p_index, m, a).view(np.int64)).to(dev)
+        Tm, Fm, _ = b.decode_batch(L, p, s, T_max, want_syndrome=False, workspace=ws, out=(T[:m], F[:m], None))
+        Fi = Fm.to(torch.int64)
+        done = (Fi & 2) == 0
+        Td = torch.where(done, Tm.to(torch.int64), torch.zeros_like(Fi))
+        acc += torch.stack([(Fi & 1).sum(), (Fi >> 1 & 1).sum(), Td.sum(), (Td * Td).sum(),
+                            Tm.to(torch.int64).sum()])
+    v = acc.cpu().tolist()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fails, timeouts, T_sum, T_sq, T_all = (int(x) for x in v)
+    return dict(L=L, p=p, n=n, T_max=T_max, fails=fails, timeouts=timeouts, T_sum=T_sum, T_sq=T_sq,
+                seconds=dt, site_updates=T_all * L * L)
+
+
+def p_log(r: dict) -> float:
+    return r["fails"] / r["n"]
+
+
+def p_log_err(r: dict) -> float:
+    f = p_log(r)
+    return math.sqrt(max(f * (1 - f), 1.0 / r["n"]) / r["n"])
+
+
+def mean_T(r: dict):
+    """(mean T_dec, its standard error) over the samples that finished."""
+    k = r["n"] - r["timeouts"]
+    if k == 0:
+        return float("nan"), float("nan")
+    m = r["T_sum"] / k
+    var = max(r["T_sq"] / k - m * m, 0.0)
+    return m, math.sqrt(var / k)
+
+
+def crossing(ps, f1, f2):
+    """First p at which p_log of the larger size stops being below that of the
+    smaller one.  Between the two grid points around the sign change,
+    ln(f2 / f1) is interpolated linearly in ln p, which is exact for
+    p_log = C (p/p_c)^(gamma L) with a common C; None if there is no change."""
+    f1 = np.asarray(f1, dtype=float)
+    f2 = np.asarray(f2, dtype=float)
+    for i in range(1, len(ps)):
+        if f2[i - 1] < f1[i - 1] and f2[i] >= f1[i]:
+            if min(f1[i - 1], f1[i], f2[i - 1], f2[i]) > 0:
+                d0, d1 = math.log(f2[i - 1] / f1[i - 1]), math.log(f2[i] / f1[i])
+                x0, x1 = math.log(ps[i - 1]), math.log(ps[i])
+                return math.exp(x0 + (x1 - x0) * (-d0) / (d1 - d0))
+            d0, d1 = f2[i - 1] - f1[i - 1], f2[i] - f1[i]
+            return ps[i - 1] + (ps[i] - ps[i - 1]) * (-d0) / (d1 - d0)
+    return None
+
+
+def slope_gamma(L1: int, f1: float, L2: int, f2: float, p: float, p_c: float) -> float:
+    """gamma of p_log = C (p/p_c)^(gamma L) from two sizes at one p."""
+    return math.log(f2 / f1) / ((L2 - L1) * math.log(p / p_c))
+
+
+def fit_log(Ls, T, w=None):
+    """Weighted least squares of T = A ln L + B; returns (A, B)."""
+    x = np.log(np.asarray(Ls, dtype=float))
+    y = np.asarray(T, dtype=float)
+    w = np.ones_like(x) if w is None else np.asarray(w, dtype=float)
+    X = np.stack([x, np.ones_like(x)], axis=1) * np.sqrt(w)[:, None]
+    A, B = np.linalg.lstsq(X, y * np.sqrt(w), rcond=None)[0]
+    return float(A), float(B)
+
+
+def run(quick: bool = False, T_max: int = 4096, log=print) -> dict:
+    scale = 0.05 if quick else 1.0
+    res = dict(T_max=T_max, threshold=[], slope=[], tdec=[])
+
+    def go(kind, grid_L, grid_p, p_base):
+        for L, n in grid_L:
+            n = max(256, int(n * scale))
+            for i, p in enumerate(grid_p):
+                r = point(L, p, n, p_base + i, T_max)
+                m, e = mean_T(r)
+                log(f"{kind} L={L} p={p}: p_log={p_log(r):.5f}±{p_log_err(r):.5f} timeouts={r['timeouts']} "
+                    f"T={m:.3f}±{e:.3f} n={n} {r['seconds']:.2f}s "
+                    f"{r['site_updates'] / max(r['seconds'], 1e-9):.3g} site-updates/s")
+                res[kind].append(r)
+
+    go("threshold", THRESHOLD_L, THRESHOLD_P, 0)
+    go("slope", SLOPE_L, SLOPE_P, 32)
+    go("tdec", TDEC_L, TDEC_P, 64)
+    res["summary"] = summarize(res)
+    return res
+
+
+TDEC_FIT_LMIN = 64   # the ln L fit uses sizes from here on (smaller ones bend below the line)
+
+
+def summarize(res: dict) -> dict:
+    """Crossings of consecutive sizes (all samples, and decoded samples only),
+    slopes gamma against the crossing of the two largest sizes, and
+    unweighted fits of mean T_dec = A ln L + B over L >= TDEC_FIT_LMIN."""
+    out = {}
+    th = res["threshold"]
+    Ls = sorted({r["L"] for r in th})
+    ps = sorted({r["p"] for r in th})
+    tab = {(r["L"], r["p"]): p_log(r) for r in th}
+    dec = {(r["L"], r["p"]): (r["fails"] - r["timeouts"]) / max(r["n"] - r["timeouts"], 1) for r in th}
+    for key, t in (("crossings", tab), ("crossings_decoded_only", dec)):
+        out[key] = {f"{L1}/{L2}": crossing(ps, [t[(L1, p)] for p in ps], [t[(L2, p)] for p in ps])
+                    for L1, L2 in zip(Ls, Ls[1:])}
+    pcs = [c for c in out["crossings"].values() if c is not None]
+    p_c = pcs[-1] if pcs else 0.073
+    out["p_c_used_for_gamma"] = p_c
+    sl = res["slope"]
+    sLs = sorted({r["L"] for r in sl})
+    stab = {(r["L"], r["p"]): p_log(r) for r in sl}
+    gam = {}
+    for p in sorted({r["p"] for r in sl}):
+        for L1, L2 in zip(sLs, sLs[1:]):
+            f1, f2 = stab[(L1, p)], stab[(L2, p)]
+            if f1 > 0 and f2 > 0:
+                gam[f"p={p} L={L1}/{L2}"] = slope_gamma(L1, f1, L2, f2, p, p_c)
+    out["gamma"] = gam
+    td = res["tdec"]
+    fits = {}
+    for p in sorted({r["p"] for r in td}):
+        rows = sorted((r for r in td if r["p"] == p), key=lambda r: r["L"])
+        Lp = [r["L"] for r in rows]
+        mT = [mean_T(r) for r in rows]
+        use = [i for i, L in enumerate(Lp) if L >= TDEC_FIT_LMIN]
+        A, B = fit_log([Lp[i] for i in use], [mT[i][0] for i in use])
+        resid = [mT[i][0] - (A * math.log(Lp[i]) + B) for i in use]
+        fits[str(p)] = dict(A=A, B=B, L=Lp, T=[m for m, _ in mT], err=[e for _, e in mT],
+                            max_abs_resid=max(abs(x) for x in resid))
+    out["tdec_fit"] = fits
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--quick", action="store_true", help="5%% of the samples per point")
+    ap.add_argument("--T-max", type=int, default=4096)
+    ap.add_argument("--json", default=None, help="write all counts and fits here")
+    a = ap.parse_args(argv)
+    import torch
+    if not torch.cuda.is_available():
+        sys.exit("sweep: needs a GPU (the decoder runs only in libmpd's HIP kernels)")
+    res = run(a.quick, a.T_max, log=lambda s: print(s, flush=True))
+    print(json.dumps(res["summary"], indent=1), flush=True)
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -142,3 +142,15 @@ def test_mixed_workspace_is_per_band_class(lib):
     cs = (ctypes.c_int64 * 3)(10, 4, 2)
     total = lib.mpd_mixed_workspace_bytes(3, Ls, cs)
     assert total >= lib.mpd_workspace_bytes(256, 4) + lib.mpd_workspace_bytes(256, 2)
+
+
+@pytest.mark.parametrize("stmt", ["from paper_2506_03266_amd import binding, sweep, learned",
+                                  "import paper_2506_03266_amd as m; m.sweep.SWEEP_CONFIG; m.binding.syndrome_words(8)"])
+def test_package_submodules_load_lazily(stmt):
+    """Each submodule loads on first use, in a fresh interpreter (as under
+    ``python -m paper_2506_03266_amd.sweep``)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", stmt], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]

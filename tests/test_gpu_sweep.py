@@ -1,0 +1,53 @@
+"""The Sec. 7.2 sweep's per-point counts (failures, timeouts, sums of T_dec)
+equal those of the oracle on the same seeds, near and above threshold and on
+both decoder paths (resident L <= 128, band L >= 256)."""
+import numpy as np
+import pytest
+
+from paper_2506_03266_amd import sweep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03266_amd.binding as b
+    b.lib()
+    return b
+
+
+@pytest.mark.parametrize("L,p,n,T_max", [(16, 0.075, 4000, 4096), (32, 0.09, 1500, 512), (64, 0.08, 300, 1024),
+                                         (256, 0.075, 24, 160)])
+def test_point_counts_match_oracle(gpu, orc, L, p, n, T_max):
+    r = sweep.point(L, p, n, p_index=200, T_max=T_max)
+    ref = orc.decode_seeds(L, p, sweep.seed_block(L, 200, n), T_max, threads=16, want_sigma=False)
+    T = ref["T_dec"].astype(np.int64)
+    F = ref["flags"].astype(np.int64)
+    done = (F & 2) == 0
+    want = dict(fails=int((F & 1).sum()), timeouts=int((~done).sum()), T_sum=int(T[done].sum()),
+                T_sq=int((T[done] ** 2).sum()), site_updates=int(T.sum()) * L * L)
+    got = {k: r[k] for k in want}
+    assert got == want, (L, p, got, want)
+    assert want["fails"] > 0
+
+
+def test_point_spans_chunks(gpu, orc):
+    """A point larger than one call's chunk sums its chunks (band path, chunk
+    limit forced down to two samples)."""
+    L, p, n, T_max = 512, 0.07, 5, 96
+    old = sweep._chunk
+    try:
+        sweep._chunk = lambda L: 2
+        r = sweep.point(L, p, n, p_index=201, T_max=T_max)
+    finally:
+        sweep._chunk = old
+    ref = orc.decode_seeds(L, p, sweep.seed_block(L, 201, n), T_max, threads=16, want_sigma=False)
+    T = ref["T_dec"].astype(np.int64)
+    F = ref["flags"].astype(np.int64)
+    done = (F & 2) == 0
+    assert r["fails"] == int((F & 1).sum()) and r["timeouts"] == int((~done).sum())
+    assert r["T_sum"] == int(T[done].sum()) and r["T_sq"] == int((T[done] ** 2).sum())
+    assert r["site_updates"] == int(T.sum()) * L * L
