@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="batches in flight, each on its own stream, host thread and workspace (default 3 for "
                          "the L = 256 workloads c3/c5, 1 for the short batches of c1/c2/c4)")
+    ap.add_argument("--band-driver", choices=["auto", "host", "device"], default="auto",
+                    help="who drives the later passes of the band path (L >= 256): the host (a survivor-count "
+                         "readback per pass) or the device (one persistent launch); auto = the library's choice")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -93,6 +96,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    b.set_band_driver({"auto": b.BAND_DRIVER_AUTO, "host": b.BAND_DRIVER_HOST,
+                       "device": b.BAND_DRIVER_DEVICE}[args.band_driver])
 
     if args.copy_calib:
         nbytes = args.copy_calib << 20
@@ -134,6 +140,7 @@ def main():
     runner.run(fifo, range(W))
     elapsed = runner.run(fifo, range(W, W + K))
 
+    device_leg = device_driven(b, batches, outs, W, K, n, wss[0], torch) if args.band_driver == "auto" else None
     learned_leg = None if args.no_learned else learned_scheduling(b, batches, outs, W, K, n, elapsed, torch, np,
                                                                   runner)
 
@@ -187,6 +194,7 @@ def main():
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE,
                      "launches": tile_launches, "avg_launch_ms": avg_launch_s * 1e3},
         "cpu_baseline": cpu,
+        "device_driver": device_leg,
         "learned_sched": learned_leg,
     }
     print(json.dumps(line), flush=True)
@@ -237,6 +245,49 @@ class Runner:
         if errs:
             raise errs[0]
         return dt
+
+
+def device_driven(b, batches, outs, W, K, n, ws, torch):
+    """The same K batches, one stream, with the later passes driven on the
+    device (no host wait in a decode), then as replays of one captured HIP
+    graph (the seeds copied into the graph's input before each replay).
+    Checks that every output equals the plain run's."""
+    dev = torch.device("cuda")
+    st = torch.cuda.current_stream()
+    o = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+         torch.empty((n, b.syndrome_words(L)), dtype=torch.int32, device=dev))
+    same = True
+    b.set_band_driver(b.BAND_DRIVER_DEVICE)
+    try:
+        for i in range(W):
+            b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
+        torch.cuda.synchronize()
+        el_dev = time.perf_counter() - t0
+        same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
+    finally:
+        b.set_band_driver(b.BAND_DRIVER_AUTO)
+    s_in = batches[0].clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.decode_batch(L, P, s_in, T_MAX, workspace=ws, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        s_in.copy_(batches[i])
+        g.replay()
+        if i < W + 2:  # a couple of replays checked against the plain run as they go
+            torch.cuda.synchronize()
+            same = same and all(torch.equal(x, y) for x, y in zip(o, outs[i]))
+    torch.cuda.synchronize()
+    el_graph = time.perf_counter() - t0
+    same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
+    return {"samples_per_s": K * n / el_dev, "ms_per_step": el_dev / K * 1e3,
+            "graph_replay_samples_per_s": K * n / el_graph, "graph_replay_ms_per_step": el_graph / K * 1e3,
+            "identical_results": bool(same)}
 
 
 def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, runner, L_eval=L):

@@ -47,10 +47,14 @@
  *     Calls on different streams with separate workspaces may run
  *     concurrently from several host threads; their kernels then overlap on
  *     the device (one batch's short final passes fill in around another's).
- *   - The large-lattice (band) path reads a survivor counter back to the host
- *     between decoder passes, so those calls synchronize `stream` (they cannot
- *     be captured into a HIP graph).  Lattices up to L = 128 decode in a
- *     single launch with no host synchronization and can be captured.
+ *   - Lattices up to L = 128 decode in a single launch with no host
+ *     synchronization.  The large-lattice (band) path runs its later passes
+ *     either from the host, reading a survivor counter back before each pass
+ *     (the call then synchronizes `stream`), or on the device with no host
+ *     wait (see mpd_set_band_driver).  A call on a stream that is being
+ *     captured into a HIP graph always takes the device, so every
+ *     mpd_decode_batch can be captured; mpd_decode_learned reads its group
+ *     sizes back and cannot.
  *   - Return value 0 on success, a negative MPD_ERR_* code otherwise; the
  *     message of the last failing call on this host thread is returned by
  *     mpd_last_error().  On an error nothing has been enqueued unless the
@@ -140,11 +144,36 @@ int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_
 int mpd_set_band_schedule(int L, int k_first, int k_next);
 int mpd_get_band_schedule(int L, int *k_first, int *k_next);
 
+/* Who drives the later passes of the band path (L >= 256).
+ *   MPD_BAND_DRIVER_HOST    one launch per pass; before each, the host reads
+ *                           the survivor count back (a wait on the stream)
+ *                           and sizes the grid to it, with 4-wave regions
+ *                           when the survivors would leave compute units
+ *                           idle.  Fastest for a few samples.
+ *   MPD_BAND_DRIVER_DEVICE  one persistent launch after the first pass:
+ *                           each workgroup takes surviving samples from a
+ *                           device list and runs all their passes, tile by
+ *                           tile, until each is decoded or reaches T_max.
+ *                           No host wait: a band-path decode can then be
+ *                           captured into a HIP graph.
+ *   MPD_BAND_DRIVER_AUTO    the device on a stream that is being captured,
+ *                           else the host.
+ * Results never depend on the driver.  L = 0 sets the default and the
+ * driver of every per-L setting; otherwise this L only.  A stream under
+ * capture always takes the device.  Process-wide, guarded by a mutex;
+ * MPD_ERR_N for an unknown driver. */
+#define MPD_BAND_DRIVER_AUTO 0
+#define MPD_BAND_DRIVER_HOST 1
+#define MPD_BAND_DRIVER_DEVICE 2
+int mpd_set_band_driver(int L, int driver);
+int mpd_get_band_driver(int L, int *driver);
+
 /* Autotuner for the band path: decodes the probe batch (same arguments as
  * mpd_decode_batch, outputs overwritten) once per candidate schedule
- * k_first in [2, 6] x k_next in [1, 4], timing each with HIP events on
- * `stream`, and keeps the fastest for this L (mpd_get_band_schedule then
- * returns it).  *k_first, *k_next and *best_ms receive the choice.
+ * driver (host, device) x k_first in [2, 6] x k_next in [1, 4], timing each
+ * with HIP events on `stream`, and keeps the fastest for this L
+ * (mpd_get_band_schedule and mpd_get_band_driver then return it).
+ * *k_first, *k_next and *best_ms receive the choice.
  * Synchronizes `stream`. */
 int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
                       uint8_t *d_flags, void *d_workspace, size_t ws_bytes, void *stream, int *k_first,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libmpd.so")
 MPD_FLAG_FAIL = 1
 MPD_FLAG_TIMEOUT = 2
 MPD_T_MAX_LIMIT = 10922
+BAND_DRIVER_AUTO, BAND_DRIVER_HOST, BAND_DRIVER_DEVICE = 0, 1, 2
 
 _lib = None
 
@@ -50,6 +51,10 @@ def lib():
     L.mpd_set_band_schedule.restype = I
     L.mpd_get_band_schedule.argtypes = [I, P, P]
     L.mpd_get_band_schedule.restype = I
+    L.mpd_set_band_driver.argtypes = [I, I]
+    L.mpd_set_band_driver.restype = I
+    L.mpd_get_band_driver.argtypes = [I, P]
+    L.mpd_get_band_driver.restype = I
     L.mpd_autotune_band.argtypes = [I, D, P, I64, I, P, P, P, SZ, P, P, P, P]
     L.mpd_autotune_band.restype = I
     L.mpd_mixed_workspace_bytes.argtypes = [I, P, P]
@@ -203,9 +208,22 @@ def get_band_schedule(L: int = 0):
     return a.value, c.value
 
 
+def set_band_driver(driver: int, L: int = 0):
+    """Who drives the band path's later passes: BAND_DRIVER_AUTO, _HOST or
+    _DEVICE; L = 0 sets the default and every per-L setting."""
+    _check(lib().mpd_set_band_driver(int(L), int(driver)), "mpd_set_band_driver")
+
+
+def get_band_driver(L: int = 0) -> int:
+    d = ctypes.c_int(-1)
+    _check(lib().mpd_get_band_driver(int(L), ctypes.byref(d)), "mpd_get_band_driver")
+    return d.value
+
+
 def autotune_band(L: int, p: float, seeds, T_max: int = 4096, stream=None):
-    """Time the band-path schedules on a probe batch and keep the fastest for L.
-    Returns (k_first, k_next, best_ms)."""
+    """Time the band-path schedules (driver x k_first x k_next) on a probe
+    batch and keep the fastest for L.  Returns (k_first, k_next, best_ms);
+    get_band_driver(L) gives the chosen driver."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()

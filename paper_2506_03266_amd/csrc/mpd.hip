@@ -216,11 +216,17 @@ struct BandArgs {
   int *zero_count;  // counter to clear for the following compaction, or nullptr
 };
 
-// A region has NW * 16 rows.  With ty == L it spans the full height
-// (L == NW * 16, rows wrap); otherwise regions overlap by hy rows (a
-// multiple of 16) above and below.
+// One pass of tile `tile` of `sample`, which has done t0 steps: loads the
+// region from (Esrc, Ssrc), runs up to a.k steps, stores the owned part to
+// (Edst, Sdst) (the Esrc/Ssrc/Edst/Sdst fields of `a` are not used).  A region has NW * 16
+// rows.  With ty == L it spans the full height (L == NW * 16, rows wrap);
+// otherwise regions overlap by hy rows (a multiple of 16) above and below.
+// Returns, valid in thread 0: x = anyon bits of the owned part (bit 0 at the
+// pass start, bit j after step j), y = winding bits of the correction links
+// the pass flipped there.
 template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
+__device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sample, int t0, const uint4 *Esrc,
+                                             const uint2 *Ssrc, uint4 *Edst, uint2 *Sdst) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint4 *BND = reinterpret_cast<uint4 *>(smem);                   // [2][NW*2*64]
   uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * NW * 2 * 64);  // [NW*64]
@@ -231,15 +237,12 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   const int L = a.L;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (scalar)
-  const int sample = a.active[blockIdx.y];
-  if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
-  const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
   const int ks = min(a.k, a.T_max - t0);  // steps of this sample in this pass
   if (threadIdx.x < 16) AW[threadIdx.x] = 0u;
   if (threadIdx.x == 0) red[0] = 0u;
 
   const bool wrapY = a.ty == L;
-  const int tix = blockIdx.x % a.ntx, tiy = blockIdx.x / a.ntx;
+  const int tix = tile % a.ntx, tiy = tile / a.ntx;
   const int wdn = w == 0 ? (wrapY ? NW - 1 : 0) : w - 1;
   const int wup = w == NW - 1 ? (wrapY ? 0 : NW - 1) : w + 1;
   // global column of this lane's first column, global row of the wave's first row
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
 #pragma unroll
     for (int h = 0; h < H; ++h) b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
   } else {
-    const uint4 *E = a.Esrc + (size_t)sample * L * half_row;
+    const uint4 *E = Esrc + (size_t)sample * L * half_row;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const uint4 e = E[(size_t)(gy + h) * half_row + (gx >> 1)];
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
     }
   }
   {
-    const uint2 sv = a.Ssrc[sidx];
+    const uint2 sv = Ssrc[sidx];
     b.s0 = sv.x;
     b.s1 = sv.y;
   }
@@ -312,21 +315,132 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   }
 
   if (own && a.write_state) {
-    uint4 *E = a.Edst + (size_t)sample * L * half_row;
+    uint4 *E = Edst + (size_t)sample * L * half_row;
 #pragma unroll
     for (int h = 0; h < H; ++h)
       if ((own_rows >> h) & 1u)
         E[(size_t)(gy + h) * half_row + (gx >> 1)] = make_uint4(b.P0[h], b.Q0[h], b.P1[h], b.Q1[h]);
     // hy and ty are multiples of 16, so an owned strip is always whole
-    a.Sdst[sidx] = make_uint2(b.s0, b.s1);
+    Sdst[sidx] = make_uint2(b.s0, b.s1);
   }
   if (wind) atomicXor(&red[0], wind);
   __syncthreads();
   if (threadIdx.x == 0)
     for (int st = 0; st < ks; ++st) bits |= AW[st] ? 2u << st : 0u;
+  return make_uint2(bits, red[0]);
+}
+
+// One pass over the samples in a.active: grid (tiles, samples).
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
+  const int sample = a.active[blockIdx.y];
+  if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
+  const uint2 r = band_region<NW>(a, blockIdx.x, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
   if (threadIdx.x == 0) {
-    if (bits) atomicOr(&a.alive[sample], bits);
-    if (red[0]) atomicXor(&a.wind[sample], red[0]);
+    if (r.x) atomicOr(&a.alive[sample], r.x);
+    if (r.y) atomicXor(&a.wind[sample], r.y);
+  }
+}
+
+// One pass over survivors whose number is only known on the device
+// (*count): (sample, tile) tasks in a grid-stride loop, each as one k_band
+// workgroup.  Workgroups never wait for each other.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_band_grid(BandArgs a, const int *count, int ntiles) {
+  if (a.zero_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  const int64_t ntask = (int64_t)(*count) * ntiles;
+  for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+    __syncthreads();  // the LDS slots of the previous task are no longer read
+    const int i = (int)(task / ntiles), tile = (int)(task % ntiles);
+    const int sample = a.active[i];
+    const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
+    const uint2 r = band_region<NW>(a, tile, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
+    if (threadIdx.x == 0) {
+      if (r.x) atomicOr(&a.alive[sample], r.x);
+      if (r.y) atomicXor(&a.wind[sample], r.y);
+    }
+  }
+}
+
+// Later passes of the band path, driven on the device.  Each workgroup takes
+// the next surviving sample from `list` and runs its passes -- every tile of
+// a pass one after another, then the bookkeeping of k_finalize for that
+// sample -- until it is decoded or reaches T_max.  Workgroups share nothing
+// but the atomic list head and never wait for each other; every one exits
+// once the list is used up.
+struct TailArgs {
+  BandArgs a;  // tile geometry of a pass, k, T_max, wind
+  int ntiles;
+  int cur;     // buffer holding the survivors' state after the first pass
+  uint4 *E[2];
+  uint2 *S[2];
+  const int32_t *list;  // survivors of the first pass
+  const int *count;     // their number
+  int *head;            // next list entry to take (zero before the launch)
+  int32_t *t_done;
+  int32_t *T_dec;
+  uint8_t *status;
+};
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
+  __shared__ int s_take, s_more;
+  __shared__ uint32_t s_bits, s_wind;
+  const BandArgs &a = ta.a;
+  const int nlist = *ta.count;
+  for (;;) {
+    __syncthreads();  // s_take of the previous sample has been read
+    if (threadIdx.x == 0) s_take = atomicAdd(ta.head, 1);
+    __syncthreads();
+    const int i = __builtin_amdgcn_readfirstlane(s_take);
+    if (i >= nlist) return;
+    const int s = ta.list[i];
+    int c = ta.cur;
+    int t0 = __builtin_amdgcn_readfirstlane(ta.t_done[s]);
+    for (;;) {
+      const int ks = min(a.k, a.T_max - t0);  // >= 1: a survivor is below T_max
+      if (threadIdx.x == 0) {
+        s_bits = 1u;  // the sample held anyons when the pass started
+        s_wind = 0u;
+      }
+      for (int tile = 0; tile < ta.ntiles; ++tile) {
+        __syncthreads();  // the LDS slots of the previous tile are no longer read
+        const uint2 r = band_region<NW>(a, tile, s, t0, ta.E[c], ta.S[c], ta.E[c ^ 1], ta.S[c ^ 1]);
+        if (threadIdx.x == 0) {
+          s_bits |= r.x;
+          s_wind ^= r.y;
+        }
+      }
+      // the state this pass stored is read by other waves in the next pass
+      __threadfence();
+      if (threadIdx.x == 0) {
+        const uint32_t bits = s_bits;
+        int td = -1;
+        for (int j = 0; j <= ks; ++j)
+          if (!((bits >> j) & 1u)) {
+            td = t0 + j;
+            break;
+          }
+        if (s_wind) a.wind[s] ^= s_wind;  // only this workgroup holds sample s
+        ta.t_done[s] = t0 + ks;
+        int more = 0;
+        if (td >= 0) {
+          ta.T_dec[s] = td;
+          ta.status[s] = 1;
+        } else if (t0 + ks >= a.T_max) {
+          ta.T_dec[s] = a.T_max;
+          ta.status[s] = (uint8_t)(2 | ((c ^ 1) << 2));
+        } else {
+          more = 1;
+        }
+        s_more = more;
+      }
+      __syncthreads();
+      if (!s_more) break;
+      t0 += ks;
+      c ^= 1;
+    }
   }
 }
 
@@ -410,15 +524,16 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
 }
 
 // Per-pass bookkeeping: T_dec from the per-step bits, compaction of the
-// samples that still hold anyons.  status: 0 running, 1 decoded, 2 timeout;
+// samples that still hold anyons.  The pass covered active[0 .. nact) or, if
+// nact_dev is set, active[0 .. *nact_dev) (nact is then an upper bound).  status: 0 running, 1 decoded, 2 timeout;
 // bit 2 of a timeout: the state buffer (0/1) that holds its final syndrome
 // (samples of first-pass groups of different depth time out in different
 // passes).  `dst` is the buffer this pass wrote.
-__global__ void k_finalize(int k, int T_max, int dst, const int32_t *active, int nact, int32_t *t_done,
-                           uint32_t *alive, int32_t *T_dec, uint8_t *status, int32_t *next,
+__global__ void k_finalize(int k, int T_max, int dst, const int32_t *active, int nact, const int *nact_dev,
+                           int32_t *t_done, uint32_t *alive, int32_t *T_dec, uint8_t *status, int32_t *next,
                            int *next_count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nact) return;
+  if (i >= (nact_dev != nullptr ? *nact_dev : nact)) return;
   const int s = active[i];
   const int t0 = t_done[s];
   const int ks = min(k, T_max - t0);
@@ -443,9 +558,10 @@ __global__ void k_finalize(int k, int T_max, int dst, const int32_t *active, int
 }
 
 __global__ void k_tile_init(int64_t n, uint32_t *alive, uint32_t *wind, uint8_t *status, int32_t *t_done,
-                            int32_t *active) {
+                            int32_t *active, int *tail_head) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (i == 0) *tail_head = 0;
   alive[i] = 0u;
   wind[i] = 0u;
   status[i] = 0;
@@ -593,7 +709,7 @@ struct BandWorkspace {
   uint8_t *status;
   int32_t *t_done;
   int32_t *active[2];
-  int *count;  // [2]
+  int *count;  // [3]: survivors after passes into buffer 0 / 1; list head of the device-driven passes
   size_t bytes;
 };
 
@@ -615,7 +731,7 @@ BandWorkspace band_layout(int L, int64_t n, void *base) {
   w.status = (uint8_t *)take((size_t)n);
   w.t_done = (int32_t *)take((size_t)n * 4);
   for (int b = 0; b < 2; ++b) w.active[b] = (int32_t *)take((size_t)n * 4);
-  w.count = (int *)take(2 * sizeof(int));
+  w.count = (int *)take(3 * sizeof(int));
   w.bytes = off;
   return w;
 }
@@ -626,6 +742,7 @@ BandWorkspace band_layout(int L, int64_t n, void *base) {
 struct BandSchedule {
   int k_first = 4;
   int k_next = 2;
+  int driver = MPD_BAND_DRIVER_AUTO;
 };
 std::mutex g_sched_mu;
 BandSchedule g_sched_default;
@@ -662,7 +779,7 @@ NoiseShape noise_shape(int L) {
 int band_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, const BandWorkspace &w,
                uint8_t *d_counts, hipStream_t stream) {
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
-                     w.status, w.t_done, w.active[0]);
+                     w.status, w.t_done, w.active[0], &w.count[2]);
   HIP_TRY(hipGetLastError());
   const NoiseShape g = noise_shape(L);
   ProfScope ps("k_band_noise", stream);
@@ -695,24 +812,17 @@ int later_pass_k(int L, int nact) {
   return (kn < K_SMALL && small_pass(L, kn, nact)) ? K_SMALL : kn;
 }
 
-int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *active, int nact, int cur, bool zero,
-              int32_t *d_T_dec, hipStream_t stream) {
-  BandArgs ba;
+// Tiles of a pass of k steps in regions of ry rows: a halo of 4k columns and
+// of 4k rows rounded up to whole 16-row strips (none when one region spans
+// the height).  Fills the geometry fields of `ba`; returns the tiles along y.
+int tile_geometry(int L, int k, int ry, BandArgs &ba) {
   ba.L = L;
   ba.write_state = 1;
   ba.k = k;
-  ba.T_max = T_max;
-  ba.t_done = w.t_done;
   ba.hx = 4 * k;
   ba.tx = BAND_RX - 2 * ba.hx;
   ba.ntx = (L + ba.tx - 1) / ba.tx;
-  const int hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;  // row halo of 4k in whole 16-row strips
-  // Full-size regions (16 waves, 256 rows) unless their grid would leave
-  // compute units idle: then 4-wave regions of 64 rows, which need more
-  // (overlapping) tiles but take about a quarter of the time per step.
-  const int ry4 = BAND_NW_SMALL * BAND_H;
-  const bool small = small_pass(L, k, nact) && ry4 - 2 * hy >= TILE_H;
-  const int ry = small ? ry4 : BAND_RY;
+  const int hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
   if (L == ry) {
     ba.hy = 0;
     ba.ty = L;
@@ -720,7 +830,21 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
     ba.hy = hy;
     ba.ty = ry - 2 * hy;
   }
-  const int nty = (L + ba.ty - 1) / ba.ty;
+  return (L + ba.ty - 1) / ba.ty;
+}
+
+int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *active, int nact, int cur, bool zero,
+              int32_t *d_T_dec, hipStream_t stream) {
+  BandArgs ba;
+  // Full-size regions (16 waves, 256 rows) unless their grid would leave
+  // compute units idle: then 4-wave regions of 64 rows, which need more
+  // (overlapping) tiles but take about a quarter of the time per step.
+  const int hy = (4 * k + TILE_H - 1) / TILE_H * TILE_H;
+  const int ry4 = BAND_NW_SMALL * BAND_H;
+  const bool small = small_pass(L, k, nact) && ry4 - 2 * hy >= TILE_H;
+  const int nty = tile_geometry(L, k, small ? ry4 : BAND_RY, ba);
+  ba.T_max = T_max;
+  ba.t_done = w.t_done;
   ba.active = active;
   ba.Esrc = w.E[cur];
   ba.Ssrc = w.S[cur];
@@ -740,7 +864,8 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   }
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, cur ^ 1, active,
-                     nact, w.t_done, w.alive, d_T_dec, w.status, w.active[cur ^ 1], &w.count[cur ^ 1]);
+                     nact, (const int *)nullptr, w.t_done, w.alive, d_T_dec, w.status, w.active[cur ^ 1],
+                     &w.count[cur ^ 1]);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -784,10 +909,90 @@ int *pinned_counts(int need) {
   return buf;
 }
 
-// Runs the passes of several band-path batches in lockstep: the first passes
-// of every batch, then rounds of one survivor-count readback per batch (one
-// host wait per round) and one pass for each batch with survivors.  Batches
-// on different streams overlap on the device.
+// Later passes of a batch on the device, with no host wait: DEVICE_GRID_PASSES
+// passes over all survivors at once (k_band_grid, tile-parallel, the
+// survivor count read on the device), then one launch of k_band_tail for the
+// samples still left (one workgroup per sample), then the export.  Full-size
+// regions and the schedule's k_next steps per pass throughout.
+constexpr int DEVICE_GRID_PASSES = 3;
+int band_tail(BandRun &r, int64_t first_count) {
+  const int k = min(schedule_for(r.L).k_next, r.T_max > 0 ? r.T_max : 1);
+  BandArgs ba;
+  const int nty = tile_geometry(r.L, k, BAND_RY, ba);
+  const int ntiles = ba.ntx * nty;
+  ba.T_max = r.T_max;
+  ba.t_done = r.w.t_done;
+  ba.alive = r.w.alive;
+  ba.wind = r.w.wind;
+  int cur = 1;  // the first passes wrote buffer 1 and listed their survivors in active[1]
+  for (int pass = 0; pass < DEVICE_GRID_PASSES && first_count > 0; ++pass) {
+    ba.active = r.w.active[cur];
+    ba.Esrc = r.w.E[cur];
+    ba.Ssrc = r.w.S[cur];
+    ba.Edst = r.w.E[cur ^ 1];
+    ba.Sdst = r.w.S[cur ^ 1];
+    ba.zero_count = &r.w.count[cur ^ 1];
+    const int64_t grid = std::min<int64_t>(first_count * ntiles, cu_count());
+    {
+      ProfScope ps("k_band_grid", r.stream);
+      hipLaunchKernelGGL(k_band_grid<BAND_NW>, dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
+                         r.stream, ba, (const int *)&r.w.count[cur], ntiles);
+    }
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((first_count + 255) / 256)), dim3(256), 0, r.stream, k, r.T_max,
+                       cur ^ 1, r.w.active[cur], (int)first_count, (const int *)&r.w.count[cur], r.w.t_done,
+                       r.w.alive, r.T_dec, r.w.status, r.w.active[cur ^ 1], &r.w.count[cur ^ 1]);
+    HIP_TRY(hipGetLastError());
+    cur ^= 1;
+  }
+  TailArgs ta;
+  ta.a = ba;
+  ta.a.active = nullptr;
+  ta.a.zero_count = nullptr;
+  ta.ntiles = ntiles;
+  ta.cur = cur;
+  for (int b = 0; b < 2; ++b) {
+    ta.E[b] = r.w.E[b];
+    ta.S[b] = r.w.S[b];
+  }
+  ta.list = r.w.active[cur];
+  ta.count = &r.w.count[cur];
+  ta.head = &r.w.count[2];
+  ta.t_done = r.w.t_done;
+  ta.T_dec = r.T_dec;
+  ta.status = r.w.status;
+  const int64_t grid = std::min<int64_t>(first_count, cu_count());
+  if (grid > 0) {
+    ProfScope ps("k_band_tail", r.stream);
+    hipLaunchKernelGGL(k_band_tail<BAND_NW>, dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW), r.stream,
+                       ta);
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_band_export, dim3((unsigned)r.n), dim3(256), 0, r.stream, r.L, r.n, r.w.status, r.w.wind,
+                     r.w.S[0], r.w.S[1], r.flags, r.syn);
+  HIP_TRY(hipGetLastError());
+  r.done = true;
+  return MPD_OK;
+}
+
+// Whether the later passes of a batch run on the device (band_tail) or from
+// the host (a survivor-count readback before every pass).  A stream being
+// captured into a graph always takes the device: a graph holds no host waits.
+bool device_driven(const BandRun &r, int64_t first_count) {
+  const int mode = schedule_for(r.L).driver;
+  if (mode == MPD_BAND_DRIVER_DEVICE) return true;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(r.stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return true;
+  if (mode == MPD_BAND_DRIVER_HOST) return false;
+  (void)first_count;
+  return false;
+}
+
+// Runs the passes of several band-path batches: the first passes of every
+// batch, then, for the batches driven from the host, rounds of one
+// survivor-count readback per batch (one host wait per round) and one pass
+// for each batch with survivors; batches driven on the device finish with
+// one launch.  Batches on different streams overlap on the device.
 int band_passes(BandRun *runs, int nr) {
   for (int i = 0; i < nr; ++i) {
     BandRun &r = runs[i];
@@ -801,7 +1006,16 @@ int band_passes(BandRun *runs, int nr) {
     }
     r.cur = 1;
     r.done = false;
+    int64_t first = 0;
+    for (int b = 0; b < r.fp.nb; ++b) first += r.fp.count[b];
+    if (device_driven(r, first)) {
+      const int rc = band_tail(r, first);
+      if (rc != MPD_OK) return rc;
+    }
   }
+  bool pending = false;
+  for (int i = 0; i < nr; ++i) pending = pending || !runs[i].done;
+  if (!pending) return MPD_OK;
   int *hc = pinned_counts(nr);
   if (hc == nullptr) return fail_with(MPD_ERR_HIP, "could not allocate pinned host memory for the pass counters");
   for (;;) {
@@ -1142,16 +1356,42 @@ int mpd_set_band_schedule(int L, int k_first, int k_next) {
   // the halo 4k must leave owned columns in a 128-column region
   if (k_first < 1 || k_next < 1 || 4 * k_first >= BAND_RX / 2 || 4 * k_next >= BAND_RX / 2)
     return fail_with(MPD_ERR_TMAX, "steps per pass must be in [1, 15]");
-  BandSchedule b;
-  b.k_first = k_first;
-  b.k_next = k_next;
   std::lock_guard<std::mutex> lk(g_sched_mu);
   if (L == 0) {
-    g_sched_default = b;
+    g_sched_default.k_first = k_first;
+    g_sched_default.k_next = k_next;
     g_sched_by_L.clear();
   } else {
+    auto it = g_sched_by_L.find(L);
+    BandSchedule b = it == g_sched_by_L.end() ? g_sched_default : it->second;
+    b.k_first = k_first;
+    b.k_next = k_next;
     g_sched_by_L[L] = b;
   }
+  return MPD_OK;
+}
+
+int mpd_set_band_driver(int L, int driver) {
+  g_last_error.clear();
+  if (driver != MPD_BAND_DRIVER_AUTO && driver != MPD_BAND_DRIVER_HOST && driver != MPD_BAND_DRIVER_DEVICE)
+    return fail_with(MPD_ERR_N, "driver %d: use MPD_BAND_DRIVER_AUTO, _HOST or _DEVICE", driver);
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  if (L == 0) {
+    g_sched_default.driver = driver;
+    for (auto &kv : g_sched_by_L) kv.second.driver = driver;
+  } else {
+    auto it = g_sched_by_L.find(L);
+    BandSchedule b = it == g_sched_by_L.end() ? g_sched_default : it->second;
+    b.driver = driver;
+    g_sched_by_L[L] = b;
+  }
+  return MPD_OK;
+}
+
+int mpd_get_band_driver(int L, int *driver) {
+  g_last_error.clear();
+  if (driver == nullptr) return fail_with(MPD_ERR_PTR, "NULL output");
+  *driver = schedule_for(L).driver;
   return MPD_OK;
 }
 
@@ -1184,29 +1424,31 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
   float best = 1e30f;
   BandSchedule pick = saved;
   int rc = MPD_OK;
-  for (int kf = 2; kf <= 6 && rc == MPD_OK; ++kf)
-    for (int kn = 1; kn <= 4 && rc == MPD_OK; ++kn) {
-      {
-        std::lock_guard<std::mutex> lk(g_sched_mu);
-        g_sched_by_L[L] = BandSchedule{kf, kn};
+  for (int drv = MPD_BAND_DRIVER_HOST; drv <= MPD_BAND_DRIVER_DEVICE && rc == MPD_OK; ++drv) {
+    for (int kf = 2; kf <= 6 && rc == MPD_OK; ++kf)
+      for (int kn = 1; kn <= 4 && rc == MPD_OK; ++kn) {
+        {
+          std::lock_guard<std::mutex> lk(g_sched_mu);
+          g_sched_by_L[L] = BandSchedule{kf, kn, drv};
+        }
+        // warm-up run, then a timed run
+        rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
+        if (rc) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail_with(MPD_ERR_HIP, "event record"); break; }
+        rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
+        if (rc) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail_with(MPD_ERR_HIP, "event timing");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          pick = BandSchedule{kf, kn, drv};
+        }
       }
-      // warm-up run, then a timed run
-      rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
-      if (rc) break;
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail_with(MPD_ERR_HIP, "event record"); break; }
-      rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
-      if (rc) break;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        rc = fail_with(MPD_ERR_HIP, "event timing");
-        break;
-      }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        pick = BandSchedule{kf, kn};
-      }
-    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   {

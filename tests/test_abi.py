@@ -144,6 +144,34 @@ def test_mixed_workspace_is_per_band_class(lib):
     assert total >= lib.mpd_workspace_bytes(256, 4) + lib.mpd_workspace_bytes(256, 2)
 
 
+def test_band_driver_setting(lib):
+    """Driver of the band path's later passes: default auto, per-L settings
+    kept by mpd_set_band_schedule, L = 0 applying to every L, bad values and
+    NULL outputs rejected."""
+    d = ctypes.c_int(-1)
+    get = lambda L: (lib.mpd_get_band_driver(L, ctypes.byref(d)), d.value)[1]
+    try:
+        assert get(0) == 0 and get(512) == 0
+        assert lib.mpd_set_band_driver(0, 3) == -7 and len(lib.mpd_last_error()) > 0
+        assert lib.mpd_set_band_driver(0, -1) == -7
+        assert lib.mpd_get_band_driver(0, None) == -4
+        assert lib.mpd_set_band_driver(512, 2) == 0
+        assert get(512) == 2 and get(256) == 0
+        assert lib.mpd_set_band_schedule(512, 3, 3) == 0   # keeps the driver of L = 512
+        assert get(512) == 2
+        kf, kn = ctypes.c_int(0), ctypes.c_int(0)
+        assert lib.mpd_get_band_schedule(512, ctypes.byref(kf), ctypes.byref(kn)) == 0 and (kf.value, kn.value) == (3, 3)
+        assert lib.mpd_set_band_driver(0, 1) == 0           # default and every per-L setting
+        assert get(512) == 1 and get(0) == 1 and get(256) == 1
+        assert lib.mpd_set_band_schedule(0, 4, 2) == 0      # forgets per-L settings
+        assert get(512) == 1
+        assert lib.mpd_get_band_schedule(512, ctypes.byref(kf), ctypes.byref(kn)) == 0 and (kf.value, kn.value) == (4, 2)
+    finally:
+        lib.mpd_set_band_driver(0, 0)
+        lib.mpd_set_band_schedule(0, 4, 2)
+    assert get(0) == 0
+
+
 @pytest.mark.parametrize("stmt", ["from paper_2506_03266_amd import binding, sweep, learned",
                                   "import paper_2506_03266_amd as m; m.sweep.SWEEP_CONFIG; m.binding.syndrome_words(8)"])
 def test_package_submodules_load_lazily(stmt):
