@@ -52,6 +52,18 @@
  *       index; word 2(i&1) drives the x-link and word 2(i&1)+1 the y-link of
  *       site i; a link flips iff the word is below floor(p * 2^32).
  *
+ * Limited classical memory (Sec. 5.3, the corollary on thresholds with
+ * limited memory), an optional variant of the rule:
+ *   R17 with a finite m_max, registers take values in {0, ..., m_max}: an
+ *       update whose value would exceed m_max yields 0 (the message
+ *       disappears).  m_max = 0 here means no truncation (R8).
+ *   R18 with u > 0, at every decoder step t (counted from 1) with t a
+ *       multiple of u, each anyon moves in a random direction instead of
+ *       following its messages: Philox4x32-10 keyed by the sample's seed,
+ *       counter (i >> 1, t, 0x4D4F5645, 0); word (i & 1) of site i, taken
+ *       mod 4, gives +x, -x, +y, -y for 0..3.  Moves flip links through the
+ *       same OR rule.  u = 0 means no random moves.
+ *
  * Site index i = y*L + x.  The x-link of site (x,y) joins (x,y) and
  * (x+1,y); its y-link joins (x,y) and (x,y+1) (indices mod L).
  * Register order in every array: d = 0: +x, 1: -x, 2: +y, 3: -y, i.e.
@@ -128,6 +140,10 @@ int orc_noise(int L, double p, uint64_t seed, uint8_t *ex, uint8_t *ey) {
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int L, v;
+  int m_max;          /* R17: 0 = no truncation */
+  int u;              /* R18: 0 = no random moves */
+  uint32_t key[2];    /* the sample's seed, for the random moves */
+  int t;              /* the decoder step being applied (from 1) */
   int64_t n;          /* number of sites L*L */
   int32_t *m[4];      /* m^{sa}_r, registers after the last update */
   int32_t *mnew[4];   /* scratch for the synchronous update */
@@ -213,6 +229,7 @@ static void orc_message_update(orc_state *st) {
         if (anyon) out = 1;
         else if (minnz == 0) out = 0;
         else out = minnz + 1;
+        if (st->m_max > 0 && out > st->m_max) out = 0;   /* R17 */
         st->mnew[d][y * L + x] = out;
       }
   }
@@ -238,12 +255,28 @@ static int orc_or(int x, int y) { return (x == 1 || y == 1) ? 1 : 0; }
  * registers (ties broken by m + s a / (D+1), eq. (degbreak)), then the link
  * exponent sigma_r f^a_r OR sigma_{r+a}(-f^a_{r+a}) of eq. (ddfeedback).
  * Returns the number of anyons after the step. */
+/* Direction of the random move of site i at step t (R18): 0 +x, 1 -x,
+ * 2 +y, 3 -y. */
+static int orc_random_direction(const orc_state *st, int64_t i) {
+  uint32_t ctr[4] = {(uint32_t)(i >> 1), (uint32_t)st->t, 0x4D4F5645u, 0u};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, st->key, w);
+  return (int)(w[i & 1] & 3u);
+}
+
 static int64_t orc_feedback(orc_state *st) {
   int L = st->L;
   int64_t n = st->n;
+  const int random_step = st->u > 0 && st->t % st->u == 0;
   for (int64_t i = 0; i < n; ++i) {
     st->fx[i] = 0; st->fy[i] = 0;
     if (st->sigma[i] != -1) continue;           /* R4 */
+    if (random_step) {                          /* R18 */
+      int d = orc_random_direction(st, i);
+      if (d < 2) st->fx[i] = (int8_t)(d == 0 ? +1 : -1);
+      else st->fy[i] = (int8_t)(d == 2 ? +1 : -1);
+      continue;
+    }
     int best = -1;
     int32_t bestm = 0, bestoff = 0;
     for (int d = 0; d < 4; ++d) {
@@ -315,17 +348,25 @@ static void orc_pack_sigma(const orc_state *st, uint32_t *words) {
  *   m_out     [4][L*L] int32 registers at the end,
  *   cx_out, cy_out  [L*L] correction chain,
  *   wind_out  [4] = (Wx_E, Wy_E, Wx_C, Wy_C). */
-int orc_decode_errors(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_max,
-                      int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words,
-                      int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out, int32_t *wind_out) {
-  if (L < 3 || v < 1 || T_max < 0) return ORC_EBADARG;
+/* The same with the limited-memory variant: m_max (R17) and u (R18, random
+ * moves keyed by `seed`). */
+int orc_decode_errors_rule(int L, int v, int m_max, int u, uint64_t seed, const uint8_t *ex,
+                           const uint8_t *ey, int T_max, int32_t *T_dec, uint8_t *flags,
+                           uint32_t *sigma_words, int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out,
+                           int32_t *wind_out) {
+  if (L < 3 || v < 1 || T_max < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   orc_state st;
   if (orc_alloc(&st, L, v) != ORC_OK) return ORC_ENOMEM;
+  st.m_max = m_max;
+  st.u = u;
+  st.key[0] = (uint32_t)(seed & 0xffffffffu);
+  st.key[1] = (uint32_t)(seed >> 32);
   orc_syndrome(&st, ex, ey);
   int64_t anyons = orc_count_anyons(&st);
   int t = 0;
   while (anyons > 0 && t < T_max) {
     for (int j = 0; j < v; ++j) orc_message_update(&st);
+    st.t = t + 1;
     anyons = orc_feedback(&st);
     ++t;
   }
@@ -346,22 +387,34 @@ int orc_decode_errors(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_
   return ORC_OK;
 }
 
+int orc_decode_errors(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_max,
+                      int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words,
+                      int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out, int32_t *wind_out) {
+  return orc_decode_errors_rule(L, v, 0, 0, 0, ex, ey, T_max, T_dec, flags, sigma_words, m_out, cx_out,
+                                cy_out, wind_out);
+}
+
 /* Run exactly t_exact decoder steps (no early exit) from the noise pattern,
  * starting from m = 0.  Outputs the registers, the syndrome (+1/-1 bytes)
  * and the correction chain after the last step.  With record != NULL, the
  * anyon indicator after every step k = 0..t_exact is written to
  * record[k*L*L + i] (k = 0 is the initial syndrome). */
-int orc_run_steps(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exact,
-                  int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out, uint8_t *cy_out,
-                  uint8_t *record) {
-  if (L < 3 || v < 1 || t_exact < 0) return ORC_EBADARG;
+int orc_run_steps_rule(int L, int v, int m_max, int u, uint64_t seed, const uint8_t *ex,
+                       const uint8_t *ey, int t_exact, int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out,
+                       uint8_t *cy_out, uint8_t *record) {
+  if (L < 3 || v < 1 || t_exact < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   orc_state st;
   if (orc_alloc(&st, L, v) != ORC_OK) return ORC_ENOMEM;
+  st.m_max = m_max;
+  st.u = u;
+  st.key[0] = (uint32_t)(seed & 0xffffffffu);
+  st.key[1] = (uint32_t)(seed >> 32);
   orc_syndrome(&st, ex, ey);
   if (record)
     for (int64_t i = 0; i < st.n; ++i) record[i] = st.sigma[i] == -1;
   for (int t = 0; t < t_exact; ++t) {
     for (int j = 0; j < v; ++j) orc_message_update(&st);
+    st.t = t + 1;
     orc_feedback(&st);
     if (record)
       for (int64_t i = 0; i < st.n; ++i)
@@ -376,13 +429,19 @@ int orc_run_steps(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exac
   return ORC_OK;
 }
 
+int orc_run_steps(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exact,
+                  int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out, uint8_t *cy_out,
+                  uint8_t *record) {
+  return orc_run_steps_rule(L, v, 0, 0, 0, ex, ey, t_exact, m_out, sigma_out, cx_out, cy_out, record);
+}
+
 /* Noise + decode for a batch of seeds; samples are spread over nthreads
  * OpenMP threads (nthreads <= 0: the OpenMP default).  Returns the number
  * of threads actually used through *threads_used. */
-int orc_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds,
-                     int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
-                     uint32_t *sigma_words, int *threads_used) {
-  if (L < 3 || v < 1 || T_max < 0 || n < 0) return ORC_EBADARG;
+int orc_decode_seeds_rule(int L, int v, int m_max, int u, const double *p, int p_stride,
+                          const uint64_t *seeds, int64_t n, int T_max, int nthreads, int32_t *T_dec,
+                          uint8_t *flags, uint32_t *sigma_words, int *threads_used) {
+  if (L < 3 || v < 1 || T_max < 0 || n < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   int64_t nsite = (int64_t)L * L;
   int64_t nw = (nsite + 31) / 32;
   int err = ORC_OK;
@@ -405,8 +464,8 @@ int orc_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t
     int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
     if (rc == ORC_OK) rc = orc_noise(L, p[p_stride ? k : 0], seeds[k], ex, ey);
     if (rc == ORC_OK)
-      rc = orc_decode_errors(L, v, ex, ey, T_max, &T_dec[k], &flags[k],
-                             sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+      rc = orc_decode_errors_rule(L, v, m_max, u, seeds[k], ex, ey, T_max, &T_dec[k], &flags[k],
+                                  sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
     if (rc != ORC_OK) {
 #pragma omp critical
       err = rc;
@@ -417,12 +476,21 @@ int orc_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t
   return err;
 }
 
+int orc_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds,
+                     int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
+                     uint32_t *sigma_words, int *threads_used) {
+  return orc_decode_seeds_rule(L, v, 0, 0, p, p_stride, seeds, n, T_max, nthreads, T_dec, flags,
+                               sigma_words, threads_used);
+}
+
 /* Decode a batch of explicit error chains given as link bits: link id
  * l = 2*i + dir (dir 0: x-link of site i, dir 1: y-link), bit l%32 of word
  * l/32, ceil(2*L*L/32) words per sample. */
-int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, int nthreads,
-                     int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words) {
-  if (L < 3 || v < 1 || T_max < 0 || n < 0) return ORC_EBADARG;
+int orc_decode_links_rule(int L, int v, int m_max, int u, const uint64_t *seeds, const uint32_t *links,
+                          int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
+                          uint32_t *sigma_words) {
+  if (L < 3 || v < 1 || T_max < 0 || n < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
+  if (u > 0 && seeds == NULL) return ORC_EBADARG;
   int64_t nsite = (int64_t)L * L;
   int64_t lw = (2 * nsite + 31) / 32, nw = (nsite + 31) / 32;
   int err = ORC_OK;
@@ -443,8 +511,8 @@ int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, 
         ex[i] = (uint8_t)((w[lx >> 5] >> (lx & 31)) & 1u);
         ey[i] = (uint8_t)((w[ly >> 5] >> (ly & 31)) & 1u);
       }
-      rc = orc_decode_errors(L, v, ex, ey, T_max, &T_dec[k], &flags[k],
-                             sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+      rc = orc_decode_errors_rule(L, v, m_max, u, seeds ? seeds[k] : 0, ex, ey, T_max, &T_dec[k], &flags[k],
+                                  sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
     }
     if (rc != ORC_OK) {
 #pragma omp critical
@@ -454,4 +522,9 @@ int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, 
     free(ey);
   }
   return err;
+}
+
+int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, int nthreads,
+                     int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words) {
+  return orc_decode_links_rule(L, v, 0, 0, NULL, links, n, T_max, nthreads, T_dec, flags, sigma_words);
 }

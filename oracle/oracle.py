@@ -58,6 +58,15 @@ def _load():
     lib.orc_decode_seeds.restype = ctypes.c_int
     lib.orc_decode_links.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int64, ctypes.c_int,
                                      ctypes.c_int, P, P, P]
+    I, U64 = ctypes.c_int, ctypes.c_uint64
+    lib.orc_decode_errors_rule.argtypes = [I, I, I, I, U64, P, P, I, P, P, P, P, P, P, P]
+    lib.orc_decode_errors_rule.restype = I
+    lib.orc_run_steps_rule.argtypes = [I, I, I, I, U64, P, P, I, P, P, P, P, P]
+    lib.orc_run_steps_rule.restype = I
+    lib.orc_decode_seeds_rule.argtypes = [I, I, I, I, P, I, P, ctypes.c_int64, I, I, P, P, P, P]
+    lib.orc_decode_seeds_rule.restype = I
+    lib.orc_decode_links_rule.argtypes = [I, I, I, I, P, P, ctypes.c_int64, I, I, P, P, P]
+    lib.orc_decode_links_rule.restype = I
     lib.orc_decode_links.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -105,11 +114,14 @@ def pack_bits(bits):
     return w.sum(axis=1).astype(np.uint32)
 
 
-def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = False):
+def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = False, m_max: int = 0,
+                  u: int = 0, seed: int = 0):
     """Decode one explicit error chain.
 
     Returns dict(T_dec, flags, sigma_words) and, with want_state, also
     m [4, L, L] int32, cx, cy [L, L] and wind (Wx_E, Wy_E, Wx_C, Wy_C).
+    m_max > 0 truncates messages (R17); u > 0 makes every u-th step a random
+    move keyed by `seed` (R18).
     """
     ex = np.ascontiguousarray(np.asarray(ex, dtype=np.uint8).reshape(-1))
     ey = np.ascontiguousarray(np.asarray(ey, dtype=np.uint8).reshape(-1))
@@ -121,8 +133,8 @@ def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = Fal
     cx = np.zeros(L * L, dtype=np.uint8) if want_state else None
     cy = np.zeros(L * L, dtype=np.uint8) if want_state else None
     wind = np.zeros(4, dtype=np.int32) if want_state else None
-    _check(_load().orc_decode_errors(L, v, _ptr(ex), _ptr(ey), int(T_max), _ptr(T), _ptr(fl),
-                                     _ptr(sw), _ptr(m), _ptr(cx), _ptr(cy), _ptr(wind)),
+    _check(_load().orc_decode_errors_rule(L, v, int(m_max), int(u), int(seed), _ptr(ex), _ptr(ey), int(T_max),
+                                          _ptr(T), _ptr(fl), _ptr(sw), _ptr(m), _ptr(cx), _ptr(cy), _ptr(wind)),
            "decode_errors")
     out = dict(T_dec=int(T[0]), flags=int(fl[0]), sigma_words=sw)
     if want_state:
@@ -131,7 +143,8 @@ def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = Fal
     return out
 
 
-def run_steps(L: int, ex, ey, t_exact: int, v: int = 3, record: bool = False):
+def run_steps(L: int, ex, ey, t_exact: int, v: int = 3, record: bool = False, m_max: int = 0, u: int = 0,
+              seed: int = 0):
     """Run exactly t_exact steps.  Returns (m [4,L,L], sigma [L,L] (+1/-1),
     (cx, cy), history) with history [t_exact+1, L, L] anyon indicators or None."""
     ex = np.ascontiguousarray(np.asarray(ex, dtype=np.uint8).reshape(-1))
@@ -141,14 +154,14 @@ def run_steps(L: int, ex, ey, t_exact: int, v: int = 3, record: bool = False):
     cx = np.zeros(L * L, dtype=np.uint8)
     cy = np.zeros(L * L, dtype=np.uint8)
     hist = np.zeros((t_exact + 1) * L * L, dtype=np.uint8) if record else None
-    _check(_load().orc_run_steps(L, v, _ptr(ex), _ptr(ey), int(t_exact), _ptr(m), _ptr(sig),
-                                 _ptr(cx), _ptr(cy), _ptr(hist)), "run_steps")
+    _check(_load().orc_run_steps_rule(L, v, int(m_max), int(u), int(seed), _ptr(ex), _ptr(ey), int(t_exact),
+                                      _ptr(m), _ptr(sig), _ptr(cx), _ptr(cy), _ptr(hist)), "run_steps")
     return (m.reshape(4, L, L), sig.reshape(L, L), (cx.reshape(L, L), cy.reshape(L, L)),
             None if hist is None else hist.reshape(t_exact + 1, L, L))
 
 
 def decode_seeds(L: int, p, seeds, T_max: int, v: int = 3, threads: int = 0,
-                 want_sigma: bool = True):
+                 want_sigma: bool = True, m_max: int = 0, u: int = 0):
     """Noise from each seed (one p, or one p per seed) and decode.
 
     Returns dict(T_dec int32[n], flags uint8[n], sigma_words uint32[n, W] or
@@ -165,9 +178,9 @@ def decode_seeds(L: int, p, seeds, T_max: int, v: int = 3, threads: int = 0,
     W = (L * L + 31) // 32
     sw = np.zeros((n, W), dtype=np.uint32) if want_sigma else None
     used = ctypes.c_int(0)
-    _check(_load().orc_decode_seeds(L, v, _ptr(pa), stride, _ptr(seeds), n, int(T_max),
-                                    int(threads), _ptr(T), _ptr(fl), _ptr(sw),
-                                    ctypes.byref(used)), "decode_seeds")
+    _check(_load().orc_decode_seeds_rule(L, v, int(m_max), int(u), _ptr(pa), stride, _ptr(seeds), n,
+                                         int(T_max), int(threads), _ptr(T), _ptr(fl), _ptr(sw),
+                                         ctypes.byref(used)), "decode_seeds")
     return dict(T_dec=T, flags=fl, sigma_words=sw, threads=int(used.value))
 
 
@@ -183,14 +196,18 @@ def links_from_chains(L: int, ex, ey):
     return np.stack([pack_bits(b) for b in bits]) if n else np.zeros((0, (2 * L * L + 31) // 32), np.uint32)
 
 
-def decode_links(L: int, links, T_max: int, v: int = 3, threads: int = 0):
-    """Decode explicit error chains given as packed link words [n, W]."""
+def decode_links(L: int, links, T_max: int, v: int = 3, threads: int = 0, m_max: int = 0, u: int = 0,
+                 seeds=None):
+    """Decode explicit error chains given as packed link words [n, W]; with
+    u > 0 the random moves of chain k are keyed by seeds[k]."""
     lw = (2 * L * L + 31) // 32
     links = np.ascontiguousarray(np.asarray(links, dtype=np.uint32).reshape(-1, lw))
     n = links.shape[0]
     T = np.zeros(n, dtype=np.int32)
     fl = np.zeros(n, dtype=np.uint8)
     sw = np.zeros((n, (L * L + 31) // 32), dtype=np.uint32)
-    _check(_load().orc_decode_links(L, v, _ptr(links), n, int(T_max), int(threads), _ptr(T),
-                                    _ptr(fl), _ptr(sw)), "decode_links")
+    sd = None if seeds is None else np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
+    assert sd is None or sd.size == n
+    _check(_load().orc_decode_links_rule(L, v, int(m_max), int(u), _ptr(sd), _ptr(links), n, int(T_max),
+                                         int(threads), _ptr(T), _ptr(fl), _ptr(sw)), "decode_links")
     return dict(T_dec=T, flags=fl, sigma_words=sw)
