@@ -272,9 +272,11 @@ static int64_t orc_feedback(orc_state *st) {
     st->fx[i] = 0; st->fy[i] = 0;
     if (st->sigma[i] != -1) continue;           /* R4 */
     if (random_step) {                          /* R18 */
+      /* The link exponent carries sigma_r f_r and sigma_r = -1 here, so an
+       * anyon moves along +a for f^a = -1 (as for a force from orc_force). */
       int d = orc_random_direction(st, i);
-      if (d < 2) st->fx[i] = (int8_t)(d == 0 ? +1 : -1);
-      else st->fy[i] = (int8_t)(d == 2 ? +1 : -1);
+      if (d < 2) st->fx[i] = (int8_t)(d == 0 ? -1 : +1);
+      else st->fy[i] = (int8_t)(d == 2 ? -1 : +1);
       continue;
     }
     int best = -1;

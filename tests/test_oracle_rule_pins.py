@@ -136,6 +136,27 @@ def test_random_directions_are_uniform(orc):
     assert chi2 < 37.7, cnt  # 15 degrees of freedom, 0.1% point
 
 
+def test_random_direction_table(orc):
+    """R18's table, a project convention (unpinned by the paper beyond
+    uniformity): word (i & 1) of Philox(key = seed, counter = (i >> 1, t,
+    0x4D4F5645, 0)), mod 4, moves the anyon of site i by +x, -x, +y, -y."""
+    L = 24
+    ex, ey = chains(L, [[4 + k, 10] for k in range(8)], [])
+    step = {0: (1, 0), 1: (-1, 0), 2: (0, 1), 3: (0, -1)}
+    for s in seeds(100, 2, 64):
+        s = int(s)
+        key = [s & 0xFFFFFFFF, s >> 32]
+        want = []
+        for x in (4, 12):
+            i = 10 * L + x
+            w = orc.philox4x32_10([i >> 1, 1, 0x4D4F5645, 0], key)
+            dx, dy = step[int(w[i & 1]) & 3]
+            want.append(((x + dx) % L, (10 + dy) % L))
+        _, sig, _, _ = orc.run_steps(L, ex, ey, 1, m_max=1, u=1, seed=s)
+        ys, xs = np.nonzero(sig == -1)
+        assert sorted(zip(xs.tolist(), ys.tolist())) == sorted(want)
+
+
 def test_adjacent_sites_draw_independent_directions(orc):
     """A single flipped x-link leaves anyons on two neighbouring sites (one
     site pair of the generator's counter).  With every step random, they
