@@ -78,6 +78,7 @@ extern "C" {
 #define MPD_ERR_WORKSPACE (-5) /* ws_bytes < mpd_workspace_bytes(...) */
 #define MPD_ERR_HIP (-6)       /* a HIP runtime call failed */
 #define MPD_ERR_N (-7)         /* n < 0 or too large */
+#define MPD_ERR_RULE (-8)      /* m_max < 0 or u < 0 */
 
 #define MPD_FLAG_FAIL 1u
 #define MPD_FLAG_TIMEOUT 2u
@@ -134,6 +135,32 @@ int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int3
  * Supported L: 3 <= L <= 128. */
 int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
+/* Limited classical memory (Sec. 5.3, the corollary on thresholds with
+ * limited memory; message values in {0, ..., m_max} as in Sec. 3.1).
+ *   m_max   > 0: an update whose message value would exceed m_max yields 0
+ *           (the message disappears); 0: no truncation
+ *   u       > 0: at every decoder step t (counted from 1) that is a multiple
+ *           of u, every anyon moves one link in a random direction instead of
+ *           following its messages (links flip through the same OR rule);
+ *           0: no random moves.  Directions: Philox4x32-10 keyed by the
+ *           sample's 64-bit seed, counter (i >> 1, t, 0x4D4F5645, 0), word
+ *           (i & 1) of site i = y*L + x, mod 4 -> +x, -x, +y, -y.
+ * With m_max = u = 0 each call equals its plain counterpart.  The seeds of
+ * mpd_decode_rule key both the noise and the random moves; the explicit-
+ * error forms take move seeds (may be NULL when u = 0).  MPD_ERR_RULE for
+ * m_max < 0 or u < 0; other arguments and errors as the plain calls.  Both
+ * band-path drivers support the variant; mixed and learned decodes use the
+ * plain rule. */
+int mpd_decode_rule(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int m_max, int u,
+                    int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace,
+                    size_t ws_bytes, void *stream);
+int mpd_decode_errors_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n,
+                           int T_max, int m_max, int u, int32_t *d_T_dec, uint8_t *d_flags,
+                           uint32_t *d_final_syndrome, void *stream);
+int mpd_run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n,
+                       int t_exact, int m_max, int u, int16_t *d_m_out, uint32_t *d_sigma_out,
+                       uint8_t *d_wind_out, void *stream);
 
 /* Temporal blocking of the band path (L >= 256): decoder steps run on chip per
  * pass over HBM, in the first pass (registers still empty) and in later

@@ -47,6 +47,12 @@ def lib():
     L.mpd_decode_errors.restype = I
     L.mpd_run_steps.argtypes = [I, P, I64, I, P, P, P, P]
     L.mpd_run_steps.restype = I
+    L.mpd_decode_rule.argtypes = [I, D, P, I64, I, I, I, P, P, P, P, SZ, P]
+    L.mpd_decode_rule.restype = I
+    L.mpd_decode_errors_rule.argtypes = [I, P, P, I64, I, I, I, P, P, P, P]
+    L.mpd_decode_errors_rule.restype = I
+    L.mpd_run_steps_rule.argtypes = [I, P, P, I64, I, I, I, P, P, P, P]
+    L.mpd_run_steps_rule.restype = I
     L.mpd_set_band_schedule.argtypes = [I, I, I]
     L.mpd_set_band_schedule.restype = I
     L.mpd_get_band_schedule.argtypes = [I, P, P]
@@ -151,36 +157,73 @@ def decode_batch(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool
     return T, F, S
 
 
-def decode_errors(L: int, links, T_max: int = 4096, want_syndrome: bool = True, stream=None):
-    """Decode explicit error patterns given as link words [n, link_words(L)]."""
-    dev = torch.device("cuda")
+def _links_tensor(L, links, dev):
     if not isinstance(links, torch.Tensor):
         links = torch.from_numpy(np.ascontiguousarray(np.asarray(links, dtype=np.uint32)).view(np.int32))
-    links = links.to(dev).contiguous().view(-1, link_words(L))
+    return links.to(dev).contiguous().view(-1, link_words(L))
+
+
+def decode_errors(L: int, links, T_max: int = 4096, want_syndrome: bool = True, stream=None, m_max: int = 0,
+                  u: int = 0, move_seeds=None):
+    """Decode explicit error patterns given as link words [n, link_words(L)].
+    m_max / u select the limited-memory variant (random moves keyed by
+    move_seeds, one per pattern)."""
+    dev = torch.device("cuda")
+    links = _links_tensor(L, links, dev)
     n = links.shape[0]
     T = torch.empty(n, dtype=torch.int32, device=dev)
     F = torch.empty(n, dtype=torch.uint8, device=dev)
     S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
-    ws = alloc_workspace(L, n)
-    rc = lib().mpd_decode_errors(L, _ptr(links), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws), ws.numel(),
-                                 _stream_ptr(stream))
-    _check(rc, "mpd_decode_errors")
+    if m_max == 0 and u == 0 and move_seeds is None:
+        ws = alloc_workspace(L, n)
+        rc = lib().mpd_decode_errors(L, _ptr(links), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws), ws.numel(),
+                                     _stream_ptr(stream))
+        _check(rc, "mpd_decode_errors")
+    else:
+        ms = None if move_seeds is None else _seeds_tensor(move_seeds, dev)
+        rc = lib().mpd_decode_errors_rule(L, _ptr(links), _ptr(ms), n, int(T_max), int(m_max), int(u), _ptr(T),
+                                          _ptr(F), _ptr(S), _stream_ptr(stream))
+        _check(rc, "mpd_decode_errors_rule")
     return T, F, S
 
 
-def run_steps(L: int, links, t_exact: int, stream=None):
+def run_steps(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int = 0, move_seeds=None):
     """Run exactly t_exact steps; returns (m int16[n,4,L,L], syndrome int32[n,W], wind uint8[n])."""
     dev = torch.device("cuda")
-    if not isinstance(links, torch.Tensor):
-        links = torch.from_numpy(np.ascontiguousarray(np.asarray(links, dtype=np.uint32)).view(np.int32))
-    links = links.to(dev).contiguous().view(-1, link_words(L))
+    links = _links_tensor(L, links, dev)
     n = links.shape[0]
     M = torch.empty((n, 4, L, L), dtype=torch.int16, device=dev)
     S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
     W = torch.empty(n, dtype=torch.uint8, device=dev)
-    rc = lib().mpd_run_steps(L, _ptr(links), n, int(t_exact), _ptr(M), _ptr(S), _ptr(W), _stream_ptr(stream))
-    _check(rc, "mpd_run_steps")
+    if m_max == 0 and u == 0 and move_seeds is None:
+        rc = lib().mpd_run_steps(L, _ptr(links), n, int(t_exact), _ptr(M), _ptr(S), _ptr(W), _stream_ptr(stream))
+        _check(rc, "mpd_run_steps")
+    else:
+        ms = None if move_seeds is None else _seeds_tensor(move_seeds, dev)
+        rc = lib().mpd_run_steps_rule(L, _ptr(links), _ptr(ms), n, int(t_exact), int(m_max), int(u), _ptr(M),
+                                      _ptr(S), _ptr(W), _stream_ptr(stream))
+        _check(rc, "mpd_run_steps_rule")
     return M, S, W
+
+
+def decode_rule(L: int, p: float, seeds, T_max: int = 4096, m_max: int = 0, u: int = 0, want_syndrome: bool = True,
+                workspace=None, out=None, stream=None):
+    """decode_batch with the limited-memory variant: messages truncated at
+    m_max (0: none), a random move of every anyon every u steps (0: none)."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    else:
+        T, F, S = out
+    ws = workspace if workspace is not None else alloc_workspace(L, n)
+    rc = lib().mpd_decode_rule(L, float(p), _ptr(s), n, int(T_max), int(m_max), int(u), _ptr(T), _ptr(F), _ptr(S),
+                               _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc, "mpd_decode_rule")
+    return T, F, S
 
 
 def profile(enable: bool):

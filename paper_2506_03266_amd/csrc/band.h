@@ -49,14 +49,16 @@ struct Moves {
 
 // Move decision of one site from its registers (see engine.h): the largest
 // emission time wins (smallest message), ties in the order -y, -x, +x, +y,
-// and no move if the opposite register on that axis ties.  Sets bit `bit`
-// of the mask of the chosen move; `anyon` gates it.
-__device__ __forceinline__ void decide_site(uint32_t P, uint32_t Q, bool anyon, uint32_t bit, Moves &mv) {
+// and no move if the opposite register on that axis ties.  Registers below
+// `ethr` (live_threshold) hold no live message.  Sets bit `bit` of the mask
+// of the chosen move; `anyon` gates it.
+__device__ __forceinline__ void decide_site(uint32_t P, uint32_t Q, bool anyon, uint32_t bit, uint32_t ethr,
+                                            Moves &mv) {
   const uint32_t T = pmax(P, Q);  // (max(+x, +y), max(-x, -y))
   const uint16_t M = max((uint16_t)T, (uint16_t)(T >> 16));
   const bool sx = (uint16_t)P == M, tx = (uint16_t)(P >> 16) == M;
   const bool sy = (uint16_t)Q == M, ty = (uint16_t)(Q >> 16) == M;
-  const bool ok = anyon && M != 0;
+  const bool ok = anyon && (uint32_t)M >= ethr;
   const bool go_py = ok && ty && !sy;
   const bool go_px = ok && !ty && tx && !sx;
   const bool go_mx = ok && !ty && !tx && sx;
@@ -106,7 +108,7 @@ __device__ __forceinline__ void band_fold(BandLane<H> &b, uint32_t ss, uint32_t 
 // flagged in `rows` are decided from the new values as each row completes.
 template <int H, bool DECIDE>
 __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, int wdn, int wup, int lane,
-                                             uint32_t rows, Moves &mv) {
+                                             uint32_t rows, uint32_t ethr, Moves &mv) {
   BND[(w * 2 + 0) * 64 + lane] = make_uint4(b.P0[0], b.Q0[0], b.P1[0], b.Q1[0]);
   BND[(w * 2 + 1) * 64 + lane] = make_uint4(b.P0[H - 1], b.Q0[H - 1], b.P1[H - 1], b.Q1[H - 1]);
   __syncthreads();
@@ -154,9 +156,27 @@ __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, 
     hq0c = hq0n;
     hq1c = hq1n;
     if (DECIDE && ((rows >> h) & 1u)) {  // wave-uniform: rows holding an anyon
-      decide_site(b.P0[h], b.Q0[h], (b.s0 >> h) & 1u, 1u << h, mv);
-      decide_site(b.P1[h], b.Q1[h], (b.s1 >> h) & 1u, 1u << (16 + h), mv);
+      decide_site(b.P0[h], b.Q0[h], (b.s0 >> h) & 1u, 1u << h, ethr, mv);
+      decide_site(b.P1[h], b.Q1[h], (b.s1 >> h) & 1u, 1u << (16 + h), ethr, mv);
     }
+  }
+}
+
+// Random moves of a random-move step t (limited-memory variant, see
+// engine.h) for the anyons in the rows flagged in `rows`: the lane's two
+// columns gx, gx + 1 (gx even) of row gy + h are the sites of generator
+// pair ((gy + h) L + gx) / 2.
+template <int H>
+__device__ __forceinline__ void band_random_moves(const BandLane<H> &b, uint32_t rows, int gx, int gy, int L,
+                                                  uint32_t t, uint32_t k0, uint32_t k1, Moves &mv) {
+  for (int h = 0; h < H; ++h) {
+    if (!((rows >> h) & 1u)) continue;
+    const uint2 d = random_dirs((uint32_t)(((gy + h) * L + gx) >> 1), t, k0, k1);
+    const uint32_t b0 = ((b.s0 >> h) & 1u) << h, b1 = ((b.s1 >> h) & 1u) << (16 + h);
+    mv.px |= (d.x == 0u ? b0 : 0u) | (d.y == 0u ? b1 : 0u);
+    mv.mx |= (d.x == 1u ? b0 : 0u) | (d.y == 1u ? b1 : 0u);
+    mv.py |= (d.x == 2u ? b0 : 0u) | (d.y == 2u ? b1 : 0u);
+    mv.my |= (d.x == 3u ? b0 : 0u) | (d.y == 3u ? b1 : 0u);
   }
 }
 

@@ -37,13 +37,14 @@ __device__ __forceinline__ uint32_t pmax3(uint32_t a, uint32_t b, uint32_t c) {
   return pmax(pmax(a, b), c);
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter (c0, c1, 0, 0).
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter (c0, c1, c2, 0).
 struct Words4 {
   uint32_t w0, w1, w2, w3;
 };
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t k0, uint32_t k1, uint32_t c1 = 0u) {
-  uint32_t c2 = 0u, c3 = 0u;
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t k0, uint32_t k1, uint32_t c1 = 0u,
+                                                uint32_t c2 = 0u) {
+  uint32_t c3 = 0u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32 -> 64-bit product each (v_mad_u64_u32) instead of separate lo/hi multiplies
@@ -70,6 +71,30 @@ __device__ __forceinline__ void site_noise(uint32_t i, uint32_t k0, uint32_t k1,
   const uint32_t wy = (i & 1u) ? w.w3 : w.w1;
   fx = (uint64_t)wx < thr;
   fy = (uint64_t)wy < thr;
+}
+
+// Limited-memory variant of the rule (Sec. 5.3, corollary on limited
+// classical memory).  With a finite m_max a message whose value would exceed
+// m_max disappears.  In emission-time form a register is live after sub-step
+// s iff e >= s + 1 - m_max: a dropped message keeps a stale emission time
+// that is smaller than every live one, so the 3-wide maxima of the update
+// stay exact and only the decision has to ignore registers below the
+// threshold.  With u > 0, every u-th decoder step t (from 1) moves each
+// anyon in a random direction instead: Philox4x32-10 keyed by the sample's
+// seed, counter (i >> 1, t, MOVE_TAG, 0), word (i & 1) of site i, mod 4 ->
+// +x, -x, +y, -y.
+constexpr uint32_t MOVE_TAG = 0x4D4F5645u;
+
+// Smallest live emission time after sub-step s (1 with no truncation).
+__device__ __forceinline__ uint32_t live_threshold(uint32_t s, int m_max) {
+  return (m_max > 0 && s + 1u > (uint32_t)m_max + 1u) ? s + 1u - (uint32_t)m_max : 1u;
+}
+
+// Random directions of the two sites of a generator pair (word 0: the even
+// site 2q, word 1: the odd site 2q + 1): 0 +x, 1 -x, 2 +y, 3 -y.
+__device__ __forceinline__ uint2 random_dirs(uint32_t pair, uint32_t t, uint32_t k0, uint32_t k1) {
+  const Words4 w = philox4x32_10(pair, k0, k1, t, MOVE_TAG);
+  return make_uint2(w.w0 & 3u, w.w1 & 3u);
 }
 
 // Per-thread view of the region.
@@ -161,11 +186,29 @@ __device__ __forceinline__ void substep(uint32_t (&P)[H], uint32_t (&Q)[H], uint
 // across it (OR of eq. (ddfeedback)).  Returns the new syndrome mask; xo
 // and yo receive the flipped x-links (x,y)-(x+1,y) and y-links
 // (x,y)-(x,y+1) of the strip, for the correction winding.
-template <int H>
+// `ethr` is the smallest live emission time (live_threshold); with `rnd`
+// (a random-move step t of the limited-memory variant) every anyon of the
+// strip moves in its random direction instead, drawn with key (k0, k1) for
+// site i = row * L + g.c.
+template <int H, bool RULE>
 __device__ __forceinline__ uint32_t feedback(const uint32_t (&P)[H], const uint32_t (&Q)[H], uint32_t sig,
-                                             uint4 *MV, const Geo &g, uint32_t &xo, uint32_t &yo) {
+                                             uint4 *MV, const Geo &g, uint32_t &xo, uint32_t &yo, uint32_t ethr,
+                                             bool rnd, uint32_t t, uint32_t k0, uint32_t k1, int L) {
   uint32_t mpx = 0u, mmx = 0u, mpy = 0u, mmy = 0u;
-  if (sig) {
+  if (RULE && sig && rnd) {
+    for (int h = 0; h < H; ++h) {
+      if ((sig >> h) & 1u) {
+        const uint32_t i = (uint32_t)((g.y0 + h) * L + g.c);
+        const uint2 d = random_dirs(i >> 1, t, k0, k1);
+        const uint32_t dir = (i & 1u) ? d.y : d.x;
+        const uint32_t bit = 1u << h;
+        mpx |= dir == 0u ? bit : 0u;
+        mmx |= dir == 1u ? bit : 0u;
+        mpy |= dir == 2u ? bit : 0u;
+        mmy |= dir == 3u ? bit : 0u;
+      }
+    }
+  } else if (sig) {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       if ((sig >> h) & 1u) {
@@ -173,7 +216,7 @@ __device__ __forceinline__ uint32_t feedback(const uint32_t (&P)[H], const uint3
         const uint32_t py = Q[h] & 0xFFFFu, my = Q[h] >> 16;
         const uint32_t M = max(max(px, mx), max(py, my));
         const uint32_t bit = 1u << h;
-        if (M != 0u) {
+        if (M >= ethr) {  // some live message (M != 0 without truncation)
           if (my == M) {
             if (py != M) mpy |= bit;   // -y message: source above, move +y
           } else if (mx == M) {

@@ -53,6 +53,9 @@ struct ResidentArgs {
   uint32_t *syn;           // final syndrome bits (may be null)
   int16_t *m_out;          // state export (t_exact >= 0)
   uint8_t *wind_out;
+  int m_max;               // limited-memory variant: 0 = no truncation
+  int u;                   // random moves every u steps, 0 = none
+  const uint64_t *move_seeds;  // keys of the random moves in explicit-error mode
 };
 
 __device__ __forceinline__ uint32_t parity32(uint32_t x) { return __popc(x) & 1u; }
@@ -65,7 +68,9 @@ __device__ __forceinline__ uint64_t device_threshold(double p) {
   return (uint64_t)t;
 }
 
-template <int H>
+// RULE: the limited-memory variant (a.m_max, a.u) is compiled in; the plain
+// rule is instantiated without it.
+template <int H, bool RULE>
 __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = a.L, RX = L, NS = L / H;
@@ -128,6 +133,12 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   int alive = __syncthreads_or(sig != 0u);
   const bool exact = a.t_exact >= 0;
   const int steps = exact ? a.t_exact : a.T_max;
+  uint32_t mk0 = 0u, mk1 = 0u;  // key of the random moves
+  if (RULE && a.u > 0) {
+    const uint64_t ms = a.links == nullptr ? a.seeds[sample] : a.move_seeds[sample];
+    mk0 = (uint32_t)ms;
+    mk1 = (uint32_t)(ms >> 32);
+  }
   int t = 0;
   while (t < steps && (exact || alive)) {
 #pragma unroll 1
@@ -136,7 +147,13 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
       substep<H>(P, Q, sig, s | (s << 16), F, g);
     }
     uint32_t xo, yo;
-    sig = feedback<H>(P, Q, sig, MV, g, xo, yo);
+    const uint32_t t1 = (uint32_t)(t + 1);
+    if (RULE) {
+      const bool rnd = a.u > 0 && t1 % (uint32_t)a.u == 0u;
+      sig = feedback<H, true>(P, Q, sig, MV, g, xo, yo, live_threshold(3u * t1, a.m_max), rnd, t1, mk0, mk1, L);
+    } else {
+      sig = feedback<H, false>(P, Q, sig, MV, g, xo, yo, 1u, false, t1, 0u, 0u, L);
+    }
     if (g.c == L - 1) wind ^= parity32(xo) << 2;
     if (g.j == NS - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
     ++t;
@@ -167,6 +184,7 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   if (exact) {
     if (a.m_out != nullptr) {
       const uint32_t snow = 3u * (uint32_t)a.t_exact;
+      const uint32_t live = RULE ? live_threshold(snow, a.m_max) : 1u;
       const int64_t n2 = (int64_t)L * L;
       int16_t *mo = a.m_out + sample * 4 * n2;
 #pragma unroll
@@ -174,7 +192,7 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
         const int64_t i = (int64_t)(g.y0 + h) * L + g.c;
         const uint32_t e[4] = {P[h] & 0xFFFFu, P[h] >> 16, Q[h] & 0xFFFFu, Q[h] >> 16};
 #pragma unroll
-        for (int d = 0; d < 4; ++d) mo[d * n2 + i] = (int16_t)(e[d] ? (snow - e[d] + 1u) : 0u);
+        for (int d = 0; d < 4; ++d) mo[d * n2 + i] = (int16_t)(e[d] >= live ? (snow - e[d] + 1u) : 0u);
       }
     }
     if (tid == 0 && a.wind_out != nullptr) a.wind_out[sample] = (uint8_t)W;
@@ -214,6 +232,18 @@ struct BandArgs {
   uint32_t *alive;  // per sample: bit 0 anyons at pass start, bit j after step t_done+j
   uint32_t *wind;   // per sample winding bits: Wx(E), Wy(E), Wx(C), Wy(C)
   int *zero_count;  // counter to clear for the following compaction, or nullptr
+  int m_max;        // limited-memory variant: 0 = no truncation
+  int u;            // random moves every u steps, 0 = none
+  const uint64_t *seeds;  // per sample: key of the random moves (read only when u > 0)
+};
+
+// Limited-memory variant of the rule for a batch (see engine.h): kernels are
+// instantiated without it (RULE = false) for the plain rule.
+struct Rule {
+  int m_max = 0;
+  int u = 0;
+  const uint64_t *seeds = nullptr;
+  bool on() const { return m_max > 0 || u > 0; }
 };
 
 // One pass of tile `tile` of `sample`, which has done t0 steps: loads the
@@ -224,7 +254,7 @@ struct BandArgs {
 // Returns, valid in thread 0: x = anyon bits of the owned part (bit 0 at the
 // pass start, bit j after step j), y = winding bits of the correction links
 // the pass flipped there.
-template <int NW>
+template <int NW, bool RULE>
 __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sample, int t0, const uint4 *Esrc,
                                              const uint2 *Ssrc, uint4 *Edst, uint2 *Sdst) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -292,18 +322,32 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
   const uint32_t own_mask = own_col ? own_rows : 0u;
   uint32_t bits = __syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u) ? 1u : 0u;
   uint4 *BND0 = BND, *BND1 = BND + NW * 2 * 64;
+  uint32_t mk0 = 0u, mk1 = 0u;  // key of the random moves
+  if (RULE && a.u > 0) {
+    const uint64_t ms = a.seeds[sample];
+    mk0 = (uint32_t)ms;
+    mk1 = (uint32_t)(ms >> 32);
+  }
   for (int st = 0; st < ks; ++st) {
     const uint32_t t3 = (uint32_t)(3 * (t0 + st));
+    const uint32_t t1 = (uint32_t)(t0 + st + 1);  // the decoder step being applied
     const uint32_t rows = wave_rows<H>(b.s0, b.s1);
     Moves mv = {0u, 0u, 0u, 0u};
     // three message updates; LDS boundary slots alternate between sub-steps
     uint4 *slot_a = (st & 1) ? BND1 : BND0, *slot_b = (st & 1) ? BND0 : BND1;
     if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16), rows);
-    band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, mv);
+    band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, 1u, mv);
     if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), rows);
-    band_substep<H, false>(b, slot_b, w, wdn, wup, lane, rows, mv);
+    band_substep<H, false>(b, slot_b, w, wdn, wup, lane, rows, 1u, mv);
     if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), rows);
-    band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, mv);
+    if (!RULE) {
+      band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, 1u, mv);
+    } else if (a.u > 0 && t1 % (uint32_t)a.u == 0u) {  // random-move step (wave-uniform)
+      band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, 1u, mv);
+      band_random_moves<H>(b, rows, gx, gy, L, t1, mk0, mk1, mv);
+    } else {
+      band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, live_threshold(t3 + 3u, a.m_max), mv);
+    }
     uint32_t xo[2], yo[2];
     band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);
     if (last_col) wind ^= (__popc(xo[1] & own_rows) & 1u) << 2;
@@ -331,12 +375,12 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
 }
 
 // One pass over the samples in a.active: grid (tiles, samples).
-template <int NW>
+template <int NW, bool RULE>
 __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   const int sample = a.active[blockIdx.y];
   if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
   const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
-  const uint2 r = band_region<NW>(a, blockIdx.x, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
+  const uint2 r = band_region<NW, RULE>(a, blockIdx.x, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
   if (threadIdx.x == 0) {
     if (r.x) atomicOr(&a.alive[sample], r.x);
     if (r.y) atomicXor(&a.wind[sample], r.y);
@@ -346,7 +390,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
 // One pass over survivors whose number is only known on the device
 // (*count): (sample, tile) tasks in a grid-stride loop, each as one k_band
 // workgroup.  Workgroups never wait for each other.
-template <int NW>
+template <int NW, bool RULE>
 __global__ __launch_bounds__(NW * 64) void k_band_grid(BandArgs a, const int *count, int ntiles) {
   if (a.zero_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_count = 0;
   const int64_t ntask = (int64_t)(*count) * ntiles;
@@ -355,7 +399,7 @@ __global__ __launch_bounds__(NW * 64) void k_band_grid(BandArgs a, const int *co
     const int i = (int)(task / ntiles), tile = (int)(task % ntiles);
     const int sample = a.active[i];
     const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
-    const uint2 r = band_region<NW>(a, tile, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
+    const uint2 r = band_region<NW, RULE>(a, tile, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
     if (threadIdx.x == 0) {
       if (r.x) atomicOr(&a.alive[sample], r.x);
       if (r.y) atomicXor(&a.wind[sample], r.y);
@@ -383,7 +427,7 @@ struct TailArgs {
   uint8_t *status;
 };
 
-template <int NW>
+template <int NW, bool RULE>
 __global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
   __shared__ int s_take, s_more;
   __shared__ uint32_t s_bits, s_wind;
@@ -406,7 +450,7 @@ __global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
       }
       for (int tile = 0; tile < ta.ntiles; ++tile) {
         __syncthreads();  // the LDS slots of the previous tile are no longer read
-        const uint2 r = band_region<NW>(a, tile, s, t0, ta.E[c], ta.S[c], ta.E[c ^ 1], ta.S[c ^ 1]);
+        const uint2 r = band_region<NW, RULE>(a, tile, s, t0, ta.E[c], ta.S[c], ta.E[c ^ 1], ta.S[c ^ 1]);
         if (threadIdx.x == 0) {
           s_bits |= r.x;
           s_wind ^= r.y;
@@ -666,7 +710,10 @@ int launch_resident_h(const ResidentArgs &a, hipStream_t stream) {
   const size_t lds = resident_lds(a.L, H);
   const int threads = a.L * a.L / H;
   ProfScope ps("k_resident", stream);
-  hipLaunchKernelGGL(k_resident<H>, dim3((unsigned)a.n), dim3(threads), lds, stream, a);
+  if (a.m_max > 0 || a.u > 0)
+    hipLaunchKernelGGL((k_resident<H, true>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
+  else
+    hipLaunchKernelGGL((k_resident<H, false>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -834,7 +881,7 @@ int tile_geometry(int L, int k, int ry, BandArgs &ba) {
 }
 
 int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *active, int nact, int cur, bool zero,
-              int32_t *d_T_dec, hipStream_t stream) {
+              int32_t *d_T_dec, const Rule &rule, hipStream_t stream) {
   BandArgs ba;
   // Full-size regions (16 waves, 256 rows) unless their grid would leave
   // compute units idle: then 4-wave regions of 64 rows, which need more
@@ -853,14 +900,22 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   ba.alive = w.alive;
   ba.wind = w.wind;
   ba.zero_count = zero ? &w.count[cur ^ 1] : nullptr;
+  ba.m_max = rule.m_max;
+  ba.u = rule.u;
+  ba.seeds = rule.seeds;
   {
     ProfScope ps("k_band", stream);
-    if (small)
-      hipLaunchKernelGGL(k_band<BAND_NW_SMALL>, dim3((unsigned)(ba.ntx * nty), (unsigned)nact),
-                         dim3(BAND_NW_SMALL * 64), band_lds(BAND_NW_SMALL), stream, ba);
+    const dim3 grid((unsigned)(ba.ntx * nty), (unsigned)nact);
+    if (small && rule.on())
+      hipLaunchKernelGGL((k_band<BAND_NW_SMALL, true>), grid, dim3(BAND_NW_SMALL * 64), band_lds(BAND_NW_SMALL),
+                         stream, ba);
+    else if (small)
+      hipLaunchKernelGGL((k_band<BAND_NW_SMALL, false>), grid, dim3(BAND_NW_SMALL * 64), band_lds(BAND_NW_SMALL),
+                         stream, ba);
+    else if (rule.on())
+      hipLaunchKernelGGL((k_band<BAND_NW, true>), grid, dim3(BAND_NW * 64), band_lds(BAND_NW), stream, ba);
     else
-      hipLaunchKernelGGL(k_band<BAND_NW>, dim3((unsigned)(ba.ntx * nty), (unsigned)nact), dim3(BAND_NW * 64),
-                         band_lds(BAND_NW), stream, ba);
+      hipLaunchKernelGGL((k_band<BAND_NW, false>), grid, dim3(BAND_NW * 64), band_lds(BAND_NW), stream, ba);
   }
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, cur ^ 1, active,
@@ -890,6 +945,7 @@ struct BandRun {
   uint8_t *flags = nullptr;
   uint32_t *syn = nullptr;
   hipStream_t stream = nullptr;
+  Rule rule;
   int cur = 1;
   bool done = false;
 };
@@ -924,6 +980,9 @@ int band_tail(BandRun &r, int64_t first_count) {
   ba.t_done = r.w.t_done;
   ba.alive = r.w.alive;
   ba.wind = r.w.wind;
+  ba.m_max = r.rule.m_max;
+  ba.u = r.rule.u;
+  ba.seeds = r.rule.seeds;
   int cur = 1;  // the first passes wrote buffer 1 and listed their survivors in active[1]
   for (int pass = 0; pass < DEVICE_GRID_PASSES && first_count > 0; ++pass) {
     ba.active = r.w.active[cur];
@@ -935,8 +994,12 @@ int band_tail(BandRun &r, int64_t first_count) {
     const int64_t grid = std::min<int64_t>(first_count * ntiles, cu_count());
     {
       ProfScope ps("k_band_grid", r.stream);
-      hipLaunchKernelGGL(k_band_grid<BAND_NW>, dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
-                         r.stream, ba, (const int *)&r.w.count[cur], ntiles);
+      if (r.rule.on())
+        hipLaunchKernelGGL((k_band_grid<BAND_NW, true>), dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
+                           r.stream, ba, (const int *)&r.w.count[cur], ntiles);
+      else
+        hipLaunchKernelGGL((k_band_grid<BAND_NW, false>), dim3((unsigned)grid), dim3(BAND_NW * 64),
+                           band_lds(BAND_NW), r.stream, ba, (const int *)&r.w.count[cur], ntiles);
     }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((first_count + 255) / 256)), dim3(256), 0, r.stream, k, r.T_max,
@@ -964,8 +1027,12 @@ int band_tail(BandRun &r, int64_t first_count) {
   const int64_t grid = std::min<int64_t>(first_count, cu_count());
   if (grid > 0) {
     ProfScope ps("k_band_tail", r.stream);
-    hipLaunchKernelGGL(k_band_tail<BAND_NW>, dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW), r.stream,
-                       ta);
+    if (r.rule.on())
+      hipLaunchKernelGGL((k_band_tail<BAND_NW, true>), dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
+                         r.stream, ta);
+    else
+      hipLaunchKernelGGL((k_band_tail<BAND_NW, false>), dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
+                         r.stream, ta);
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_band_export, dim3((unsigned)r.n), dim3(256), 0, r.stream, r.L, r.n, r.w.status, r.w.wind,
@@ -1000,7 +1067,7 @@ int band_passes(BandRun *runs, int nr) {
     for (int b = 0; b < r.fp.nb; ++b) {
       if (r.fp.count[b] == 0) continue;
       const int rc = band_pass(r.L, min(r.fp.k[b], r.T_max), r.T_max, r.w, r.fp.list[b], r.fp.count[b], 0, zero,
-                               r.T_dec, r.stream);
+                               r.T_dec, r.rule, r.stream);
       if (rc != MPD_OK) return rc;
       zero = false;
     }
@@ -1037,7 +1104,7 @@ int band_passes(BandRun *runs, int nr) {
         continue;
       }
       const int rc = band_pass(r.L, later_pass_k(r.L, hc[i]), r.T_max, r.w, r.w.active[r.cur], hc[i], r.cur, true,
-                               r.T_dec, r.stream);
+                               r.T_dec, r.rule, r.stream);
       if (rc != MPD_OK) return rc;
       r.cur ^= 1;
       any = true;
@@ -1066,10 +1133,11 @@ int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_
 }
 
 int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
-                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, const Rule &rule, hipStream_t stream) {
   BandRun r;
   const int rc = band_setup(r, L, thr, d_p, d_seeds, n, T_max, d_T_dec, d_flags, d_syn, ws, stream);
   if (rc != MPD_OK) return rc;
+  r.rule = rule;
   return band_passes(&r, 1);
 }
 
@@ -1198,10 +1266,15 @@ size_t mpd_workspace_bytes(int L, int64_t n) {
   return 0;
 }
 
-int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
-                     uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes,
-                     void *stream) {
-  g_last_error.clear();
+// Range of the limited-memory parameters.
+int check_rule(int m_max, int u) {
+  if (m_max < 0 || u < 0) return fail_with(MPD_ERR_RULE, "m_max=%d, u=%d: both must be >= 0", m_max, u);
+  return MPD_OK;
+}
+
+int decode_seeded(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const Rule &rule,
+                  int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace,
+                  size_t ws_bytes, void *stream) {
   if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
   int rc = check_common(L, n, T_max, d_T_dec, d_flags);
   if (rc) return rc;
@@ -1226,13 +1299,37 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
     a.T_dec = d_T_dec;
     a.flags = d_flags;
     a.syn = d_final_syndrome;
+    a.m_max = rule.m_max;
+    a.u = rule.u;
     return launch_resident(a, st);
   }
   const size_t need = mpd_workspace_bytes(L, n);
   if (ws_bytes < need || d_workspace == nullptr)
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
   if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
-  return decode_band(L, thr, nullptr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, st);
+  return decode_band(L, thr, nullptr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace, rule, st);
+}
+
+int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                     uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes,
+                     void *stream) {
+  g_last_error.clear();
+  return decode_seeded(L, p, d_seeds, n, T_max, Rule(), d_T_dec, d_flags, d_final_syndrome, d_workspace, ws_bytes,
+                       stream);
+}
+
+int mpd_decode_rule(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int m_max, int u,
+                    int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace,
+                    size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  const int rc = check_rule(m_max, u);
+  if (rc) return rc;
+  Rule rule;
+  rule.m_max = m_max;
+  rule.u = u;
+  rule.seeds = d_seeds;
+  return decode_seeded(L, p, d_seeds, n, T_max, rule, d_T_dec, d_flags, d_final_syndrome, d_workspace, ws_bytes,
+                       stream);
 }
 
 int mpd_syndrome_counts(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, uint8_t *d_counts,
@@ -1556,16 +1653,18 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
   return MPD_OK;
 }
 
-int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
-                      uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream) {
-  g_last_error.clear();
-  (void)d_workspace;
-  (void)ws_bytes;
+int decode_links_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int T_max,
+                      int m_max, int u, int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
+                      void *stream) {
   int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  rc = check_rule(m_max, u);
   if (rc) return rc;
   if (!resident_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported for explicit errors (3..128)", L);
   if (n == 0) return MPD_OK;
   if (d_links == nullptr || ((uintptr_t)d_links & 3u)) return fail_with(MPD_ERR_PTR, "links NULL or misaligned");
+  if (u > 0 && (d_move_seeds == nullptr || ((uintptr_t)d_move_seeds & 7u)))
+    return fail_with(MPD_ERR_PTR, "random moves need aligned move seeds");
   ResidentArgs a = {};
   a.L = L;
   a.n = n;
@@ -1575,19 +1674,40 @@ int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int3
   a.T_dec = d_T_dec;
   a.flags = d_flags;
   a.syn = d_final_syndrome;
+  a.m_max = m_max;
+  a.u = u;
+  a.move_seeds = d_move_seeds;
   return launch_resident(a, (hipStream_t)stream);
 }
 
-int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out, uint32_t *d_sigma_out,
-                  uint8_t *d_wind_out, void *stream) {
+int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
+                      uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream) {
   g_last_error.clear();
+  (void)d_workspace;
+  (void)ws_bytes;
+  return decode_links_rule(L, d_links, nullptr, n, T_max, 0, 0, d_T_dec, d_flags, d_final_syndrome, stream);
+}
+
+int mpd_decode_errors_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int T_max,
+                           int m_max, int u, int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
+                           void *stream) {
+  g_last_error.clear();
+  return decode_links_rule(L, d_links, d_move_seeds, n, T_max, m_max, u, d_T_dec, d_flags, d_final_syndrome, stream);
+}
+
+int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact, int m_max,
+                   int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
   if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
   if (t_exact < 0 || t_exact > MPD_T_MAX_LIMIT) return fail_with(MPD_ERR_TMAX, "t_exact out of range");
+  const int rc = check_rule(m_max, u);
+  if (rc) return rc;
   if (!resident_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported for run_steps (3..128)", L);
   if (n == 0) return MPD_OK;
   if (d_links == nullptr || ((uintptr_t)d_links & 3u)) return fail_with(MPD_ERR_PTR, "links NULL or misaligned");
   if (d_m_out == nullptr || d_sigma_out == nullptr || d_wind_out == nullptr)
     return fail_with(MPD_ERR_PTR, "state outputs must not be NULL");
+  if (u > 0 && (d_move_seeds == nullptr || ((uintptr_t)d_move_seeds & 7u)))
+    return fail_with(MPD_ERR_PTR, "random moves need aligned move seeds");
   ResidentArgs a = {};
   a.L = L;
   a.n = n;
@@ -1597,7 +1717,22 @@ int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_
   a.syn = d_sigma_out;
   a.m_out = d_m_out;
   a.wind_out = d_wind_out;
+  a.m_max = m_max;
+  a.u = u;
+  a.move_seeds = d_move_seeds;
   return launch_resident(a, (hipStream_t)stream);
+}
+
+int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out, uint32_t *d_sigma_out,
+                  uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  return run_steps_rule(L, d_links, nullptr, n, t_exact, 0, 0, d_m_out, d_sigma_out, d_wind_out, stream);
+}
+
+int mpd_run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact,
+                       int m_max, int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  return run_steps_rule(L, d_links, d_move_seeds, n, t_exact, m_max, u, d_m_out, d_sigma_out, d_wind_out, stream);
 }
 
 }  // extern "C"

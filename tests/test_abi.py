@@ -182,3 +182,19 @@ def test_package_submodules_load_lazily(stmt):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     r = subprocess.run([sys.executable, "-c", stmt], cwd=root, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
+
+
+def test_rule_arguments_rejected(lib):
+    """The limited-memory entry points reject negative m_max / u (MPD_ERR_RULE)
+    and random moves without move seeds, before touching the GPU."""
+    dummy = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    assert lib.mpd_decode_rule(16, 0.1, dummy, 4, 8, -1, 0, dummy, dummy, None, None, 0, None) == -8
+    assert lib.mpd_decode_rule(16, 0.1, dummy, 4, 8, 0, -2, dummy, dummy, None, None, 0, None) == -8
+    assert lib.mpd_decode_rule(16, 1.5, dummy, 4, 8, 2, 0, dummy, dummy, None, None, 0, None) == -2
+    assert lib.mpd_decode_rule(16, 0.1, dummy, 0, 8, 2, 3, dummy, dummy, None, None, 0, None) == 0  # empty
+    assert lib.mpd_decode_errors_rule(16, dummy, None, 4, 8, 2, 3, dummy, dummy, None, None) == -4
+    assert lib.mpd_decode_errors_rule(16, dummy, None, 4, 8, -1, 0, dummy, dummy, None, None) == -8
+    assert lib.mpd_decode_errors_rule(256, dummy, None, 4, 8, 2, 0, dummy, dummy, None, None) == -1
+    assert lib.mpd_run_steps_rule(16, dummy, None, 4, 3, 2, 1, dummy, dummy, dummy, None) == -4
+    assert lib.mpd_run_steps_rule(16, dummy, None, 4, 3, 2, -1, dummy, dummy, dummy, None) == -8
+    assert len(lib.mpd_last_error()) > 0
