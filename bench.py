@@ -64,9 +64,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1024)
-    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn", "rule"], default="c3",
                     help="c3 (default) is the headline line; c1/c2/c4/c5 print a line for that configuration, "
-                         "cnn times the predictor's kernels")
+                         "cnn times the predictor's kernels, rule the limited-memory variant at L = 256")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduling leg")
     ap.add_argument("--streams", type=int, default=None,
                     help="batches in flight, each on its own stream, host thread and workspace (default 3 for "
@@ -345,6 +345,8 @@ def other_workload(args, b, seeds, torch, np):
         return learned_c5(args, b, seeds, torch, np, runner)
     if args.workload == "cnn":
         return cnn_kernels(args, b, seeds, torch, np)
+    if args.workload == "rule":
+        return limited_memory(args, b, seeds, torch, np, runner)
     if args.workload == "c4":
         Ls, ps, ss = mixed_batch()
         classes = [(L, int((Ls == L).sum())) for L in dict.fromkeys(Ls.tolist())]
@@ -388,6 +390,36 @@ def other_workload(args, b, seeds, torch, np):
         print(json.dumps({"workload": f"config {args.workload[1]}: L={L} p={p} {n} samples",
                           "samples_per_s": K * n / dt, "site_updates_per_s": L * L * T.sum() / dt,
                           "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean()), "concurrent_batches": S}))
+
+
+def limited_memory(args, b, seeds, torch, np, runner):
+    """The limited-memory variant (messages truncated at m_max, a random move
+    of every anyon every u steps) on the L = 256, p = 0.01 batches, against
+    the plain rule at the same step budget (T_max = 512, which bounds the
+    cost of samples that a small m_max leaves stuck)."""
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    n, T_max = N_SAMPLES, 512
+    batches = [torch.from_numpy(seeds(3, i % 256, n).view(np.int64)).to(dev) for i in range(W + K)]
+    ws = b.alloc_workspace(L, n)
+    st = runner.streams[0]
+    for m_max, u in ((0, 0), (16, 0), (16, 8), (6, 4)):
+        outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None)
+                for _ in range(W + K)]
+        for i in range(W):
+            b.decode_rule(L, P, batches[i], T_max, m_max=m_max, u=u, workspace=ws, out=outs[i], stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            b.decode_rule(L, P, batches[i], T_max, m_max=m_max, u=u, workspace=ws, out=outs[i], stream=st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
+        F = torch.cat([outs[i][1] for i in range(W, W + K)]).cpu().numpy()
+        print(json.dumps({"workload": f"limited memory: L={L} p={P} {n} samples, T_max={T_max}, m_max={m_max}, u={u}",
+                          "samples_per_s": K * n / dt, "site_updates_per_s": L * L * T.sum() / dt,
+                          "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean()),
+                          "fail_rate": float((F & 1).mean()), "timeouts": int(((F & 2) > 0).sum())}), flush=True)
 
 
 def learned_c5(args, b, seeds, torch, np, runner):

@@ -340,13 +340,10 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
     if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), rows);
     band_substep<H, false>(b, slot_b, w, wdn, wup, lane, rows, 1u, mv);
     if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), rows);
-    if (!RULE) {
-      band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, 1u, mv);
-    } else if (a.u > 0 && t1 % (uint32_t)a.u == 0u) {  // random-move step (wave-uniform)
-      band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, 1u, mv);
+    band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, RULE ? live_threshold(t3 + 3u, a.m_max) : 1u, mv);
+    if (RULE && a.u > 0 && t1 % (uint32_t)a.u == 0u) {  // random-move step (wave-uniform): replaces the decisions
+      mv = {0u, 0u, 0u, 0u};
       band_random_moves<H>(b, rows, gx, gy, L, t1, mk0, mk1, mv);
-    } else {
-      band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, live_threshold(t3 + 3u, a.m_max), mv);
     }
     uint32_t xo[2], yo[2];
     band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);

@@ -7,7 +7,10 @@ Three measurements, all on i.i.d. bit-flip noise, periodic L x L lattices, v = 3
 * the slope gamma of p_log = C (p / p_c)^(gamma L) below threshold, from
   p_log at two sizes: gamma = ln(p_log(L2) / p_log(L1)) / ((L2 - L1) ln(p / p_c));
 * the mean decoding time T_dec against ln L below threshold, fitted by
-  T_dec = A ln L + B.
+  T_dec = A ln L + B;
+* with ``--memory``: p_log, timeouts and T_dec of the limited-memory variant
+  (Sec. 5.3: messages truncated at m_max, with and without a random move of
+  every anyon every u steps) against m_max at several L.
 
 Every sample is decoded by libmpd (noise, decoding and classification run in
 the HIP kernels); this module chooses seeds, sums the per-sample results on
@@ -36,6 +39,11 @@ SLOPE_P = [0.03, 0.04, 0.05]
 SLOPE_L = [(8, 4000000), (12, 4000000), (16, 4000000), (24, 4000000), (32, 4000000)]
 TDEC_P = [0.01, 0.02, 0.03, 0.05]
 TDEC_L = [(16, 100000), (32, 100000), (64, 50000), (128, 20000), (256, 8000), (512, 2000), (1024, 512)]
+MEMORY_P = 0.03
+MEMORY_M = [2, 3, 4, 6, 8, 12, 16, 0]        # 0: no truncation
+MEMORY_U = [0, 8]
+MEMORY_L = [(32, 20000), (64, 10000), (128, 4000)]
+MEMORY_T_MAX = 2048
 
 
 def seed_block(L: int, p_index: int, n: int, start: int = 0) -> np.ndarray:
@@ -51,8 +59,9 @@ def _chunk(L: int) -> int:
     return 262144 if L <= 128 else int(max(64, min(8192, (8 << 30) // (17 * L * L))))
 
 
-def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096) -> dict:
-    """Decode n seeded samples at (L, p); returns the counts and sums of the point.
+def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int = 0, u: int = 0) -> dict:
+    """Decode n seeded samples at (L, p) (with the limited-memory variant if
+    m_max or u is set); returns the counts and sums of the point.
 
     fails counts flag bit 0 (timeouts included), timeouts flag bit 1; T_sum
     and T_sq sum T_dec over the samples that finished.
@@ -70,7 +79,11 @@ def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096) -> dict:
     for a in range(0, n, c):
         m = min(c, n - a)
         s = torch.from_numpy(seed_block(L, p_index, m, a).view(np.int64)).to(dev)
-        Tm, Fm, _ = b.decode_batch(L, p, s, T_max, want_syndrome=False, workspace=ws, out=(T[:m], F[:m], None))
+        if m_max or u:
+            Tm, Fm, _ = b.decode_rule(L, p, s, T_max, m_max=m_max, u=u, want_syndrome=False, workspace=ws,
+                                      out=(T[:m], F[:m], None))
+        else:
+            Tm, Fm, _ = b.decode_batch(L, p, s, T_max, want_syndrome=False, workspace=ws, out=(T[:m], F[:m], None))
         Fi = Fm.to(torch.int64)
         done = (Fi & 2) == 0
         Td = torch.where(done, Tm.to(torch.int64), torch.zeros_like(Fi))
@@ -80,8 +93,8 @@ def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096) -> dict:
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fails, timeouts, T_sum, T_sq, T_all = (int(x) for x in v)
-    return dict(L=L, p=p, n=n, T_max=T_max, fails=fails, timeouts=timeouts, T_sum=T_sum, T_sq=T_sq,
-                seconds=dt, site_updates=T_all * L * L)
+    return dict(L=L, p=p, n=n, T_max=T_max, m_max=m_max, u=u, fails=fails, timeouts=timeouts, T_sum=T_sum,
+                T_sq=T_sq, seconds=dt, site_updates=T_all * L * L)
 
 
 def p_log(r: dict) -> float:
@@ -161,6 +174,22 @@ def run(quick: bool = False, T_max: int = 4096, log=print) -> dict:
 TDEC_FIT_LMIN = 64   # the ln L fit uses sizes from here on (smaller ones bend below the line)
 
 
+def run_memory(quick: bool = False, log=print) -> list:
+    """The limited-memory grid: every (L, m_max, u) at p = MEMORY_P."""
+    scale = 0.05 if quick else 1.0
+    out = []
+    for L, n in MEMORY_L:
+        n = max(256, int(n * scale))
+        for j, u in enumerate(MEMORY_U):
+            for i, m in enumerate(MEMORY_M):
+                r = point(L, MEMORY_P, n, 128 + 16 * j + i, MEMORY_T_MAX, m_max=m, u=u)
+                mt, e = mean_T(r)
+                log(f"memory L={L} m_max={m} u={u}: p_log={p_log(r):.5f} timeouts={r['timeouts']} "
+                    f"T={mt:.3f}±{e:.3f} n={n} {r['seconds']:.2f}s")
+                out.append(r)
+    return out
+
+
 def summarize(res: dict) -> dict:
     """Crossings of consecutive sizes (all samples, and decoded samples only),
     slopes gamma against the crossing of the two largest sizes, and
@@ -207,10 +236,17 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true", help="5%% of the samples per point")
     ap.add_argument("--T-max", type=int, default=4096)
     ap.add_argument("--json", default=None, help="write all counts and fits here")
+    ap.add_argument("--memory", action="store_true", help="only the limited-memory grid")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         sys.exit("sweep: needs a GPU (the decoder runs only in libmpd's HIP kernels)")
+    if a.memory:
+        res = run_memory(a.quick, log=lambda s: print(s, flush=True))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     res = run(a.quick, a.T_max, log=lambda s: print(s, flush=True))
     print(json.dumps(res["summary"], indent=1), flush=True)
     if a.json:

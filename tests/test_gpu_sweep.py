@@ -51,3 +51,16 @@ def test_point_spans_chunks(gpu, orc):
     assert r["fails"] == int((F & 1).sum()) and r["timeouts"] == int((~done).sum())
     assert r["T_sum"] == int(T[done].sum()) and r["T_sq"] == int((T[done] ** 2).sum())
     assert r["site_updates"] == int(T.sum()) * L * L
+
+
+@pytest.mark.parametrize("L,n,m_max,u", [(32, 1000, 3, 0), (32, 1000, 4, 8), (64, 200, 2, 8)])
+def test_memory_point_matches_oracle(gpu, orc, L, n, m_max, u):
+    """A point of the limited-memory grid: the same counts as the oracle."""
+    r = sweep.point(L, sweep.MEMORY_P, n, p_index=202, T_max=512, m_max=m_max, u=u)
+    ref = orc.decode_seeds(L, sweep.MEMORY_P, sweep.seed_block(L, 202, n), 512, threads=16, want_sigma=False,
+                           m_max=m_max, u=u)
+    T = ref["T_dec"].astype(np.int64)
+    F = ref["flags"].astype(np.int64)
+    done = (F & 2) == 0
+    assert (r["fails"], r["timeouts"]) == (int((F & 1).sum()), int((~done).sum()))
+    assert (r["T_sum"], r["T_sq"]) == (int(T[done].sum()), int((T[done] ** 2).sum()))
