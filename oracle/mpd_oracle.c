@@ -64,6 +64,24 @@
  *       mod 4, gives +x, -x, +y, -y for 0..3.  Moves flip links through the
  *       same OR rule.  u = 0 means no random moves.
  *
+ * Open boundaries (appendix "open boundaries", Def. "message passing
+ * automaton with open boundaries"), an optional variant of the lattice:
+ *   R19 sites (x, y), 0 <= x, y < L, no wrap; the rough boundary B is the
+ *       columns x = 0 and x = L-1 (eq. (lrboundaries)); rows y = 0 and
+ *       y = L-1 end without a boundary of that kind (smooth).
+ *   R20 qubits are the links with a bulk endpoint: x-links (x,y)-(x+1,y)
+ *       for x <= L-2, y-links (x,y)-(x,y+1) for y <= L-2 and 1 <= x <= L-2.
+ *       Noise and explicit errors on other links are ignored.  Only bulk
+ *       sites carry a syndrome; a string may end on B.
+ *   R21 messages: registers at B sites are 0; m^{+x} (m^{-x}) is 1 at bulk
+ *       sites whose left (right) neighbour is in B; lines are clipped to the
+ *       lattice and empty when their centre lies outside it; otherwise the
+ *       rule of R1-R2.  Feedback unchanged; an anyon moving onto B is
+ *       absorbed.
+ *   R22 one logical qubit: failure iff E + C crosses the cut between
+ *       columns L-2 and L-1 an odd number of times (a string from B_L to
+ *       B_R); timeouts count as failures.
+ *
  * Site index i = y*L + x.  The x-link of site (x,y) joins (x,y) and
  * (x+1,y); its y-link joins (x,y) and (x,y+1) (indices mod L).
  * Register order in every array: d = 0: +x, 1: -x, 2: +y, 3: -y, i.e.
@@ -140,6 +158,7 @@ int orc_noise(int L, double p, uint64_t seed, uint8_t *ex, uint8_t *ey) {
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int L, v;
+  int open;           /* R19-R22: open boundaries instead of the torus */
   int m_max;          /* R17: 0 = no truncation */
   int u;              /* R18: 0 = no random moves */
   uint32_t key[2];    /* the sample's seed, for the random moves */
@@ -190,15 +209,28 @@ static int orc_alloc(orc_state *st, int L, int v) {
   return ORC_OK;
 }
 
+/* Open boundaries: is column x part of the rough boundary B (R19)? */
+static int orc_in_B(const orc_state *st, int x) { return st->open && (x == 0 || x == st->L - 1); }
+
+/* Does the link of site (x, y) in direction dir (0: x-link, 1: y-link)
+ * exist (R20)?  Every link does on the torus. */
+static int orc_link_exists(const orc_state *st, int x, int y, int dir) {
+  if (!st->open) return 1;
+  if (dir == 0) return x <= st->L - 2;
+  return y <= st->L - 2 && x >= 1 && x <= st->L - 2;
+}
+
 /* sigma = boundary of the error chain: -1 where an odd number of the four
- * incident links carry an error (Def. "synchronous automaton decoder"). */
+ * incident links carry an error (Def. "synchronous automaton decoder").
+ * With open boundaries only bulk sites carry a syndrome, and links that do
+ * not exist must be 0 in ex / ey. */
 static void orc_syndrome(orc_state *st, const uint8_t *ex, const uint8_t *ey) {
   int L = st->L;
   for (int y = 0; y < L; ++y)
     for (int x = 0; x < L; ++x) {
       int i = y * L + x;
       int par = ex[i] ^ ex[y * L + wrap(x - 1, L)] ^ ey[i] ^ ey[wrap(y - 1, L) * L + x];
-      st->sigma[i] = par ? -1 : +1;
+      st->sigma[i] = (par && !orc_in_B(st, x)) ? -1 : +1;
     }
 }
 
@@ -218,8 +250,22 @@ static void orc_message_update(orc_state *st) {
         int cxp = x - s * ax, cyp = y - s * ay;   /* centre r - s a-hat */
         int anyon = 0;
         int32_t minnz = 0;
+        if (st->open) {                           /* R21 */
+          if (orc_in_B(st, x)) {
+            st->mnew[d][y * L + x] = 0;
+            continue;
+          }
+          if (cxp < 0 || cxp >= L || cyp < 0 || cyp >= L) {
+            st->mnew[d][y * L + x] = 0;           /* empty line */
+            continue;
+          }
+          if (orc_in_B(st, cxp)) anyon = 1;       /* B sources x-messages */
+        }
         for (int k = -1; k <= 1; ++k) {
-          int qx = wrap(cxp + k * bx, L), qy = wrap(cyp + k * by, L);
+          int qx = cxp + k * bx, qy = cyp + k * by;
+          if (st->open && (qx < 0 || qx >= L || qy < 0 || qy >= L)) continue;   /* clipped */
+          qx = wrap(qx, L);
+          qy = wrap(qy, L);
           int q = qy * L + qx;
           if (st->sigma[q] == -1) anyon = 1;
           int32_t mv = st->m[d][q];
@@ -301,8 +347,10 @@ static int64_t orc_feedback(orc_state *st) {
     for (int x = 0; x < L; ++x) {
       int i = y * L + x;
       int ix = y * L + wrap(x + 1, L), iy = wrap(y + 1, L) * L + x;
-      st->flx[i] = (uint8_t)orc_or(st->sigma[i] * st->fx[i], st->sigma[ix] * (-st->fx[ix]));
-      st->fly[i] = (uint8_t)orc_or(st->sigma[i] * st->fy[i], st->sigma[iy] * (-st->fy[iy]));
+      st->flx[i] = orc_link_exists(st, x, y, 0)
+                       ? (uint8_t)orc_or(st->sigma[i] * st->fx[i], st->sigma[ix] * (-st->fx[ix])) : 0;
+      st->fly[i] = orc_link_exists(st, x, y, 1)
+                       ? (uint8_t)orc_or(st->sigma[i] * st->fy[i], st->sigma[iy] * (-st->fy[iy])) : 0;
     }
   int64_t anyons = 0;
   for (int y = 0; y < L; ++y)
@@ -312,7 +360,7 @@ static int64_t orc_feedback(orc_state *st) {
                 st->fly[wrap(y - 1, L) * L + x];
       st->cx[i] ^= st->flx[i];
       st->cy[i] ^= st->fly[i];
-      if (par) st->sigma[i] = (int8_t)(-st->sigma[i]);
+      if (par && !orc_in_B(st, x)) st->sigma[i] = (int8_t)(-st->sigma[i]);   /* B absorbs (R20) */
     }
   for (int64_t i = 0; i < n; ++i) anyons += (st->sigma[i] == -1);
   return anyons;
@@ -325,12 +373,31 @@ static int64_t orc_count_anyons(const orc_state *st) {
 }
 
 /* Winding parity of a chain across the fixed cuts: x-links leaving column
- * L-1 and y-links leaving row L-1. */
-static void orc_winding(int L, const uint8_t *cx, const uint8_t *cy, int *wx, int *wy) {
+ * L-1 and y-links leaving row L-1 on the torus (R11); with open boundaries
+ * the x-links from column L-2 to L-1 and no second cycle (R22). */
+static void orc_winding(int L, int open, const uint8_t *cx, const uint8_t *cy, int *wx, int *wy) {
   int a = 0, b = 0;
-  for (int y = 0; y < L; ++y) a ^= cx[y * L + (L - 1)];
-  for (int x = 0; x < L; ++x) b ^= cy[(L - 1) * L + x];
+  int cut = open ? L - 2 : L - 1;
+  for (int y = 0; y < L; ++y) a ^= cx[y * L + cut];
+  if (!open)
+    for (int x = 0; x < L; ++x) b ^= cy[(L - 1) * L + x];
   *wx = a; *wy = b;
+}
+
+/* Copy of an error chain without the links that do not exist (R20). */
+static int orc_masked_chain(const orc_state *st, const uint8_t *ex, const uint8_t *ey, uint8_t **mx,
+                            uint8_t **my) {
+  int L = st->L;
+  *mx = (uint8_t *)malloc((size_t)st->n);
+  *my = (uint8_t *)malloc((size_t)st->n);
+  if (!*mx || !*my) { free(*mx); free(*my); return ORC_ENOMEM; }
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      int i = y * L + x;
+      (*mx)[i] = orc_link_exists(st, x, y, 0) ? ex[i] : 0;
+      (*my)[i] = orc_link_exists(st, x, y, 1) ? ey[i] : 0;
+    }
+  return ORC_OK;
 }
 
 static void orc_pack_sigma(const orc_state *st, uint32_t *words) {
@@ -352,17 +419,20 @@ static void orc_pack_sigma(const orc_state *st, uint32_t *words) {
  *   wind_out  [4] = (Wx_E, Wy_E, Wx_C, Wy_C). */
 /* The same with the limited-memory variant: m_max (R17) and u (R18, random
  * moves keyed by `seed`). */
-int orc_decode_errors_rule(int L, int v, int m_max, int u, uint64_t seed, const uint8_t *ex,
-                           const uint8_t *ey, int T_max, int32_t *T_dec, uint8_t *flags,
-                           uint32_t *sigma_words, int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out,
-                           int32_t *wind_out) {
+static int orc_decode_any(int L, int v, int open, int m_max, int u, uint64_t seed, const uint8_t *ex_in,
+                          const uint8_t *ey_in, int T_max, int32_t *T_dec, uint8_t *flags,
+                          uint32_t *sigma_words, int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out,
+                          int32_t *wind_out) {
   if (L < 3 || v < 1 || T_max < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   orc_state st;
   if (orc_alloc(&st, L, v) != ORC_OK) return ORC_ENOMEM;
+  st.open = open;
   st.m_max = m_max;
   st.u = u;
   st.key[0] = (uint32_t)(seed & 0xffffffffu);
   st.key[1] = (uint32_t)(seed >> 32);
+  uint8_t *ex, *ey;
+  if (orc_masked_chain(&st, ex_in, ey_in, &ex, &ey) != ORC_OK) { orc_free(&st); return ORC_ENOMEM; }
   orc_syndrome(&st, ex, ey);
   int64_t anyons = orc_count_anyons(&st);
   int t = 0;
@@ -373,8 +443,10 @@ int orc_decode_errors_rule(int L, int v, int m_max, int u, uint64_t seed, const 
     ++t;
   }
   int wxe, wye, wxc, wyc;
-  orc_winding(L, ex, ey, &wxe, &wye);
-  orc_winding(L, st.cx, st.cy, &wxc, &wyc);
+  orc_winding(L, open, ex, ey, &wxe, &wye);
+  orc_winding(L, open, st.cx, st.cy, &wxc, &wyc);
+  free(ex);
+  free(ey);
   int timeout = anyons > 0;
   int fail = timeout || ((wxe ^ wxc) | (wye ^ wyc));
   *T_dec = t;
@@ -389,6 +461,22 @@ int orc_decode_errors_rule(int L, int v, int m_max, int u, uint64_t seed, const 
   return ORC_OK;
 }
 
+int orc_decode_errors_rule(int L, int v, int m_max, int u, uint64_t seed, const uint8_t *ex,
+                           const uint8_t *ey, int T_max, int32_t *T_dec, uint8_t *flags,
+                           uint32_t *sigma_words, int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out,
+                           int32_t *wind_out) {
+  return orc_decode_any(L, v, 0, m_max, u, seed, ex, ey, T_max, T_dec, flags, sigma_words, m_out, cx_out,
+                        cy_out, wind_out);
+}
+
+/* Open boundaries (R19-R22): wind_out[1] and [3] are 0. */
+int orc_decode_errors_open(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_max, int32_t *T_dec,
+                           uint8_t *flags, uint32_t *sigma_words, int32_t *m_out, uint8_t *cx_out,
+                           uint8_t *cy_out, int32_t *wind_out) {
+  return orc_decode_any(L, v, 1, 0, 0, 0, ex, ey, T_max, T_dec, flags, sigma_words, m_out, cx_out, cy_out,
+                        wind_out);
+}
+
 int orc_decode_errors(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_max,
                       int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words,
                       int32_t *m_out, uint8_t *cx_out, uint8_t *cy_out, int32_t *wind_out) {
@@ -401,17 +489,22 @@ int orc_decode_errors(int L, int v, const uint8_t *ex, const uint8_t *ey, int T_
  * and the correction chain after the last step.  With record != NULL, the
  * anyon indicator after every step k = 0..t_exact is written to
  * record[k*L*L + i] (k = 0 is the initial syndrome). */
-int orc_run_steps_rule(int L, int v, int m_max, int u, uint64_t seed, const uint8_t *ex,
-                       const uint8_t *ey, int t_exact, int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out,
+static int orc_run_any(int L, int v, int open, int m_max, int u, uint64_t seed, const uint8_t *ex_in,
+                       const uint8_t *ey_in, int t_exact, int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out,
                        uint8_t *cy_out, uint8_t *record) {
   if (L < 3 || v < 1 || t_exact < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   orc_state st;
   if (orc_alloc(&st, L, v) != ORC_OK) return ORC_ENOMEM;
+  st.open = open;
   st.m_max = m_max;
   st.u = u;
   st.key[0] = (uint32_t)(seed & 0xffffffffu);
   st.key[1] = (uint32_t)(seed >> 32);
+  uint8_t *ex, *ey;
+  if (orc_masked_chain(&st, ex_in, ey_in, &ex, &ey) != ORC_OK) { orc_free(&st); return ORC_ENOMEM; }
   orc_syndrome(&st, ex, ey);
+  free(ex);
+  free(ey);
   if (record)
     for (int64_t i = 0; i < st.n; ++i) record[i] = st.sigma[i] == -1;
   for (int t = 0; t < t_exact; ++t) {
@@ -431,6 +524,17 @@ int orc_run_steps_rule(int L, int v, int m_max, int u, uint64_t seed, const uint
   return ORC_OK;
 }
 
+int orc_run_steps_rule(int L, int v, int m_max, int u, uint64_t seed, const uint8_t *ex,
+                       const uint8_t *ey, int t_exact, int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out,
+                       uint8_t *cy_out, uint8_t *record) {
+  return orc_run_any(L, v, 0, m_max, u, seed, ex, ey, t_exact, m_out, sigma_out, cx_out, cy_out, record);
+}
+
+int orc_run_steps_open(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exact, int32_t *m_out,
+                       int8_t *sigma_out, uint8_t *cx_out, uint8_t *cy_out, uint8_t *record) {
+  return orc_run_any(L, v, 1, 0, 0, 0, ex, ey, t_exact, m_out, sigma_out, cx_out, cy_out, record);
+}
+
 int orc_run_steps(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exact,
                   int32_t *m_out, int8_t *sigma_out, uint8_t *cx_out, uint8_t *cy_out,
                   uint8_t *record) {
@@ -440,9 +544,9 @@ int orc_run_steps(int L, int v, const uint8_t *ex, const uint8_t *ey, int t_exac
 /* Noise + decode for a batch of seeds; samples are spread over nthreads
  * OpenMP threads (nthreads <= 0: the OpenMP default).  Returns the number
  * of threads actually used through *threads_used. */
-int orc_decode_seeds_rule(int L, int v, int m_max, int u, const double *p, int p_stride,
-                          const uint64_t *seeds, int64_t n, int T_max, int nthreads, int32_t *T_dec,
-                          uint8_t *flags, uint32_t *sigma_words, int *threads_used) {
+static int orc_seeds_any(int L, int v, int open, int m_max, int u, const double *p, int p_stride,
+                         const uint64_t *seeds, int64_t n, int T_max, int nthreads, int32_t *T_dec,
+                         uint8_t *flags, uint32_t *sigma_words, int *threads_used) {
   if (L < 3 || v < 1 || T_max < 0 || n < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   int64_t nsite = (int64_t)L * L;
   int64_t nw = (nsite + 31) / 32;
@@ -466,8 +570,8 @@ int orc_decode_seeds_rule(int L, int v, int m_max, int u, const double *p, int p
     int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
     if (rc == ORC_OK) rc = orc_noise(L, p[p_stride ? k : 0], seeds[k], ex, ey);
     if (rc == ORC_OK)
-      rc = orc_decode_errors_rule(L, v, m_max, u, seeds[k], ex, ey, T_max, &T_dec[k], &flags[k],
-                                  sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+      rc = orc_decode_any(L, v, open, m_max, u, seeds[k], ex, ey, T_max, &T_dec[k], &flags[k],
+                          sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
     if (rc != ORC_OK) {
 #pragma omp critical
       err = rc;
@@ -478,19 +582,33 @@ int orc_decode_seeds_rule(int L, int v, int m_max, int u, const double *p, int p
   return err;
 }
 
+int orc_decode_seeds_rule(int L, int v, int m_max, int u, const double *p, int p_stride,
+                          const uint64_t *seeds, int64_t n, int T_max, int nthreads, int32_t *T_dec,
+                          uint8_t *flags, uint32_t *sigma_words, int *threads_used) {
+  return orc_seeds_any(L, v, 0, m_max, u, p, p_stride, seeds, n, T_max, nthreads, T_dec, flags, sigma_words,
+                       threads_used);
+}
+
+int orc_decode_seeds_open(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
+                          int T_max, int nthreads, int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words,
+                          int *threads_used) {
+  return orc_seeds_any(L, v, 1, 0, 0, p, p_stride, seeds, n, T_max, nthreads, T_dec, flags, sigma_words,
+                       threads_used);
+}
+
 int orc_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds,
                      int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
                      uint32_t *sigma_words, int *threads_used) {
-  return orc_decode_seeds_rule(L, v, 0, 0, p, p_stride, seeds, n, T_max, nthreads, T_dec, flags,
-                               sigma_words, threads_used);
+  return orc_seeds_any(L, v, 0, 0, 0, p, p_stride, seeds, n, T_max, nthreads, T_dec, flags, sigma_words,
+                       threads_used);
 }
 
 /* Decode a batch of explicit error chains given as link bits: link id
  * l = 2*i + dir (dir 0: x-link of site i, dir 1: y-link), bit l%32 of word
  * l/32, ceil(2*L*L/32) words per sample. */
-int orc_decode_links_rule(int L, int v, int m_max, int u, const uint64_t *seeds, const uint32_t *links,
-                          int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
-                          uint32_t *sigma_words) {
+static int orc_links_any(int L, int v, int open, int m_max, int u, const uint64_t *seeds, const uint32_t *links,
+                         int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
+                         uint32_t *sigma_words) {
   if (L < 3 || v < 1 || T_max < 0 || n < 0 || m_max < 0 || u < 0) return ORC_EBADARG;
   if (u > 0 && seeds == NULL) return ORC_EBADARG;
   int64_t nsite = (int64_t)L * L;
@@ -513,8 +631,8 @@ int orc_decode_links_rule(int L, int v, int m_max, int u, const uint64_t *seeds,
         ex[i] = (uint8_t)((w[lx >> 5] >> (lx & 31)) & 1u);
         ey[i] = (uint8_t)((w[ly >> 5] >> (ly & 31)) & 1u);
       }
-      rc = orc_decode_errors_rule(L, v, m_max, u, seeds ? seeds[k] : 0, ex, ey, T_max, &T_dec[k], &flags[k],
-                                  sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+      rc = orc_decode_any(L, v, open, m_max, u, seeds ? seeds[k] : 0, ex, ey, T_max, &T_dec[k], &flags[k],
+                          sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
     }
     if (rc != ORC_OK) {
 #pragma omp critical
@@ -526,7 +644,18 @@ int orc_decode_links_rule(int L, int v, int m_max, int u, const uint64_t *seeds,
   return err;
 }
 
+int orc_decode_links_rule(int L, int v, int m_max, int u, const uint64_t *seeds, const uint32_t *links,
+                          int64_t n, int T_max, int nthreads, int32_t *T_dec, uint8_t *flags,
+                          uint32_t *sigma_words) {
+  return orc_links_any(L, v, 0, m_max, u, seeds, links, n, T_max, nthreads, T_dec, flags, sigma_words);
+}
+
+int orc_decode_links_open(int L, int v, const uint32_t *links, int64_t n, int T_max, int nthreads,
+                          int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words) {
+  return orc_links_any(L, v, 1, 0, 0, NULL, links, n, T_max, nthreads, T_dec, flags, sigma_words);
+}
+
 int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, int nthreads,
                      int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words) {
-  return orc_decode_links_rule(L, v, 0, 0, NULL, links, n, T_max, nthreads, T_dec, flags, sigma_words);
+  return orc_links_any(L, v, 0, 0, 0, NULL, links, n, T_max, nthreads, T_dec, flags, sigma_words);
 }

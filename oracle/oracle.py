@@ -67,6 +67,14 @@ def _load():
     lib.orc_decode_seeds_rule.restype = I
     lib.orc_decode_links_rule.argtypes = [I, I, I, I, P, P, ctypes.c_int64, I, I, P, P, P]
     lib.orc_decode_links_rule.restype = I
+    lib.orc_decode_errors_open.argtypes = [I, I, P, P, I, P, P, P, P, P, P, P]
+    lib.orc_decode_errors_open.restype = I
+    lib.orc_run_steps_open.argtypes = [I, I, P, P, I, P, P, P, P, P]
+    lib.orc_run_steps_open.restype = I
+    lib.orc_decode_seeds_open.argtypes = [I, I, P, I, P, ctypes.c_int64, I, I, P, P, P, P]
+    lib.orc_decode_seeds_open.restype = I
+    lib.orc_decode_links_open.argtypes = [I, I, P, ctypes.c_int64, I, I, P, P, P]
+    lib.orc_decode_links_open.restype = I
     lib.orc_decode_links.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -115,13 +123,14 @@ def pack_bits(bits):
 
 
 def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = False, m_max: int = 0,
-                  u: int = 0, seed: int = 0):
+                  u: int = 0, seed: int = 0, open_bc: bool = False):
     """Decode one explicit error chain.
 
     Returns dict(T_dec, flags, sigma_words) and, with want_state, also
     m [4, L, L] int32, cx, cy [L, L] and wind (Wx_E, Wy_E, Wx_C, Wy_C).
     m_max > 0 truncates messages (R17); u > 0 makes every u-th step a random
-    move keyed by `seed` (R18).
+    move keyed by `seed` (R18); open_bc decodes on the lattice with rough left
+    and right boundaries (R19-R22; not combined with m_max / u).
     """
     ex = np.ascontiguousarray(np.asarray(ex, dtype=np.uint8).reshape(-1))
     ey = np.ascontiguousarray(np.asarray(ey, dtype=np.uint8).reshape(-1))
@@ -133,9 +142,14 @@ def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = Fal
     cx = np.zeros(L * L, dtype=np.uint8) if want_state else None
     cy = np.zeros(L * L, dtype=np.uint8) if want_state else None
     wind = np.zeros(4, dtype=np.int32) if want_state else None
-    _check(_load().orc_decode_errors_rule(L, v, int(m_max), int(u), int(seed), _ptr(ex), _ptr(ey), int(T_max),
-                                          _ptr(T), _ptr(fl), _ptr(sw), _ptr(m), _ptr(cx), _ptr(cy), _ptr(wind)),
-           "decode_errors")
+    if open_bc:
+        assert m_max == 0 and u == 0
+        _check(_load().orc_decode_errors_open(L, v, _ptr(ex), _ptr(ey), int(T_max), _ptr(T), _ptr(fl), _ptr(sw),
+                                              _ptr(m), _ptr(cx), _ptr(cy), _ptr(wind)), "decode_errors")
+    else:
+        _check(_load().orc_decode_errors_rule(L, v, int(m_max), int(u), int(seed), _ptr(ex), _ptr(ey), int(T_max),
+                                              _ptr(T), _ptr(fl), _ptr(sw), _ptr(m), _ptr(cx), _ptr(cy), _ptr(wind)),
+               "decode_errors")
     out = dict(T_dec=int(T[0]), flags=int(fl[0]), sigma_words=sw)
     if want_state:
         out.update(m=m.reshape(4, L, L), cx=cx.reshape(L, L), cy=cy.reshape(L, L),
@@ -144,7 +158,7 @@ def decode_errors(L: int, ex, ey, T_max: int, v: int = 3, want_state: bool = Fal
 
 
 def run_steps(L: int, ex, ey, t_exact: int, v: int = 3, record: bool = False, m_max: int = 0, u: int = 0,
-              seed: int = 0):
+              seed: int = 0, open_bc: bool = False):
     """Run exactly t_exact steps.  Returns (m [4,L,L], sigma [L,L] (+1/-1),
     (cx, cy), history) with history [t_exact+1, L, L] anyon indicators or None."""
     ex = np.ascontiguousarray(np.asarray(ex, dtype=np.uint8).reshape(-1))
@@ -154,14 +168,19 @@ def run_steps(L: int, ex, ey, t_exact: int, v: int = 3, record: bool = False, m_
     cx = np.zeros(L * L, dtype=np.uint8)
     cy = np.zeros(L * L, dtype=np.uint8)
     hist = np.zeros((t_exact + 1) * L * L, dtype=np.uint8) if record else None
-    _check(_load().orc_run_steps_rule(L, v, int(m_max), int(u), int(seed), _ptr(ex), _ptr(ey), int(t_exact),
-                                      _ptr(m), _ptr(sig), _ptr(cx), _ptr(cy), _ptr(hist)), "run_steps")
+    if open_bc:
+        assert m_max == 0 and u == 0
+        _check(_load().orc_run_steps_open(L, v, _ptr(ex), _ptr(ey), int(t_exact), _ptr(m), _ptr(sig), _ptr(cx),
+                                          _ptr(cy), _ptr(hist)), "run_steps")
+    else:
+        _check(_load().orc_run_steps_rule(L, v, int(m_max), int(u), int(seed), _ptr(ex), _ptr(ey), int(t_exact),
+                                          _ptr(m), _ptr(sig), _ptr(cx), _ptr(cy), _ptr(hist)), "run_steps")
     return (m.reshape(4, L, L), sig.reshape(L, L), (cx.reshape(L, L), cy.reshape(L, L)),
             None if hist is None else hist.reshape(t_exact + 1, L, L))
 
 
 def decode_seeds(L: int, p, seeds, T_max: int, v: int = 3, threads: int = 0,
-                 want_sigma: bool = True, m_max: int = 0, u: int = 0):
+                 want_sigma: bool = True, m_max: int = 0, u: int = 0, open_bc: bool = False):
     """Noise from each seed (one p, or one p per seed) and decode.
 
     Returns dict(T_dec int32[n], flags uint8[n], sigma_words uint32[n, W] or
@@ -178,9 +197,14 @@ def decode_seeds(L: int, p, seeds, T_max: int, v: int = 3, threads: int = 0,
     W = (L * L + 31) // 32
     sw = np.zeros((n, W), dtype=np.uint32) if want_sigma else None
     used = ctypes.c_int(0)
-    _check(_load().orc_decode_seeds_rule(L, v, int(m_max), int(u), _ptr(pa), stride, _ptr(seeds), n,
-                                         int(T_max), int(threads), _ptr(T), _ptr(fl), _ptr(sw),
-                                         ctypes.byref(used)), "decode_seeds")
+    if open_bc:
+        assert m_max == 0 and u == 0
+        _check(_load().orc_decode_seeds_open(L, v, _ptr(pa), stride, _ptr(seeds), n, int(T_max), int(threads),
+                                             _ptr(T), _ptr(fl), _ptr(sw), ctypes.byref(used)), "decode_seeds")
+    else:
+        _check(_load().orc_decode_seeds_rule(L, v, int(m_max), int(u), _ptr(pa), stride, _ptr(seeds), n,
+                                             int(T_max), int(threads), _ptr(T), _ptr(fl), _ptr(sw),
+                                             ctypes.byref(used)), "decode_seeds")
     return dict(T_dec=T, flags=fl, sigma_words=sw, threads=int(used.value))
 
 
@@ -197,7 +221,7 @@ def links_from_chains(L: int, ex, ey):
 
 
 def decode_links(L: int, links, T_max: int, v: int = 3, threads: int = 0, m_max: int = 0, u: int = 0,
-                 seeds=None):
+                 seeds=None, open_bc: bool = False):
     """Decode explicit error chains given as packed link words [n, W]; with
     u > 0 the random moves of chain k are keyed by seeds[k]."""
     lw = (2 * L * L + 31) // 32
@@ -208,6 +232,11 @@ def decode_links(L: int, links, T_max: int, v: int = 3, threads: int = 0, m_max:
     sw = np.zeros((n, (L * L + 31) // 32), dtype=np.uint32)
     sd = None if seeds is None else np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
     assert sd is None or sd.size == n
-    _check(_load().orc_decode_links_rule(L, v, int(m_max), int(u), _ptr(sd), _ptr(links), n, int(T_max),
-                                         int(threads), _ptr(T), _ptr(fl), _ptr(sw)), "decode_links")
+    if open_bc:
+        assert m_max == 0 and u == 0
+        _check(_load().orc_decode_links_open(L, v, _ptr(links), n, int(T_max), int(threads), _ptr(T), _ptr(fl),
+                                             _ptr(sw)), "decode_links")
+    else:
+        _check(_load().orc_decode_links_rule(L, v, int(m_max), int(u), _ptr(sd), _ptr(links), n, int(T_max),
+                                             int(threads), _ptr(T), _ptr(fl), _ptr(sw)), "decode_links")
     return dict(T_dec=T, flags=fl, sigma_words=sw)
