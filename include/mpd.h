@@ -162,6 +162,28 @@ int mpd_run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_se
                        int t_exact, int m_max, int u, int16_t *d_m_out, uint32_t *d_sigma_out,
                        uint8_t *d_wind_out, void *stream);
 
+/* Open lattice (the appendix on open boundaries, Def. "message passing
+ * automaton with open boundaries"): sites (x, y), 0 <= x, y < L, no wrap.
+ * The columns x = 0 and x = L-1 are the rough boundary B: they carry no
+ * syndrome and no messages, source x-messages into the bulk (a bulk site
+ * next to B reads a message of value 1 from it) and absorb anyons that move
+ * onto them.  Rows y = 0 and y = L-1 end smooth (lines are clipped).  The
+ * qubits are the links with a bulk endpoint: x-links (x,y)-(x+1,y) for
+ * x <= L-2 and y-links (x,y)-(x,y+1) for y <= L-2, 1 <= x <= L-2; noise on,
+ * and explicit error bits of, other links are ignored (same link ids and
+ * noise words as on the torus).  One logical qubit: flag bit 0 is set iff
+ * error + correction crosses the cut between columns L-2 and L-1 an odd
+ * number of times, or on timeout.  Final syndromes have no bits at B; the
+ * state export reports 0 registers at B, and wind bits 0 (error) and 2
+ * (correction) on that cut (bits 1 and 3 are 0).  Supported L: 3..128 (the
+ * resident kernel); other arguments and errors as the torus calls. */
+int mpd_decode_open(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                    uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream);
+int mpd_decode_errors_open(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec,
+                           uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream);
+int mpd_run_steps_open(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
+                       uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
 /* Temporal blocking of the band path (L >= 256): decoder steps run on chip per
  * pass over HBM, in the first pass (registers still empty) and in later
  * passes.  Results do not depend on it; speed does.  Each value in

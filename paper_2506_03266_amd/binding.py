@@ -53,6 +53,12 @@ def lib():
     L.mpd_decode_errors_rule.restype = I
     L.mpd_run_steps_rule.argtypes = [I, P, P, I64, I, I, I, P, P, P, P]
     L.mpd_run_steps_rule.restype = I
+    L.mpd_decode_open.argtypes = [I, D, P, I64, I, P, P, P, P]
+    L.mpd_decode_open.restype = I
+    L.mpd_decode_errors_open.argtypes = [I, P, I64, I, P, P, P, P]
+    L.mpd_decode_errors_open.restype = I
+    L.mpd_run_steps_open.argtypes = [I, P, I64, I, P, P, P, P]
+    L.mpd_run_steps_open.restype = I
     L.mpd_set_band_schedule.argtypes = [I, I, I]
     L.mpd_set_band_schedule.restype = I
     L.mpd_get_band_schedule.argtypes = [I, P, P]
@@ -203,6 +209,46 @@ def run_steps(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int =
         rc = lib().mpd_run_steps_rule(L, _ptr(links), _ptr(ms), n, int(t_exact), int(m_max), int(u), _ptr(M),
                                       _ptr(S), _ptr(W), _stream_ptr(stream))
         _check(rc, "mpd_run_steps_rule")
+    return M, S, W
+
+
+def decode_open(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True, stream=None):
+    """Decode seeded noise on the open lattice (rough left / right columns,
+    smooth top / bottom rows), L <= 128."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    T = torch.empty(n, dtype=torch.int32, device=dev)
+    F = torch.empty(n, dtype=torch.uint8, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    _check(lib().mpd_decode_open(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _stream_ptr(stream)),
+           "mpd_decode_open")
+    return T, F, S
+
+
+def decode_errors_open(L: int, links, T_max: int = 4096, want_syndrome: bool = True, stream=None):
+    """Explicit error patterns on the open lattice."""
+    dev = torch.device("cuda")
+    links = _links_tensor(L, links, dev)
+    n = links.shape[0]
+    T = torch.empty(n, dtype=torch.int32, device=dev)
+    F = torch.empty(n, dtype=torch.uint8, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    _check(lib().mpd_decode_errors_open(L, _ptr(links), n, int(T_max), _ptr(T), _ptr(F), _ptr(S),
+                                        _stream_ptr(stream)), "mpd_decode_errors_open")
+    return T, F, S
+
+
+def run_steps_open(L: int, links, t_exact: int, stream=None):
+    """Exactly t_exact steps on the open lattice; returns (m, syndrome, wind)."""
+    dev = torch.device("cuda")
+    links = _links_tensor(L, links, dev)
+    n = links.shape[0]
+    M = torch.empty((n, 4, L, L), dtype=torch.int16, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
+    W = torch.empty(n, dtype=torch.uint8, device=dev)
+    _check(lib().mpd_run_steps_open(L, _ptr(links), n, int(t_exact), _ptr(M), _ptr(S), _ptr(W), _stream_ptr(stream)),
+           "mpd_run_steps_open")
     return M, S, W
 
 

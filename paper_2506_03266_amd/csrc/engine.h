@@ -117,15 +117,19 @@ __device__ __forceinline__ constexpr uint32_t full_mask() {
 // One application of A^{(D)} to all four registers of every site (all
 // threads of the block together).  sub-step time s is passed packed as
 // ss = s | s << 16.  F is the LDS exchange buffer (one uint2 per site).
-template <int H>
+// With OPEN, a thread of a rough-boundary column (inB) publishes "emits now"
+// in P, so that its neighbours' x-registers read a message of value 1, and
+// nothing in Q.
+template <int H, bool OPEN = false>
 __device__ __forceinline__ void substep(uint32_t (&P)[H], uint32_t (&Q)[H], uint32_t sig, uint32_t ss,
-                                        uint2 *F, const Geo &g) {
+                                        uint2 *F, const Geo &g, bool inB = false) {
   const int RX = g.RX;
   // publish the folded values: an anyon site reads as "emits now"
 #pragma unroll
   for (int h = 0; h < H; ++h) {
     const bool a = (sig >> h) & 1u;
-    F[(g.y0 + h) * RX + g.c] = make_uint2(a ? ss : P[h], a ? ss : Q[h]);
+    F[(g.y0 + h) * RX + g.c] =
+        (OPEN && inB) ? make_uint2(ss, 0u) : make_uint2(a ? ss : P[h], a ? ss : Q[h]);
   }
   __syncthreads();
   // Rolling window over region rows y0-1 .. y0+H.  For row r:

@@ -56,7 +56,12 @@ struct ResidentArgs {
   int m_max;               // limited-memory variant: 0 = no truncation
   int u;                   // random moves every u steps, 0 = none
   const uint64_t *move_seeds;  // keys of the random moves in explicit-error mode
+  int open;                // 1: open lattice (rough left / right columns)
 };
+
+// Kernel variants of the resident decoder: the plain rule, the
+// limited-memory rule (m_max, u), and the open lattice.
+enum ResidentMode { RES_PLAIN = 0, RES_RULE = 1, RES_OPEN = 2 };
 
 __device__ __forceinline__ uint32_t parity32(uint32_t x) { return __popc(x) & 1u; }
 
@@ -68,14 +73,25 @@ __device__ __forceinline__ uint64_t device_threshold(double p) {
   return (uint64_t)t;
 }
 
-// RULE: the limited-memory variant (a.m_max, a.u) is compiled in; the plain
-// rule is instantiated without it.
-template <int H, bool RULE>
+// MODE RES_RULE compiles in the limited-memory variant (a.m_max, a.u).
+// MODE RES_OPEN decodes on the open lattice of the appendix on open
+// boundaries: sites (x, y) without wrap; the columns x = 0 and x = L-1 are
+// the rough boundary B (no syndrome, no messages; they source x-messages
+// into the bulk and absorb anyons); rows y = 0 and y = L-1 end smooth.
+// Qubits are the links with a bulk endpoint (x-links for x <= L-2, y-links
+// for y <= L-2 in bulk columns); bits of other links are ignored.  The
+// region keeps one extra LDS row of zeros that the bottom and top strips
+// read as their outer neighbour row, which clips every line at the smooth
+// edges; B columns publish "emits now" in P (so their x-messages enter the
+// bulk) and 0 in Q.  One logical qubit: the correction and error windings
+// are read on the x-links from column L-2 to L-1.
+template <int H, int MODE>
 __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
+  constexpr bool RULE = MODE == RES_RULE, OPEN = MODE == RES_OPEN;
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = a.L, RX = L, NS = L / H;
   uint2 *F = reinterpret_cast<uint2 *>(smem);
-  uint4 *MV = reinterpret_cast<uint4 *>(smem + (size_t)RX * L * sizeof(uint2));
+  uint4 *MV = reinterpret_cast<uint4 *>(smem + (size_t)RX * (OPEN ? L + 1 : L) * sizeof(uint2));
   uint32_t *red = reinterpret_cast<uint32_t *>(MV + (size_t)RX * NS);
   const int64_t sample = blockIdx.x;
   const int tid = threadIdx.x;
@@ -89,8 +105,10 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   g.cr = g.c == RX - 1 ? 0 : g.c + 1;
   g.jd = g.j == 0 ? NS - 1 : g.j - 1;
   g.ju = g.j == NS - 1 ? 0 : g.j + 1;
-  g.rowDn = g.y0 == 0 ? L - 1 : g.y0 - 1;
-  g.rowUp = g.y0 + H == L ? 0 : g.y0 + H;
+  g.rowDn = g.y0 == 0 ? (OPEN ? L : L - 1) : g.y0 - 1;
+  g.rowUp = g.y0 + H == L ? (OPEN ? L : 0) : g.y0 + H;
+  const bool inB = OPEN && (g.c == 0 || g.c == L - 1);  // rough boundary column
+  if (OPEN && g.j == 0) F[(size_t)L * RX + g.c] = make_uint2(0u, 0u);  // the zero row
 
   if (tid == 0) red[0] = 0u;
 
@@ -118,10 +136,16 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
       eyb |= ((w[ly >> 5] >> (ly & 31u)) & 1u) << h;
     }
   }
+  if (OPEN) {  // drop the links that do not exist on the open lattice
+    if (g.c == L - 1) exb = 0u;
+    if (inB) eyb = 0u;
+    if (g.j == NS - 1) eyb &= ~(1u << (H - 1));
+  }
   uint32_t wind = 0u;  // bit0 Wx(E), bit1 Wy(E), bit2 Wx(C), bit3 Wy(C)
-  if (g.c == L - 1) wind ^= parity32(exb);
-  if (g.j == NS - 1) wind ^= ((eyb >> (H - 1)) & 1u) << 1;
+  if (g.c == (OPEN ? L - 2 : L - 1)) wind ^= parity32(exb);
+  if (!OPEN && g.j == NS - 1) wind ^= ((eyb >> (H - 1)) & 1u) << 1;
   uint32_t sig = syndrome_from_links<H>(exb, eyb, MV, g);
+  if (inB) sig = 0u;
 
   uint32_t P[H], Q[H];
 #pragma unroll
@@ -144,7 +168,7 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
 #pragma unroll 1
     for (int sub = 1; sub <= 3; ++sub) {
       const uint32_t s = (uint32_t)(3 * t + sub);
-      substep<H>(P, Q, sig, s | (s << 16), F, g);
+      substep<H, OPEN>(P, Q, sig, s | (s << 16), F, g, inB);
     }
     uint32_t xo, yo;
     const uint32_t t1 = (uint32_t)(t + 1);
@@ -154,8 +178,9 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
     } else {
       sig = feedback<H, false>(P, Q, sig, MV, g, xo, yo, 1u, false, t1, 0u, 0u, L);
     }
-    if (g.c == L - 1) wind ^= parity32(xo) << 2;
-    if (g.j == NS - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
+    if (inB) sig = 0u;  // an anyon moved onto B is absorbed
+    if (g.c == (OPEN ? L - 2 : L - 1)) wind ^= parity32(xo) << 2;
+    if (!OPEN && g.j == NS - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
     ++t;
     alive = __syncthreads_or(sig != 0u);
   }
@@ -192,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
         const int64_t i = (int64_t)(g.y0 + h) * L + g.c;
         const uint32_t e[4] = {P[h] & 0xFFFFu, P[h] >> 16, Q[h] & 0xFFFFu, Q[h] >> 16};
 #pragma unroll
-        for (int d = 0; d < 4; ++d) mo[d * n2 + i] = (int16_t)(e[d] >= live ? (snow - e[d] + 1u) : 0u);
+        for (int d = 0; d < 4; ++d) mo[d * n2 + i] = (int16_t)(e[d] >= live && !inB ? (snow - e[d] + 1u) : 0u);
       }
     }
     if (tid == 0 && a.wind_out != nullptr) a.wind_out[sample] = (uint8_t)W;
@@ -694,8 +719,10 @@ int resident_H(int L) {
   return best;
 }
 
-size_t resident_lds(int L, int H) {
-  return (size_t)L * L * sizeof(uint2) + (size_t)L * (L / H) * sizeof(uint4) + 64;
+// Region rows, the move/link exchange and the reduction word; one more row
+// (the zero row) for the open lattice.
+size_t resident_lds(int L, int H, bool open = false) {
+  return (size_t)L * (open ? L + 1 : L) * sizeof(uint2) + (size_t)L * (L / H) * sizeof(uint4) + 64;
 }
 
 size_t band_lds(int nw) {
@@ -704,13 +731,15 @@ size_t band_lds(int nw) {
 
 template <int H>
 int launch_resident_h(const ResidentArgs &a, hipStream_t stream) {
-  const size_t lds = resident_lds(a.L, H);
+  const size_t lds = resident_lds(a.L, H, a.open != 0);
   const int threads = a.L * a.L / H;
   ProfScope ps("k_resident", stream);
-  if (a.m_max > 0 || a.u > 0)
-    hipLaunchKernelGGL((k_resident<H, true>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
+  if (a.open)
+    hipLaunchKernelGGL((k_resident<H, RES_OPEN>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
+  else if (a.m_max > 0 || a.u > 0)
+    hipLaunchKernelGGL((k_resident<H, RES_RULE>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
   else
-    hipLaunchKernelGGL((k_resident<H, false>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
+    hipLaunchKernelGGL((k_resident<H, RES_PLAIN>), dim3((unsigned)a.n), dim3(threads), lds, stream, a);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -1264,12 +1293,12 @@ size_t mpd_workspace_bytes(int L, int64_t n) {
 }
 
 // Range of the limited-memory parameters.
-int check_rule(int m_max, int u) {
+static int check_rule(int m_max, int u) {
   if (m_max < 0 || u < 0) return fail_with(MPD_ERR_RULE, "m_max=%d, u=%d: both must be >= 0", m_max, u);
   return MPD_OK;
 }
 
-int decode_seeded(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const Rule &rule,
+static int decode_seeded(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const Rule &rule,
                   int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace,
                   size_t ws_bytes, void *stream) {
   if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
@@ -1650,9 +1679,12 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
   return MPD_OK;
 }
 
-int decode_links_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int T_max,
+// Open lattices need the zero row in LDS too.
+static bool open_ok(int L) { return resident_ok(L) && resident_lds(L, resident_H(L), true) <= 160 * 1024; }
+
+static int decode_links_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int T_max,
                       int m_max, int u, int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
-                      void *stream) {
+                      void *stream, int open = 0) {
   int rc = check_common(L, n, T_max, d_T_dec, d_flags);
   if (rc) return rc;
   rc = check_rule(m_max, u);
@@ -1674,6 +1706,8 @@ int decode_links_rule(int L, const uint32_t *d_links, const uint64_t *d_move_see
   a.m_max = m_max;
   a.u = u;
   a.move_seeds = d_move_seeds;
+  a.open = open;
+  if (open && !open_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported on the open lattice (3..128)", L);
   return launch_resident(a, (hipStream_t)stream);
 }
 
@@ -1692,8 +1726,8 @@ int mpd_decode_errors_rule(int L, const uint32_t *d_links, const uint64_t *d_mov
   return decode_links_rule(L, d_links, d_move_seeds, n, T_max, m_max, u, d_T_dec, d_flags, d_final_syndrome, stream);
 }
 
-int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact, int m_max,
-                   int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
+static int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact, int m_max,
+                   int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream, int open = 0) {
   if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
   if (t_exact < 0 || t_exact > MPD_T_MAX_LIMIT) return fail_with(MPD_ERR_TMAX, "t_exact out of range");
   const int rc = check_rule(m_max, u);
@@ -1717,6 +1751,8 @@ int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds,
   a.m_max = m_max;
   a.u = u;
   a.move_seeds = d_move_seeds;
+  a.open = open;
+  if (open && !open_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported on the open lattice (3..128)", L);
   return launch_resident(a, (hipStream_t)stream);
 }
 
@@ -1730,6 +1766,48 @@ int mpd_run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_se
                        int m_max, int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
   g_last_error.clear();
   return run_steps_rule(L, d_links, d_move_seeds, n, t_exact, m_max, u, d_m_out, d_sigma_out, d_wind_out, stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// Open lattice (rough left / right boundaries), resident kernel only
+// ---------------------------------------------------------------------------
+
+int mpd_decode_open(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                    uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream) {
+  g_last_error.clear();
+  if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
+  const int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (!open_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported on the open lattice (3..128)", L);
+  if (n == 0) return MPD_OK;
+  if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u)) return fail_with(MPD_ERR_PTR, "seeds NULL or misaligned");
+  if (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u))
+    return fail_with(MPD_ERR_PTR, "final_syndrome misaligned");
+  ResidentArgs a = {};
+  a.L = L;
+  a.n = n;
+  a.seeds = d_seeds;
+  a.thr = threshold_of(p);
+  a.T_max = T_max;
+  a.t_exact = -1;
+  a.T_dec = d_T_dec;
+  a.flags = d_flags;
+  a.syn = d_final_syndrome;
+  a.open = 1;
+  return launch_resident(a, (hipStream_t)stream);
+}
+
+int mpd_decode_errors_open(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
+                           uint32_t *d_final_syndrome, void *stream) {
+  g_last_error.clear();
+  return decode_links_rule(L, d_links, nullptr, n, T_max, 0, 0, d_T_dec, d_flags, d_final_syndrome, stream, 1);
+}
+
+int mpd_run_steps_open(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
+                       uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  return run_steps_rule(L, d_links, nullptr, n, t_exact, 0, 0, d_m_out, d_sigma_out, d_wind_out, stream, 1);
 }
 
 }  // extern "C"
