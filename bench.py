@@ -64,9 +64,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1024)
-    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn", "rule"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn", "rule", "open"], default="c3",
                     help="c3 (default) is the headline line; c1/c2/c4/c5 print a line for that configuration, "
-                         "cnn times the predictor's kernels, rule the limited-memory variant at L = 256")
+                         "cnn times the predictor's kernels, rule the limited-memory variant at L = 256, open the "
+                         "open lattice at L = 64 and 128")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduling leg")
     ap.add_argument("--streams", type=int, default=None,
                     help="batches in flight, each on its own stream, host thread and workspace (default 3 for "
@@ -347,6 +348,8 @@ def other_workload(args, b, seeds, torch, np):
         return cnn_kernels(args, b, seeds, torch, np)
     if args.workload == "rule":
         return limited_memory(args, b, seeds, torch, np, runner)
+    if args.workload == "open":
+        return open_lattice(args, b, seeds, torch, np)
     if args.workload == "c4":
         Ls, ps, ss = mixed_batch()
         classes = [(L, int((Ls == L).sum())) for L in dict.fromkeys(Ls.tolist())]
@@ -420,6 +423,35 @@ def limited_memory(args, b, seeds, torch, np, runner):
                           "samples_per_s": K * n / dt, "site_updates_per_s": L * L * T.sum() / dt,
                           "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean()),
                           "fail_rate": float((F & 1).mean()), "timeouts": int(((F & 2) > 0).sum())}), flush=True)
+
+
+def open_lattice(args, b, seeds, torch, np):
+    """The open lattice (rough left / right boundaries) against the torus at
+    the same L, p and samples: configuration 2's L = 64 batches at p = 0.01
+    and 0.02, and L = 128 (resident kernel), one batch at a time."""
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    for L, p, n in ((64, 0.01, 10000), (64, 0.02, 10000), (128, 0.01, 2500)):
+        batches = [torch.from_numpy(seeds(9, int(p * 1000), n, start=i * n).view(np.int64)).to(dev)
+                   for i in range(W + K)]
+        line = {"workload": f"open lattice vs torus: L={L} p={p} {n} samples, T_max=4096"}
+        for name, fn in (("open", lambda s: b.decode_open(L, p, s, 4096, want_syndrome=False)),
+                         ("torus", lambda s: b.decode_batch(L, p, s, 4096, want_syndrome=False))):
+            outs = [None] * (W + K)
+            for i in range(W):
+                outs[i] = fn(batches[i])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(W, W + K):
+                outs[i] = fn(batches[i])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
+            F = torch.cat([outs[i][1] for i in range(W, W + K)]).cpu().numpy()
+            line[name] = {"samples_per_s": K * n / dt, "site_updates_per_s": L * L * T.sum() / dt,
+                          "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean()),
+                          "fail_rate": float((F & 1).mean())}
+        print(json.dumps(line), flush=True)
 
 
 def learned_c5(args, b, seeds, torch, np, runner):

@@ -10,7 +10,9 @@ Three measurements, all on i.i.d. bit-flip noise, periodic L x L lattices, v = 3
   T_dec = A ln L + B;
 * with ``--memory``: p_log, timeouts and T_dec of the limited-memory variant
   (Sec. 5.3: messages truncated at m_max, with and without a random move of
-  every anyon every u steps) against m_max at several L.
+  every anyon every u steps) against m_max at several L;
+* with ``--open``: p_log against p on the open lattice (rough left and right
+  boundaries, appendix on open boundaries) and its crossings.
 
 Every sample is decoded by libmpd (noise, decoding and classification run in
 the HIP kernels); this module chooses seeds, sums the per-sample results on
@@ -44,6 +46,8 @@ MEMORY_M = [2, 3, 4, 6, 8, 12, 16, 0]        # 0: no truncation
 MEMORY_U = [0, 8]
 MEMORY_L = [(32, 20000), (64, 10000), (128, 4000)]
 MEMORY_T_MAX = 2048
+OPEN_P = [0.06, 0.07, 0.075, 0.08, 0.085, 0.09, 0.1]
+OPEN_L = [(16, 100000), (32, 50000), (64, 20000), (128, 5000)]
 
 
 def seed_block(L: int, p_index: int, n: int, start: int = 0) -> np.ndarray:
@@ -59,7 +63,8 @@ def _chunk(L: int) -> int:
     return 262144 if L <= 128 else int(max(64, min(8192, (8 << 30) // (17 * L * L))))
 
 
-def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int = 0, u: int = 0) -> dict:
+def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int = 0, u: int = 0,
+          open_bc: bool = False) -> dict:
     """Decode n seeded samples at (L, p) (with the limited-memory variant if
     m_max or u is set); returns the counts and sums of the point.
 
@@ -79,7 +84,9 @@ def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int 
     for a in range(0, n, c):
         m = min(c, n - a)
         s = torch.from_numpy(seed_block(L, p_index, m, a).view(np.int64)).to(dev)
-        if m_max or u:
+        if open_bc:
+            Tm, Fm, _ = b.decode_open(L, p, s, T_max, want_syndrome=False)
+        elif m_max or u:
             Tm, Fm, _ = b.decode_rule(L, p, s, T_max, m_max=m_max, u=u, want_syndrome=False, workspace=ws,
                                       out=(T[:m], F[:m], None))
         else:
@@ -93,7 +100,7 @@ def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fails, timeouts, T_sum, T_sq, T_all = (int(x) for x in v)
-    return dict(L=L, p=p, n=n, T_max=T_max, m_max=m_max, u=u, fails=fails, timeouts=timeouts, T_sum=T_sum,
+    return dict(L=L, p=p, n=n, T_max=T_max, m_max=m_max, u=u, open=open_bc, fails=fails, timeouts=timeouts, T_sum=T_sum,
                 T_sq=T_sq, seconds=dt, site_updates=T_all * L * L)
 
 
@@ -190,6 +197,25 @@ def run_memory(quick: bool = False, log=print) -> list:
     return out
 
 
+def run_open(quick: bool = False, T_max: int = 4096, log=print) -> dict:
+    """p_log against p on the open lattice, and the crossings of consecutive sizes."""
+    scale = 0.05 if quick else 1.0
+    pts = []
+    for L, n in OPEN_L:
+        n = max(256, int(n * scale))
+        for i, p in enumerate(OPEN_P):
+            r = point(L, p, n, 192 + i, T_max, open_bc=True)
+            mt, e = mean_T(r)
+            log(f"open L={L} p={p}: p_log={p_log(r):.5f}±{p_log_err(r):.5f} timeouts={r['timeouts']} "
+                f"T={mt:.3f}±{e:.3f} n={n} {r['seconds']:.2f}s")
+            pts.append(r)
+    Ls = [L for L, _ in OPEN_L]
+    tab = {(r["L"], r["p"]): p_log(r) for r in pts}
+    cross = {f"{L1}/{L2}": crossing(OPEN_P, [tab[(L1, p)] for p in OPEN_P], [tab[(L2, p)] for p in OPEN_P])
+             for L1, L2 in zip(Ls, Ls[1:])}
+    return dict(points=pts, crossings=cross)
+
+
 def summarize(res: dict) -> dict:
     """Crossings of consecutive sizes (all samples, and decoded samples only),
     slopes gamma against the crossing of the two largest sizes, and
@@ -237,10 +263,18 @@ def main(argv=None):
     ap.add_argument("--T-max", type=int, default=4096)
     ap.add_argument("--json", default=None, help="write all counts and fits here")
     ap.add_argument("--memory", action="store_true", help="only the limited-memory grid")
+    ap.add_argument("--open", action="store_true", help="only the open-lattice threshold grid")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         sys.exit("sweep: needs a GPU (the decoder runs only in libmpd's HIP kernels)")
+    if a.open:
+        res = run_open(a.quick, a.T_max, log=lambda s: print(s, flush=True))
+        print(json.dumps(res["crossings"]), flush=True)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     if a.memory:
         res = run_memory(a.quick, log=lambda s: print(s, flush=True))
         if a.json:

@@ -64,3 +64,15 @@ def test_memory_point_matches_oracle(gpu, orc, L, n, m_max, u):
     done = (F & 2) == 0
     assert (r["fails"], r["timeouts"]) == (int((F & 1).sum()), int((~done).sum()))
     assert (r["T_sum"], r["T_sq"]) == (int(T[done].sum()), int((T[done] ** 2).sum()))
+
+
+@pytest.mark.parametrize("L,p,n", [(16, 0.08, 2000), (64, 0.09, 100)])
+def test_open_point_matches_oracle(gpu, orc, L, p, n):
+    """A point of the open-lattice grid: the same counts as the oracle."""
+    r = sweep.point(L, p, n, p_index=203, T_max=1024, open_bc=True)
+    ref = orc.decode_seeds(L, p, sweep.seed_block(L, 203, n), 1024, threads=16, want_sigma=False, open_bc=True)
+    T = ref["T_dec"].astype(np.int64)
+    F = ref["flags"].astype(np.int64)
+    done = (F & 2) == 0
+    assert (r["fails"], r["timeouts"]) == (int((F & 1).sum()), int((~done).sum()))
+    assert (r["T_sum"], r["T_sq"]) == (int(T[done].sum()), int((T[done] ** 2).sum()))
