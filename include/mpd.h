@@ -176,9 +176,13 @@ int mpd_run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_se
  * number of times, or on timeout.  Final syndromes have no bits at B; the
  * state export reports 0 registers at B, and wind bits 0 (error) and 2
  * (correction) on that cut (bits 1 and 3 are 0).  Supported L: 3..128 (the
- * resident kernel); other arguments and errors as the torus calls. */
+ * resident kernel; the explicit-error and state-export forms take only
+ * these), and for mpd_decode_open also multiples of 16 from 256 to 16384
+ * (the band path, either driver; workspace as for mpd_decode_batch).  Other
+ * arguments and errors as the torus calls. */
 int mpd_decode_open(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
-                    uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream);
+                    uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes,
+                    void *stream);
 int mpd_decode_errors_open(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec,
                            uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream);
 int mpd_run_steps_open(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,

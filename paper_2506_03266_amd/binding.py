@@ -53,7 +53,7 @@ def lib():
     L.mpd_decode_errors_rule.restype = I
     L.mpd_run_steps_rule.argtypes = [I, P, P, I64, I, I, I, P, P, P, P]
     L.mpd_run_steps_rule.restype = I
-    L.mpd_decode_open.argtypes = [I, D, P, I64, I, P, P, P, P]
+    L.mpd_decode_open.argtypes = [I, D, P, I64, I, P, P, P, P, SZ, P]
     L.mpd_decode_open.restype = I
     L.mpd_decode_errors_open.argtypes = [I, P, I64, I, P, P, P, P]
     L.mpd_decode_errors_open.restype = I
@@ -212,17 +212,22 @@ def run_steps(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int =
     return M, S, W
 
 
-def decode_open(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True, stream=None):
+def decode_open(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True, workspace=None, out=None,
+                stream=None):
     """Decode seeded noise on the open lattice (rough left / right columns,
-    smooth top / bottom rows), L <= 128."""
+    smooth top / bottom rows): L <= 128 or a multiple of 16 from 256."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()
-    T = torch.empty(n, dtype=torch.int32, device=dev)
-    F = torch.empty(n, dtype=torch.uint8, device=dev)
-    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
-    _check(lib().mpd_decode_open(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _stream_ptr(stream)),
-           "mpd_decode_open")
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    else:
+        T, F, S = out
+    ws = workspace if workspace is not None else alloc_workspace(L, n)
+    _check(lib().mpd_decode_open(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws), ws.numel(),
+                                 _stream_ptr(stream)), "mpd_decode_open")
     return T, F, S
 
 

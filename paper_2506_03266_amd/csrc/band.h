@@ -101,6 +101,27 @@ __device__ __forceinline__ void band_fold(BandLane<H> &b, uint32_t ss, uint32_t 
   }
 }
 
+// Open lattice: before every update, lanes outside the lattice hold
+// nothing, and a rough-boundary column (bL: the lane's first column is
+// x = 0, bR: its second is x = L-1) reads as "emits now" in P, so that the
+// x-registers of its bulk neighbour receive a message of value 1, and as
+// nothing in Q.
+template <int H>
+__device__ __forceinline__ void band_boundary_fold(BandLane<H> &b, uint32_t ss, bool outside, bool bL, bool bR) {
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    if (outside) b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
+    if (bL) {
+      b.P0[h] = ss;
+      b.Q0[h] = 0u;
+    }
+    if (bR) {
+      b.P1[h] = ss;
+      b.Q1[h] = 0u;
+    }
+  }
+}
+
 // One application of A^{(D)} to the band (registers hold folded values on
 // entry and the new emission times on exit).  BND is this sub-step's LDS
 // slot for boundary rows: [wave][2][64] of (P0, Q0, P1, Q1).  With DECIDE

@@ -262,13 +262,17 @@ struct BandArgs {
   const uint64_t *seeds;  // per sample: key of the random moves (read only when u > 0)
 };
 
-// Limited-memory variant of the rule for a batch (see engine.h): kernels are
-// instantiated without it (RULE = false) for the plain rule.
+// Variant of a band-path batch: the limited-memory rule (see engine.h) or
+// the open lattice.  Kernels are instantiated per mode (BAND_PLAIN,
+// BAND_RULE, BAND_OPEN); the plain rule compiles without either.
+enum BandMode { BAND_PLAIN = 0, BAND_RULE = 1, BAND_OPEN = 2 };
 struct Rule {
   int m_max = 0;
   int u = 0;
   const uint64_t *seeds = nullptr;
+  bool open = false;
   bool on() const { return m_max > 0 || u > 0; }
+  int mode() const { return open ? BAND_OPEN : (on() ? BAND_RULE : BAND_PLAIN); }
 };
 
 // One pass of tile `tile` of `sample`, which has done t0 steps: loads the
@@ -279,12 +283,21 @@ struct Rule {
 // Returns, valid in thread 0: x = anyon bits of the owned part (bit 0 at the
 // pass start, bit j after step j), y = winding bits of the correction links
 // the pass flipped there.
-template <int NW, bool RULE>
+//
+// MODE BAND_OPEN: the open lattice (see k_resident): lanes and strips that
+// lie outside [0, L) hold nothing, the rough-boundary columns 0 and L-1
+// publish "emits now" in P and nothing in Q before every update (a boundary
+// fold, run only by waves that hold such lanes), hold no anyon, and the
+// full-height region (ty == L) reads a zero slot instead of its wrapped
+// outer rows.  The correction winding is read on the x-links from column
+// L-2 to L-1.
+template <int NW, int MODE>
 __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sample, int t0, const uint4 *Esrc,
                                              const uint2 *Ssrc, uint4 *Edst, uint2 *Sdst) {
+  constexpr bool RULE = MODE == BAND_RULE, OPEN = MODE == BAND_OPEN;
   extern __shared__ __align__(16) unsigned char smem[];
-  uint4 *BND = reinterpret_cast<uint4 *>(smem);                   // [2][NW*2*64]
-  uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * NW * 2 * 64);  // [NW*64]
+  uint4 *BND = reinterpret_cast<uint4 *>(smem);                         // [2][(NW+1)*2*64], slot NW stays 0
+  uint2 *MB = reinterpret_cast<uint2 *>(BND + 2 * (NW + 1) * 2 * 64);  // [NW*64]
   uint32_t *red = reinterpret_cast<uint32_t *>(MB + NW * 64);      // [16]
   uint32_t *AW = red + 16;  // [16] per step of the pass: nonzero if anyons are left after it
   constexpr int H = BAND_H;
@@ -298,14 +311,26 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
 
   const bool wrapY = a.ty == L;
   const int tix = tile % a.ntx, tiy = tile / a.ntx;
-  const int wdn = w == 0 ? (wrapY ? NW - 1 : 0) : w - 1;
-  const int wup = w == NW - 1 ? (wrapY ? 0 : NW - 1) : w + 1;
+  // neighbour strips (wrapped in a full-height region); for the message
+  // updates the open full-height region reads the zero slot NW instead of
+  // its wrapped outer rows (no move ever crosses those rows, so the move
+  // exchange may keep the wrapped neighbours)
+  const int wdn_f = w == 0 ? (wrapY ? NW - 1 : 0) : w - 1;
+  const int wup_f = w == NW - 1 ? (wrapY ? 0 : NW - 1) : w + 1;
+  const int wdn = (OPEN && wrapY && w == 0) ? NW : wdn_f;
+  const int wup = (OPEN && wrapY && w == NW - 1) ? NW : wup_f;
+  if (OPEN && threadIdx.x < 4 * 64) BND[(threadIdx.x >> 7) * (NW + 1) * 2 * 64 + NW * 2 * 64 + (threadIdx.x & 127)] =
+      make_uint4(0u, 0u, 0u, 0u);
   // global column of this lane's first column, global row of the wave's first row
   const int tx0 = tix * a.tx, ty0 = tiy * a.ty;
-  int gx = tx0 - a.hx + 2 * lane;
-  gx = gx < 0 ? gx + L : (gx >= L ? gx - L : gx);
-  int gy = (wrapY ? 0 : ty0 - a.hy) + w * H;
-  gy = gy < 0 ? gy + L : (gy >= L ? gy - L : gy);
+  const int gx_raw = tx0 - a.hx + 2 * lane;
+  int gx = gx_raw < 0 ? gx_raw + L : (gx_raw >= L ? gx_raw - L : gx_raw);
+  const int gy_raw = (wrapY ? 0 : ty0 - a.hy) + w * H;
+  int gy = gy_raw < 0 ? gy_raw + L : (gy_raw >= L ? gy_raw - L : gy_raw);
+  // open lattice: lanes / strips outside the lattice, rough-boundary columns of this lane
+  const bool outside = OPEN && (gx_raw < 0 || gx_raw >= L || gy_raw < 0 || gy_raw >= L);
+  const bool bL = OPEN && gx_raw == 0, bR = OPEN && gx_raw == L - 2;
+  const bool edge_wave = OPEN && __builtin_amdgcn_ballot_w64(outside || bL || bR) != 0ull;
   const int owned_w = min(a.tx, L - tx0);
   const bool own_col = 2 * lane >= a.hx && 2 * lane < a.hx + owned_w;
   // owned rows of this wave (wave-uniform); a strip never straddles row L-1 -> 0
@@ -317,8 +342,8 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
     for (int h = 0; h < H; ++h) own_rows |= (uint32_t)(r0 + h >= 0 && r0 + h < owned_h) << h;
   own_rows = __builtin_amdgcn_readfirstlane(own_rows);
   const bool own = own_col && own_rows != 0u;
-  const bool top = gy == L - H && ((own_rows >> (H - 1)) & 1u);  // owns row L-1 (bit H-1)
-  const bool last_col = own_col && gx == L - 2;                   // column L-1 is the second column
+  const bool top = !OPEN && gy == L - H && ((own_rows >> (H - 1)) & 1u);  // owns row L-1 (bit H-1)
+  const bool last_col = own_col && gx == L - 2;  // torus: column L-1 is the second column; open: L-2 the first
 
   BandLane<H> b;
   uint32_t wind = 0u;
@@ -343,10 +368,15 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
     b.s0 = sv.x;
     b.s1 = sv.y;
   }
+  if (OPEN) {  // nothing outside the lattice, no anyon on B
+    if (outside) b.s0 = b.s1 = 0u;
+    if (bL) b.s0 = 0u;
+    if (bR) b.s1 = 0u;
+  }
 
   const uint32_t own_mask = own_col ? own_rows : 0u;
   uint32_t bits = __syncthreads_or(((b.s0 | b.s1) & own_mask) != 0u) ? 1u : 0u;
-  uint4 *BND0 = BND, *BND1 = BND + NW * 2 * 64;
+  uint4 *BND0 = BND, *BND1 = BND + (NW + 1) * 2 * 64;
   uint32_t mk0 = 0u, mk1 = 0u;  // key of the random moves
   if (RULE && a.u > 0) {
     const uint64_t ms = a.seeds[sample];
@@ -361,18 +391,26 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
     // three message updates; LDS boundary slots alternate between sub-steps
     uint4 *slot_a = (st & 1) ? BND1 : BND0, *slot_b = (st & 1) ? BND0 : BND1;
     if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16), rows);
+    if (OPEN && edge_wave) band_boundary_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16), outside, bL, bR);
     band_substep<H, false>(b, slot_a, w, wdn, wup, lane, rows, 1u, mv);
     if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), rows);
+    if (OPEN && edge_wave) band_boundary_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), outside, bL, bR);
     band_substep<H, false>(b, slot_b, w, wdn, wup, lane, rows, 1u, mv);
     if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), rows);
+    if (OPEN && edge_wave) band_boundary_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), outside, bL, bR);
     band_substep<H, true>(b, slot_a, w, wdn, wup, lane, rows, RULE ? live_threshold(t3 + 3u, a.m_max) : 1u, mv);
     if (RULE && a.u > 0 && t1 % (uint32_t)a.u == 0u) {  // random-move step (wave-uniform): replaces the decisions
       mv = {0u, 0u, 0u, 0u};
       band_random_moves<H>(b, rows, gx, gy, L, t1, mk0, mk1, mv);
     }
     uint32_t xo[2], yo[2];
-    band_feedback<H>(b, mv, MB, w, wdn, wup, lane, xo, yo);
-    if (last_col) wind ^= (__popc(xo[1] & own_rows) & 1u) << 2;
+    band_feedback<H>(b, mv, MB, w, wdn_f, wup_f, lane, xo, yo);
+    if (OPEN) {  // anyons moved onto B are absorbed
+      if (bL) b.s0 = 0u;
+      if (bR) b.s1 = 0u;
+      if (outside) b.s0 = b.s1 = 0u;
+    }
+    if (last_col) wind ^= (__popc(xo[OPEN ? 0 : 1] & own_rows) & 1u) << 2;
     if (own_col && top) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
     // anyons left after this step: waves OR into the step's flag, read after
     // the pass (no barrier of its own)
@@ -397,12 +435,12 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
 }
 
 // One pass over the samples in a.active: grid (tiles, samples).
-template <int NW, bool RULE>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
   const int sample = a.active[blockIdx.y];
   if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
   const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
-  const uint2 r = band_region<NW, RULE>(a, blockIdx.x, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
+  const uint2 r = band_region<NW, MODE>(a, blockIdx.x, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
   if (threadIdx.x == 0) {
     if (r.x) atomicOr(&a.alive[sample], r.x);
     if (r.y) atomicXor(&a.wind[sample], r.y);
@@ -412,7 +450,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(BandArgs a) {
 // One pass over survivors whose number is only known on the device
 // (*count): (sample, tile) tasks in a grid-stride loop, each as one k_band
 // workgroup.  Workgroups never wait for each other.
-template <int NW, bool RULE>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_band_grid(BandArgs a, const int *count, int ntiles) {
   if (a.zero_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_count = 0;
   const int64_t ntask = (int64_t)(*count) * ntiles;
@@ -421,7 +459,7 @@ __global__ __launch_bounds__(NW * 64) void k_band_grid(BandArgs a, const int *co
     const int i = (int)(task / ntiles), tile = (int)(task % ntiles);
     const int sample = a.active[i];
     const int t0 = __builtin_amdgcn_readfirstlane(a.t_done[sample]);
-    const uint2 r = band_region<NW, RULE>(a, tile, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
+    const uint2 r = band_region<NW, MODE>(a, tile, sample, t0, a.Esrc, a.Ssrc, a.Edst, a.Sdst);
     if (threadIdx.x == 0) {
       if (r.x) atomicOr(&a.alive[sample], r.x);
       if (r.y) atomicXor(&a.wind[sample], r.y);
@@ -449,7 +487,7 @@ struct TailArgs {
   uint8_t *status;
 };
 
-template <int NW, bool RULE>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
   __shared__ int s_take, s_more;
   __shared__ uint32_t s_bits, s_wind;
@@ -472,7 +510,7 @@ __global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
       }
       for (int tile = 0; tile < ta.ntiles; ++tile) {
         __syncthreads();  // the LDS slots of the previous tile are no longer read
-        const uint2 r = band_region<NW, RULE>(a, tile, s, t0, ta.E[c], ta.S[c], ta.E[c ^ 1], ta.S[c ^ 1]);
+        const uint2 r = band_region<NW, MODE>(a, tile, s, t0, ta.E[c], ta.S[c], ta.E[c ^ 1], ta.S[c ^ 1]);
         if (threadIdx.x == 0) {
           s_bits |= r.x;
           s_wind ^= r.y;
@@ -518,9 +556,15 @@ __global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
 // of anyons in every 8x8 block as uint8 [n][L/8][L/8].  Links that cross into another workgroup (the y-links of
 // the row below the group, the x-links left of its first column when the
 // group is narrower than the lattice) are drawn again from the generator.
+// With OPEN, links of the open lattice that do not exist are dropped (the
+// x-links leaving column L-1, the y-links leaving row L-1 and those of the
+// boundary columns 0 and L-1), the boundary columns carry no syndrome, and
+// the error winding is read on the x-links from column L-2.
+template <bool OPEN>
 __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const uint64_t *seeds, uint64_t thr,
                                                      const double *p_arr, uint2 *Sout, uint32_t *wind,
                                                      uint8_t *counts) {
+  constexpr bool open = OPEN;
   extern __shared__ __align__(16) unsigned char smem[];
   const int P = L / 2;                                  // column pairs of the lattice
   const int NB = CP / 4;                                // 8-column blocks of the group
@@ -548,14 +592,24 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
     ex1 |= (uint32_t)((uint64_t)r.w2 < t) << h;
     ey1 |= (uint32_t)((uint64_t)r.w3 < t) << h;
   }
+  if (open) {
+    if (q == P - 1) ex1 = 0u;                       // x-links leaving column L-1
+    if (q == 0) ey0 = 0u;                           // column 0 is the boundary
+    if (q == P - 1) ey1 = 0u;                       // column L-1 is the boundary
+    if (y0 + TILE_H == L) {                         // y-links leaving row L-1
+      ey0 &= ~(1u << (TILE_H - 1));
+      ey1 &= ~(1u << (TILE_H - 1));
+    }
+  }
   uint32_t eyd = 0u;  // y-links of the row below the strip (bit 0 col 0, bit 1 col 1)
-  if (jl == 0) {      // that row belongs to another workgroup
+  if (jl == 0 && !(open && y0 == 0)) {  // that row belongs to another workgroup
     const int yb = y0 == 0 ? L - 1 : y0 - 1;
     const Words4 r = philox4x32_10((uint32_t)(yb * L + gx) >> 1, k0, k1);
     eyd = (uint32_t)((uint64_t)r.w1 < t) | ((uint32_t)((uint64_t)r.w3 < t) << 1);
+    if (open) eyd &= (q == 0 ? 2u : 3u) & (q == P - 1 ? 1u : 3u);
   }
   uint32_t exl = 0u;  // x-links entering column 2q from the left
-  if (ql == 0 && CP < P) {
+  if (ql == 0 && CP < P && !(open && q == 0)) {
     const int xl = gx == 0 ? L - 2 : gx - 2;  // pair holding column 2q-1 as its second column
 #pragma unroll 4
     for (int h = 0; h < TILE_H; ++h) {
@@ -569,12 +623,20 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
   if (ql > 0 || CP == P) exl = ex1s[jl * CP + (ql == 0 ? CP - 1 : ql - 1)];
   if (jl > 0) eyd = eyts[(jl - 1) * CP + ql];
   constexpr uint32_t F = full_mask<TILE_H>();
-  const uint32_t s0 = (ex0 ^ exl ^ ey0 ^ ((ey0 << 1) | (eyd & 1u))) & F;
-  const uint32_t s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | (eyd >> 1))) & F;
+  uint32_t s0 = (ex0 ^ exl ^ ey0 ^ ((ey0 << 1) | (eyd & 1u))) & F;
+  uint32_t s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | (eyd >> 1))) & F;
+  if (open) {  // the boundary columns carry no syndrome
+    if (q == 0) s0 = 0u;
+    if (q == P - 1) s1 = 0u;
+  }
   if (Sout != nullptr) Sout[((size_t)sample * (L / TILE_H) + j) * P + q] = make_uint2(s0, s1);
   uint32_t wd = 0u;
-  if (q == P - 1) wd ^= __popc(ex1) & 1u;                                  // x-links leaving column L-1
-  if (j == L / TILE_H - 1) wd ^= (((ey0 ^ ey1) >> (TILE_H - 1)) & 1u) << 1;  // y-links leaving row L-1
+  if (open) {
+    if (q == P - 1) wd ^= __popc(ex0) & 1u;  // x-links from column L-2 to L-1
+  } else {
+    if (q == P - 1) wd ^= __popc(ex1) & 1u;                                  // x-links leaving column L-1
+    if (j == L / TILE_H - 1) wd ^= (((ey0 ^ ey1) >> (TILE_H - 1)) & 1u) << 1;  // y-links leaving row L-1
+  }
   if (wd) atomicXor(&red[0], wd);
   if (counts != nullptr) {
     const int bx = ql / 4;  // 8 columns = 4 pairs per block
@@ -725,8 +787,8 @@ size_t resident_lds(int L, int H, bool open = false) {
   return (size_t)L * (open ? L + 1 : L) * sizeof(uint2) + (size_t)L * (L / H) * sizeof(uint4) + 64;
 }
 
-size_t band_lds(int nw) {
-  return (size_t)2 * nw * 2 * 64 * sizeof(uint4) + (size_t)nw * 64 * sizeof(uint2) + 64 + 64;
+size_t band_lds(int nw) {  // boundary slots of nw strips plus a zero slot, move masks, flags
+  return (size_t)2 * (nw + 1) * 2 * 64 * sizeof(uint4) + (size_t)nw * 64 * sizeof(uint2) + 64 + 64;
 }
 
 template <int H>
@@ -850,14 +912,18 @@ NoiseShape noise_shape(int L) {
 
 // Noise, syndrome and bookkeeping of a band-path batch (before the passes).
 int band_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, const BandWorkspace &w,
-               uint8_t *d_counts, hipStream_t stream) {
+               uint8_t *d_counts, hipStream_t stream, int open = 0) {
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
                      w.status, w.t_done, w.active[0], &w.count[2]);
   HIP_TRY(hipGetLastError());
   const NoiseShape g = noise_shape(L);
   ProfScope ps("k_band_noise", stream);
-  hipLaunchKernelGGL(k_band_noise, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, stream, L, g.CP, g.S,
-                     d_seeds, thr, d_p, w.S[0], w.wind, d_counts);
+  if (open)
+    hipLaunchKernelGGL(k_band_noise<true>, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, stream, L, g.CP,
+                       g.S, d_seeds, thr, d_p, w.S[0], w.wind, d_counts);
+  else
+    hipLaunchKernelGGL(k_band_noise<false>, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, stream, L, g.CP,
+                       g.S, d_seeds, thr, d_p, w.S[0], w.wind, d_counts);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -932,16 +998,23 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   {
     ProfScope ps("k_band", stream);
     const dim3 grid((unsigned)(ba.ntx * nty), (unsigned)nact);
-    if (small && rule.on())
-      hipLaunchKernelGGL((k_band<BAND_NW_SMALL, true>), grid, dim3(BAND_NW_SMALL * 64), band_lds(BAND_NW_SMALL),
-                         stream, ba);
-    else if (small)
-      hipLaunchKernelGGL((k_band<BAND_NW_SMALL, false>), grid, dim3(BAND_NW_SMALL * 64), band_lds(BAND_NW_SMALL),
-                         stream, ba);
-    else if (rule.on())
-      hipLaunchKernelGGL((k_band<BAND_NW, true>), grid, dim3(BAND_NW * 64), band_lds(BAND_NW), stream, ba);
-    else
-      hipLaunchKernelGGL((k_band<BAND_NW, false>), grid, dim3(BAND_NW * 64), band_lds(BAND_NW), stream, ba);
+    if (small) {
+      const dim3 blk(BAND_NW_SMALL * 64);
+      const size_t lds = band_lds(BAND_NW_SMALL);
+      switch (rule.mode()) {
+        case BAND_RULE: hipLaunchKernelGGL((k_band<BAND_NW_SMALL, BAND_RULE>), grid, blk, lds, stream, ba); break;
+        case BAND_OPEN: hipLaunchKernelGGL((k_band<BAND_NW_SMALL, BAND_OPEN>), grid, blk, lds, stream, ba); break;
+        default: hipLaunchKernelGGL((k_band<BAND_NW_SMALL, BAND_PLAIN>), grid, blk, lds, stream, ba);
+      }
+    } else {
+      const dim3 blk(BAND_NW * 64);
+      const size_t lds = band_lds(BAND_NW);
+      switch (rule.mode()) {
+        case BAND_RULE: hipLaunchKernelGGL((k_band<BAND_NW, BAND_RULE>), grid, blk, lds, stream, ba); break;
+        case BAND_OPEN: hipLaunchKernelGGL((k_band<BAND_NW, BAND_OPEN>), grid, blk, lds, stream, ba); break;
+        default: hipLaunchKernelGGL((k_band<BAND_NW, BAND_PLAIN>), grid, blk, lds, stream, ba);
+      }
+    }
   }
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, stream, k, T_max, cur ^ 1, active,
@@ -1020,12 +1093,18 @@ int band_tail(BandRun &r, int64_t first_count) {
     const int64_t grid = std::min<int64_t>(first_count * ntiles, cu_count());
     {
       ProfScope ps("k_band_grid", r.stream);
-      if (r.rule.on())
-        hipLaunchKernelGGL((k_band_grid<BAND_NW, true>), dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
-                           r.stream, ba, (const int *)&r.w.count[cur], ntiles);
-      else
-        hipLaunchKernelGGL((k_band_grid<BAND_NW, false>), dim3((unsigned)grid), dim3(BAND_NW * 64),
-                           band_lds(BAND_NW), r.stream, ba, (const int *)&r.w.count[cur], ntiles);
+      const dim3 g((unsigned)grid), blk(BAND_NW * 64);
+      const size_t lds = band_lds(BAND_NW);
+      const int *cnt = &r.w.count[cur];
+      switch (r.rule.mode()) {
+        case BAND_RULE:
+          hipLaunchKernelGGL((k_band_grid<BAND_NW, BAND_RULE>), g, blk, lds, r.stream, ba, cnt, ntiles);
+          break;
+        case BAND_OPEN:
+          hipLaunchKernelGGL((k_band_grid<BAND_NW, BAND_OPEN>), g, blk, lds, r.stream, ba, cnt, ntiles);
+          break;
+        default: hipLaunchKernelGGL((k_band_grid<BAND_NW, BAND_PLAIN>), g, blk, lds, r.stream, ba, cnt, ntiles);
+      }
     }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((first_count + 255) / 256)), dim3(256), 0, r.stream, k, r.T_max,
@@ -1053,12 +1132,13 @@ int band_tail(BandRun &r, int64_t first_count) {
   const int64_t grid = std::min<int64_t>(first_count, cu_count());
   if (grid > 0) {
     ProfScope ps("k_band_tail", r.stream);
-    if (r.rule.on())
-      hipLaunchKernelGGL((k_band_tail<BAND_NW, true>), dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
-                         r.stream, ta);
-    else
-      hipLaunchKernelGGL((k_band_tail<BAND_NW, false>), dim3((unsigned)grid), dim3(BAND_NW * 64), band_lds(BAND_NW),
-                         r.stream, ta);
+    const dim3 g((unsigned)grid), blk(BAND_NW * 64);
+    const size_t lds = band_lds(BAND_NW);
+    switch (r.rule.mode()) {
+      case BAND_RULE: hipLaunchKernelGGL((k_band_tail<BAND_NW, BAND_RULE>), g, blk, lds, r.stream, ta); break;
+      case BAND_OPEN: hipLaunchKernelGGL((k_band_tail<BAND_NW, BAND_OPEN>), g, blk, lds, r.stream, ta); break;
+      default: hipLaunchKernelGGL((k_band_tail<BAND_NW, BAND_PLAIN>), g, blk, lds, r.stream, ta);
+    }
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_band_export, dim3((unsigned)r.n), dim3(256), 0, r.stream, r.L, r.n, r.w.status, r.w.wind,
@@ -1155,15 +1235,15 @@ int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_
   r.fp.list[0] = r.w.active[0];
   r.fp.count[0] = (int)n;
   r.fp.k[0] = schedule_for(L).k_first;
-  return band_start(L, thr, d_p, d_seeds, n, r.w, nullptr, stream);
+  return band_start(L, thr, d_p, d_seeds, n, r.w, nullptr, stream, r.rule.open ? 1 : 0);
 }
 
 int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
                 int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, const Rule &rule, hipStream_t stream) {
   BandRun r;
+  r.rule = rule;
   const int rc = band_setup(r, L, thr, d_p, d_seeds, n, T_max, d_T_dec, d_flags, d_syn, ws, stream);
   if (rc != MPD_OK) return rc;
-  r.rule = rule;
   return band_passes(&r, 1);
 }
 
@@ -1368,9 +1448,9 @@ int mpd_syndrome_counts(int L, double p, const double *d_p, const uint64_t *d_se
   if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u) || d_counts == nullptr || ((uintptr_t)d_p & 7u))
     return fail_with(MPD_ERR_PTR, "seeds/counts NULL or misaligned");
   const NoiseShape g = noise_shape(L);
-  hipLaunchKernelGGL(k_band_noise, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds, (hipStream_t)stream, L,
-                     g.CP, g.S, d_seeds, threshold_of(d_p ? 0.0 : p), d_p, (uint2 *)nullptr, (uint32_t *)nullptr,
-                     d_counts);
+  hipLaunchKernelGGL(k_band_noise<false>, dim3((unsigned)(n * g.groups)), dim3(g.CP * g.S), g.lds,
+                     (hipStream_t)stream, L, g.CP, g.S, d_seeds, threshold_of(d_p ? 0.0 : p), d_p, (uint2 *)nullptr,
+                     (uint32_t *)nullptr, d_counts);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -1774,28 +1854,41 @@ int mpd_run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_se
 // ---------------------------------------------------------------------------
 
 int mpd_decode_open(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
-                    uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream) {
+                    uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream) {
   g_last_error.clear();
   if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
   const int rc = check_common(L, n, T_max, d_T_dec, d_flags);
   if (rc) return rc;
-  if (!open_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported on the open lattice (3..128)", L);
+  if (!open_ok(L) && !tiled_ok(L))
+    return fail_with(MPD_ERR_L, "L=%d unsupported on the open lattice (3..128, or a multiple of 16 in [256, 16384])",
+                     L);
   if (n == 0) return MPD_OK;
   if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u)) return fail_with(MPD_ERR_PTR, "seeds NULL or misaligned");
   if (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u))
     return fail_with(MPD_ERR_PTR, "final_syndrome misaligned");
-  ResidentArgs a = {};
-  a.L = L;
-  a.n = n;
-  a.seeds = d_seeds;
-  a.thr = threshold_of(p);
-  a.T_max = T_max;
-  a.t_exact = -1;
-  a.T_dec = d_T_dec;
-  a.flags = d_flags;
-  a.syn = d_final_syndrome;
-  a.open = 1;
-  return launch_resident(a, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (open_ok(L)) {
+    ResidentArgs a = {};
+    a.L = L;
+    a.n = n;
+    a.seeds = d_seeds;
+    a.thr = threshold_of(p);
+    a.T_max = T_max;
+    a.t_exact = -1;
+    a.T_dec = d_T_dec;
+    a.flags = d_flags;
+    a.syn = d_final_syndrome;
+    a.open = 1;
+    return launch_resident(a, st);
+  }
+  const size_t need = mpd_workspace_bytes(L, n);
+  if (ws_bytes < need || d_workspace == nullptr)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  Rule rule;
+  rule.open = true;
+  return decode_band(L, threshold_of(p), nullptr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace,
+                     rule, st);
 }
 
 int mpd_decode_errors_open(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec, uint8_t *d_flags,

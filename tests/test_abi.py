@@ -202,11 +202,12 @@ def test_rule_arguments_rejected(lib):
 
 def test_open_arguments_rejected(lib):
     dummy = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
-    assert lib.mpd_decode_open(256, 0.1, dummy, 4, 8, dummy, dummy, None, None) == -1
-    assert lib.mpd_decode_open(2, 0.1, dummy, 4, 8, dummy, dummy, None, None) == -1
-    assert lib.mpd_decode_open(16, -0.5, dummy, 4, 8, dummy, dummy, None, None) == -2
-    assert lib.mpd_decode_open(16, 0.1, None, 4, 8, dummy, dummy, None, None) == -4
-    assert lib.mpd_decode_open(16, 0.1, dummy, 0, 8, dummy, dummy, None, None) == 0
+    assert lib.mpd_decode_open(200, 0.1, dummy, 4, 8, dummy, dummy, None, None, 0, None) == -1
+    assert lib.mpd_decode_open(2, 0.1, dummy, 4, 8, dummy, dummy, None, None, 0, None) == -1
+    assert lib.mpd_decode_open(16, -0.5, dummy, 4, 8, dummy, dummy, None, None, 0, None) == -2
+    assert lib.mpd_decode_open(16, 0.1, None, 4, 8, dummy, dummy, None, None, 0, None) == -4
+    assert lib.mpd_decode_open(16, 0.1, dummy, 0, 8, dummy, dummy, None, None, 0, None) == 0
+    assert lib.mpd_decode_open(256, 0.1, dummy, 4, 8, dummy, dummy, None, None, 0, None) == -5  # workspace
     assert lib.mpd_decode_errors_open(16, None, 4, 8, dummy, dummy, None, None) == -4
     assert lib.mpd_run_steps_open(16, dummy, 4, 3, None, dummy, dummy, None) == -4
     assert lib.mpd_run_steps_open(200, dummy, 4, 3, dummy, dummy, dummy, None) == -1

@@ -92,3 +92,21 @@ def test_open_run_steps_state(gpu, orc, L):
             assert np.array_equal(S[k], orc.pack_bits((sig == -1).reshape(-1))), (t, k)
             assert (int(W[k]) >> 2) == int(cx[:, L - 2].sum() % 2), (t, k)
             assert int(W[k]) & 0b1010 == 0
+
+
+@pytest.mark.parametrize("driver", ["host", "device"])
+@pytest.mark.parametrize("L,p,n,T_max", [(256, 0.03, 8, 64), (256, 0.07, 6, 40), (256, 0.02, 100, 64),
+                                         (272, 0.05, 4, 48), (320, 0.06, 3, 30), (512, 0.04, 3, 40),
+                                         (256, 0.0, 4, 16), (256, 1.0, 2, 16)])
+def test_open_band_matches_oracle(gpu, orc, driver, L, p, n, T_max):
+    """The band path on the open lattice: full-height and 2D tiles, small and
+    full-size regions, budgets ending inside passes, both drivers; p = 1
+    flips every existing link (no syndrome, a crossing of every row)."""
+    gpu.set_band_driver(gpu.BAND_DRIVER_HOST if driver == "host" else gpu.BAND_DRIVER_DEVICE)
+    try:
+        s = seeds(133, L + T_max, n)
+        T, F, S = gpu.decode_open(L, p, s, T_max)
+    finally:
+        gpu.set_band_driver(gpu.BAND_DRIVER_AUTO)
+    ref = orc.decode_seeds(L, p, s, T_max, threads=16, open_bc=True)
+    compare(f"open band L={L} p={p} {driver}", T, F, S, ref)
