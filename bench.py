@@ -427,16 +427,17 @@ def limited_memory(args, b, seeds, torch, np, runner):
 
 def open_lattice(args, b, seeds, torch, np):
     """The open lattice (rough left / right boundaries) against the torus at
-    the same L, p and samples: configuration 2's L = 64 batches at p = 0.01
-    and 0.02, and L = 128 (resident kernel), one batch at a time."""
+    the same L, p and samples: L = 64 at p = 0.01 and 0.02 and L = 128 on the
+    resident kernel, L = 256 on the band path, one batch at a time."""
     dev = torch.device("cuda:0")
     K, W = args.steps, args.warmup
-    for L, p, n in ((64, 0.01, 10000), (64, 0.02, 10000), (128, 0.01, 2500)):
+    for L, p, n in ((64, 0.01, 10000), (64, 0.02, 10000), (128, 0.01, 2500), (256, 0.01, 4096)):
         batches = [torch.from_numpy(seeds(9, int(p * 1000), n, start=i * n).view(np.int64)).to(dev)
                    for i in range(W + K)]
         line = {"workload": f"open lattice vs torus: L={L} p={p} {n} samples, T_max=4096"}
-        for name, fn in (("open", lambda s: b.decode_open(L, p, s, 4096, want_syndrome=False)),
-                         ("torus", lambda s: b.decode_batch(L, p, s, 4096, want_syndrome=False))):
+        ws = b.alloc_workspace(L, n)
+        for name, fn in (("open", lambda s: b.decode_open(L, p, s, 4096, want_syndrome=False, workspace=ws)),
+                         ("torus", lambda s: b.decode_batch(L, p, s, 4096, want_syndrome=False, workspace=ws))):
             outs = [None] * (W + K)
             for i in range(W):
                 outs[i] = fn(batches[i])

@@ -47,7 +47,7 @@ MEMORY_U = [0, 8]
 MEMORY_L = [(32, 20000), (64, 10000), (128, 4000)]
 MEMORY_T_MAX = 2048
 OPEN_P = [0.06, 0.07, 0.075, 0.08, 0.085, 0.09, 0.1]
-OPEN_L = [(16, 100000), (32, 50000), (64, 20000), (128, 5000)]
+OPEN_L = [(16, 100000), (32, 50000), (64, 20000), (128, 5000), (256, 3000), (512, 1500)]
 
 
 def seed_block(L: int, p_index: int, n: int, start: int = 0) -> np.ndarray:
