@@ -16,4 +16,7 @@ from .oracle import (  # noqa: F401
     pack_bits,
     links_from_chains,
     decode_links,
+    ring_threshold,
+    async_run,
+    async_decode_seeds,
 )

@@ -82,6 +82,39 @@
  *       columns L-2 and L-1 an odd number of times (a string from B_L to
  *       B_R); timeouts count as failures.
  *
+ * Marching-soldiers desynchronization (Sec. "Desynchronization and
+ * Lindbladian dynamics"), an optional asynchronous driver of the plain rule
+ * on the torus:
+ *   R23 each decoder step is v + 1 automaton updates of a site: v message
+ *       updates, then one feedback update that applies F to the two links
+ *       the site owns (r -> r + x-hat, r -> r + y-hat).  The definition
+ *       applies feedback together with the v-th update; its own update slot
+ *       keeps v message updates per feedback and makes the simulated
+ *       dynamics exactly F o A^v of R6.  t_sim counts these updates.
+ *   R24 Delta = 1 (A and F read the 3 x 3 block around a site and F writes
+ *       inside it); an update of r is accepted iff t_sim(q) >= t_sim(r) for
+ *       every q != r with |q - r|_inf <= 2 Delta; a rejected one does nothing.
+ *   R25 per-site state: m^old, m^new, the physical syndrome sigma and two
+ *       flip parities acc[k mod 2] (flips applied at the site by the feedback
+ *       of step k).  The present view of a neighbour q is m^new_q when level
+ *       with r and m^old_q when one update ahead; a feedback update of step
+ *       k reads sigma_q (-1)^{acc[k mod 2]_q}, a message update sigma_q as it
+ *       is; a site's first update of step k clears its acc[(k-1) mod 2].  This
+ *       stores what sigma^old, sigma^new and sigma^future store, with the
+ *       reset tied to the site's own progress as in the definition.
+ *   R26 clock: time runs in slots; in slot s site i rings iff word 2(i&1) of
+ *       Philox4x32-10(key = seed, counter = (i >> 1, s, 0x41535943, 0)) is
+ *       below ring_thr (a probability times 2^32), and ringing sites attempt
+ *       one update each in increasing order of (word 2(i&1)+1, i).  As the
+ *       probability goes to 0 with slots of that length this is the
+ *       independent rate-1 Poisson clocks the section names as an example;
+ *       the simulated decoder does not depend on the order (Prop. "faithful
+ *       Lindbladian simulation").
+ *   R27 a desynchronized decode ends at the first slot boundary where the
+ *       physical syndrome holds no anyon and no acc bit is set: every view
+ *       then holds no anyon, so no link can flip again.  T_async = 1 + the
+ *       last slot with a flip (0 if none); outcome as R10, R11.
+ *
  * Site index i = y*L + x.  The x-link of site (x,y) joins (x,y) and
  * (x+1,y); its y-link joins (x,y) and (x,y+1) (indices mod L).
  * Register order in every array: d = 0: +x, 1: -x, 2: +y, 3: -y, i.e.
@@ -234,51 +267,50 @@ static void orc_syndrome(orc_state *st, const uint8_t *ex, const uint8_t *ey) {
     }
 }
 
-/* One application of A^{(D)}, D = 2, to every register simultaneously.
- * For direction (s,a) the register at r reads the line C^{(a)}_{r - s a}:
+/* The value A^{(D)}, D = 2, gives register d of site (x, y) from the
+ * registers m and syndrome sigma it reads.  For direction (s,a) the
+ * register at r reads the line C^{(a)}_{r - s a}:
  *   1                                  if an anyon sits on the line,
  *   0                                  if every register on it is 0,
  *   (min of the nonzero registers) + 1 otherwise (R1, R2). */
+static int32_t orc_register_value(const orc_state *st, int32_t *const m[4], const int8_t *sigma, int d, int x,
+                                  int y) {
+  int L = st->L;
+  int s = DIR_S[d], a = DIR_A[d];
+  int ax = (a == 1), ay = (a == 2);       /* unit vector a-hat */
+  int bx = ay, by = ax;                   /* unit vector normal to a */
+  int cxp = x - s * ax, cyp = y - s * ay; /* centre r - s a-hat */
+  int anyon = 0;
+  int32_t minnz = 0;
+  if (st->open) {                                                    /* R21 */
+    if (orc_in_B(st, x)) return 0;
+    if (cxp < 0 || cxp >= L || cyp < 0 || cyp >= L) return 0;       /* empty line */
+    if (orc_in_B(st, cxp)) anyon = 1;                                /* B sources x-messages */
+  }
+  for (int k = -1; k <= 1; ++k) {
+    int qx = cxp + k * bx, qy = cyp + k * by;
+    if (st->open && (qx < 0 || qx >= L || qy < 0 || qy >= L)) continue;   /* clipped */
+    qx = wrap(qx, L);
+    qy = wrap(qy, L);
+    int q = qy * L + qx;
+    if (sigma[q] == -1) anyon = 1;
+    int32_t mv = m[d][q];
+    if (mv > 0 && (minnz == 0 || mv < minnz)) minnz = mv;
+  }
+  int32_t out;
+  if (anyon) out = 1;
+  else if (minnz == 0) out = 0;
+  else out = minnz + 1;
+  if (st->m_max > 0 && out > st->m_max) out = 0;   /* R17 */
+  return out;
+}
+
+/* One application of A^{(D)} to every register simultaneously. */
 static void orc_message_update(orc_state *st) {
   int L = st->L;
-  for (int d = 0; d < 4; ++d) {
-    int s = DIR_S[d], a = DIR_A[d];
-    int ax = (a == 1), ay = (a == 2);       /* unit vector a-hat */
-    int bx = ay, by = ax;                   /* unit vector normal to a */
+  for (int d = 0; d < 4; ++d)
     for (int y = 0; y < L; ++y)
-      for (int x = 0; x < L; ++x) {
-        int cxp = x - s * ax, cyp = y - s * ay;   /* centre r - s a-hat */
-        int anyon = 0;
-        int32_t minnz = 0;
-        if (st->open) {                           /* R21 */
-          if (orc_in_B(st, x)) {
-            st->mnew[d][y * L + x] = 0;
-            continue;
-          }
-          if (cxp < 0 || cxp >= L || cyp < 0 || cyp >= L) {
-            st->mnew[d][y * L + x] = 0;           /* empty line */
-            continue;
-          }
-          if (orc_in_B(st, cxp)) anyon = 1;       /* B sources x-messages */
-        }
-        for (int k = -1; k <= 1; ++k) {
-          int qx = cxp + k * bx, qy = cyp + k * by;
-          if (st->open && (qx < 0 || qx >= L || qy < 0 || qy >= L)) continue;   /* clipped */
-          qx = wrap(qx, L);
-          qy = wrap(qy, L);
-          int q = qy * L + qx;
-          if (st->sigma[q] == -1) anyon = 1;
-          int32_t mv = st->m[d][q];
-          if (mv > 0 && (minnz == 0 || mv < minnz)) minnz = mv;
-        }
-        int32_t out;
-        if (anyon) out = 1;
-        else if (minnz == 0) out = 0;
-        else out = minnz + 1;
-        if (st->m_max > 0 && out > st->m_max) out = 0;   /* R17 */
-        st->mnew[d][y * L + x] = out;
-      }
-  }
+      for (int x = 0; x < L; ++x) st->mnew[d][y * L + x] = orc_register_value(st, st->m, st->sigma, d, x, y);
   for (int d = 0; d < 4; ++d) {
     int32_t *t = st->m[d];
     st->m[d] = st->mnew[d];
@@ -297,10 +329,6 @@ static int orc_force(int32_t mp, int32_t mm) {
 /* x OR y for x, y in {-1, 0, +1}: 1 iff either equals 1. */
 static int orc_or(int x, int y) { return (x == 1 || y == 1) ? 1 : 0; }
 
-/* Feedback F^{(D)}: per-site force f^a_r from argmin' over the nonzero
- * registers (ties broken by m + s a / (D+1), eq. (degbreak)), then the link
- * exponent sigma_r f^a_r OR sigma_{r+a}(-f^a_{r+a}) of eq. (ddfeedback).
- * Returns the number of anyons after the step. */
 /* Direction of the random move of site i at step t (R18): 0 +x, 1 -x,
  * 2 +y, 3 -y. */
 static int orc_random_direction(const orc_state *st, int64_t i) {
@@ -310,39 +338,47 @@ static int orc_random_direction(const orc_state *st, int64_t i) {
   return (int)(w[i & 1] & 3u);
 }
 
+/* The forces (f^x_r, f^y_r) of site i from the registers m and syndrome
+ * sigma it reads, at decoder step st->t. */
+static void orc_site_force(const orc_state *st, int32_t *const m[4], const int8_t *sigma, int64_t i, int8_t *fx,
+                           int8_t *fy) {
+  *fx = 0; *fy = 0;
+  if (sigma[i] != -1) return;                   /* R4 */
+  if (st->u > 0 && st->t % st->u == 0) {        /* R18 */
+    /* The link exponent carries sigma_r f_r and sigma_r = -1 here, so an
+     * anyon moves along +a for f^a = -1 (as for a force from orc_force). */
+    int d = orc_random_direction(st, i);
+    if (d < 2) *fx = (int8_t)(d == 0 ? -1 : +1);
+    else *fy = (int8_t)(d == 2 ? -1 : +1);
+    return;
+  }
+  int best = -1;
+  int32_t bestm = 0, bestoff = 0;
+  for (int d = 0; d < 4; ++d) {
+    int32_t mv = m[d][i];
+    if (mv <= 0) continue;
+    /* argmin' of eq. (degbreak): the offset s a / (D+1) only breaks ties
+     * between equal messages (R5): smallest m first, then smallest s*a. */
+    int32_t off = DIR_S[d] * DIR_A[d];
+    if (best < 0 || mv < bestm || (mv == bestm && off < bestoff)) {
+      best = d;
+      bestm = mv;
+      bestoff = off;
+    }
+  }
+  if (best < 0) return;                         /* M_r empty: no feedback */
+  if (DIR_A[best] == 1) *fx = (int8_t)orc_force(m[0][i], m[1][i]);
+  else *fy = (int8_t)orc_force(m[2][i], m[3][i]);
+}
+
+/* Feedback F^{(D)}: per-site force f^a_r from argmin' over the nonzero
+ * registers (ties broken by m + s a / (D+1), eq. (degbreak)), then the link
+ * exponent sigma_r f^a_r OR sigma_{r+a}(-f^a_{r+a}) of eq. (ddfeedback).
+ * Returns the number of anyons after the step. */
 static int64_t orc_feedback(orc_state *st) {
   int L = st->L;
   int64_t n = st->n;
-  const int random_step = st->u > 0 && st->t % st->u == 0;
-  for (int64_t i = 0; i < n; ++i) {
-    st->fx[i] = 0; st->fy[i] = 0;
-    if (st->sigma[i] != -1) continue;           /* R4 */
-    if (random_step) {                          /* R18 */
-      /* The link exponent carries sigma_r f_r and sigma_r = -1 here, so an
-       * anyon moves along +a for f^a = -1 (as for a force from orc_force). */
-      int d = orc_random_direction(st, i);
-      if (d < 2) st->fx[i] = (int8_t)(d == 0 ? -1 : +1);
-      else st->fy[i] = (int8_t)(d == 2 ? -1 : +1);
-      continue;
-    }
-    int best = -1;
-    int32_t bestm = 0, bestoff = 0;
-    for (int d = 0; d < 4; ++d) {
-      int32_t mv = st->m[d][i];
-      if (mv <= 0) continue;
-      /* argmin' of eq. (degbreak): the offset s a / (D+1) only breaks ties
-       * between equal messages (R5): smallest m first, then smallest s*a. */
-      int32_t off = DIR_S[d] * DIR_A[d];
-      if (best < 0 || mv < bestm || (mv == bestm && off < bestoff)) {
-        best = d;
-        bestm = mv;
-        bestoff = off;
-      }
-    }
-    if (best < 0) continue;                     /* M_r empty: no feedback */
-    if (DIR_A[best] == 1) st->fx[i] = (int8_t)orc_force(st->m[0][i], st->m[1][i]);
-    else st->fy[i] = (int8_t)orc_force(st->m[2][i], st->m[3][i]);
-  }
+  for (int64_t i = 0; i < n; ++i) orc_site_force(st, st->m, st->sigma, i, &st->fx[i], &st->fy[i]);
   for (int y = 0; y < L; ++y)
     for (int x = 0; x < L; ++x) {
       int i = y * L + x;
@@ -658,4 +694,242 @@ int orc_decode_links_open(int L, int v, const uint32_t *links, int64_t n, int T_
 int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, int nthreads,
                      int32_t *T_dec, uint8_t *flags, uint32_t *sigma_words) {
   return orc_links_any(L, v, 0, 0, 0, NULL, links, n, T_max, nthreads, T_dec, flags, sigma_words);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Marching-soldiers desynchronization (Sec. "Desynchronization and          */
+/* Lindbladian dynamics": Def. "simulation and lag times", Def. "marching    */
+/* soldiers desynchronization", Def. "desynchronized decoders", Prop.       */
+/* "faithful Lindbladian simulation"), readings R23-R27, torus only.        */
+/* ------------------------------------------------------------------------ */
+#define ORC_CLOCK_TAG 0x41535943u
+#define ORC_EBROKEN -3   /* a lag left {0, 1} inside the update ball */
+
+typedef struct {
+  orc_state st;        /* st.m = m^new, st.sigma = the physical syndrome, st.cx / st.cy = C */
+  int32_t *mold[4];    /* m^old */
+  int32_t *pm[4];      /* the present view (m^present) around the updating site */
+  int8_t *ps;          /* sigma^present around the updating site */
+  int32_t *tsim;       /* t_sim: updates performed at each site */
+  uint8_t *acc[2];     /* flips applied at each site by the feedback of step k, slot k mod 2 (R25) */
+  int64_t updates;     /* accepted updates */
+  int64_t flips;       /* links flipped */
+} orc_async;
+
+static void orc_async_free(orc_async *a) {
+  for (int d = 0; d < 4; ++d) { free(a->mold[d]); free(a->pm[d]); }
+  free(a->ps); free(a->tsim); free(a->acc[0]); free(a->acc[1]);
+  orc_free(&a->st);
+}
+
+static int orc_async_alloc(orc_async *a, int L, int v) {
+  memset(a, 0, sizeof(*a));
+  if (orc_alloc(&a->st, L, v) != ORC_OK) return ORC_ENOMEM;
+  size_t n = (size_t)a->st.n;
+  int ok = 1;
+  for (int d = 0; d < 4; ++d) {
+    a->mold[d] = (int32_t *)calloc(n, 4);
+    a->pm[d] = (int32_t *)calloc(n, 4);
+    ok = ok && a->mold[d] && a->pm[d];
+  }
+  a->ps = (int8_t *)calloc(n, 1);
+  a->tsim = (int32_t *)calloc(n, 4);
+  a->acc[0] = (uint8_t *)calloc(n, 1);
+  a->acc[1] = (uint8_t *)calloc(n, 1);
+  ok = ok && a->ps && a->tsim && a->acc[0] && a->acc[1];
+  if (!ok) { orc_async_free(a); return ORC_ENOMEM; }
+  return ORC_OK;
+}
+
+/* One attempted automaton update of site (x, y) of the desynchronized
+ * decoder.  Returns 1 if accepted, 0 if rejected, ORC_EBROKEN if the present
+ * view could not be formed (a neighbour neither level with nor one update
+ * ahead of the site, which the acceptance rule excludes). */
+static int orc_async_update(orc_async *a, int x, int y) {
+  orc_state *st = &a->st;
+  int L = st->L, v = st->v;
+  int64_t r = (int64_t)y * L + x;
+  int32_t j = a->tsim[r];
+  /* R24: accepted only if no site of the ball of radius 2 Delta is behind. */
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (!dx && !dy) continue;
+      if (a->tsim[wrap(y + dy, L) * L + wrap(x + dx, L)] < j) return 0;
+    }
+  int k = j / (v + 1), phase = j % (v + 1);
+  int feedback = phase == v;                    /* R23 */
+  /* The present view of the ball of radius Delta (R25): a level neighbour
+   * shows m^new, a neighbour one update ahead m^old; during a feedback
+   * update sigma excludes the flips of this step already applied. */
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      int64_t q = (int64_t)wrap(y + dy, L) * L + wrap(x + dx, L);
+      int32_t lag = a->tsim[q] - j;
+      if (lag != 0 && lag != 1) return ORC_EBROKEN;
+      for (int d = 0; d < 4; ++d) a->pm[d][q] = lag == 0 ? st->m[d][q] : a->mold[d][q];
+      a->ps[q] = feedback && a->acc[k & 1][q] ? (int8_t)(-st->sigma[q]) : st->sigma[q];
+    }
+  if (!feedback) {
+    if (phase == 0 && k > 0) a->acc[(k - 1) & 1][r] = 0;   /* R25: last step's flips are seen by all */
+    int32_t out[4];
+    for (int d = 0; d < 4; ++d) out[d] = orc_register_value(st, a->pm, a->ps, d, x, y);
+    for (int d = 0; d < 4; ++d) {
+      a->mold[d][r] = st->m[d][r];
+      st->m[d][r] = out[d];
+    }
+  } else {
+    /* F of the links r -> r + x-hat and r -> r + y-hat, from the present
+     * view, as in orc_feedback. */
+    st->t = k + 1;
+    int64_t rx = (int64_t)y * L + wrap(x + 1, L), ry = (int64_t)wrap(y + 1, L) * L + x;
+    int8_t fxr, fyr, fxx, fyx, fxy, fyy;
+    orc_site_force(st, a->pm, a->ps, r, &fxr, &fyr);
+    orc_site_force(st, a->pm, a->ps, rx, &fxx, &fyx);
+    orc_site_force(st, a->pm, a->ps, ry, &fxy, &fyy);
+    int lx = orc_or(a->ps[r] * fxr, a->ps[rx] * (-fxx));
+    int ly = orc_or(a->ps[r] * fyr, a->ps[ry] * (-fyy));
+    uint8_t *acc = a->acc[k & 1];
+    if (lx) {
+      st->cx[r] ^= 1;
+      st->sigma[r] = (int8_t)(-st->sigma[r]); st->sigma[rx] = (int8_t)(-st->sigma[rx]);
+      acc[r] ^= 1; acc[rx] ^= 1;
+      ++a->flips;
+    }
+    if (ly) {
+      st->cy[r] ^= 1;
+      st->sigma[r] = (int8_t)(-st->sigma[r]); st->sigma[ry] = (int8_t)(-st->sigma[ry]);
+      acc[r] ^= 1; acc[ry] ^= 1;
+      ++a->flips;
+    }
+    for (int d = 0; d < 4; ++d) a->mold[d][r] = st->m[d][r];
+  }
+  a->tsim[r] = j + 1;
+  ++a->updates;
+  return 1;
+}
+
+typedef struct { uint32_t prio; int32_t i; } orc_ring;
+
+static int orc_ring_cmp(const void *pa, const void *pb) {
+  const orc_ring *a = (const orc_ring *)pa, *b = (const orc_ring *)pb;
+  if (a->prio != b->prio) return a->prio < b->prio ? -1 : 1;
+  return (a->i > b->i) - (a->i < b->i);
+}
+
+/* The desynchronized decoder on one error chain (torus, L >= 5).
+ *   t_target >= 0: run until every site has performed (v+1) t_target
+ *       updates (sites that have stop attempting), or S_max slots;
+ *       flags bit1 set if the target was not reached.
+ *   t_target < 0: decode -- run until the physical syndrome holds no anyon
+ *       and no flip of any step is pending (R27), or S_max slots (timeout,
+ *       flags bit1); flags bit0 = logical failure or timeout (R10, R11).
+ * The clock (R26) is keyed by `seed`; ring_thr in [1, 2^32] is the ring
+ * probability per slot times 2^32.  Outputs: slots run, T_async = 1 + the
+ * slot of the last flip (0 if none), accepted updates, and optionally the
+ * final syndrome words, m^new [4][L*L], t_sim [L*L] and the chain C. */
+int orc_async_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex, const uint8_t *ey,
+                  int t_target, int S_max, int32_t *slots_out, int32_t *T_async, uint8_t *flags,
+                  int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out, int32_t *tsim_out,
+                  uint8_t *cx_out, uint8_t *cy_out) {
+  if (L < 5 || v < 1 || S_max < 0 || ring_thr < 1 || ring_thr > ((uint64_t)1 << 32)) return ORC_EBADARG;
+  orc_async a;
+  if (orc_async_alloc(&a, L, v) != ORC_OK) return ORC_ENOMEM;
+  orc_state *st = &a.st;
+  st->key[0] = (uint32_t)(seed & 0xffffffffu);
+  st->key[1] = (uint32_t)(seed >> 32);
+  orc_syndrome(st, ex, ey);
+  int64_t n = st->n;
+  int32_t target = t_target >= 0 ? (v + 1) * t_target : 0;
+  orc_ring *ring = (orc_ring *)malloc((size_t)n * sizeof(orc_ring));
+  if (!ring) { orc_async_free(&a); return ORC_ENOMEM; }
+  int rc = ORC_OK, done = 0;
+  int32_t slot = 0, last_flip = -1;
+  for (;;) {
+    /* stop test at the start of each slot (before the first: nothing to do) */
+    if (t_target >= 0) {
+      done = 1;
+      for (int64_t i = 0; i < n; ++i) done = done && a.tsim[i] >= target;
+    } else {
+      done = 1;
+      for (int64_t i = 0; i < n; ++i) done = done && st->sigma[i] == 1 && !a.acc[0][i] && !a.acc[1][i];
+    }
+    if (done || slot >= S_max) break;
+    /* R26: who rings in this slot, and in which order */
+    int64_t nr = 0;
+    for (int64_t i = 0; i < n; i += 2) {
+      uint32_t ctr[4] = {(uint32_t)(i >> 1), (uint32_t)slot, ORC_CLOCK_TAG, 0u}, w[4];
+      orc_philox4x32_10(ctr, st->key, w);
+      for (int h = 0; h < 2 && i + h < n; ++h)
+        if ((uint64_t)w[2 * h] < ring_thr) { ring[nr].prio = w[2 * h + 1]; ring[nr].i = (int32_t)(i + h); ++nr; }
+    }
+    qsort(ring, (size_t)nr, sizeof(orc_ring), orc_ring_cmp);
+    int64_t f0 = a.flips;
+    for (int64_t q = 0; q < nr && rc == ORC_OK; ++q) {
+      int32_t i = ring[q].i;
+      if (t_target >= 0 && a.tsim[i] >= target) continue;
+      int got = orc_async_update(&a, i % L, i / L);
+      if (got < 0) rc = got;
+    }
+    if (rc != ORC_OK) break;
+    if (a.flips != f0) last_flip = slot;
+    ++slot;
+  }
+  free(ring);
+  if (rc == ORC_OK) {
+    int wxe, wye, wxc, wyc;
+    orc_winding(L, 0, ex, ey, &wxe, &wye);
+    orc_winding(L, 0, st->cx, st->cy, &wxc, &wyc);
+    int timeout = !done;
+    int fail = t_target < 0 && (timeout || ((wxe ^ wxc) | (wye ^ wyc)));
+    if (slots_out) *slots_out = slot;
+    if (T_async) *T_async = last_flip + 1;
+    if (flags) *flags = (uint8_t)((fail ? 1 : 0) | (timeout ? 2 : 0));
+    if (updates_out) *updates_out = a.updates;
+    if (sigma_words) orc_pack_sigma(st, sigma_words);
+    if (m_out)
+      for (int d = 0; d < 4; ++d) memcpy(m_out + (size_t)d * n, st->m[d], (size_t)n * 4);
+    if (tsim_out) memcpy(tsim_out, a.tsim, (size_t)n * 4);
+    if (cx_out) memcpy(cx_out, st->cx, (size_t)n);
+    if (cy_out) memcpy(cy_out, st->cy, (size_t)n);
+  }
+  orc_async_free(&a);
+  return rc;
+}
+
+/* Noise (R12) + desynchronized decode for a batch of seeds, spread over
+ * OpenMP threads; the seed keys both the noise and the clock. */
+int orc_async_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
+                           uint64_t ring_thr, int S_max, int nthreads, int32_t *T_async, uint8_t *flags,
+                           int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
+  if (L < 5 || v < 1 || n < 0 || S_max < 0) return ORC_EBADARG;
+  int64_t nsite = (int64_t)L * L, nw = (nsite + 31) / 32;
+  int err = ORC_OK, used = 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+  {
+#pragma omp single
+    used = omp_get_num_threads();
+  }
+#else
+  (void)nthreads;
+#endif
+  if (threads_used) *threads_used = used;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n; ++k) {
+    uint8_t *ex = (uint8_t *)malloc((size_t)nsite);
+    uint8_t *ey = (uint8_t *)malloc((size_t)nsite);
+    int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
+    if (rc == ORC_OK) rc = orc_noise(L, p[p_stride ? k : 0], seeds[k], ex, ey);
+    if (rc == ORC_OK)
+      rc = orc_async_run(L, v, seeds[k], ring_thr, ex, ey, -1, S_max, &slots_out[k], &T_async[k], &flags[k],
+                         &updates_out[k], sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+    if (rc != ORC_OK) {
+#pragma omp critical
+      err = rc;
+    }
+    free(ex);
+    free(ey);
+  }
+  return err;
 }

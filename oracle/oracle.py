@@ -76,6 +76,10 @@ def _load():
     lib.orc_decode_links_open.argtypes = [I, I, P, ctypes.c_int64, I, I, P, P, P]
     lib.orc_decode_links_open.restype = I
     lib.orc_decode_links.restype = ctypes.c_int
+    lib.orc_async_run.argtypes = [I, I, U64, U64, P, P, I, I, P, P, P, P, P, P, P, P, P]
+    lib.orc_async_run.restype = I
+    lib.orc_async_decode_seeds.argtypes = [I, I, P, I, P, ctypes.c_int64, U64, I, I, P, P, P, P, P, P]
+    lib.orc_async_decode_seeds.restype = I
     _lib = lib
     return lib
 
@@ -240,3 +244,58 @@ def decode_links(L: int, links, T_max: int, v: int = 3, threads: int = 0, m_max:
         _check(_load().orc_decode_links_rule(L, v, int(m_max), int(u), _ptr(sd), _ptr(links), n, int(T_max),
                                              int(threads), _ptr(T), _ptr(fl), _ptr(sw)), "decode_links")
     return dict(T_dec=T, flags=fl, sigma_words=sw)
+
+
+def ring_threshold(rho: float) -> int:
+    """Ring probability per slot as the integer threshold of R26 (rho * 2^32,
+    clamped to [1, 2^32])."""
+    return max(1, min(1 << 32, int(rho * 4294967296.0)))
+
+
+def async_run(L: int, ex, ey, seed: int, rho: float = 1.0, t_target: int = -1, S_max: int = 100000,
+              v: int = 3):
+    """Marching-soldiers desynchronization of the plain rule (R23-R27) on one
+    error chain, clock keyed by `seed`.  t_target >= 0 runs until every site
+    has performed (v+1) t_target updates; t_target < 0 decodes.  Returns a dict
+    with slots, T_async, flags, updates, sigma_words, m (m^new, [4, L, L]),
+    tsim [L, L], cx, cy."""
+    n = L * L
+    ex = np.ascontiguousarray(ex, dtype=np.uint8).reshape(-1)
+    ey = np.ascontiguousarray(ey, dtype=np.uint8).reshape(-1)
+    slots = np.zeros(1, np.int32)
+    T = np.zeros(1, np.int32)
+    flags = np.zeros(1, np.uint8)
+    upd = np.zeros(1, np.int64)
+    words = np.zeros((n + 31) // 32, np.uint32)
+    m = np.zeros((4, n), np.int32)
+    tsim = np.zeros(n, np.int32)
+    cx = np.zeros(n, np.uint8)
+    cy = np.zeros(n, np.uint8)
+    _check(_load().orc_async_run(L, v, int(seed) & (2**64 - 1), ring_threshold(rho), _ptr(ex), _ptr(ey),
+                                 int(t_target), int(S_max), _ptr(slots), _ptr(T), _ptr(flags), _ptr(upd),
+                                 _ptr(words), _ptr(m), _ptr(tsim), _ptr(cx), _ptr(cy)), "async_run")
+    return {"slots": int(slots[0]), "T_async": int(T[0]), "flags": int(flags[0]), "updates": int(upd[0]),
+            "sigma_words": words, "m": m.reshape(4, L, L), "tsim": tsim.reshape(L, L),
+            "cx": cx.reshape(L, L), "cy": cy.reshape(L, L)}
+
+
+def async_decode_seeds(L: int, p, seeds, rho: float = 1.0, S_max: int = 100000, v: int = 3,
+                       threads: int = 0, want_sigma: bool = True):
+    """Noise + desynchronized decode per seed (R12, R23-R27)."""
+    s = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    n = s.size
+    pa = np.ascontiguousarray(np.atleast_1d(np.asarray(p, dtype=np.float64)))
+    T = np.zeros(n, np.int32)
+    flags = np.zeros(n, np.uint8)
+    slots = np.zeros(n, np.int32)
+    upd = np.zeros(n, np.int64)
+    words = np.zeros((n, (L * L + 31) // 32), np.uint32) if want_sigma else None
+    used = ctypes.c_int(0)
+    _check(_load().orc_async_decode_seeds(L, v, _ptr(pa), 1 if pa.size > 1 else 0, _ptr(s), n,
+                                          ring_threshold(rho), int(S_max), int(threads), _ptr(T), _ptr(flags),
+                                          _ptr(slots), _ptr(upd), _ptr(words), ctypes.byref(used)),
+           "async_decode_seeds")
+    out = {"T_async": T, "flags": flags, "slots": slots, "updates": upd, "threads": used.value}
+    if want_sigma:
+        out["sigma_words"] = words
+    return out

@@ -1,0 +1,191 @@
+"""Pins of the marching-soldiers desynchronization (Sec. "Desynchronization
+and Lindbladian dynamics", readings R23-R27 of the oracle).  The section
+proves that the desynchronized decoder simulates the synchronous one
+exactly: each site's registers equal the synchronous registers at the
+site's own simulation time (eq. (faithful_sim_control)), and once every site
+has reached a time the whole state is the synchronous state of that time,
+whatever the update order (Prop. "faithful Lindbladian simulation"); hence
+the same correction and the same logical outcome (Theorem on desynchronized
+thresholds).  These tests check the asynchronous oracle against the
+synchronous oracle (itself pinned elsewhere) and against the lightfront
+definition of the messages, plus the lag bound the acceptance rule enforces.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_03266_amd.workloads import seeds
+from test_oracle_pins import lightcone_messages
+
+V = 3
+
+
+def sync_state(orc, L, ex, ey, t):
+    m, sig, (cx, cy), _ = orc.run_steps(L, ex, ey, t)
+    return m, orc.pack_bits((sig == -1).reshape(-1)), cx, cy
+
+
+@pytest.mark.parametrize("L,p", [(5, 0.12), (6, 0.1), (8, 0.08), (11, 0.06), (16, 0.05)])
+def test_every_order_reaches_the_synchronous_state(orc, L, p):
+    """Run until every site has completed t decoder steps: registers,
+    syndrome and correction equal the synchronous decoder's after t steps,
+    for several clocks (seeds) and ring probabilities."""
+    for s in seeds(130, 10 * L, 3):
+        ex, ey = orc.noise(L, p, int(s))
+        for t in (1, 2, 4, 7):
+            m, sw, cx, cy = sync_state(orc, L, ex, ey, t)
+            for rho, clock in ((0.05, 1), (0.3, 2), (0.8, 3)):
+                r = orc.async_run(L, ex, ey, seed=int(s) + clock, rho=rho, t_target=t)
+                assert r["flags"] == 0 and (r["tsim"] == (V + 1) * t).all()
+                assert np.array_equal(r["m"], m), (L, int(s), t, rho)
+                assert np.array_equal(r["sigma_words"], sw), (L, int(s), t, rho)
+                assert np.array_equal(r["cx"], cx) and np.array_equal(r["cy"], cy), (L, int(s), t, rho)
+
+
+def substep(j):
+    """Synchronous message sub-step reached after j updates of a site (R23):
+    v message updates and one feedback update per decoder step."""
+    return (j // (V + 1)) * V + min(j % (V + 1), V)
+
+
+@pytest.mark.parametrize("L,p,rho", [(6, 0.1, 0.2), (8, 0.08, 0.1), (9, 0.06, 0.5)])
+def test_registers_follow_the_lightfront_at_every_time(orc, L, p, rho):
+    """Eq. (faithful_sim_control) at arbitrary times: stopping the clock after
+    any number of slots, every site's m^new equals the lightfront messages of
+    the synchronous history at that site's own sub-step."""
+    s = int(seeds(131, L, 1)[0])
+    ex, ey = orc.noise(L, p, s)
+    _, _, _, hist = orc.run_steps(L, ex, ey, 12, record=True)
+    cache = {}
+    for S in (3, 11, 26, 40, 57, 80):
+        r = orc.async_run(L, ex, ey, seed=s, rho=rho, t_target=12, S_max=S)
+        for j in np.unique(r["tsim"]):
+            sub = substep(int(j))
+            if sub not in cache:
+                cache[sub] = lightcone_messages(L, hist, V, sub)
+            at = r["tsim"] == j
+            assert np.array_equal(r["m"][:, at], cache[sub][:, at]), (S, int(j))
+
+
+@pytest.mark.parametrize("L,rho", [(7, 0.1), (12, 0.3), (16, 0.05)])
+def test_lags_stay_within_one_inside_the_ball(orc, L, rho):
+    """The acceptance rule keeps |t_sim(r) - t_sim(q)| <= 1 for q within
+    infinity-distance 2 (Def. "marching soldiers desynchronization", comment
+    on the lag variables), hence <= ceil(d / 2) at distance d."""
+    ex, ey = orc.noise(L, 0.07, 5 + L)
+    for S in (1, 5, 17, 60, 150):
+        t = orc.async_run(L, ex, ey, seed=9 * L, rho=rho, t_target=50, S_max=S)["tsim"]
+        for dy in range(-L // 2, L // 2 + 1):
+            for dx in range(-L // 2, L // 2 + 1):
+                d = max(min(abs(dx), L - abs(dx)), min(abs(dy), L - abs(dy)))
+                lag = np.abs(t - np.roll(np.roll(t, dy, 0), dx, 1)).max()
+                assert lag <= (d + 1) // 2, (S, dx, dy, lag)
+
+
+def test_first_slot_advances_exactly_the_ringing_sites(orc):
+    """R26's clock, a project convention: in slot 0 every site is level, so
+    each site that rings advances once and no other does.  Site i rings iff
+    word 2(i&1) of Philox(key = seed, counter = (i >> 1, 0, 0x41535943, 0)) is
+    below rho 2^32."""
+    L = 10
+    ex, ey = orc.noise(L, 0.05, 3)
+    for seed, rho in ((12345, 0.3), (2**40 + 7, 0.7), (99, 0.02)):
+        r = orc.async_run(L, ex, ey, seed=seed, rho=rho, t_target=5, S_max=1)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        thr = orc.ring_threshold(rho)
+        want = np.zeros(L * L, np.int32)
+        for i in range(L * L):
+            w = orc.philox4x32_10([i >> 1, 0, 0x41535943, 0], key)
+            want[i] = int(w[2 * (i & 1)]) < thr
+        assert np.array_equal(r["tsim"].reshape(-1), want)
+        assert r["updates"] == want.sum()
+
+
+def test_certain_ringing_is_lockstep(orc):
+    """With ring probability 1 every site attempts once per slot and, all
+    sites starting level, every attempt is accepted: t steps take exactly
+    (v+1) t slots and n (v+1) t updates."""
+    L = 8
+    ex, ey = orc.noise(L, 0.08, 4)
+    for t in (1, 3, 6):
+        r = orc.async_run(L, ex, ey, seed=t, rho=1.0, t_target=t)
+        assert r["slots"] == (V + 1) * t and r["updates"] == L * L * (V + 1) * t
+
+
+@pytest.mark.parametrize("L,p", [(6, 0.1), (8, 0.08), (12, 0.06), (16, 0.05), (24, 0.04)])
+def test_decoding_outcome_is_the_synchronous_one(orc, L, p):
+    """Desynchronized decodes end with the synchronous decoder's correction,
+    final syndrome and logical outcome, sample by sample (R27); a sample the
+    synchronous rule leaves in a steady state with anyons times out here too."""
+    for s in seeds(132, 10 * L, 8):
+        ex, ey = orc.noise(L, p, int(s))
+        rs = orc.decode_errors(L, ex, ey, 300, want_state=True)
+        for rho in (0.1, 0.5):
+            r = orc.async_run(L, ex, ey, seed=int(s), rho=rho, S_max=20000)
+            assert r["flags"] == rs["flags"], (L, int(s), rho)
+            assert np.array_equal(r["sigma_words"], rs["sigma_words"])
+            assert np.array_equal(r["cx"], rs["cx"]) and np.array_equal(r["cy"], rs["cy"])
+            if rs["T_dec"] == 0:
+                assert r["T_async"] == 0 and r["slots"] == 0
+
+
+def test_pair_decoding_time_scales_with_the_slowdown(orc):
+    """A lone straight pair at distance 2 annihilates in synchronous step 1
+    (T_dec = 1, ceil(d/3) - 1 + ceil(d/2)).  Asynchronously the last flip
+    comes when its owner completes its first feedback update, after at least
+    v + 1 = 4 of its own updates: with ring probability 1 exactly slot 4."""
+    L = 12
+    ex = np.zeros((L, L), np.uint8)
+    ey = np.zeros((L, L), np.uint8)
+    ex[5, 3:5] = 1
+    assert orc.decode_errors(L, ex, ey, 10)["T_dec"] == 1
+    r = orc.async_run(L, ex, ey, seed=1, rho=1.0)
+    assert (r["T_async"], r["flags"]) == (V + 1, 0)
+    for seed in range(20):
+        r = orc.async_run(L, ex, ey, seed=seed, rho=0.25)
+        assert r["flags"] == 0 and r["T_async"] >= V + 1
+
+
+def test_batch_decode_matches_single_runs(orc):
+    """The OpenMP batch entry equals per-sample runs (noise from the seed)."""
+    L, p = 10, 0.07
+    s = seeds(133, 0, 24)
+    b = orc.async_decode_seeds(L, p, s, rho=0.25, S_max=20000, threads=8)
+    for k, seed in enumerate(s):
+        ex, ey = orc.noise(L, p, int(seed))
+        r = orc.async_run(L, ex, ey, seed=int(seed), rho=0.25, S_max=20000)
+        assert (b["T_async"][k], b["flags"][k], b["slots"][k], b["updates"][k]) == \
+            (r["T_async"], r["flags"], r["slots"], r["updates"])
+        assert np.array_equal(b["sigma_words"][k], r["sigma_words"])
+
+
+def clock_times(orc, L, seed, rho, S, target):
+    """Simulation times after S slots from R24 and R26 alone: the lag process
+    does not depend on the decoder's registers or syndrome."""
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    thr = orc.ring_threshold(rho)
+    t = np.zeros((L, L), np.int64)
+    for slot in range(S):
+        ring = []
+        for i in range(L * L):
+            w = orc.philox4x32_10([i >> 1, slot, 0x41535943, 0], key)
+            if int(w[2 * (i & 1)]) < thr:
+                ring.append((int(w[2 * (i & 1) + 1]), i))
+        for _, i in sorted(ring):
+            x, y = i % L, i // L
+            if t[y, x] >= target:
+                continue
+            ball = [t[(y + dy) % L, (x + dx) % L] for dy in range(-2, 3) for dx in range(-2, 3) if dx or dy]
+            if min(ball) >= t[y, x]:
+                t[y, x] += 1
+    return t
+
+
+@pytest.mark.parametrize("L,rho,seed", [(6, 0.5, 77), (7, 0.9, 2**33 + 1), (9, 0.25, 5)])
+def test_simulation_times_follow_the_clock_order(orc, L, rho, seed):
+    """Within a slot the ringing sites attempt in increasing order of their
+    priority word (R26); the order decides which attempts the lag rule accepts
+    (R24), so the simulation times after a few slots fix it."""
+    ex, ey = orc.noise(L, 0.1, 17)
+    for S in (2, 7, 15):
+        r = orc.async_run(L, ex, ey, seed=seed, rho=rho, t_target=6, S_max=S)
+        assert np.array_equal(r["tsim"], clock_times(orc, L, seed, rho, S, 4 * 6)), S
