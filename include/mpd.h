@@ -188,6 +188,61 @@ int mpd_decode_errors_open(int L, const uint32_t *d_links, int64_t n, int T_max,
 int mpd_run_steps_open(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
                        uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
+/* Marching-soldiers desynchronization (Sec. "Desynchronization and
+ * Lindbladian dynamics": Def. "marching soldiers desynchronization", Def.
+ * "desynchronized decoders", Prop. "faithful Lindbladian simulation") of the
+ * plain rule on the torus, 5 <= L <= 64, one workgroup per sample.
+ *
+ * Each site advances on its own: v = 3 message updates, then one feedback
+ * update applying F to its links to (x+1,y) and (x,y+1); t_sim counts them.
+ * An update of a site is accepted only if no site within infinity-distance
+ * 2 has a smaller t_sim.  Neighbours one update ahead are read through their
+ * previous registers, and feedback of step k reads every syndrome without
+ * the step-k flips already applied, so the decoder computes exactly what the
+ * synchronous one computes, in any update order.
+ *
+ * Clock: time runs in slots.  In slot s site i rings iff word 2*(i&1) of
+ * Philox4x32-10(key = clock seed, counter (i >> 1, s, 0x41535943, 0)) is
+ * below floor(rho * 2^32) (at least 1); ringing sites attempt one update
+ * each in increasing order of (word 2*(i&1)+1, i).  Small rho approaches
+ * independent rate-1 Poisson clocks with slots of length rho.
+ *
+ * mpd_decode_async: noise from d_seeds as mpd_decode_batch (the same seed
+ * keys the clock), then run until the syndrome holds no anyon and no flip
+ * of any step is pending, or S_max slots.  Outputs per sample:
+ *   d_T_async   [n] int32: 1 + the last slot in which a link flipped (0 if
+ *               none); times rho is the decoding time in units of the
+ *               clocks' mean interval
+ *   d_flags     [n] uint8: as mpd_decode_batch; timeout = S_max slots spent
+ *               with anyons or pending flips left
+ *   d_slots     [n] int32 slots run (may be NULL)
+ *   d_updates   [n] int64 accepted updates over all sites (may be NULL)
+ *   d_final_syndrome  [n][ceil(L*L/32)] (may be NULL)
+ * The correction, the final syndrome and the failure bit equal those of the
+ * synchronous decoder with the same seed whenever neither times out.
+ *
+ * mpd_run_async: explicit error chains (link bit arrays) and clock seeds;
+ * runs until every site has made 4 t_target updates (sites that have stop
+ * attempting) or S_max slots.  Outputs: d_slots [n] int32; d_updates [n]
+ * int64 (may be NULL); d_m_out [n][4][L*L] int16 registers m^new in
+ * distance form (order +x, -x, +y, -y); d_tsim_out [n][L*L] uint16; the
+ * physical syndrome d_sigma_out as a syndrome bit array; d_wind_out as
+ * mpd_run_steps.  Once every site has reached the target these equal
+ * mpd_run_steps(t_exact = t_target).
+ *
+ * Errors: MPD_ERR_L (L outside 5..64), MPD_ERR_P (p outside [0, 1] or rho
+ * outside (0, 1]), MPD_ERR_TMAX (S_max outside [0, MPD_ASYNC_SLOT_LIMIT],
+ * t_target outside [0, MPD_ASYNC_SLOT_LIMIT / 4]), MPD_ERR_N, MPD_ERR_PTR
+ * (required pointer NULL, or any pointer misaligned for its type).  No
+ * workspace; no host synchronization. */
+#define MPD_ASYNC_SLOT_LIMIT 65000
+int mpd_decode_async(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_async,
+                     uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
+                     void *stream);
+int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target, double rho,
+                  int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out, uint16_t *d_tsim_out,
+                  uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
 /* Temporal blocking of the band path (L >= 256): decoder steps run on chip per
  * pass over HBM, in the first pass (registers still empty) and in later
  * passes.  Results do not depend on it; speed does.  Each value in

@@ -96,6 +96,10 @@ def lib():
     L.mpd_learned_workspace_bytes.restype = SZ
     L.mpd_decode_learned.argtypes = [I, D, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
     L.mpd_decode_learned.restype = I
+    L.mpd_decode_async.argtypes = [I, D, P, I64, D, I, P, P, P, P, P, P]
+    L.mpd_decode_async.restype = I
+    L.mpd_run_async.argtypes = [I, P, P, I64, I, D, I, P, P, P, P, P, P, P]
+    L.mpd_run_async.restype = I
     _lib = L
     return L
 
@@ -210,6 +214,56 @@ def run_steps(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int =
                                       _ptr(S), _ptr(W), _stream_ptr(stream))
         _check(rc, "mpd_run_steps_rule")
     return M, S, W
+
+
+ASYNC_SLOT_LIMIT = 65000
+
+
+def decode_async(L: int, p: float, seeds, rho: float, S_max: int = ASYNC_SLOT_LIMIT, want_syndrome: bool = True,
+                 out=None, stream=None):
+    """Marching-soldiers desynchronized decode of seeded noise (5 <= L <= 64):
+    the seed keys the noise and the clock, rho is the ring probability per
+    slot.  Returns (T_async int32[n], flags uint8[n], slots int32[n],
+    updates int64[n], syndrome int32[n, W] or None) on the device; `out` may
+    pass all five preallocated."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        SL = torch.empty(n, dtype=torch.int32, device=dev)
+        U = torch.empty(n, dtype=torch.int64, device=dev)
+        S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    else:
+        T, F, SL, U, S = out
+    rc = lib().mpd_decode_async(L, float(p), _ptr(s), n, float(rho), int(S_max), _ptr(T), _ptr(F), _ptr(SL), _ptr(U),
+                                _ptr(S), _stream_ptr(stream))
+    _check(rc, "mpd_decode_async")
+    return T, F, SL, U, S
+
+
+def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int = ASYNC_SLOT_LIMIT, stream=None):
+    """Desynchronized run of explicit error patterns until every site has
+    completed t_target decoder steps (or S_max slots).  Returns (slots
+    int32[n], updates int64[n], m int16[n,4,L,L], tsim int16[n,L,L] holding
+    uint16 values, syndrome int32[n,W], wind uint8[n])."""
+    dev = torch.device("cuda")
+    links = _links_tensor(L, links, dev)
+    n = links.shape[0]
+    cs = _seeds_tensor(clock_seeds, dev)
+    if cs.numel() != n:
+        raise ValueError("one clock seed per pattern")
+    SL = torch.empty(n, dtype=torch.int32, device=dev)
+    U = torch.empty(n, dtype=torch.int64, device=dev)
+    M = torch.empty((n, 4, L, L), dtype=torch.int16, device=dev)
+    TS = torch.empty((n, L, L), dtype=torch.int16, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
+    W = torch.empty(n, dtype=torch.uint8, device=dev)
+    rc = lib().mpd_run_async(L, _ptr(links), _ptr(cs), n, int(t_target), float(rho), int(S_max), _ptr(SL), _ptr(U),
+                             _ptr(M), _ptr(TS), _ptr(S), _ptr(W), _stream_ptr(stream))
+    _check(rc, "mpd_run_async")
+    return SL, U, M, TS, S, W
 
 
 def decode_open(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True, workspace=None, out=None,

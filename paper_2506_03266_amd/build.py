@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libmpd.so")
-SOURCES = ["mpd.hip", "cnn.hip"]
+SOURCES = ["mpd.hip", "cnn.hip", "async.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

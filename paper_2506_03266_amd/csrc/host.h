@@ -73,6 +73,9 @@ struct ProfScope {
 // Compute units of the current device (cached per device).
 int cu_count();
 
+// floor(p 2^32) clamped to [0, 2^32]: the flip threshold of noise strength p.
+uint64_t threshold_of(double p);
+
 // Forward pass of the decode-time predictor (cnn.hip) on count maps
 // [n][M][M]: pred [n], and optionally feat / argmax [n][16] and the stored
 // activations of layers 1-3 (`store`, M <= 32 only).  `ws` holds

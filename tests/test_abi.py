@@ -211,3 +211,22 @@ def test_open_arguments_rejected(lib):
     assert lib.mpd_decode_errors_open(16, None, 4, 8, dummy, dummy, None, None) == -4
     assert lib.mpd_run_steps_open(16, dummy, 4, 3, None, dummy, dummy, None) == -4
     assert lib.mpd_run_steps_open(200, dummy, 4, 3, dummy, dummy, dummy, None) == -1
+
+
+def test_async_arguments_rejected(lib):
+    """The desynchronized entry points check L (5..64), p, rho, the slot
+    budget, t_target and pointers before any launch."""
+    dummy = ctypes.c_void_p(256)
+    d = lambda L=16, p=0.1, n=4, rho=0.5, S=100, T=dummy, F=dummy, sd=dummy: lib.mpd_decode_async(
+        L, p, sd, n, rho, S, T, F, None, None, None, None)
+    assert d(L=4) == -1 and d(L=65) == -1 and d(L=128) == -1
+    assert d(p=1.5) == -2 and d(rho=0.0) == -2 and d(rho=1.01) == -2 and d(rho=float("nan")) == -2
+    assert d(S=-1) == -3 and d(S=65001) == -3
+    assert d(n=-1) == -7
+    assert d(sd=None) == -4 and d(T=None) == -4 and d(sd=ctypes.c_void_p(260)) == -4
+    assert d(n=0) == 0
+    r = lambda L=16, n=4, t=3, rho=0.5, S=100, links=dummy, cs=dummy, m=dummy: lib.mpd_run_async(
+        L, links, cs, n, t, rho, S, dummy, None, m, dummy, dummy, dummy, None)
+    assert r(L=3) == -1 and r(rho=2.0) == -2 and r(t=-1) == -3 and r(t=16251) == -3 and r(S=70000) == -3
+    assert r(links=None) == -4 and r(cs=None) == -4 and r(m=None) == -4 and r(m=ctypes.c_void_p(257)) == -4
+    assert r(n=0) == 0
