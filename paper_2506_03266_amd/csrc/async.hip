@@ -26,16 +26,22 @@
 // apart commute; and any two ringers within distance 2 attempt in key order.
 // Each slot therefore ends in the state of the sequential order.
 //
+// A ringer's key is (priority word << 32 | i), unique per site; an idle site
+// (not ringing, or done for this slot) holds the key ~0.  A pending site is
+// ready when its key is the minimum of the 5 x 5 box around it, found in two
+// separable passes (row minima, then column minima of those).
+//
 // One workgroup holds one sample (5 <= L <= 64) in LDS for its whole run:
+//   K, H    u64 per site: key of the current slot, row minimum of the keys
 //   MN, MO  uint2 per site: m^new / m^old in distance form, packed u16
 //           (.x = m^{+x} | m^{-x} << 16, .y = m^{+y} | m^{-y} << 16)
-//   PR      u32 priority word of the current slot
 //   TS      u16 simulation time
 //   FL      u8: bit 0 anyon (the physical syndrome), bit 1 + (k & 1) flip
 //           parity of step k
 //   CH      u8: bit 0 x-link, bit 1 y-link of the correction chain (during
 //           set-up: of the error chain)
-//   PD      u8: ringing and not yet attempted in the current slot
+//   RL      u16 list of the sites ready in the current round, so that the
+//           updates run on consecutive lanes instead of scattered ones
 // Registers and t_sim stay below 2^16 because at most one update per site
 // happens per slot and the slot count is capped.
 #include <hip/hip_runtime.h>
@@ -69,10 +75,15 @@ struct AsyncArgs {
   uint8_t *wind_out;
 };
 
+constexpr uint64_t IDLE = ~(uint64_t)0;
+constexpr int ASYNC_SITES = 4;   // sites per thread; the launch uses at least N / 4 threads
+
 size_t async_lds(int L) {
   const size_t N = (size_t)L * L;
-  return ((25 * N + 15) & ~(size_t)15) + 16;
+  return ((38 * N + 15) & ~(size_t)15) + 16;
 }
+
+__device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ int wrapc(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
@@ -109,35 +120,51 @@ __device__ __forceinline__ void site_force(uint2 m, int &fx, int &fy) {
 }
 
 struct AsyncLds {
+  uint64_t *K, *H;
   uint2 *MN, *MO;
-  uint32_t *PR;
   uint16_t *TS;
-  uint8_t *FL, *CH, *PD;
+  uint8_t *FL, *CH;
+  uint16_t *RL;
 };
 
 // One attempted update of site i.  Returns 0 if rejected, 1 if accepted,
 // 2 if accepted and a link flipped.
-__device__ __forceinline__ int async_attempt(const AsyncLds &s, int L, int i) {
-  const int x = i % L, y = i / L;
-  const uint32_t j = s.TS[i];
-  for (int dy = -2; dy <= 2; ++dy) {
-    const int row = wrapc(y + dy, L) * L;
-    for (int dx = -2; dx <= 2; ++dx)
-      if ((dx | dy) && s.TS[row + wrapc(x + dx, L)] < j) return 0;
+__device__ __forceinline__ int async_attempt(const AsyncLds &s, int L, int i, int x, int y) {
+  int col[5], row[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    col[d] = wrapc(x + d - 2, L);
+    row[d] = wrapc(y + d - 2, L) * L;
   }
-  const int xl = wrapc(x - 1, L), xr = wrapc(x + 1, L);
-  const int rd = wrapc(y - 1, L) * L, rc = y * L, ru = wrapc(y + 1, L) * L;
+  // every t_sim of the 5 x 5 ball, loaded together
+  uint32_t tv[5][5];
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) tv[dy][dx] = s.TS[row[dy] + col[dx]];
+  const uint32_t j = tv[2][2];
+  uint32_t tmin = 0xFFFFu;
+#pragma unroll
+  for (int dy = 0; dy < 5; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx)
+      if (dx != 2 || dy != 2) tmin = min(tmin, tv[dy][dx]);
+  if (tmin < j) return 0;
+  const int xl = col[1], xr = col[3];
+  const int rd = row[1], rc = row[2], ru = row[3];
   const uint32_t k = j >> 2, phase = j & 3u;
   int ret = 1;
   if (phase < 3u) {
-    // present views of the 3 x 3 block
-    auto mv = [&](int q) { return s.TS[q] == j ? s.MN[q] : s.MO[q]; };
+    // present views of the 3 x 3 block: level neighbours show m^new, those
+    // one update ahead m^old
     auto an = [&](int q) { return (s.FL[q] & 1u) != 0u; };
     const int dl = rd + xl, dc = rd + x, dr = rd + xr;
     const int cl = rc + xl, cr = rc + xr;
     const int ul = ru + xl, uc = ru + x, ur = ru + xr;
-    const uint2 mdl = mv(dl), mdc = mv(dc), mdr = mv(dr), mcl = mv(cl), mcr = mv(cr), mul = mv(ul), muc = mv(uc),
-                mur = mv(ur);
+    const uint2 mdl = (tv[1][1] == j ? s.MN : s.MO)[dl], mdc = (tv[1][2] == j ? s.MN : s.MO)[dc],
+                mdr = (tv[1][3] == j ? s.MN : s.MO)[dr], mcl = (tv[2][1] == j ? s.MN : s.MO)[cl],
+                mcr = (tv[2][3] == j ? s.MN : s.MO)[cr], mul = (tv[3][1] == j ? s.MN : s.MO)[ul],
+                muc = (tv[3][2] == j ? s.MN : s.MO)[uc], mur = (tv[3][3] == j ? s.MN : s.MO)[ur];
     const uint32_t px = rule_A(an(dl) || an(cl) || an(ul), mdl.x & 0xFFFFu, mcl.x & 0xFFFFu, mul.x & 0xFFFFu);
     const uint32_t mx = rule_A(an(dr) || an(cr) || an(ur), mdr.x >> 16, mcr.x >> 16, mur.x >> 16);
     const uint32_t py = rule_A(an(dl) || an(dc) || an(dr), mdl.y & 0xFFFFu, mdc.y & 0xFFFFu, mdr.y & 0xFFFFu);
@@ -150,12 +177,12 @@ __device__ __forceinline__ int async_attempt(const AsyncLds &s, int L, int i) {
     const uint32_t sb = 2u << (k & 1u);
     const int ix = rc + xr, iy = ru + x;
     auto an = [&](int q) { return ((s.FL[q] ^ ((s.FL[q] & sb) ? 1u : 0u)) & 1u) != 0u; };
-    auto mv = [&](int q) { return s.TS[q] == j ? s.MN[q] : s.MO[q]; };
     const bool ar = an(i), ax = an(ix), ay = an(iy);
+    const uint2 vr = s.MN[i], vx = (tv[2][3] == j ? s.MN : s.MO)[ix], vy = (tv[3][2] == j ? s.MN : s.MO)[iy];
     int fxr = 0, fyr = 0, fxx = 0, fyx = 0, fxy = 0, fyy = 0;
-    if (ar) site_force(s.MN[i], fxr, fyr);
-    if (ax) site_force(mv(ix), fxx, fyx);
-    if (ay) site_force(mv(iy), fxy, fyy);
+    if (ar) site_force(vr, fxr, fyr);
+    if (ax) site_force(vx, fxx, fyx);
+    if (ay) site_force(vy, fxy, fyy);
     // link exponent sigma_r f_r OR sigma_{r+a} (-f_{r+a}); f = 0 off anyons
     const bool lx = (ar && fxr == -1) || (ax && fxx == 1);
     const bool ly = (ar && fyr == -1) || (ay && fyy == 1);
@@ -181,14 +208,16 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int L = a.L, N = L * L;
   AsyncLds s;
-  s.MN = (uint2 *)lds;
+  s.K = (uint64_t *)lds;
+  s.H = s.K + N;
+  s.MN = (uint2 *)(s.H + N);
   s.MO = s.MN + N;
-  s.PR = (uint32_t *)(s.MO + N);
-  s.TS = (uint16_t *)(s.PR + N);
+  s.TS = (uint16_t *)(s.MO + N);
   s.FL = (uint8_t *)(s.TS + N);
   s.CH = s.FL + N;
-  s.PD = s.CH + N;
-  int *RED = (int *)(lds + ((25 * (size_t)N + 15) & ~(size_t)15));   // wind bits, 1 + last flip slot, updates
+  s.RL = (uint16_t *)(s.CH + N);
+  // wind bits, 1 + last flip slot, updates, length of the ready list
+  int *RED = (int *)(lds + ((38 * (size_t)N + 15) & ~(size_t)15));
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x, T = blockDim.x;
   const uint64_t seed = a.seeds != nullptr ? a.seeds[b] : 0u;
@@ -225,6 +254,14 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   for (int i = tid; i < N; i += T) s.CH[i] = 0;
   __syncthreads();
 
+  // coordinates of the sites this thread owns (x | y << 16), so that no
+  // division by L runs inside the slot loop
+  uint32_t xy[ASYNC_SITES];
+#pragma unroll
+  for (int k = 0; k < ASYNC_SITES; ++k) {
+    const int i = min(tid + k * T, N - 1);
+    xy[k] = (uint32_t)(i % L) | (uint32_t)(i / L) << 16;
+  }
   const bool run = a.t_target >= 0;
   const uint32_t target = run ? 4u * (uint32_t)a.t_target : 0u;
   int last_flip = -1;
@@ -238,43 +275,65 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
       for (int h = tid; 2 * h < N; h += T) {
         const Words4 w = philox4x32_10((uint32_t)h, k0, k1, (uint32_t)slot, CLOCK_TAG);
         const int i0 = 2 * h, i1 = 2 * h + 1;
-        s.PR[i0] = w.w1;
-        s.PD[i0] = (uint64_t)w.w0 < a.ring_thr && (!run || s.TS[i0] < target);
+        const bool r0 = (uint64_t)w.w0 < a.ring_thr && (!run || s.TS[i0] < target);
+        s.K[i0] = r0 ? ((uint64_t)w.w1 << 32 | (uint32_t)i0) : IDLE;
         if (i1 < N) {
-          s.PR[i1] = w.w3;
-          s.PD[i1] = (uint64_t)w.w2 < a.ring_thr && (!run || s.TS[i1] < target);
+          const bool r1 = (uint64_t)w.w2 < a.ring_thr && (!run || s.TS[i1] < target);
+          s.K[i1] = r1 ? ((uint64_t)w.w3 << 32 | (uint32_t)i1) : IDLE;
         }
       }
     }
     busy_any = __syncthreads_or(busy);
     if (!busy_any || slot >= a.S_max) break;
     for (;;) {
-      uint32_t ready = 0;
-      int pend = 0, kk = 0;
-      for (int i = tid; i < N; i += T, ++kk) {
-        if (!s.PD[i]) continue;
-        pend = 1;
-        const int x = i % L, y = i / L;
-        const uint32_t pri = s.PR[i];
-        bool first = true;
-        for (int dy = -2; dy <= 2 && first; ++dy) {
-          const int row = wrapc(y + dy, L) * L;
-          for (int dx = -2; dx <= 2; ++dx) {
-            const int q = row + wrapc(x + dx, L);
-            if ((dx | dy) && s.PD[q] && (s.PR[q] < pri || (s.PR[q] == pri && q < i))) {
-              first = false;
-              break;
-            }
-          }
+      // row minima of the keys over x - 2 .. x + 2
+      int pend = 0;
+      if (tid == 0) RED[3] = 0;
+#pragma unroll
+      for (int k = 0; k < ASYNC_SITES; ++k) {
+        const int i = tid + k * T;
+        if (i < N) {
+          const int x = (int)(xy[k] & 0xFFFFu), r0 = i - x;
+          const uint64_t key = s.K[i];
+          pend |= key != IDLE;
+          s.H[i] = min64(min64(min64(key, s.K[r0 + wrapc(x - 2, L)]), min64(s.K[r0 + wrapc(x - 1, L)],
+                         s.K[r0 + wrapc(x + 1, L)])), s.K[r0 + wrapc(x + 2, L)]);
         }
-        if (first) ready |= 1u << kk;
       }
       if (!__syncthreads_or(pend)) break;
-      kk = 0;
-      for (int i = tid; i < N; i += T, ++kk) {
-        if (!((ready >> kk) & 1u)) continue;
-        s.PD[i] = 0;
-        const int r = async_attempt(s, L, i);
+      // a pending site holding the minimum of its box is ready: list it
+#pragma unroll
+      for (int k = 0; k < ASYNC_SITES; ++k) {
+        const int i = tid + k * T;
+        bool ready = false;
+        if (i < N) {
+          const uint64_t key = s.K[i];
+          if (key != IDLE) {
+            const int x = (int)(xy[k] & 0xFFFFu), y = (int)(xy[k] >> 16);
+            const uint64_t m = min64(min64(min64(s.H[i], s.H[wrapc(y - 2, L) * L + x]),
+                                           min64(s.H[wrapc(y - 1, L) * L + x], s.H[wrapc(y + 1, L) * L + x])),
+                                     s.H[wrapc(y + 2, L) * L + x]);
+            ready = m == key;
+          }
+        }
+        const uint64_t bal = __ballot(ready);
+        if (bal) {
+          const int lane = tid & 63;
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&RED[3], __popcll(bal));
+          base = __shfl(base, 0);
+          if (ready) {
+            s.RL[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)i;
+            s.K[i] = IDLE;
+          }
+        }
+      }
+      __syncthreads();
+      // the listed sites attempt their updates, one per lane
+      const int nready = RED[3];
+      for (int e = tid; e < nready; e += T) {
+        const int i = s.RL[e];
+        const int r = async_attempt(s, L, i, i % L, i / L);
         my_updates += r > 0;
         if (r == 2) last_flip = slot;
       }
@@ -325,11 +384,13 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   }
 }
 
-bool async_ok(int L) { return L >= 5 && L <= 64; }
+bool async_ok(int L) { return L >= 5 && L <= 64 && async_lds(L) <= 160 * 1024; }
 
 int launch_async(const AsyncArgs &a, int64_t n, hipStream_t stream) {
   const int N = a.L * a.L;
-  const int threads = std::min(1024, (N + 63) / 64 * 64);
+  // four sites per thread (one wave for the smallest lattices), so that small
+  // lattices leave room for several workgroups per compute unit
+  const int threads = std::min(1024, std::max(64, (N / 4 + 63) / 64 * 64));
   ProfScope ps("k_async", stream);
   hipLaunchKernelGGL(k_async, dim3((unsigned)n), dim3(threads), async_lds(a.L), stream, a);
   HIP_TRY(hipGetLastError());
