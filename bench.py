@@ -64,11 +64,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1024)
-    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn", "rule", "open"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn", "rule", "open", "async"],
+                    default="c3",
                     help="c3 (default) is the headline line; c1/c2/c4/c5 print a line for that configuration, "
                          "cnn times the predictor's kernels, rule the limited-memory variant at L = 256, open the "
-                         "open lattice at L = 64 and 128")
+                         "open lattice at L = 64 and 128, async the marching-soldiers desynchronized decoder at "
+                         "L = 32 and 64")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduling leg")
+    ap.add_argument("--async-case", type=int, default=-1,
+                    help="async workload: run only this case of its list (0: L=64 p=0.05, 1: L=64 p=0.03, "
+                         "2: L=32 p=0.05); -1 runs all")
     ap.add_argument("--streams", type=int, default=None,
                     help="batches in flight, each on its own stream, host thread and workspace (default 3 for "
                          "the L = 256 workloads c3/c5, 1 for the short batches of c1/c2/c4)")
@@ -350,6 +355,8 @@ def other_workload(args, b, seeds, torch, np):
         return limited_memory(args, b, seeds, torch, np, runner)
     if args.workload == "open":
         return open_lattice(args, b, seeds, torch, np)
+    if args.workload == "async":
+        return desynchronized(args, b, seeds, torch, np)
     if args.workload == "c4":
         Ls, ps, ss = mixed_batch()
         classes = [(L, int((Ls == L).sum())) for L in dict.fromkeys(Ls.tolist())]
@@ -452,6 +459,70 @@ def open_lattice(args, b, seeds, torch, np):
             line[name] = {"samples_per_s": K * n / dt, "site_updates_per_s": L * L * T.sum() / dt,
                           "ms_per_batch": dt / K * 1e3, "mean_T_dec": float(T.mean()),
                           "fail_rate": float((F & 1).mean())}
+        print(json.dumps(line), flush=True)
+
+
+def desynchronized(args, b, seeds, torch, np):
+    """The marching-soldiers desynchronized decoder (ring probability 1/8 per
+    slot, close to independent Poisson clocks) on fresh seeded batches, timed
+    with HIP events on its stream, beside the synchronous decoder on the same
+    seeds (decoding-time slowdown, identical outcomes) and the oracle."""
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    rho, S_max = 0.125, 20000
+    st = torch.cuda.current_stream()
+    cases = ((64, 0.05, 1024), (64, 0.03, 1024), (32, 0.05, 2048))
+    for L_a, p, n in (cases if args.async_case < 0 else cases[args.async_case:args.async_case + 1]):
+        batches = [torch.from_numpy(seeds(11, int(p * 1000) + L_a, n, start=i * n).view(np.int64)).to(dev)
+                   for i in range(W + K)]
+        outs = [tuple(torch.empty(n, dtype=dt, device=dev) for dt in (torch.int32, torch.uint8, torch.int32,
+                                                                        torch.int64)) + (None,)
+                for _ in range(W + K)]
+        for i in range(W):
+            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st)
+        torch.cuda.synchronize()
+        b.profile(True)
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.profile(False)
+        kms, launches = b.profile_read("k_async")
+        cat = lambda j: torch.cat([outs[i][j] for i in range(W, W + K)]).cpu().numpy()
+        T, F, SL, U = cat(0), cat(1), cat(2).astype(np.int64), cat(3).astype(np.int64)
+        # the synchronous decoder on the same seeds
+        sync = [b.decode_batch(L_a, p, batches[i], 4096, want_syndrome=False) for i in range(W, W + K)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sync = [b.decode_batch(L_a, p, batches[i], 4096, want_syndrome=False) for i in range(W, W + K)]
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t1
+        Ts = torch.cat([x[0] for x in sync]).cpu().numpy().astype(np.int64)
+        Fs = torch.cat([x[1] for x in sync]).cpu().numpy()
+        both = ((F & 2) == 0) & ((Fs & 2) == 0)
+        line = {"workload": f"desynchronized decoder: L={L_a} p={p} {n} samples per batch, ring probability {rho} "
+                            f"per slot, S_max={S_max}",
+                "samples_per_s": K * n / dt, "ms_per_batch": dt / K * 1e3,
+                "kernel": {"name": "k_async", "avg_launch_ms": kms / max(launches, 1), "launches": launches},
+                "accepted_updates_per_s": float(U.sum()) / dt,
+                "slots_mean": float(SL.mean()), "slots_max": int(SL.max()),
+                "decoding_time_mean": float(T.mean()) * rho, "sync_T_dec_mean": float(Ts.mean()),
+                "slowdown": float(T.mean()) * rho / max(float(Ts.mean()), 1e-9),
+                "fail_rate": float((F & 1).mean()), "sync_fail_rate": float((Fs & 1).mean()),
+                "timeouts": int(((F & 2) > 0).sum()),
+                "outcomes_equal_sync": bool(np.array_equal(F[both], Fs[both])),
+                "sync_samples_per_s": K * n / dts}
+        if not args.no_cpu_baseline:
+            import oracle
+            m = 64
+            s_cpu = seeds(11, int(p * 1000) + L_a, m, start=W * n)
+            tc = time.perf_counter()
+            r = oracle.async_decode_seeds(L_a, p, s_cpu, rho=rho, S_max=S_max, want_sigma=False)
+            tcpu = time.perf_counter() - tc
+            line["cpu_baseline"] = {"value": m / tcpu, "unit": "samples/s", "cores": r["threads"], "kind": "oracle",
+                                    "sample": f"first {m} samples of the first timed batch, {tcpu:.1f} s wall"}
+            assert np.array_equal(r["T_async"], T[:m]) and np.array_equal(r["flags"], F[:m])
         print(json.dumps(line), flush=True)
 
 

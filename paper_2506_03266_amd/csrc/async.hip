@@ -80,7 +80,7 @@ constexpr int ASYNC_SITES = 4;   // sites per thread; the launch uses at least N
 
 size_t async_lds(int L) {
   const size_t N = (size_t)L * L;
-  return ((38 * N + 15) & ~(size_t)15) + 16;
+  return ((38 * N + 15) & ~(size_t)15) + 32;
 }
 
 __device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
@@ -216,13 +216,13 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   s.FL = (uint8_t *)(s.TS + N);
   s.CH = s.FL + N;
   s.RL = (uint16_t *)(s.CH + N);
-  // wind bits, 1 + last flip slot, updates, length of the ready list
+  // wind bits, 1 + last flip slot, updates, lengths of the ready list (two)
   int *RED = (int *)(lds + ((38 * (size_t)N + 15) & ~(size_t)15));
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x, T = blockDim.x;
   const uint64_t seed = a.seeds != nullptr ? a.seeds[b] : 0u;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  if (tid < 4) RED[tid] = 0;
+  if (tid < 8) RED[tid] = 0;
   const int LW = (2 * N + 31) / 32;
   for (int i = tid; i < N; i += T) {
     uint32_t e;
@@ -285,59 +285,89 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
     }
     busy_any = __syncthreads_or(busy);
     if (!busy_any || slot >= a.S_max) break;
-    for (;;) {
-      // row minima of the keys over x - 2 .. x + 2
+    // Rounds.  The row pass of the next round shares the update phase of the
+    // current one: it reads only the keys, which change only in the listing
+    // phase, and writes H, which only the listing phase reads.  The
+    // ready-list length alternates between two counters so that one is
+    // cleared while the other is read.
+    if (tid == 0) {
+      RED[3] = 0;
+      RED[4] = 0;
+    }
+    uint64_t kv[ASYNC_SITES][5];
+    auto row_pass = [&]() {
+      // row minima of the keys over x - 2 .. x + 2 (all loads of the thread's
+      // sites issued together); returns whether any own site is pending
+#pragma unroll
+      for (int k = 0; k < ASYNC_SITES; ++k) {
+        const int i = min(tid + k * T, N - 1);
+        const int x = (int)(xy[k] & 0xFFFFu), r0 = i - x;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) kv[k][d] = s.K[r0 + wrapc(x + d - 2, L)];
+      }
       int pend = 0;
-      if (tid == 0) RED[3] = 0;
 #pragma unroll
       for (int k = 0; k < ASYNC_SITES; ++k) {
         const int i = tid + k * T;
         if (i < N) {
-          const int x = (int)(xy[k] & 0xFFFFu), r0 = i - x;
-          const uint64_t key = s.K[i];
-          pend |= key != IDLE;
-          s.H[i] = min64(min64(min64(key, s.K[r0 + wrapc(x - 2, L)]), min64(s.K[r0 + wrapc(x - 1, L)],
-                         s.K[r0 + wrapc(x + 1, L)])), s.K[r0 + wrapc(x + 2, L)]);
+          pend |= kv[k][2] != IDLE;
+          s.H[i] = min64(min64(min64(kv[k][0], kv[k][1]), min64(kv[k][2], kv[k][3])), kv[k][4]);
         }
       }
+      return pend;
+    };
+    int pend = row_pass();
+    for (int round = 0;; ++round) {
       if (!__syncthreads_or(pend)) break;
-      // a pending site holding the minimum of its box is ready: list it
+      int *cnt = &RED[3 + (round & 1)];
+      // a pending site holding the minimum of its box is ready
+      uint32_t rbits = 0;
 #pragma unroll
       for (int k = 0; k < ASYNC_SITES; ++k) {
-        const int i = tid + k * T;
-        bool ready = false;
-        if (i < N) {
-          const uint64_t key = s.K[i];
-          if (key != IDLE) {
-            const int x = (int)(xy[k] & 0xFFFFu), y = (int)(xy[k] >> 16);
-            const uint64_t m = min64(min64(min64(s.H[i], s.H[wrapc(y - 2, L) * L + x]),
-                                           min64(s.H[wrapc(y - 1, L) * L + x], s.H[wrapc(y + 1, L) * L + x])),
-                                     s.H[wrapc(y + 2, L) * L + x]);
-            ready = m == key;
-          }
+        const int x = (int)(xy[k] & 0xFFFFu), y = (int)(xy[k] >> 16);
+        uint64_t m = IDLE;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) m = min64(m, s.H[wrapc(y + d - 2, L) * L + x]);
+        const bool ready = tid + k * T < N && kv[k][2] != IDLE && m == kv[k][2];
+        rbits |= (ready ? 1u : 0u) << k;
+      }
+      // list the ready sites: one atomic per wave, offsets from the ballots
+      {
+        const int lane = tid & 63;
+        const uint64_t below = (lane ? (~0ull >> (64 - lane)) : 0ull);
+        uint64_t bal[ASYNC_SITES];
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < ASYNC_SITES; ++k) {
+          bal[k] = __ballot((rbits >> k) & 1u);
+          tot += __popcll(bal[k]);
         }
-        const uint64_t bal = __ballot(ready);
-        if (bal) {
-          const int lane = tid & 63;
+        if (tot) {
           int base = 0;
-          if (lane == 0) base = atomicAdd(&RED[3], __popcll(bal));
-          base = __shfl(base, 0);
-          if (ready) {
-            s.RL[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)i;
-            s.K[i] = IDLE;
+          if (lane == 0) base = atomicAdd(cnt, tot);
+          base = __builtin_amdgcn_readfirstlane(base);
+#pragma unroll
+          for (int k = 0; k < ASYNC_SITES; ++k) {
+            if ((rbits >> k) & 1u) {
+              const int i = tid + k * T;
+              s.RL[base + __popcll(bal[k] & below)] = (uint16_t)i;
+              s.K[i] = IDLE;
+            }
+            base += __popcll(bal[k]);
           }
         }
       }
       __syncthreads();
       // the listed sites attempt their updates, one per lane
-      const int nready = RED[3];
+      const int nready = *cnt;
+      if (tid == 0) RED[3 + ((round + 1) & 1)] = 0;
       for (int e = tid; e < nready; e += T) {
         const int i = s.RL[e];
         const int r = async_attempt(s, L, i, i % L, i / L);
         my_updates += r > 0;
         if (r == 2) last_flip = slot;
       }
-      __syncthreads();
+      pend = row_pass();
     }
   }
 
