@@ -115,6 +115,15 @@
  *       then holds no anyon, so no link can flip again.  T_async = 1 + the
  *       last slot with a flip (0 if none); outcome as R10, R11.
  *
+ * Uncoordinated desynchronization (Sec. "Uncoordinated desynchronization"):
+ *   R28 the same clock (R26) and update schedule (v message updates, then one
+ *       motion update, cyclically), without the lag rule and without old
+ *       copies: a message update reads the current registers and syndromes
+ *       on its lines; a motion update of an anyon site moves that anyon one
+ *       link along its force (+a for f^a = -1, -a for f^a = +1), which
+ *       annihilates it with an anyon there.  A decode ends at the first slot
+ *       boundary with no anyon; T_un = 1 + the last slot with a move.
+ *
  * Site index i = y*L + x.  The x-link of site (x,y) joins (x,y) and
  * (x+1,y); its y-link joins (x,y) and (x,y+1) (indices mod L).
  * Register order in every array: d = 0: +x, 1: -x, 2: +y, 3: -y, i.e.
@@ -714,6 +723,7 @@ typedef struct {
   uint8_t *acc[2];     /* flips applied at each site by the feedback of step k, slot k mod 2 (R25) */
   int64_t updates;     /* accepted updates */
   int64_t flips;       /* links flipped */
+  int unc;             /* uncoordinated desynchronization (R28) instead of marching soldiers */
 } orc_async;
 
 static void orc_async_free(orc_async *a) {
@@ -739,6 +749,39 @@ static int orc_async_alloc(orc_async *a, int L, int v) {
   ok = ok && a->ps && a->tsim && a->acc[0] && a->acc[1];
   if (!ok) { orc_async_free(a); return ORC_ENOMEM; }
   return ORC_OK;
+}
+
+/* One update of site (x, y) of the uncoordinated desynchronization (R28):
+ * no lag rule, current values only.  Returns 1 (every update is applied). */
+static int orc_uncoord_update(orc_async *a, int x, int y) {
+  orc_state *st = &a->st;
+  int L = st->L, v = st->v;
+  int64_t r = (int64_t)y * L + x;
+  int32_t j = a->tsim[r];
+  if (j % (v + 1) < v) {
+    int32_t out[4];
+    for (int d = 0; d < 4; ++d) out[d] = orc_register_value(st, st->m, st->sigma, d, x, y);
+    for (int d = 0; d < 4; ++d) st->m[d][r] = out[d];
+  } else if (st->sigma[r] == -1) {
+    /* the anyon at r moves one link along its force: +a for f^a = -1, -a for
+     * f^a = +1 (the sign of the link exponent sigma_r f_r with sigma_r = -1) */
+    int8_t fx, fy;
+    st->t = j / (v + 1) + 1;
+    orc_site_force(st, st->m, st->sigma, r, &fx, &fy);
+    int64_t q = -1;
+    if (fx == -1) { st->cx[r] ^= 1; q = (int64_t)y * L + wrap(x + 1, L); }
+    else if (fx == 1) { q = (int64_t)y * L + wrap(x - 1, L); st->cx[q] ^= 1; }
+    else if (fy == -1) { st->cy[r] ^= 1; q = (int64_t)wrap(y + 1, L) * L + x; }
+    else if (fy == 1) { q = (int64_t)wrap(y - 1, L) * L + x; st->cy[q] ^= 1; }
+    if (q >= 0) {
+      st->sigma[r] = (int8_t)(-st->sigma[r]);
+      st->sigma[q] = (int8_t)(-st->sigma[q]);
+      ++a->flips;
+    }
+  }
+  a->tsim[r] = j + 1;
+  ++a->updates;
+  return 1;
 }
 
 /* One attempted automaton update of site (x, y) of the desynchronized
@@ -827,13 +870,14 @@ static int orc_ring_cmp(const void *pa, const void *pb) {
  * probability per slot times 2^32.  Outputs: slots run, T_async = 1 + the
  * slot of the last flip (0 if none), accepted updates, and optionally the
  * final syndrome words, m^new [4][L*L], t_sim [L*L] and the chain C. */
-int orc_async_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex, const uint8_t *ey,
-                  int t_target, int S_max, int32_t *slots_out, int32_t *T_async, uint8_t *flags,
-                  int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out, int32_t *tsim_out,
-                  uint8_t *cx_out, uint8_t *cy_out) {
+static int orc_desync_run(int unc, int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex,
+                          const uint8_t *ey, int t_target, int S_max, int32_t *slots_out, int32_t *T_async,
+                          uint8_t *flags, int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out,
+                          int32_t *tsim_out, uint8_t *cx_out, uint8_t *cy_out) {
   if (L < 5 || v < 1 || S_max < 0 || ring_thr < 1 || ring_thr > ((uint64_t)1 << 32)) return ORC_EBADARG;
   orc_async a;
   if (orc_async_alloc(&a, L, v) != ORC_OK) return ORC_ENOMEM;
+  a.unc = unc;
   orc_state *st = &a.st;
   st->key[0] = (uint32_t)(seed & 0xffffffffu);
   st->key[1] = (uint32_t)(seed >> 32);
@@ -867,7 +911,7 @@ int orc_async_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t 
     for (int64_t q = 0; q < nr && rc == ORC_OK; ++q) {
       int32_t i = ring[q].i;
       if (t_target >= 0 && a.tsim[i] >= target) continue;
-      int got = orc_async_update(&a, i % L, i / L);
+      int got = a.unc ? orc_uncoord_update(&a, i % L, i / L) : orc_async_update(&a, i % L, i / L);
       if (got < 0) rc = got;
     }
     if (rc != ORC_OK) break;
@@ -896,11 +940,29 @@ int orc_async_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t 
   return rc;
 }
 
+int orc_async_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex, const uint8_t *ey,
+                  int t_target, int S_max, int32_t *slots_out, int32_t *T_async, uint8_t *flags,
+                  int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out, int32_t *tsim_out,
+                  uint8_t *cx_out, uint8_t *cy_out) {
+  return orc_desync_run(0, L, v, seed, ring_thr, ex, ey, t_target, S_max, slots_out, T_async, flags, updates_out,
+                        sigma_words, m_out, tsim_out, cx_out, cy_out);
+}
+
+/* The uncoordinated desynchronization (R28) with the same clock, outputs
+ * and stopping rules; t_sim counts every update. */
+int orc_uncoord_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex, const uint8_t *ey,
+                    int t_target, int S_max, int32_t *slots_out, int32_t *T_un, uint8_t *flags,
+                    int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out, int32_t *tsim_out,
+                    uint8_t *cx_out, uint8_t *cy_out) {
+  return orc_desync_run(1, L, v, seed, ring_thr, ex, ey, t_target, S_max, slots_out, T_un, flags, updates_out,
+                        sigma_words, m_out, tsim_out, cx_out, cy_out);
+}
+
 /* Noise (R12) + desynchronized decode for a batch of seeds, spread over
  * OpenMP threads; the seed keys both the noise and the clock. */
-int orc_async_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
-                           uint64_t ring_thr, int S_max, int nthreads, int32_t *T_async, uint8_t *flags,
-                           int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
+static int orc_desync_seeds(int unc, int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
+                            uint64_t ring_thr, int S_max, int nthreads, int32_t *T_async, uint8_t *flags,
+                            int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
   if (L < 5 || v < 1 || n < 0 || S_max < 0) return ORC_EBADARG;
   int64_t nsite = (int64_t)L * L, nw = (nsite + 31) / 32;
   int err = ORC_OK, used = 1;
@@ -922,8 +984,8 @@ int orc_async_decode_seeds(int L, int v, const double *p, int p_stride, const ui
     int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
     if (rc == ORC_OK) rc = orc_noise(L, p[p_stride ? k : 0], seeds[k], ex, ey);
     if (rc == ORC_OK)
-      rc = orc_async_run(L, v, seeds[k], ring_thr, ex, ey, -1, S_max, &slots_out[k], &T_async[k], &flags[k],
-                         &updates_out[k], sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
+      rc = orc_desync_run(unc, L, v, seeds[k], ring_thr, ex, ey, -1, S_max, &slots_out[k], &T_async[k], &flags[k],
+                          &updates_out[k], sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
     if (rc != ORC_OK) {
 #pragma omp critical
       err = rc;
@@ -932,4 +994,18 @@ int orc_async_decode_seeds(int L, int v, const double *p, int p_stride, const ui
     free(ey);
   }
   return err;
+}
+
+int orc_async_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
+                           uint64_t ring_thr, int S_max, int nthreads, int32_t *T_async, uint8_t *flags,
+                           int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
+  return orc_desync_seeds(0, L, v, p, p_stride, seeds, n, ring_thr, S_max, nthreads, T_async, flags, slots_out,
+                          updates_out, sigma_words, threads_used);
+}
+
+int orc_uncoord_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
+                             uint64_t ring_thr, int S_max, int nthreads, int32_t *T_un, uint8_t *flags,
+                             int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
+  return orc_desync_seeds(1, L, v, p, p_stride, seeds, n, ring_thr, S_max, nthreads, T_un, flags, slots_out,
+                          updates_out, sigma_words, threads_used);
 }
