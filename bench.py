@@ -466,7 +466,8 @@ def desynchronized(args, b, seeds, torch, np):
     """The marching-soldiers desynchronized decoder (ring probability 1/8 per
     slot, close to independent Poisson clocks) on fresh seeded batches, timed
     with HIP events on its stream, beside the synchronous decoder on the same
-    seeds (decoding-time slowdown, identical outcomes) and the oracle."""
+    seeds (decoding-time slowdown, identical outcomes), the uncoordinated
+    desynchronization on the same batches, and the oracle of each."""
     dev = torch.device("cuda:0")
     K, W = args.steps, args.warmup
     rho, S_max = 0.125, 20000
@@ -513,16 +514,39 @@ def desynchronized(args, b, seeds, torch, np):
                 "timeouts": int(((F & 2) > 0).sum()),
                 "outcomes_equal_sync": bool(np.array_equal(F[both], Fs[both])),
                 "sync_samples_per_s": K * n / dts}
+        # the uncoordinated desynchronization on the same batches
+        for i in range(W):
+            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st, uncoordinated=True)
+        torch.cuda.synchronize()
+        b.profile(True)
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st, uncoordinated=True)
+        torch.cuda.synchronize()
+        dtu = time.perf_counter() - t0
+        b.profile(False)
+        kmu, lu = b.profile_read("k_async_unc")
+        Tu, Fu, SLu, Uu = cat(0), cat(1), cat(2).astype(np.int64), cat(3).astype(np.int64)
+        line["uncoordinated"] = {"samples_per_s": K * n / dtu, "ms_per_batch": dtu / K * 1e3,
+                                 "kernel": {"name": "k_async_unc", "avg_launch_ms": kmu / max(lu, 1), "launches": lu},
+                                 "updates_per_s": float(Uu.sum()) / dtu, "slots_mean": float(SLu.mean()),
+                                 "decoding_time_mean": float(Tu.mean()) * rho, "fail_rate": float((Fu & 1).mean()),
+                                 "timeouts": int(((Fu & 2) > 0).sum())}
         if not args.no_cpu_baseline:
             import oracle
-            m = 64
+            m = 256
             s_cpu = seeds(11, int(p * 1000) + L_a, m, start=W * n)
-            tc = time.perf_counter()
-            r = oracle.async_decode_seeds(L_a, p, s_cpu, rho=rho, S_max=S_max, want_sigma=False)
-            tcpu = time.perf_counter() - tc
-            line["cpu_baseline"] = {"value": m / tcpu, "unit": "samples/s", "cores": r["threads"], "kind": "oracle",
-                                    "sample": f"first {m} samples of the first timed batch, {tcpu:.1f} s wall"}
-            assert np.array_equal(r["T_async"], T[:m]) and np.array_equal(r["flags"], F[:m])
+            for key, unc, Tg, Fg in (("cpu_baseline", False, T, F), ("uncoordinated_cpu_baseline", True, Tu, Fu)):
+                tc = time.perf_counter()
+                r = oracle.async_decode_seeds(L_a, p, s_cpu, rho=rho, S_max=S_max, want_sigma=False, uncoordinated=unc)
+                tcpu = time.perf_counter() - tc
+                cpu = {"value": m / tcpu, "unit": "samples/s", "cores": r["threads"], "kind": "oracle",
+                       "sample": f"first {m} samples of the first timed batch, {tcpu:.1f} s wall"}
+                if unc:
+                    line["uncoordinated"]["cpu_baseline"] = cpu
+                else:
+                    line["cpu_baseline"] = cpu
+                assert np.array_equal(r["T_async"], Tg[:m]) and np.array_equal(r["flags"], Fg[:m])
         print(json.dumps(line), flush=True)
 
 

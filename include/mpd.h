@@ -243,6 +243,28 @@ int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds,
                   int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out, uint16_t *d_tsim_out,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
+/* Uncoordinated desynchronization (Sec. "Uncoordinated desynchronization")
+ * of the plain rule on the torus, 5 <= L <= 64: the same clock and update
+ * schedule as the marching-soldiers decoder (v = 3 message updates, then one
+ * motion update, per site and cyclically) without the lag rule and without
+ * old copies.  A message update reads the current registers and syndromes on
+ * its lines; a motion update of an anyon site moves that anyon one link
+ * along its force (+a for f^a = -1, -a for f^a = +1), annihilating it with
+ * an anyon there.  This is a different dynamics from the synchronous
+ * decoder's: outcomes and decoding times differ.
+ *
+ * mpd_decode_uncoord: as mpd_decode_async; a decode ends at the first slot
+ * boundary with no anyon; d_T_un = 1 + the last slot with a move.
+ * mpd_run_uncoord: as mpd_run_async (every site runs 4 t_target updates);
+ * t_sim counts all updates.  Arguments, layouts and errors as the
+ * marching-soldiers calls. */
+int mpd_decode_uncoord(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_un,
+                       uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
+                       void *stream);
+int mpd_run_uncoord(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
+                    double rho, int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
+                    uint16_t *d_tsim_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
 /* Temporal blocking of the band path (L >= 256): decoder steps run on chip per
  * pass over HBM, in the first pass (registers still empty) and in later
  * passes.  Results do not depend on it; speed does.  Each value in

@@ -100,6 +100,10 @@ def lib():
     L.mpd_decode_async.restype = I
     L.mpd_run_async.argtypes = [I, P, P, I64, I, D, I, P, P, P, P, P, P, P]
     L.mpd_run_async.restype = I
+    L.mpd_decode_uncoord.argtypes = L.mpd_decode_async.argtypes
+    L.mpd_decode_uncoord.restype = I
+    L.mpd_run_uncoord.argtypes = L.mpd_run_async.argtypes
+    L.mpd_run_uncoord.restype = I
     _lib = L
     return L
 
@@ -220,12 +224,13 @@ ASYNC_SLOT_LIMIT = 65000
 
 
 def decode_async(L: int, p: float, seeds, rho: float, S_max: int = ASYNC_SLOT_LIMIT, want_syndrome: bool = True,
-                 out=None, stream=None):
+                 out=None, stream=None, uncoordinated: bool = False):
     """Marching-soldiers desynchronized decode of seeded noise (5 <= L <= 64):
     the seed keys the noise and the clock, rho is the ring probability per
     slot.  Returns (T_async int32[n], flags uint8[n], slots int32[n],
     updates int64[n], syndrome int32[n, W] or None) on the device; `out` may
-    pass all five preallocated."""
+    pass all five preallocated.  uncoordinated=True runs the uncoordinated
+    desynchronization (mpd_decode_uncoord) instead."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()
@@ -237,17 +242,21 @@ def decode_async(L: int, p: float, seeds, rho: float, S_max: int = ASYNC_SLOT_LI
         S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
     else:
         T, F, SL, U, S = out
-    rc = lib().mpd_decode_async(L, float(p), _ptr(s), n, float(rho), int(S_max), _ptr(T), _ptr(F), _ptr(SL), _ptr(U),
-                                _ptr(S), _stream_ptr(stream))
-    _check(rc, "mpd_decode_async")
+    fn, name = (lib().mpd_decode_uncoord, "mpd_decode_uncoord") if uncoordinated else \
+        (lib().mpd_decode_async, "mpd_decode_async")
+    rc = fn(L, float(p), _ptr(s), n, float(rho), int(S_max), _ptr(T), _ptr(F), _ptr(SL), _ptr(U), _ptr(S),
+            _stream_ptr(stream))
+    _check(rc, name)
     return T, F, SL, U, S
 
 
-def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int = ASYNC_SLOT_LIMIT, stream=None):
+def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int = ASYNC_SLOT_LIMIT, stream=None,
+              uncoordinated: bool = False):
     """Desynchronized run of explicit error patterns until every site has
     completed t_target decoder steps (or S_max slots).  Returns (slots
     int32[n], updates int64[n], m int16[n,4,L,L], tsim int16[n,L,L] holding
-    uint16 values, syndrome int32[n,W], wind uint8[n])."""
+    uint16 values, syndrome int32[n,W], wind uint8[n]).  uncoordinated=True
+    runs mpd_run_uncoord."""
     dev = torch.device("cuda")
     links = _links_tensor(L, links, dev)
     n = links.shape[0]
@@ -260,9 +269,10 @@ def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int 
     TS = torch.empty((n, L, L), dtype=torch.int16, device=dev)
     S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
     W = torch.empty(n, dtype=torch.uint8, device=dev)
-    rc = lib().mpd_run_async(L, _ptr(links), _ptr(cs), n, int(t_target), float(rho), int(S_max), _ptr(SL), _ptr(U),
-                             _ptr(M), _ptr(TS), _ptr(S), _ptr(W), _stream_ptr(stream))
-    _check(rc, "mpd_run_async")
+    fn, name = (lib().mpd_run_uncoord, "mpd_run_uncoord") if uncoordinated else (lib().mpd_run_async, "mpd_run_async")
+    rc = fn(L, _ptr(links), _ptr(cs), n, int(t_target), float(rho), int(S_max), _ptr(SL), _ptr(U), _ptr(M), _ptr(TS),
+            _ptr(S), _ptr(W), _stream_ptr(stream))
+    _check(rc, name)
     return SL, U, M, TS, S, W
 
 

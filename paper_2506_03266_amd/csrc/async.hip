@@ -204,6 +204,59 @@ __device__ __forceinline__ int async_attempt(const AsyncLds &s, int L, int i, in
   return ret;
 }
 
+// One update of site i of the uncoordinated desynchronization: no lag rule
+// and no old copies.  Message updates read the current registers and anyon
+// bits on their lines; a motion update of an anyon site moves its anyon one
+// link along its force (+a for f^a = -1, -a for f^a = +1), annihilating it
+// with an anyon there.  Returns 1, or 2 if a link flipped.
+__device__ __forceinline__ int uncoord_update(const AsyncLds &s, int L, int i, int x, int y) {
+  const uint32_t j = s.TS[i];
+  const int xl = wrapc(x - 1, L), xr = wrapc(x + 1, L);
+  const int rd = wrapc(y - 1, L) * L, rc = y * L, ru = wrapc(y + 1, L) * L;
+  int ret = 1;
+  if ((j & 3u) < 3u) {
+    auto an = [&](int q) { return (s.FL[q] & 1u) != 0u; };
+    const int dl = rd + xl, dc = rd + x, dr = rd + xr;
+    const int cl = rc + xl, cr = rc + xr;
+    const int ul = ru + xl, uc = ru + x, ur = ru + xr;
+    const uint2 mdl = s.MN[dl], mdc = s.MN[dc], mdr = s.MN[dr], mcl = s.MN[cl], mcr = s.MN[cr], mul = s.MN[ul],
+                muc = s.MN[uc], mur = s.MN[ur];
+    const uint32_t px = rule_A(an(dl) || an(cl) || an(ul), mdl.x & 0xFFFFu, mcl.x & 0xFFFFu, mul.x & 0xFFFFu);
+    const uint32_t mx = rule_A(an(dr) || an(cr) || an(ur), mdr.x >> 16, mcr.x >> 16, mur.x >> 16);
+    const uint32_t py = rule_A(an(dl) || an(dc) || an(dr), mdl.y & 0xFFFFu, mdc.y & 0xFFFFu, mdr.y & 0xFFFFu);
+    const uint32_t my = rule_A(an(ul) || an(uc) || an(ur), mul.y >> 16, muc.y >> 16, mur.y >> 16);
+    s.MN[i] = make_uint2(px | mx << 16, py | my << 16);
+  } else if (s.FL[i] & 1u) {
+    int fx, fy;
+    site_force(s.MN[i], fx, fy);
+    int q = -1;
+    if (fx == -1) {
+      q = rc + xr;
+      s.CH[i] ^= 1u;
+    } else if (fx == 1) {
+      q = rc + xl;
+      s.CH[q] ^= 1u;
+    } else if (fy == -1) {
+      q = ru + x;
+      s.CH[i] ^= 2u;
+    } else if (fy == 1) {
+      q = rd + x;
+      s.CH[q] ^= 2u;
+    }
+    if (q >= 0) {
+      s.FL[i] ^= 1u;
+      s.FL[q] ^= 1u;
+      ret = 2;
+    }
+  }
+  s.TS[i] = (uint16_t)(j + 1u);
+  return ret;
+}
+
+// UNC selects the uncoordinated desynchronization; the clock, the rounds and
+// the outputs are shared (its ready sites are likewise more than 2 apart,
+// and what it reads and writes lies within distance 1).
+template <bool UNC>
 __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int L = a.L, N = L * L;
@@ -363,7 +416,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
       if (tid == 0) RED[3 + ((round + 1) & 1)] = 0;
       for (int e = tid; e < nready; e += T) {
         const int i = s.RL[e];
-        const int r = async_attempt(s, L, i, i % L, i / L);
+        const int r = UNC ? uncoord_update(s, L, i, i % L, i / L) : async_attempt(s, L, i, i % L, i / L);
         my_updates += r > 0;
         if (r == 2) last_flip = slot;
       }
@@ -416,13 +469,16 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
 
 bool async_ok(int L) { return L >= 5 && L <= 64 && async_lds(L) <= 160 * 1024; }
 
-int launch_async(const AsyncArgs &a, int64_t n, hipStream_t stream) {
+int launch_async(const AsyncArgs &a, int64_t n, bool unc, hipStream_t stream) {
   const int N = a.L * a.L;
   // four sites per thread (one wave for the smallest lattices), so that small
   // lattices leave room for several workgroups per compute unit
   const int threads = std::min(1024, std::max(64, (N / 4 + 63) / 64 * 64));
-  ProfScope ps("k_async", stream);
-  hipLaunchKernelGGL(k_async, dim3((unsigned)n), dim3(threads), async_lds(a.L), stream, a);
+  ProfScope ps(unc ? "k_async_unc" : "k_async", stream);
+  if (unc)
+    hipLaunchKernelGGL(k_async<true>, dim3((unsigned)n), dim3(threads), async_lds(a.L), stream, a);
+  else
+    hipLaunchKernelGGL(k_async<false>, dim3((unsigned)n), dim3(threads), async_lds(a.L), stream, a);
   HIP_TRY(hipGetLastError());
   return MPD_OK;
 }
@@ -443,20 +499,17 @@ static int async_check(int L, int64_t n, double rho, int S_max, uint64_t *ring_t
   return MPD_OK;
 }
 
-extern "C" {
-
-int mpd_decode_async(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_async,
-                     uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
-                     void *stream) {
-  g_last_error.clear();
+static int decode_desync(bool unc, int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max,
+                         int32_t *d_T, uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates,
+                         uint32_t *d_final_syndrome, void *stream) {
   uint64_t ring_thr = 0;
   int rc = async_check(L, n, rho, S_max, &ring_thr);
   if (rc) return rc;
   if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
   if (n == 0) return MPD_OK;
   if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u)) return fail_with(MPD_ERR_PTR, "seeds NULL or misaligned");
-  if (d_T_async == nullptr || d_flags == nullptr || ((uintptr_t)d_T_async & 3u))
-    return fail_with(MPD_ERR_PTR, "T_async / flags NULL or misaligned");
+  if (d_T == nullptr || d_flags == nullptr || ((uintptr_t)d_T & 3u))
+    return fail_with(MPD_ERR_PTR, "decoding-time / flags output NULL or misaligned");
   if ((d_slots != nullptr && ((uintptr_t)d_slots & 3u)) || (d_updates != nullptr && ((uintptr_t)d_updates & 7u)) ||
       (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u)))
     return fail_with(MPD_ERR_PTR, "optional output misaligned");
@@ -467,18 +520,17 @@ int mpd_decode_async(int L, double p, const uint64_t *d_seeds, int64_t n, double
   a.ring_thr = ring_thr;
   a.t_target = -1;
   a.S_max = S_max;
-  a.T_async = d_T_async;
+  a.T_async = d_T;
   a.flags = d_flags;
   a.slots = d_slots;
   a.updates = d_updates;
   a.syn = d_final_syndrome;
-  return launch_async(a, n, (hipStream_t)stream);
+  return launch_async(a, n, unc, (hipStream_t)stream);
 }
 
-int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target, double rho,
-                  int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out, uint16_t *d_tsim_out,
-                  uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
-  g_last_error.clear();
+static int run_desync(bool unc, int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
+                      double rho, int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
+                      uint16_t *d_tsim_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
   uint64_t ring_thr = 0;
   int rc = async_check(L, n, rho, S_max, &ring_thr);
   if (rc) return rc;
@@ -506,7 +558,41 @@ int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds,
   a.m_out = d_m_out;
   a.tsim_out = d_tsim_out;
   a.wind_out = d_wind_out;
-  return launch_async(a, n, (hipStream_t)stream);
+  return launch_async(a, n, unc, (hipStream_t)stream);
+}
+
+extern "C" {
+
+int mpd_decode_async(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_async,
+                     uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
+                     void *stream) {
+  g_last_error.clear();
+  return decode_desync(false, L, p, d_seeds, n, rho, S_max, d_T_async, d_flags, d_slots, d_updates, d_final_syndrome,
+                       stream);
+}
+
+int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target, double rho,
+                  int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out, uint16_t *d_tsim_out,
+                  uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  return run_desync(false, L, d_links, d_clock_seeds, n, t_target, rho, S_max, d_slots, d_updates, d_m_out,
+                    d_tsim_out, d_sigma_out, d_wind_out, stream);
+}
+
+int mpd_decode_uncoord(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_un,
+                       uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
+                       void *stream) {
+  g_last_error.clear();
+  return decode_desync(true, L, p, d_seeds, n, rho, S_max, d_T_un, d_flags, d_slots, d_updates, d_final_syndrome,
+                       stream);
+}
+
+int mpd_run_uncoord(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
+                    double rho, int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
+                    uint16_t *d_tsim_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  return run_desync(true, L, d_links, d_clock_seeds, n, t_target, rho, S_max, d_slots, d_updates, d_m_out,
+                    d_tsim_out, d_sigma_out, d_wind_out, stream);
 }
 
 }  // extern "C"

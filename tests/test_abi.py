@@ -230,3 +230,15 @@ def test_async_arguments_rejected(lib):
     assert r(L=3) == -1 and r(rho=2.0) == -2 and r(t=-1) == -3 and r(t=16251) == -3 and r(S=70000) == -3
     assert r(links=None) == -4 and r(cs=None) == -4 and r(m=None) == -4 and r(m=ctypes.c_void_p(257)) == -4
     assert r(n=0) == 0
+
+
+def test_uncoord_arguments_rejected(lib):
+    """The uncoordinated entry points share the desynchronized checks."""
+    dummy = ctypes.c_void_p(256)
+    assert lib.mpd_decode_uncoord(4, 0.1, dummy, 4, 0.5, 100, dummy, dummy, None, None, None, None) == -1
+    assert lib.mpd_decode_uncoord(16, 0.1, dummy, 4, 0.0, 100, dummy, dummy, None, None, None, None) == -2
+    assert lib.mpd_decode_uncoord(16, 0.1, dummy, 4, 0.5, -1, dummy, dummy, None, None, None, None) == -3
+    assert lib.mpd_decode_uncoord(16, 0.1, None, 4, 0.5, 100, dummy, dummy, None, None, None, None) == -4
+    assert lib.mpd_decode_uncoord(16, 0.1, dummy, 0, 0.5, 100, dummy, dummy, None, None, None, None) == 0
+    assert lib.mpd_run_uncoord(16, dummy, dummy, 4, -1, 0.5, 100, dummy, None, dummy, dummy, dummy, dummy, None) == -3
+    assert lib.mpd_run_uncoord(16, dummy, None, 4, 2, 0.5, 100, dummy, None, dummy, dummy, dummy, dummy, None) == -4
