@@ -123,6 +123,11 @@
  *       link along its force (+a for f^a = -1, -a for f^a = +1), which
  *       annihilates it with an anyon there.  A decode ends at the first slot
  *       boundary with no anyon; T_un = 1 + the last slot with a move.
+ *       Schedule "cyclic": the (v+1)-th update of a site is a motion.
+ *       Schedule "random": each update is a motion with probability
+ *       1 / (v+1), independently: word (i & 1) of Philox4x32-10(key = seed,
+ *       counter (i >> 1, slot, 0x54595045, 0)) mod (v+1) == v (the two kinds
+ *       of updates then run on independent Poisson clocks of rates v and 1).
  *
  * Site index i = y*L + x.  The x-link of site (x,y) joins (x,y) and
  * (x+1,y); its y-link joins (x,y) and (x,y+1) (indices mod L).
@@ -712,6 +717,7 @@ int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, 
 /* "faithful Lindbladian simulation"), readings R23-R27, torus only.        */
 /* ------------------------------------------------------------------------ */
 #define ORC_CLOCK_TAG 0x41535943u
+#define ORC_TYPE_TAG 0x54595045u
 #define ORC_EBROKEN -3   /* a lag left {0, 1} inside the update ball */
 
 typedef struct {
@@ -724,6 +730,8 @@ typedef struct {
   int64_t updates;     /* accepted updates */
   int64_t flips;       /* links flipped */
   int unc;             /* uncoordinated desynchronization (R28) instead of marching soldiers */
+  int sched;           /* R28 schedule: 0 cyclic, 1 random update types */
+  int32_t slot;        /* the slot being run */
 } orc_async;
 
 static void orc_async_free(orc_async *a) {
@@ -758,7 +766,15 @@ static int orc_uncoord_update(orc_async *a, int x, int y) {
   int L = st->L, v = st->v;
   int64_t r = (int64_t)y * L + x;
   int32_t j = a->tsim[r];
-  if (j % (v + 1) < v) {
+  int motion;
+  if (a->sched == 0) {
+    motion = j % (v + 1) == v;
+  } else {
+    uint32_t ctr[4] = {(uint32_t)(r >> 1), (uint32_t)a->slot, ORC_TYPE_TAG, 0u}, w[4];
+    orc_philox4x32_10(ctr, st->key, w);
+    motion = w[r & 1] % (uint32_t)(v + 1) == (uint32_t)v;
+  }
+  if (!motion) {
     int32_t out[4];
     for (int d = 0; d < 4; ++d) out[d] = orc_register_value(st, st->m, st->sigma, d, x, y);
     for (int d = 0; d < 4; ++d) st->m[d][r] = out[d];
@@ -870,7 +886,7 @@ static int orc_ring_cmp(const void *pa, const void *pb) {
  * probability per slot times 2^32.  Outputs: slots run, T_async = 1 + the
  * slot of the last flip (0 if none), accepted updates, and optionally the
  * final syndrome words, m^new [4][L*L], t_sim [L*L] and the chain C. */
-static int orc_desync_run(int unc, int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex,
+static int orc_desync_run(int unc, int sched, int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex,
                           const uint8_t *ey, int t_target, int S_max, int32_t *slots_out, int32_t *T_async,
                           uint8_t *flags, int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out,
                           int32_t *tsim_out, uint8_t *cx_out, uint8_t *cy_out) {
@@ -878,6 +894,7 @@ static int orc_desync_run(int unc, int L, int v, uint64_t seed, uint64_t ring_th
   orc_async a;
   if (orc_async_alloc(&a, L, v) != ORC_OK) return ORC_ENOMEM;
   a.unc = unc;
+  a.sched = sched;
   orc_state *st = &a.st;
   st->key[0] = (uint32_t)(seed & 0xffffffffu);
   st->key[1] = (uint32_t)(seed >> 32);
@@ -908,6 +925,7 @@ static int orc_desync_run(int unc, int L, int v, uint64_t seed, uint64_t ring_th
     }
     qsort(ring, (size_t)nr, sizeof(orc_ring), orc_ring_cmp);
     int64_t f0 = a.flips;
+    a.slot = slot;
     for (int64_t q = 0; q < nr && rc == ORC_OK; ++q) {
       int32_t i = ring[q].i;
       if (t_target >= 0 && a.tsim[i] >= target) continue;
@@ -944,23 +962,25 @@ int orc_async_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t 
                   int t_target, int S_max, int32_t *slots_out, int32_t *T_async, uint8_t *flags,
                   int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out, int32_t *tsim_out,
                   uint8_t *cx_out, uint8_t *cy_out) {
-  return orc_desync_run(0, L, v, seed, ring_thr, ex, ey, t_target, S_max, slots_out, T_async, flags, updates_out,
+  return orc_desync_run(0, 0, L, v, seed, ring_thr, ex, ey, t_target, S_max, slots_out, T_async, flags, updates_out,
                         sigma_words, m_out, tsim_out, cx_out, cy_out);
 }
 
 /* The uncoordinated desynchronization (R28) with the same clock, outputs
- * and stopping rules; t_sim counts every update. */
-int orc_uncoord_run(int L, int v, uint64_t seed, uint64_t ring_thr, const uint8_t *ex, const uint8_t *ey,
+ * and stopping rules; t_sim counts every update; sched 0 cyclic, 1 random
+ * update types. */
+int orc_uncoord_run(int L, int v, int sched, uint64_t seed, uint64_t ring_thr, const uint8_t *ex, const uint8_t *ey,
                     int t_target, int S_max, int32_t *slots_out, int32_t *T_un, uint8_t *flags,
                     int64_t *updates_out, uint32_t *sigma_words, int32_t *m_out, int32_t *tsim_out,
                     uint8_t *cx_out, uint8_t *cy_out) {
-  return orc_desync_run(1, L, v, seed, ring_thr, ex, ey, t_target, S_max, slots_out, T_un, flags, updates_out,
+  if (sched < 0 || sched > 1) return ORC_EBADARG;
+  return orc_desync_run(1, sched, L, v, seed, ring_thr, ex, ey, t_target, S_max, slots_out, T_un, flags, updates_out,
                         sigma_words, m_out, tsim_out, cx_out, cy_out);
 }
 
 /* Noise (R12) + desynchronized decode for a batch of seeds, spread over
  * OpenMP threads; the seed keys both the noise and the clock. */
-static int orc_desync_seeds(int unc, int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
+static int orc_desync_seeds(int unc, int sched, int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
                             uint64_t ring_thr, int S_max, int nthreads, int32_t *T_async, uint8_t *flags,
                             int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
   if (L < 5 || v < 1 || n < 0 || S_max < 0) return ORC_EBADARG;
@@ -984,7 +1004,7 @@ static int orc_desync_seeds(int unc, int L, int v, const double *p, int p_stride
     int rc = (ex && ey) ? ORC_OK : ORC_ENOMEM;
     if (rc == ORC_OK) rc = orc_noise(L, p[p_stride ? k : 0], seeds[k], ex, ey);
     if (rc == ORC_OK)
-      rc = orc_desync_run(unc, L, v, seeds[k], ring_thr, ex, ey, -1, S_max, &slots_out[k], &T_async[k], &flags[k],
+      rc = orc_desync_run(unc, sched, L, v, seeds[k], ring_thr, ex, ey, -1, S_max, &slots_out[k], &T_async[k], &flags[k],
                           &updates_out[k], sigma_words ? sigma_words + k * nw : NULL, NULL, NULL, NULL, NULL);
     if (rc != ORC_OK) {
 #pragma omp critical
@@ -999,13 +1019,14 @@ static int orc_desync_seeds(int unc, int L, int v, const double *p, int p_stride
 int orc_async_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
                            uint64_t ring_thr, int S_max, int nthreads, int32_t *T_async, uint8_t *flags,
                            int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
-  return orc_desync_seeds(0, L, v, p, p_stride, seeds, n, ring_thr, S_max, nthreads, T_async, flags, slots_out,
+  return orc_desync_seeds(0, 0, L, v, p, p_stride, seeds, n, ring_thr, S_max, nthreads, T_async, flags, slots_out,
                           updates_out, sigma_words, threads_used);
 }
 
-int orc_uncoord_decode_seeds(int L, int v, const double *p, int p_stride, const uint64_t *seeds, int64_t n,
-                             uint64_t ring_thr, int S_max, int nthreads, int32_t *T_un, uint8_t *flags,
+int orc_uncoord_decode_seeds(int L, int v, int sched, const double *p, int p_stride, const uint64_t *seeds,
+                             int64_t n, uint64_t ring_thr, int S_max, int nthreads, int32_t *T_un, uint8_t *flags,
                              int32_t *slots_out, int64_t *updates_out, uint32_t *sigma_words, int *threads_used) {
-  return orc_desync_seeds(1, L, v, p, p_stride, seeds, n, ring_thr, S_max, nthreads, T_un, flags, slots_out,
+  if (sched < 0 || sched > 1) return ORC_EBADARG;
+  return orc_desync_seeds(1, sched, L, v, p, p_stride, seeds, n, ring_thr, S_max, nthreads, T_un, flags, slots_out,
                           updates_out, sigma_words, threads_used);
 }

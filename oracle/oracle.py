@@ -80,9 +80,9 @@ def _load():
     lib.orc_async_run.restype = I
     lib.orc_async_decode_seeds.argtypes = [I, I, P, I, P, ctypes.c_int64, U64, I, I, P, P, P, P, P, P]
     lib.orc_async_decode_seeds.restype = I
-    lib.orc_uncoord_run.argtypes = lib.orc_async_run.argtypes
+    lib.orc_uncoord_run.argtypes = [I, I, I] + lib.orc_async_run.argtypes[2:]
     lib.orc_uncoord_run.restype = I
-    lib.orc_uncoord_decode_seeds.argtypes = lib.orc_async_decode_seeds.argtypes
+    lib.orc_uncoord_decode_seeds.argtypes = [I, I, I] + lib.orc_async_decode_seeds.argtypes[2:]
     lib.orc_uncoord_decode_seeds.restype = I
     _lib = lib
     return lib
@@ -256,14 +256,17 @@ def ring_threshold(rho: float) -> int:
     return max(1, min(1 << 32, int(rho * 4294967296.0)))
 
 
+SCHEDULES = {"cyclic": 0, "random": 1}
+
+
 def async_run(L: int, ex, ey, seed: int, rho: float = 1.0, t_target: int = -1, S_max: int = 100000,
-              v: int = 3, uncoordinated: bool = False):
+              v: int = 3, uncoordinated: bool = False, schedule: str = "cyclic"):
     """Marching-soldiers desynchronization of the plain rule (R23-R27) on one
     error chain, clock keyed by `seed`.  t_target >= 0 runs until every site
     has performed (v+1) t_target updates; t_target < 0 decodes.  Returns a dict
     with slots, T_async, flags, updates, sigma_words, m (m^new, [4, L, L]),
     tsim [L, L], cx, cy.  uncoordinated=True runs the uncoordinated
-    desynchronization instead (R28)."""
+    desynchronization instead (R28, with its "cyclic" or "random" schedule)."""
     n = L * L
     ex = np.ascontiguousarray(ex, dtype=np.uint8).reshape(-1)
     ey = np.ascontiguousarray(ey, dtype=np.uint8).reshape(-1)
@@ -276,7 +279,10 @@ def async_run(L: int, ex, ey, seed: int, rho: float = 1.0, t_target: int = -1, S
     tsim = np.zeros(n, np.int32)
     cx = np.zeros(n, np.uint8)
     cy = np.zeros(n, np.uint8)
-    fn = _load().orc_uncoord_run if uncoordinated else _load().orc_async_run
+    if uncoordinated:
+        fn = lambda L, v, *rest: _load().orc_uncoord_run(L, v, SCHEDULES[schedule], *rest)  # noqa: E731
+    else:
+        fn = _load().orc_async_run
     _check(fn(L, v, int(seed) & (2**64 - 1), ring_threshold(rho), _ptr(ex), _ptr(ey),
                                  int(t_target), int(S_max), _ptr(slots), _ptr(T), _ptr(flags), _ptr(upd),
                                  _ptr(words), _ptr(m), _ptr(tsim), _ptr(cx), _ptr(cy)), "async_run")
@@ -286,7 +292,8 @@ def async_run(L: int, ex, ey, seed: int, rho: float = 1.0, t_target: int = -1, S
 
 
 def async_decode_seeds(L: int, p, seeds, rho: float = 1.0, S_max: int = 100000, v: int = 3,
-                       threads: int = 0, want_sigma: bool = True, uncoordinated: bool = False):
+                       threads: int = 0, want_sigma: bool = True, uncoordinated: bool = False,
+                       schedule: str = "cyclic"):
     """Noise + desynchronized decode per seed (R12, R23-R27; R28 with
     uncoordinated=True)."""
     s = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
@@ -298,7 +305,10 @@ def async_decode_seeds(L: int, p, seeds, rho: float = 1.0, S_max: int = 100000, 
     upd = np.zeros(n, np.int64)
     words = np.zeros((n, (L * L + 31) // 32), np.uint32) if want_sigma else None
     used = ctypes.c_int(0)
-    fn = _load().orc_uncoord_decode_seeds if uncoordinated else _load().orc_async_decode_seeds
+    if uncoordinated:
+        fn = lambda L, v, *rest: _load().orc_uncoord_decode_seeds(L, v, SCHEDULES[schedule], *rest)  # noqa: E731
+    else:
+        fn = _load().orc_async_decode_seeds
     _check(fn(L, v, _ptr(pa), 1 if pa.size > 1 else 0, _ptr(s), n,
                                           ring_threshold(rho), int(S_max), int(threads), _ptr(T), _ptr(flags),
                                           _ptr(slots), _ptr(upd), _ptr(words), ctypes.byref(used)),

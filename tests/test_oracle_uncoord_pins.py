@@ -5,7 +5,9 @@ something other than the synchronous decoder, so it is pinned by what holds
 for any update order: every ring is applied, message registers settle on the
 static lightfront distance of fixed anyons (the fixed point of the min-plus
 rule), hand-derived pair decodes, the invariants of anyon motion, and a
-threshold between low and high noise.
+threshold between low and high noise.  Both schedules of R28 are covered:
+"cyclic" (every (v+1)-th update of a site is a motion) and "random" (each
+update is a motion with probability 1/(v+1), drawn from Philox).
 """
 import numpy as np
 import pytest
@@ -87,15 +89,16 @@ def test_close_pairs_annihilate_at_the_first_motion(orc, d, axis):
         assert np.array_equal(r["cx"], ex) and np.array_equal(r["cy"], ey)
 
 
+@pytest.mark.parametrize("schedule", ["cyclic", "random"])
 @pytest.mark.parametrize("L,p,rho", [(8, 0.06, 0.25), (10, 0.08, 1.0), (12, 0.05, 0.5)])
-def test_motion_invariants(orc, L, p, rho):
+def test_motion_invariants(orc, L, p, rho, schedule):
     """sigma stays the boundary of E + C, anyons stay paired and never
     multiply, and a finished decode leaves no anyon."""
     for s in seeds(150, 10 * L, 4):
         ex, ey = orc.noise(L, p, int(s))
         prev = None
         for S in range(0, 120, 4):
-            r = orc.async_run(L, ex, ey, seed=int(s), rho=rho, S_max=S, uncoordinated=True)
+            r = orc.async_run(L, ex, ey, seed=int(s), rho=rho, S_max=S, uncoordinated=True, schedule=schedule)
             sig = np.zeros(L * L, np.uint8)
             words = r["sigma_words"]
             for i in range(L * L):
@@ -106,19 +109,20 @@ def test_motion_invariants(orc, L, p, rho):
             if prev is not None:
                 assert anyon.sum() <= prev
             prev = anyon.sum()
-        r = orc.async_run(L, ex, ey, seed=int(s), rho=rho, S_max=30000, uncoordinated=True)
+        r = orc.async_run(L, ex, ey, seed=int(s), rho=rho, S_max=30000, uncoordinated=True, schedule=schedule)
         if not r["flags"] & 2:
             assert not r["sigma_words"].any()
 
 
-def test_uncoordinated_threshold(orc):
+@pytest.mark.parametrize("schedule", ["cyclic", "random"])
+def test_uncoordinated_threshold(orc, schedule):
     """The section reports a threshold for the uncoordinated decoder: larger
     lattices fail less at low noise and more at high noise."""
     res = {}
     for p in (0.03, 0.12):
         for L in (10, 20):
             r = orc.async_decode_seeds(L, p, seeds(151, 10 * L + int(100 * p), 1500), rho=0.25, S_max=30000,
-                                       threads=8, want_sigma=False, uncoordinated=True)
+                                       threads=8, want_sigma=False, uncoordinated=True, schedule=schedule)
             res[(p, L)] = float((r["flags"] & 1).mean())
     assert res[(0.03, 20)] < res[(0.03, 10)]
     assert res[(0.12, 20)] > res[(0.12, 10)]
@@ -134,3 +138,49 @@ def test_uncoordinated_batch_matches_single_runs(orc):
         assert (b["T_async"][k], b["flags"][k], b["slots"][k], b["updates"][k]) == \
             (r["T_async"], r["flags"], r["slots"], r["updates"])
         assert np.array_equal(b["sigma_words"][k], r["sigma_words"])
+
+
+def test_random_schedule_draws_the_update_type(orc):
+    """Schedule "random" (R28): an update of site i in slot s is a motion iff
+    word (i & 1) of Philox(key = seed, counter (i >> 1, s, 0x54595045, 0)) mod 4
+    is 3.  For a lone pair at distance 1 with certain ringing, an endpoint's
+    registers see its partner after its first message update, so the pair
+    annihilates in the first slot in which an endpoint draws a motion after
+    having drawn a message: T follows from the draws alone."""
+    L = 12
+    ex = np.zeros((L, L), np.uint8)
+    ey = np.zeros((L, L), np.uint8)
+    ex[5, 4] = 1
+    ends = [5 * L + 4, 5 * L + 5]
+    for seed in range(40):
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        seen = {i: False for i in ends}
+        want = None
+        for slot in range(200):
+            for i in ends:
+                w = orc.philox4x32_10([i >> 1, slot, 0x54595045, 0], key)
+                motion = int(w[i & 1]) % 4 == 3
+                if motion and seen[i]:
+                    want = slot + 1
+                if not motion:
+                    seen[i] = True
+            if want:
+                break
+        r = orc.async_run(L, ex, ey, seed=seed, rho=1.0, uncoordinated=True, schedule="random")
+        assert (r["T_async"], r["flags"]) == (want, 0), seed
+        assert np.array_equal(r["cx"], ex)
+
+
+def test_random_schedule_applies_every_ring(orc):
+    L = 9
+    ex, ey = orc.noise(L, 0.05, 8)
+    seed, rho, S = 77, 0.4, 7
+    r = orc.async_run(L, ex, ey, seed=seed, rho=rho, S_max=S, t_target=1000, uncoordinated=True, schedule="random")
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    thr = orc.ring_threshold(rho)
+    want = np.zeros(L * L, np.int64)
+    for s_ in range(S):
+        for i in range(L * L):
+            w = orc.philox4x32_10([i >> 1, s_, 0x41535943, 0], key)
+            want[i] += int(w[2 * (i & 1)]) < thr
+    assert np.array_equal(r["tsim"].reshape(-1), want)
