@@ -244,25 +244,34 @@ int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
 /* Uncoordinated desynchronization (Sec. "Uncoordinated desynchronization")
- * of the plain rule on the torus, 5 <= L <= 64: the same clock and update
- * schedule as the marching-soldiers decoder (v = 3 message updates, then one
- * motion update, per site and cyclically) without the lag rule and without
- * old copies.  A message update reads the current registers and syndromes on
- * its lines; a motion update of an anyon site moves that anyon one link
- * along its force (+a for f^a = -1, -a for f^a = +1), annihilating it with
- * an anyon there.  This is a different dynamics from the synchronous
- * decoder's: outcomes and decoding times differ.
+ * of the plain rule on the torus, 5 <= L <= 64: the marching-soldiers clock
+ * without the lag rule and without old copies.  Every ring applies one update
+ * to the site: a message update reads the current registers and syndromes on
+ * its lines; a motion update of an anyon site moves that anyon one link along
+ * its force (+a for f^a = -1, -a for f^a = +1), annihilating it with an anyon
+ * there.  Which updates are motions is set by `schedule`:
+ *   MPD_UNCOORD_CYCLIC  every fourth update of a site (v = 3 message updates,
+ *                       then one motion, as in the synchronous step);
+ *   MPD_UNCOORD_RANDOM  each update independently with probability 1/4:
+ *                       word (i & 1) of Philox4x32-10(key = seed, counter
+ *                       (i >> 1, slot, 0x54595045, 0)) mod 4 == 3 (messages and
+ *                       motion then run on independent Poisson clocks of
+ *                       rates 3 and 1 as rho -> 0).
+ * This is a different dynamics from the synchronous decoder's: outcomes and
+ * decoding times differ.
  *
  * mpd_decode_uncoord: as mpd_decode_async; a decode ends at the first slot
  * boundary with no anyon; d_T_un = 1 + the last slot with a move.
  * mpd_run_uncoord: as mpd_run_async (every site runs 4 t_target updates);
  * t_sim counts all updates.  Arguments, layouts and errors as the
- * marching-soldiers calls. */
-int mpd_decode_uncoord(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_un,
-                       uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
-                       void *stream);
+ * marching-soldiers calls; MPD_ERR_N for an unknown schedule. */
+#define MPD_UNCOORD_CYCLIC 0
+#define MPD_UNCOORD_RANDOM 1
+int mpd_decode_uncoord(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int schedule,
+                       int32_t *d_T_un, uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates,
+                       uint32_t *d_final_syndrome, void *stream);
 int mpd_run_uncoord(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
-                    double rho, int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
+                    double rho, int S_max, int schedule, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
                     uint16_t *d_tsim_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
 /* Temporal blocking of the band path (L >= 256): decoder steps run on chip per

@@ -100,9 +100,9 @@ def lib():
     L.mpd_decode_async.restype = I
     L.mpd_run_async.argtypes = [I, P, P, I64, I, D, I, P, P, P, P, P, P, P]
     L.mpd_run_async.restype = I
-    L.mpd_decode_uncoord.argtypes = L.mpd_decode_async.argtypes
+    L.mpd_decode_uncoord.argtypes = [I, D, P, I64, D, I, I, P, P, P, P, P, P]
     L.mpd_decode_uncoord.restype = I
-    L.mpd_run_uncoord.argtypes = L.mpd_run_async.argtypes
+    L.mpd_run_uncoord.argtypes = [I, P, P, I64, I, D, I, I, P, P, P, P, P, P, P]
     L.mpd_run_uncoord.restype = I
     _lib = L
     return L
@@ -221,16 +221,18 @@ def run_steps(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int =
 
 
 ASYNC_SLOT_LIMIT = 65000
+UNCOORD_SCHEDULES = {"cyclic": 0, "random": 1}
 
 
 def decode_async(L: int, p: float, seeds, rho: float, S_max: int = ASYNC_SLOT_LIMIT, want_syndrome: bool = True,
-                 out=None, stream=None, uncoordinated: bool = False):
+                 out=None, stream=None, uncoordinated: bool = False, schedule: str = "cyclic"):
     """Marching-soldiers desynchronized decode of seeded noise (5 <= L <= 64):
     the seed keys the noise and the clock, rho is the ring probability per
     slot.  Returns (T_async int32[n], flags uint8[n], slots int32[n],
     updates int64[n], syndrome int32[n, W] or None) on the device; `out` may
     pass all five preallocated.  uncoordinated=True runs the uncoordinated
-    desynchronization (mpd_decode_uncoord) instead."""
+    desynchronization (mpd_decode_uncoord) instead, with its "cyclic" or
+    "random" schedule."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()
@@ -242,16 +244,19 @@ def decode_async(L: int, p: float, seeds, rho: float, S_max: int = ASYNC_SLOT_LI
         S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
     else:
         T, F, SL, U, S = out
-    fn, name = (lib().mpd_decode_uncoord, "mpd_decode_uncoord") if uncoordinated else \
-        (lib().mpd_decode_async, "mpd_decode_async")
-    rc = fn(L, float(p), _ptr(s), n, float(rho), int(S_max), _ptr(T), _ptr(F), _ptr(SL), _ptr(U), _ptr(S),
-            _stream_ptr(stream))
-    _check(rc, name)
+    if uncoordinated:
+        rc = lib().mpd_decode_uncoord(L, float(p), _ptr(s), n, float(rho), int(S_max), UNCOORD_SCHEDULES[schedule],
+                                      _ptr(T), _ptr(F), _ptr(SL), _ptr(U), _ptr(S), _stream_ptr(stream))
+        _check(rc, "mpd_decode_uncoord")
+    else:
+        rc = lib().mpd_decode_async(L, float(p), _ptr(s), n, float(rho), int(S_max), _ptr(T), _ptr(F), _ptr(SL),
+                                    _ptr(U), _ptr(S), _stream_ptr(stream))
+        _check(rc, "mpd_decode_async")
     return T, F, SL, U, S
 
 
 def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int = ASYNC_SLOT_LIMIT, stream=None,
-              uncoordinated: bool = False):
+              uncoordinated: bool = False, schedule: str = "cyclic"):
     """Desynchronized run of explicit error patterns until every site has
     completed t_target decoder steps (or S_max slots).  Returns (slots
     int32[n], updates int64[n], m int16[n,4,L,L], tsim int16[n,L,L] holding
@@ -269,10 +274,15 @@ def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int 
     TS = torch.empty((n, L, L), dtype=torch.int16, device=dev)
     S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
     W = torch.empty(n, dtype=torch.uint8, device=dev)
-    fn, name = (lib().mpd_run_uncoord, "mpd_run_uncoord") if uncoordinated else (lib().mpd_run_async, "mpd_run_async")
-    rc = fn(L, _ptr(links), _ptr(cs), n, int(t_target), float(rho), int(S_max), _ptr(SL), _ptr(U), _ptr(M), _ptr(TS),
-            _ptr(S), _ptr(W), _stream_ptr(stream))
-    _check(rc, name)
+    if uncoordinated:
+        rc = lib().mpd_run_uncoord(L, _ptr(links), _ptr(cs), n, int(t_target), float(rho), int(S_max),
+                                   UNCOORD_SCHEDULES[schedule], _ptr(SL), _ptr(U), _ptr(M), _ptr(TS), _ptr(S), _ptr(W),
+                                   _stream_ptr(stream))
+        _check(rc, "mpd_run_uncoord")
+    else:
+        rc = lib().mpd_run_async(L, _ptr(links), _ptr(cs), n, int(t_target), float(rho), int(S_max), _ptr(SL),
+                                 _ptr(U), _ptr(M), _ptr(TS), _ptr(S), _ptr(W), _stream_ptr(stream))
+        _check(rc, "mpd_run_async")
     return SL, U, M, TS, S, W
 
 

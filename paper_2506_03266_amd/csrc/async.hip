@@ -56,6 +56,7 @@
 namespace mpd {
 
 constexpr uint32_t CLOCK_TAG = 0x41535943u;
+constexpr uint32_t TYPE_TAG = 0x54595045u;   // update type of the uncoordinated "random" schedule
 
 struct AsyncArgs {
   int L;
@@ -65,6 +66,7 @@ struct AsyncArgs {
   uint64_t ring_thr;       // ring probability per slot times 2^32, in [1, 2^32]
   int t_target;            // >= 0: run until every site has made 4 t_target updates
   int S_max;               // slot budget
+  int sched;               // uncoordinated schedule: 0 cyclic, 1 random update types
   int32_t *T_async;
   uint8_t *flags;
   int32_t *slots;
@@ -208,13 +210,24 @@ __device__ __forceinline__ int async_attempt(const AsyncLds &s, int L, int i, in
 // and no old copies.  Message updates read the current registers and anyon
 // bits on their lines; a motion update of an anyon site moves its anyon one
 // link along its force (+a for f^a = -1, -a for f^a = +1), annihilating it
-// with an anyon there.  Returns 1, or 2 if a link flipped.
-__device__ __forceinline__ int uncoord_update(const AsyncLds &s, int L, int i, int x, int y) {
+// with an anyon there.  Schedule 0: every fourth update of a site is a
+// motion; schedule 1: an update is a motion iff word (i & 1) of
+// Philox(key, counter (i >> 1, slot, TYPE_TAG, 0)) mod 4 is 3.  Returns 1, or
+// 2 if a link flipped.
+__device__ __forceinline__ int uncoord_update(const AsyncLds &s, int L, int i, int x, int y, int sched,
+                                              uint32_t slot, uint32_t k0, uint32_t k1) {
   const uint32_t j = s.TS[i];
+  bool motion;
+  if (sched == 0) {
+    motion = (j & 3u) == 3u;
+  } else {
+    const Words4 w = philox4x32_10((uint32_t)i >> 1, k0, k1, slot, TYPE_TAG);
+    motion = (((i & 1) ? w.w1 : w.w0) & 3u) == 3u;
+  }
   const int xl = wrapc(x - 1, L), xr = wrapc(x + 1, L);
   const int rd = wrapc(y - 1, L) * L, rc = y * L, ru = wrapc(y + 1, L) * L;
   int ret = 1;
-  if ((j & 3u) < 3u) {
+  if (!motion) {
     auto an = [&](int q) { return (s.FL[q] & 1u) != 0u; };
     const int dl = rd + xl, dc = rd + x, dr = rd + xr;
     const int cl = rc + xl, cr = rc + xr;
@@ -416,7 +429,8 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
       if (tid == 0) RED[3 + ((round + 1) & 1)] = 0;
       for (int e = tid; e < nready; e += T) {
         const int i = s.RL[e];
-        const int r = UNC ? uncoord_update(s, L, i, i % L, i / L) : async_attempt(s, L, i, i % L, i / L);
+        const int r = UNC ? uncoord_update(s, L, i, i % L, i / L, a.sched, (uint32_t)slot, k0, k1)
+                          : async_attempt(s, L, i, i % L, i / L);
         my_updates += r > 0;
         if (r == 2) last_flip = slot;
       }
@@ -499,8 +513,8 @@ static int async_check(int L, int64_t n, double rho, int S_max, uint64_t *ring_t
   return MPD_OK;
 }
 
-static int decode_desync(bool unc, int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max,
-                         int32_t *d_T, uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates,
+static int decode_desync(bool unc, int sched, int L, double p, const uint64_t *d_seeds, int64_t n, double rho,
+                         int S_max, int32_t *d_T, uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates,
                          uint32_t *d_final_syndrome, void *stream) {
   uint64_t ring_thr = 0;
   int rc = async_check(L, n, rho, S_max, &ring_thr);
@@ -520,6 +534,7 @@ static int decode_desync(bool unc, int L, double p, const uint64_t *d_seeds, int
   a.ring_thr = ring_thr;
   a.t_target = -1;
   a.S_max = S_max;
+  a.sched = sched;
   a.T_async = d_T;
   a.flags = d_flags;
   a.slots = d_slots;
@@ -528,7 +543,7 @@ static int decode_desync(bool unc, int L, double p, const uint64_t *d_seeds, int
   return launch_async(a, n, unc, (hipStream_t)stream);
 }
 
-static int run_desync(bool unc, int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
+static int run_desync(bool unc, int sched, int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
                       double rho, int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
                       uint16_t *d_tsim_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
   uint64_t ring_thr = 0;
@@ -552,6 +567,7 @@ static int run_desync(bool unc, int L, const uint32_t *d_links, const uint64_t *
   a.ring_thr = ring_thr;
   a.t_target = t_target;
   a.S_max = S_max;
+  a.sched = sched;
   a.slots = d_slots;
   a.updates = d_updates;
   a.syn = d_sigma_out;
@@ -567,7 +583,7 @@ int mpd_decode_async(int L, double p, const uint64_t *d_seeds, int64_t n, double
                      uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
                      void *stream) {
   g_last_error.clear();
-  return decode_desync(false, L, p, d_seeds, n, rho, S_max, d_T_async, d_flags, d_slots, d_updates, d_final_syndrome,
+  return decode_desync(false, 0, L, p, d_seeds, n, rho, S_max, d_T_async, d_flags, d_slots, d_updates, d_final_syndrome,
                        stream);
 }
 
@@ -575,23 +591,27 @@ int mpd_run_async(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds,
                   int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out, uint16_t *d_tsim_out,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
   g_last_error.clear();
-  return run_desync(false, L, d_links, d_clock_seeds, n, t_target, rho, S_max, d_slots, d_updates, d_m_out,
+  return run_desync(false, 0, L, d_links, d_clock_seeds, n, t_target, rho, S_max, d_slots, d_updates, d_m_out,
                     d_tsim_out, d_sigma_out, d_wind_out, stream);
 }
 
-int mpd_decode_uncoord(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int32_t *d_T_un,
-                       uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates, uint32_t *d_final_syndrome,
-                       void *stream) {
+int mpd_decode_uncoord(int L, double p, const uint64_t *d_seeds, int64_t n, double rho, int S_max, int schedule,
+                       int32_t *d_T_un, uint8_t *d_flags, int32_t *d_slots, int64_t *d_updates,
+                       uint32_t *d_final_syndrome, void *stream) {
   g_last_error.clear();
-  return decode_desync(true, L, p, d_seeds, n, rho, S_max, d_T_un, d_flags, d_slots, d_updates, d_final_syndrome,
+  if (schedule != MPD_UNCOORD_CYCLIC && schedule != MPD_UNCOORD_RANDOM)
+    return fail_with(MPD_ERR_N, "unknown schedule %d", schedule);
+  return decode_desync(true, schedule, L, p, d_seeds, n, rho, S_max, d_T_un, d_flags, d_slots, d_updates, d_final_syndrome,
                        stream);
 }
 
 int mpd_run_uncoord(int L, const uint32_t *d_links, const uint64_t *d_clock_seeds, int64_t n, int t_target,
-                    double rho, int S_max, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
+                    double rho, int S_max, int schedule, int32_t *d_slots, int64_t *d_updates, int16_t *d_m_out,
                     uint16_t *d_tsim_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
   g_last_error.clear();
-  return run_desync(true, L, d_links, d_clock_seeds, n, t_target, rho, S_max, d_slots, d_updates, d_m_out,
+  if (schedule != MPD_UNCOORD_CYCLIC && schedule != MPD_UNCOORD_RANDOM)
+    return fail_with(MPD_ERR_N, "unknown schedule %d", schedule);
+  return run_desync(true, schedule, L, d_links, d_clock_seeds, n, t_target, rho, S_max, d_slots, d_updates, d_m_out,
                     d_tsim_out, d_sigma_out, d_wind_out, stream);
 }
 

@@ -12,7 +12,10 @@ Three measurements, all on i.i.d. bit-flip noise, periodic L x L lattices, v = 3
   (Sec. 5.3: messages truncated at m_max, with and without a random move of
   every anyon every u steps) against m_max at several L;
 * with ``--open``: p_log against p on the open lattice (rough left and right
-  boundaries, appendix on open boundaries) and its crossings.
+  boundaries, appendix on open boundaries) and its crossings;
+* with ``--uncoord``: p_log against p of the uncoordinated desynchronization
+  (Sec. "Uncoordinated desynchronization") beside the synchronous decoder on
+  the same seeds, and the crossings of both.
 
 Every sample is decoded by libmpd (noise, decoding and classification run in
 the HIP kernels); this module chooses seeds, sums the per-sample results on
@@ -48,6 +51,10 @@ MEMORY_L = [(32, 20000), (64, 10000), (128, 4000)]
 MEMORY_T_MAX = 2048
 OPEN_P = [0.06, 0.07, 0.075, 0.08, 0.085, 0.09, 0.1]
 OPEN_L = [(16, 100000), (32, 50000), (64, 20000), (128, 5000), (256, 3000), (512, 1500)]
+UNCOORD_P = [0.05, 0.06, 0.065, 0.07, 0.075, 0.08, 0.09]
+UNCOORD_L = [(16, 40000), (32, 20000), (64, 8000)]
+UNCOORD_RHO = 0.125     # ring probability per slot: close to independent Poisson clocks
+UNCOORD_S_MAX = 20000   # slots
 
 
 def seed_block(L: int, p_index: int, n: int, start: int = 0) -> np.ndarray:
@@ -64,12 +71,15 @@ def _chunk(L: int) -> int:
 
 
 def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int = 0, u: int = 0,
-          open_bc: bool = False) -> dict:
+          open_bc: bool = False, uncoord: str = "") -> dict:
     """Decode n seeded samples at (L, p) (with the limited-memory variant if
-    m_max or u is set); returns the counts and sums of the point.
+    m_max or u is set, on the open lattice with open_bc, with the uncoordinated
+    desynchronization under schedule `uncoord` ("cyclic" or "random") if it
+    is set); returns the counts and sums of the point.
 
     fails counts flag bit 0 (timeouts included), timeouts flag bit 1; T_sum
-    and T_sq sum T_dec over the samples that finished.
+    and T_sq sum T_dec over the samples that finished (for the uncoordinated
+    decoder: the decoding time in slots, T_max being ignored for it).
     """
     import torch
     from . import binding as b
@@ -84,7 +94,10 @@ def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int 
     for a in range(0, n, c):
         m = min(c, n - a)
         s = torch.from_numpy(seed_block(L, p_index, m, a).view(np.int64)).to(dev)
-        if open_bc:
+        if uncoord:
+            Tm, Fm, _, _, _ = b.decode_async(L, p, s, UNCOORD_RHO, UNCOORD_S_MAX, want_syndrome=False,
+                                             uncoordinated=True, schedule=uncoord)
+        elif open_bc:
             Tm, Fm, _ = b.decode_open(L, p, s, T_max, want_syndrome=False)
         elif m_max or u:
             Tm, Fm, _ = b.decode_rule(L, p, s, T_max, m_max=m_max, u=u, want_syndrome=False, workspace=ws,
@@ -100,8 +113,8 @@ def point(L: int, p: float, n: int, p_index: int, T_max: int = 4096, m_max: int 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fails, timeouts, T_sum, T_sq, T_all = (int(x) for x in v)
-    return dict(L=L, p=p, n=n, T_max=T_max, m_max=m_max, u=u, open=open_bc, fails=fails, timeouts=timeouts, T_sum=T_sum,
-                T_sq=T_sq, seconds=dt, site_updates=T_all * L * L)
+    return dict(L=L, p=p, n=n, T_max=T_max, m_max=m_max, u=u, open=open_bc, uncoord=uncoord, fails=fails,
+                timeouts=timeouts, T_sum=T_sum, T_sq=T_sq, seconds=dt, site_updates=T_all * L * L)
 
 
 def p_log(r: dict) -> float:
@@ -216,6 +229,34 @@ def run_open(quick: bool = False, T_max: int = 4096, log=print) -> dict:
     return dict(points=pts, crossings=cross)
 
 
+def run_uncoord(quick: bool = False, log=print) -> dict:
+    """p_log against p of the uncoordinated decoder (both schedules) and of the
+    synchronous one on the same seeds, and the crossings of consecutive sizes
+    of each."""
+    scale = 0.05 if quick else 1.0
+    pts = {"cyclic": [], "random": [], "synchronous": []}
+    for L, n in UNCOORD_L:
+        n = max(256, int(n * scale))
+        for i, p in enumerate(UNCOORD_P):
+            rc = point(L, p, n, 224 + i, uncoord="cyclic")
+            rr = point(L, p, n, 224 + i, uncoord="random")
+            rs = point(L, p, n, 224 + i)
+            log(f"uncoord L={L} p={p}: cyclic p_log={p_log(rc):.5f}±{p_log_err(rc):.5f} (timeouts {rc['timeouts']}, "
+                f"time {mean_T(rc)[0] * UNCOORD_RHO:.2f}) | random p_log={p_log(rr):.5f}±{p_log_err(rr):.5f} "
+                f"(timeouts {rr['timeouts']}, time {mean_T(rr)[0] * UNCOORD_RHO:.2f}) | synchronous "
+                f"p_log={p_log(rs):.5f} T={mean_T(rs)[0]:.2f} n={n}")
+            pts["cyclic"].append(rc)
+            pts["random"].append(rr)
+            pts["synchronous"].append(rs)
+    Ls = [L for L, _ in UNCOORD_L]
+    cross = {}
+    for key, rows in pts.items():
+        tab = {(r["L"], r["p"]): p_log(r) for r in rows}
+        cross[key] = {f"{L1}/{L2}": crossing(UNCOORD_P, [tab[(L1, p)] for p in UNCOORD_P],
+                                             [tab[(L2, p)] for p in UNCOORD_P]) for L1, L2 in zip(Ls, Ls[1:])}
+    return dict(points=pts, crossings=cross, rho=UNCOORD_RHO, S_max=UNCOORD_S_MAX)
+
+
 def summarize(res: dict) -> dict:
     """Crossings of consecutive sizes (all samples, and decoded samples only),
     slopes gamma against the crossing of the two largest sizes, and
@@ -264,10 +305,18 @@ def main(argv=None):
     ap.add_argument("--json", default=None, help="write all counts and fits here")
     ap.add_argument("--memory", action="store_true", help="only the limited-memory grid")
     ap.add_argument("--open", action="store_true", help="only the open-lattice threshold grid")
+    ap.add_argument("--uncoord", action="store_true", help="only the uncoordinated-desynchronization threshold grid")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         sys.exit("sweep: needs a GPU (the decoder runs only in libmpd's HIP kernels)")
+    if a.uncoord:
+        res = run_uncoord(a.quick, log=lambda s: print(s, flush=True))
+        print(json.dumps(res["crossings"]), flush=True)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     if a.open:
         res = run_open(a.quick, a.T_max, log=lambda s: print(s, flush=True))
         print(json.dumps(res["crossings"]), flush=True)

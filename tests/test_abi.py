@@ -233,12 +233,13 @@ def test_async_arguments_rejected(lib):
 
 
 def test_uncoord_arguments_rejected(lib):
-    """The uncoordinated entry points share the desynchronized checks."""
+    """The uncoordinated entry points share the desynchronized checks and
+    reject an unknown schedule."""
     dummy = ctypes.c_void_p(256)
-    assert lib.mpd_decode_uncoord(4, 0.1, dummy, 4, 0.5, 100, dummy, dummy, None, None, None, None) == -1
-    assert lib.mpd_decode_uncoord(16, 0.1, dummy, 4, 0.0, 100, dummy, dummy, None, None, None, None) == -2
-    assert lib.mpd_decode_uncoord(16, 0.1, dummy, 4, 0.5, -1, dummy, dummy, None, None, None, None) == -3
-    assert lib.mpd_decode_uncoord(16, 0.1, None, 4, 0.5, 100, dummy, dummy, None, None, None, None) == -4
-    assert lib.mpd_decode_uncoord(16, 0.1, dummy, 0, 0.5, 100, dummy, dummy, None, None, None, None) == 0
-    assert lib.mpd_run_uncoord(16, dummy, dummy, 4, -1, 0.5, 100, dummy, None, dummy, dummy, dummy, dummy, None) == -3
-    assert lib.mpd_run_uncoord(16, dummy, None, 4, 2, 0.5, 100, dummy, None, dummy, dummy, dummy, dummy, None) == -4
+    d = lambda L=16, rho=0.5, S=100, sch=0, sd=dummy, n=4: lib.mpd_decode_uncoord(  # noqa: E731
+        L, 0.1, sd, n, rho, S, sch, dummy, dummy, None, None, None, None)
+    assert d(L=4) == -1 and d(rho=0.0) == -2 and d(S=-1) == -3 and d(sd=None) == -4 and d(sch=2) == -7
+    assert d(n=0) == 0 and d(n=0, sch=1) == 0
+    r = lambda t=2, cs=dummy, sch=0: lib.mpd_run_uncoord(  # noqa: E731
+        16, dummy, cs, 4, t, 0.5, 100, sch, dummy, None, dummy, dummy, dummy, dummy, None)
+    assert r(t=-1) == -3 and r(cs=None) == -4 and r(sch=-1) == -7

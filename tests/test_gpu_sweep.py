@@ -76,3 +76,18 @@ def test_open_point_matches_oracle(gpu, orc, L, p, n):
     done = (F & 2) == 0
     assert (r["fails"], r["timeouts"]) == (int((F & 1).sum()), int((~done).sum()))
     assert (r["T_sum"], r["T_sq"]) == (int(T[done].sum()), int((T[done] ** 2).sum()))
+
+
+@pytest.mark.parametrize("schedule", ["cyclic", "random"])
+@pytest.mark.parametrize("L,p,n", [(16, 0.07, 1500), (32, 0.08, 200)])
+def test_uncoord_point_matches_oracle(gpu, orc, L, p, n, schedule):
+    """A point of the uncoordinated grid: the same counts as the oracle
+    (decoding times in slots)."""
+    r = sweep.point(L, p, n, p_index=204, uncoord=schedule)
+    ref = orc.async_decode_seeds(L, p, sweep.seed_block(L, 204, n), rho=sweep.UNCOORD_RHO, S_max=sweep.UNCOORD_S_MAX,
+                                 threads=16, want_sigma=False, uncoordinated=True, schedule=schedule)
+    T = ref["T_async"].astype(np.int64)
+    F = ref["flags"].astype(np.int64)
+    done = (F & 2) == 0
+    assert (r["fails"], r["timeouts"]) == (int((F & 1).sum()), int((~done).sum()))
+    assert (r["T_sum"], r["T_sq"]) == (int(T[done].sum()), int((T[done] ** 2).sum()))
