@@ -514,29 +514,35 @@ def desynchronized(args, b, seeds, torch, np):
                 "timeouts": int(((F & 2) > 0).sum()),
                 "outcomes_equal_sync": bool(np.array_equal(F[both], Fs[both])),
                 "sync_samples_per_s": K * n / dts}
-        # the uncoordinated desynchronization on the same batches
-        for i in range(W):
-            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st, uncoordinated=True)
-        torch.cuda.synchronize()
-        b.profile(True)
-        t0 = time.perf_counter()
-        for i in range(W, W + K):
-            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st, uncoordinated=True)
-        torch.cuda.synchronize()
-        dtu = time.perf_counter() - t0
-        b.profile(False)
-        kmu, lu = b.profile_read("k_async_unc")
-        Tu, Fu, SLu, Uu = cat(0), cat(1), cat(2).astype(np.int64), cat(3).astype(np.int64)
-        line["uncoordinated"] = {"samples_per_s": K * n / dtu, "ms_per_batch": dtu / K * 1e3,
-                                 "kernel": {"name": "k_async_unc", "avg_launch_ms": kmu / max(lu, 1), "launches": lu},
-                                 "updates_per_s": float(Uu.sum()) / dtu, "slots_mean": float(SLu.mean()),
-                                 "decoding_time_mean": float(Tu.mean()) * rho, "fail_rate": float((Fu & 1).mean()),
-                                 "timeouts": int(((Fu & 2) > 0).sum())}
+        # the uncoordinated desynchronization on the same batches, both schedules
+        for sched in ("cyclic", "random"):
+            for i in range(W):
+                b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st, uncoordinated=True,
+                               schedule=sched)
+            torch.cuda.synchronize()
+            b.profile(True)
+            t0 = time.perf_counter()
+            for i in range(W, W + K):
+                b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=st, uncoordinated=True,
+                               schedule=sched)
+            torch.cuda.synchronize()
+            dtu = time.perf_counter() - t0
+            b.profile(False)
+            kmu, lu = b.profile_read("k_async_unc")
+            Tu, Fu, SLu, Uu = cat(0), cat(1), cat(2).astype(np.int64), cat(3).astype(np.int64)
+            key = "uncoordinated" if sched == "cyclic" else "uncoordinated_random"
+            line[key] = {"samples_per_s": K * n / dtu, "ms_per_batch": dtu / K * 1e3,
+                         "kernel": {"name": "k_async_unc", "avg_launch_ms": kmu / max(lu, 1), "launches": lu},
+                         "updates_per_s": float(Uu.sum()) / dtu, "slots_mean": float(SLu.mean()),
+                         "decoding_time_mean": float(Tu.mean()) * rho, "fail_rate": float((Fu & 1).mean()),
+                         "timeouts": int(((Fu & 2) > 0).sum())}
+            if sched == "cyclic":
+                Tc, Fc = Tu, Fu
         if not args.no_cpu_baseline:
             import oracle
             m = 256
             s_cpu = seeds(11, int(p * 1000) + L_a, m, start=W * n)
-            for key, unc, Tg, Fg in (("cpu_baseline", False, T, F), ("uncoordinated_cpu_baseline", True, Tu, Fu)):
+            for unc, Tg, Fg in ((False, T, F), (True, Tc, Fc)):
                 tc = time.perf_counter()
                 r = oracle.async_decode_seeds(L_a, p, s_cpu, rho=rho, S_max=S_max, want_sigma=False, uncoordinated=unc)
                 tcpu = time.perf_counter() - tc
