@@ -188,6 +188,23 @@ int mpd_decode_errors_open(int L, const uint32_t *d_links, int64_t n, int T_max,
 int mpd_run_steps_open(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
                        uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
+/* Resume the decoder from an exported state (checkpoint / resume): the state
+ * mpd_run_steps, mpd_run_steps_rule or this call wrote after t_start steps --
+ * registers d_m_in [n][4][L*L] int16 in distance form, syndrome bits
+ * d_sigma_in and winding bits d_wind_in (layouts as mpd_run_steps) -- is run
+ * for exactly t_exact more steps and exported in the same form.  The result
+ * equals mpd_run_steps(t_start + t_exact) on the original errors; with the
+ * limited-memory variant (m_max, u; move seeds as mpd_run_steps_rule) the
+ * steps keep their absolute numbers t_start + 1, ...  Inputs must be such an
+ * export (registers at most 3 t_start); other values give unspecified
+ * results but no out-of-bounds access.  Inputs and outputs may be the same
+ * buffers (each sample is read completely before it is written).  Torus, L =
+ * 3..128 (the resident kernel); t_start + t_exact <= MPD_T_MAX_LIMIT.
+ * Errors as mpd_run_steps_rule. */
+int mpd_run_steps_from(int L, const int16_t *d_m_in, const uint32_t *d_sigma_in, const uint8_t *d_wind_in, int64_t n,
+                       int t_start, int t_exact, int m_max, int u, const uint64_t *d_move_seeds, int16_t *d_m_out,
+                       uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
 /* Marching-soldiers desynchronization (Sec. "Desynchronization and
  * Lindbladian dynamics": Def. "marching soldiers desynchronization", Def.
  * "desynchronized decoders", Prop. "faithful Lindbladian simulation") of the

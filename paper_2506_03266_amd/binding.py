@@ -96,6 +96,8 @@ def lib():
     L.mpd_learned_workspace_bytes.restype = SZ
     L.mpd_decode_learned.argtypes = [I, D, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
     L.mpd_decode_learned.restype = I
+    L.mpd_run_steps_from.argtypes = [I, P, P, P, I64, I, I, I, I, P, P, P, P, P]
+    L.mpd_run_steps_from.restype = I
     L.mpd_decode_async.argtypes = [I, D, P, I64, D, I, P, P, P, P, P, P]
     L.mpd_decode_async.restype = I
     L.mpd_run_async.argtypes = [I, P, P, I64, I, D, I, P, P, P, P, P, P, P]
@@ -284,6 +286,27 @@ def run_async(L: int, links, clock_seeds, t_target: int, rho: float, S_max: int 
                                  _ptr(U), _ptr(M), _ptr(TS), _ptr(S), _ptr(W), _stream_ptr(stream))
         _check(rc, "mpd_run_async")
     return SL, U, M, TS, S, W
+
+
+def run_steps_from(L: int, M, S, W, t_start: int, t_exact: int, stream=None, m_max: int = 0, u: int = 0,
+                   move_seeds=None, out=None):
+    """Resume exported states (m int16[n,4,L,L], syndrome int32[n,W], wind
+    uint8[n], as run_steps returns them after t_start steps) for t_exact more
+    steps; returns the new (m, syndrome, wind).  `out` may pass the three
+    output tensors (they may be the inputs themselves)."""
+    dev = torch.device("cuda")
+    n = M.shape[0]
+    if out is None:
+        Mo = torch.empty_like(M)
+        So = torch.empty_like(S)
+        Wo = torch.empty_like(W)
+    else:
+        Mo, So, Wo = out
+    ms = None if move_seeds is None else _seeds_tensor(move_seeds, dev)
+    rc = lib().mpd_run_steps_from(L, _ptr(M), _ptr(S), _ptr(W), n, int(t_start), int(t_exact), int(m_max), int(u),
+                                  _ptr(ms), _ptr(Mo), _ptr(So), _ptr(Wo), _stream_ptr(stream))
+    _check(rc, "mpd_run_steps_from")
+    return Mo, So, Wo
 
 
 def decode_open(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True, workspace=None, out=None,

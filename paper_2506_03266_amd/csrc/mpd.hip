@@ -57,6 +57,12 @@ struct ResidentArgs {
   int u;                   // random moves every u steps, 0 = none
   const uint64_t *move_seeds;  // keys of the random moves in explicit-error mode
   int open;                // 1: open lattice (rough left / right columns)
+  // resume from an exported state (torus): registers [n][4][L*L] in distance
+  // form, syndrome bits and winding bits after t_start steps
+  const int16_t *m_in;
+  const uint32_t *syn_in;
+  const uint8_t *wind_in;
+  int t_start;
 };
 
 // Kernel variants of the resident decoder: the plain rule, the
@@ -112,6 +118,36 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
 
   if (tid == 0) red[0] = 0u;
 
+  uint32_t P[H], Q[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    P[h] = 0u;
+    Q[h] = 0u;
+  }
+  uint32_t wind = 0u;  // bit0 Wx(E), bit1 Wy(E), bit2 Wx(C), bit3 Wy(C)
+  uint32_t sig = 0u;
+  const uint32_t t0 = a.syn_in != nullptr ? (uint32_t)a.t_start : 0u;  // steps already run
+  if (a.syn_in != nullptr) {
+    // ---- resume: syndrome bits, registers (distance m -> emission time
+    // 3 t0 - m + 1) and the winding bits of the exported state
+    const int64_t n2 = (int64_t)L * L, nw = (n2 + 31) / 32;
+    const int16_t *mi = a.m_in + sample * 4 * n2;
+    const uint32_t s0 = 3u * t0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int64_t i = (int64_t)(g.y0 + h) * L + g.c;
+      sig |= ((a.syn_in[sample * nw + (i >> 5)] >> (i & 31)) & 1u) << h;
+      uint32_t e[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t m = (uint32_t)(uint16_t)mi[d * n2 + i];
+        e[d] = m != 0u ? ((s0 - m + 1u) & 0xFFFFu) : 0u;
+      }
+      P[h] = e[0] | e[1] << 16;
+      Q[h] = e[2] | e[3] << 16;
+    }
+    if (tid == 0) wind = a.wind_in[sample] & 15u;
+  } else {
   // ---- noise / error pattern -> link bits of the strip
   uint32_t exb = 0u, eyb = 0u;
   if (a.links == nullptr) {
@@ -141,17 +177,10 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
     if (inB) eyb = 0u;
     if (g.j == NS - 1) eyb &= ~(1u << (H - 1));
   }
-  uint32_t wind = 0u;  // bit0 Wx(E), bit1 Wy(E), bit2 Wx(C), bit3 Wy(C)
   if (g.c == (OPEN ? L - 2 : L - 1)) wind ^= parity32(exb);
   if (!OPEN && g.j == NS - 1) wind ^= ((eyb >> (H - 1)) & 1u) << 1;
-  uint32_t sig = syndrome_from_links<H>(exb, eyb, MV, g);
+  sig = syndrome_from_links<H>(exb, eyb, MV, g);
   if (inB) sig = 0u;
-
-  uint32_t P[H], Q[H];
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    P[h] = 0u;
-    Q[h] = 0u;
   }
 
   int alive = __syncthreads_or(sig != 0u);
@@ -159,7 +188,9 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   const int steps = exact ? a.t_exact : a.T_max;
   uint32_t mk0 = 0u, mk1 = 0u;  // key of the random moves
   if (RULE && a.u > 0) {
-    const uint64_t ms = a.links == nullptr ? a.seeds[sample] : a.move_seeds[sample];
+    // seeded decodes move with their noise seed; explicit errors and resumed
+    // states with their move seeds
+    const uint64_t ms = (a.links == nullptr && a.syn_in == nullptr) ? a.seeds[sample] : a.move_seeds[sample];
     mk0 = (uint32_t)ms;
     mk1 = (uint32_t)(ms >> 32);
   }
@@ -167,11 +198,11 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
   while (t < steps && (exact || alive)) {
 #pragma unroll 1
     for (int sub = 1; sub <= 3; ++sub) {
-      const uint32_t s = (uint32_t)(3 * t + sub);
+      const uint32_t s = 3u * (t0 + (uint32_t)t) + (uint32_t)sub;
       substep<H, OPEN>(P, Q, sig, s | (s << 16), F, g, inB);
     }
     uint32_t xo, yo;
-    const uint32_t t1 = (uint32_t)(t + 1);
+    const uint32_t t1 = t0 + (uint32_t)(t + 1);
     if (RULE) {
       const bool rnd = a.u > 0 && t1 % (uint32_t)a.u == 0u;
       sig = feedback<H, true>(P, Q, sig, MV, g, xo, yo, live_threshold(3u * t1, a.m_max), rnd, t1, mk0, mk1, L);
@@ -208,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_resident(ResidentArgs a) {
 
   if (exact) {
     if (a.m_out != nullptr) {
-      const uint32_t snow = 3u * (uint32_t)a.t_exact;
+      const uint32_t snow = 3u * (t0 + (uint32_t)a.t_exact);
       const uint32_t live = RULE ? live_threshold(snow, a.m_max) : 1u;
       const int64_t n2 = (int64_t)L * L;
       int16_t *mo = a.m_out + sample * 4 * n2;
@@ -1833,6 +1864,44 @@ static int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move
   a.move_seeds = d_move_seeds;
   a.open = open;
   if (open && !open_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported on the open lattice (3..128)", L);
+  return launch_resident(a, (hipStream_t)stream);
+}
+
+int mpd_run_steps_from(int L, const int16_t *d_m_in, const uint32_t *d_sigma_in, const uint8_t *d_wind_in, int64_t n,
+                       int t_start, int t_exact, int m_max, int u, const uint64_t *d_move_seeds, int16_t *d_m_out,
+                       uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream) {
+  g_last_error.clear();
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
+  if (t_start < 0 || t_exact < 0 || (int64_t)t_start + t_exact > MPD_T_MAX_LIMIT)
+    return fail_with(MPD_ERR_TMAX, "t_start=%d, t_exact=%d: both >= 0 with a sum <= %d", t_start, t_exact,
+                     MPD_T_MAX_LIMIT);
+  const int rc = check_rule(m_max, u);
+  if (rc) return rc;
+  if (!resident_ok(L)) return fail_with(MPD_ERR_L, "L=%d unsupported for run_steps_from (3..128)", L);
+  if (n == 0) return MPD_OK;
+  if (d_m_in == nullptr || d_sigma_in == nullptr || d_wind_in == nullptr || ((uintptr_t)d_m_in & 1u) ||
+      ((uintptr_t)d_sigma_in & 3u))
+    return fail_with(MPD_ERR_PTR, "state inputs NULL or misaligned");
+  if (d_m_out == nullptr || d_sigma_out == nullptr || d_wind_out == nullptr || ((uintptr_t)d_m_out & 1u) ||
+      ((uintptr_t)d_sigma_out & 3u))
+    return fail_with(MPD_ERR_PTR, "state outputs NULL or misaligned");
+  if (u > 0 && (d_move_seeds == nullptr || ((uintptr_t)d_move_seeds & 7u)))
+    return fail_with(MPD_ERR_PTR, "random moves need aligned move seeds");
+  ResidentArgs a = {};
+  a.L = L;
+  a.n = n;
+  a.T_max = t_exact;
+  a.t_exact = t_exact;
+  a.syn = d_sigma_out;
+  a.m_out = d_m_out;
+  a.wind_out = d_wind_out;
+  a.m_max = m_max;
+  a.u = u;
+  a.move_seeds = d_move_seeds;
+  a.m_in = d_m_in;
+  a.syn_in = d_sigma_in;
+  a.wind_in = d_wind_in;
+  a.t_start = t_start;
   return launch_resident(a, (hipStream_t)stream);
 }
 

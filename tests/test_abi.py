@@ -243,3 +243,17 @@ def test_uncoord_arguments_rejected(lib):
     r = lambda t=2, cs=dummy, sch=0: lib.mpd_run_uncoord(  # noqa: E731
         16, dummy, cs, 4, t, 0.5, 100, sch, dummy, None, dummy, dummy, dummy, dummy, None)
     assert r(t=-1) == -3 and r(cs=None) == -4 and r(sch=-1) == -7
+
+
+def test_resume_arguments_rejected(lib):
+    """mpd_run_steps_from checks L, the step range, the rule, and its state
+    pointers before any launch."""
+    d = ctypes.c_void_p(256)
+    f = lambda L=16, t0=2, t=3, mm=0, u=0, m_in=d, s_in=d, w_in=d, ms=None, m_out=d, n=4: lib.mpd_run_steps_from(  # noqa
+        L, m_in, s_in, w_in, n, t0, t, mm, u, ms, m_out, d, d, None)
+    assert f(L=2) == -1 and f(L=256) == -1
+    assert f(t0=-1) == -3 and f(t=-1) == -3 and f(t0=10000, t=923) == -3
+    assert f(mm=-1) == -8 and f(u=-1) == -8
+    assert f(m_in=None) == -4 and f(s_in=None) == -4 and f(w_in=None) == -4 and f(m_out=None) == -4
+    assert f(m_in=ctypes.c_void_p(257)) == -4 and f(u=2) == -4
+    assert f(n=-1) == -7 and f(n=0) == 0
