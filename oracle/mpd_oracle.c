@@ -105,7 +105,8 @@
  *   R26 clock: time runs in slots; in slot s site i rings iff word 2(i&1) of
  *       Philox4x32-10(key = seed, counter = (i >> 1, s, 0x41535943, 0)) is
  *       below ring_thr (a probability times 2^32), and ringing sites attempt
- *       one update each in increasing order of (word 2(i&1)+1, i).  As the
+ *       one update each in increasing order of (top 19 bits of word
+ *       2(i&1)+1, i), i.e. of word >> 13, then the site index.  As the
  *       probability goes to 0 with slots of that length this is the
  *       independent rate-1 Poisson clocks the section names as an example;
  *       the simulated decoder does not depend on the order (Prop. "faithful
@@ -921,7 +922,7 @@ static int orc_desync_run(int unc, int sched, int L, int v, uint64_t seed, uint6
       uint32_t ctr[4] = {(uint32_t)(i >> 1), (uint32_t)slot, ORC_CLOCK_TAG, 0u}, w[4];
       orc_philox4x32_10(ctr, st->key, w);
       for (int h = 0; h < 2 && i + h < n; ++h)
-        if ((uint64_t)w[2 * h] < ring_thr) { ring[nr].prio = w[2 * h + 1]; ring[nr].i = (int32_t)(i + h); ++nr; }
+        if ((uint64_t)w[2 * h] < ring_thr) { ring[nr].prio = w[2 * h + 1] >> 13; ring[nr].i = (int32_t)(i + h); ++nr; }
     }
     qsort(ring, (size_t)nr, sizeof(orc_ring), orc_ring_cmp);
     int64_t f0 = a.flips;

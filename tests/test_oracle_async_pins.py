@@ -169,7 +169,7 @@ def clock_times(orc, L, seed, rho, S, target):
         for i in range(L * L):
             w = orc.philox4x32_10([i >> 1, slot, 0x41535943, 0], key)
             if int(w[2 * (i & 1)]) < thr:
-                ring.append((int(w[2 * (i & 1) + 1]), i))
+                ring.append((int(w[2 * (i & 1) + 1]) >> 13, i))
         for _, i in sorted(ring):
             x, y = i % L, i // L
             if t[y, x] >= target:
@@ -182,9 +182,10 @@ def clock_times(orc, L, seed, rho, S, target):
 
 @pytest.mark.parametrize("L,rho,seed", [(6, 0.5, 77), (7, 0.9, 2**33 + 1), (9, 0.25, 5)])
 def test_simulation_times_follow_the_clock_order(orc, L, rho, seed):
-    """Within a slot the ringing sites attempt in increasing order of their
-    priority word (R26); the order decides which attempts the lag rule accepts
-    (R24), so the simulation times after a few slots fix it."""
+    """Within a slot the ringing sites attempt in increasing order of the top
+    19 bits of their priority word, then of their index (R26); the order
+    decides which attempts the lag rule accepts (R24), so the simulation times
+    after a few slots fix it."""
     ex, ey = orc.noise(L, 0.1, 17)
     for S in (2, 7, 15):
         r = orc.async_run(L, ex, ey, seed=seed, rho=rho, t_target=6, S_max=S)
