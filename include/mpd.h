@@ -221,7 +221,7 @@ int mpd_run_steps_from(int L, const int16_t *d_m_in, const uint32_t *d_sigma_in,
  * Clock: time runs in slots.  In slot s site i rings iff word 2*(i&1) of
  * Philox4x32-10(key = clock seed, counter (i >> 1, s, 0x41535943, 0)) is
  * below floor(rho * 2^32) (at least 1); ringing sites attempt one update
- * each in increasing order of (word 2*(i&1)+1, i).  Small rho approaches
+ * each in increasing order of (word 2*(i&1)+1 >> 13, i).  Small rho approaches
  * independent rate-1 Poisson clocks with slots of length rho.
  *
  * mpd_decode_async: noise from d_seeds as mpd_decode_batch (the same seed

@@ -19,20 +19,21 @@
 // Clock: time runs in slots.  In slot s site i rings iff word 2(i&1) of
 // Philox4x32-10(key = seed, counter (i >> 1, s, CLOCK_TAG, 0)) is below the
 // ring threshold, and the ringing sites attempt one update each in
-// increasing order of (word 2(i&1)+1, i).  The workgroup realises that order
+// increasing order of (word 2(i&1)+1 >> 13, i).  The workgroup realises that order
 // in parallel rounds: every pending ringer whose key is the smallest among
 // the pending ringers within distance 2 attempts.  Those sites are more than
 // 2 apart, so what they read and write is disjoint; updates more than 2
 // apart commute; and any two ringers within distance 2 attempt in key order.
 // Each slot therefore ends in the state of the sequential order.
 //
-// A ringer's key is (priority word << 32 | i), unique per site; an idle site
-// (not ringing, or done for this slot) holds the key ~0.  A pending site is
+// A ringer's key is (priority word >> 13) << 13 | i, unique per site (i <
+// 4096); the largest, 0xFFFFEFFF, stays below the key ~0 of an idle site
+// (not ringing, or done for this slot).  A pending site is
 // ready when its key is the minimum of the 5 x 5 box around it, found in two
 // separable passes (row minima, then column minima of those).
 //
 // One workgroup holds one sample (5 <= L <= 64) in LDS for its whole run:
-//   K, H    u64 per site: key of the current slot, row minimum of the keys
+//   K, H    u32 per site: key of the current slot, row minimum of the keys
 //   MN, MO  uint2 per site: m^new / m^old in distance form, packed u16
 //           (.x = m^{+x} | m^{-x} << 16, .y = m^{+y} | m^{-y} << 16)
 //   TS      u16 simulation time
@@ -77,15 +78,15 @@ struct AsyncArgs {
   uint8_t *wind_out;
 };
 
-constexpr uint64_t IDLE = ~(uint64_t)0;
+constexpr uint32_t IDLE = 0xFFFFFFFFu;
 constexpr int ASYNC_SITES = 4;   // sites per thread; the launch uses at least N / 4 threads
 
 size_t async_lds(int L) {
   const size_t N = (size_t)L * L;
-  return ((38 * N + 15) & ~(size_t)15) + 32;
+  return ((30 * N + 15) & ~(size_t)15) + 32;
 }
 
-__device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
 
 __device__ __forceinline__ int wrapc(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
@@ -122,7 +123,7 @@ __device__ __forceinline__ void site_force(uint2 m, int &fx, int &fy) {
 }
 
 struct AsyncLds {
-  uint64_t *K, *H;
+  uint32_t *K, *H;
   uint2 *MN, *MO;
   uint16_t *TS;
   uint8_t *FL, *CH;
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int L = a.L, N = L * L;
   AsyncLds s;
-  s.K = (uint64_t *)lds;
+  s.K = (uint32_t *)lds;
   s.H = s.K + N;
   s.MN = (uint2 *)(s.H + N);
   s.MO = s.MN + N;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   s.CH = s.FL + N;
   s.RL = (uint16_t *)(s.CH + N);
   // wind bits, 1 + last flip slot, updates, lengths of the ready list (two)
-  int *RED = (int *)(lds + ((38 * (size_t)N + 15) & ~(size_t)15));
+  int *RED = (int *)(lds + ((30 * (size_t)N + 15) & ~(size_t)15));
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x, T = blockDim.x;
   const uint64_t seed = a.seeds != nullptr ? a.seeds[b] : 0u;
@@ -342,10 +343,10 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
         const Words4 w = philox4x32_10((uint32_t)h, k0, k1, (uint32_t)slot, CLOCK_TAG);
         const int i0 = 2 * h, i1 = 2 * h + 1;
         const bool r0 = (uint64_t)w.w0 < a.ring_thr && (!run || s.TS[i0] < target);
-        s.K[i0] = r0 ? ((uint64_t)w.w1 << 32 | (uint32_t)i0) : IDLE;
+        s.K[i0] = r0 ? ((w.w1 >> 13) << 13 | (uint32_t)i0) : IDLE;
         if (i1 < N) {
           const bool r1 = (uint64_t)w.w2 < a.ring_thr && (!run || s.TS[i1] < target);
-          s.K[i1] = r1 ? ((uint64_t)w.w3 << 32 | (uint32_t)i1) : IDLE;
+          s.K[i1] = r1 ? ((w.w3 >> 13) << 13 | (uint32_t)i1) : IDLE;
         }
       }
     }
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
       RED[3] = 0;
       RED[4] = 0;
     }
-    uint64_t kv[ASYNC_SITES][5];
+    uint32_t kv[ASYNC_SITES][5];
     auto row_pass = [&]() {
       // row minima of the keys over x - 2 .. x + 2 (all loads of the thread's
       // sites issued together); returns whether any own site is pending
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
         const int i = tid + k * T;
         if (i < N) {
           pend |= kv[k][2] != IDLE;
-          s.H[i] = min64(min64(min64(kv[k][0], kv[k][1]), min64(kv[k][2], kv[k][3])), kv[k][4]);
+          s.H[i] = min(min(min(kv[k][0], kv[k][1]), min(kv[k][2], kv[k][3])), kv[k][4]);
         }
       }
       return pend;
@@ -391,9 +392,9 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
 #pragma unroll
       for (int k = 0; k < ASYNC_SITES; ++k) {
         const int x = (int)(xy[k] & 0xFFFFu), y = (int)(xy[k] >> 16);
-        uint64_t m = IDLE;
+        uint32_t m = IDLE;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) m = min64(m, s.H[wrapc(y + d - 2, L) * L + x]);
+        for (int d = 0; d < 5; ++d) m = min(m, s.H[wrapc(y + d - 2, L) * L + x]);
         const bool ready = tid + k * T < N && kv[k][2] != IDLE && m == kv[k][2];
         rbits |= (ready ? 1u : 0u) << k;
       }
