@@ -112,3 +112,21 @@ def test_edge_cases(gpu, orc):
     T, F, SL, U, S = (_np(x) for x in gpu.decode_async(5, 0.15, s, 0.4, S_max=65000))
     assert np.array_equal(T, ref["T_async"]) and np.array_equal(F, ref["flags"])
     assert np.array_equal(SL, ref["slots"]) and np.array_equal(U, ref["updates"])
+
+
+@pytest.mark.parametrize("mode", ["marching", "cyclic", "random"])
+def test_bench_batch_sampled_against_oracle(gpu, orc, mode):
+    """The benchmark's launch: 1024 samples of L = 64 at p = 0.05, ring
+    probability 1/8, S_max = 20000, in one call; the oracle recomputes a
+    spread of 32 of them one by one."""
+    L, p, n, rho, S_max = 64, 0.05, 1024, 0.125, 20000
+    s = seeds(11, int(p * 1000) + L, n, start=n)
+    unc = mode != "marching"
+    T, F, SL, U, S = (_np(x) for x in gpu.decode_async(L, p, s, rho, S_max, uncoordinated=unc,
+                                                       schedule=mode if unc else "cyclic"))
+    pick = np.linspace(0, n - 1, 32).astype(int)
+    ref = orc.async_decode_seeds(L, p, s[pick], rho=rho, S_max=S_max, threads=16, uncoordinated=unc,
+                                 schedule=mode if unc else "cyclic")
+    for key, got in (("T_async", T), ("flags", F), ("slots", SL), ("updates", U)):
+        assert np.array_equal(got[pick], ref[key]), key
+    assert np.array_equal(S.view(np.uint32)[pick], ref["sigma_words"])
