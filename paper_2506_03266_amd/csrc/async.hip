@@ -1,36 +1,40 @@
-// async.hip -- marching-soldiers desynchronization of the decoder on the GPU
-// (Sec. "Desynchronization and Lindbladian dynamics": Def. "simulation and
-// lag times", Def. "marching soldiers desynchronization", Def.
-// "desynchronized decoders").
+// async.hip -- desynchronized decoders on the GPU (Sec. "Desynchronization
+// and Lindbladian dynamics": Def. "simulation and lag times", Def. "marching
+// soldiers desynchronization", Def. "desynchronized decoders"; Sec.
+// "Uncoordinated desynchronization").
 //
-// Every site runs the synchronous schedule at its own pace: v = 3 message
-// updates, then one feedback update that applies F to the two links the site
-// owns (r -> r + x-hat, r -> r + y-hat); t_sim counts these updates.  An
-// update of r is accepted only if no site within infinity-distance 2 (twice
-// the range Delta = 1 over which A and F read and write) is behind r.  A site
-// keeps m^old and m^new: a neighbour one update ahead shows m^old, a level
-// one m^new.  Feedback of step k must see each syndrome before any step-k
-// feedback: the flips applied at a site by step-k feedback are recorded in a
-// flip parity of slot k mod 2, which the reader undoes; a site clears the
-// slot of step k - 1 when it starts step k.  The simulated dynamics is then
-// exactly the synchronous decoder's, whatever the order of the accepted
-// updates (Prop. "faithful Lindbladian simulation").
+// Marching soldiers.  Every site runs the synchronous schedule at its own
+// pace: v = 3 message updates, then one feedback update that applies F to the
+// two links the site owns (r -> r + x-hat, r -> r + y-hat); t_sim counts
+// these updates.  An update of r is accepted only if no site within
+// infinity-distance 2 (twice the range Delta = 1 over which A and F read and
+// write) is behind r.  A site keeps m^old and m^new: a neighbour one update
+// ahead shows m^old, a level one m^new.  Feedback of step k must see each
+// syndrome before any step-k feedback: the flips applied at a site by step-k
+// feedback are recorded in a flip parity of slot k mod 2, which the reader
+// undoes; a site clears the slot of step k - 1 when it starts step k.  The
+// simulated dynamics is then exactly the synchronous decoder's, whatever the
+// order of the accepted updates (Prop. "faithful Lindbladian simulation").
+//
+// Uncoordinated (template mode UNC).  The same clock and rounds without the
+// lag rule or old copies: message updates read current values, and a motion
+// update moves the site's anyon along its force (uncoord_update).
 //
 // Clock: time runs in slots.  In slot s site i rings iff word 2(i&1) of
 // Philox4x32-10(key = seed, counter (i >> 1, s, CLOCK_TAG, 0)) is below the
 // ring threshold, and the ringing sites attempt one update each in
-// increasing order of (word 2(i&1)+1 >> 13, i).  The workgroup realises that order
-// in parallel rounds: every pending ringer whose key is the smallest among
-// the pending ringers within distance 2 attempts.  Those sites are more than
+// increasing order of (word 2(i&1)+1 >> 13, i).  The workgroup realises that
+// order in parallel rounds: every pending ringer whose key is the smallest
+// among the pending ringers within distance 2 attempts.  Those sites are more than
 // 2 apart, so what they read and write is disjoint; updates more than 2
 // apart commute; and any two ringers within distance 2 attempt in key order.
 // Each slot therefore ends in the state of the sequential order.
 //
 // A ringer's key is (priority word >> 13) << 13 | i, unique per site (i <
-// 4096); the largest, 0xFFFFEFFF, stays below the key ~0 of an idle site
-// (not ringing, or done for this slot).  A pending site is
-// ready when its key is the minimum of the 5 x 5 box around it, found in two
-// separable passes (row minima, then column minima of those).
+// 4096); the largest, 0xFFFFEFFF, stays below the key ~0 of an idle site (not
+// ringing, or done for this slot).  A pending site is ready when its key is
+// the minimum of the 5 x 5 box around it, found in two separable passes (row
+// minima, then column minima of those).
 //
 // One workgroup holds one sample (5 <= L <= 64) in LDS for its whole run:
 //   K, H    u32 per site: key of the current slot, row minimum of the keys
