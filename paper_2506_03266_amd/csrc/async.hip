@@ -126,6 +126,22 @@ __device__ __forceinline__ void site_force(uint2 m, int &fx, int &fy) {
   fy = axis == 1 ? force_of(py, my) : 0;
 }
 
+// Workgroup OR of a predicate through a single barrier (the library form
+// takes three).  Three flags rotate: call c ORs into flag c % 3 and clears
+// flag (c + 1) % 3 for the next call, before its barrier.  The readers of a
+// flag read it right after the barrier of its call and pass one more barrier
+// before the flag is cleared again, and the next writers of the cleared flag
+// start only after this call's barrier.  Every thread must make the same
+// calls.
+__device__ __forceinline__ bool wg_or(bool pred, int *flags, uint32_t &c) {
+  const uint32_t cur = c % 3u, nxt = (c + 1u) % 3u;
+  ++c;
+  if (threadIdx.x == 0) flags[nxt] = 0;
+  if (__ballot(pred) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&flags[cur], 1);
+  __syncthreads();
+  return flags[cur] != 0;
+}
+
 struct AsyncLds {
   uint32_t *K, *H;
   uint2 *MN, *MO;
@@ -287,7 +303,8 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   s.FL = (uint8_t *)(s.TS + N);
   s.CH = s.FL + N;
   s.RL = (uint16_t *)(s.CH + N);
-  // wind bits, 1 + last flip slot, updates, lengths of the ready list (two)
+  // wind bits, 1 + last flip slot, updates, lengths of the ready list (two),
+  // the three flags of wg_or
   int *RED = (int *)(lds + ((30 * (size_t)N + 15) & ~(size_t)15));
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x, T = blockDim.x;
@@ -339,6 +356,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   uint32_t my_updates = 0;
   int slot = 0;
   int busy_any = 0;
+  uint32_t orc = 0;  // calls of wg_or so far (RED[5..7] are its flags)
   for (;; ++slot) {
     int busy = 0;
     for (int i = tid; i < N; i += T) busy |= run ? (s.TS[i] < target) : (s.FL[i] != 0);
@@ -354,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
         }
       }
     }
-    busy_any = __syncthreads_or(busy);
+    busy_any = wg_or(busy != 0, RED + 5, orc);
     if (!busy_any || slot >= a.S_max) break;
     // Rounds.  The row pass of the next round shares the update phase of the
     // current one: it reads only the keys, which change only in the listing
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
     };
     int pend = row_pass();
     for (int round = 0;; ++round) {
-      if (!__syncthreads_or(pend)) break;
+      if (!wg_or(pend != 0, RED + 5, orc)) break;
       int *cnt = &RED[3 + (round & 1)];
       // a pending site holding the minimum of its box is ready
       uint32_t rbits = 0;
