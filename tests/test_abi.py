@@ -257,3 +257,27 @@ def test_resume_arguments_rejected(lib):
     assert f(m_in=None) == -4 and f(s_in=None) == -4 and f(w_in=None) == -4 and f(m_out=None) == -4
     assert f(m_in=ctypes.c_void_p(257)) == -4 and f(u=2) == -4
     assert f(n=-1) == -7 and f(n=0) == 0
+
+
+def test_band_tuning_round_trip(lib, tmp_path):
+    """save_band_tuning / load_band_tuning persist per-L schedules and
+    drivers across processes (here: across a reset of the settings)."""
+    import paper_2506_03266_amd.binding as b
+    try:
+        b.set_band_schedule(5, 3, 0)
+        b.set_band_schedule(2, 1, 512)
+        b.set_band_driver(b.BAND_DRIVER_DEVICE, 512)
+        b.set_band_schedule(6, 4, 1024)
+        path = str(tmp_path / "tuning.json")
+        saved = b.save_band_tuning(path, [512, 1024])
+        assert saved["per_L"]["512"] == {"k_first": 2, "k_next": 1, "driver": b.BAND_DRIVER_DEVICE}
+        b.set_band_driver(b.BAND_DRIVER_AUTO, 0)
+        b.set_band_schedule(4, 2, 0)
+        assert b.get_band_schedule(512) == (4, 2)
+        b.load_band_tuning(path)
+        assert b.get_band_schedule(0) == (5, 3)
+        assert b.get_band_schedule(512) == (2, 1) and b.get_band_driver(512) == b.BAND_DRIVER_DEVICE
+        assert b.get_band_schedule(1024) == (6, 4) and b.get_band_driver(1024) == b.get_band_driver(0)
+    finally:
+        b.set_band_driver(b.BAND_DRIVER_AUTO, 0)
+        b.set_band_schedule(4, 2, 0)
