@@ -15,7 +15,10 @@ Three measurements, all on i.i.d. bit-flip noise, periodic L x L lattices, v = 3
   boundaries, appendix on open boundaries) and its crossings;
 * with ``--uncoord``: p_log against p of the uncoordinated desynchronization
   (Sec. "Uncoordinated desynchronization") beside the synchronous decoder on
-  the same seeds, and the crossings of both.
+  the same seeds, and the crossings of both;
+* with ``--slowdown``: the marching-soldiers decoder's decoding time against
+  the synchronous T_dec on the same seeds, for several L (Lemma "constant
+  slowdown for desynchronization": the ratio tends to a constant).
 
 Every sample is decoded by libmpd (noise, decoding and classification run in
 the HIP kernels); this module chooses seeds, sums the per-sample results on
@@ -55,6 +58,8 @@ UNCOORD_P = [0.05, 0.06, 0.065, 0.07, 0.075, 0.08, 0.09]
 UNCOORD_L = [(16, 40000), (32, 20000), (64, 8000)]
 UNCOORD_RHO = 0.125     # ring probability per slot: close to independent Poisson clocks
 UNCOORD_S_MAX = 20000   # slots
+SLOWDOWN_P = [0.01, 0.03]
+SLOWDOWN_L = [(8, 8192), (16, 8192), (32, 4096), (48, 2048), (64, 2048)]
 
 
 def seed_block(L: int, p_index: int, n: int, start: int = 0) -> np.ndarray:
@@ -257,6 +262,37 @@ def run_uncoord(quick: bool = False, log=print) -> dict:
     return dict(points=pts, crossings=cross, rho=UNCOORD_RHO, S_max=UNCOORD_S_MAX)
 
 
+def run_slowdown(quick: bool = False, log=print) -> list:
+    """Mean decoding time of the marching-soldiers decoder (slots x ring
+    probability) against the mean synchronous T_dec on the same seeds, over
+    the samples both finish; outcomes must agree on every such sample."""
+    import torch
+    from . import binding as b
+    scale = 0.1 if quick else 1.0
+    rows = []
+    for p in SLOWDOWN_P:
+        for L, n in SLOWDOWN_L:
+            n = max(256, int(n * scale))
+            s = torch.from_numpy(seed_block(L, 240 + SLOWDOWN_P.index(p), n).view(np.int64)).cuda()
+            t0 = time.perf_counter()
+            Ta, Fa, _, Ua, _ = b.decode_async(L, p, s, UNCOORD_RHO, UNCOORD_S_MAX, want_syndrome=False)
+            Ts, Fs, _ = b.decode_batch(L, p, s, 4096, want_syndrome=False)
+            Ta, Fa, Ua = Ta.cpu().numpy(), Fa.cpu().numpy(), Ua.cpu().numpy()
+            Ts, Fs = Ts.cpu().numpy(), Fs.cpu().numpy()
+            dt = time.perf_counter() - t0
+            both = ((Fa & 2) == 0) & ((Fs & 2) == 0) & (Ts > 0)
+            ta = Ta[both].astype(np.float64) * UNCOORD_RHO
+            ts = Ts[both].astype(np.float64)
+            r = dict(L=L, p=p, n=n, decoded=int(both.sum()), time_async=float(ta.mean()), T_sync=float(ts.mean()),
+                     ratio=float(ta.mean() / ts.mean()), ratio_median=float(np.median(ta / ts)),
+                     outcomes_equal=bool(np.array_equal(Fa[both], Fs[both])), seconds=dt)
+            log(f"slowdown L={L} p={p}: async time {r['time_async']:.2f} / sync T {r['T_sync']:.3f} = {r['ratio']:.2f} "
+                f"(median per sample {r['ratio_median']:.2f}) over {r['decoded']} samples, outcomes equal "
+                f"{r['outcomes_equal']}, {dt:.1f}s")
+            rows.append(r)
+    return rows
+
+
 def summarize(res: dict) -> dict:
     """Crossings of consecutive sizes (all samples, and decoded samples only),
     slopes gamma against the crossing of the two largest sizes, and
@@ -306,10 +342,17 @@ def main(argv=None):
     ap.add_argument("--memory", action="store_true", help="only the limited-memory grid")
     ap.add_argument("--open", action="store_true", help="only the open-lattice threshold grid")
     ap.add_argument("--uncoord", action="store_true", help="only the uncoordinated-desynchronization threshold grid")
+    ap.add_argument("--slowdown", action="store_true", help="only the marching-soldiers slowdown against L")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         sys.exit("sweep: needs a GPU (the decoder runs only in libmpd's HIP kernels)")
+    if a.slowdown:
+        res = run_slowdown(a.quick, log=lambda s: print(s, flush=True))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     if a.uncoord:
         res = run_uncoord(a.quick, log=lambda s: print(s, flush=True))
         print(json.dumps(res["crossings"]), flush=True)
