@@ -91,3 +91,15 @@ def test_uncoord_point_matches_oracle(gpu, orc, L, p, n, schedule):
     done = (F & 2) == 0
     assert (r["fails"], r["timeouts"]) == (int((F & 1).sum()), int((~done).sum()))
     assert (r["T_sum"], r["T_sq"]) == (int(T[done].sum()), int((T[done] ** 2).sum()))
+
+
+def test_slowdown_rows(gpu):
+    """The slowdown sweep (quick): most samples have anyons and finish, with
+    outcomes equal to the synchronous decoder's, and the ratio lies in the
+    band the lag rule allows (at least v + 1 = 4 updates per step, each
+    accepted at most once per ring)."""
+    rows = sweep.run_slowdown(quick=True, log=lambda s: None)
+    assert len(rows) == len(sweep.SLOWDOWN_P) * len(sweep.SLOWDOWN_L)
+    for r in rows:
+        assert r["outcomes_equal"] and r["decoded"] > 0.5 * r["n"]
+        assert 4.0 <= r["ratio"] <= 40.0, r
