@@ -712,10 +712,12 @@ int orc_decode_links(int L, int v, const uint32_t *links, int64_t n, int T_max, 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Marching-soldiers desynchronization (Sec. "Desynchronization and          */
-/* Lindbladian dynamics": Def. "simulation and lag times", Def. "marching    */
-/* soldiers desynchronization", Def. "desynchronized decoders", Prop.       */
-/* "faithful Lindbladian simulation"), readings R23-R27, torus only.        */
+/* Desynchronized decoders, torus only: marching soldiers (Sec.             */
+/* "Desynchronization and Lindbladian dynamics": Def. "simulation and lag   */
+/* times", Def. "marching soldiers desynchronization", Def. "desynchronized */
+/* decoders", Prop. "faithful Lindbladian simulation"; readings R23-R27)    */
+/* and the uncoordinated desynchronization (Sec. "Uncoordinated             */
+/* desynchronization"; reading R28), on one clock.                          */
 /* ------------------------------------------------------------------------ */
 #define ORC_CLOCK_TAG 0x41535943u
 #define ORC_TYPE_TAG 0x54595045u
