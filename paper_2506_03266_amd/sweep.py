@@ -254,12 +254,21 @@ def run_uncoord(quick: bool = False, log=print) -> dict:
             pts["random"].append(rr)
             pts["synchronous"].append(rs)
     Ls = [L for L, _ in UNCOORD_L]
-    cross = {}
+    cross, gamma = {}, {}
     for key, rows in pts.items():
         tab = {(r["L"], r["p"]): p_log(r) for r in rows}
         cross[key] = {f"{L1}/{L2}": crossing(UNCOORD_P, [tab[(L1, p)] for p in UNCOORD_P],
                                              [tab[(L2, p)] for p in UNCOORD_P]) for L1, L2 in zip(Ls, Ls[1:])}
-    return dict(points=pts, crossings=cross, rho=UNCOORD_RHO, S_max=UNCOORD_S_MAX)
+        # slope of p_log = C (p / p_c)^(gamma L) below threshold, from the two
+        # largest sizes, against the decoder's own crossing of those sizes
+        p_c = cross[key][f"{Ls[-2]}/{Ls[-1]}"]
+        gamma[key] = {}
+        if p_c:
+            for p in UNCOORD_P:
+                f1, f2 = tab[(Ls[-2], p)], tab[(Ls[-1], p)]
+                if p < p_c and f1 > 0 and f2 > 0:
+                    gamma[key][str(p)] = slope_gamma(Ls[-2], f1, Ls[-1], f2, p, p_c)
+    return dict(points=pts, crossings=cross, gamma=gamma, rho=UNCOORD_RHO, S_max=UNCOORD_S_MAX)
 
 
 def run_slowdown(quick: bool = False, log=print) -> list:
@@ -355,7 +364,7 @@ def main(argv=None):
         return
     if a.uncoord:
         res = run_uncoord(a.quick, log=lambda s: print(s, flush=True))
-        print(json.dumps(res["crossings"]), flush=True)
+        print(json.dumps({"crossings": res["crossings"], "gamma": res["gamma"]}), flush=True)
         if a.json:
             with open(a.json, "w") as f:
                 json.dump(res, f, indent=1)
