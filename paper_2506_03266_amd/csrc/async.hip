@@ -510,7 +510,8 @@ int launch_async(const AsyncArgs &a, int64_t n, bool unc, hipStream_t stream) {
   const int N = a.L * a.L;
   // four sites per thread (one wave for the smallest lattices), so that small
   // lattices leave room for several workgroups per compute unit
-  const int threads = std::min(1024, std::max(64, (N / 4 + 63) / 64 * 64));
+  const int threads = std::min(1024, std::max(64, ((N + 3) / 4 + 63) / 64 * 64));
+  if (threads * ASYNC_SITES < N) return fail_with(MPD_ERR_L, "L=%d: more than %d sites per thread", a.L, ASYNC_SITES);
   ProfScope ps(unc ? "k_async_unc" : "k_async", stream);
   if (unc)
     hipLaunchKernelGGL(k_async<true>, dim3((unsigned)n), dim3(threads), async_lds(a.L), stream, a);
