@@ -63,7 +63,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--cpu-samples", type=int, default=5120,
+                    help="samples of the oracle CPU baseline (about 10 s on 16 host threads)")
     ap.add_argument("--workload", choices=["c3", "c1", "c2", "c4", "c5", "cnn", "rule", "open", "async"],
                     default="c3",
                     help="c3 (default) is the headline line; c1/c2/c4/c5 print a line for that configuration, "
