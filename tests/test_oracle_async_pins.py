@@ -190,3 +190,21 @@ def test_simulation_times_follow_the_clock_order(orc, L, rho, seed):
     for S in (2, 7, 15):
         r = orc.async_run(L, ex, ey, seed=seed, rho=rho, t_target=6, S_max=S)
         assert np.array_equal(r["tsim"], clock_times(orc, L, seed, rho, S, 4 * 6)), S
+
+
+def test_decode_stops_at_the_first_quiet_slot_boundary(orc):
+    """R27: a decode ends at the first slot boundary with no anyon and no
+    pending flip.  With one slot less the stop rule does not hold yet, so the
+    run reports a timeout, and its last flip came no later; with exactly that
+    many slots the run is the same decode."""
+    L = 12
+    for s in seeds(134, 0, 12):
+        ex, ey = orc.noise(L, 0.06, int(s))
+        r = orc.async_run(L, ex, ey, seed=int(s), rho=0.3, S_max=20000)
+        if r["flags"] & 2 or r["slots"] == 0:
+            continue
+        short = orc.async_run(L, ex, ey, seed=int(s), rho=0.3, S_max=r["slots"] - 1)
+        assert short["flags"] & 2 and short["slots"] == r["slots"] - 1
+        assert short["T_async"] <= r["T_async"] <= r["slots"]
+        again = orc.async_run(L, ex, ey, seed=int(s), rho=0.3, S_max=r["slots"])
+        assert (again["flags"], again["slots"], again["T_async"]) == (r["flags"], r["slots"], r["T_async"])
