@@ -130,3 +130,30 @@ def test_bench_batch_sampled_against_oracle(gpu, orc, mode):
     for key, got in (("T_async", T), ("flags", F), ("slots", SL), ("updates", U)):
         assert np.array_equal(got[pick], ref[key]), key
     assert np.array_equal(S.view(np.uint32)[pick], ref["sigma_words"])
+
+
+def _random_cases(k):
+    rng = np.random.default_rng(20261203)
+    cases = []
+    for _ in range(k):
+        L = int(rng.integers(5, 65))
+        p = float(rng.choice([0.01, 0.03, 0.05, 0.08, 0.12]))
+        rho = float(rng.choice([0.02, 0.1, 0.25, 0.6, 1.0]))
+        mode = str(rng.choice(["marching", "cyclic", "random"]))
+        S_max = int(rng.choice([50, 400, 5000]))
+        cases.append((L, p, rho, mode, S_max))
+    return cases
+
+
+@pytest.mark.parametrize("L,p,rho,mode,S_max", _random_cases(36))
+def test_random_configurations_match_oracle(gpu, orc, L, p, rho, mode, S_max):
+    """Seeded random lattice sizes (ragged waves and syndrome words), noise,
+    ring probabilities, decoders and slot budgets: whole decodes bit for bit."""
+    s = seeds(145, 1000 * L + int(100 * rho), 6)
+    unc = mode != "marching"
+    sched = mode if unc else "cyclic"
+    T, F, SL, U, S = (_np(x) for x in gpu.decode_async(L, p, s, rho, S_max, uncoordinated=unc, schedule=sched))
+    ref = orc.async_decode_seeds(L, p, s, rho=rho, S_max=S_max, threads=8, uncoordinated=unc, schedule=sched)
+    for key, got in (("T_async", T), ("flags", F), ("slots", SL), ("updates", U)):
+        assert np.array_equal(got, ref[key]), (key, got, ref[key])
+    assert np.array_equal(S.view(np.uint32), ref["sigma_words"])
