@@ -64,3 +64,24 @@ def test_resume_keeps_the_step_numbers_of_the_rule_variant(gpu, orc, L, m_max, u
         assert torch.equal(M2, Mr) and torch.equal(S2, Sr) and torch.equal(W2, Wr), (t1, t2)
         m, sig, _, _ = orc.run_steps(L, exs[1], eys[1], t1 + t2, m_max=m_max, u=u, seed=int(ms[1]))
         assert np.array_equal(M2[1].cpu().numpy().astype(np.int64), m.astype(np.int64))
+
+
+@pytest.mark.parametrize("L", [64, 80, 96])
+def test_strip_table_sizes_in_every_mode(gpu, orc, L):
+    """The lattice sizes whose strip height is set by the measured table
+    (64 -> 8, 80 -> 10, 96 -> 12): seeded decodes of the plain rule, the
+    limited-memory rule and the open lattice, and a state export, against
+    the oracle."""
+    n = 6
+    s = seeds(181, L, n)
+    for kw, okw, fn in ((dict(), dict(), gpu.decode_batch),
+                        (dict(m_max=4, u=3), dict(m_max=4, u=3), gpu.decode_rule),
+                        (dict(), dict(open_bc=True), gpu.decode_open)):
+        T, F, S = fn(L, 0.05, s, 300, **kw)
+        ref = orc.decode_seeds(L, 0.05, s, 300, threads=8, **okw)
+        assert np.array_equal(T.cpu().numpy(), ref["T_dec"]) and np.array_equal(F.cpu().numpy(), ref["flags"]), fn
+        assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"]), fn
+    ms, exs, eys, links = patterns(orc, L, 0.06, 2, 4)
+    M, S, W = gpu.run_steps(L, links, 5)
+    m, sig, _, _ = orc.run_steps(L, exs[0], eys[0], 5)
+    assert np.array_equal(M[0].cpu().numpy().astype(np.int64), m.astype(np.int64))
