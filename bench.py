@@ -148,8 +148,7 @@ def main():
     elapsed = runner.run(fifo, range(W, W + K))
 
     device_leg = device_driven(b, batches, outs, W, K, n, wss[0], torch) if args.band_driver == "auto" else None
-    learned_leg = None if args.no_learned else learned_scheduling(b, batches, outs, W, K, n, elapsed, torch, np,
-                                                                  runner)
+    learned_leg = None if args.no_learned else learned_scheduling(b, batches, outs, W, K, n, torch, np, runner)
 
     T_all = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
     F_all = torch.cat([outs[i][1] for i in range(W, W + K)]).cpu().numpy()
@@ -297,9 +296,10 @@ def device_driven(b, batches, outs, W, K, n, ws, torch):
             "identical_results": bool(same)}
 
 
-def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, runner, L_eval=L):
+def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
     """Train, tune and time the learned-scheduling decode on the benchmark's batches
-    (same streams and batches in flight as the plain run)."""
+    (same streams and batches in flight as the plain run), in rounds that
+    alternate with the plain decode of the same batches."""
     from paper_2506_03266_amd import learned
     from paper_2506_03266_amd.workloads import seeds
     from scipy.stats import spearmanr
@@ -310,8 +310,10 @@ def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, runne
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     tune = torch.from_numpy(seeds(3, 201, n).view(np.int64)).to(dev)
-    policy, t_best, t_single, _ = learned.tune_policy(L_eval, P, tune, params, reps=2)
+    policy, t_best, t_single, res = learned.tune_policy(L_eval, P, tune, params, reps=2)
     lwss = [b.learned_workspace(L_eval, n) for _ in runner.streams]
+    tune_set = [(torch.from_numpy(seeds(3, 201 + i, n).view(np.int64)).to(dev), P) for i in range(6)]
+    policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
     louts = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
               torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev),
               torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
@@ -320,8 +322,12 @@ def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, runne
         b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lwss[j],
                          out=louts[i], stream=stream)
 
+    def fifo(i, j, stream):
+        b.decode_batch(L_eval, P, batches[i], T_MAX, workspace=fifo_ws[j], out=outs[i], stream=stream)
+
+    fifo_ws = [b.alloc_workspace(L_eval, n) for _ in runner.streams]
     runner.run(learned, range(W))
-    el = runner.run(learned, range(W, W + K))
+    el_fifo, el = alternate(runner, fifo, learned, W, K)
     # inference time per batch, one stream (no overlap with other batches)
     b.profile(True)
     for i in range(W):
@@ -333,12 +339,103 @@ def learned_scheduling(b, batches, outs, W, K, n, fifo_elapsed, torch, np, runne
     T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy()
     pred = torch.cat([louts[i][3] for i in range(W, W + K)]).cpu().numpy()
     y = np.log1p(T)
-    return {"samples_per_s": K * n / el, "ms_per_step": el / K * 1e3, "ratio_vs_fifo": fifo_elapsed / el,
+    mixed = learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval)
+    return {"samples_per_s": K * n / el, "ms_per_step": el / K * 1e3, "ratio_vs_fifo": el_fifo / el,
             "identical_results": bool(same), "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])},
             "cnn_forward_ms_per_step": cnn_ms / max(cnn_n, 1), "train_s": t_train,
             "train_mse_last_epoch": hist[-1], "eval_mae_ln": float(np.abs(pred - y).mean()),
             "eval_spearman": float(spearmanr(pred, T).correlation),
-            "tuning_ms": {"best": t_best * 1e3, "single_bin": t_single * 1e3}}
+            "tuning_ms": {"best": t_best * 1e3, "single_bin": t_single * 1e3, "in_flight": in_flight},
+            "mixed_p": mixed}
+
+
+def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=8):
+    """Re-times the policies that were fastest one batch at a time, and the
+    single-group policy, with the runner's batches in flight (the way the
+    decode is used), on a set of tuning batches; returns (best policy,
+    {policy: ms per batch})."""
+    n = tune_set[0][0].numel()
+    dev = tune_set[0][0].device
+    outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None,
+             torch.empty(n, dtype=torch.float32, device=dev)) for _ in tune_set]
+    cands = [res[0][1]] + [pol for _, pol in sorted(res[1:], key=lambda r: r[0])[:short]]
+    times = {}
+    for pol in cands:
+        def run(i, j, stream, pol=pol):
+            b.decode_learned(L_eval, tune_set[i][1], tune_set[i][0], params, pol[0], pol[1], T_MAX,
+                             want_syndrome=False, workspace=lwss[j], out=outs[i], stream=stream)
+        runner.run(run, range(len(tune_set)))
+        t = min(runner.run(run, range(len(tune_set))) for _ in range(2))
+        times[pol] = t / len(tune_set) * 1e3
+    best = min(times, key=times.get)
+    return best, {f"{list(p[0])}/{list(p[1])}": t for p, t in times.items()}
+
+
+def alternate(runner, fn_a, fn_b, W, K, rounds=3):
+    """Times fn_a and fn_b over batches W..W+K-1 in alternating rounds (so
+    that drift of the device clock falls on both alike); returns the mean
+    wall time of one round of each."""
+    ta = tb = 0.0
+    for _ in range(rounds):
+        ta += runner.run(fn_a, range(W, W + K))
+        tb += runner.run(fn_b, range(W, W + K))
+    return ta / rounds, tb / rounds
+
+
+def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
+    """The same comparison on batches whose samples each draw their own p from
+    the training range U[0.005, 0.02], where decoding times spread from 2 to
+    about 10 steps.  FIFO runs at the first-pass depth that is fastest for
+    these batches (timed on a tuning batch), and the learned policy is tuned
+    around that depth; both decode the same K batches, 3 in flight."""
+    from paper_2506_03266_amd import learned
+    from paper_2506_03266_amd.workloads import seeds
+    from scipy.stats import spearmanr
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(6)
+    pr = learned.P_RANGE
+    tune_s = torch.from_numpy(seeds(3, 219, n).view(np.int64)).to(dev)
+    tune_p = torch.from_numpy(rng.uniform(pr[0], pr[1], n)).to(dev)
+    bs = [torch.from_numpy(seeds(3, 220 + i, n).view(np.int64)).to(dev) for i in range(W + K)]
+    ps = [torch.from_numpy(rng.uniform(pr[0], pr[1], n)).to(dev) for _ in range(W + K)]
+    k0, kn = b.get_band_schedule(L_eval)
+    k_fifo, fifo_times = learned.best_fifo_depth(L_eval, tune_p, tune_s, T_MAX)
+    wss = [b.mixed_workspace([(L_eval, n)]) for _ in runner.streams]
+    lwss = [b.learned_workspace(L_eval, n) for _ in runner.streams]
+    fo = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+           torch.empty(n * b.syndrome_words(L_eval), dtype=torch.int32, device=dev)) for _ in range(W + K)]
+    lo = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+           torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev),
+           torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
+    b.set_band_schedule(k_fifo, kn, L_eval)
+    try:
+        policy, _, _, res = learned.tune_policy(L_eval, tune_p, tune_s, params, T_MAX, k_first=k_fifo, reps=2,
+                                                wide=True)
+        tune_set = [(torch.from_numpy(seeds(3, 250 + i, n).view(np.int64)).to(dev),
+                     torch.from_numpy(rng.uniform(pr[0], pr[1], n)).to(dev)) for i in range(6)]
+        policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
+
+        def fifo(i, j, stream):
+            b.decode_mixed([(L_eval, n)], ps[i], bs[i], T_MAX, workspace=wss[j], out=fo[i], stream=stream)
+
+        def lrn(i, j, stream):
+            b.decode_learned(L_eval, ps[i], bs[i], params, policy[0], policy[1], T_MAX, workspace=lwss[j],
+                             out=lo[i], stream=stream)
+
+        runner.run(fifo, range(W))
+        runner.run(lrn, range(W))
+        el_fifo, el_lrn = alternate(runner, fifo, lrn, W, K)
+    finally:
+        b.set_band_schedule(k0, kn, L_eval)
+    same = all(torch.equal(fo[i][0], lo[i][0]) and torch.equal(fo[i][1], lo[i][1]) and
+               torch.equal(fo[i][2], lo[i][2].reshape(-1)) for i in range(W, W + K))
+    T = torch.cat([fo[i][0] for i in range(W, W + K)]).cpu().numpy()
+    pred = torch.cat([lo[i][3] for i in range(W, W + K)]).cpu().numpy()
+    return {"p": "per sample U[0.005, 0.02]", "fifo_samples_per_s": K * n / el_fifo,
+            "learned_samples_per_s": K * n / el_lrn, "ratio_vs_fifo": el_fifo / el_lrn,
+            "fifo_first_pass_depth": k_fifo, "fifo_tuning_ms": {str(k): t * 1e3 for k, t in fifo_times.items()},
+            "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])}, "tuning_ms_in_flight": in_flight,
+            "eval_spearman": float(spearmanr(pred, T).correlation), "identical_results": bool(same)}
 
 
 def other_workload(args, b, seeds, torch, np):

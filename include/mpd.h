@@ -438,14 +438,17 @@ int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d
  * predictions, then samples with h_edges[b-1] <= pred < h_edges[b] (n_bins
  * groups, 1 <= n_bins <= 8, edges ascending) start with a pass of
  * h_depth[b] steps (1..15); later passes run every survivor at the band
- * schedule's k_next.  Outputs as mpd_decode_batch, plus d_pred [n] if not
- * NULL.  L: a multiple of 16 in [256, 16384].  Workspace:
- * mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.  Synchronizes
- * `stream`. */
+ * schedule's k_next.  p applies to every sample unless d_p (per-sample [n]
+ * double, 8-byte aligned) is given; with d_p the results equal those of
+ * mpd_decode_mixed with the one class (L, n).  Outputs as mpd_decode_batch,
+ * plus d_pred [n] if not NULL.  L: a multiple of 16 in [256, 16384].
+ * Workspace: mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.
+ * Synchronizes `stream`. */
 size_t mpd_learned_workspace_bytes(int L, int64_t n);
-int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const float *d_params,
-                       int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec, uint8_t *d_flags,
-                       uint32_t *d_final_syndrome, float *d_pred, void *d_workspace, size_t ws_bytes, void *stream);
+int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
+                       const float *d_params, int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec,
+                       uint8_t *d_flags, uint32_t *d_final_syndrome, float *d_pred, void *d_workspace,
+                       size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -94,7 +94,7 @@ def lib():
     L.mpd_cnn_adam_step.restype = I
     L.mpd_learned_workspace_bytes.argtypes = [I, I64]
     L.mpd_learned_workspace_bytes.restype = SZ
-    L.mpd_decode_learned.argtypes = [I, D, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
+    L.mpd_decode_learned.argtypes = [I, D, P, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
     L.mpd_decode_learned.restype = I
     L.mpd_run_steps_from.argtypes = [I, P, P, P, I64, I, I, I, I, P, P, P, P, P]
     L.mpd_run_steps_from.restype = I
@@ -458,6 +458,15 @@ def autotune_band(L: int, p: float, seeds, T_max: int = 4096, stream=None):
     return kf.value, kn.value, ms.value
 
 
+def mixed_workspace(classes, device="cuda"):
+    """Workspace for decode_mixed over classes = [(L, count), ...]."""
+    hL = np.ascontiguousarray([c[0] for c in classes], dtype=np.int32)
+    hC = np.ascontiguousarray([c[1] for c in classes], dtype=np.int64)
+    nb = int(lib().mpd_mixed_workspace_bytes(len(hL), hL.ctypes.data_as(ctypes.c_void_p),
+                                             hC.ctypes.data_as(ctypes.c_void_p)))
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+
+
 def decode_mixed(classes, p, seeds, T_max: int = 4096, want_syndrome: bool = True, workspace=None, out=None,
                  stream=None):
     """Decode a batch ordered by class: classes = [(L, count), ...], p and seeds
@@ -577,14 +586,16 @@ def learned_workspace(L: int, n: int, device="cuda"):
     return torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
 
 
-def decode_learned(L: int, p: float, seeds, params, edges, depths, T_max: int = 4096, want_syndrome: bool = True,
+def decode_learned(L: int, p, seeds, params, edges, depths, T_max: int = 4096, want_syndrome: bool = True,
                    workspace=None, out=None, stream=None):
     """Decode with learned scheduling: samples with edges[b-1] <= pred < edges[b]
-    start with a pass of depths[b] steps.  Returns (T_dec, flags, syndrome,
-    pred), results identical to decode_batch."""
+    start with a pass of depths[b] steps.  p is a number or per-sample values.
+    Returns (T_dec, flags, syndrome, pred), results identical to decode_batch
+    (decode_mixed with the one class (L, n) for per-sample p)."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()
+    pt = _p_tensor(p, n, dev)
     if out is None:
         T = torch.empty(n, dtype=torch.int32, device=dev)
         F = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -596,7 +607,8 @@ def decode_learned(L: int, p: float, seeds, params, edges, depths, T_max: int = 
     hd = np.ascontiguousarray(depths, dtype=np.int32)
     assert hd.size == he.size + 1
     ws = workspace if workspace is not None else learned_workspace(L, n)
-    rc = lib().mpd_decode_learned(L, float(p), _ptr(s), n, int(T_max), _ptr(params), int(hd.size),
+    rc = lib().mpd_decode_learned(L, float(p) if pt is None else 0.0, _ptr(pt), _ptr(s), n, int(T_max),
+                                  _ptr(params), int(hd.size),
                                   he.ctypes.data_as(ctypes.c_void_p), hd.ctypes.data_as(ctypes.c_void_p), _ptr(T),
                                   _ptr(F), _ptr(S), _ptr(pred), _ptr(ws), ws.numel(), _stream_ptr(stream))
     _check(rc, "mpd_decode_learned")

@@ -1500,11 +1500,12 @@ size_t mpd_learned_workspace_bytes(int L, int64_t n) {
   return learned_layout(L, n, nullptr).bytes;
 }
 
-int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, const float *d_params,
-                       int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec, uint8_t *d_flags,
-                       uint32_t *d_final_syndrome, float *d_pred, void *d_workspace, size_t ws_bytes, void *stream) {
+int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
+                       const float *d_params, int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec,
+                       uint8_t *d_flags, uint32_t *d_final_syndrome, float *d_pred, void *d_workspace,
+                       size_t ws_bytes, void *stream) {
   g_last_error.clear();
-  if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
+  if (d_p == nullptr && !(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
   int rc = check_common(L, n, T_max, d_T_dec, d_flags);
   if (rc) return rc;
   if (!tiled_ok(L)) return fail_with(MPD_ERR_L, "L=%d: learned scheduling needs a multiple of 16 in [256, 16384]", L);
@@ -1522,14 +1523,14 @@ int mpd_decode_learned(int L, double p, const uint64_t *d_seeds, int64_t n, int 
   }
   if (n == 0) return MPD_OK;
   if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u) || d_params == nullptr || ((uintptr_t)d_params & 3u) ||
-      ((uintptr_t)d_pred & 3u) || ((uintptr_t)d_final_syndrome & 3u))
-    return fail_with(MPD_ERR_PTR, "seeds/params/pred/syndrome NULL or misaligned");
+      ((uintptr_t)d_pred & 3u) || ((uintptr_t)d_final_syndrome & 3u) || ((uintptr_t)d_p & 7u))
+    return fail_with(MPD_ERR_PTR, "seeds/params/pred/syndrome/p NULL or misaligned");
   const LearnedLayout l = learned_layout(L, n, d_workspace);
   if (d_workspace == nullptr || ws_bytes < l.bytes)
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, l.bytes);
   if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
-  rc = band_start(L, threshold_of(p), nullptr, d_seeds, n, l.band, l.counts, st);
+  rc = band_start(L, threshold_of(d_p ? 0.0 : p), d_p, d_seeds, n, l.band, l.counts, st);
   if (rc != MPD_OK) return rc;
   rc = cnn_forward_run(l.counts, L / 8, n, d_params, l.pred, nullptr, nullptr, nullptr, l.cnn_ws, st);
   if (rc != MPD_OK) return rc;

@@ -81,19 +81,66 @@ def predict(counts, params, chunk: int = 16384):
     return torch.cat([b.cnn_forward(counts[a:a + chunk], params) for a in range(0, counts.shape[0], chunk)])
 
 
-def candidate_policies(pred: np.ndarray, k_first: int):
+def candidate_policies(pred: np.ndarray, k_first: int, wide: bool = False):
     """Binning policies to try: one bin at the default depth (no use of the
     prediction), and splits at prediction quantiles that give the samples
-    predicted shortest one step less and/or the longest one step more."""
+    predicted shortest one step less and/or the longest one step more.  With
+    `wide`, two-group splits take any pair of depths within two steps of
+    k_first and three-group splits also spread by two steps (for batches
+    whose decoding times spread widely, e.g. mixed noise strengths)."""
     qs = np.quantile(pred, [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
-    pol = [((), (k_first,))]
+    k = k_first
+    pairs = [(k - 1, k), (k, k + 1)]
+    triples = [(k - 1, k, k + 1)]
+    if wide:
+        pairs = [(a, c) for a in range(k - 2, k + 3) for c in range(a + 1, k + 3)]
+        triples += [(k - 2, k, k + 2), (k - 1, k, k + 2), (k - 2, k - 1, k + 1), (k - 1, k + 1, k + 2)]
+    pairs = [d for d in pairs if d[0] >= 1]
+    triples = [d for d in triples if d[0] >= 1]
+    pol = [((), (k,))]
     for a in qs:
-        pol.append(((float(a),), (k_first - 1, k_first)))
-        pol.append(((float(a),), (k_first, k_first + 1)))
+        for d in pairs:
+            pol.append(((float(a),), d))
     for i, a in enumerate(qs):
         for c in qs[i + 1:]:
-            pol.append(((float(a), float(c)), (k_first - 1, k_first, k_first + 1)))
+            for d in triples:
+                pol.append(((float(a), float(c)), d))
     return pol
+
+
+def plain_decode(L, p, seeds_t, T_max, out=None, workspace=None, stream=None):
+    """The decode without a predictor (FIFO): decode_batch for one p,
+    decode_mixed with the one class (L, n) for per-sample p."""
+    if isinstance(p, (float, int)):
+        return b.decode_batch(L, p, seeds_t, T_max, want_syndrome=out is None or out[2] is not None,
+                              workspace=workspace, out=out, stream=stream)
+    return b.decode_mixed([(L, seeds_t.numel())], p, seeds_t, T_max, want_syndrome=out is None or out[2] is not None,
+                          workspace=workspace, out=out, stream=stream)
+
+
+def best_fifo_depth(L, p, seeds_t, T_max: int = 4096, depths=range(2, 9), reps: int = 3, log=None):
+    """First-pass depth that minimises the plain decode's time on a tuning
+    batch (later passes at the current k_next).  Leaves the band schedule
+    as it found it; returns (depth, {depth: median seconds})."""
+    k0, kn = b.get_band_schedule(L)
+    times = {}
+    try:
+        for k in depths:
+            b.set_band_schedule(k, kn, L)
+            plain_decode(L, p, seeds_t, T_max)
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plain_decode(L, p, seeds_t, T_max)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            times[k] = float(np.median(ts))
+            if log:
+                log(f"fifo depth {k}: {times[k] * 1e3:.3f} ms")
+    finally:
+        b.set_band_schedule(k0, kn, L)
+    return min(times, key=times.get), times
 
 
 def time_policy(L, p, seeds_t, params, policy, T_max, reps: int = 3, ws=None, out=None):
@@ -109,9 +156,11 @@ def time_policy(L, p, seeds_t, params, policy, T_max, reps: int = 3, ws=None, ou
     return float(np.median(ts))
 
 
-def tune_policy(L, p, seeds_t, params, T_max: int = 4096, k_first: int | None = None, reps: int = 3, log=None):
+def tune_policy(L, p, seeds_t, params, T_max: int = 4096, k_first: int | None = None, reps: int = 3, log=None,
+                wide: bool = False):
     """Time every candidate policy on a tuning batch; returns (best policy,
-    its time, time of the single-bin policy, all timings)."""
+    its time, time of the single-bin policy, all timings).  p is a number or
+    per-sample values."""
     n = seeds_t.numel()
     if k_first is None:
         k_first = b.get_band_schedule(L)[0]
@@ -122,7 +171,7 @@ def tune_policy(L, p, seeds_t, params, T_max: int = 4096, k_first: int | None = 
     b.decode_learned(L, p, seeds_t, params, (), (k_first,), T_max, want_syndrome=False, workspace=ws, out=out)
     pred = out[3].cpu().numpy()
     res = []
-    for pol in candidate_policies(pred, k_first):
+    for pol in candidate_policies(pred, k_first, wide):
         t = time_policy(L, p, seeds_t, params, pol, T_max, reps, ws, out)
         res.append((t, pol))
         if log:

@@ -111,7 +111,7 @@ def test_counts_and_predictor_arguments(lib):
 def test_learned_decode_arguments(lib):
     d = ctypes.c_void_p(4096)
     P, I, I64, SZ, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
-    lib.mpd_decode_learned.argtypes = [I, D, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
+    lib.mpd_decode_learned.argtypes = [I, D, P, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
     lib.mpd_learned_workspace_bytes.argtypes = [I, I64]
     lib.mpd_learned_workspace_bytes.restype = SZ
     assert lib.mpd_learned_workspace_bytes(128, 10) == 0
@@ -121,8 +121,8 @@ def test_learned_decode_arguments(lib):
     depths = (ctypes.c_int * 3)(3, 4, 5)
     deep = (ctypes.c_int * 3)(3, 4, 16)
 
-    def call(L=256, p=0.01, n=8, T=64, nb=3, e=edges, k=depths, ws_bytes=1 << 40):
-        return lib.mpd_decode_learned(L, p, d, n, T, d, nb, e, k, d, d, None, None, d, ws_bytes, None)
+    def call(L=256, p=0.01, n=8, T=64, nb=3, e=edges, k=depths, ws_bytes=1 << 40, dp=None):
+        return lib.mpd_decode_learned(L, p, dp, d, n, T, d, nb, e, k, d, d, None, None, d, ws_bytes, None)
 
     assert call(L=128) == -1
     assert call(p=2.0) == -2
@@ -133,6 +133,8 @@ def test_learned_decode_arguments(lib):
     assert call(e=None) == -4 and call(k=None) == -4
     assert call(ws_bytes=1024) == -5
     assert call(n=0) == 0
+    # per-sample p: the scalar is not checked, the array's alignment is
+    assert call(p=2.0, dp=ctypes.c_void_p(4097)) == -4
 
 
 def test_mixed_workspace_is_per_band_class(lib):
