@@ -315,8 +315,8 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
     tune_set = [(torch.from_numpy(seeds(3, 201 + i, n).view(np.int64)).to(dev), P) for i in range(6)]
     policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
     louts = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
-              torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev),
-              torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
+              torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev), None)
+             for _ in range(W + K)]
 
     def learned(i, j, stream):
         b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lwss[j],
@@ -328,16 +328,17 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
     fifo_ws = [b.alloc_workspace(L_eval, n) for _ in runner.streams]
     runner.run(learned, range(W))
     el_fifo, el = alternate(runner, fifo, learned, W, K)
-    # inference time per batch, one stream (no overlap with other batches)
+    # the evaluation samples' predictions (outside the timed region; a
+    # one-group policy does not compute them) and the inference time per
+    # batch, one stream
     b.profile(True)
-    for i in range(W):
-        learned(i, 0, runner.streams[0])
+    preds = [b.cnn_forward(b.syndrome_counts(L_eval, P, batches[i]), params) for i in range(W, W + K)]
     torch.cuda.synchronize()
     b.profile(False)
     cnn_ms, cnn_n = b.profile_read("k_cnn_forward")
     same = all(torch.equal(outs[i][j], louts[i][j]) for i in range(W, W + K) for j in range(3))
     T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy()
-    pred = torch.cat([louts[i][3] for i in range(W, W + K)]).cpu().numpy()
+    pred = torch.cat(preds).cpu().numpy()
     y = np.log1p(T)
     mixed = learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval)
     return {"samples_per_s": K * n / el, "ms_per_step": el / K * 1e3, "ratio_vs_fifo": el_fifo / el,
@@ -349,7 +350,7 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
             "mixed_p": mixed}
 
 
-def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=8):
+def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=12):
     """Re-times the policies that were fastest one batch at a time, and the
     single-group policy, with the runner's batches in flight (the way the
     decode is used), on a set of tuning batches; returns (best policy,
@@ -357,7 +358,7 @@ def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=
     n = tune_set[0][0].numel()
     dev = tune_set[0][0].device
     outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None,
-             torch.empty(n, dtype=torch.float32, device=dev)) for _ in tune_set]
+             None) for _ in tune_set]
     cands = [res[0][1]] + [pol for _, pol in sorted(res[1:], key=lambda r: r[0])[:short]]
     times = {}
     for pol in cands:
@@ -405,8 +406,7 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
     fo = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
            torch.empty(n * b.syndrome_words(L_eval), dtype=torch.int32, device=dev)) for _ in range(W + K)]
     lo = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
-           torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev),
-           torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
+           torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev), None) for _ in range(W + K)]
     b.set_band_schedule(k_fifo, kn, L_eval)
     try:
         policy, _, _, res = learned.tune_policy(L_eval, tune_p, tune_s, params, T_MAX, k_first=k_fifo, reps=2,
@@ -430,7 +430,8 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
     same = all(torch.equal(fo[i][0], lo[i][0]) and torch.equal(fo[i][1], lo[i][1]) and
                torch.equal(fo[i][2], lo[i][2].reshape(-1)) for i in range(W, W + K))
     T = torch.cat([fo[i][0] for i in range(W, W + K)]).cpu().numpy()
-    pred = torch.cat([lo[i][3] for i in range(W, W + K)]).cpu().numpy()
+    pred = torch.cat([b.cnn_forward(b.syndrome_counts(L_eval, ps[i], bs[i]), params)
+                      for i in range(W, W + K)]).cpu().numpy()
     return {"p": "per sample U[0.005, 0.02]", "fifo_samples_per_s": K * n / el_fifo,
             "learned_samples_per_s": K * n / el_lrn, "ratio_vs_fifo": el_fifo / el_lrn,
             "fifo_first_pass_depth": k_fifo, "fifo_tuning_ms": {str(k): t * 1e3 for k, t in fifo_times.items()},

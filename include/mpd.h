@@ -441,9 +441,12 @@ int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d
  * schedule's k_next.  p applies to every sample unless d_p (per-sample [n]
  * double, 8-byte aligned) is given; with d_p the results equal those of
  * mpd_decode_mixed with the one class (L, n).  Outputs as mpd_decode_batch,
- * plus d_pred [n] if not NULL.  L: a multiple of 16 in [256, 16384].
- * Workspace: mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.
- * Synchronizes `stream`. */
+ * plus d_pred [n] if not NULL.  With one group and d_pred NULL the network
+ * is not evaluated: the call is the plain decode with first-pass depth
+ * h_depth[0] (the FIFO fallback; d_params is still checked).  L: a multiple
+ * of 16 in [256, 16384].  Workspace: mpd_learned_workspace_bytes(L, n)
+ * bytes, 256-byte aligned.  Synchronizes `stream`, except in the fallback
+ * when the band schedule's driver runs the later passes on the device. */
 size_t mpd_learned_workspace_bytes(int L, int64_t n);
 int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
                        const float *d_params, int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec,

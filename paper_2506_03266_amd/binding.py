@@ -587,11 +587,13 @@ def learned_workspace(L: int, n: int, device="cuda"):
 
 
 def decode_learned(L: int, p, seeds, params, edges, depths, T_max: int = 4096, want_syndrome: bool = True,
-                   workspace=None, out=None, stream=None):
+                   workspace=None, out=None, stream=None, want_pred: bool = True):
     """Decode with learned scheduling: samples with edges[b-1] <= pred < edges[b]
     start with a pass of depths[b] steps.  p is a number or per-sample values.
     Returns (T_dec, flags, syndrome, pred), results identical to decode_batch
-    (decode_mixed with the one class (L, n) for per-sample p)."""
+    (decode_mixed with the one class (L, n) for per-sample p).  Without
+    predictions (want_pred False, or out[3] None) a one-group policy skips
+    the network: the plain decode at depths[0]."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()
@@ -600,7 +602,7 @@ def decode_learned(L: int, p, seeds, params, edges, depths, T_max: int = 4096, w
         T = torch.empty(n, dtype=torch.int32, device=dev)
         F = torch.empty(n, dtype=torch.uint8, device=dev)
         S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
-        pred = torch.empty(n, dtype=torch.float32, device=dev)
+        pred = torch.empty(n, dtype=torch.float32, device=dev) if want_pred else None
     else:
         T, F, S, pred = out
     he = np.ascontiguousarray(edges, dtype=np.float32)

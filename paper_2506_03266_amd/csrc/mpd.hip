@@ -1530,6 +1530,17 @@ int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_see
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, l.bytes);
   if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
+  if (n_bins == 1 && d_pred == nullptr) {
+    // One group and no predictions asked for: nothing would read the
+    // network's output, so this is the plain decode (FIFO) at the group's
+    // first-pass depth, without inference.
+    BandRun r;
+    rc = band_setup(r, L, threshold_of(d_p ? 0.0 : p), d_p, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome,
+                    d_workspace, st);
+    if (rc != MPD_OK) return rc;
+    r.fp.k[0] = h_depth[0];
+    return band_passes(&r, 1);
+  }
   rc = band_start(L, threshold_of(d_p ? 0.0 : p), d_p, d_seeds, n, l.band, l.counts, st);
   if (rc != MPD_OK) return rc;
   rc = cnn_forward_run(l.counts, L / 8, n, d_params, l.pred, nullptr, nullptr, nullptr, l.cnn_ws, st);
@@ -1738,6 +1749,42 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
   if (need > 0 && ((uintptr_t)d_workspace & 255u)) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
+  {
+    // A batch of one size: no fork onto the side streams, one decode on
+    // `stream` (the band workspace then starts at d_workspace).
+    int nz = 0, c1 = -1;
+    int64_t off1 = 0, syn1 = 0, o = 0, so = 0;
+    for (int c = 0; c < n_classes; ++c) {
+      if (h_count[c] > 0) {
+        ++nz;
+        c1 = c;
+        off1 = o;
+        syn1 = so;
+      }
+      o += h_count[c];
+      so += h_count[c] * (((int64_t)h_L[c] * h_L[c] + 31) / 32);
+    }
+    if (nz == 1) {
+      const int L = h_L[c1];
+      const int64_t cnt = h_count[c1];
+      uint32_t *syn = d_final_syndrome ? d_final_syndrome + syn1 : nullptr;
+      if (!resident_ok(L))
+        return decode_band(L, 0, d_p + off1, d_seeds + off1, cnt, T_max, d_T_dec + off1, d_flags + off1, syn,
+                           d_workspace, Rule(), st);
+      ResidentArgs a = {};
+      a.L = L;
+      a.n = cnt;
+      a.seeds = d_seeds + off1;
+      a.p_arr = d_p + off1;
+      a.links = nullptr;
+      a.T_max = T_max;
+      a.t_exact = -1;
+      a.T_dec = d_T_dec + off1;
+      a.flags = d_flags + off1;
+      a.syn = syn;
+      return launch_resident(a, st);
+    }
+  }
   SideStream *side = side_stream();
   if (side == nullptr) return fail_with(MPD_ERR_HIP, "could not create the side stream");
   // fork: resident classes on the side stream

@@ -86,15 +86,15 @@ def candidate_policies(pred: np.ndarray, k_first: int, wide: bool = False):
     prediction), and splits at prediction quantiles that give the samples
     predicted shortest one step less and/or the longest one step more.  With
     `wide`, two-group splits take any pair of depths within two steps of
-    k_first and three-group splits also spread by two steps (for batches
-    whose decoding times spread widely, e.g. mixed noise strengths)."""
+    k_first and three-group splits any three such depths (for batches whose
+    decoding times spread widely, e.g. mixed noise strengths)."""
     qs = np.quantile(pred, [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
     k = k_first
     pairs = [(k - 1, k), (k, k + 1)]
     triples = [(k - 1, k, k + 1)]
     if wide:
         pairs = [(a, c) for a in range(k - 2, k + 3) for c in range(a + 1, k + 3)]
-        triples += [(k - 2, k, k + 2), (k - 1, k, k + 2), (k - 2, k - 1, k + 1), (k - 1, k + 1, k + 2)]
+        triples = [(a, c, d) for a in range(k - 2, k + 3) for c in range(a + 1, k + 3) for d in range(c + 1, k + 3)]
     pairs = [d for d in pairs if d[0] >= 1]
     triples = [d for d in triples if d[0] >= 1]
     pol = [((), (k,))]
@@ -144,13 +144,18 @@ def best_fifo_depth(L, p, seeds_t, T_max: int = 4096, depths=range(2, 9), reps: 
 
 
 def time_policy(L, p, seeds_t, params, policy, T_max, reps: int = 3, ws=None, out=None):
-    """Median wall time (s) of decode_learned with this policy on a resident seed batch."""
+    """Median wall time (s) of decode_learned with this policy on a resident
+    seed batch, predictions not copied out (so that a one-group policy times
+    the FIFO fallback, which skips the network)."""
     edges, depths = policy
+    if out is not None:
+        out = (out[0], out[1], out[2], None)
     ts = []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b.decode_learned(L, p, seeds_t, params, edges, depths, T_max, want_syndrome=False, workspace=ws, out=out)
+        b.decode_learned(L, p, seeds_t, params, edges, depths, T_max, want_syndrome=False, workspace=ws, out=out,
+                         want_pred=False)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     return float(np.median(ts))

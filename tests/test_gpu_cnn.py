@@ -215,6 +215,24 @@ def test_learned_decode_per_sample_p(gpu, orc, policy):
     assert np.isfinite(pred.cpu().numpy()).all()
 
 
+@pytest.mark.parametrize("depth,per_sample", [(4, False), (1, False), (5, True)])
+def test_one_group_without_predictions_is_plain(gpu, depth, per_sample):
+    """A one-group policy with no predictions asked for skips the network
+    (the FIFO fallback) and returns the plain decode's results, also when
+    the schedule's first-pass depth differs from the group's."""
+    L, n = 256, 96
+    s = seeds(59, depth, n)
+    p = np.random.default_rng(59).uniform(0.005, 0.03, n) if per_sample else 0.02
+    params = torch.from_numpy(trained_like_params(13)).cuda()
+    if per_sample:
+        T0, F0, S0 = gpu.decode_mixed([(L, n)], p, s, 4096)
+    else:
+        T0, F0, S0 = gpu.decode_batch(L, p, s, 4096)
+    T1, F1, S1, pred = gpu.decode_learned(L, p, s, params, (), (depth,), 4096, want_pred=False)
+    assert pred is None
+    assert torch.equal(T0, T1) and torch.equal(F0, F1) and torch.equal(S0.reshape(-1), S1.reshape(-1))
+
+
 @pytest.fixture(scope="module")
 def trained(gpu):
     """The predictor as the learned schedule uses it: 200000 decoder-labelled
@@ -239,7 +257,8 @@ def test_learned_vs_fifo_L256(gpu, trained, capsys):
     """What the trained network gains (or loses) over plain FIFO batching at
     L = 256, p = 0.01 (4096 samples per batch), end to end (noise, inference,
     binning, decoding).  Picks the binning policy by timing on a tuning
-    batch, then times both on fresh batches.  Results must be identical; the
+    batch (a one-group policy is the FIFO fallback, without inference),
+    then times both on fresh batches.  Results must be identical; the
     measured ratio is reported, and the network must beat the best constant
     predictor of the training labels on the evaluation samples."""
     from paper_2506_03266_amd import learned
@@ -255,13 +274,14 @@ def test_learned_vs_fifo_L256(gpu, trained, capsys):
         return _time_batches([(x,) for x in batches], fn)
 
     t_fifo, o_fifo = run(lambda s: gpu.decode_batch(L, p, s, 4096, workspace=ws))
-    t_lrn, o_lrn = run(lambda s: gpu.decode_learned(L, p, s, params, policy[0], policy[1], 4096, workspace=lws))
+    t_lrn, o_lrn = run(lambda s: gpu.decode_learned(L, p, s, params, policy[0], policy[1], 4096, workspace=lws,
+                                                    want_pred=False))
     for a, c in zip(o_fifo, o_lrn):
         for x, y in zip(a[:3], c[:3]):
             assert torch.equal(x, y)
     T = torch.cat([o[0] for o in o_fifo]).double()
     y = torch.log1p(T)
-    pred = torch.cat([o[3] for o in o_lrn]).double()
+    pred = torch.cat([gpu.cnn_forward(gpu.syndrome_counts(L, p, s), params) for s in batches[1:]]).double()
     mse_net = float(((pred - y) ** 2).mean())
     mse_const = float(((float(target.double().mean()) - y) ** 2).mean())
     with capsys.disabled():
@@ -296,13 +316,14 @@ def test_learned_vs_fifo_mixed_p(gpu, trained, capsys):
         policy, _, _, _ = learned.tune_policy(L, tune_p, tune_s, params, k_first=k_fifo, reps=2, wide=True)
         t_fifo, o_fifo = _time_batches(batches, lambda s, p: gpu.decode_mixed([(L, n)], p, s, 4096, workspace=ws))
         t_lrn, o_lrn = _time_batches(batches, lambda s, p: gpu.decode_learned(L, p, s, params, policy[0],
-                                                                                 policy[1], 4096, workspace=lws))
+                                                                                 policy[1], 4096, workspace=lws,
+                                                                                 want_pred=False))
     finally:
         gpu.set_band_schedule(k0, kn, L)
     for a, c in zip(o_fifo, o_lrn):
         assert torch.equal(a[0], c[0]) and torch.equal(a[1], c[1]) and torch.equal(a[2], c[2].reshape(-1))
     T = torch.cat([o[0] for o in o_fifo]).cpu().numpy()
-    pred = torch.cat([o[3] for o in o_lrn]).cpu().numpy()
+    pred = torch.cat([gpu.cnn_forward(gpu.syndrome_counts(L, p, s), params) for s, p in batches[1:]]).cpu().numpy()
     rho = float(np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(T)))[0, 1])
     with capsys.disabled():
         print(f"\nlearned vs FIFO at L=256, p ~ U[0.005, 0.02]: fifo {n / t_fifo:.4g} samples/s (first pass "

@@ -239,6 +239,21 @@ def test_per_sample_p_matches_single_p(gpu):
         assert np.array_equal(_np(S1).reshape(-1), _np(S2))
 
 
+@pytest.mark.parametrize("L", [48, 256])
+def test_one_nonempty_class_among_empty_ones(gpu, orc, L):
+    """A mixed call whose samples are all of one size (other classes empty)
+    runs on the caller's stream without the side streams: outputs land at
+    that class's offsets and equal the oracle's."""
+    n = 40
+    s = seeds(49, L, n)
+    p = np.random.default_rng(L).uniform(0.003, 0.05, n)
+    classes = [(32, 0), (L, n), (512, 0)]
+    T, F, S = gpu.decode_mixed(classes, p, s, 512)
+    ref = orc.decode_seeds(L, p, s, 512, threads=8)
+    assert np.array_equal(_np(T), ref["T_dec"]) and np.array_equal(_np(F), ref["flags"])
+    assert np.array_equal(_np(S).view(np.uint32), ref["sigma_words"].reshape(-1))
+
+
 def test_autotune_keeps_results(gpu):
     """The autotuner picks a schedule for L; decoding with it is unchanged."""
     s = seeds(48, 0, 256)
