@@ -657,7 +657,8 @@ def desynchronized(args, b, seeds, torch, np):
 
 def learned_c5(args, b, seeds, torch, np, runner):
     """Configuration 5: plain vs learned scheduling at L = 256 (4096 samples)
-    and L = 1024 (1024 samples), p = 0.01, with one predictor trained at L = 256."""
+    and L = 1024 (1024 samples), p = 0.01, with one predictor trained at L = 256;
+    policies re-timed in flight, FIFO and learned timed in alternating rounds."""
     from paper_2506_03266_amd import learned
     dev = torch.device("cuda")
     K, W = args.steps, args.warmup
@@ -668,24 +669,27 @@ def learned_c5(args, b, seeds, torch, np, runner):
         batches = [torch.from_numpy(seeds(5, 100 + pidx, n, start=i * n).view(np.int64)).to(dev)
                    for i in range(W + K)]
         tune = torch.from_numpy(seeds(5, 200 + pidx, n).view(np.int64)).to(dev)
-        policy, _, _, _ = learned.tune_policy(Lc, P, tune, params, reps=2)
+        policy, _, _, tres = learned.tune_policy(Lc, P, tune, params, reps=2)
         wss = [b.alloc_workspace(Lc, n) for _ in range(S)]
         lwss = [b.learned_workspace(Lc, n) for _ in range(S)]
-        res = {}
-        for name in ("fifo", "learned"):
-            outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
-                     None, torch.empty(n, dtype=torch.float32, device=dev)) for _ in range(W + K)]
+        tune_set = [(torch.from_numpy(seeds(5, 200 + pidx, n, start=i * n).view(np.int64)).to(dev), P)
+                    for i in range(6)]
+        policy, _ = tune_in_flight(b, runner, Lc, tune_set, params, tres, lwss, torch)
+        outs = {name: [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+                        None, None) for _ in range(W + K)] for name in ("fifo", "learned")}
 
-            def fn(i, j, stream, name=name, outs=outs):
-                if name == "fifo":
-                    b.decode_batch(Lc, P, batches[i], T_MAX, want_syndrome=False, workspace=wss[j],
-                                   out=outs[i][:3], stream=stream)
-                else:
-                    b.decode_learned(Lc, P, batches[i], params, policy[0], policy[1], T_MAX, want_syndrome=False,
-                                     workspace=lwss[j], out=outs[i], stream=stream)
+        def fifo(i, j, stream):
+            b.decode_batch(Lc, P, batches[i], T_MAX, want_syndrome=False, workspace=wss[j],
+                           out=outs["fifo"][i][:3], stream=stream)
 
-            runner.run(fn, range(W))
-            res[name] = (runner.run(fn, range(W, W + K)), outs)
+        def lrn(i, j, stream):
+            b.decode_learned(Lc, P, batches[i], params, policy[0], policy[1], T_MAX, want_syndrome=False,
+                             workspace=lwss[j], out=outs["learned"][i], stream=stream)
+
+        runner.run(fifo, range(W))
+        runner.run(lrn, range(W))
+        el_fifo, el_lrn = alternate(runner, fifo, lrn, W, K)
+        res = {"fifo": (el_fifo, outs["fifo"]), "learned": (el_lrn, outs["learned"])}
         same = all(torch.equal(a[0], c[0]) and torch.equal(a[1], c[1])
                    for a, c in zip(res["fifo"][1][W:], res["learned"][1][W:]))
         print(json.dumps({"workload": f"config 5: L={Lc} p={P} {n} samples, plain vs learned scheduling",
