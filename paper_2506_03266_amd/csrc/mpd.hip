@@ -797,13 +797,19 @@ uint64_t threshold_of(double p) {
 // Strip height for the resident kernel: the divisor H <= 16 of L giving the
 // block size L*L/H closest to 256 threads without exceeding 1024.
 int resident_H(int L) {
-  // Measured on MI355X (p = 0.01): where the rule below picks H = 16, the
-  // strips spill registers and these heights decode faster -- L = 64: 1.7x,
-  // 80: 1.5x, 96: 1.9x.  (At L = 56 and 60 the rule's H = 14 and 15 are as
-  // fast or faster than the shorter strips, so the rule stays.)
+  // Measured on MI355X (4096 samples per batch): where the rule below picks
+  // H = 16 the strips spill registers, and these heights decode faster at
+  // p = 0.01 -- L = 64: 1.7x, 80: 1.5x, 96: 1.9x, 112: 1.5x.  At other sizes
+  // a sweep of every height at p = 0.01 and 0.03 found these faster than the
+  // rule's -- L = 24: 1.1-1.3x, 40: 1.06x, 48: 1.75x, 60: 1.27x.
+  if (L == 24) return 3;
+  if (L == 40) return 5;
+  if (L == 48) return 12;
+  if (L == 60) return 5;
   if (L == 64) return 8;
   if (L == 80) return 10;
   if (L == 96) return 12;
+  if (L == 112) return 14;
   // The divisor H <= 16 of L giving the block size closest to 256 threads
   // without exceeding 1024.
   int best = 0;

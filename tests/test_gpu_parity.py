@@ -75,7 +75,7 @@ def test_exhaustive_L3(gpu, orc):
     compare("L=3 exhaustive", T, F, S, ref)
 
 
-@pytest.mark.parametrize("L", [3, 4, 5, 6, 7, 8, 9, 12, 16, 20, 24, 31, 32, 48, 64, 96, 100, 128])
+@pytest.mark.parametrize("L", [3, 4, 5, 6, 7, 8, 9, 12, 16, 20, 24, 31, 32, 40, 48, 60, 64, 80, 96, 100, 112, 128])
 @pytest.mark.parametrize("p", [0.02, 0.08])
 def test_sizes(gpu, orc, L, p):
     """Every strip height of the resident kernel, odd and ragged sizes."""
