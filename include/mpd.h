@@ -350,7 +350,9 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
  * sample); larger classes run the band path, each on a library-owned stream
  * with its own part of the workspace, their passes in lockstep (one host wait
  * per round of passes); the call returns after all of them have been joined
- * into `stream`.  Every p in [0, 1]; errors as mpd_decode_batch. */
+ * into `stream`.  When only one class has samples, its decode runs on
+ * `stream` itself (no side streams).  Every p in [0, 1]; errors as
+ * mpd_decode_batch. */
 size_t mpd_mixed_workspace_bytes(int n_classes, const int32_t *h_L, const int64_t *h_count);
 int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, const double *d_p,
                      const uint64_t *d_seeds, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
