@@ -173,7 +173,9 @@ __device__ __forceinline__ void load_biases(const float *__restrict__ P, float *
 // side).  CIN1: single-channel input [..]; otherwise [..][16].  Outputs go
 // to out[(y + o) S_out + x + o][16] (o = out_off); LAST folds them into the
 // pooling state instead, with global position ((oy + y) mod M, (ox + x) mod M).
-template <bool CIN1, bool LAST, class G>
+// MONO: a lane meets its global positions in increasing order, so only a
+// strictly larger value can replace its running maximum (no tie test).
+template <bool CIN1, bool LAST, class G, bool MONO = false>
 __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint16_t *__restrict__ out, const G &geo,
                                            const bf16x8 *A, const float *__restrict__ b, int M, int oy, int ox,
                                            Pool &pool) {
@@ -231,7 +233,15 @@ __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint
     } else {
       const int gi = ((oy + y) % M) * M + (ox + x) % M;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) keep_max(v[r], gi, pool.best[r], pool.idx[r]);
+      for (int r = 0; r < 4; ++r) {
+        if (MONO) {
+          const bool gt = v[r] > pool.best[r];
+          pool.best[r] = gt ? v[r] : pool.best[r];
+          pool.idx[r] = gt ? gi : pool.idx[r];
+        } else {
+          keep_max(v[r], gi, pool.best[r], pool.idx[r]);
+        }
+      }
     }
   };
   // Spare lanes (past the last position) repeat the last position and store nothing.
@@ -397,7 +407,7 @@ __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4)
     fill_border(bufA, M);
     if (a.store) store_interior(bufA, a.store + ((size_t)2 * a.n + s) * act, M);
     __syncthreads();
-    conv_layer<false, true>(bufA, nullptr, geol, Wc.A, bias_s + 3 * CH, M, 0, 0, pool);
+    conv_layer<false, true, GeoL, true>(bufA, nullptr, geol, Wc.A, bias_s + 3 * CH, M, 0, 0, pool);
     Wc = Wn;
     float best;
     int bi;
