@@ -19,4 +19,7 @@ from .oracle import (  # noqa: F401
     ring_threshold,
     async_run,
     async_decode_seeds,
+    set_reading,
+    get_reading,
+    decide,
 )

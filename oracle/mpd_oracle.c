@@ -223,6 +223,42 @@ typedef struct {
 static const int DIR_S[4] = {+1, -1, +1, -1};
 static const int DIR_A[4] = {1, 1, 2, 2};
 
+/* Alternative readings of the garbled or ambiguous passages, for the
+ * comparison with the paper's printed threshold and slope only (a script
+ * beside this file tabulates them).  0, the default, is the reading R1-R5
+ * above, which every decoder entry point and every test uses.  Bits:
+ *   ORC_READ_LITERAL_SIGN  f^a = sgn(m^{-a} - m^{+a}) with an absent message
+ *                          taken as the value 0 (instead of R3's +infinity)
+ *   ORC_READ_LITERAL_KEY   argmin' minimises the number m + s a/(D+1) itself
+ *                          (eq. (degbreak) as printed) instead of R5's
+ *                          messages-first order
+ *   ORC_READ_TIE_MOVES     an anyon whose two registers on the chosen axis
+ *                          are equal still moves toward the source of the
+ *                          chosen register (instead of sgn(0) = 0)
+ *   ORC_READ_TIE_MIRROR    ties between equal messages in the order
+ *                          +y < +x < -x < -y (R5 mirrored)
+ *   ORC_READ_LINE_SITE     C^{(a)} is the single site r - s a-hat (the
+ *                          1D rule applied per direction, no sideways spread)
+ *   ORC_READ_LINE_BALL     C^{(a)} is the whole unit infinity-ball around
+ *                          r - s a-hat (the printed constraint dropped)
+ * Set once, before decoding; it is process-wide. */
+#define ORC_READ_LITERAL_SIGN 1
+#define ORC_READ_LITERAL_KEY 2
+#define ORC_READ_TIE_MOVES 4
+#define ORC_READ_TIE_MIRROR 8
+#define ORC_READ_LINE_SITE 16
+#define ORC_READ_LINE_BALL 32
+#define ORC_READ_ALL 63
+static int g_reading = 0;
+
+int orc_set_reading(int r) {
+  if (r < 0 || (r & ~ORC_READ_ALL) || ((r & ORC_READ_LINE_SITE) && (r & ORC_READ_LINE_BALL))) return ORC_EBADARG;
+  g_reading = r;
+  return ORC_OK;
+}
+
+int orc_get_reading(void) { return g_reading; }
+
 static int wrap(int c, int L) {
   c %= L;
   return c < 0 ? c + L : c;
@@ -302,8 +338,13 @@ static int32_t orc_register_value(const orc_state *st, int32_t *const m[4], cons
     if (cxp < 0 || cxp >= L || cyp < 0 || cyp >= L) return 0;       /* empty line */
     if (orc_in_B(st, cxp)) anyon = 1;                                /* B sources x-messages */
   }
-  for (int k = -1; k <= 1; ++k) {
-    int qx = cxp + k * bx, qy = cyp + k * by;
+  /* the line C^{(a)}_{r - s a}: offsets k b-hat, |k| <= 1 (R1); the
+   * alternative readings take the centre alone or the whole unit ball */
+  int kmax = (g_reading & ORC_READ_LINE_SITE) ? 0 : 1;
+  int jmax = (g_reading & ORC_READ_LINE_BALL) ? 1 : 0;
+  for (int j = -jmax; j <= jmax; ++j)
+  for (int k = -kmax; k <= kmax; ++k) {
+    int qx = cxp + k * bx + j * ax, qy = cyp + k * by + j * ay;
     if (st->open && (qx < 0 || qx >= L || qy < 0 || qy >= L)) continue;   /* clipped */
     qx = wrap(qx, L);
     qy = wrap(qy, L);
@@ -335,6 +376,7 @@ static void orc_message_update(orc_state *st) {
 
 /* sgn(mm - mp) with an absent message (0) read as +infinity (R3). */
 static int orc_force(int32_t mp, int32_t mm) {
+  if (g_reading & ORC_READ_LITERAL_SIGN) return (mm > mp) - (mm < mp);
   if (mp == 0 && mm == 0) return 0;
   if (mp == 0) return -1;   /* only m^{-a}: source on the +a side */
   if (mm == 0) return +1;   /* only m^{+a}: source on the -a side */
@@ -375,15 +417,47 @@ static void orc_site_force(const orc_state *st, int32_t *const m[4], const int8_
     /* argmin' of eq. (degbreak): the offset s a / (D+1) only breaks ties
      * between equal messages (R5): smallest m first, then smallest s*a. */
     int32_t off = DIR_S[d] * DIR_A[d];
-    if (best < 0 || mv < bestm || (mv == bestm && off < bestoff)) {
+    if (g_reading & ORC_READ_TIE_MIRROR) off = -off;
+    int better;
+    if (g_reading & ORC_READ_LITERAL_KEY)   /* m + s a/3 < m' + s' a'/3, in thirds */
+      better = best < 0 || 3 * mv + off < 3 * bestm + bestoff;
+    else
+      better = best < 0 || mv < bestm || (mv == bestm && off < bestoff);
+    if (better) {
       best = d;
       bestm = mv;
       bestoff = off;
     }
   }
   if (best < 0) return;                         /* M_r empty: no feedback */
-  if (DIR_A[best] == 1) *fx = (int8_t)orc_force(m[0][i], m[1][i]);
-  else *fy = (int8_t)orc_force(m[2][i], m[3][i]);
+  int f = DIR_A[best] == 1 ? orc_force(m[0][i], m[1][i]) : orc_force(m[2][i], m[3][i]);
+  /* on an exact tie along the chosen axis: follow the chosen register
+   * (source on the -s side, so the anyon moves along -s, i.e. f = s) */
+  if (f == 0 && (g_reading & ORC_READ_TIE_MOVES)) f = DIR_S[best];
+  if (DIR_A[best] == 1) *fx = (int8_t)f;
+  else *fy = (int8_t)f;
+}
+
+/* The decision of a single site from its four registers (order +x, -x, +y,
+ * -y) and its syndrome: the forces (f^x, f^y) of eq. (ddfeedback)'s
+ * exponent, as the feedback of a plain-rule step computes them. */
+int orc_decide(const int32_t m_in[4], int anyon, int *fx, int *fy) {
+  orc_state st;
+  memset(&st, 0, sizeof(st));
+  st.L = 1;
+  st.n = 1;
+  int32_t reg[4];
+  int32_t *m[4];
+  for (int d = 0; d < 4; ++d) {
+    if (m_in[d] < 0) return ORC_EBADARG;
+    reg[d] = m_in[d];
+    m[d] = &reg[d];
+  }
+  int8_t sigma = anyon ? -1 : +1, a = 0, b = 0;
+  orc_site_force(&st, m, &sigma, 0, &a, &b);
+  *fx = a;
+  *fy = b;
+  return ORC_OK;
 }
 
 /* Feedback F^{(D)}: per-site force f^a_r from argmin' over the nonzero

@@ -84,6 +84,12 @@ def _load():
     lib.orc_uncoord_run.restype = I
     lib.orc_uncoord_decode_seeds.argtypes = [I, I, I] + lib.orc_async_decode_seeds.argtypes[2:]
     lib.orc_uncoord_decode_seeds.restype = I
+    lib.orc_set_reading.argtypes = [I]
+    lib.orc_set_reading.restype = I
+    lib.orc_get_reading.argtypes = []
+    lib.orc_get_reading.restype = I
+    lib.orc_decide.argtypes = [P, I, P, P]
+    lib.orc_decide.restype = I
     _lib = lib
     return lib
 
@@ -317,3 +323,35 @@ def async_decode_seeds(L: int, p, seeds, rho: float = 1.0, S_max: int = 100000, 
     if want_sigma:
         out["sigma_words"] = words
     return out
+
+
+# Alternative readings of the garbled or ambiguous passages (bits of
+# ``set_reading``); 0 is the reading every test pins (R1-R5 of the C file).
+READ_LITERAL_SIGN = 1   # f^a = sgn(m^{-a} - m^{+a}) with an absent message as 0
+READ_LITERAL_KEY = 2    # argmin' minimises m + s a/(D+1) as printed (eq. (degbreak))
+READ_TIE_MOVES = 4      # move toward the chosen register even on an axis tie
+READ_TIE_MIRROR = 8     # ties in the order +y < +x < -x < -y
+READ_LINE_SITE = 16     # C^{(a)} = the single site r - s a-hat
+READ_LINE_BALL = 32     # C^{(a)} = the unit infinity-ball around r - s a-hat
+
+
+def set_reading(bits: int) -> None:
+    """Select an alternative reading for every later decode (process-wide)."""
+    _check(_load().orc_set_reading(int(bits)), "set_reading")
+
+
+def get_reading() -> int:
+    return int(_load().orc_get_reading())
+
+
+def decide(m, anyon: bool):
+    """Forces (f^x, f^y) of one site from its registers m = (m^{+x}, m^{-x},
+    m^{+y}, m^{-y}) and its syndrome, as the plain-rule feedback computes them
+    (argmin' of eq. (degbreak), force of Def. "message passing automaton,
+    general dimensions").  An anyon moves along +a for f^a = -1 and along -a
+    for f^a = +1."""
+    reg = np.ascontiguousarray(np.asarray(m, dtype=np.int32).reshape(4))
+    fx = ctypes.c_int(0)
+    fy = ctypes.c_int(0)
+    _check(_load().orc_decide(_ptr(reg), 1 if anyon else 0, ctypes.byref(fx), ctypes.byref(fy)), "decide")
+    return int(fx.value), int(fy.value)
