@@ -110,14 +110,17 @@ size_t mpd_workspace_bytes(int L, int64_t n);
  *                      (may be NULL when that size is 0)
  * Supported L: 3 <= L <= 128 when a strip height H <= 16 divides L with
  * L*L/H <= 1024 threads (every L <= 32, and e.g. 48, 64, 96, 100, 128), and
- * multiples of 16 from 256 to 16384. */
+ * multiples of 16 from 256 to 16384 (at most 65535 samples per call for
+ * these, else MPD_ERR_N). */
 int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max,
                      int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
                      void *d_workspace, size_t ws_bytes, void *stream);
 
 /* Decode n explicit error patterns (hand-built cases, exhaustive checks).
  *   d_links            [n][ceil(2*L*L/32)] uint32 link bits (see above)
- * Other arguments as mpd_decode_batch.  Supported L: 3 <= L <= 128. */
+ * Other arguments as mpd_decode_batch.  Supported L: as mpd_decode_batch;
+ * the workspace is needed from L = 256 on (mpd_workspace_bytes(L, n)),
+ * where the decode runs the same passes as a seeded one. */
 int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec,
                       uint8_t *d_flags, uint32_t *d_final_syndrome, void *d_workspace,
                       size_t ws_bytes, void *stream);
@@ -132,7 +135,7 @@ int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int3
  *                      bit 3 Wy(C), winding parities of the error and of the
  *                      correction applied so far, across the cuts x = L-1 and
  *                      y = L-1
- * Supported L: 3 <= L <= 128. */
+ * Supported L: 3 <= L <= 128 (mpd_run_steps_ws takes every size). */
 int mpd_run_steps(int L, const uint32_t *d_links, int64_t n, int t_exact, int16_t *d_m_out,
                   uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
 
@@ -204,6 +207,31 @@ int mpd_run_steps_open(int L, const uint32_t *d_links, int64_t n, int t_exact, i
 int mpd_run_steps_from(int L, const int16_t *d_m_in, const uint32_t *d_sigma_in, const uint8_t *d_wind_in, int64_t n,
                        int t_start, int t_exact, int m_max, int u, const uint64_t *d_move_seeds, int16_t *d_m_out,
                        uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream);
+
+/* State export and resume for every supported lattice size (checkpoint /
+ * resume, parity debugging), Def. "synchronous automaton decoder": exactly
+ * t_exact decoder steps, no early exit.
+ *   mpd_run_steps_ws       from explicit errors d_links, as
+ *                          mpd_run_steps_rule (m_max, u, move seeds);
+ *   mpd_run_steps_from_ws  from a state exported after t_start steps, as
+ *                          mpd_run_steps_from.
+ * Outputs (d_m_out [n][4][L*L] int16 distance form, d_sigma_out syndrome
+ * bits, d_wind_out winding bits) as mpd_run_steps.  Up to L = 128 these are
+ * the resident calls and the workspace is ignored; for multiples of 16 from
+ * 256 to 16384 the band path runs passes of up to k_first steps over all
+ * samples (no compaction) in a workspace of mpd_workspace_bytes(L, n)
+ * bytes (256-byte aligned), then converts its state (at most 65535 samples
+ * per call, else MPD_ERR_N).  Results equal the resident kernel's and the
+ * paper's rule step by step; on the band path the inputs and outputs of the
+ * resume form must not overlap.  Errors as mpd_run_steps_rule /
+ * mpd_run_steps_from plus MPD_ERR_WORKSPACE. */
+int mpd_run_steps_ws(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact, int m_max,
+                     int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *d_workspace,
+                     size_t ws_bytes, void *stream);
+int mpd_run_steps_from_ws(int L, const int16_t *d_m_in, const uint32_t *d_sigma_in, const uint8_t *d_wind_in,
+                          int64_t n, int t_start, int t_exact, int m_max, int u, const uint64_t *d_move_seeds,
+                          int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *d_workspace,
+                          size_t ws_bytes, void *stream);
 
 /* Marching-soldiers desynchronization (Sec. "Desynchronization and
  * Lindbladian dynamics": Def. "marching soldiers desynchronization", Def.

@@ -97,6 +97,10 @@ def lib():
     L.mpd_decode_learned.argtypes = [I, D, P, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
     L.mpd_decode_learned.restype = I
     L.mpd_run_steps_from.argtypes = [I, P, P, P, I64, I, I, I, I, P, P, P, P, P]
+    L.mpd_run_steps_ws.argtypes = [I, P, P, I64, I, I, I, P, P, P, P, SZ, P]
+    L.mpd_run_steps_ws.restype = I
+    L.mpd_run_steps_from_ws.argtypes = [I, P, P, P, I64, I, I, I, I, P, P, P, P, P, SZ, P]
+    L.mpd_run_steps_from_ws.restype = I
     L.mpd_run_steps_from.restype = I
     L.mpd_decode_async.argtypes = [I, D, P, I64, D, I, P, P, P, P, P, P]
     L.mpd_decode_async.restype = I
@@ -220,6 +224,40 @@ def run_steps(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int =
                                       _ptr(S), _ptr(W), _stream_ptr(stream))
         _check(rc, "mpd_run_steps_rule")
     return M, S, W
+
+
+def run_steps_ws(L: int, links, t_exact: int, stream=None, m_max: int = 0, u: int = 0, move_seeds=None,
+                 workspace=None):
+    """mpd_run_steps_ws: exactly t_exact steps from explicit errors at any
+    supported L (the band path from L = 256 on); returns (m int16[n,4,L,L],
+    syndrome int32[n,W], wind uint8[n])."""
+    dev = torch.device("cuda")
+    links = _links_tensor(L, links, dev)
+    n = links.shape[0]
+    M = torch.empty((n, 4, L, L), dtype=torch.int16, device=dev)
+    S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev)
+    W = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = alloc_workspace(L, n) if workspace is None else workspace
+    ms = None if move_seeds is None else _seeds_tensor(move_seeds, dev)
+    rc = lib().mpd_run_steps_ws(L, _ptr(links), _ptr(ms), n, int(t_exact), int(m_max), int(u), _ptr(M), _ptr(S),
+                                _ptr(W), _ptr(ws), ws.numel(), _stream_ptr(stream))
+    _check(rc, "mpd_run_steps_ws")
+    return M, S, W
+
+
+def run_steps_from_ws(L: int, M, S, W, t_start: int, t_exact: int, stream=None, m_max: int = 0, u: int = 0,
+                      move_seeds=None, workspace=None, out=None):
+    """mpd_run_steps_from_ws: resume exported states at any supported L."""
+    dev = torch.device("cuda")
+    n = M.shape[0]
+    Mo, So, Wo = (torch.empty_like(M), torch.empty_like(S), torch.empty_like(W)) if out is None else out
+    ws = alloc_workspace(L, n) if workspace is None else workspace
+    ms = None if move_seeds is None else _seeds_tensor(move_seeds, dev)
+    rc = lib().mpd_run_steps_from_ws(L, _ptr(M), _ptr(S), _ptr(W), n, int(t_start), int(t_exact), int(m_max),
+                                     int(u), _ptr(ms), _ptr(Mo), _ptr(So), _ptr(Wo), _ptr(ws), ws.numel(),
+                                     _stream_ptr(stream))
+    _check(rc, "mpd_run_steps_from_ws")
+    return Mo, So, Wo
 
 
 ASYNC_SLOT_LIMIT = 65000

@@ -270,6 +270,7 @@ constexpr int BAND_NW_SMALL = 4;           // waves per workgroup for passes tha
 constexpr int BAND_RX = 128;               // region columns (2 per lane)
 constexpr int BAND_RY = BAND_NW * BAND_H;  // region rows (full-size regions)
 constexpr int TILE_H = BAND_H;             // rows per syndrome word pair in HBM
+constexpr int BAND_MAX_N = 65535;          // samples per band-path pass (grid y dimension)
 
 struct BandArgs {
   int L;
@@ -757,6 +758,120 @@ __global__ void k_band_export(int L, int64_t n, const uint8_t *status, const uin
 }
 
 // ---------------------------------------------------------------------------
+// Band path: explicit errors and the full state (checkpoint / resume)
+// ---------------------------------------------------------------------------
+
+// Initial syndrome and error winding of explicit error patterns in the band
+// layout (instead of k_band_noise).  One thread per sample, 16-row strip j
+// and column pair q.  Link id 2i + dir of site i = y L + x puts the four
+// links of the pair (x-link 2q, y-link 2q, x-link 2q+1, y-link 2q+1) of row y
+// in the nibble (y L/2 + q) of the sample's link words.
+__global__ void k_band_links(int L, int64_t n, const uint32_t *links, uint2 *Sout, uint32_t *wind) {
+  const int P = L / 2, NJ = L / TILE_H;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * NJ * P) return;
+  const int64_t sample = g / ((int64_t)NJ * P);
+  const int j = (int)((g / P) % NJ), q = (int)(g % P);
+  const uint32_t *w = links + sample * ((int64_t)L * L / 16);
+  auto nib = [&](int y, int qq) -> uint32_t {
+    const size_t idx = (size_t)y * P + qq;
+    return (w[idx >> 3] >> ((idx & 7u) * 4u)) & 0xFu;
+  };
+  const int ql = q == 0 ? P - 1 : q - 1;
+  uint32_t s0 = 0u, s1 = 0u, wd = 0u;
+  for (int h = 0; h < TILE_H; ++h) {
+    const int y = j * TILE_H + h, yd = y == 0 ? L - 1 : y - 1;
+    const uint32_t c = nib(y, q), l = nib(y, ql), d = nib(yd, q);
+    // sigma = ex ^ ex(left) ^ ey ^ ey(below)
+    s0 |= (((c >> 0) ^ (l >> 2) ^ (c >> 1) ^ (d >> 1)) & 1u) << h;
+    s1 |= (((c >> 2) ^ (c >> 0) ^ (c >> 3) ^ (d >> 3)) & 1u) << h;
+    if (q == P - 1) wd ^= (c >> 2) & 1u;                            // x-links leaving column L-1
+    if (y == L - 1) wd ^= (((c >> 1) ^ (c >> 3)) & 1u) << 1;        // y-links leaving row L-1
+  }
+  Sout[((size_t)sample * NJ + j) * P + q] = make_uint2(s0, s1);
+  if (wd) atomicXor(&wind[sample], wd);
+}
+
+// Steps done after a pass of k steps with no early exit (every sample runs
+// to t_end); the per-step anyon bits are not needed.
+__global__ void k_band_advance(int64_t n, int k, int t_end, int32_t *t_done, uint32_t *alive) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  t_done[s] = min(t_done[s] + k, t_end);
+  alive[s] = 0u;
+}
+
+// Exported state (registers [n][4][L L] int16 in distance form, syndrome
+// bits, winding bits) after t0 steps -> band layout with emission times
+// e = 3 t0 - m + 1 (0 for m = 0).  One thread per sample, strip and pair.
+__global__ void k_band_state_import(int L, int64_t n, int t0, const int16_t *m_in, const uint32_t *syn_in,
+                                    const uint8_t *wind_in, uint4 *E, uint2 *S, uint32_t *wind, int32_t *t_done) {
+  const int P = L / 2, NJ = L / TILE_H;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * NJ * P) return;
+  const int64_t sample = g / ((int64_t)NJ * P);
+  const int j = (int)((g / P) % NJ), q = (int)(g % P);
+  const int64_t n2 = (int64_t)L * L, nw = n2 / 32;
+  const int16_t *mi = m_in + sample * 4 * n2;
+  const uint32_t s0t = 3u * (uint32_t)t0;
+  auto em = [&](int d, int64_t i) -> uint32_t {
+    const uint32_t m = (uint32_t)(uint16_t)mi[d * n2 + i];
+    return m != 0u ? ((s0t - m + 1u) & 0xFFFFu) : 0u;
+  };
+  uint32_t s0 = 0u, s1 = 0u;
+  for (int h = 0; h < TILE_H; ++h) {
+    const int y = j * TILE_H + h;
+    const int64_t i = (int64_t)y * L + 2 * q;
+    E[(size_t)sample * L * P + (size_t)y * P + q] =
+        make_uint4(em(0, i) | em(1, i) << 16, em(2, i) | em(3, i) << 16, em(0, i + 1) | em(1, i + 1) << 16,
+                   em(2, i + 1) | em(3, i + 1) << 16);
+    const uint32_t word = syn_in[sample * nw + (i >> 5)];
+    s0 |= ((word >> (i & 31)) & 1u) << h;
+    s1 |= ((word >> ((i + 1) & 31)) & 1u) << h;
+  }
+  S[((size_t)sample * NJ + j) * P + q] = make_uint2(s0, s1);
+  if (j == 0 && q == 0) {
+    wind[sample] = wind_in[sample] & 15u;
+    t_done[sample] = t0;
+  }
+}
+
+// Band state after `steps` steps -> exported form: registers in distance
+// form m = s - e + 1 for live emission times (s = 3 steps; none before the
+// first step), syndrome bits row-major, winding bits.  Grid: one thread per
+// sample and syndrome word.
+__global__ void k_band_state_export(int L, int64_t n, int steps, int m_max, const uint4 *E, const uint2 *S,
+                                    const uint32_t *wind, int16_t *m_out, uint32_t *syn_out, uint8_t *wind_out) {
+  const int P = L / 2, NJ = L / TILE_H;
+  const int64_t n2 = (int64_t)L * L, nw = n2 / 32;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * nw) return;
+  const int64_t sample = g / nw, wd = g % nw;
+  const uint32_t snow = 3u * (uint32_t)steps;
+  const uint32_t live = live_threshold(snow, m_max);
+  int16_t *mo = m_out + sample * 4 * n2;
+  uint32_t word = 0u;
+  for (int bt = 0; bt < 32; bt += 2) {
+    const int64_t i = wd * 32 + bt;
+    const int y = (int)(i / L), x = (int)(i % L), q = x >> 1;
+    const uint2 sv = S[((size_t)sample * NJ + y / TILE_H) * P + q];
+    word |= ((sv.x >> (y % TILE_H)) & 1u) << bt;
+    word |= ((sv.y >> (y % TILE_H)) & 1u) << (bt + 1);
+    uint4 e = make_uint4(0u, 0u, 0u, 0u);
+    if (steps > 0) e = E[(size_t)sample * L * P + (size_t)y * P + q];
+    const uint32_t v[8] = {e.x & 0xFFFFu, e.x >> 16, e.y & 0xFFFFu, e.y >> 16,
+                           e.z & 0xFFFFu, e.z >> 16, e.w & 0xFFFFu, e.w >> 16};
+    for (int c = 0; c < 2; ++c)
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t ev = v[4 * c + d];
+        mo[d * n2 + i + c] = (int16_t)(steps > 0 && ev >= live ? (snow - ev + 1u) : 0u);
+      }
+  }
+  syn_out[sample * nw + wd] = word;
+  if (wd == 0) wind_out[sample] = (uint8_t)(wind[sample] & 15u);
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -958,10 +1073,17 @@ NoiseShape noise_shape(int L) {
 
 // Noise, syndrome and bookkeeping of a band-path batch (before the passes).
 int band_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, const BandWorkspace &w,
-               uint8_t *d_counts, hipStream_t stream, int open = 0) {
+               uint8_t *d_counts, hipStream_t stream, int open = 0, const uint32_t *d_links = nullptr) {
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
                      w.status, w.t_done, w.active[0], &w.count[2]);
   HIP_TRY(hipGetLastError());
+  if (d_links != nullptr) {  // explicit error patterns instead of seeded noise
+    const int64_t threads = n * (L / TILE_H) * (L / 2);
+    hipLaunchKernelGGL(k_band_links, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, L, n, d_links,
+                       w.S[0], w.wind);
+    HIP_TRY(hipGetLastError());
+    return MPD_OK;
+  }
   const NoiseShape g = noise_shape(L);
   ProfScope ps("k_band_noise", stream);
   if (open)
@@ -1266,9 +1388,10 @@ int band_passes(BandRun *runs, int nr) {
   return MPD_OK;
 }
 
-// Noise and first-pass setup of a plain (single-group) band batch.
+// Noise (or explicit errors) and first-pass setup of a plain (single-group) band batch.
 int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
-               int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream) {
+               int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream,
+               const uint32_t *d_links = nullptr) {
   r.L = L;
   r.n = n;
   r.T_max = T_max;
@@ -1281,7 +1404,7 @@ int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_
   r.fp.list[0] = r.w.active[0];
   r.fp.count[0] = (int)n;
   r.fp.k[0] = schedule_for(L).k_first;
-  return band_start(L, thr, d_p, d_seeds, n, r.w, nullptr, stream, r.rule.open ? 1 : 0);
+  return band_start(L, thr, d_p, d_seeds, n, r.w, nullptr, stream, r.rule.open ? 1 : 0, d_links);
 }
 
 int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
@@ -1291,6 +1414,52 @@ int decode_band(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds,
   const int rc = band_setup(r, L, thr, d_p, d_seeds, n, T_max, d_T_dec, d_flags, d_syn, ws, stream);
   if (rc != MPD_OK) return rc;
   return band_passes(&r, 1);
+}
+
+// Exactly t_exact decoder steps from step t_start for every sample on the
+// band path (no early exit, no compaction): passes of up to k_first steps
+// over all samples, the state alternating between the two buffers.  The
+// initial state is in buffer 0; returns the buffer that holds the final one.
+int band_run_exact(int L, int64_t n, int t_start, int t_exact, const BandWorkspace &w, const Rule &rule,
+                   hipStream_t stream, int *final_buf) {
+  const int t_end = t_start + t_exact;
+  const int kf = schedule_for(L).k_first;
+  int cur = 0;
+  for (int t = t_start; t < t_end;) {
+    const int k = std::min(kf, t_end - t);
+    BandArgs ba;
+    const int nty = tile_geometry(L, k, BAND_RY, ba);
+    ba.T_max = t_end;
+    ba.t_done = w.t_done;
+    ba.active = w.active[0];
+    ba.Esrc = w.E[cur];
+    ba.Ssrc = w.S[cur];
+    ba.Edst = w.E[cur ^ 1];
+    ba.Sdst = w.S[cur ^ 1];
+    ba.alive = w.alive;
+    ba.wind = w.wind;
+    ba.zero_count = nullptr;
+    ba.m_max = rule.m_max;
+    ba.u = rule.u;
+    ba.seeds = rule.seeds;
+    {
+      ProfScope ps("k_band", stream);
+      const dim3 grid((unsigned)(ba.ntx * nty), (unsigned)n), blk(BAND_NW * 64);
+      const size_t lds = band_lds(BAND_NW);
+      if (rule.on())
+        hipLaunchKernelGGL((k_band<BAND_NW, BAND_RULE>), grid, blk, lds, stream, ba);
+      else
+        hipLaunchKernelGGL((k_band<BAND_NW, BAND_PLAIN>), grid, blk, lds, stream, ba);
+    }
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_band_advance, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, k, t_end,
+                       w.t_done, w.alive);
+    HIP_TRY(hipGetLastError());
+    cur ^= 1;
+    t += k;
+  }
+  *final_buf = cur;
+  return MPD_OK;
 }
 
 // Library-owned side streams (default priority, non-blocking) with
@@ -1455,6 +1624,7 @@ static int decode_seeded(int L, double p, const uint64_t *d_seeds, int64_t n, in
     a.u = rule.u;
     return launch_resident(a, st);
   }
+  if (n > BAND_MAX_N) return fail_with(MPD_ERR_N, "n=%lld: at most %d samples per band-path call", (long long)n, BAND_MAX_N);
   const size_t need = mpd_workspace_bytes(L, n);
   if (ws_bytes < need || d_workspace == nullptr)
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
@@ -1515,6 +1685,7 @@ int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_see
   int rc = check_common(L, n, T_max, d_T_dec, d_flags);
   if (rc) return rc;
   if (!tiled_ok(L)) return fail_with(MPD_ERR_L, "L=%d: learned scheduling needs a multiple of 16 in [256, 16384]", L);
+  if (n > BAND_MAX_N) return fail_with(MPD_ERR_N, "n=%lld: at most %d samples per band-path call", (long long)n, BAND_MAX_N);
   if (n_bins < 1 || n_bins > MAX_BINS) return fail_with(MPD_ERR_N, "n_bins=%d outside [1, %d]", n_bins, MAX_BINS);
   if (h_depth == nullptr || (n_bins > 1 && h_edges == nullptr)) return fail_with(MPD_ERR_PTR, "NULL policy");
   BinEdges e;
@@ -1743,6 +1914,8 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
   for (int c = 0; c < n_classes; ++c) {
     if (!resident_ok(h_L[c]) && !tiled_ok(h_L[c])) return fail_with(MPD_ERR_L, "class %d: L=%d unsupported", c, h_L[c]);
     if (h_count[c] < 0) return fail_with(MPD_ERR_N, "class %d: negative count", c);
+    if (!resident_ok(h_L[c]) && h_count[c] > BAND_MAX_N)
+      return fail_with(MPD_ERR_N, "class %d: at most %d samples of a band-path size", c, BAND_MAX_N);
     n += h_count[c];
   }
   int rc = check_common(4, n, T_max, d_T_dec, d_flags);
@@ -1885,12 +2058,119 @@ static int decode_links_rule(int L, const uint32_t *d_links, const uint64_t *d_m
   return launch_resident(a, (hipStream_t)stream);
 }
 
+static int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact,
+                          int m_max, int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out,
+                          void *stream, int open = 0);
+
 int mpd_decode_errors(int L, const uint32_t *d_links, int64_t n, int T_max, int32_t *d_T_dec, uint8_t *d_flags,
                       uint32_t *d_final_syndrome, void *d_workspace, size_t ws_bytes, void *stream) {
   g_last_error.clear();
-  (void)d_workspace;
-  (void)ws_bytes;
-  return decode_links_rule(L, d_links, nullptr, n, T_max, 0, 0, d_T_dec, d_flags, d_final_syndrome, stream);
+  if (resident_ok(L) || !tiled_ok(L))
+    return decode_links_rule(L, d_links, nullptr, n, T_max, 0, 0, d_T_dec, d_flags, d_final_syndrome, stream);
+  // the band path (L >= 256): the same passes as a seeded decode
+  int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (n == 0) return MPD_OK;
+  if (n > BAND_MAX_N) return fail_with(MPD_ERR_N, "n=%lld: at most %d samples per band-path call", (long long)n, BAND_MAX_N);
+  if (d_links == nullptr || ((uintptr_t)d_links & 3u)) return fail_with(MPD_ERR_PTR, "links NULL or misaligned");
+  if (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u))
+    return fail_with(MPD_ERR_PTR, "final_syndrome misaligned");
+  const size_t need = mpd_workspace_bytes(L, n);
+  if (ws_bytes < need || d_workspace == nullptr)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  BandRun r;
+  rc = band_setup(r, L, 0, nullptr, nullptr, n, T_max, d_T_dec, d_flags, d_final_syndrome, d_workspace,
+                  (hipStream_t)stream, d_links);
+  if (rc != MPD_OK) return rc;
+  return band_passes(&r, 1);
+}
+
+// Band-path state export and resume: exactly t_exact steps after t_start,
+// from explicit errors (m_in == nullptr) or from an exported state.
+static int band_steps_export(int L, const uint32_t *d_links, const int16_t *d_m_in, const uint32_t *d_sigma_in,
+                             const uint8_t *d_wind_in, int64_t n, int t_start, int t_exact, int m_max, int u,
+                             const uint64_t *d_move_seeds, int16_t *d_m_out, uint32_t *d_sigma_out,
+                             uint8_t *d_wind_out, void *d_workspace, size_t ws_bytes, hipStream_t st) {
+  if (n > BAND_MAX_N) return fail_with(MPD_ERR_N, "n=%lld: at most %d samples per band-path call", (long long)n, BAND_MAX_N);
+  const size_t need = mpd_workspace_bytes(L, n);
+  if (ws_bytes < need || d_workspace == nullptr)
+    return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+  if ((uintptr_t)d_workspace & 255u) return fail_with(MPD_ERR_PTR, "workspace must be 256-byte aligned");
+  const BandWorkspace w = band_layout(L, n, d_workspace);
+  Rule rule;
+  rule.m_max = m_max;
+  rule.u = u;
+  rule.seeds = d_move_seeds;
+  const int P = L / 2, NJ = L / TILE_H;
+  const int64_t strips = n * NJ * P;
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, w.alive, w.wind, w.status,
+                     w.t_done, w.active[0], &w.count[2]);
+  HIP_TRY(hipGetLastError());
+  if (d_m_in == nullptr) {
+    hipLaunchKernelGGL(k_band_links, dim3((unsigned)((strips + 255) / 256)), dim3(256), 0, st, L, n, d_links, w.S[0],
+                       w.wind);
+  } else {
+    hipLaunchKernelGGL(k_band_state_import, dim3((unsigned)((strips + 255) / 256)), dim3(256), 0, st, L, n, t_start,
+                       d_m_in, d_sigma_in, d_wind_in, w.E[0], w.S[0], w.wind, w.t_done);
+  }
+  HIP_TRY(hipGetLastError());
+  int buf = 0;
+  int rc = band_run_exact(L, n, t_start, t_exact, w, rule, st, &buf);
+  if (rc != MPD_OK) return rc;
+  const int64_t words = n * ((int64_t)L * L / 32);
+  hipLaunchKernelGGL(k_band_state_export, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, L, n,
+                     t_start + t_exact, m_max, w.E[buf], w.S[buf], w.wind, d_m_out, d_sigma_out, d_wind_out);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
+int mpd_run_steps_ws(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact, int m_max,
+                     int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *d_workspace,
+                     size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  if (resident_ok(L) || !tiled_ok(L))
+    return run_steps_rule(L, d_links, d_move_seeds, n, t_exact, m_max, u, d_m_out, d_sigma_out, d_wind_out, stream);
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
+  if (t_exact < 0 || t_exact > MPD_T_MAX_LIMIT) return fail_with(MPD_ERR_TMAX, "t_exact out of range");
+  const int rc = check_rule(m_max, u);
+  if (rc) return rc;
+  if (n == 0) return MPD_OK;
+  if (d_links == nullptr || ((uintptr_t)d_links & 3u)) return fail_with(MPD_ERR_PTR, "links NULL or misaligned");
+  if (d_m_out == nullptr || d_sigma_out == nullptr || d_wind_out == nullptr || ((uintptr_t)d_m_out & 1u) ||
+      ((uintptr_t)d_sigma_out & 3u))
+    return fail_with(MPD_ERR_PTR, "state outputs NULL or misaligned");
+  if (u > 0 && (d_move_seeds == nullptr || ((uintptr_t)d_move_seeds & 7u)))
+    return fail_with(MPD_ERR_PTR, "random moves need aligned move seeds");
+  return band_steps_export(L, d_links, nullptr, nullptr, nullptr, n, 0, t_exact, m_max, u, d_move_seeds, d_m_out,
+                           d_sigma_out, d_wind_out, d_workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int mpd_run_steps_from_ws(int L, const int16_t *d_m_in, const uint32_t *d_sigma_in, const uint8_t *d_wind_in,
+                          int64_t n, int t_start, int t_exact, int m_max, int u, const uint64_t *d_move_seeds,
+                          int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *d_workspace,
+                          size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  if (resident_ok(L) || !tiled_ok(L))
+    return mpd_run_steps_from(L, d_m_in, d_sigma_in, d_wind_in, n, t_start, t_exact, m_max, u, d_move_seeds, d_m_out,
+                              d_sigma_out, d_wind_out, stream);
+  if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
+  if (t_start < 0 || t_exact < 0 || (int64_t)t_start + t_exact > MPD_T_MAX_LIMIT)
+    return fail_with(MPD_ERR_TMAX, "t_start=%d, t_exact=%d: both >= 0 with a sum <= %d", t_start, t_exact,
+                     MPD_T_MAX_LIMIT);
+  const int rc = check_rule(m_max, u);
+  if (rc) return rc;
+  if (n == 0) return MPD_OK;
+  if (d_m_in == nullptr || d_sigma_in == nullptr || d_wind_in == nullptr || ((uintptr_t)d_m_in & 1u) ||
+      ((uintptr_t)d_sigma_in & 3u))
+    return fail_with(MPD_ERR_PTR, "state inputs NULL or misaligned");
+  if (d_m_out == nullptr || d_sigma_out == nullptr || d_wind_out == nullptr || ((uintptr_t)d_m_out & 1u) ||
+      ((uintptr_t)d_sigma_out & 3u))
+    return fail_with(MPD_ERR_PTR, "state outputs NULL or misaligned");
+  if (u > 0 && (d_move_seeds == nullptr || ((uintptr_t)d_move_seeds & 7u)))
+    return fail_with(MPD_ERR_PTR, "random moves need aligned move seeds");
+  return band_steps_export(L, nullptr, d_m_in, d_sigma_in, d_wind_in, n, t_start, t_exact, m_max, u, d_move_seeds,
+                           d_m_out, d_sigma_out, d_wind_out, d_workspace, ws_bytes, (hipStream_t)stream);
 }
 
 int mpd_decode_errors_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int T_max,
@@ -1901,7 +2181,7 @@ int mpd_decode_errors_rule(int L, const uint32_t *d_links, const uint64_t *d_mov
 }
 
 static int run_steps_rule(int L, const uint32_t *d_links, const uint64_t *d_move_seeds, int64_t n, int t_exact, int m_max,
-                   int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream, int open = 0) {
+                   int u, int16_t *d_m_out, uint32_t *d_sigma_out, uint8_t *d_wind_out, void *stream, int open) {
   if (n < 0 || n > (int64_t)1 << 31) return fail_with(MPD_ERR_N, "n out of range");
   if (t_exact < 0 || t_exact > MPD_T_MAX_LIMIT) return fail_with(MPD_ERR_TMAX, "t_exact out of range");
   const int rc = check_rule(m_max, u);
@@ -2013,6 +2293,7 @@ int mpd_decode_open(int L, double p, const uint64_t *d_seeds, int64_t n, int T_m
     a.open = 1;
     return launch_resident(a, st);
   }
+  if (n > BAND_MAX_N) return fail_with(MPD_ERR_N, "n=%lld: at most %d samples per band-path call", (long long)n, BAND_MAX_N);
   const size_t need = mpd_workspace_bytes(L, n);
   if (ws_bytes < need || d_workspace == nullptr)
     return fail_with(MPD_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);

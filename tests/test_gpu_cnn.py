@@ -196,6 +196,25 @@ def test_learned_decode_budgets_and_sizes(gpu, orc, L, p, n, T_max):
     assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"])
 
 
+def test_config5_L1024_fifo_and_learned(gpu, orc):
+    """The L = 1024, p = 0.01 evaluation of the learned-scheduling workload on
+    64 samples: the plain (FIFO) decode and a three-group learned decode
+    (the predictor's tiled kernel, groups with first passes of 2, 4 and 6
+    steps) both equal the oracle on every sample."""
+    L, p, n = 1024, 0.01, 64
+    s = seeds(5, 201, n)
+    params = torch.from_numpy(trained_like_params(14)).cuda()
+    pred = gpu.cnn_forward(gpu.syndrome_counts(L, p, s), params).cpu().numpy()
+    edges = tuple(float(v) for v in np.quantile(pred, [1 / 3, 2 / 3]))
+    ref = orc.decode_seeds(L, p, s, 4096, threads=16)
+    T0, F0, S0 = gpu.decode_batch(L, p, s, 4096)
+    T1, F1, S1, _ = gpu.decode_learned(L, p, s, params, edges, (2, 4, 6), 4096)
+    for tag, (T, F, S) in (("fifo", (T0, F0, S0)), ("learned", (T1, F1, S1))):
+        assert np.array_equal(T.cpu().numpy(), ref["T_dec"]), tag
+        assert np.array_equal(F.cpu().numpy(), ref["flags"]), tag
+        assert np.array_equal(S.cpu().numpy().reshape(n, -1).view(np.uint32), ref["sigma_words"]), tag
+
+
 @pytest.mark.parametrize("policy", POLICIES[:4])
 def test_learned_decode_per_sample_p(gpu, orc, policy):
     """Per-sample noise strengths: any policy returns exactly what the plain

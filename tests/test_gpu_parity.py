@@ -104,16 +104,22 @@ def test_config2_full(gpu, orc):
         compare(f"config 2 p={p}", T, F, S, ref)
 
 
-def test_config3_sampled(gpu, orc):
-    """Full L=256 batch in the benchmark's launch shape; the oracle recomputes
-    a spread of samples one by one."""
+def test_config3_full(gpu, orc):
+    """The whole L=256, p=0.01 batch of 4096 samples in the benchmark's launch
+    shape, every sample against the oracle (T_dec, flags, final syndrome),
+    with the later passes driven from the host and on the device."""
     cfg = CONFIGS[3]
     n = cfg["n"]
     s = seeds(3, 0, n)
-    T, F, S = gpu.decode_batch(cfg["L"], cfg["p"][0], s, cfg["T_max"])
-    pick = np.unique(np.concatenate([np.arange(0, n, 37), [n - 1]]))
-    ref = orc.decode_seeds(cfg["L"], cfg["p"][0], s[pick], cfg["T_max"], threads=8)
-    compare("config 3 sampled", T[pick], F[pick], S[pick], ref)
+    ref = orc.decode_seeds(cfg["L"], cfg["p"][0], s, cfg["T_max"], threads=16)
+    for drv in (gpu.BAND_DRIVER_HOST, gpu.BAND_DRIVER_DEVICE):
+        old = gpu.get_band_driver(cfg["L"])
+        gpu.set_band_driver(drv, cfg["L"])
+        try:
+            T, F, S = gpu.decode_batch(cfg["L"], cfg["p"][0], s, cfg["T_max"])
+        finally:
+            gpu.set_band_driver(old, cfg["L"])
+        compare(f"config 3 driver {drv}", T, F, S, ref)
 
 
 @pytest.mark.parametrize("T_max", [0, 1, 2, 3, 5, 6, 7])
