@@ -116,6 +116,27 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
                      int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_final_syndrome,
                      void *d_workspace, size_t ws_bytes, void *stream);
 
+/* Allocation-free decode, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as mpd_decode_batch without the
+ * workspace: the band path (L >= 256) keeps its state in a scratch array of
+ * MPD_STATIC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends, and runs its later passes on the device (no host
+ * wait, no pinned host memory).  A call whose band-path state would exceed
+ * the scratch (mpd_workspace_bytes(L, n) > MPD_STATIC_SCRATCH_BYTES: about
+ * 124 samples at L = 256, 31 at L = 512, 7 at L = 1024) fails with
+ * MPD_ERR_WORKSPACE and enqueues nothing; lattices up to L = 128 need no
+ * scratch.  No call allocates or frees device or pinned host memory (the
+ * first call on a device looks the scratch up; with mpd_profile on, timing
+ * events are still created).  Every call on one device shares that
+ * device's scratch: calls that overlap on a device (several streams or host
+ * threads) race and give wrong results; order them on one stream.  The
+ * scratch keeps the last call's contents; each call clears what it reads
+ * before reading it. */
+#define MPD_STATIC_SCRATCH_BYTES (128u << 20)
+int mpd_decode_batch_static(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                            uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream);
+
 /* Decode n explicit error patterns (hand-built cases, exhaustive checks).
  *   d_links            [n][ceil(2*L*L/32)] uint32 link bits (see above)
  * Other arguments as mpd_decode_batch.  Supported L: as mpd_decode_batch;

@@ -97,6 +97,8 @@ def lib():
     L.mpd_decode_learned.argtypes = [I, D, P, P, I64, I, P, I, P, P, P, P, P, P, P, SZ, P]
     L.mpd_decode_learned.restype = I
     L.mpd_run_steps_from.argtypes = [I, P, P, P, I64, I, I, I, I, P, P, P, P, P]
+    L.mpd_decode_batch_static.argtypes = [I, D, P, I64, I, P, P, P, P]
+    L.mpd_decode_batch_static.restype = I
     L.mpd_run_steps_ws.argtypes = [I, P, P, I64, I, I, I, P, P, P, P, SZ, P]
     L.mpd_run_steps_ws.restype = I
     L.mpd_run_steps_from_ws.argtypes = [I, P, P, P, I64, I, I, I, I, P, P, P, P, P, SZ, P]
@@ -174,6 +176,29 @@ def decode_batch(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool
     rc = lib().mpd_decode_batch(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(S), _ptr(ws),
                                 ws.numel(), _stream_ptr(stream))
     _check(rc, "mpd_decode_batch")
+    return T, F, S
+
+
+STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def decode_batch_static(L: int, p: float, seeds, T_max: int = 4096, want_syndrome: bool = True, out=None,
+                        stream=None):
+    """mpd_decode_batch_static: decode_batch without a workspace (the
+    library's own scratch on the device; calls on one device must not
+    overlap).  Returns (T_dec, flags, syndrome)."""
+    dev = torch.device("cuda")
+    s = _seeds_tensor(seeds, dev)
+    n = s.numel()
+    if out is None:
+        T = torch.empty(n, dtype=torch.int32, device=dev)
+        F = torch.empty(n, dtype=torch.uint8, device=dev)
+        S = torch.empty((n, syndrome_words(L)), dtype=torch.int32, device=dev) if want_syndrome else None
+    else:
+        T, F, S = out
+    rc = lib().mpd_decode_batch_static(L, float(p), _ptr(s), n, int(T_max), _ptr(T), _ptr(F), _ptr(S),
+                                       _stream_ptr(stream))
+    _check(rc, "mpd_decode_batch_static")
     return T, F, S
 
 

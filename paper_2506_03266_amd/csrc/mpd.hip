@@ -1215,6 +1215,7 @@ struct BandRun {
   Rule rule;
   int cur = 1;
   bool done = false;
+  bool device_only = false;  // later passes on the device whatever the setting (no host memory, no wait)
 };
 
 // Pinned host words for the survivor counts, one block per host thread,
@@ -1320,6 +1321,7 @@ int band_tail(BandRun &r, int64_t first_count) {
 // the host (a survivor-count readback before every pass).  A stream being
 // captured into a graph always takes the device: a graph holds no host waits.
 bool device_driven(const BandRun &r, int64_t first_count) {
+  if (r.device_only) return true;
   const int mode = schedule_for(r.L).driver;
   if (mode == MPD_BAND_DRIVER_DEVICE) return true;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1570,6 +1572,38 @@ LearnedLayout learned_layout(int L, int64_t n, void *base) {
   return l;
 }
 
+// Library-held scratch of the allocation-free decode (mpd_decode_batch_static):
+// the band path's state and bookkeeping for up to MPD_STATIC_SCRATCH_BYTES.
+// Each device the library runs on holds its own copy until the process
+// ends.  Host code never passes `scratch` itself (on the host it only names
+// the symbol): it looks the device address up once per device and passes
+// that pointer to the kernels.
+static __device__ __align__(256) unsigned char scratch[MPD_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device, looked up on
+// the first call for that device (with it current), then reused.  The
+// compute-unit count is cached at the same time, so that later calls touch
+// no allocating container.
+int static_scratch(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail_with(MPD_ERR_HIP, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr || ((uintptr_t)p & 255u)) return fail_with(MPD_ERR_HIP, "scratch symbol has no usable address");
+    (void)cu_count();
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPD_OK;
+}
+
 }  // namespace mpd
 
 using namespace mpd;
@@ -1638,6 +1672,48 @@ int mpd_decode_batch(int L, double p, const uint64_t *d_seeds, int64_t n, int T_
   g_last_error.clear();
   return decode_seeded(L, p, d_seeds, n, T_max, Rule(), d_T_dec, d_flags, d_final_syndrome, d_workspace, ws_bytes,
                        stream);
+}
+
+int mpd_decode_batch_static(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
+                            uint8_t *d_flags, uint32_t *d_final_syndrome, void *stream) {
+  g_last_error.clear();
+  if (!(p >= 0.0 && p <= 1.0)) return fail_with(MPD_ERR_P, "p must lie in [0, 1]");
+  int rc = check_common(L, n, T_max, d_T_dec, d_flags);
+  if (rc) return rc;
+  if (!resident_ok(L) && !tiled_ok(L))
+    return fail_with(MPD_ERR_L, "L=%d unsupported (3..128 with a strip height, or a multiple of 16 in [256, 16384])", L);
+  if (n == 0) return MPD_OK;
+  if (d_seeds == nullptr || ((uintptr_t)d_seeds & 7u)) return fail_with(MPD_ERR_PTR, "seeds NULL or misaligned");
+  if (d_final_syndrome != nullptr && ((uintptr_t)d_final_syndrome & 3u))
+    return fail_with(MPD_ERR_PTR, "final_syndrome misaligned");
+  hipStream_t st = (hipStream_t)stream;
+  if (resident_ok(L)) {  // decodes on chip: no scratch at all
+    ResidentArgs a = {};
+    a.L = L;
+    a.n = n;
+    a.seeds = d_seeds;
+    a.thr = threshold_of(p);
+    a.T_max = T_max;
+    a.t_exact = -1;
+    a.T_dec = d_T_dec;
+    a.flags = d_flags;
+    a.syn = d_final_syndrome;
+    return launch_resident(a, st);
+  }
+  if (n > BAND_MAX_N) return fail_with(MPD_ERR_N, "n=%lld: at most %d samples per band-path call", (long long)n, BAND_MAX_N);
+  const size_t need = mpd_workspace_bytes(L, n);
+  if (need > (size_t)MPD_STATIC_SCRATCH_BYTES)
+    return fail_with(MPD_ERR_WORKSPACE,
+                     "L=%d, n=%lld needs %zu bytes of scratch; the library holds %zu (use mpd_decode_batch with a "
+                     "workspace)", L, (long long)n, need, (size_t)MPD_STATIC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc != MPD_OK) return rc;
+  BandRun r;
+  r.device_only = true;
+  rc = band_setup(r, L, threshold_of(p), nullptr, d_seeds, n, T_max, d_T_dec, d_flags, d_final_syndrome, ws, st);
+  if (rc != MPD_OK) return rc;
+  return band_passes(&r, 1);
 }
 
 int mpd_decode_rule(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int m_max, int u,
