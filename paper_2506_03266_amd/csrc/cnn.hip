@@ -92,10 +92,34 @@ __device__ __forceinline__ float relu(float z) { return z > 0.f ? z : 0.f; }
 // (lane groups 0, 1) and 2jj + 1 (groups 2, 3), 16 input channels each;
 // layer 1: K = tap (< 9) in block 0.
 constexpr int AOP_UINT4 = 4 * 5 * 64;
+// A second packing of layers 2-4 for the row-streaming layers of 32 x 32
+// maps (conv_rows32): Arow[layer - 1][lane][2 (dy + 1) + blk] (a lane's six
+// blocks are contiguous, so one base address serves them).  Block 0
+// holds taps (dy, dx = -1) in K 0..15 and (dy, 0) in K 16..31, block 1 the
+// tap (dy, +1) in K 0..15 and zeros, 16 input channels per tap.
+constexpr int AROW_UINT4 = 3 * 6 * 64;
+constexpr int PREP_UINT4 = AOP_UINT4 + AROW_UINT4;
 
 __global__ void k_cnn_prep(const float *__restrict__ params, uint4 *__restrict__ Aop) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= AOP_UINT4) return;
+  if (t >= PREP_UINT4) return;
+  if (t >= AOP_UINT4) {
+    const int u = t - AOP_UINT4;
+    const int layer = 1 + u / 384, lane = (u % 384) / 6, b = u % 6;
+    const int co = lane & 15, g = lane >> 4, dy = b / 2 - 1, blk = b & 1;
+    const int off = layer == 1 ? OFF_W2 : (layer == 2 ? OFF_W3 : OFF_W4);
+    const int dx = blk == 0 ? (g < 2 ? -1 : 0) : 1;
+    const bool zero = blk == 1 && g >= 2;
+    const int tap = 3 * (dy + 1) + (dx + 1), ci0 = 8 * (g & 1);
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = zero ? 0.f : params[off + (co * 9 + tap) * CH + ci0 + j];
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = pack_bf16(v[2 * j], v[2 * j + 1]);
+    Aop[t] = make_uint4(w[0], w[1], w[2], w[3]);
+    return;
+  }
   const int layer = t / 320, jj = (t / 64) % 5, lane = t % 64;
   const int co = lane & 15, g = lane >> 4;
   float v[8];
@@ -253,6 +277,174 @@ __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint
   }
 }
 
+// A 16 -> 16 layer of a whole 32 x 32 map (bordered input and output
+// buffers [34^2][16]), streamed by rows: wave w computes the 16 columns
+// x0 = 16 (w & 1) of output rows y0 .. y0 + 7, y0 = 8 (w >> 1).  It walks
+// the bordered input rows R = y0 .. y0 + 9 once; the operand fragment of a
+// row (the taps dx = -1, 0 in one K block, dx = +1 in a second) serves the
+// three output rows R, R - 1, R - 2 that read it (with the weights of
+// dy = -1, 0, +1), which keep three accumulators in flight.  So each input
+// fragment is read from LDS once for three output rows.  A holds the six
+// blocks of Arow for this layer.  LAST folds the outputs into the pooling
+// state (a lane meets its positions in increasing order).
+template <bool LAST>
+__device__ __forceinline__ void conv_rows32(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
+                                            const bf16x8 *A, const float *__restrict__ b, Pool &pool) {
+  constexpr int M = 32, S = M + 2, RPW = 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int x0 = (wave & 1) * 16, y0 = (wave >> 1) * RPW;
+  float bias[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bias[r] = b[4 * g + r];
+  // bordered columns of this lane's K slices: block 0 dx = -1 (groups 0, 1)
+  // or 0 (groups 2, 3); block 1 dx = +1 (groups 0, 1 only)
+  const uint16_t *p0 = in + (y0 * S + x0 + j + (g >> 1)) * CH + 8 * (g & 1);
+  const uint16_t *p1 = in + (y0 * S + x0 + j + 2) * CH + 8 * (g & 1);
+  f32x4 acc[3];
+  // fragments of the next input row are loaded one row ahead
+  uint4 n0 = *reinterpret_cast<const uint4 *>(p0), n1 = make_uint4(0u, 0u, 0u, 0u);
+  if (g < 2) n1 = *reinterpret_cast<const uint4 *>(p1);
+#pragma unroll
+  for (int t = 0; t < RPW + 2; ++t) {  // bordered input row y0 + t
+    const bf16x8 B0 = __builtin_bit_cast(bf16x8, n0), B1 = __builtin_bit_cast(bf16x8, n1);
+    if (t + 1 < RPW + 2) {
+      n0 = *reinterpret_cast<const uint4 *>(p0 + (t + 1) * S * CH);
+      if (g < 2) n1 = *reinterpret_cast<const uint4 *>(p1 + (t + 1) * S * CH);
+    }
+    // output row u = t - 1 - dy reads this row with the weights of dy
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int u = t - 1 - dy;
+      if (u < 0 || u >= RPW) continue;
+      f32x4 c = acc[u % 3];
+      if (dy == -1) c = f32x4{0.f, 0.f, 0.f, 0.f};  // first contribution to row u
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2 * (dy + 1)], B0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2 * (dy + 1) + 1], B1, c, 0, 0, 0);
+      acc[u % 3] = c;
+    }
+    // row u = t - 2 is complete: bias, ReLU, store or pool
+    if (t >= 2) {
+      const int u = t - 2, y = y0 + u, x = x0 + j;
+      const f32x4 c = acc[u % 3];
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = relu(c[r] + bias[r]);
+      if (!LAST) {
+        *reinterpret_cast<uint2 *>(out + ((y + 1) * S + x + 1) * CH + 4 * g) =
+            make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+      } else {
+        const int gi = y * M + x;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const bool gt = v[r] > pool.best[r];
+          pool.best[r] = gt ? v[r] : pool.best[r];
+          pool.idx[r] = gt ? gi : pool.idx[r];
+          // update the pooling state here, not after the loop (which would
+          // keep every row's accumulators alive)
+          asm volatile("" : "+v"(pool.best[r]), "+v"(pool.idx[r]));
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads one row ahead, not all hoisted
+  }
+}
+
+// Layer 1 (one input channel) of a whole 32 x 32 map, streamed by rows as
+// conv_rows32: wave w computes columns x0 = 16 (w & 1) of output rows
+// y0 .. y0 + 7, y0 = 8 (w >> 1).  T[R][c] (R = 0..33 bordered rows, c =
+// 0..31) holds the inputs at bordered columns c, c + 1, c + 2 of row R as
+// four bfloat16 (the last zero).  A lane keeps the triplets of the last
+// three rows and assembles the 3 x 3 window of its output position as K =
+// tap = 3 (dy + 1) + (dx + 1): K 0..7 in lane group 0, K 8 in group 1 (the
+// operand layout of the layer-1 block of Aop), so one instruction per
+// output row and position group.
+__device__ __forceinline__ void conv1_rows32(const uint2 *__restrict__ T, uint16_t *__restrict__ out,
+                                             const bf16x8 &A1, const float *__restrict__ b) {
+  constexpr int M = 32, S = M + 2, RPW = 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int x0 = (wave & 1) * 16, y0 = (wave >> 1) * RPW;
+  float bias[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bias[r] = b[4 * g + r];
+  const uint2 *p = T + y0 * M + x0 + j;
+  uint2 r0 = make_uint2(0u, 0u), r1 = r0, r2 = r0;  // triplets of rows t - 2, t - 1, t
+  if (g < 2) {
+    r1 = p[0];
+    r2 = p[M];
+  }
+#pragma unroll
+  for (int t = 2; t < RPW + 2; ++t) {
+    r0 = r1;
+    r1 = r2;
+    if (g < 2) r2 = p[t * M];
+    // window of output row y0 + t - 2: rows r0 (dy = -1), r1 (0), r2 (+1)
+    uint4 k = make_uint4(0u, 0u, 0u, 0u);
+    if (g == 0)
+      k = make_uint4(r0.x, (r0.y & 0xFFFFu) | (r1.x << 16), (r1.x >> 16) | (r1.y << 16), r2.x);
+    else if (g == 1)
+      k.x = r2.y & 0xFFFFu;
+    const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, __builtin_bit_cast(bf16x8, k),
+                                                           f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    const int y = y0 + t - 2, x = x0 + j;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = relu(c[r] + bias[r]);
+    *reinterpret_cast<uint2 *>(out + ((y + 1) * S + x + 1) * CH + 4 * g) =
+        make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+  }
+}
+
+// One step of a 64-bit (hi, lo) maximum across the lanes of a 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ void key_step(uint32_t &hi, uint32_t &lo) {
+  const uint32_t oh = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, CTRL, 0xF, 0xF, true);
+  const uint32_t ol = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, CTRL, 0xF, 0xF, true);
+  const bool gt = oh > hi || (oh == hi && ol > lo);
+  hi = gt ? oh : hi;
+  lo = gt ? ol : lo;
+}
+
+// Per-channel (maximum, lowest position) of the pooling state of a
+// row-streamed layer 4: every value is >= 0 after the ReLU, so the float
+// bits order like the values, and the key (bits << 32 | ~position) has its
+// maximum at the largest value with the lowest position.  The 16 lanes of a
+// row (one channel group, 16 positions) reduce with DPP row shifts; lane 15
+// of each row leaves its four keys in keys[wave][16]; threads 0..15 then
+// reduce over the waves.
+__device__ __forceinline__ void pool_keys_reduce(const Pool &pool, unsigned long long *keys, float &best, int &bi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    uint32_t hi = __float_as_uint(pool.best[r]), lo = ~(uint32_t)pool.idx[r];
+    key_step<0x111>(hi, lo);  // row_shr:1, 2, 4, 8; lanes below the shift read 0 (bound_ctrl)
+    key_step<0x112>(hi, lo);
+    key_step<0x114>(hi, lo);
+    key_step<0x118>(hi, lo);
+    if ((lane & 15) == 15) keys[wave * CH + 4 * (lane >> 4) + r] = ((unsigned long long)hi << 32) | lo;
+  }
+  __syncthreads();
+  best = -1.f;
+  bi = 0x7FFFFFFF;
+  if (threadIdx.x < CH) {
+    unsigned long long m = 0ull;
+    for (int w = 0; w < nwaves; ++w) m = max(m, keys[w * CH + threadIdx.x]);
+    best = __uint_as_float((uint32_t)(m >> 32));
+    bi = (int)~(uint32_t)m;
+  }
+}
+
+// Operands of one row-streamed layer (layer 1..3 = network layers 2..4).
+struct LayerRow {
+  bf16x8 A[6];
+};
+__device__ __forceinline__ void load_layer_rows(const uint4 *__restrict__ Arow, int layer, LayerRow &W) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) W.A[b] = __builtin_bit_cast(bf16x8, Arow[(layer - 1) * 384 + lane * 6 + b]);
+}
+
 // Wrapped border of a [(M+2)^2][16] buffer: row 0 / M+1 and column 0 / M+1
 // copy the opposite interior edge.
 __device__ __forceinline__ void fill_border(uint16_t *buf, int M) {
@@ -346,9 +538,10 @@ __device__ __forceinline__ void pool_init(Pool &pool) {
   }
 }
 
-// Whole map per workgroup (M <= 32), buffers with a wrapped border of one
-// position.  LDS: x [(M+2)^2] | A, B [(M+2)^2][16] | pooling.  MC > 0: the
-// map side as a compile-time constant (L = 256 maps), 0: at run time.
+// Whole map per workgroup (M < 32; 32 x 32 maps take k_cnn_forward32),
+// buffers with a wrapped border of one position.  LDS: x [(M+2)^2] | A, B
+// [(M+2)^2][16] | pooling.  MC > 0: the map side as a compile-time
+// constant, 0: at run time.
 template <int MC>
 __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4))) void k_cnn_forward_wrap(
     FwdArgs a) {  // 4 waves per SIMD: two workgroups per CU, as the LDS allows
@@ -419,6 +612,91 @@ __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4)
     }
     __syncthreads();
     if (threadIdx.x == 0) a.pred[s] = head(P, feat_s);
+  }
+}
+
+// Whole 32 x 32 maps (L = 256): one workgroup of 8 waves per map, two
+// workgroups per CU, a fixed grid walking the maps.  Every layer is
+// streamed by rows (conv1_rows32, conv_rows32); the wrapped borders are
+// refreshed after each layer.  The next map's counts are fetched into registers while the
+// current map's last layer runs.  LDS: A, B [34^2][16] bfloat16 (layer 1's
+// tap triplets and the staged counts live in B until layer 2 writes it) |
+// per-wave pooling keys.
+__global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4))) void k_cnn_forward32(FwdArgs a) {
+  constexpr int M = 32, S = M + 2, SS = S * S;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint16_t *bufA = reinterpret_cast<uint16_t *>(smem);
+  uint16_t *bufB = bufA + SS * CH;
+  uint2 *T = reinterpret_cast<uint2 *>(bufB);                        // [34][32] layer-1 tap triplets
+  uint16_t *stage = reinterpret_cast<uint16_t *>(T + S * M);         // [M*M/2] staged counts (2 per entry)
+  unsigned long long *pool_keys = reinterpret_cast<unsigned long long *>(bufB + SS * CH);  // [NW][16]
+  __shared__ float feat_s[CH];
+  __shared__ float bias_s[4 * CH];
+  __shared__ float head_s[CH + 1];
+  const float *P = a.params;
+  load_biases(P, bias_s);
+  if (threadIdx.x <= CH) head_s[threadIdx.x] = P[OFF_WL + threadIdx.x];  // Wl[16], then bl
+  const int lane = threadIdx.x & 63;
+  const size_t act = (size_t)M * M * CH;
+  // this thread's two counts of the first map (M*M/2 = THREADS_WRAP pairs)
+  uint16_t nxt = 0;
+  if ((int64_t)blockIdx.x < a.n) nxt = reinterpret_cast<const uint16_t *>(a.counts + blockIdx.x * M * M)[threadIdx.x];
+  for (int64_t s = blockIdx.x; s < a.n; s += gridDim.x) {
+    stage[threadIdx.x] = nxt;
+    __syncthreads();
+    {  // tap triplets of layer 1: T[R][c] = x at bordered columns c .. c + 2 of bordered row R
+      const uint8_t *cs = reinterpret_cast<const uint8_t *>(stage);
+      for (int i = threadIdx.x; i < S * M; i += blockDim.x) {
+        const int R = i / M, c = i - R * M, y = (R + M - 1) % M;
+        const float u0 = (float)cs[y * M + (c + M - 1) % M], u1 = (float)cs[y * M + c],
+                    u2 = (float)cs[y * M + (c + 1) % M];
+        T[i] = make_uint2(pack_bf16(u0 * 0.125f, u1 * 0.125f), pack_bf16(u2 * 0.125f, 0.f));
+      }
+    }
+    __syncthreads();
+    // The operand base is opaque per map (it stays in scalar registers), so
+    // that the compiler does not hoist one 64-bit address per operand block
+    // out of the loop.
+    const uint4 *Aop = a.Aop;
+    asm volatile("" : "+s"(Aop));
+    const uint4 *Arow = Aop + AOP_UINT4;
+    LayerRow Wr;
+    conv1_rows32(T, bufA, __builtin_bit_cast(bf16x8, Aop[lane]), bias_s);
+    Pool pool;
+    pool_init(pool);
+    load_layer_rows(Arow, 1, Wr);
+    __syncthreads();
+    fill_border(bufA, M);
+    if (a.store) store_interior(bufA, a.store + (size_t)s * act, M);
+    __syncthreads();
+    conv_rows32<false>(bufA, bufB, Wr.A, bias_s + CH, pool);
+    load_layer_rows(Arow, 2, Wr);
+    __syncthreads();
+    fill_border(bufB, M);
+    if (a.store) store_interior(bufB, a.store + ((size_t)a.n + s) * act, M);
+    __syncthreads();
+    conv_rows32<false>(bufB, bufA, Wr.A, bias_s + 2 * CH, pool);
+    load_layer_rows(Arow, 3, Wr);
+    __syncthreads();
+    fill_border(bufA, M);
+    if (a.store) store_interior(bufA, a.store + ((size_t)2 * a.n + s) * act, M);
+    __syncthreads();
+    if (s + gridDim.x < a.n) nxt = reinterpret_cast<const uint16_t *>(a.counts + (s + gridDim.x) * M * M)[threadIdx.x];
+    conv_rows32<true>(bufA, nullptr, Wr.A, bias_s + 3 * CH, pool);
+    float best;
+    int bi;
+    pool_keys_reduce(pool, pool_keys, best, bi);
+    if (threadIdx.x < CH) {
+      feat_s[threadIdx.x] = best;
+      if (a.feat) a.feat[s * CH + threadIdx.x] = best;
+      if (a.argmax) a.argmax[s * CH + threadIdx.x] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float acc = head_s[CH];
+      for (int c = 0; c < CH; ++c) acc = fmaf(head_s[c], feat_s[c], acc);
+      a.pred[s] = acc;
+    }
   }
 }
 
@@ -751,6 +1029,9 @@ size_t wrap_lds(int M, int threads) {
   const size_t SS = (size_t)(M + 2) * (M + 2);
   return ((SS + 7) & ~(size_t)7) * 2 + 2 * SS * CH * 2 + (size_t)(threads / 64) * CH * 8;
 }
+size_t fwd32_lds() {  // A, B [34^2][16] bfloat16, per-wave pooling results
+  return (size_t)2 * 34 * 34 * CH * 2 + (size_t)(THREADS_WRAP / 64) * CH * 8;
+}
 size_t tile_lds(int threads) {
   constexpr size_t R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4;
   return R0 * R0 * 2 + (R1 * R1 + R2 * R2) * CH * 2 + (size_t)(threads / 64) * CH * 8;
@@ -794,7 +1075,8 @@ int check_map(int M, int64_t n) {
 
 // Forward workspace: packed weights, then (maps wider than 32) the pooled maxima.
 size_t cnn_forward_ws(int M, int64_t n) {
-  return align256(AOP_UINT4 * sizeof(uint4)) + (M <= WRAP_MAX ? 0 : align256((size_t)n * CH * sizeof(unsigned long long)));
+  return align256(PREP_UINT4 * sizeof(uint4)) +
+         (M <= WRAP_MAX ? 0 : align256((size_t)n * CH * sizeof(unsigned long long)));
 }
 
 int cnn_forward_run(const uint8_t *counts, int M, int64_t n, const float *params, float *pred, float *feat,
@@ -813,21 +1095,21 @@ int cnn_forward_run(const uint8_t *counts, int M, int64_t n, const float *params
   a.n = n;
   uint4 *Aop = (uint4 *)ws;
   a.Aop = Aop;
-  hipLaunchKernelGGL(k_cnn_prep, dim3((AOP_UINT4 + 255) / 256), dim3(256), 0, stream, params, Aop);
+  hipLaunchKernelGGL(k_cnn_prep, dim3((PREP_UINT4 + 255) / 256), dim3(256), 0, stream, params, Aop);
   HIP_TRY(hipGetLastError());
   ProfScope ps("k_cnn_forward", stream);
   if (M <= WRAP_MAX) {
     // two workgroups per CU fit in LDS; each walks its share of the maps
     const unsigned grid = (unsigned)std::min<int64_t>(n, 2 * (int64_t)cu_count());
     if (M == 32)
-      hipLaunchKernelGGL(k_cnn_forward_wrap<32>, dim3(grid), dim3(THREADS_WRAP), wrap_lds(M, THREADS_WRAP), stream, a);
+      hipLaunchKernelGGL(k_cnn_forward32, dim3(grid), dim3(THREADS_WRAP), fwd32_lds(), stream, a);
     else
       hipLaunchKernelGGL(k_cnn_forward_wrap<0>, dim3(grid), dim3(THREADS_WRAP), wrap_lds(M, THREADS_WRAP), stream, a);
     HIP_TRY(hipGetLastError());
     return MPD_OK;
   }
   if (store != nullptr) return fail_with(MPD_ERR_L, "stored activations need M <= %d", WRAP_MAX);
-  a.pool = (unsigned long long *)((char *)ws + align256(AOP_UINT4 * sizeof(uint4)));
+  a.pool = (unsigned long long *)((char *)ws + align256(PREP_UINT4 * sizeof(uint4)));
   const int64_t cnt = n * CH;
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.pool, cnt);
   HIP_TRY(hipGetLastError());
