@@ -53,8 +53,7 @@
  *     (the call then synchronizes `stream`), or on the device with no host
  *     wait (see mpd_set_band_driver).  A call on a stream that is being
  *     captured into a HIP graph always takes the device, so every
- *     mpd_decode_batch can be captured; mpd_decode_learned reads its group
- *     sizes back and cannot.
+ *     mpd_decode_batch and mpd_decode_learned can be captured.
  *   - Return value 0 on success, a negative MPD_ERR_* code otherwise; the
  *     message of the last failing call on this host thread is returned by
  *     mpd_last_error().  On an error nothing has been enqueued unless the
@@ -495,9 +494,13 @@ int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d
  * plus d_pred [n] if not NULL.  With one group and d_pred NULL the network
  * is not evaluated: the call is the plain decode with first-pass depth
  * h_depth[0] (the FIFO fallback; d_params is still checked).  L: a multiple
- * of 16 in [256, 16384].  Workspace: mpd_learned_workspace_bytes(L, n)
- * bytes, 256-byte aligned.  Synchronizes `stream`, except in the fallback
- * when the band schedule's driver runs the later passes on the device. */
+ * of 16 in [256, 16384], at most 65535 samples.  Workspace:
+ * mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.  The group
+ * sizes stay on the device (each group's first pass is sized there), so
+ * the call waits for the host only where mpd_decode_batch does: before the
+ * later passes when the host drives them (mpd_set_band_driver).  With the
+ * device driver, or on a stream under capture, it never synchronizes and
+ * can be captured into a graph. */
 size_t mpd_learned_workspace_bytes(int L, int64_t n);
 int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
                        const float *d_params, int n_bins, const float *h_edges, const int *h_depth, int32_t *d_T_dec,

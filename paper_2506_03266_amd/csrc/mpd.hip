@@ -1192,12 +1192,52 @@ int band_pass(int L, int k, int T_max, const BandWorkspace &w, const int32_t *ac
   return MPD_OK;
 }
 
+// A pass like band_pass over a list whose length is only known on the
+// device (*count, at most `bound`): the persistent k_band_grid walks the
+// (sample, tile) tasks and k_finalize reads the count itself, so the host
+// does not wait for it.
+int band_pass_dev(int L, int k, int T_max, const BandWorkspace &w, const int32_t *active, const int *count,
+                  int64_t bound, int cur, bool zero, int32_t *d_T_dec, const Rule &rule, hipStream_t stream) {
+  BandArgs ba;
+  const int nty = tile_geometry(L, k, BAND_RY, ba);
+  const int ntiles = ba.ntx * nty;
+  ba.T_max = T_max;
+  ba.t_done = w.t_done;
+  ba.active = active;
+  ba.Esrc = w.E[cur];
+  ba.Ssrc = w.S[cur];
+  ba.Edst = w.E[cur ^ 1];
+  ba.Sdst = w.S[cur ^ 1];
+  ba.alive = w.alive;
+  ba.wind = w.wind;
+  ba.zero_count = zero ? &w.count[cur ^ 1] : nullptr;
+  ba.m_max = rule.m_max;
+  ba.u = rule.u;
+  ba.seeds = rule.seeds;
+  {
+    ProfScope ps("k_band", stream);
+    const dim3 g((unsigned)std::min<int64_t>(bound * ntiles, cu_count())), blk(BAND_NW * 64);
+    const size_t lds = band_lds(BAND_NW);
+    switch (rule.mode()) {
+      case BAND_RULE: hipLaunchKernelGGL((k_band_grid<BAND_NW, BAND_RULE>), g, blk, lds, stream, ba, count, ntiles); break;
+      case BAND_OPEN: hipLaunchKernelGGL((k_band_grid<BAND_NW, BAND_OPEN>), g, blk, lds, stream, ba, count, ntiles); break;
+      default: hipLaunchKernelGGL((k_band_grid<BAND_NW, BAND_PLAIN>), g, blk, lds, stream, ba, count, ntiles);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((bound + 255) / 256)), dim3(256), 0, stream, k, T_max, cur ^ 1, active,
+                     (int)bound, count, w.t_done, w.alive, d_T_dec, w.status, w.active[cur ^ 1], &w.count[cur ^ 1]);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
 // First pass of a batch: groups of samples (device lists) with their own
 // depth.  Every later pass runs all survivors at the schedule's k_next.
 struct FirstPass {
   int nb = 0;
   const int32_t *list[8];
-  int count[8];
+  int count[8];            // group sizes known to the host, or upper bounds when dcount is set
+  const int *dcount[8] = {};  // group sizes in device memory (the pass is then sized on the device)
   int k[8];
 };
 
@@ -1342,8 +1382,12 @@ int band_passes(BandRun *runs, int nr) {
     bool zero = true;
     for (int b = 0; b < r.fp.nb; ++b) {
       if (r.fp.count[b] == 0) continue;
-      const int rc = band_pass(r.L, min(r.fp.k[b], r.T_max), r.T_max, r.w, r.fp.list[b], r.fp.count[b], 0, zero,
-                               r.T_dec, r.rule, r.stream);
+      const int kb = min(r.fp.k[b], r.T_max > 0 ? r.T_max : 1);
+      const int rc = r.fp.dcount[b] != nullptr
+                         ? band_pass_dev(r.L, kb, r.T_max, r.w, r.fp.list[b], r.fp.dcount[b], r.fp.count[b], 0, zero,
+                                         r.T_dec, r.rule, r.stream)
+                         : band_pass(r.L, min(r.fp.k[b], r.T_max), r.T_max, r.w, r.fp.list[b], r.fp.count[b], 0, zero,
+                                     r.T_dec, r.rule, r.stream);
       if (rc != MPD_OK) return rc;
       zero = false;
     }
@@ -1813,12 +1857,11 @@ int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_see
   r.syn = d_final_syndrome;
   r.stream = st;
   r.fp.nb = n_bins;
-  int *hc = pinned_counts(n_bins);
-  if (hc == nullptr) return fail_with(MPD_ERR_HIP, "could not allocate pinned host memory for the bin counters");
-  HIP_TRY(hipMemcpyAsync(hc, l.bin_count, n_bins * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  // the group sizes stay on the device: each group's first pass is sized
+  // there (no host wait before the first passes)
   for (int b = 0; b < n_bins; ++b) {
-    r.fp.count[b] = hc[b];
+    r.fp.count[b] = (int)n;
+    r.fp.dcount[b] = l.bin_count + b;
     r.fp.list[b] = l.lists + (int64_t)b * n;
     r.fp.k[b] = h_depth[b];
   }
