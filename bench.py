@@ -45,16 +45,29 @@ def kernel_source_sha():
     return hashlib.sha256(b"".join(parts)).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_band launch from the committed rocprofv3 counter summary,
-    or None if the kernel's code changed since the counters were taken."""
+def profile_summary():
+    """The committed rocprofv3 summary of k_band (HBM bytes per launch from the
+    calibrated FETCH_SIZE / WRITE_SIZE counters, VALU issue fraction of the
+    first pass from the SQ counters), or {} if the kernel's code changed since
+    the counters were taken."""
     try:
         with open(PROFILE_SUMMARY) as f:
             summ = json.load(f)
         sha = kernel_source_sha()
     except (OSError, ValueError):
-        return None
-    return summ["traffic_bytes_per_launch"] if summ.get("kernel_source_sha16") == sha else None
+        return {}
+    return summ if summ.get("kernel_source_sha16") == sha else {}
+
+
+def wilson(k, n, z=1.96):
+    """Wilson score interval of a binomial proportion k / n."""
+    if n == 0:
+        return [0.0, 1.0]
+    ph = k / n
+    d = 1 + z * z / n
+    c = (ph + z * z / (2 * n)) / d
+    h = z * ((ph * (1 - ph) / n + z * z / (4 * n * n)) ** 0.5) / d
+    return [max(0.0, c - h), min(1.0, c + h)]
 
 
 def main():
@@ -155,6 +168,7 @@ def main():
     site_updates = float(L * L * T_all.sum())
     samples_per_s = K * n / elapsed
     su_per_s = site_updates / elapsed
+    summ = profile_summary()
     algo_bytes_per_launch = BYTES_PER_SITE_UPDATE * site_updates / max(tile_launches, 1)
     avg_launch_s = tile_ms / 1e3 / max(tile_launches, 1)
     achieved = algo_bytes_per_launch / avg_launch_s / 1e9 if tile_launches else None
@@ -167,9 +181,15 @@ def main():
         tc = time.perf_counter()
         r = oracle.decode_seeds(L, P, s_cpu, T_MAX, want_sigma=False)
         tcpu = time.perf_counter() - tc
+        m1 = max(1, m // 16)
+        tc = time.perf_counter()
+        r1 = oracle.decode_seeds(L, P, s_cpu[:m1], T_MAX, threads=1, want_sigma=False)
+        tcpu1 = time.perf_counter() - tc
         cpu = {"value": m / tcpu, "unit": "samples/s", "cores": r["threads"], "kind": "oracle",
                "sample": f"first {m} samples of batch 0 (same L, p, T_max), {tcpu:.1f} s wall",
-               "site_updates_per_s": float(L * L * r["T_dec"].astype(np.int64).sum()) / tcpu}
+               "site_updates_per_s": float(L * L * r["T_dec"].astype(np.int64).sum()) / tcpu,
+               "one_core": {"value": m1 / tcpu1, "unit": "samples/s", "cores": r1["threads"],
+                            "sample": f"first {m1} samples of batch 0, {tcpu1:.1f} s wall"}}
 
     line = {
         "metric": METRIC,
@@ -192,13 +212,26 @@ def main():
         "site_updates_per_s": su_per_s,
         "mean_T_dec": float(T_all.mean()),
         "max_T_dec": int(T_all.max()),
+        "T_dec_histogram": {str(int(t)): int(c) for t, c in zip(*np.unique(T_all, return_counts=True))},
         "fail_rate": float((F_all & 1).mean()),
+        "fail_rate_wilson95": wilson(int((F_all & 1).sum()), int(F_all.size)),
         "timeouts": int(((F_all & 2) > 0).sum()),
         "roofline": {"bound": "hbm", "kernel": "k_band",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": summ.get(
+                         "traffic_bytes_per_launch"),
+                     "achieved_basis": "modelled effective bandwidth: 16.25 B of algorithmic state traffic per "
+                                       "useful site-update (registers and syndrome read and written once per "
+                                       "decoder step) over the measured launch time; temporal blocking keeps the "
+                                       "state on chip for several steps, so the HBM bytes actually moved are "
+                                       "'traffic' (rocprofv3 counters)",
+                     "measured_hbm_GBps": (summ["traffic_bytes_per_launch"] / avg_launch_s / 1e9)
+                     if summ.get("traffic_bytes_per_launch") and tile_launches else None,
+                     "valu_issue_frac_first_pass": summ.get("valu_issue_frac_first_pass"),
+                     "binding_unit": "VALU issue (SQ counters)" if summ.get("valu_issue_frac_first_pass") else None,
                      "bytes_per_site_update": BYTES_PER_SITE_UPDATE,
                      "launches": tile_launches, "avg_launch_ms": avg_launch_s * 1e3},
+        "kernel_source_sha16": kernel_source_sha(),
         "cpu_baseline": cpu,
         "device_driver": device_leg,
         "learned_sched": learned_leg,
@@ -313,8 +346,11 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
     policy, t_best, t_single, res = learned.tune_policy(L_eval, P, tune, params, reps=2)
     lwss = [b.learned_workspace(L_eval, n) for _ in runner.streams]
     tune_set = [(torch.from_numpy(seeds(3, 201 + i, n).view(np.int64)).to(dev), P) for i in range(6)]
-    policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
+    policy, net_policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
     louts = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+              torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev), None)
+             for _ in range(W + K)]
+    nouts = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
               torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev), None)
              for _ in range(W + K)]
 
@@ -322,12 +358,17 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
         b.decode_learned(L_eval, P, batches[i], params, policy[0], policy[1], T_MAX, workspace=lwss[j],
                          out=louts[i], stream=stream)
 
+    def net_on(i, j, stream):
+        b.decode_learned(L_eval, P, batches[i], params, net_policy[0], net_policy[1], T_MAX, workspace=lwss[j],
+                         out=nouts[i], stream=stream)
+
     def fifo(i, j, stream):
         b.decode_batch(L_eval, P, batches[i], T_MAX, workspace=fifo_ws[j], out=outs[i], stream=stream)
 
     fifo_ws = [b.alloc_workspace(L_eval, n) for _ in runner.streams]
     runner.run(learned, range(W))
-    el_fifo, el = alternate(runner, fifo, learned, W, K)
+    runner.run(net_on, range(W))
+    el_fifo, el, el_net = alternate(runner, [fifo, learned, net_on], W, K)
     # the evaluation samples' predictions (outside the timed region; a
     # one-group policy does not compute them) and the inference time per
     # batch, one stream
@@ -336,13 +377,17 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
     torch.cuda.synchronize()
     b.profile(False)
     cnn_ms, cnn_n = b.profile_read("k_cnn_forward")
-    same = all(torch.equal(outs[i][j], louts[i][j]) for i in range(W, W + K) for j in range(3))
+    same = all(torch.equal(outs[i][j], louts[i][j]) and torch.equal(outs[i][j], nouts[i][j])
+               for i in range(W, W + K) for j in range(3))
     T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy()
     pred = torch.cat(preds).cpu().numpy()
     y = np.log1p(T)
     mixed = learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval)
     return {"samples_per_s": K * n / el, "ms_per_step": el / K * 1e3, "ratio_vs_fifo": el_fifo / el,
+            "fifo_samples_per_s": K * n / el_fifo,
             "identical_results": bool(same), "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])},
+            "network_on": {"policy": {"edges": list(net_policy[0]), "first_pass_depth": list(net_policy[1])},
+                           "samples_per_s": K * n / el_net, "ratio_vs_fifo": el_fifo / el_net},
             "cnn_forward_ms_per_step": cnn_ms / max(cnn_n, 1), "train_s": t_train,
             "train_mse_last_epoch": hist[-1], "eval_mae_ln": float(np.abs(pred - y).mean()),
             "eval_spearman": float(spearmanr(pred, T).correlation),
@@ -353,8 +398,8 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
 def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=12):
     """Re-times the policies that were fastest one batch at a time, and the
     single-group policy, with the runner's batches in flight (the way the
-    decode is used), on a set of tuning batches; returns (best policy,
-    {policy: ms per batch})."""
+    decode is used), on a set of tuning batches; returns (best policy, best
+    policy that runs the network, {policy: ms per batch})."""
     n = tune_set[0][0].numel()
     dev = tune_set[0][0].device
     outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None,
@@ -369,18 +414,20 @@ def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=
         t = min(runner.run(run, range(len(tune_set))) for _ in range(2))
         times[pol] = t / len(tune_set) * 1e3
     best = min(times, key=times.get)
-    return best, {f"{list(p[0])}/{list(p[1])}": t for p, t in times.items()}
+    net = [p for p in times if len(p[1]) > 1]
+    best_net = min(net, key=times.get) if net else best
+    return best, best_net, {f"{list(p[0])}/{list(p[1])}": t for p, t in times.items()}
 
 
-def alternate(runner, fn_a, fn_b, W, K, rounds=3):
-    """Times fn_a and fn_b over batches W..W+K-1 in alternating rounds (so
-    that drift of the device clock falls on both alike); returns the mean
-    wall time of one round of each."""
-    ta = tb = 0.0
+def alternate(runner, fns, W, K, rounds=5):
+    """Times each function of `fns` over batches W..W+K-1 in alternating
+    rounds (so that drift of the device clock falls on all alike); returns
+    the mean wall time of one round of each."""
+    tot = [0.0] * len(fns)
     for _ in range(rounds):
-        ta += runner.run(fn_a, range(W, W + K))
-        tb += runner.run(fn_b, range(W, W + K))
-    return ta / rounds, tb / rounds
+        for k, fn in enumerate(fns):
+            tot[k] += runner.run(fn, range(W, W + K))
+    return [t / rounds for t in tot]
 
 
 def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
@@ -407,13 +454,15 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
            torch.empty(n * b.syndrome_words(L_eval), dtype=torch.int32, device=dev)) for _ in range(W + K)]
     lo = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
            torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev), None) for _ in range(W + K)]
+    no = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+           torch.empty((n, b.syndrome_words(L_eval)), dtype=torch.int32, device=dev), None) for _ in range(W + K)]
     b.set_band_schedule(k_fifo, kn, L_eval)
     try:
         policy, _, _, res = learned.tune_policy(L_eval, tune_p, tune_s, params, T_MAX, k_first=k_fifo, reps=2,
                                                 wide=True)
         tune_set = [(torch.from_numpy(seeds(3, 250 + i, n).view(np.int64)).to(dev),
                      torch.from_numpy(rng.uniform(pr[0], pr[1], n)).to(dev)) for i in range(6)]
-        policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
+        policy, net_policy, in_flight = tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch)
 
         def fifo(i, j, stream):
             b.decode_mixed([(L_eval, n)], ps[i], bs[i], T_MAX, workspace=wss[j], out=fo[i], stream=stream)
@@ -422,13 +471,18 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
             b.decode_learned(L_eval, ps[i], bs[i], params, policy[0], policy[1], T_MAX, workspace=lwss[j],
                              out=lo[i], stream=stream)
 
+        def net_on(i, j, stream):
+            b.decode_learned(L_eval, ps[i], bs[i], params, net_policy[0], net_policy[1], T_MAX, workspace=lwss[j],
+                             out=no[i], stream=stream)
+
         runner.run(fifo, range(W))
         runner.run(lrn, range(W))
-        el_fifo, el_lrn = alternate(runner, fifo, lrn, W, K)
+        runner.run(net_on, range(W))
+        el_fifo, el_lrn, el_net = alternate(runner, [fifo, lrn, net_on], W, K)
     finally:
         b.set_band_schedule(k0, kn, L_eval)
-    same = all(torch.equal(fo[i][0], lo[i][0]) and torch.equal(fo[i][1], lo[i][1]) and
-               torch.equal(fo[i][2], lo[i][2].reshape(-1)) for i in range(W, W + K))
+    same = all(torch.equal(fo[i][0], x[i][0]) and torch.equal(fo[i][1], x[i][1]) and
+               torch.equal(fo[i][2], x[i][2].reshape(-1)) for i in range(W, W + K) for x in (lo, no))
     T = torch.cat([fo[i][0] for i in range(W, W + K)]).cpu().numpy()
     pred = torch.cat([b.cnn_forward(b.syndrome_counts(L_eval, ps[i], bs[i]), params)
                       for i in range(W, W + K)]).cpu().numpy()
@@ -436,6 +490,8 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
             "learned_samples_per_s": K * n / el_lrn, "ratio_vs_fifo": el_fifo / el_lrn,
             "fifo_first_pass_depth": k_fifo, "fifo_tuning_ms": {str(k): t * 1e3 for k, t in fifo_times.items()},
             "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])}, "tuning_ms_in_flight": in_flight,
+            "network_on": {"policy": {"edges": list(net_policy[0]), "first_pass_depth": list(net_policy[1])},
+                           "samples_per_s": K * n / el_net, "ratio_vs_fifo": el_fifo / el_net},
             "eval_spearman": float(spearmanr(pred, T).correlation), "identical_results": bool(same)}
 
 
@@ -674,9 +730,9 @@ def learned_c5(args, b, seeds, torch, np, runner):
         lwss = [b.learned_workspace(Lc, n) for _ in range(S)]
         tune_set = [(torch.from_numpy(seeds(5, 200 + pidx, n, start=i * n).view(np.int64)).to(dev), P)
                     for i in range(6)]
-        policy, _ = tune_in_flight(b, runner, Lc, tune_set, params, tres, lwss, torch)
+        policy, net_policy, _ = tune_in_flight(b, runner, Lc, tune_set, params, tres, lwss, torch)
         outs = {name: [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
-                        None, None) for _ in range(W + K)] for name in ("fifo", "learned")}
+                        None, None) for _ in range(W + K)] for name in ("fifo", "learned", "network_on")}
 
         def fifo(i, j, stream):
             b.decode_batch(Lc, P, batches[i], T_MAX, want_syndrome=False, workspace=wss[j],
@@ -686,17 +742,26 @@ def learned_c5(args, b, seeds, torch, np, runner):
             b.decode_learned(Lc, P, batches[i], params, policy[0], policy[1], T_MAX, want_syndrome=False,
                              workspace=lwss[j], out=outs["learned"][i], stream=stream)
 
+        def net_on(i, j, stream):
+            b.decode_learned(Lc, P, batches[i], params, net_policy[0], net_policy[1], T_MAX, want_syndrome=False,
+                             workspace=lwss[j], out=outs["network_on"][i], stream=stream)
+
         runner.run(fifo, range(W))
         runner.run(lrn, range(W))
-        el_fifo, el_lrn = alternate(runner, fifo, lrn, W, K)
+        runner.run(net_on, range(W))
+        el_fifo, el_lrn, el_net = alternate(runner, [fifo, lrn, net_on], W, K)
         res = {"fifo": (el_fifo, outs["fifo"]), "learned": (el_lrn, outs["learned"])}
-        same = all(torch.equal(a[0], c[0]) and torch.equal(a[1], c[1])
-                   for a, c in zip(res["fifo"][1][W:], res["learned"][1][W:]))
+        same = all(torch.equal(a[0], c[0]) and torch.equal(a[1], c[1]) and torch.equal(a[0], d[0])
+                   and torch.equal(a[1], d[1])
+                   for a, c, d in zip(res["fifo"][1][W:], res["learned"][1][W:], outs["network_on"][W:]))
         print(json.dumps({"workload": f"config 5: L={Lc} p={P} {n} samples, plain vs learned scheduling",
                           "fifo_samples_per_s": K * n / res["fifo"][0],
                           "learned_samples_per_s": K * n / res["learned"][0],
                           "ratio": res["fifo"][0] / res["learned"][0], "identical_results": same,
                           "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])},
+                          "network_on": {"policy": {"edges": list(net_policy[0]),
+                                                    "first_pass_depth": list(net_policy[1])},
+                                         "samples_per_s": K * n / el_net, "ratio": el_fifo / el_net},
                           "concurrent_batches": S}), flush=True)
 
 
