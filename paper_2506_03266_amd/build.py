@@ -18,7 +18,8 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
-    # keep the compiler from emitting packed-FP32 instructions
+    # keep the device pass from emitting packed-FP32 instructions (v_pk_*_f32);
+    # the host pass warns that it does not know the feature, which is harmless
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

@@ -42,38 +42,97 @@ def make_dataset(n: int, L: int = 256, p_range=P_RANGE, config: int = TRAIN_CONF
     return counts, target, T, p
 
 
+class HipTrainOps:
+    """The training step on the library's kernels: initial parameters,
+    loss gradient and Adam update, all in device memory (float32)."""
+
+    def __init__(self, M: int, batch: int, dev):
+        self.ws = b.train_workspace(M, batch, dev)
+        self.out = (torch.empty(1, dtype=torch.float32, device=dev),
+                    torch.empty(b.CNN_PARAMS, dtype=torch.float32, device=dev),
+                    torch.empty(batch, dtype=torch.float32, device=dev))
+        self.dev = dev
+
+    def init(self, seed):
+        params = b.cnn_init(seed)
+        return params, torch.zeros_like(params), torch.zeros_like(params)
+
+    def loss_grad(self, c, params, y):
+        loss, grad, _ = b.cnn_loss_grad(c, params, y, workspace=self.ws, out=self.out)
+        return loss, grad
+
+    def adam(self, params, grad, m, v, step, lr):
+        b.cnn_adam_step(params, grad, m, v, step, lr)
+        return params, m, v
+
+    def to_device(self, t):
+        return t.to(self.dev, dtype=torch.float32).contiguous()
+
+
+def save_checkpoint(path: str, params, m, v, step: int, epoch: int, gen: torch.Generator, hist):
+    """Training state after a whole epoch: master weights and Adam moments
+    (as held, float32 on the device), the update count, the epoch count, the
+    data-order generator's state and the epoch losses (safetensors: no code
+    is executed when it is read back)."""
+    from safetensors.torch import save_file
+    t = lambda x: torch.as_tensor(x).detach().to("cpu").contiguous()
+    save_file({"params": t(params), "m": t(m), "v": t(v), "step": torch.tensor([step], dtype=torch.int64),
+               "epoch": torch.tensor([epoch], dtype=torch.int64), "gen_state": gen.get_state(),
+               "hist": torch.tensor(hist, dtype=torch.float64)}, path)
+
+
+def load_checkpoint(path: str):
+    from safetensors.torch import load_file
+    return load_file(path)
+
+
 def train(counts, target, epochs: int = 8, batch: int = 256, lr: float = 2e-3, seed: int = 1,
-          lr_final: float = 2e-4, log=None):
+          lr_final: float = 2e-4, log=None, checkpoint: str | None = None, resume: str | None = None,
+          stop_after: int | None = None, ops=None):
     """Adam on the mean squared error of ln(1 + T_dec); cosine learning-rate
-    decay from lr to lr_final.  Returns (params, history of epoch losses)."""
+    decay from lr to lr_final.  Returns (params, history of epoch losses).
+
+    checkpoint: a path rewritten after every epoch with the training state
+    (save_checkpoint); resume: such a file to continue from, which gives the
+    same result, bit for bit, as the run that was not interrupted (the data
+    order comes from the saved generator state, the schedule from the saved
+    step count); stop_after: return after this many epochs of the schedule
+    (an interrupted run).  ops: the step operations (HipTrainOps by
+    default)."""
     n, M = counts.shape[0], counts.shape[-1]
     dev = counts.device
-    params = b.cnn_init(seed)
-    m = torch.zeros_like(params)
-    v = torch.zeros_like(params)
-    ws = b.train_workspace(M, batch, dev)
-    out = (torch.empty(1, dtype=torch.float32, device=dev), torch.empty(b.CNN_PARAMS, dtype=torch.float32, device=dev),
-           torch.empty(batch, dtype=torch.float32, device=dev))
+    ops = HipTrainOps(M, batch, dev) if ops is None else ops
     g = torch.Generator(device="cpu").manual_seed(seed)
     steps_per_epoch = n // batch
     total = epochs * steps_per_epoch
     step = 0
+    ep0 = 0
     hist = []
-    for ep in range(epochs):
+    if resume is not None:
+        st = load_checkpoint(resume)
+        params, m, v = (ops.to_device(st[k]) for k in ("params", "m", "v"))
+        step, ep0 = int(st["step"][0]), int(st["epoch"][0])
+        g.set_state(st["gen_state"])
+        hist = [float(x) for x in st["hist"]]
+    else:
+        params, m, v = ops.init(seed)
+    for ep in range(ep0, epochs if stop_after is None else min(epochs, stop_after)):
         perm = torch.randperm(n, generator=g).to(dev)
-        acc = torch.zeros(1, dtype=torch.float32, device=dev)
+        acc = 0.0
         for i in range(steps_per_epoch):
             idx = perm[i * batch:(i + 1) * batch]
             c = counts.index_select(0, idx)
             y = target.index_select(0, idx)
-            loss, grad, _ = b.cnn_loss_grad(c, params, y, workspace=ws, out=out)
-            acc += loss
+            loss, grad = ops.loss_grad(c, params, y)
+            acc = acc + loss
             step += 1
             lr_t = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * step / total))
-            b.cnn_adam_step(params, grad, m, v, step, lr_t)
-        hist.append(float(acc.item()) / steps_per_epoch)
+            params, m, v = ops.adam(params, grad, m, v, step, lr_t)
+        hist.append(float(acc.item() if torch.is_tensor(acc) else acc) / steps_per_epoch)
         if log:
             log(f"epoch {ep}: train mse {hist[-1]:.5f}")
+        if checkpoint is not None:
+            save_checkpoint(checkpoint, params, m, v, step, ep + 1, g, hist)
     return params, hist
 
 

@@ -368,3 +368,23 @@ def test_learned_timeouts_in_different_passes(gpu, orc, depths, T_max):
     assert np.array_equal(F.cpu().numpy(), ref["flags"])
     assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"])
     assert (F.cpu().numpy() & 2).sum() > 0  # some timeouts
+
+
+def test_training_resume_bitwise(gpu, tmp_path):
+    """Predictor training on the library's kernels, interrupted after one
+    epoch and resumed from its checkpoint, ends bit for bit where the
+    uninterrupted run ends (deterministic gradient reduction, saved
+    moments, step count and data order)."""
+    import os
+    from paper_2506_03266_amd import learned
+    n = 1024
+    counts = gpu.syndrome_counts(256, 0.01, seeds(57, 0, n))
+    target = (torch.from_numpy(np.random.default_rng(57).uniform(1.0, 2.0, n)).float()).cuda()
+    kw = dict(epochs=2, batch=256, seed=2)
+    p_full, h_full = learned.train(counts, target, **kw)
+    ck = os.path.join(tmp_path, "train.safetensors")
+    p_cut, _ = learned.train(counts, target, checkpoint=ck, stop_after=1, **kw)
+    p_res, h_res = learned.train(counts, target, resume=ck, **kw)
+    assert torch.equal(p_res, p_full)
+    assert h_res == h_full
+    assert not torch.equal(p_cut, p_full)
