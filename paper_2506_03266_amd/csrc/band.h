@@ -21,13 +21,20 @@ namespace mpd {
 // read 0 (bound_ctrl), which lets the compiler fold the shift into the
 // consuming instruction; those edge lanes only feed the halo.
 constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i <- lane i+1
+constexpr int DPP_WAVE_ROL1 = 0x134;  // lane i <- lane i+1 mod 64
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i <- lane i-1
+constexpr int DPP_WAVE_ROR1 = 0x13C;  // lane i <- lane i-1 mod 64
 
+// Neighbour lanes' values.  ROT: the wave is periodic (a region that spans
+// the lattice's width with 64 lanes, the torus wrap in x); otherwise the
+// edge lanes read 0 and only feed a halo.
+template <bool ROT = false>
 __device__ __forceinline__ uint32_t from_left(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, DPP_WAVE_SHR1, 0xF, 0xF, true);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ROT ? DPP_WAVE_ROR1 : DPP_WAVE_SHR1, 0xF, 0xF, !ROT);
 }
+template <bool ROT = false>
 __device__ __forceinline__ uint32_t from_right(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, DPP_WAVE_SHL1, 0xF, 0xF, true);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ROT ? DPP_WAVE_ROL1 : DPP_WAVE_SHL1, 0xF, 0xF, !ROT);
 }
 
 // low 16 bits from a, high 16 bits from b
@@ -127,7 +134,7 @@ __device__ __forceinline__ void band_boundary_fold(BandLane<H> &b, uint32_t ss, 
 // slot for boundary rows: [wave][2][64] of (P0, Q0, P1, Q1).  With DECIDE
 // (last sub-step of a decoder step) the moves of the anyons in the rows
 // flagged in `rows` are decided from the new values as each row completes.
-template <int H, bool DECIDE>
+template <int H, bool DECIDE, bool ROT = false>
 __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, int wdn, int wup, int lane,
                                              uint32_t rows, uint32_t ethr, Moves &mv) {
   BND[(w * 2 + 0) * 64 + lane] = make_uint4(b.P0[0], b.Q0[0], b.P1[0], b.Q1[0]);
@@ -140,11 +147,11 @@ __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, 
   uint32_t hq0m, hq1m, hq0c, hq1c;
   {
     const uint32_t t = pmax(dn.y, dn.w);
-    hq0m = pmax(t, from_left(dn.w));
-    hq1m = pmax(t, from_right(dn.y));
+    hq0m = pmax(t, from_left<ROT>(dn.w));
+    hq1m = pmax(t, from_right<ROT>(dn.y));
     const uint32_t t2 = pmax(b.Q0[0], b.Q1[0]);
-    hq0c = pmax(t2, from_left(b.Q1[0]));
-    hq1c = pmax(t2, from_right(b.Q0[0]));
+    hq0c = pmax(t2, from_left<ROT>(b.Q1[0]));
+    hq1c = pmax(t2, from_right<ROT>(b.Q0[0]));
   }
   // vertical max of P over rows h-1..h+1 as max of the pair maxima
   // (h-1, h) and (h, h+1): the old P of row h is then dead before its new
@@ -161,15 +168,15 @@ __device__ __forceinline__ void band_substep(BandLane<H> &b, uint4 *BND, int w, 
     const uint32_t q0n = h < last ? b.Q0[hn] : up.y;
     const uint32_t q1n = h < last ? b.Q1[hn] : up.w;
     const uint32_t tn = pmax(q0n, q1n);
-    const uint32_t hq0n = pmax(tn, from_left(q1n));
-    const uint32_t hq1n = pmax(tn, from_right(q0n));
+    const uint32_t hq0n = pmax(tn, from_left<ROT>(q1n));
+    const uint32_t hq1n = pmax(tn, from_right<ROT>(q0n));
     const uint32_t pn0 = pmax(b.P0[h], p0n), pn1 = pmax(b.P1[h], p1n);
     const uint32_t vm0 = pmax(pm0, pn0);  // vertical max, column 2i
     const uint32_t vm1 = pmax(pm1, pn1);  // vertical max, column 2i+1
     pm0 = pn0;
     pm1 = pn1;
-    b.P0[h] = lohi(from_left(vm1), vm1);   // +x from column 2i-1, -x from 2i+1
-    b.P1[h] = lohi(vm0, from_right(vm0));  // +x from column 2i, -x from 2i+2
+    b.P0[h] = lohi(from_left<ROT>(vm1), vm1);   // +x from column 2i-1, -x from 2i+1
+    b.P1[h] = lohi(vm0, from_right<ROT>(vm0));  // +x from column 2i, -x from 2i+2
     b.Q0[h] = lohi(hq0m, hq0n);            // +y from the row below, -y from above
     b.Q1[h] = lohi(hq1m, hq1n);
     hq0m = hq0c;
@@ -206,7 +213,7 @@ __device__ __forceinline__ void band_random_moves(const BandLane<H> &b, uint32_t
 // used to pass the y-moves across wave boundaries.  xo[c] receives the
 // flipped x-links to the right of column c, yo[c] the flipped y-links above
 // each row of column c.
-template <int H>
+template <int H, bool ROT = false>
 __device__ __forceinline__ void band_feedback(BandLane<H> &b, const Moves &mv, uint2 *MB, int w, int wdn,
                                               int wup, int lane, uint32_t (&xo)[2], uint32_t (&yo)[2]) {
   static_assert(H <= 16, "move masks hold 16 rows per column");
@@ -217,8 +224,8 @@ __device__ __forceinline__ void band_feedback(BandLane<H> &b, const Moves &mv, u
   constexpr uint32_t F = full_mask<H>();
   // x-links: column 2i -> 2i+1 and column 2i+1 -> 2i+2 (next lane's column 2i)
   xo[0] = (mv.px | (mv.mx >> 16)) & F;
-  xo[1] = ((mv.px >> 16) | from_right(mv.mx)) & F;
-  const uint32_t xl0 = from_left(xo[1]), xl1 = xo[0];
+  xo[1] = ((mv.px >> 16) | from_right<ROT>(mv.mx)) & F;
+  const uint32_t xl0 = from_left<ROT>(xo[1]), xl1 = xo[0];
   {
     const uint32_t py = mv.py & F, my = mv.my & F;
     const uint32_t yd = ((py << 1) | ((dnpy >> (H - 1)) & 1u) | my) & F;
