@@ -61,6 +61,9 @@ struct Moves {
 // of the chosen move; `anyon` gates it.
 __device__ __forceinline__ void decide_site(uint32_t P, uint32_t Q, bool anyon, uint32_t bit, uint32_t ethr,
                                             Moves &mv) {
+  // The row bit lives in an SGPR set where it is used: as a literal it would
+  // be materialised in a VGPR of its own per row and hoisted out of every loop.
+  asm volatile("" : "+s"(bit));
   const uint32_t T = pmax(P, Q);  // (max(+x, +y), max(-x, -y))
   const uint16_t M = max((uint16_t)T, (uint16_t)(T >> 16));
   const bool sx = (uint16_t)P == M, tx = (uint16_t)(P >> 16) == M;

@@ -124,11 +124,16 @@ template <int H, bool OPEN = false>
 __device__ __forceinline__ void substep(uint32_t (&P)[H], uint32_t (&Q)[H], uint32_t sig, uint32_t ss,
                                         uint2 *F, const Geo &g, bool inB = false) {
   const int RX = g.RX;
+  // Opaque copies of the column indices: every row address below is then
+  // formed where it is used instead of being hoisted out of the decoder loop
+  // (with a run-time row stride each row would hold its own address VGPRs).
+  int gc = g.c, gcl = g.cl, gcr = g.cr;
+  asm volatile("" : "+v"(gc), "+v"(gcl), "+v"(gcr));
   // publish the folded values: an anyon site reads as "emits now"
 #pragma unroll
   for (int h = 0; h < H; ++h) {
     const bool a = (sig >> h) & 1u;
-    F[(g.y0 + h) * RX + g.c] =
+    F[(g.y0 + h) * RX + gc] =
         (OPEN && inB) ? make_uint2(ss, 0u) : make_uint2(a ? ss : P[h], a ? ss : Q[h]);
   }
   __syncthreads();
@@ -138,14 +143,14 @@ __device__ __forceinline__ void substep(uint32_t (&P)[H], uint32_t (&Q)[H], uint
   //           -y from row above).
   uint32_t pl2, pl1, pr2, pr1, hq2, hq1;
   {
-    const uint2 a = F[g.rowDn * RX + g.cl], b = F[g.rowDn * RX + g.cr];
-    const uint32_t q = F[g.rowDn * RX + g.c].y;
+    const uint2 a = F[g.rowDn * RX + gcl], b = F[g.rowDn * RX + gcr];
+    const uint32_t q = F[g.rowDn * RX + gc].y;
     pl2 = a.x;
     pr2 = b.x;
     hq2 = pmax3(a.y, q, b.y);
   }
   {
-    const uint2 a = F[g.y0 * RX + g.cl], b = F[g.y0 * RX + g.cr];
+    const uint2 a = F[g.y0 * RX + gcl], b = F[g.y0 * RX + gcr];
     const uint32_t q = (sig & 1u) ? ss : Q[0];
     pl1 = a.x;
     pr1 = b.x;
@@ -157,13 +162,13 @@ __device__ __forceinline__ void substep(uint32_t (&P)[H], uint32_t (&Q)[H], uint
     uint32_t q;
     if (i <= H) {
       const int r = g.y0 + i - 1;
-      a = F[r * RX + g.cl];
-      b = F[r * RX + g.cr];
+      a = F[r * RX + gcl];
+      b = F[r * RX + gcr];
       q = ((sig >> (i - 1)) & 1u) ? ss : Q[i - 1];
     } else {
-      a = F[g.rowUp * RX + g.cl];
-      b = F[g.rowUp * RX + g.cr];
-      q = F[g.rowUp * RX + g.c].y;
+      a = F[g.rowUp * RX + gcl];
+      b = F[g.rowUp * RX + gcr];
+      q = F[g.rowUp * RX + gc].y;
     }
     const uint32_t pl0 = a.x, pr0 = b.x, hq0 = pmax3(a.y, q, b.y);
     const int h = i - 2;

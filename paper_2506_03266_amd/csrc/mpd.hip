@@ -502,8 +502,14 @@ __device__ __forceinline__ uint2 band_region(const BandArgs &a, int tile, int sa
   constexpr int H = BAND_H;
   constexpr uint32_t F = full_mask<H>();
   const int L = a.L;
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (scalar)
+  // Opaque thread index: in the kernels that run several regions per
+  // workgroup, every lane-dependent value (columns, addresses, ownership) is
+  // then formed anew per region instead of being kept live across the step
+  // loop, whose register working set is close to the budget.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (scalar)
   const int ks = min(a.k, a.T_max - t0);  // steps of this sample in this pass
   if (threadIdx.x < 16) AW[threadIdx.x] = 0u;
   if (threadIdx.x == 0) red[0] = 0u;
@@ -709,7 +715,13 @@ __global__ __launch_bounds__(NW * 64) void k_band_tail(TailArgs ta) {
       }
       for (int tile = 0; tile < ta.ntiles; ++tile) {
         __syncthreads();  // the LDS slots of the previous tile are no longer read
-        const uint2 r = band_region<NW, MODE>(a, tile, s, t0, ta.E[c], ta.S[c], ta.E[c ^ 1], ta.S[c ^ 1]);
+        // buffers chosen by selects: an index into the kernel-argument arrays
+        // would copy them to private memory
+        const uint4 *Ein = c ? ta.E[1] : ta.E[0];
+        uint4 *Eout = c ? ta.E[0] : ta.E[1];
+        const uint2 *Sin = c ? ta.S[1] : ta.S[0];
+        uint2 *Sout = c ? ta.S[0] : ta.S[1];
+        const uint2 r = band_region<NW, MODE>(a, tile, s, t0, Ein, Sin, Eout, Sout);
         if (threadIdx.x == 0) {
           s_bits |= r.x;
           s_wind ^= r.y;
