@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="batches in flight, each on its own stream, host thread and workspace (default 3 for "
                          "the L = 256 workloads c3/c5, 1 for the short batches of c1/c2/c4)")
+    ap.add_argument("--band-bits", type=int, default=None, metavar="K",
+                    help="steps of the bit-sliced first kernel at L=256 (0: the band path's first pass)")
     ap.add_argument("--band-driver", choices=["auto", "host", "device"], default="auto",
                     help="who drives the later passes of the band path (L >= 256): the host (a survivor-count "
                          "readback per pass) or the device (one persistent launch); auto = the library's choice")
@@ -119,6 +121,8 @@ def main():
 
     b.set_band_driver({"auto": b.BAND_DRIVER_AUTO, "host": b.BAND_DRIVER_HOST,
                        "device": b.BAND_DRIVER_DEVICE}[args.band_driver])
+    if args.band_bits is not None:
+        b.set_band_bits(args.band_bits)
 
     if args.copy_calib:
         nbytes = args.copy_calib << 20

@@ -372,6 +372,20 @@ int mpd_get_band_schedule(int L, int *k_first, int *k_next);
 int mpd_set_band_driver(int L, int driver);
 int mpd_get_band_driver(int L, int *driver);
 
+/* First steps of a plain seeded L = 256 batch in the bit-sliced kernel.
+ * During the first five decoder steps every emission time is at most 15, so
+ * the registers fit in 4-bit planes and a whole L = 256 torus fits in one
+ * workgroup (no halo, no HBM state); a sample leaves as soon as it has no
+ * anyon, and the others continue on the band path from the state it hands
+ * over.  k_bits in [0, 5]: the number of such steps (0: the band path's
+ * first pass instead).  Applies to mpd_decode_batch, mpd_decode_mixed and
+ * the one-group learned decode at L = 256 with the plain rule (Def.
+ * "message passing automaton, general dimensions"); results never depend on
+ * it.  L = 0 sets the default and every per-L setting (default 5).
+ * Process-wide, guarded by a mutex; MPD_ERR_TMAX outside [0, 5]. */
+int mpd_set_band_bits(int L, int k_bits);
+int mpd_get_band_bits(int L, int *k_bits);
+
 /* Autotuner for the band path: decodes the probe batch (same arguments as
  * mpd_decode_batch, outputs overwritten) once per candidate schedule
  * driver (host, device) x k_first in [2, 6] x k_next in [1, 4], timing each

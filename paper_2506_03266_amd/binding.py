@@ -67,6 +67,10 @@ def lib():
     L.mpd_set_band_driver.restype = I
     L.mpd_get_band_driver.argtypes = [I, P]
     L.mpd_get_band_driver.restype = I
+    L.mpd_set_band_bits.argtypes = [I, I]
+    L.mpd_set_band_bits.restype = I
+    L.mpd_get_band_bits.argtypes = [I, P]
+    L.mpd_get_band_bits.restype = I
     L.mpd_autotune_band.argtypes = [I, D, P, I64, I, P, P, P, SZ, P, P, P, P]
     L.mpd_autotune_band.restype = I
     L.mpd_mixed_workspace_bytes.argtypes = [I, P, P]
@@ -472,6 +476,19 @@ def get_band_driver(L: int = 0) -> int:
     d = ctypes.c_int(-1)
     _check(lib().mpd_get_band_driver(int(L), ctypes.byref(d)), "mpd_get_band_driver")
     return d.value
+
+
+def set_band_bits(k_bits: int, L: int = 0):
+    """Decoder steps of a plain L = 256 batch that run in the bit-sliced
+    whole-lattice kernel before the band passes (0..5; 0: the band path's
+    first pass instead); L = 0 sets the default and every per-L setting."""
+    _check(lib().mpd_set_band_bits(int(L), int(k_bits)), "mpd_set_band_bits")
+
+
+def get_band_bits(L: int = 0) -> int:
+    k = ctypes.c_int(-1)
+    _check(lib().mpd_get_band_bits(int(L), ctypes.byref(k)), "mpd_get_band_bits")
+    return k.value
 
 
 def save_band_tuning(path: str, Ls) -> dict:

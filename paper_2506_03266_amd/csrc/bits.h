@@ -1,0 +1,507 @@
+// bits.h -- bit-sliced whole-lattice kernel for the first decoder steps at
+// L = 256 (gfx950).
+//
+// While a decode is in its first five decoder steps every emission time is
+// at most 3 * 5 = 15 (registers hold emission times, see engine.h), so one
+// register fits in 4 bits.  Stored as bit planes -- one 32-bit word holds one
+// bit of one register for 32 consecutive rows of one column -- the whole
+// state of an L = 256 torus is 256 x 256 sites x 4 registers x 4 bits =
+// 128 KiB, which a workgroup of four waves keeps in VGPRs.  The first steps
+// then need no halo (the torus wraps inside the workgroup) and no HBM state,
+// a sample leaves as soon as it has no anyon, and the update works on 32
+// sites per instruction:
+//
+//  * Rule A^{(D)} of Def. "message passing automaton, general dimensions" in
+//    emission-time form is e'(r) = max over the 3-site line C of
+//    (sigma_q ? s : e_q).  The fold (anyon sites emit at the sub-step time
+//    s) is one select per plane; the 3-wide maximum of 4-bit values is a
+//    most-significant-bit-first candidate filter (19 bitwise operations for
+//    32 sites).
+//  * The move decision of eq. (degbreak) with the reading of engine.h (the
+//    largest emission time wins; ties in the order -y, -x, +x, +y; no move
+//    when the opposite register on that axis ties) is the same filter over
+//    the four registers of a site.
+//  * The feedback of eq. (ddfeedback) (a link flips iff one endpoint moves
+//    across it) and the syndrome update are bitwise on the masks.
+//
+// Layout: wave v holds rows 64v .. 64v + 63, lane i columns 4i .. 4i + 3;
+// word w of a column covers rows 64v + 32w .. + 31 (bit r = row 64v + 32w + r).
+// Vertical neighbours inside a lane are funnel shifts (v_alignbit); across
+// waves the edge rows travel through LDS packed 32 to a word, once per
+// sub-step (one barrier).  Horizontal neighbours are in the lane or one
+// wave-wide DPP rotation away (the wrap in x).
+//
+// A sample that still holds anyons after its steps leaves its state in the
+// band path's HBM layout (packed u16 emission times, 16-row syndrome masks),
+// from which the band kernels continue exactly.
+#pragma once
+
+#include "band.h"
+
+namespace mpd {
+
+constexpr int BITS_L = 256;
+constexpr int BITS_CPL = 4;          // columns per lane
+constexpr int BITS_NW = 4;           // waves (64 rows each)
+constexpr int BITS_MAX_STEPS = 5;    // emission times <= 15 fit in 4 bits
+
+struct BitsArgs {
+  const uint64_t *seeds;
+  uint64_t thr;          // flip threshold floor(p 2^32) when p_arr == nullptr
+  const double *p_arr;   // per-sample noise strength or nullptr
+  int k;                 // decoder steps at most (<= BITS_MAX_STEPS and <= T_max)
+  uint4 *E;              // band layout [n][L][L/2] register pairs (samples with anyons left)
+  uint2 *S;              // band layout [n][L/16][L/2] syndrome masks
+  uint32_t *alive;       // per sample: bit 0 anyons at the start, bit j anyons after step j
+  uint32_t *wind;        // per sample: Wx(E), Wy(E), Wx(C), Wy(C)
+  int *zero_count;       // survivor counter of the following compaction (cleared here)
+};
+
+// Bit planes of one 4-bit register field, most significant plane last.
+struct V4 {
+  uint32_t p[4];
+};
+
+// Site-wise maximum of three 4-bit fields: the planes from the top, keeping
+// per operand a mask of the sites where it still equals the running maximum.
+__device__ __forceinline__ V4 max3v(const V4 &a, const V4 &b, const V4 &c) {
+  V4 r;
+  r.p[3] = a.p[3] | b.p[3] | c.p[3];
+  uint32_t ka = a.p[3] | ~r.p[3], kb = b.p[3] | ~r.p[3], kc = c.p[3] | ~r.p[3];
+#pragma unroll
+  for (int q = 2; q >= 0; --q) {
+    r.p[q] = (a.p[q] & ka) | (b.p[q] & kb) | (c.p[q] & kc);
+    if (q > 0) {
+      ka &= a.p[q] | ~r.p[q];
+      kb &= b.p[q] | ~r.p[q];
+      kc &= c.p[q] | ~r.p[q];
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t s) {
+  return __builtin_amdgcn_alignbit(hi, lo, s);  // ({hi, lo} >> s)[31:0]
+}
+
+// A copy of x that the compiler cannot see through: values derived from it
+// are formed where they are used instead of being hoisted (and kept live)
+// ahead of a long stretch of code.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+struct BitsLane {
+  uint32_t E[4][4][BITS_CPL][2];  // [register: +x, -x, +y, -y][bit][column][word]
+  uint32_t S[BITS_CPL][2];        // syndrome (anyon = 1)
+};
+
+// Vertical maximum over rows y - 1, y, y + 1 of register d, column c: r0/r1
+// for words 0/1.  cdn: words whose bit 31 is the register's plane at the row
+// below word 0; cup: words whose bit 0 is the plane at the row above word 1.
+__device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, const uint32_t (&cdn)[4],
+                                          const uint32_t (&cup)[4], V4 &r0, V4 &r1) {
+  V4 x0, x1, dn, up;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    x0.p[q] = s.E[d][q][c][0];
+    x1.p[q] = s.E[d][q][c][1];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    dn.p[q] = fshr(x0.p[q], cdn[q], 31);   // row y - 1
+    up.p[q] = fshr(x1.p[q], x0.p[q], 1);   // row y + 1
+  }
+  r0 = max3v(dn, x0, up);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    dn.p[q] = fshr(x1.p[q], x0.p[q], 31);
+    up.p[q] = fshr(cup[q], x1.p[q], 1);
+  }
+  r1 = max3v(dn, x1, up);
+}
+
+// One application of A^{(D)} at sub-step time ss (1 .. 15) to the whole
+// lattice.  XS: this sub-step's exchange slot [wave][64] of (up0, up1, dn0,
+// dn1): up words carry a wave's top row to the wave above, dn words its
+// bottom row to the wave below.  Packed items: ±x planes (d, q, c) at index
+// j = (4d + q) 4 + c (up0: bit 31 - j, dn0: bit j); the row maxima of +y
+// (up1, bit 15 - j') and of -y (dn1, bit 16 + j'), j' = 4q + c.
+__device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS, int v, int vdn, int vup,
+                                             int lane) {
+  // anyon sites emit now: their registers read ss
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t M = ((ss >> q) & 1u) ? ~0u : 0u;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c)
+#pragma unroll
+        for (int w = 0; w < 2; ++w)  // S ? M : E (one v_bitop3; M is uniform)
+          s.E[d][q][c][w] = __builtin_amdgcn_bitop3_b32(M, s.E[d][q][c][w], s.S[c][w], 0xE4);
+  }
+
+  // ±x edge rows for the neighbour waves (folded values, before the update)
+  uint32_t up0 = 0u, dn0 = 0u, up1 = 0u, dn1 = 0u;
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c) {
+        up0 = fshr(up0, s.E[d][q][c][1], 31);  // shift in bit 31 (top row)
+        dn0 = fshr(s.E[d][q][c][0], dn0, 1);   // shift in bit 0 (bottom row)
+      }
+
+  // ±y: maxima over columns c - 1 .. c + 1 of the row (in place), then the
+  // shift by one row within the lane; the cross-wave bit follows the barrier
+#pragma unroll
+  for (int d = 2; d < 4; ++d) {
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      V4 left, right, prev;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        left.p[q] = from_left<true>(s.E[d][q][BITS_CPL - 1][w]);  // lane i - 1, last column
+        right.p[q] = from_right<true>(s.E[d][q][0][w]);           // lane i + 1, first column
+      }
+      prev = left;
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c) {
+        V4 cur, nxt;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cur.p[q] = s.E[d][q][c][w];
+          nxt.p[q] = c + 1 < BITS_CPL ? s.E[d][q][c + 1][w] : right.p[q];
+        }
+        const V4 h = max3v(prev, cur, nxt);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s.E[d][q][c][w] = h.p[q];
+        prev = cur;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c) {
+        const uint32_t h0 = s.E[d][q][c][0], h1 = s.E[d][q][c][1];
+        if (d == 2) {  // +y reads the row below: word 1 now, word 0 after the exchange
+          up1 = fshr(up1, h1, 31);
+          s.E[d][q][c][1] = fshr(h1, h0, 31);
+        } else {  // -y reads the row above: word 0 now, word 1 after the exchange
+          dn1 = fshr(h0, dn1, 1);
+          s.E[d][q][c][0] = fshr(h1, h0, 1);
+        }
+      }
+  }
+
+  XS[v * 64 + lane] = make_uint4(up0, up1, dn0, dn1);
+  __syncthreads();
+  const uint4 B = XS[vdn * 64 + lane];  // top row of the wave below
+  const uint4 A = XS[vup * 64 + lane];  // bottom row of the wave above
+
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < BITS_CPL; ++c) {
+      const int j = 4 * q + c;
+      s.E[2][q][c][0] = fshr(s.E[2][q][c][0], opaque(B.y) << (16 + j), 31);
+      s.E[3][q][c][1] = fshr(opaque(A.w) >> (16 + j), s.E[3][q][c][1], 1);
+    }
+
+  // +x: column c reads the vertical maxima of column c - 1
+  {
+    V4 r0, r1, h0, h1;
+    uint32_t cdn[4], cup[4];
+    constexpr int d = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + BITS_CPL - 1);
+      cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + BITS_CPL - 1);
+    }
+    bits_vmax(s, d, BITS_CPL - 1, cdn, cup, r0, r1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h0.p[q] = from_left<true>(r0.p[q]);
+      h1.p[q] = from_left<true>(r1.p[q]);
+    }
+#pragma unroll
+    for (int c = BITS_CPL - 1; c >= 1; --c) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + c - 1);
+        cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + c - 1);
+      }
+      bits_vmax(s, d, c - 1, cdn, cup, r0, r1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        s.E[d][q][c][0] = r0.p[q];
+        s.E[d][q][c][1] = r1.p[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s.E[d][q][0][0] = h0.p[q];
+      s.E[d][q][0][1] = h1.p[q];
+    }
+  }
+  // -x: column c reads the vertical maxima of column c + 1
+  {
+    V4 r0, r1, h0, h1;
+    uint32_t cdn[4], cup[4];
+    constexpr int d = 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + 0);
+      cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + 0);
+    }
+    bits_vmax(s, d, 0, cdn, cup, r0, r1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h0.p[q] = from_right<true>(r0.p[q]);
+      h1.p[q] = from_right<true>(r1.p[q]);
+    }
+#pragma unroll
+    for (int c = 0; c + 1 < BITS_CPL; ++c) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + c + 1);
+        cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + c + 1);
+      }
+      bits_vmax(s, d, c + 1, cdn, cup, r0, r1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        s.E[d][q][c][0] = r0.p[q];
+        s.E[d][q][c][1] = r1.p[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s.E[d][q][BITS_CPL - 1][0] = h0.p[q];
+      s.E[d][q][BITS_CPL - 1][1] = h1.p[q];
+    }
+  }
+}
+
+// Moves of the anyons of one column word from the registers after the last
+// sub-step of a step (see decide_site in band.h).
+__device__ __forceinline__ void bits_decide(const BitsLane &s, int c, int w, uint32_t &px, uint32_t &mx,
+                                            uint32_t &py, uint32_t &my) {
+  uint32_t k[4];
+  uint32_t m = s.E[0][3][c][w] | s.E[1][3][c][w] | s.E[2][3][c][w] | s.E[3][3][c][w];
+  uint32_t nz = m;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) k[d] = s.E[d][3][c][w] | ~m;
+#pragma unroll
+  for (int q = 2; q >= 0; --q) {
+    m = (s.E[0][q][c][w] & k[0]) | (s.E[1][q][c][w] & k[1]) | (s.E[2][q][c][w] & k[2]) | (s.E[3][q][c][w] & k[3]);
+    nz |= m;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) k[d] &= s.E[d][q][c][w] | ~m;
+  }
+  // k[d]: register d holds the site's largest emission time
+  const uint32_t ok = s.S[c][w] & nz;
+  const uint32_t sx = k[0], tx = k[1], sy = k[2], ty = k[3];
+  py = ok & ty & ~sy;
+  px = ok & ~ty & tx & ~sx;
+  mx = ok & ~ty & ~tx & sx;
+  my = ok & ~ty & ~tx & ~sx;
+}
+
+// Feedback of one decoder step: moves, OR'd link flips, syndrome update and
+// the correction's winding bits (x-links leaving column L - 1: bit 2; y-links
+// leaving row L - 1: bit 3).  Columns are decided one at a time, so that only
+// one column's moves are live; the y-links across a wave boundary need one
+// bit per column from each neighbour wave (MX: exchange area [wave][64]).
+__device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int vdn, int vup, int lane,
+                                              uint32_t &wind) {
+  uint32_t upw = 0u, dnw = 0u;  // bit c: top-row +y move / bottom-row -y move of column c
+  uint32_t ytop = 0u;           // bit c: y-link above the top row flips by this wave's own moves
+  uint32_t pxl[2], mx0[2];      // previous column's +x moves; column 0's -x moves
+  uint32_t xs[2];               // x-links of the last column
+#pragma unroll
+  for (int c = 0; c < BITS_CPL; ++c) {
+    uint32_t px[2], mx[2], py[2], my[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) bits_decide(s, c, w, px[w], mx[w], py[w], my[w]);
+    // y-link above row y flips iff row y moves +y or row y + 1 moves -y; the
+    // link above the top row also flips if the wave above moves -y there, the
+    // link below the bottom row if the wave below moves +y there (after the
+    // exchange).  Y of row y toggles rows y and y + 1.
+    const uint32_t Y0 = py[0] | fshr(my[1], my[0], 1);
+    const uint32_t Y1 = py[1] | (my[1] >> 1);
+    s.S[c][0] ^= Y0 ^ (Y0 << 1);
+    s.S[c][1] ^= Y1 ^ fshr(Y1, Y0, 31);
+    upw |= (py[1] >> 31) << c;
+    dnw |= (my[0] & 1u) << c;
+    ytop |= (Y1 >> 31) << c;
+    if (c == 0) {
+      mx0[0] = mx[0];
+      mx0[1] = mx[1];
+    } else {
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {  // the x-link between columns c - 1 and c
+        const uint32_t X = pxl[w] | mx[w];
+        s.S[c - 1][w] ^= X;
+        s.S[c][w] ^= X;
+      }
+    }
+    pxl[0] = px[0];
+    pxl[1] = px[1];
+  }
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {  // the x-link from the last column to lane i + 1's first
+    xs[w] = pxl[w] | from_right<true>(mx0[w]);
+    s.S[BITS_CPL - 1][w] ^= xs[w];
+    s.S[0][w] ^= from_left<true>(xs[w]);
+  }
+  MX[v * 64 + lane] = make_uint2(upw, dnw);
+  __syncthreads();
+  const uint32_t pyb = MX[vdn * 64 + lane].x;  // wave below: its top row moves +y
+  const uint32_t mya = MX[vup * 64 + lane].y;  // wave above: its bottom row moves -y
+  // the link below the bottom row flips iff row 64v - 1 moves +y or row 64v
+  // moves -y; the link above the top row iff the top row moves +y (applied
+  // above) or row 64v + 64 moves -y
+#pragma unroll
+  for (int c = 0; c < BITS_CPL; ++c) {
+    s.S[c][0] ^= ((pyb | dnw) >> c) & 1u;
+    s.S[c][1] ^= (((mya & ~upw) >> c) & 1u) << 31;
+  }
+  const uint32_t yflip = ytop | mya;
+  if (lane == 63) wind ^= ((__popc(xs[0]) + __popc(xs[1])) & 1u) << 2;
+  if (v == BITS_NW - 1) wind ^= (__popc(yflip & full_mask<BITS_CPL>()) & 1u) << 3;
+}
+
+// One workgroup per sample: noise, initial syndrome and windings, then up to
+// a.k decoder steps, stopping after the first step that leaves no anyon.
+// Writes the per-step anyon bits and the windings for k_finalize, and for a
+// sample that still holds anyons its state in the band layout.
+__global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
+  constexpr int L = BITS_L;
+  __shared__ uint4 XS[2][BITS_NW * 64];
+  __shared__ uint2 MX[BITS_NW * 64];
+  __shared__ uint32_t red;
+  const int lane = threadIdx.x & 63;
+  const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int vdn = v == 0 ? BITS_NW - 1 : v - 1, vup = v == BITS_NW - 1 ? 0 : v + 1;
+  const int64_t sample = blockIdx.x;
+  if (a.zero_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  if (threadIdx.x == 0) red = 0u;
+  const uint64_t seed = a.seeds[sample];
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
+
+  BitsLane s;
+  uint32_t wind = 0u;
+  {
+    // noise (R12 of the oracle's readings): site pairs (4i, 4i + 1) and
+    // (4i + 2, 4i + 3) of row y are generator blocks y L/2 + 2i and + 1
+    uint32_t ex[BITS_CPL][2], ey[BITS_CPL][2];
+#pragma unroll
+    for (int c = 0; c < BITS_CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = 0u;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll 2
+      for (int r = 0; r < 32; ++r) {
+        const uint32_t y = (uint32_t)(64 * v + 32 * w + r);
+        const uint32_t blk = y * (L / 2) + 2u * (uint32_t)lane;
+        const Words4 A = philox4x32_10(blk, k0, k1);
+        const Words4 B = philox4x32_10(blk + 1u, k0, k1);
+        ex[0][w] |= (uint32_t)((uint64_t)A.w0 < thr) << r;
+        ey[0][w] |= (uint32_t)((uint64_t)A.w1 < thr) << r;
+        ex[1][w] |= (uint32_t)((uint64_t)A.w2 < thr) << r;
+        ey[1][w] |= (uint32_t)((uint64_t)A.w3 < thr) << r;
+        ex[2][w] |= (uint32_t)((uint64_t)B.w0 < thr) << r;
+        ey[2][w] |= (uint32_t)((uint64_t)B.w1 < thr) << r;
+        ex[3][w] |= (uint32_t)((uint64_t)B.w2 < thr) << r;
+        ey[3][w] |= (uint32_t)((uint64_t)B.w3 < thr) << r;
+      }
+    }
+    uint32_t upw = 0u;
+#pragma unroll
+    for (int c = 0; c < BITS_CPL; ++c) upw |= (ey[c][1] >> 31) << c;
+    MX[v * 64 + lane] = make_uint2(upw, 0u);
+    __syncthreads();
+    const uint32_t eyb = MX[vdn * 64 + lane].x;  // y-links above the top row of the wave below
+    uint32_t wy = 0u;
+#pragma unroll
+    for (int c = 0; c < BITS_CPL; ++c) {
+      const uint32_t xl0 = c > 0 ? ex[c - 1][0] : from_left<true>(ex[BITS_CPL - 1][0]);
+      const uint32_t xl1 = c > 0 ? ex[c - 1][1] : from_left<true>(ex[BITS_CPL - 1][1]);
+      s.S[c][0] = ex[c][0] ^ xl0 ^ ey[c][0] ^ ((ey[c][0] << 1) | ((eyb >> c) & 1u));
+      s.S[c][1] = ex[c][1] ^ xl1 ^ ey[c][1] ^ fshr(ey[c][1], ey[c][0], 31);
+      wy ^= ey[c][1] >> 31;
+    }
+    if (lane == 63) wind ^= (__popc(ex[BITS_CPL - 1][0]) + __popc(ex[BITS_CPL - 1][1])) & 1u;
+    if (v == BITS_NW - 1) wind ^= wy << 1;
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c) s.E[d][q][c][0] = s.E[d][q][c][1] = 0u;
+
+  auto any_anyon = [&]() {
+    uint32_t o = 0u;
+#pragma unroll
+    for (int c = 0; c < BITS_CPL; ++c) o |= s.S[c][0] | s.S[c][1];
+    return o != 0u;
+  };
+  bool alive = __syncthreads_or(any_anyon()) != 0;
+  uint32_t bits = alive ? 1u : 0u;
+  int t = 0;
+  while (alive && t < a.k) {
+    const uint32_t t3 = 3u * (uint32_t)t;
+#pragma unroll 1
+    for (uint32_t j = 1; j <= 3; ++j) bits_substep(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
+    bits_feedback(s, MX, v, vdn, vup, lane, wind);
+    ++t;
+    alive = __syncthreads_or(any_anyon()) != 0;
+    if (alive) bits |= 1u << t;
+  }
+
+  if (wind) atomicXor(&red, wind);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.alive[sample] = bits;
+    a.wind[sample] = red;
+  }
+  if (!alive) return;
+  // anyons left: the state in the band layout, emission times as packed u16
+  // (P = e^{+x} | e^{-x} << 16, Q = e^{+y} | e^{-y} << 16) and 16-row syndrome masks
+  constexpr size_t half_row = L / 2;
+  uint4 *E = a.E + (size_t)sample * L * half_row;
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+#pragma unroll 1
+    for (int r = 0; r < 32; ++r) {
+      uint32_t P[BITS_CPL], Q[BITS_CPL];
+      const uint32_t rr = opaque((uint32_t)r);  // no shifted copies of the planes carried across rows
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c) {
+        uint32_t e[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          e[d] = 0u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
+        }
+        P[c] = e[0] | (e[1] << 16);
+        Q[c] = e[2] | (e[3] << 16);
+      }
+      const size_t y = (size_t)(64 * v + 32 * w + r);
+      E[y * half_row + 2 * lane] = make_uint4(P[0], Q[0], P[1], Q[1]);
+      E[y * half_row + 2 * lane + 1] = make_uint4(P[2], Q[2], P[3], Q[3]);
+    }
+    const size_t strip = (size_t)sample * (L / TILE_H) + (size_t)(4 * v + 2 * w);
+    a.S[strip * half_row + 2 * lane] = make_uint2(s.S[0][w] & 0xFFFFu, s.S[1][w] & 0xFFFFu);
+    a.S[strip * half_row + 2 * lane + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
+    a.S[(strip + 1) * half_row + 2 * lane] = make_uint2(s.S[0][w] >> 16, s.S[1][w] >> 16);
+    a.S[(strip + 1) * half_row + 2 * lane + 1] = make_uint2(s.S[2][w] >> 16, s.S[3][w] >> 16);
+  }
+}
+
+}  // namespace mpd

@@ -63,6 +63,14 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t k0, uint32
   return {c0, c1, c2, c3};
 }
 
+// floor(p 2^32) clamped to [0, 2^32]; exact in double, so identical to the
+// host's value for the same p.
+__device__ __forceinline__ uint64_t device_threshold(double p) {
+  double t = floor(p * 4294967296.0);
+  t = t < 0.0 ? 0.0 : (t > 4294967296.0 ? 4294967296.0 : t);
+  return (uint64_t)t;
+}
+
 // Link flips of site i = y*L + x from its Philox words (x-link, y-link).
 __device__ __forceinline__ void site_noise(uint32_t i, uint32_t k0, uint32_t k1, uint64_t thr,
                                            bool &fx, bool &fy) {

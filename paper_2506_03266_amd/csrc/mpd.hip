@@ -72,14 +72,6 @@ enum ResidentMode { RES_PLAIN = 0, RES_RULE = 1, RES_OPEN = 2 };
 
 __device__ __forceinline__ uint32_t parity32(uint32_t x) { return __popc(x) & 1u; }
 
-// floor(p 2^32) clamped to [0, 2^32]; exact in double, so identical to the
-// host's value for the same p.
-__device__ __forceinline__ uint64_t device_threshold(double p) {
-  double t = floor(p * 4294967296.0);
-  t = t < 0.0 ? 0.0 : (t > 4294967296.0 ? 4294967296.0 : t);
-  return (uint64_t)t;
-}
-
 // MODE RES_RULE compiles in the limited-memory variant (a.m_max, a.u).
 // MODE RES_OPEN decodes on the open lattice of the appendix on open
 // boundaries: sites (x, y) without wrap; the columns x = 0 and x = L-1 are
@@ -438,6 +430,12 @@ constexpr int BAND_RX = 128;               // region columns (2 per lane)
 constexpr int BAND_RY = BAND_NW * BAND_H;  // region rows (full-size regions)
 constexpr int TILE_H = BAND_H;             // rows per syndrome word pair in HBM
 constexpr int BAND_MAX_N = 65535;          // samples per band-path pass (grid y dimension)
+
+}  // namespace mpd
+
+#include "bits.h"
+
+namespace mpd {
 
 struct BandArgs {
   int L;
@@ -1268,6 +1266,7 @@ struct BandSchedule {
   int k_first = 4;
   int k_next = 2;
   int driver = MPD_BAND_DRIVER_AUTO;
+  int k_bits = BITS_MAX_STEPS;  // steps of the bit-sliced first kernel (L = 256, plain rule); 0 = band first pass
 };
 std::mutex g_sched_mu;
 BandSchedule g_sched_default;
@@ -1485,6 +1484,7 @@ struct BandRun {
   int cur = 1;
   bool done = false;
   bool device_only = false;  // later passes on the device whatever the setting (no host memory, no wait)
+  int64_t first_bound = 0;   // survivors of a first kernel outside fp (the bit-sliced one): an upper bound
 };
 
 // Pinned host words for the survivor counts, one block per host thread,
@@ -1622,7 +1622,7 @@ int band_passes(BandRun *runs, int nr) {
     }
     r.cur = 1;
     r.done = false;
-    int64_t first = 0;
+    int64_t first = r.first_bound;
     for (int b = 0; b < r.fp.nb; ++b) first += r.fp.count[b];
     if (device_driven(r, first)) {
       const int rc = band_tail(r, first);
@@ -1663,6 +1663,36 @@ int band_passes(BandRun *runs, int nr) {
   return MPD_OK;
 }
 
+// Noise and the first k steps of a plain L = 256 batch in the bit-sliced
+// kernel (bits.h), then the usual bookkeeping: T_dec of the samples it
+// finished, the survivors' state in buffer 1 and their list in active[1].
+int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max, int k,
+               const BandWorkspace &w, int32_t *d_T_dec, hipStream_t stream) {
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
+                     w.status, w.t_done, w.active[0], &w.count[2]);
+  HIP_TRY(hipGetLastError());
+  BitsArgs a;
+  a.seeds = d_seeds;
+  a.thr = thr;
+  a.p_arr = d_p;
+  a.k = k;
+  a.E = w.E[1];
+  a.S = w.S[1];
+  a.alive = w.alive;
+  a.wind = w.wind;
+  a.zero_count = &w.count[1];
+  {
+    ProfScope ps("k_bits", stream);
+    hipLaunchKernelGGL(k_bits, dim3((unsigned)n), dim3(BITS_NW * 64), 0, stream, a);
+  }
+  HIP_TRY(hipGetLastError());
+  (void)L;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, k, T_max, 1, w.active[0],
+                     (int)n, (const int *)nullptr, w.t_done, w.alive, d_T_dec, w.status, w.active[1], &w.count[1]);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
 // Noise (or explicit errors) and first-pass setup of a plain (single-group) band batch.
 int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream,
@@ -1675,6 +1705,14 @@ int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_
   r.flags = d_flags;
   r.syn = d_syn;
   r.stream = stream;
+  const int kb = schedule_for(L).k_bits;
+  if (L == BITS_L && kb > 0 && d_links == nullptr && r.rule.mode() == BAND_PLAIN) {
+    // noise and the first min(k_bits, T_max) steps in the bit-sliced kernel,
+    // which leaves the survivors in buffer 1 as a band first pass would
+    r.fp.nb = 0;
+    r.first_bound = n;
+    return bits_start(L, thr, d_p, d_seeds, n, T_max, std::min(kb, T_max), r.w, d_T_dec, stream);
+  }
   r.fp.nb = 1;
   r.fp.list[0] = r.w.active[0];
   r.fp.count[0] = (int)n;
@@ -2172,6 +2210,29 @@ int mpd_get_band_schedule(int L, int *k_first, int *k_next) {
   const BandSchedule b = schedule_for(L);
   *k_first = b.k_first;
   *k_next = b.k_next;
+  return MPD_OK;
+}
+
+int mpd_set_band_bits(int L, int k_bits) {
+  g_last_error.clear();
+  if (k_bits < 0 || k_bits > BITS_MAX_STEPS) return fail_with(MPD_ERR_TMAX, "bit-sliced steps must be in [0, %d]", BITS_MAX_STEPS);
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  if (L == 0) {
+    g_sched_default.k_bits = k_bits;
+    for (auto &kv : g_sched_by_L) kv.second.k_bits = k_bits;
+  } else {
+    auto it = g_sched_by_L.find(L);
+    BandSchedule b = it == g_sched_by_L.end() ? g_sched_default : it->second;
+    b.k_bits = k_bits;
+    g_sched_by_L[L] = b;
+  }
+  return MPD_OK;
+}
+
+int mpd_get_band_bits(int L, int *k_bits) {
+  g_last_error.clear();
+  if (k_bits == nullptr) return fail_with(MPD_ERR_PTR, "NULL output");
+  *k_bits = schedule_for(L).k_bits;
   return MPD_OK;
 }
 
