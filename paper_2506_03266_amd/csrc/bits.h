@@ -62,14 +62,16 @@ struct V4 {
   uint32_t p[4];
 };
 
-// Site-wise maximum of three 4-bit fields: the planes from the top, keeping
-// per operand a mask of the sites where it still equals the running maximum.
+// Site-wise maximum of three B-bit fields (planes B .. 3 are zero): the
+// planes from the top, keeping per operand a mask of the sites where it
+// still equals the running maximum.
+template <int B>
 __device__ __forceinline__ V4 max3v(const V4 &a, const V4 &b, const V4 &c) {
   V4 r;
-  r.p[3] = a.p[3] | b.p[3] | c.p[3];
-  uint32_t ka = a.p[3] | ~r.p[3], kb = b.p[3] | ~r.p[3], kc = c.p[3] | ~r.p[3];
+  r.p[B - 1] = a.p[B - 1] | b.p[B - 1] | c.p[B - 1];
+  uint32_t ka = a.p[B - 1] | ~r.p[B - 1], kb = b.p[B - 1] | ~r.p[B - 1], kc = c.p[B - 1] | ~r.p[B - 1];
 #pragma unroll
-  for (int q = 2; q >= 0; --q) {
+  for (int q = B - 2; q >= 0; --q) {
     r.p[q] = (a.p[q] & ka) | (b.p[q] & kb) | (c.p[q] & kc);
     if (q > 0) {
       ka &= a.p[q] | ~r.p[q];
@@ -77,6 +79,8 @@ __device__ __forceinline__ V4 max3v(const V4 &a, const V4 &b, const V4 &c) {
       kc &= c.p[q] | ~r.p[q];
     }
   }
+#pragma unroll
+  for (int q = B; q < 4; ++q) r.p[q] = 0u;
   return r;
 }
 
@@ -97,11 +101,28 @@ struct BitsLane {
   uint32_t S[BITS_CPL][2];        // syndrome (anyon = 1)
 };
 
-// Vertical maximum over rows y - 1, y, y + 1 of register d, column c: r0/r1
-// for words 0/1.  cdn: words whose bit 31 is the register's plane at the row
-// below word 0; cup: words whose bit 0 is the plane at the row above word 1.
-__device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, const uint32_t (&cdn)[4],
-                                          const uint32_t (&cup)[4], V4 &r0, V4 &r1) {
+// Edge rows of other waves, packed one bit per (register, plane, column) in
+// the order they are used: `top` is consumed from bit 31 (then shifted
+// left), `bot` from bit 0 (then shifted right).
+struct Carry {
+  uint32_t top, bot;
+  __device__ __forceinline__ uint32_t take_top() {  // a word whose bit 31 is the next item
+    const uint32_t w = top;
+    top <<= 1;
+    return w;
+  }
+  __device__ __forceinline__ uint32_t take_bot() {  // a word whose bit 0 is the next item
+    const uint32_t w = bot;
+    bot >>= 1;
+    return w;
+  }
+};
+
+// Vertical maximum over rows y - 1, y, y + 1 of register d, column c (B
+// planes): r0/r1 for words 0/1.  The row below word 0 and the row above word
+// 1 come from the neighbour waves through `cr`.
+template <int B>
+__device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, Carry &cr, V4 &r0, V4 &r1) {
   V4 x0, x1, dn, up;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -109,30 +130,33 @@ __device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, const
     x1.p[q] = s.E[d][q][c][1];
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    dn.p[q] = fshr(x0.p[q], cdn[q], 31);   // row y - 1
-    up.p[q] = fshr(x1.p[q], x0.p[q], 1);   // row y + 1
+  for (int q = 0; q < B; ++q) {
+    dn.p[q] = fshr(x0.p[q], cr.take_top(), 31);  // row y - 1
+    up.p[q] = fshr(x1.p[q], x0.p[q], 1);         // row y + 1
   }
-  r0 = max3v(dn, x0, up);
+  r0 = max3v<B>(dn, x0, up);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < B; ++q) {
     dn.p[q] = fshr(x1.p[q], x0.p[q], 31);
-    up.p[q] = fshr(cup[q], x1.p[q], 1);
+    up.p[q] = fshr(cr.take_bot(), x1.p[q], 1);
   }
-  r1 = max3v(dn, x1, up);
+  r1 = max3v<B>(dn, x1, up);
 }
 
-// One application of A^{(D)} at sub-step time ss (1 .. 15) to the whole
-// lattice.  XS: this sub-step's exchange slot [wave][64] of (up0, up1, dn0,
-// dn1): up words carry a wave's top row to the wave above, dn words its
-// bottom row to the wave below.  Packed items: ±x planes (d, q, c) at index
-// j = (4d + q) 4 + c (up0: bit 31 - j, dn0: bit j); the row maxima of +y
-// (up1, bit 15 - j') and of -y (dn1, bit 16 + j'), j' = 4q + c.
+// One application of A^{(D)} at sub-step time ss to the whole lattice, with
+// every emission time below 2^B.  XS: this sub-step's exchange slot
+// [wave][64] of (up0, up1, dn0, dn1): up words carry a wave's top row to the
+// wave above, dn words its bottom row to the wave below; up0 / dn0 hold the
+// ±x planes in the order the receiving wave uses them (+x columns 3 .. 0,
+// then -x columns 0 .. 3, planes inside), up1 / dn1 the row maxima of +y /
+// -y (columns inside planes).
+template <int B>
 __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS, int v, int vdn, int vup,
                                              int lane) {
+  constexpr int NX = 2 * B * BITS_CPL, NY = B * BITS_CPL;  // packed ±x and ±y items
   // anyon sites emit now: their registers read ss
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < B; ++q) {
     const uint32_t M = ((ss >> q) & 1u) ? ~0u : 0u;
 #pragma unroll
     for (int d = 0; d < 4; ++d)
@@ -146,14 +170,14 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   // ±x edge rows for the neighbour waves (folded values, before the update)
   uint32_t up0 = 0u, dn0 = 0u, up1 = 0u, dn1 = 0u;
 #pragma unroll
-  for (int d = 0; d < 2; ++d)
+  for (int k = 0; k < 2 * BITS_CPL; ++k) {
+    const int d = k < BITS_CPL ? 0 : 1, c = k < BITS_CPL ? BITS_CPL - 1 - k : k - BITS_CPL;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c) {
-        up0 = fshr(up0, s.E[d][q][c][1], 31);  // shift in bit 31 (top row)
-        dn0 = fshr(s.E[d][q][c][0], dn0, 1);   // shift in bit 0 (bottom row)
-      }
+    for (int q = 0; q < B; ++q) {
+      up0 = fshr(up0, s.E[d][q][c][1], 31);  // shift in bit 31 (top row)
+      dn0 = fshr(s.E[d][q][c][0], dn0, 1);   // shift in bit 0 (bottom row)
+    }
+  }
 
   // ±y: maxima over columns c - 1 .. c + 1 of the row (in place), then the
   // shift by one row within the lane; the cross-wave bit follows the barrier
@@ -164,8 +188,8 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
       V4 left, right, prev;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        left.p[q] = from_left<true>(s.E[d][q][BITS_CPL - 1][w]);  // lane i - 1, last column
-        right.p[q] = from_right<true>(s.E[d][q][0][w]);           // lane i + 1, first column
+        left.p[q] = q < B ? from_left<true>(s.E[d][q][BITS_CPL - 1][w]) : 0u;  // lane i - 1, last column
+        right.p[q] = q < B ? from_right<true>(s.E[d][q][0][w]) : 0u;           // lane i + 1, first column
       }
       prev = left;
 #pragma unroll
@@ -176,14 +200,14 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
           cur.p[q] = s.E[d][q][c][w];
           nxt.p[q] = c + 1 < BITS_CPL ? s.E[d][q][c + 1][w] : right.p[q];
         }
-        const V4 h = max3v(prev, cur, nxt);
+        const V4 h = max3v<B>(prev, cur, nxt);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s.E[d][q][c][w] = h.p[q];
+        for (int q = 0; q < B; ++q) s.E[d][q][c][w] = h.p[q];
         prev = cur;
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < B; ++q)
 #pragma unroll
       for (int c = 0; c < BITS_CPL; ++c) {
         const uint32_t h0 = s.E[d][q][c][0], h1 = s.E[d][q][c][1];
@@ -199,50 +223,40 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
 
   XS[v * 64 + lane] = make_uint4(up0, up1, dn0, dn1);
   __syncthreads();
-  const uint4 B = XS[vdn * 64 + lane];  // top row of the wave below
-  const uint4 A = XS[vup * 64 + lane];  // bottom row of the wave above
+  const uint4 Bw = XS[vdn * 64 + lane];  // top row of the wave below
+  const uint4 Aw = XS[vup * 64 + lane];  // bottom row of the wave above
+  Carry cx = {Bw.x << (32 - NX), Aw.z >> (32 - NX)};
+  Carry cy = {Bw.y << (32 - NY), Aw.w >> (32 - NY)};
 
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < B; ++q)
 #pragma unroll
     for (int c = 0; c < BITS_CPL; ++c) {
-      const int j = 4 * q + c;
-      s.E[2][q][c][0] = fshr(s.E[2][q][c][0], opaque(B.y) << (16 + j), 31);
-      s.E[3][q][c][1] = fshr(opaque(A.w) >> (16 + j), s.E[3][q][c][1], 1);
+      s.E[2][q][c][0] = fshr(s.E[2][q][c][0], cy.take_top(), 31);
+      s.E[3][q][c][1] = fshr(cy.take_bot(), s.E[3][q][c][1], 1);
     }
 
   // +x: column c reads the vertical maxima of column c - 1
   {
     V4 r0, r1, h0, h1;
-    uint32_t cdn[4], cup[4];
     constexpr int d = 0;
+    bits_vmax<B>(s, d, BITS_CPL - 1, cx, r0, r1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + BITS_CPL - 1);
-      cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + BITS_CPL - 1);
-    }
-    bits_vmax(s, d, BITS_CPL - 1, cdn, cup, r0, r1);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B; ++q) {
       h0.p[q] = from_left<true>(r0.p[q]);
       h1.p[q] = from_left<true>(r1.p[q]);
     }
 #pragma unroll
     for (int c = BITS_CPL - 1; c >= 1; --c) {
+      bits_vmax<B>(s, d, c - 1, cx, r0, r1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + c - 1);
-        cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + c - 1);
-      }
-      bits_vmax(s, d, c - 1, cdn, cup, r0, r1);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < B; ++q) {
         s.E[d][q][c][0] = r0.p[q];
         s.E[d][q][c][1] = r1.p[q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B; ++q) {
       s.E[d][q][0][0] = h0.p[q];
       s.E[d][q][0][1] = h1.p[q];
     }
@@ -250,35 +264,24 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   // -x: column c reads the vertical maxima of column c + 1
   {
     V4 r0, r1, h0, h1;
-    uint32_t cdn[4], cup[4];
     constexpr int d = 1;
+    bits_vmax<B>(s, d, 0, cx, r0, r1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + 0);
-      cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + 0);
-    }
-    bits_vmax(s, d, 0, cdn, cup, r0, r1);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B; ++q) {
       h0.p[q] = from_right<true>(r0.p[q]);
       h1.p[q] = from_right<true>(r1.p[q]);
     }
 #pragma unroll
     for (int c = 0; c + 1 < BITS_CPL; ++c) {
+      bits_vmax<B>(s, d, c + 1, cx, r0, r1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cdn[q] = opaque(B.x) << ((4 * d + q) * 4 + c + 1);
-        cup[q] = opaque(A.z) >> ((4 * d + q) * 4 + c + 1);
-      }
-      bits_vmax(s, d, c + 1, cdn, cup, r0, r1);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < B; ++q) {
         s.E[d][q][c][0] = r0.p[q];
         s.E[d][q][c][1] = r1.p[q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < B; ++q) {
       s.E[d][q][BITS_CPL - 1][0] = h0.p[q];
       s.E[d][q][BITS_CPL - 1][1] = h1.p[q];
     }
@@ -286,16 +289,17 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
 }
 
 // Moves of the anyons of one column word from the registers after the last
-// sub-step of a step (see decide_site in band.h).
+// sub-step of a step (see decide_site in band.h), every emission time below 2^B.
+template <int B>
 __device__ __forceinline__ void bits_decide(const BitsLane &s, int c, int w, uint32_t &px, uint32_t &mx,
                                             uint32_t &py, uint32_t &my) {
   uint32_t k[4];
-  uint32_t m = s.E[0][3][c][w] | s.E[1][3][c][w] | s.E[2][3][c][w] | s.E[3][3][c][w];
+  uint32_t m = s.E[0][B - 1][c][w] | s.E[1][B - 1][c][w] | s.E[2][B - 1][c][w] | s.E[3][B - 1][c][w];
   uint32_t nz = m;
 #pragma unroll
-  for (int d = 0; d < 4; ++d) k[d] = s.E[d][3][c][w] | ~m;
+  for (int d = 0; d < 4; ++d) k[d] = s.E[d][B - 1][c][w] | ~m;
 #pragma unroll
-  for (int q = 2; q >= 0; --q) {
+  for (int q = B - 2; q >= 0; --q) {
     m = (s.E[0][q][c][w] & k[0]) | (s.E[1][q][c][w] & k[1]) | (s.E[2][q][c][w] & k[2]) | (s.E[3][q][c][w] & k[3]);
     nz |= m;
 #pragma unroll
@@ -315,6 +319,7 @@ __device__ __forceinline__ void bits_decide(const BitsLane &s, int c, int w, uin
 // leaving row L - 1: bit 3).  Columns are decided one at a time, so that only
 // one column's moves are live; the y-links across a wave boundary need one
 // bit per column from each neighbour wave (MX: exchange area [wave][64]).
+template <int B>
 __device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int vdn, int vup, int lane,
                                               uint32_t &wind) {
   uint32_t upw = 0u, dnw = 0u;  // bit c: top-row +y move / bottom-row -y move of column c
@@ -325,7 +330,7 @@ __device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int
   for (int c = 0; c < BITS_CPL; ++c) {
     uint32_t px[2], mx[2], py[2], my[2];
 #pragma unroll
-    for (int w = 0; w < 2; ++w) bits_decide(s, c, w, px[w], mx[w], py[w], my[w]);
+    for (int w = 0; w < 2; ++w) bits_decide<B>(s, c, w, px[w], mx[w], py[w], my[w]);
     // y-link above row y flips iff row y moves +y or row y + 1 moves -y; the
     // link above the top row also flips if the wave above moves -y there, the
     // link below the bottom row if the wave below moves +y there (after the
@@ -372,6 +377,16 @@ __device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int
   const uint32_t yflip = ytop | mya;
   if (lane == 63) wind ^= ((__popc(xs[0]) + __popc(xs[1])) & 1u) << 2;
   if (v == BITS_NW - 1) wind ^= (__popc(yflip & full_mask<BITS_CPL>()) & 1u) << 3;
+}
+
+// One decoder step (sub-steps t3 + 1 .. t3 + 3, then the feedback) with
+// every emission time below 2^B.
+template <int B>
+__device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[BITS_NW * 64], uint2 *MX, int v,
+                                       int vdn, int vup, int lane, uint32_t &wind) {
+#pragma unroll 1
+  for (uint32_t j = 1; j <= 3; ++j) bits_substep<B>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
+  bits_feedback<B>(s, MX, v, vdn, vup, lane, wind);
 }
 
 // One workgroup per sample: noise, initial syndrome and windings, then up to
@@ -453,15 +468,26 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
   bool alive = __syncthreads_or(any_anyon()) != 0;
   uint32_t bits = alive ? 1u : 0u;
   int t = 0;
-  while (alive && t < a.k) {
-    const uint32_t t3 = 3u * (uint32_t)t;
-#pragma unroll 1
-    for (uint32_t j = 1; j <= 3; ++j) bits_substep(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
-    bits_feedback(s, MX, v, vdn, vup, lane, wind);
+  // step t + 1 ends at sub-step 3 (t + 1): emission times below 4 in the
+  // first step, below 8 in the second, below 16 up to the fifth
+  auto after_step = [&]() {
     ++t;
     alive = __syncthreads_or(any_anyon()) != 0;
     if (alive) bits |= 1u << t;
+  };
+  if (alive && t < a.k) {
+    bits_step<2>(s, 0u, XS, MX, v, vdn, vup, lane, wind);
+    after_step();
   }
+  if (alive && t < a.k) {
+    bits_step<3>(s, 3u, XS, MX, v, vdn, vup, lane, wind);
+    after_step();
+  }
+  while (alive && t < a.k) {
+    bits_step<4>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
+    after_step();
+  }
+
 
   if (wind) atomicXor(&red, wind);
   __syncthreads();
