@@ -29,27 +29,27 @@ sys.path.insert(0, ROOT)
 L, P, N_SAMPLES, T_MAX = 256, 0.01, 4096, 4096
 BYTES_PER_SITE_UPDATE = 16.25   # 4 x int16 registers + 1 syndrome bit, read and written once per step
 HBM_PEAK_GBS = 8000.0
+# VALU issue of 32-bit integer / bitwise operations: 256 CUs x 4 SIMDs x 16
+# lanes per clock x 2.4 GHz (a wave64 instruction every 4 clocks per SIMD)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "decoded samples/s & site-updates/s at L=256, p=0.01 (plain vs learned-sched)"
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_band_L256_p001.json")
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_bits_L256_p001.json")
 CSRC = os.path.join(ROOT, "paper_2506_03266_amd", "csrc")
 
 
 def kernel_source_sha():
-    """sha256[:16] of the band kernel's device code: engine.h, band.h and the
-    k_band section of mpd.hip (from its banner to the noise kernel)."""
+    """sha256[:16] of the bit-sliced kernel's device code: engine.h, band.h
+    (lane shifts) and bits.h."""
     import hashlib
-    src = open(os.path.join(CSRC, "mpd.hip")).read()
-    a = src.index("// Band path: regions")
-    b = src.index("// Noise and initial syndrome of the band path")
-    parts = [open(os.path.join(CSRC, f), "rb").read() for f in ("engine.h", "band.h")] + [src[a:b].encode()]
+    parts = [open(os.path.join(CSRC, f), "rb").read() for f in ("engine.h", "band.h", "bits.h")]
     return hashlib.sha256(b"".join(parts)).hexdigest()[:16]
 
 
 def profile_summary():
-    """The committed rocprofv3 summary of k_band (HBM bytes per launch from the
-    calibrated FETCH_SIZE / WRITE_SIZE counters, VALU issue fraction of the
-    first pass from the SQ counters), or {} if the kernel's code changed since
-    the counters were taken."""
+    """The committed rocprofv3 summary of k_bits on the benchmark batches
+    (VALU instructions per launch from SQ_INSTS_VALU, HBM bytes per launch
+    from the calibrated FETCH_SIZE / WRITE_SIZE counters), or {} if the
+    kernel's code changed since the counters were taken."""
     try:
         with open(PROFILE_SUMMARY) as f:
             summ = json.load(f)
@@ -159,7 +159,8 @@ def main():
     torch.cuda.synchronize()
     elapsed_1 = time.perf_counter() - t0
     b.profile(False)
-    tile_ms, tile_launches = b.profile_read("k_band")
+    bits_ms, bits_launches = b.profile_read("k_bits")
+    band_ms, band_launches = b.profile_read("k_band")
     # S batches in flight: the throughput figure
     runner.run(fifo, range(W))
     elapsed = runner.run(fifo, range(W, W + K))
@@ -173,9 +174,11 @@ def main():
     samples_per_s = K * n / elapsed
     su_per_s = site_updates / elapsed
     summ = profile_summary()
-    algo_bytes_per_launch = BYTES_PER_SITE_UPDATE * site_updates / max(tile_launches, 1)
-    avg_launch_s = tile_ms / 1e3 / max(tile_launches, 1)
-    achieved = algo_bytes_per_launch / avg_launch_s / 1e9 if tile_launches else None
+    avg_launch_s = bits_ms / 1e3 / max(bits_launches, 1)
+    valu = summ.get("valu_insts_per_launch")
+    achieved = valu * 64 / avg_launch_s / 1e12 if (valu and bits_launches) else None
+    # samples that reach the band passes: T_dec above the bit-sliced steps
+    k_bits = b.get_band_bits(L)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -206,7 +209,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16",
+        "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "toric code L=256, p=0.01, 4096 seeded i.i.d. bit-flip samples per step, "
                                f"T_max=4096, v=3, plain FIFO batch, {S} batches in flight on separate streams",
@@ -220,21 +223,24 @@ def main():
         "fail_rate": float((F_all & 1).mean()),
         "fail_rate_wilson95": wilson(int((F_all & 1).sum()), int(F_all.size)),
         "timeouts": int(((F_all & 2) > 0).sum()),
-        "roofline": {"bound": "hbm", "kernel": "k_band",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": summ.get(
-                         "traffic_bytes_per_launch"),
-                     "achieved_basis": "modelled effective bandwidth: 16.25 B of algorithmic state traffic per "
-                                       "useful site-update (registers and syndrome read and written once per "
-                                       "decoder step) over the measured launch time; temporal blocking keeps the "
-                                       "state on chip for several steps, so the HBM bytes actually moved are "
-                                       "'traffic' (rocprofv3 counters)",
-                     "measured_hbm_GBps": (summ["traffic_bytes_per_launch"] / avg_launch_s / 1e9)
-                     if summ.get("traffic_bytes_per_launch") and tile_launches else None,
-                     "valu_issue_frac_first_pass": summ.get("valu_issue_frac_first_pass"),
-                     "binding_unit": "VALU issue (SQ counters)" if summ.get("valu_issue_frac_first_pass") else None,
-                     "bytes_per_site_update": BYTES_PER_SITE_UPDATE,
-                     "launches": tile_launches, "avg_launch_ms": avg_launch_s * 1e3},
+        "roofline": {"bound": "alu", "kernel": "k_bits",
+                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
+                     "traffic": summ.get("traffic_bytes_per_launch"),
+                     "achieved_basis": "32-bit lane operations per launch of the bit-sliced kernel (VALU "
+                                       "instructions x 64 lanes, SQ_INSTS_VALU of the committed profile on the "
+                                       "benchmark batches; the count depends only on the seeds) over the live "
+                                       "launch time (HIP events on the launch stream)",
+                     "launches": bits_launches, "avg_launch_ms": avg_launch_s * 1e3,
+                     "valu_insts_per_launch": valu,
+                     "effective_state_GBps": BYTES_PER_SITE_UPDATE * site_updates / max(K, 1) / avg_launch_s / 1e9
+                     if bits_launches else None,
+                     "effective_state_basis": "16.25 B of u16 register and syndrome state per useful site-update "
+                                              "over the k_bits launch time: the HBM traffic a decoder that kept "
+                                              "its state in HBM between steps would need; the bit-sliced kernel "
+                                              "keeps it on chip",
+                     "band_passes": {"k_bits_steps": k_bits, "samples_beyond": int((T_all > k_bits).sum()),
+                                     "launches": band_launches, "total_ms": band_ms}},
         "kernel_source_sha16": kernel_source_sha(),
         "cpu_baseline": cpu,
         "device_driver": device_leg,
@@ -291,28 +297,31 @@ class Runner:
 
 
 def device_driven(b, batches, outs, W, K, n, ws, torch):
-    """The same K batches, one stream, with the later passes driven on the
-    device (no host wait in a decode), then as replays of one captured HIP
-    graph (the seeds copied into the graph's input before each replay).
-    Checks that every output equals the plain run's."""
+    """The same K batches, one stream: with the later passes driven from the
+    host (a survivor-count readback per pass) and on the device (no host
+    wait in a decode), then as replays of one captured HIP graph (the seeds
+    copied into the graph's input before each replay).  Checks that every
+    output equals the plain run's."""
     dev = torch.device("cuda")
     st = torch.cuda.current_stream()
     o = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
          torch.empty((n, b.syndrome_words(L)), dtype=torch.int32, device=dev))
     same = True
-    b.set_band_driver(b.BAND_DRIVER_DEVICE)
-    try:
-        for i in range(W):
-            b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(W, W + K):
-            b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
-        torch.cuda.synchronize()
-        el_dev = time.perf_counter() - t0
-        same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
-    finally:
-        b.set_band_driver(b.BAND_DRIVER_AUTO)
+    el = {}
+    for name, drv in (("host", b.BAND_DRIVER_HOST), ("device", b.BAND_DRIVER_DEVICE)):
+        b.set_band_driver(drv)
+        try:
+            for i in range(W):
+                b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(W, W + K):
+                b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
+            torch.cuda.synchronize()
+            el[name] = time.perf_counter() - t0
+            same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
+        finally:
+            b.set_band_driver(b.BAND_DRIVER_AUTO)
     s_in = batches[0].clone()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
@@ -328,7 +337,8 @@ def device_driven(b, batches, outs, W, K, n, ws, torch):
     torch.cuda.synchronize()
     el_graph = time.perf_counter() - t0
     same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
-    return {"samples_per_s": K * n / el_dev, "ms_per_step": el_dev / K * 1e3,
+    return {"samples_per_s": K * n / el["device"], "ms_per_step": el["device"] / K * 1e3,
+            "host_driver_samples_per_s": K * n / el["host"], "host_driver_ms_per_step": el["host"] / K * 1e3,
             "graph_replay_samples_per_s": K * n / el_graph, "graph_replay_ms_per_step": el_graph / K * 1e3,
             "identical_results": bool(same)}
 

@@ -360,8 +360,10 @@ int mpd_get_band_schedule(int L, int *k_first, int *k_next);
  *                           tile, until each is decoded or reaches T_max.
  *                           No host wait: a band-path decode can then be
  *                           captured into a HIP graph.
- *   MPD_BAND_DRIVER_AUTO    the device on a stream that is being captured,
- *                           else the host.
+ *   MPD_BAND_DRIVER_AUTO    the device on a stream that is being captured
+ *                           or after the bit-sliced first kernel (see
+ *                           mpd_set_band_bits; its survivors are rare and go
+ *                           straight to the persistent launch), else the host.
  * Results never depend on the driver.  L = 0 sets the default and the
  * driver of every per-L setting; otherwise this L only.  A stream under
  * capture always takes the device.  Process-wide, guarded by a mutex;
@@ -373,16 +375,16 @@ int mpd_set_band_driver(int L, int driver);
 int mpd_get_band_driver(int L, int *driver);
 
 /* First steps of a plain seeded L = 256 batch in the bit-sliced kernel.
- * During the first five decoder steps every emission time is at most 15, so
- * the registers fit in 4-bit planes and a whole L = 256 torus fits in one
+ * During the first ten decoder steps every emission time is at most 30, so
+ * the registers fit in 5-bit planes and a whole L = 256 torus fits in one
  * workgroup (no halo, no HBM state); a sample leaves as soon as it has no
  * anyon, and the others continue on the band path from the state it hands
- * over.  k_bits in [0, 5]: the number of such steps (0: the band path's
+ * over.  k_bits in [0, 10]: the number of such steps (0: the band path's
  * first pass instead).  Applies to mpd_decode_batch, mpd_decode_mixed and
  * the one-group learned decode at L = 256 with the plain rule (Def.
  * "message passing automaton, general dimensions"); results never depend on
- * it.  L = 0 sets the default and every per-L setting (default 5).
- * Process-wide, guarded by a mutex; MPD_ERR_TMAX outside [0, 5]. */
+ * it.  L = 0 sets the default and every per-L setting (default 10).
+ * Process-wide, guarded by a mutex; MPD_ERR_TMAX outside [0, 10]. */
 int mpd_set_band_bits(int L, int k_bits);
 int mpd_get_band_bits(int L, int *k_bits);
 

@@ -480,7 +480,7 @@ def get_band_driver(L: int = 0) -> int:
 
 def set_band_bits(k_bits: int, L: int = 0):
     """Decoder steps of a plain L = 256 batch that run in the bit-sliced
-    whole-lattice kernel before the band passes (0..5; 0: the band path's
+    whole-lattice kernel before the band passes (0..10; 0: the band path's
     first pass instead); L = 0 sets the default and every per-L setting."""
     _check(lib().mpd_set_band_bits(int(L), int(k_bits)), "mpd_set_band_bits")
 

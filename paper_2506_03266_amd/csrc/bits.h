@@ -1,22 +1,23 @@
 // bits.h -- bit-sliced whole-lattice kernel for the first decoder steps at
 // L = 256 (gfx950).
 //
-// While a decode is in its first five decoder steps every emission time is
-// at most 3 * 5 = 15 (registers hold emission times, see engine.h), so one
-// register fits in 4 bits.  Stored as bit planes -- one 32-bit word holds one
-// bit of one register for 32 consecutive rows of one column -- the whole
-// state of an L = 256 torus is 256 x 256 sites x 4 registers x 4 bits =
-// 128 KiB, which a workgroup of four waves keeps in VGPRs.  The first steps
-// then need no halo (the torus wraps inside the workgroup) and no HBM state,
-// a sample leaves as soon as it has no anyon, and the update works on 32
-// sites per instruction:
+// Registers hold emission times (see engine.h), and during the first ten
+// decoder steps every emission time is at most 3 * 10 = 30: a register fits
+// in 5 bits (in 2, 3 and 4 bits during the first, second and third to fifth
+// steps).  Stored as bit planes -- one 32-bit word holds one bit of one
+// register for 32 consecutive rows of one column -- the whole state of an
+// L = 256 torus is 256 x 256 sites x 4 registers x 5 bits = 160 KiB, which a
+// workgroup of four waves keeps in VGPRs.  These steps then need no halo
+// (the torus wraps inside the workgroup) and no HBM state, a sample leaves
+// as soon as it has no anyon, and the update works on 32 sites per
+// instruction:
 //
 //  * Rule A^{(D)} of Def. "message passing automaton, general dimensions" in
 //    emission-time form is e'(r) = max over the 3-site line C of
 //    (sigma_q ? s : e_q).  The fold (anyon sites emit at the sub-step time
-//    s) is one select per plane; the 3-wide maximum of 4-bit values is a
-//    most-significant-bit-first candidate filter (19 bitwise operations for
-//    32 sites).
+//    s) is one select per plane; the 3-wide maximum of B-bit values is a
+//    most-significant-bit-first candidate filter (6B - 5 bitwise operations
+//    for 32 sites).
 //  * The move decision of eq. (degbreak) with the reading of engine.h (the
 //    largest emission time wins; ties in the order -y, -x, +x, +y; no move
 //    when the opposite register on that axis ties) is the same filter over
@@ -27,7 +28,7 @@
 // Layout: wave v holds rows 64v .. 64v + 63, lane i columns 4i .. 4i + 3;
 // word w of a column covers rows 64v + 32w .. + 31 (bit r = row 64v + 32w + r).
 // Vertical neighbours inside a lane are funnel shifts (v_alignbit); across
-// waves the edge rows travel through LDS packed 32 to a word, once per
+// waves the edge rows travel through LDS packed up to 20 to a word, once per
 // sub-step (one barrier).  Horizontal neighbours are in the lane or one
 // wave-wide DPP rotation away (the wrap in x).
 //
@@ -43,7 +44,8 @@ namespace mpd {
 constexpr int BITS_L = 256;
 constexpr int BITS_CPL = 4;          // columns per lane
 constexpr int BITS_NW = 4;           // waves (64 rows each)
-constexpr int BITS_MAX_STEPS = 5;    // emission times <= 15 fit in 4 bits
+constexpr int BITS_PLANES = 5;       // bit planes per register
+constexpr int BITS_MAX_STEPS = 10;   // emission times <= 30 fit in 5 bits
 
 struct BitsArgs {
   const uint64_t *seeds;
@@ -57,9 +59,9 @@ struct BitsArgs {
   int *zero_count;       // survivor counter of the following compaction (cleared here)
 };
 
-// Bit planes of one 4-bit register field, most significant plane last.
+// Bit planes of one register field, most significant plane last.
 struct V4 {
-  uint32_t p[4];
+  uint32_t p[BITS_PLANES];
 };
 
 // Site-wise maximum of three B-bit fields (planes B .. 3 are zero): the
@@ -80,7 +82,7 @@ __device__ __forceinline__ V4 max3v(const V4 &a, const V4 &b, const V4 &c) {
     }
   }
 #pragma unroll
-  for (int q = B; q < 4; ++q) r.p[q] = 0u;
+  for (int q = B; q < BITS_PLANES; ++q) r.p[q] = 0u;
   return r;
 }
 
@@ -97,7 +99,7 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 }
 
 struct BitsLane {
-  uint32_t E[4][4][BITS_CPL][2];  // [register: +x, -x, +y, -y][bit][column][word]
+  uint32_t E[4][BITS_PLANES][BITS_CPL][2];  // [register: +x, -x, +y, -y][bit][column][word]
   uint32_t S[BITS_CPL][2];        // syndrome (anyon = 1)
 };
 
@@ -125,7 +127,7 @@ template <int B>
 __device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, Carry &cr, V4 &r0, V4 &r1) {
   V4 x0, x1, dn, up;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < BITS_PLANES; ++q) {
     x0.p[q] = s.E[d][q][c][0];
     x1.p[q] = s.E[d][q][c][1];
   }
@@ -144,16 +146,16 @@ __device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, Carry
 }
 
 // One application of A^{(D)} at sub-step time ss to the whole lattice, with
-// every emission time below 2^B.  XS: this sub-step's exchange slot
-// [wave][64] of (up0, up1, dn0, dn1): up words carry a wave's top row to the
-// wave above, dn words its bottom row to the wave below; up0 / dn0 hold the
-// ±x planes in the order the receiving wave uses them (+x columns 3 .. 0,
-// then -x columns 0 .. 3, planes inside), up1 / dn1 the row maxima of +y /
-// -y (columns inside planes).
+// every emission time below 2^B.  XS: this sub-step's exchange slots
+// [wave][2][64]: slot 0 carries a wave's top row to the wave above (+x
+// planes, -x planes, +y row maxima), slot 1 its bottom row to the wave below
+// (+x, -x, -y row maxima).  Each word holds its items in the order the
+// receiving wave uses them: +x columns 3 .. 0 and -x columns 0 .. 3 (the
+// order of the vertical maxima), ±y columns inside planes.
 template <int B>
 __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS, int v, int vdn, int vup,
                                              int lane) {
-  constexpr int NX = 2 * B * BITS_CPL, NY = B * BITS_CPL;  // packed ±x and ±y items
+  constexpr int N = B * BITS_CPL;  // items per word
   // anyon sites emit now: their registers read ss
 #pragma unroll
   for (int q = 0; q < B; ++q) {
@@ -167,15 +169,18 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
           s.E[d][q][c][w] = __builtin_amdgcn_bitop3_b32(M, s.E[d][q][c][w], s.S[c][w], 0xE4);
   }
 
-  // ±x edge rows for the neighbour waves (folded values, before the update)
-  uint32_t up0 = 0u, dn0 = 0u, up1 = 0u, dn1 = 0u;
+  // ±x edge rows for the neighbour waves (folded values, before the update);
+  // a word shifted in at bit 0 (top rows) or at bit 31 (bottom rows)
+  uint32_t upx = 0u, dpx = 0u, umx = 0u, dmx = 0u, upy = 0u, dmy = 0u;
 #pragma unroll
-  for (int k = 0; k < 2 * BITS_CPL; ++k) {
-    const int d = k < BITS_CPL ? 0 : 1, c = k < BITS_CPL ? BITS_CPL - 1 - k : k - BITS_CPL;
+  for (int k = 0; k < BITS_CPL; ++k) {
+    const int cp = BITS_CPL - 1 - k, cm = k;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      up0 = fshr(up0, s.E[d][q][c][1], 31);  // shift in bit 31 (top row)
-      dn0 = fshr(s.E[d][q][c][0], dn0, 1);   // shift in bit 0 (bottom row)
+      upx = fshr(upx, s.E[0][q][cp][1], 31);
+      dpx = fshr(s.E[0][q][cp][0], dpx, 1);
+      umx = fshr(umx, s.E[1][q][cm][1], 31);
+      dmx = fshr(s.E[1][q][cm][0], dmx, 1);
     }
   }
 
@@ -187,7 +192,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
     for (int w = 0; w < 2; ++w) {
       V4 left, right, prev;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < BITS_PLANES; ++q) {
         left.p[q] = q < B ? from_left<true>(s.E[d][q][BITS_CPL - 1][w]) : 0u;  // lane i - 1, last column
         right.p[q] = q < B ? from_right<true>(s.E[d][q][0][w]) : 0u;           // lane i + 1, first column
       }
@@ -196,7 +201,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
       for (int c = 0; c < BITS_CPL; ++c) {
         V4 cur, nxt;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < BITS_PLANES; ++q) {
           cur.p[q] = s.E[d][q][c][w];
           nxt.p[q] = c + 1 < BITS_CPL ? s.E[d][q][c + 1][w] : right.p[q];
         }
@@ -212,21 +217,23 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
       for (int c = 0; c < BITS_CPL; ++c) {
         const uint32_t h0 = s.E[d][q][c][0], h1 = s.E[d][q][c][1];
         if (d == 2) {  // +y reads the row below: word 1 now, word 0 after the exchange
-          up1 = fshr(up1, h1, 31);
+          upy = fshr(upy, h1, 31);
           s.E[d][q][c][1] = fshr(h1, h0, 31);
         } else {  // -y reads the row above: word 0 now, word 1 after the exchange
-          dn1 = fshr(h0, dn1, 1);
+          dmy = fshr(h0, dmy, 1);
           s.E[d][q][c][0] = fshr(h1, h0, 1);
         }
       }
   }
 
-  XS[v * 64 + lane] = make_uint4(up0, up1, dn0, dn1);
+  XS[(v * 2 + 0) * 64 + lane] = make_uint4(upx, umx, upy, 0u);
+  XS[(v * 2 + 1) * 64 + lane] = make_uint4(dpx, dmx, dmy, 0u);
   __syncthreads();
-  const uint4 Bw = XS[vdn * 64 + lane];  // top row of the wave below
-  const uint4 Aw = XS[vup * 64 + lane];  // bottom row of the wave above
-  Carry cx = {Bw.x << (32 - NX), Aw.z >> (32 - NX)};
-  Carry cy = {Bw.y << (32 - NY), Aw.w >> (32 - NY)};
+  const uint4 Bw = XS[(vdn * 2 + 0) * 64 + lane];  // top row of the wave below
+  const uint4 Aw = XS[(vup * 2 + 1) * 64 + lane];  // bottom row of the wave above
+  Carry cpx = {Bw.x << (32 - N), Aw.x >> (32 - N)};
+  Carry cmx = {Bw.y << (32 - N), Aw.y >> (32 - N)};
+  Carry cy = {Bw.z << (32 - N), Aw.z >> (32 - N)};
 
 #pragma unroll
   for (int q = 0; q < B; ++q)
@@ -240,7 +247,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   {
     V4 r0, r1, h0, h1;
     constexpr int d = 0;
-    bits_vmax<B>(s, d, BITS_CPL - 1, cx, r0, r1);
+    bits_vmax<B>(s, d, BITS_CPL - 1, cpx, r0, r1);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       h0.p[q] = from_left<true>(r0.p[q]);
@@ -248,7 +255,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
     }
 #pragma unroll
     for (int c = BITS_CPL - 1; c >= 1; --c) {
-      bits_vmax<B>(s, d, c - 1, cx, r0, r1);
+      bits_vmax<B>(s, d, c - 1, cpx, r0, r1);
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         s.E[d][q][c][0] = r0.p[q];
@@ -265,7 +272,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   {
     V4 r0, r1, h0, h1;
     constexpr int d = 1;
-    bits_vmax<B>(s, d, 0, cx, r0, r1);
+    bits_vmax<B>(s, d, 0, cmx, r0, r1);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       h0.p[q] = from_right<true>(r0.p[q]);
@@ -273,7 +280,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
     }
 #pragma unroll
     for (int c = 0; c + 1 < BITS_CPL; ++c) {
-      bits_vmax<B>(s, d, c + 1, cx, r0, r1);
+      bits_vmax<B>(s, d, c + 1, cmx, r0, r1);
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         s.E[d][q][c][0] = r0.p[q];
@@ -382,7 +389,7 @@ __device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int
 // One decoder step (sub-steps t3 + 1 .. t3 + 3, then the feedback) with
 // every emission time below 2^B.
 template <int B>
-__device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[BITS_NW * 64], uint2 *MX, int v,
+__device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[BITS_NW * 2 * 64], uint2 *MX, int v,
                                        int vdn, int vup, int lane, uint32_t &wind) {
 #pragma unroll 1
   for (uint32_t j = 1; j <= 3; ++j) bits_substep<B>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
@@ -395,7 +402,7 @@ __device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[
 // sample that still holds anyons its state in the band layout.
 __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
   constexpr int L = BITS_L;
-  __shared__ uint4 XS[2][BITS_NW * 64];
+  __shared__ uint4 XS[2][BITS_NW * 2 * 64];
   __shared__ uint2 MX[BITS_NW * 64];
   __shared__ uint32_t red;
   const int lane = threadIdx.x & 63;
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
 #pragma unroll
   for (int d = 0; d < 4; ++d)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < BITS_PLANES; ++q)
 #pragma unroll
       for (int c = 0; c < BITS_CPL; ++c) s.E[d][q][c][0] = s.E[d][q][c][1] = 0u;
 
@@ -469,7 +476,8 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
   uint32_t bits = alive ? 1u : 0u;
   int t = 0;
   // step t + 1 ends at sub-step 3 (t + 1): emission times below 4 in the
-  // first step, below 8 in the second, below 16 up to the fifth
+  // first step, below 8 in the second, below 16 up to the fifth, below 32
+  // up to the tenth
   auto after_step = [&]() {
     ++t;
     alive = __syncthreads_or(any_anyon()) != 0;
@@ -483,8 +491,12 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
     bits_step<3>(s, 3u, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
-  while (alive && t < a.k) {
+  while (alive && t < a.k && t < 5) {
     bits_step<4>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
+    after_step();
+  }
+  while (alive && t < a.k) {
+    bits_step<5>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
 
@@ -513,7 +525,7 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
         for (int d = 0; d < 4; ++d) {
           e[d] = 0u;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
+          for (int q = 0; q < BITS_PLANES; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
         }
         P[c] = e[0] | (e[1] << 16);
         Q[c] = e[2] | (e[3] << 16);

@@ -1508,7 +1508,7 @@ int *pinned_counts(int need) {
 // samples still left (one workgroup per sample), then the export.  Full-size
 // regions and the schedule's k_next steps per pass throughout.
 constexpr int DEVICE_GRID_PASSES = 3;
-int band_tail(BandRun &r, int64_t first_count) {
+int band_tail(BandRun &r, int64_t first_count, int grid_passes = DEVICE_GRID_PASSES) {
   const int k = min(schedule_for(r.L).k_next, r.T_max > 0 ? r.T_max : 1);
   BandArgs ba;
   const int nty = tile_geometry(r.L, k, BAND_RY, ba);
@@ -1521,7 +1521,7 @@ int band_tail(BandRun &r, int64_t first_count) {
   ba.u = r.rule.u;
   ba.seeds = r.rule.seeds;
   int cur = 1;  // the first passes wrote buffer 1 and listed their survivors in active[1]
-  for (int pass = 0; pass < DEVICE_GRID_PASSES && first_count > 0; ++pass) {
+  for (int pass = 0; pass < grid_passes && first_count > 0; ++pass) {
     ba.active = r.w.active[cur];
     ba.Esrc = r.w.E[cur];
     ba.Ssrc = r.w.S[cur];
@@ -1597,7 +1597,9 @@ bool device_driven(const BandRun &r, int64_t first_count) {
   if (hipStreamIsCapturing(r.stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return true;
   if (mode == MPD_BAND_DRIVER_HOST) return false;
   (void)first_count;
-  return false;
+  // after the bit-sliced kernel survivors are rare: a host wait for their
+  // count costs more than the device-side launches
+  return r.first_bound > 0;
 }
 
 // Runs the passes of several band-path batches: the first passes of every
@@ -1625,7 +1627,9 @@ int band_passes(BandRun *runs, int nr) {
     int64_t first = r.first_bound;
     for (int b = 0; b < r.fp.nb; ++b) first += r.fp.count[b];
     if (device_driven(r, first)) {
-      const int rc = band_tail(r, first);
+      // after the bit-sliced kernel (ten steps) the few survivors go straight
+      // to the persistent tail kernel
+      const int rc = band_tail(r, first, r.first_bound > 0 ? 0 : DEVICE_GRID_PASSES);
       if (rc != MPD_OK) return rc;
     }
   }

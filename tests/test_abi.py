@@ -175,25 +175,25 @@ def test_band_driver_setting(lib):
 
 
 def test_band_bits_setting(lib):
-    """Steps of the bit-sliced first kernel: default 5, per-L settings, L = 0
-    applying to every L, values outside [0, 5] and NULL outputs rejected."""
+    """Steps of the bit-sliced first kernel: default 10, per-L settings, L = 0
+    applying to every L, values outside [0, 10] and NULL outputs rejected."""
     k = ctypes.c_int(-1)
     get = lambda L: (lib.mpd_get_band_bits(L, ctypes.byref(k)), k.value)[1]
     try:
-        assert get(0) == 5 and get(256) == 5
-        assert lib.mpd_set_band_bits(256, 6) == -3 and len(lib.mpd_last_error()) > 0
+        assert get(0) == 10 and get(256) == 10
+        assert lib.mpd_set_band_bits(256, 11) == -3 and len(lib.mpd_last_error()) > 0
         assert lib.mpd_set_band_bits(256, -1) == -3
         assert lib.mpd_get_band_bits(256, None) == -4
         assert lib.mpd_set_band_bits(256, 2) == 0
-        assert get(256) == 2 and get(512) == 5
+        assert get(256) == 2 and get(512) == 10
         assert lib.mpd_set_band_schedule(256, 3, 3) == 0   # keeps the setting of L = 256
         assert get(256) == 2
         assert lib.mpd_set_band_bits(0, 0) == 0             # default and every per-L setting
         assert get(256) == 0 and get(0) == 0
     finally:
-        lib.mpd_set_band_bits(0, 5)
+        lib.mpd_set_band_bits(0, 10)
         lib.mpd_set_band_schedule(0, 4, 2)
-    assert get(256) == 5
+    assert get(256) == 10
 
 
 @pytest.mark.parametrize("stmt", ["from paper_2506_03266_amd import binding, sweep, learned",

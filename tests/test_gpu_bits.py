@@ -1,5 +1,6 @@
 """The bit-sliced whole-lattice kernel that runs the first decoder steps of a
-plain L = 256 batch, against the CPU oracle bit for bit (T_dec, flags and
+plain L = 256 batch (up to ten, on 2 to 5 bit planes), against the CPU
+oracle bit for bit (T_dec, flags and
 final syndrome), for every number of bit-sliced steps (0 = the band path's
 first pass), budgets that end inside those steps, noise strengths from none
 to every link, per-sample noise strength and both drivers of the later
@@ -44,11 +45,11 @@ def with_bits(gpu, k, fn):
         gpu.set_band_bits(old, L)
 
 
-def test_default_is_five_steps(gpu):
-    assert gpu.get_band_bits(L) == 5
+def test_default_is_ten_steps(gpu):
+    assert gpu.get_band_bits(L) == 10
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5, 6, 8, 10])
 @pytest.mark.parametrize("p", [0.01, 0.03, 0.06])
 def test_steps_against_oracle(gpu, orc, k, p):
     n, T_max = 24, 256
@@ -58,10 +59,10 @@ def test_steps_against_oracle(gpu, orc, k, p):
     compare(f"k_bits={k} p={p}", T, F, S, ref)
 
 
-@pytest.mark.parametrize("T_max", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("T_max", [0, 1, 2, 3, 4, 5, 6, 9, 10, 11, 12])
 def test_budgets_inside_the_bit_sliced_steps(gpu, orc, T_max):
-    """Timeouts at T_max <= 5 leave their final syndrome from the bit-sliced
-    kernel; T_max = 6 runs one band step after it."""
+    """Timeouts at T_max <= 10 leave their final syndrome from the bit-sliced
+    kernel; T_max = 11 and 12 run band steps after it."""
     p, n = 0.05, 16
     s = seeds(62, T_max, n)
     ref = orc.decode_seeds(L, p, s, T_max, threads=16)
@@ -106,7 +107,7 @@ def test_same_as_band_path_on_a_large_batch(gpu):
     n, p, T_max = 1024, 0.02, 4096
     s = seeds(66, 0, n)
     base = [x.cpu().numpy() for x in with_bits(gpu, 0, lambda: gpu.decode_batch(L, p, s, T_max))]
-    for k in (1, 3, 5):
+    for k in (1, 3, 5, 7, 10):
         got = [x.cpu().numpy() for x in with_bits(gpu, k, lambda: gpu.decode_batch(L, p, s, T_max))]
         for a, b, name in zip(got, base, ("T_dec", "flags", "syndrome")):
             assert np.array_equal(a, b), f"k_bits={k}: {name} differs from the band path"
