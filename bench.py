@@ -383,6 +383,7 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
     runner.run(learned, range(W))
     runner.run(net_on, range(W))
     el_fifo, el, el_net = alternate(runner, [fifo, learned, net_on], W, K)
+    el_sorted = oracle_order(runner, fifo_ws, outs, batches, W, K, n, torch, P)
     # the evaluation samples' predictions (outside the timed region; a
     # one-group policy does not compute them) and the inference time per
     # batch, one stream
@@ -402,11 +403,37 @@ def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
             "identical_results": bool(same), "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])},
             "network_on": {"policy": {"edges": list(net_policy[0]), "first_pass_depth": list(net_policy[1])},
                            "samples_per_s": K * n / el_net, "ratio_vs_fifo": el_fifo / el_net},
+            "oracle_order_ratio_vs_fifo": el_fifo / el_sorted,
             "cnn_forward_ms_per_step": cnn_ms / max(cnn_n, 1), "train_s": t_train,
             "train_mse_last_epoch": hist[-1], "eval_mae_ln": float(np.abs(pred - y).mean()),
             "eval_spearman": float(spearmanr(pred, T).correlation),
             "tuning_ms": {"best": t_best * 1e3, "single_bin": t_single * 1e3, "in_flight": in_flight},
             "mixed_p": mixed}
+
+
+def oracle_order(runner, wss, outs, batches, W, K, n, torch, p):
+    """The plain decode of the same batches with each batch's samples sorted
+    by their measured T_dec, longest first: what a perfect predictor of the
+    decoding time could gain by ordering (an upper bound, not a schedule)."""
+    import paper_2506_03266_amd.binding as b
+    dev = torch.device("cuda")
+    ordered, ps = {}, {}
+    for i in range(W, W + K):
+        perm = torch.argsort(outs[i][0].to(torch.int64), descending=True, stable=True)
+        ordered[i] = batches[i][perm].contiguous()
+        ps[i] = p[i][perm].contiguous() if isinstance(p, dict) else p
+    o = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev), None)
+         for _ in range(W + K)]
+
+    def run(i, j, stream):
+        if isinstance(ps[i], float):
+            b.decode_batch(L, ps[i], ordered[i], T_MAX, want_syndrome=False, workspace=wss[j], out=o[i],
+                           stream=stream)
+        else:
+            b.decode_mixed([(L, n)], ps[i], ordered[i], T_MAX, want_syndrome=False, workspace=wss[j], out=o[i],
+                           stream=stream)
+    runner.run(run, range(W, W + K))
+    return min(runner.run(run, range(W, W + K)) for _ in range(3))
 
 
 def tune_in_flight(b, runner, L_eval, tune_set, params, res, lwss, torch, short=12):
@@ -493,6 +520,7 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
         runner.run(lrn, range(W))
         runner.run(net_on, range(W))
         el_fifo, el_lrn, el_net = alternate(runner, [fifo, lrn, net_on], W, K)
+        el_sorted = oracle_order(runner, wss, fo, bs, W, K, n, torch, {i: ps[i] for i in range(W + K)})
     finally:
         b.set_band_schedule(k0, kn, L_eval)
     same = all(torch.equal(fo[i][0], x[i][0]) and torch.equal(fo[i][1], x[i][1]) and
@@ -506,6 +534,7 @@ def learned_mixed_p(b, W, K, n, params, torch, np, runner, L_eval):
             "policy": {"edges": list(policy[0]), "first_pass_depth": list(policy[1])}, "tuning_ms_in_flight": in_flight,
             "network_on": {"policy": {"edges": list(net_policy[0]), "first_pass_depth": list(net_policy[1])},
                            "samples_per_s": K * n / el_net, "ratio_vs_fifo": el_fifo / el_net},
+            "oracle_order_ratio_vs_fifo": el_fifo / el_sorted,
             "eval_spearman": float(spearmanr(pred, T).correlation), "identical_results": bool(same)}
 
 

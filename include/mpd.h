@@ -509,7 +509,11 @@ int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d
  * mpd_decode_mixed with the one class (L, n).  Outputs as mpd_decode_batch,
  * plus d_pred [n] if not NULL.  With one group and d_pred NULL the network
  * is not evaluated: the call is the plain decode with first-pass depth
- * h_depth[0] (the FIFO fallback; d_params is still checked).  L: a multiple
+ * h_depth[0] (the FIFO fallback; d_params is still checked).  At L = 256
+ * with the bit-sliced first kernel on (mpd_set_band_bits), which stops each
+ * sample as soon as it has no anyon, the groups set the order in which that
+ * kernel takes the samples instead -- the group with the longest predicted
+ * decoding time first -- and the depths only have to be valid.  L: a multiple
  * of 16 in [256, 16384], at most 65535 samples.  Workspace:
  * mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.  The group
  * sizes stay on the device (each group's first pass is sized there), so

@@ -57,6 +57,9 @@ struct BitsArgs {
   uint32_t *alive;       // per sample: bit 0 anyons at the start, bit j anyons after step j
   uint32_t *wind;        // per sample: Wx(E), Wy(E), Wx(C), Wy(C)
   int *zero_count;       // survivor counter of the following compaction (cleared here)
+  const int32_t *order;  // sample of workgroup b: order[b] (nullptr: b) -- the processing order
+  const uint2 *S_in;     // syndrome in the band layout drawn by the noise kernel (its error
+                         // windings already in wind), or nullptr: draw the noise here
 };
 
 // Bit planes of one register field, most significant plane last.
@@ -95,6 +98,17 @@ __device__ __forceinline__ uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t s) {
 // ahead of a long stretch of code.
 __device__ __forceinline__ uint32_t opaque(uint32_t x) {
   asm volatile("" : "+v"(x));
+  return x;
+}
+// The lane's index, formed where it is used (mbcnt), so that no address
+// derived from it stays live across the decoder steps.
+__device__ __forceinline__ int lane_here() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
+}
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {  // the same for a uniform value
+  asm volatile("" : "+s"(x));
   return x;
 }
 
@@ -209,6 +223,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
 #pragma unroll
         for (int q = 0; q < B; ++q) s.E[d][q][c][w] = h.p[q];
         prev = cur;
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
@@ -261,6 +276,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
         s.E[d][q][c][0] = r0.p[q];
         s.E[d][q][c][1] = r1.p[q];
       }
+      __builtin_amdgcn_sched_barrier(0);  // one column at a time: the state fills the register file
     }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -286,6 +302,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
         s.E[d][q][c][0] = r0.p[q];
         s.E[d][q][c][1] = r1.p[q];
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -396,10 +413,12 @@ __device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[
   bits_feedback<B>(s, MX, v, vdn, vup, lane, wind);
 }
 
-// One workgroup per sample: noise, initial syndrome and windings, then up to
+// One workgroup per sample (DRAWN: the syndrome and error windings come from
+// the noise kernel, in a.S_in and a.wind): noise, initial syndrome and windings, then up to
 // a.k decoder steps, stopping after the first step that leaves no anyon.
 // Writes the per-step anyon bits and the windings for k_finalize, and for a
 // sample that still holds anyons its state in the band layout.
+template <bool DRAWN>
 __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
   constexpr int L = BITS_L;
   __shared__ uint4 XS[2][BITS_NW * 2 * 64];
@@ -408,18 +427,36 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
   const int lane = threadIdx.x & 63;
   const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int vdn = v == 0 ? BITS_NW - 1 : v - 1, vup = v == BITS_NW - 1 ? 0 : v + 1;
-  const int64_t sample = blockIdx.x;
+  const int64_t sample = a.order != nullptr ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
   if (a.zero_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_count = 0;
   if (threadIdx.x == 0) red = 0u;
-  const uint64_t seed = a.seeds[sample];
-  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
 
   BitsLane s;
   uint32_t wind = 0u;
-  {
-    // noise (R12 of the oracle's readings): site pairs (4i, 4i + 1) and
-    // (4i + 2, 4i + 3) of row y are generator blocks y L/2 + 2i and + 1
+  if (DRAWN) {
+    // the noise kernel's 16-row masks of column pairs: strips 4v + 2w and
+    // 4v + 2w + 1 make word w; pairs 2i and 2i + 1 are this lane's columns
+    const uint2 *Sp = a.S_in + (size_t)sample * (L / TILE_H) * (L / 2);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const size_t j = (size_t)(4 * v + 2 * w);
+      const uint2 a0 = Sp[j * (L / 2) + 2 * lane], a1 = Sp[j * (L / 2) + 2 * lane + 1];
+      const uint2 b0 = Sp[(j + 1) * (L / 2) + 2 * lane], b1 = Sp[(j + 1) * (L / 2) + 2 * lane + 1];
+      s.S[0][w] = (a0.x & 0xFFFFu) | (b0.x << 16);
+      s.S[1][w] = (a0.y & 0xFFFFu) | (b0.y << 16);
+      s.S[2][w] = (a1.x & 0xFFFFu) | (b1.x << 16);
+      s.S[3][w] = (a1.y & 0xFFFFu) | (b1.y << 16);
+    }
+  } else {
+    const uint64_t seed = a.seeds[sample];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
+
+    // noise: one Philox4x32-10 block (key = seed, counter = site index / 2)
+    // per site pair, words 0 and 1 the x- and y-link of the even site, words
+    // 2 and 3 those of the odd site; a link flips iff its word is below
+    // thr.  Site pairs (4i, 4i + 1) and (4i + 2, 4i + 3) of row y are
+    // blocks y L/2 + 2i and + 1
     uint32_t ex[BITS_CPL][2], ey[BITS_CPL][2];
 #pragma unroll
     for (int c = 0; c < BITS_CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = 0u;
@@ -503,15 +540,20 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
 
   if (wind) atomicXor(&red, wind);
   __syncthreads();
+  // the sample index again (a scalar reload) rather than a value kept live
+  // across the steps
+  const int64_t smp = a.order != nullptr ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[opaque_s(blockIdx.x)])
+                                         : (int64_t)blockIdx.x;
   if (threadIdx.x == 0) {
-    a.alive[sample] = bits;
-    a.wind[sample] = red;
+    a.alive[smp] = bits;
+    a.wind[smp] = DRAWN ? (a.wind[smp] ^ red) : red;  // the noise kernel left Wx(E), Wy(E)
   }
   if (!alive) return;
   // anyons left: the state in the band layout, emission times as packed u16
   // (P = e^{+x} | e^{-x} << 16, Q = e^{+y} | e^{-y} << 16) and 16-row syndrome masks
   constexpr size_t half_row = L / 2;
-  uint4 *E = a.E + (size_t)sample * L * half_row;
+  const int ln = lane_here();
+  uint4 *E = a.E + (size_t)smp * L * half_row;
 #pragma unroll
   for (int w = 0; w < 2; ++w) {
 #pragma unroll 1
@@ -531,14 +573,14 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
         Q[c] = e[2] | (e[3] << 16);
       }
       const size_t y = (size_t)(64 * v + 32 * w + r);
-      E[y * half_row + 2 * lane] = make_uint4(P[0], Q[0], P[1], Q[1]);
-      E[y * half_row + 2 * lane + 1] = make_uint4(P[2], Q[2], P[3], Q[3]);
+      E[y * half_row + 2 * ln] = make_uint4(P[0], Q[0], P[1], Q[1]);
+      E[y * half_row + 2 * ln + 1] = make_uint4(P[2], Q[2], P[3], Q[3]);
     }
-    const size_t strip = (size_t)sample * (L / TILE_H) + (size_t)(4 * v + 2 * w);
-    a.S[strip * half_row + 2 * lane] = make_uint2(s.S[0][w] & 0xFFFFu, s.S[1][w] & 0xFFFFu);
-    a.S[strip * half_row + 2 * lane + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
-    a.S[(strip + 1) * half_row + 2 * lane] = make_uint2(s.S[0][w] >> 16, s.S[1][w] >> 16);
-    a.S[(strip + 1) * half_row + 2 * lane + 1] = make_uint2(s.S[2][w] >> 16, s.S[3][w] >> 16);
+    const size_t strip = (size_t)smp * (L / TILE_H) + (size_t)(4 * v + 2 * w);
+    a.S[strip * half_row + 2 * ln] = make_uint2(s.S[0][w] & 0xFFFFu, s.S[1][w] & 0xFFFFu);
+    a.S[strip * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
+    a.S[(strip + 1) * half_row + 2 * ln] = make_uint2(s.S[0][w] >> 16, s.S[1][w] >> 16);
+    a.S[(strip + 1) * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] >> 16, s.S[3][w] >> 16);
   }
 }
 

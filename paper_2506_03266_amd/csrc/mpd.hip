@@ -1670,12 +1670,20 @@ int band_passes(BandRun *runs, int nr) {
 // Noise and the first k steps of a plain L = 256 batch in the bit-sliced
 // kernel (bits.h), then the usual bookkeeping: T_dec of the samples it
 // finished, the survivors' state in buffer 1 and their list in active[1].
+// With `order` the workgroups take the samples in that order; with
+// `drawn` the noise kernel has already drawn the syndrome into buffer 0 (and
+// initialised the bookkeeping), and the kernel reads it instead of drawing.
 int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max, int k,
-               const BandWorkspace &w, int32_t *d_T_dec, hipStream_t stream) {
-  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
-                     w.status, w.t_done, w.active[0], &w.count[2]);
-  HIP_TRY(hipGetLastError());
+               const BandWorkspace &w, int32_t *d_T_dec, hipStream_t stream, const int32_t *order = nullptr,
+               bool drawn = false) {
+  if (!drawn) {
+    hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, w.alive, w.wind,
+                       w.status, w.t_done, w.active[0], &w.count[2]);
+    HIP_TRY(hipGetLastError());
+  }
   BitsArgs a;
+  a.order = order;
+  a.S_in = drawn ? w.S[0] : nullptr;
   a.seeds = d_seeds;
   a.thr = thr;
   a.p_arr = d_p;
@@ -1687,7 +1695,10 @@ int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, 
   a.zero_count = &w.count[1];
   {
     ProfScope ps("k_bits", stream);
-    hipLaunchKernelGGL(k_bits, dim3((unsigned)n), dim3(BITS_NW * 64), 0, stream, a);
+    if (drawn)
+      hipLaunchKernelGGL(k_bits<true>, dim3((unsigned)n), dim3(BITS_NW * 64), 0, stream, a);
+    else
+      hipLaunchKernelGGL(k_bits<false>, dim3((unsigned)n), dim3(BITS_NW * 64), 0, stream, a);
   }
   HIP_TRY(hipGetLastError());
   (void)L;
@@ -1852,6 +1863,23 @@ __global__ void k_bin(const float *pred, int64_t n, int nb, BinEdges e, int32_t 
   }
 }
 
+// The groups' lists one after another, from the group with the longest
+// predicted decoding time to the shortest: the order in which the bit-sliced
+// kernel takes the samples (longest first, so they do not form the tail).
+__global__ void k_order(const int32_t *lists, const int *counts, int nb, int64_t n, int32_t *order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t off = 0;
+  for (int b = nb - 1; b >= 0; --b) {
+    const int64_t c = counts[b];
+    if (i < off + c) {
+      order[i] = lists[(int64_t)b * n + (i - off)];
+      return;
+    }
+    off += c;
+  }
+}
+
 __global__ void k_zero_i32(int *p, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0;
@@ -1865,6 +1893,7 @@ struct LearnedLayout {
   float *pred;
   int32_t *lists;
   int *bin_count;
+  int32_t *order;
   void *cnn_ws;
   size_t bytes;
 };
@@ -1882,6 +1911,7 @@ LearnedLayout learned_layout(int L, int64_t n, void *base) {
   l.pred = (float *)take((size_t)n * 4);
   l.lists = (int32_t *)take((size_t)MAX_BINS * n * 4);
   l.bin_count = (int *)take(MAX_BINS * sizeof(int));
+  l.order = (int32_t *)take((size_t)n * 4);
   l.cnn_ws = take(cnn_forward_ws(M, n));
   l.bytes = off;
   return l;
@@ -2109,6 +2139,29 @@ int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_see
                      l.bin_count);
   HIP_TRY(hipGetLastError());
   if (d_pred != nullptr) HIP_TRY(hipMemcpyAsync(d_pred, l.pred, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+  const int kb = schedule_for(L).k_bits;
+  if (L == BITS_L && kb > 0) {
+    // the bit-sliced kernel stops each sample when it has no anyon, so the
+    // groups set the order in which it takes them (longest predicted first),
+    // not a depth; it reads the syndrome the noise kernel drew
+    hipLaunchKernelGGL(k_order, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, l.lists, l.bin_count, n_bins,
+                       n, l.order);
+    HIP_TRY(hipGetLastError());
+    BandRun r;
+    r.L = L;
+    r.n = n;
+    r.T_max = T_max;
+    r.w = l.band;
+    r.T_dec = d_T_dec;
+    r.flags = d_flags;
+    r.syn = d_final_syndrome;
+    r.stream = st;
+    r.fp.nb = 0;
+    r.first_bound = n;
+    rc = bits_start(L, 0, nullptr, d_seeds, n, T_max, std::min(kb, T_max), r.w, d_T_dec, st, l.order, true);
+    if (rc != MPD_OK) return rc;
+    return band_passes(&r, 1);
+  }
   BandRun r;
   r.L = L;
   r.n = n;

@@ -140,13 +140,28 @@ def predict(counts, params, chunk: int = 16384):
     return torch.cat([b.cnn_forward(counts[a:a + chunk], params) for a in range(0, counts.shape[0], chunk)])
 
 
-def candidate_policies(pred: np.ndarray, k_first: int, wide: bool = False):
+def ordering_applies(L: int) -> bool:
+    """At L = 256 the bit-sliced first kernel stops every sample on its own,
+    so groups order the samples (longest predicted first) instead of giving
+    them first-pass depths."""
+    return L == 256 and b.get_band_bits(L) > 0
+
+
+def candidate_policies(pred: np.ndarray, k_first: int, wide: bool = False, order_only: bool = False):
     """Binning policies to try: one bin at the default depth (no use of the
     prediction), and splits at prediction quantiles that give the samples
     predicted shortest one step less and/or the longest one step more.  With
     `wide`, two-group splits take any pair of depths within two steps of
     k_first and three-group splits any three such depths (for batches whose
-    decoding times spread widely, e.g. mixed noise strengths)."""
+    decoding times spread widely, e.g. mixed noise strengths).  With
+    `order_only` the groups only order the samples: the top decile or half
+    first, or 4 or 8 groups of equal size, longest predicted first."""
+    if order_only:
+        pol = [((), (k_first,))]
+        for qq in ([0.9], [0.5], [0.25, 0.5, 0.75], [0.125 * i for i in range(1, 8)]):
+            edges = tuple(float(x) for x in np.quantile(pred, qq))
+            pol.append((edges, (k_first,) * (len(edges) + 1)))
+        return pol
     qs = np.quantile(pred, [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9])
     k = k_first
     pairs = [(k - 1, k), (k, k + 1)]
@@ -180,8 +195,12 @@ def plain_decode(L, p, seeds_t, T_max, out=None, workspace=None, stream=None):
 def best_fifo_depth(L, p, seeds_t, T_max: int = 4096, depths=range(2, 9), reps: int = 3, log=None):
     """First-pass depth that minimises the plain decode's time on a tuning
     batch (later passes at the current k_next).  Leaves the band schedule
-    as it found it; returns (depth, {depth: median seconds})."""
+    as it found it; returns (depth, {depth: median seconds}).  Where the
+    bit-sliced first kernel runs (no first-pass depth to choose) it returns
+    the current depth and no timings."""
     k0, kn = b.get_band_schedule(L)
+    if ordering_applies(L):
+        return k0, {}
     times = {}
     try:
         for k in depths:
@@ -235,7 +254,7 @@ def tune_policy(L, p, seeds_t, params, T_max: int = 4096, k_first: int | None = 
     b.decode_learned(L, p, seeds_t, params, (), (k_first,), T_max, want_syndrome=False, workspace=ws, out=out)
     pred = out[3].cpu().numpy()
     res = []
-    for pol in candidate_policies(pred, k_first, wide):
+    for pol in candidate_policies(pred, k_first, wide, order_only=ordering_applies(L)):
         t = time_policy(L, p, seeds_t, params, pol, T_max, reps, ws, out)
         res.append((t, pol))
         if log:

@@ -181,6 +181,32 @@ def test_learned_decode_equals_plain(gpu, orc, policy):
     assert np.isfinite(pred.cpu().numpy()).all()
 
 
+@pytest.mark.parametrize("k_bits", [0, 3, 10])
+@pytest.mark.parametrize("p", [0.01, 0.04])
+def test_learned_order_equals_plain(gpu, orc, k_bits, p):
+    """At L = 256 the groups order the bit-sliced kernel's samples (longest
+    predicted first; the kernel reads the syndrome the noise kernel drew),
+    or, with the bit-sliced kernel off, set first-pass depths: either way
+    the results are the plain decode's, and the oracle's."""
+    L, n = 256, 160
+    s = seeds(54, int(p * 100) * 16 + k_bits, n)
+    params = torch.from_numpy(trained_like_params(11)).cuda()
+    old = gpu.get_band_bits(L)
+    gpu.set_band_bits(k_bits, L)
+    try:
+        T0, F0, S0 = gpu.decode_batch(L, p, s, 4096)
+        pr = gpu.cnn_forward(gpu.syndrome_counts(L, p, s), params).cpu().numpy()
+        edges = tuple(float(x) for x in np.quantile(pr, [0.25, 0.5, 0.75]))
+        T1, F1, S1, _ = gpu.decode_learned(L, p, s, params, edges, (2, 3, 4, 5), 4096)
+    finally:
+        gpu.set_band_bits(old, L)
+    ref = orc.decode_seeds(L, p, s, 4096, threads=16)
+    for T, F, S in ((T0, F0, S0), (T1, F1, S1)):
+        assert np.array_equal(T.cpu().numpy(), ref["T_dec"])
+        assert np.array_equal(F.cpu().numpy(), ref["flags"])
+        assert np.array_equal(S.cpu().numpy().view(np.uint32), ref["sigma_words"])
+
+
 @pytest.mark.parametrize("L,p,n,T_max", [(256, 0.07, 8, 5), (256, 0.06, 8, 0), (512, 0.02, 4, 64),
                                          (1024, 0.01, 2, 64)])
 def test_learned_decode_budgets_and_sizes(gpu, orc, L, p, n, T_max):
