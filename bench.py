@@ -100,7 +100,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.streams is None:
-        args.streams = 3 if args.workload in ("c3", "c5") else 1
+        args.streams = 3 if args.workload in ("c3", "c5") else (4 if args.workload == "async" else 1)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
               "the decoder shards by samples, see DESIGN.md", file=sys.stderr)
@@ -670,6 +670,9 @@ def desynchronized(args, b, seeds, torch, np):
     K, W = args.steps, args.warmup
     rho, S_max = 0.125, 20000
     st = torch.cuda.current_stream()
+    # batches in flight: a sample stuck until S_max holds its compute unit for
+    # the whole launch while the others finish early; other batches fill them
+    runner = Runner(max(1, args.streams), torch)
     cases = ((64, 0.05, 1024), (64, 0.03, 1024), (32, 0.05, 2048))
     for L_a, p, n in (cases if args.async_case < 0 else cases[args.async_case:args.async_case + 1]):
         batches = [torch.from_numpy(seeds(11, int(p * 1000) + L_a, n, start=i * n).view(np.int64)).to(dev)
@@ -688,6 +691,11 @@ def desynchronized(args, b, seeds, torch, np):
         dt = time.perf_counter() - t0
         b.profile(False)
         kms, launches = b.profile_read("k_async")
+        # the same batches with several in flight (one host thread and stream each)
+        def run_async(i, j, stream, unc=False, sched="cyclic"):
+            b.decode_async(L_a, p, batches[i], rho, S_max, out=outs[i], stream=stream, uncoordinated=unc,
+                           schedule=sched)
+        dt_flight = runner.run(run_async, range(W, W + K)) if len(runner.streams) > 1 else dt
         cat = lambda j: torch.cat([outs[i][j] for i in range(W, W + K)]).cpu().numpy()
         T, F, SL, U = cat(0), cat(1), cat(2).astype(np.int64), cat(3).astype(np.int64)
         # the synchronous decoder on the same seeds
@@ -702,7 +710,8 @@ def desynchronized(args, b, seeds, torch, np):
         both = ((F & 2) == 0) & ((Fs & 2) == 0)
         line = {"workload": f"desynchronized decoder: L={L_a} p={p} {n} samples per batch, ring probability {rho} "
                             f"per slot, S_max={S_max}",
-                "samples_per_s": K * n / dt, "ms_per_batch": dt / K * 1e3,
+                "samples_per_s": K * n / dt_flight, "batches_in_flight": len(runner.streams),
+                "single_stream_samples_per_s": K * n / dt, "ms_per_batch": dt / K * 1e3,
                 "kernel": {"name": "k_async", "avg_launch_ms": kms / max(launches, 1), "launches": launches},
                 "accepted_updates_per_s": float(U.sum()) / dt,
                 "slots_mean": float(SL.mean()), "slots_max": int(SL.max()),
@@ -727,9 +736,12 @@ def desynchronized(args, b, seeds, torch, np):
             dtu = time.perf_counter() - t0
             b.profile(False)
             kmu, lu = b.profile_read("k_async_unc")
+            dtu_flight = (runner.run(lambda i, j, stream: run_async(i, j, stream, True, sched), range(W, W + K))
+                          if len(runner.streams) > 1 else dtu)
             Tu, Fu, SLu, Uu = cat(0), cat(1), cat(2).astype(np.int64), cat(3).astype(np.int64)
             key = "uncoordinated" if sched == "cyclic" else "uncoordinated_random"
-            line[key] = {"samples_per_s": K * n / dtu, "ms_per_batch": dtu / K * 1e3,
+            line[key] = {"samples_per_s": K * n / dtu_flight, "single_stream_samples_per_s": K * n / dtu,
+                         "ms_per_batch": dtu / K * 1e3,
                          "kernel": {"name": "k_async_unc", "avg_launch_ms": kmu / max(lu, 1), "launches": lu},
                          "updates_per_s": float(Uu.sum()) / dtu, "slots_mean": float(SLu.mean()),
                          "decoding_time_mean": float(Tu.mean()) * rho, "fail_rate": float((Fu & 1).mean()),
