@@ -389,11 +389,13 @@ int mpd_set_band_bits(int L, int k_bits);
 int mpd_get_band_bits(int L, int *k_bits);
 
 /* Autotuner for the band path: decodes the probe batch (same arguments as
- * mpd_decode_batch, outputs overwritten) once per candidate schedule
- * driver (host, device) x k_first in [2, 6] x k_next in [1, 4], timing each
- * with HIP events on `stream`, and keeps the fastest for this L
- * (mpd_get_band_schedule and mpd_get_band_driver then return it).
- * *k_first, *k_next and *best_ms receive the choice.
+ * mpd_decode_batch, outputs overwritten) once per candidate schedule --
+ * driver (host, device) x k_first in [1, 8] x k_next in [1, 8], and at
+ * L = 256 also the steps of the bit-sliced first kernel (0, 3, 5, 8, 10;
+ * with it on, k_first is not searched, since the band passes start after
+ * it) -- timing each with HIP events on `stream`, and keeps the fastest for
+ * this L (mpd_get_band_schedule, mpd_get_band_driver and mpd_get_band_bits
+ * then return it).  *k_first, *k_next and *best_ms receive the choice.
  * Synchronizes `stream`. */
 int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
                       uint8_t *d_flags, void *d_workspace, size_t ws_bytes, void *stream, int *k_first,

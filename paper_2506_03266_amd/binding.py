@@ -492,15 +492,16 @@ def get_band_bits(L: int = 0) -> int:
 
 
 def save_band_tuning(path: str, Ls) -> dict:
-    """Write the band-path settings of the lattice sizes Ls (schedule and
-    driver, as the autotuner or the setters left them) and the defaults to a
+    """Write the band-path settings of the lattice sizes Ls (schedule,
+    driver and bit-sliced steps, as the autotuner or the setters left them) and the defaults to a
     JSON file, so that a later process can reuse them without re-tuning.
     Returns what was written."""
     import json
     state = {"default": {"k_first": get_band_schedule(0)[0], "k_next": get_band_schedule(0)[1],
-                         "driver": get_band_driver(0)},
+                         "driver": get_band_driver(0), "k_bits": get_band_bits(0)},
              "per_L": {str(int(L)): {"k_first": get_band_schedule(int(L))[0], "k_next": get_band_schedule(int(L))[1],
-                                     "driver": get_band_driver(int(L))} for L in Ls}}
+                                     "driver": get_band_driver(int(L)), "k_bits": get_band_bits(int(L))}
+                       for L in Ls}}
     with open(path, "w") as f:
         json.dump(state, f, indent=1)
     return state
@@ -515,16 +516,19 @@ def load_band_tuning(path: str) -> dict:
     d = state["default"]
     set_band_schedule(d["k_first"], d["k_next"], 0)
     set_band_driver(d["driver"], 0)
+    set_band_bits(d.get("k_bits", 10), 0)
     for L, e in state["per_L"].items():
         set_band_schedule(e["k_first"], e["k_next"], int(L))
         set_band_driver(e["driver"], int(L))
+        set_band_bits(e.get("k_bits", 10), int(L))
     return state
 
 
 def autotune_band(L: int, p: float, seeds, T_max: int = 4096, stream=None):
-    """Time the band-path schedules (driver x k_first x k_next) on a probe
-    batch and keep the fastest for L.  Returns (k_first, k_next, best_ms);
-    get_band_driver(L) gives the chosen driver."""
+    """Time the band-path schedules (driver x k_first x k_next, and at L = 256
+    the steps of the bit-sliced first kernel) on a probe batch and keep the
+    fastest for L.  Returns (k_first, k_next, best_ms); get_band_driver(L)
+    and get_band_bits(L) give the chosen driver and bit-sliced steps."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()

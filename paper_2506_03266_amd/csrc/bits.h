@@ -112,6 +112,13 @@ __device__ __forceinline__ uint32_t opaque_s(uint32_t x) {  // the same for a un
   return x;
 }
 
+// m = 2 m + [x < t] in two instructions: the comparison leaves the bit in
+// VCC and an add with carry shifts it in (the compiler would take three:
+// compare, select, shift-or).  t is uniform.
+__device__ __forceinline__ void shift_in_below(uint32_t &m, uint32_t x, uint32_t t) {
+  asm("v_cmp_gt_u32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc" : "+v"(m) : "v"(x), "s"(t) : "vcc");
+}
+
 struct BitsLane {
   uint32_t E[4][BITS_PLANES][BITS_CPL][2];  // [register: +x, -x, +y, -y][bit][column][word]
   uint32_t S[BITS_CPL][2];        // syndrome (anyon = 1)
@@ -460,23 +467,32 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
     uint32_t ex[BITS_CPL][2], ey[BITS_CPL][2];
 #pragma unroll
     for (int c = 0; c < BITS_CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = 0u;
+    // Rows from the top of each word down: a mask shifts left and takes the
+    // new row's bit at bit 0 (m = 2 m + [word < thr] through the carry of
+    // one v_addc), so row r ends at bit r.  thr = 2^32 (p = 1) flips every
+    // link; below that the 32-bit comparison is exact.
+    const uint32_t thr32 = thr > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)thr;
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
 #pragma unroll 2
-      for (int r = 0; r < 32; ++r) {
+      for (int r = 31; r >= 0; --r) {
         const uint32_t y = (uint32_t)(64 * v + 32 * w + r);
         const uint32_t blk = y * (L / 2) + 2u * (uint32_t)lane;
         const Words4 A = philox4x32_10(blk, k0, k1);
         const Words4 B = philox4x32_10(blk + 1u, k0, k1);
-        ex[0][w] |= (uint32_t)((uint64_t)A.w0 < thr) << r;
-        ey[0][w] |= (uint32_t)((uint64_t)A.w1 < thr) << r;
-        ex[1][w] |= (uint32_t)((uint64_t)A.w2 < thr) << r;
-        ey[1][w] |= (uint32_t)((uint64_t)A.w3 < thr) << r;
-        ex[2][w] |= (uint32_t)((uint64_t)B.w0 < thr) << r;
-        ey[2][w] |= (uint32_t)((uint64_t)B.w1 < thr) << r;
-        ex[3][w] |= (uint32_t)((uint64_t)B.w2 < thr) << r;
-        ey[3][w] |= (uint32_t)((uint64_t)B.w3 < thr) << r;
+        shift_in_below(ex[0][w], A.w0, thr32);
+        shift_in_below(ey[0][w], A.w1, thr32);
+        shift_in_below(ex[1][w], A.w2, thr32);
+        shift_in_below(ey[1][w], A.w3, thr32);
+        shift_in_below(ex[2][w], B.w0, thr32);
+        shift_in_below(ey[2][w], B.w1, thr32);
+        shift_in_below(ex[3][w], B.w2, thr32);
+        shift_in_below(ey[3][w], B.w3, thr32);
       }
+    }
+    if (thr > 0xFFFFFFFFull) {
+#pragma unroll
+      for (int c = 0; c < BITS_CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = ~0u;
     }
     uint32_t upw = 0u;
 #pragma unroll

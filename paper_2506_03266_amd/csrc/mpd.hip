@@ -2313,12 +2313,33 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
   float best = 1e30f;
   BandSchedule pick = saved;
   int rc = MPD_OK;
-  for (int drv = MPD_BAND_DRIVER_HOST; drv <= MPD_BAND_DRIVER_DEVICE && rc == MPD_OK; ++drv) {
-    for (int kf = 2; kf <= 6 && rc == MPD_OK; ++kf)
-      for (int kn = 1; kn <= 4 && rc == MPD_OK; ++kn) {
+  // candidates: driver x (steps of the bit-sliced first kernel where it
+  // applies: 0, 3, 5, 8, 10) x first-pass depth 1..8 (only without the
+  // bit-sliced kernel: with it the band passes start later) x later depth 1..8
+  std::vector<BandSchedule> cand;
+  const bool bits_here = L == BITS_L;
+  for (int drv = MPD_BAND_DRIVER_HOST; drv <= MPD_BAND_DRIVER_DEVICE; ++drv)
+    for (int kb : {0, 3, 5, 8, 10}) {
+      if (!bits_here && kb != 0) continue;
+      for (int kf = 1; kf <= 8; ++kf) {
+        if (kb > 0 && kf != saved.k_first) continue;
+        for (int kn = 1; kn <= 8; ++kn) {
+          BandSchedule c;
+          c.k_first = kf;
+          c.k_next = kn;
+          c.driver = drv;
+          c.k_bits = bits_here ? kb : saved.k_bits;
+          cand.push_back(c);
+        }
+      }
+    }
+  for (size_t ci = 0; ci < cand.size() && rc == MPD_OK; ++ci) {
+    const BandSchedule c = cand[ci];
+    {
+      {
         {
           std::lock_guard<std::mutex> lk(g_sched_mu);
-          g_sched_by_L[L] = BandSchedule{kf, kn, drv};
+          g_sched_by_L[L] = c;
         }
         // warm-up run, then a timed run
         rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
@@ -2334,9 +2355,10 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
           best = ms;
-          pick = BandSchedule{kf, kn, drv};
+          pick = c;
         }
       }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

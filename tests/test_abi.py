@@ -292,16 +292,21 @@ def test_band_tuning_round_trip(lib, tmp_path):
         b.set_band_schedule(2, 1, 512)
         b.set_band_driver(b.BAND_DRIVER_DEVICE, 512)
         b.set_band_schedule(6, 4, 1024)
+        b.set_band_bits(3, 256)
         path = str(tmp_path / "tuning.json")
-        saved = b.save_band_tuning(path, [512, 1024])
-        assert saved["per_L"]["512"] == {"k_first": 2, "k_next": 1, "driver": b.BAND_DRIVER_DEVICE}
+        saved = b.save_band_tuning(path, [256, 512, 1024])
+        assert saved["per_L"]["512"] == {"k_first": 2, "k_next": 1, "driver": b.BAND_DRIVER_DEVICE, "k_bits": 10}
+        assert saved["per_L"]["256"]["k_bits"] == 3
         b.set_band_driver(b.BAND_DRIVER_AUTO, 0)
         b.set_band_schedule(4, 2, 0)
-        assert b.get_band_schedule(512) == (4, 2)
+        b.set_band_bits(10, 0)
+        assert b.get_band_schedule(512) == (4, 2) and b.get_band_bits(256) == 10
         b.load_band_tuning(path)
         assert b.get_band_schedule(0) == (5, 3)
         assert b.get_band_schedule(512) == (2, 1) and b.get_band_driver(512) == b.BAND_DRIVER_DEVICE
         assert b.get_band_schedule(1024) == (6, 4) and b.get_band_driver(1024) == b.get_band_driver(0)
+        assert b.get_band_bits(256) == 3
     finally:
         b.set_band_driver(b.BAND_DRIVER_AUTO, 0)
         b.set_band_schedule(4, 2, 0)
+        b.set_band_bits(10, 0)

@@ -260,16 +260,20 @@ def test_one_nonempty_class_among_empty_ones(gpu, orc, L):
     assert np.array_equal(_np(S).view(np.uint32), ref["sigma_words"].reshape(-1))
 
 
-def test_autotune_keeps_results(gpu):
-    """The autotuner picks a schedule for L; decoding with it is unchanged."""
-    s = seeds(48, 0, 256)
-    T0, F0, _ = gpu.decode_batch(256, 0.01, s, 4096)
-    kf, kn, ms = gpu.autotune_band(256, 0.01, s, 4096)
-    assert 2 <= kf <= 6 and 1 <= kn <= 4 and ms > 0
-    assert gpu.get_band_schedule(256) == (kf, kn)
-    T1, F1, _ = gpu.decode_batch(256, 0.01, s, 4096)
+@pytest.mark.parametrize("L,p,n", [(256, 0.01, 256), (256, 0.05, 64), (512, 0.02, 16)])
+def test_autotune_keeps_results(gpu, L, p, n):
+    """The autotuner picks a schedule for L (depths 1..8, and at L = 256 the
+    bit-sliced steps); decoding with it is unchanged."""
+    s = seeds(48, L, n)
+    T0, F0, _ = gpu.decode_batch(L, p, s, 4096)
+    kf, kn, ms = gpu.autotune_band(L, p, s, 4096)
+    assert 1 <= kf <= 8 and 1 <= kn <= 8 and ms > 0
+    assert gpu.get_band_schedule(L) == (kf, kn)
+    assert gpu.get_band_bits(L) in ((0, 3, 5, 8, 10) if L == 256 else (10,))
+    T1, F1, _ = gpu.decode_batch(L, p, s, 4096)
     assert np.array_equal(_np(T0), _np(T1)) and np.array_equal(_np(F0), _np(F1))
     gpu.set_band_schedule(4, 2)  # restore the defaults for the other tests
+    gpu.set_band_bits(10)
 
 
 def test_mixed_many_band_classes(gpu, orc):
