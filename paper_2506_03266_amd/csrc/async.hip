@@ -33,11 +33,14 @@
 // A ringer's key is (priority word >> 13) << 13 | i, unique per site (i <
 // 4096); the largest, 0xFFFFEFFF, stays below the key ~0 of an idle site (not
 // ringing, or done for this slot).  A pending site is ready when its key is
-// the minimum of the 5 x 5 box around it, found in two separable passes (row
-// minima, then column minima of those).
+// the minimum of the 5 x 5 box around it.  Only pending sites are visited:
+// they are kept in a list (the ringers at the start of a slot, then the ones
+// not ready in a round), so a round reads the 25 keys of each pending site's
+// box instead of two passes over every site.
 //
 // One workgroup holds one sample (5 <= L <= 64) in LDS for its whole run:
-//   K, H    u32 per site: key of the current slot, row minimum of the keys
+//   K       u32 per site: key of the current slot
+//   PL      two u16 lists of the pending sites (the current round's, the next)
 //   MN, MO  uint2 per site: m^new / m^old in distance form, packed u16
 //           (.x = m^{+x} | m^{-x} << 16, .y = m^{+y} | m^{-y} << 16)
 //   TS      u16 simulation time
@@ -87,7 +90,7 @@ constexpr int ASYNC_SITES = 4;   // sites per thread; the launch uses at least N
 
 size_t async_lds(int L) {
   const size_t N = (size_t)L * L;
-  return ((30 * N + 15) & ~(size_t)15) + 32;
+  return ((30 * N + 15) & ~(size_t)15) + 64;
 }
 
 
@@ -143,7 +146,8 @@ __device__ __forceinline__ bool wg_or(bool pred, int *flags, uint32_t &c) {
 }
 
 struct AsyncLds {
-  uint32_t *K, *H;
+  uint32_t *K;
+  uint16_t *PL[2];
   uint2 *MN, *MO;
   uint16_t *TS;
   uint8_t *FL, *CH;
@@ -296,21 +300,23 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   const int L = a.L, N = L * L;
   AsyncLds s;
   s.K = (uint32_t *)lds;
-  s.H = s.K + N;
-  s.MN = (uint2 *)(s.H + N);
+  s.PL[0] = (uint16_t *)(s.K + N);
+  s.PL[1] = s.PL[0] + N;
+  s.MN = (uint2 *)(s.PL[1] + N);
   s.MO = s.MN + N;
   s.TS = (uint16_t *)(s.MO + N);
   s.FL = (uint8_t *)(s.TS + N);
   s.CH = s.FL + N;
   s.RL = (uint16_t *)(s.CH + N);
   // wind bits, 1 + last flip slot, updates, lengths of the ready list (two),
-  // the three flags of wg_or
+  // the three flags of wg_or, lengths of the pending lists (two)
   int *RED = (int *)(lds + ((30 * (size_t)N + 15) & ~(size_t)15));
+  int *RC = RED + 3, *PC = RED + 8;
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x, T = blockDim.x;
   const uint64_t seed = a.seeds != nullptr ? a.seeds[b] : 0u;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  if (tid < 8) RED[tid] = 0;
+  if (tid < 16) RED[tid] = 0;
   const int LW = (2 * N + 31) / 32;
   for (int i = tid; i < N; i += T) {
     uint32_t e;
@@ -342,14 +348,6 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   for (int i = tid; i < N; i += T) s.CH[i] = 0;
   __syncthreads();
 
-  // coordinates of the sites this thread owns (x | y << 16), so that no
-  // division by L runs inside the slot loop
-  uint32_t xy[ASYNC_SITES];
-#pragma unroll
-  for (int k = 0; k < ASYNC_SITES; ++k) {
-    const int i = min(tid + k * T, N - 1);
-    xy[k] = (uint32_t)(i % L) | (uint32_t)(i / L) << 16;
-  }
   const bool run = a.t_target >= 0;
   const uint32_t target = run ? 4u * (uint32_t)a.t_target : 0u;
   int last_flip = -1;
@@ -360,104 +358,108 @@ __global__ __launch_bounds__(1024) void k_async(AsyncArgs a) {
   for (;; ++slot) {
     int busy = 0;
     for (int i = tid; i < N; i += T) busy |= run ? (s.TS[i] < target) : (s.FL[i] != 0);
+    if (tid == 0) {  // read by every thread before the last barrier of the previous slot
+      RC[0] = 0;
+      RC[1] = 0;
+    }
     if (slot < a.S_max) {
-      for (int h = tid; 2 * h < N; h += T) {
-        const Words4 w = philox4x32_10((uint32_t)h, k0, k1, (uint32_t)slot, CLOCK_TAG);
+      // ring draws; the ringers are listed as the pending sites of round 0
+      // (PC[0] is zero here: its last round ended on an empty list, or zeroed it)
+      const int lane = tid & 63;
+      const uint64_t below = (lane ? (~0ull >> (64 - lane)) : 0ull);
+      for (int h0 = 0; 2 * h0 < N; h0 += T) {
+        const int h = h0 + tid;
         const int i0 = 2 * h, i1 = 2 * h + 1;
-        const bool r0 = (uint64_t)w.w0 < a.ring_thr && (!run || s.TS[i0] < target);
-        s.K[i0] = r0 ? ((w.w1 >> 13) << 13 | (uint32_t)i0) : IDLE;
-        if (i1 < N) {
-          const bool r1 = (uint64_t)w.w2 < a.ring_thr && (!run || s.TS[i1] < target);
-          s.K[i1] = r1 ? ((w.w3 >> 13) << 13 | (uint32_t)i1) : IDLE;
+        bool r0 = false, r1 = false;
+        if (2 * h < N) {
+          const Words4 w = philox4x32_10((uint32_t)h, k0, k1, (uint32_t)slot, CLOCK_TAG);
+          r0 = (uint64_t)w.w0 < a.ring_thr && (!run || s.TS[i0] < target);
+          s.K[i0] = r0 ? ((w.w1 >> 13) << 13 | (uint32_t)i0) : IDLE;
+          if (i1 < N) {
+            r1 = (uint64_t)w.w2 < a.ring_thr && (!run || s.TS[i1] < target);
+            s.K[i1] = r1 ? ((w.w3 >> 13) << 13 | (uint32_t)i1) : IDLE;
+          }
+        }
+        const uint64_t b0 = __ballot(r0), b1 = __ballot(r1);
+        const int tot = __popcll(b0) + __popcll(b1);
+        if (tot) {
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&PC[0], tot);
+          base = __builtin_amdgcn_readfirstlane(base);
+          if (r0) s.PL[0][base + __popcll(b0 & below)] = (uint16_t)i0;
+          if (r1) s.PL[0][base + __popcll(b0) + __popcll(b1 & below)] = (uint16_t)i1;
         }
       }
     }
     busy_any = wg_or(busy != 0, RED + 5, orc);
     if (!busy_any || slot >= a.S_max) break;
-    // Rounds.  The row pass of the next round shares the update phase of the
-    // current one: it reads only the keys, which change only in the listing
-    // phase, and writes H, which only the listing phase reads.  The
-    // ready-list length alternates between two counters so that one is
-    // cleared while the other is read.
-    if (tid == 0) {
-      RED[3] = 0;
-      RED[4] = 0;
-    }
-    uint32_t kv[ASYNC_SITES][5];
-    auto row_pass = [&]() {
-      // row minima of the keys over x - 2 .. x + 2 (all loads of the thread's
-      // sites issued together); returns whether any own site is pending
+    // Rounds.  Phase A: every pending site reads the keys of its 5 x 5 box
+    // (a snapshot: no key changes in this phase); the box minimum is ready
+    // and goes to the ready list, the others to the next pending list.
+    // Phase B: the ready sites go idle and attempt their updates.  Counters
+    // alternate between rounds, each cleared by thread 0 once every thread
+    // has read it (after the barrier that follows its last read).
+    for (int cur = 0;; cur ^= 1) {
+      const int npend = PC[cur];
+      if (npend == 0) break;
+      const int nxt = cur ^ 1;
+      // the lists by select, not by indexing (an indexed array would live in
+      // private memory)
+      const uint16_t *plc = cur ? s.PL[1] : s.PL[0];
+      uint16_t *pln = cur ? s.PL[0] : s.PL[1];
+      const int lane = tid & 63;
+      const uint64_t below = (lane ? (~0ull >> (64 - lane)) : 0ull);
+      for (int e0 = 0; e0 < npend; e0 += T) {
+        const int e = e0 + tid;
+        bool ready = false, keep = false;
+        int i = 0;
+        if (e < npend) {
+          i = plc[e];
+          const int x = i % L, y = i / L;
+          int col[5];
 #pragma unroll
-      for (int k = 0; k < ASYNC_SITES; ++k) {
-        const int i = min(tid + k * T, N - 1);
-        const int x = (int)(xy[k] & 0xFFFFu), r0 = i - x;
+          for (int d = 0; d < 5; ++d) col[d] = wrapc(x + d - 2, L);
+          uint32_t kb[5][5];
 #pragma unroll
-        for (int d = 0; d < 5; ++d) kv[k][d] = s.K[r0 + wrapc(x + d - 2, L)];
-      }
-      int pend = 0;
+          for (int dy = 0; dy < 5; ++dy) {
+            const int r0 = wrapc(y + dy - 2, L) * L;
 #pragma unroll
-      for (int k = 0; k < ASYNC_SITES; ++k) {
-        const int i = tid + k * T;
-        if (i < N) {
-          pend |= kv[k][2] != IDLE;
-          s.H[i] = min(min(min(kv[k][0], kv[k][1]), min(kv[k][2], kv[k][3])), kv[k][4]);
-        }
-      }
-      return pend;
-    };
-    int pend = row_pass();
-    for (int round = 0;; ++round) {
-      if (!wg_or(pend != 0, RED + 5, orc)) break;
-      int *cnt = &RED[3 + (round & 1)];
-      // a pending site holding the minimum of its box is ready
-      uint32_t rbits = 0;
-#pragma unroll
-      for (int k = 0; k < ASYNC_SITES; ++k) {
-        const int x = (int)(xy[k] & 0xFFFFu), y = (int)(xy[k] >> 16);
-        uint32_t m = IDLE;
-#pragma unroll
-        for (int d = 0; d < 5; ++d) m = min(m, s.H[wrapc(y + d - 2, L) * L + x]);
-        const bool ready = tid + k * T < N && kv[k][2] != IDLE && m == kv[k][2];
-        rbits |= (ready ? 1u : 0u) << k;
-      }
-      // list the ready sites: one atomic per wave, offsets from the ballots
-      {
-        const int lane = tid & 63;
-        const uint64_t below = (lane ? (~0ull >> (64 - lane)) : 0ull);
-        uint64_t bal[ASYNC_SITES];
-        int tot = 0;
-#pragma unroll
-        for (int k = 0; k < ASYNC_SITES; ++k) {
-          bal[k] = __ballot((rbits >> k) & 1u);
-          tot += __popcll(bal[k]);
-        }
-        if (tot) {
-          int base = 0;
-          if (lane == 0) base = atomicAdd(cnt, tot);
-          base = __builtin_amdgcn_readfirstlane(base);
-#pragma unroll
-          for (int k = 0; k < ASYNC_SITES; ++k) {
-            if ((rbits >> k) & 1u) {
-              const int i = tid + k * T;
-              s.RL[base + __popcll(bal[k] & below)] = (uint16_t)i;
-              s.K[i] = IDLE;
-            }
-            base += __popcll(bal[k]);
+            for (int dx = 0; dx < 5; ++dx) kb[dy][dx] = s.K[r0 + col[dx]];
           }
+          uint32_t m = IDLE;
+#pragma unroll
+          for (int dy = 0; dy < 5; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 5; ++dx) m = min(m, kb[dy][dx]);
+          ready = m == kb[2][2];
+          keep = !ready;
         }
+        const uint64_t br = __ballot(ready), bk = __ballot(keep);
+        int baser = 0, basek = 0;
+        if (lane == 0) {
+          if (br) baser = atomicAdd(&RC[cur], __popcll(br));
+          if (bk) basek = atomicAdd(&PC[nxt], __popcll(bk));
+        }
+        baser = __builtin_amdgcn_readfirstlane(baser);
+        basek = __builtin_amdgcn_readfirstlane(basek);
+        if (ready) s.RL[baser + __popcll(br & below)] = (uint16_t)i;
+        if (keep) pln[basek + __popcll(bk & below)] = (uint16_t)i;
       }
       __syncthreads();
-      // the listed sites attempt their updates, one per lane
-      const int nready = *cnt;
-      if (tid == 0) RED[3 + ((round + 1) & 1)] = 0;
+      const int nready = RC[cur];
+      if (tid == 0) {
+        PC[cur] = 0;  // read at this round's start, before the barrier above
+        RC[nxt] = 0;  // read in the previous round's phase B, before its closing barrier
+      }
       for (int e = tid; e < nready; e += T) {
         const int i = s.RL[e];
+        s.K[i] = IDLE;
         const int r = UNC ? uncoord_update(s, L, i, i % L, i / L, a.sched, (uint32_t)slot, k0, k1)
                           : async_attempt(s, L, i, i % L, i / L);
         my_updates += r > 0;
         if (r == 2) last_flip = slot;
       }
-      pend = row_pass();
+      __syncthreads();
     }
   }
 
