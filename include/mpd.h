@@ -360,10 +360,10 @@ int mpd_get_band_schedule(int L, int *k_first, int *k_next);
  *                           tile, until each is decoded or reaches T_max.
  *                           No host wait: a band-path decode can then be
  *                           captured into a HIP graph.
- *   MPD_BAND_DRIVER_AUTO    the device on a stream that is being captured
- *                           or after the bit-sliced first kernel (see
- *                           mpd_set_band_bits; its survivors are rare and go
- *                           straight to the persistent launch), else the host.
+ *   MPD_BAND_DRIVER_AUTO    the device on a stream that is being captured,
+ *                           else the host.  (After the bit-sliced first
+ *                           kernel, see mpd_set_band_bits, the device-driven
+ *                           survivors go straight to the persistent launch.)
  * Results never depend on the driver.  L = 0 sets the default and the
  * driver of every per-L setting; otherwise this L only.  A stream under
  * capture always takes the device.  Process-wide, guarded by a mutex;

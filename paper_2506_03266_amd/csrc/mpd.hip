@@ -1597,9 +1597,7 @@ bool device_driven(const BandRun &r, int64_t first_count) {
   if (hipStreamIsCapturing(r.stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return true;
   if (mode == MPD_BAND_DRIVER_HOST) return false;
   (void)first_count;
-  // after the bit-sliced kernel survivors are rare: a host wait for their
-  // count costs more than the device-side launches
-  return r.first_bound > 0;
+  return false;
 }
 
 // Runs the passes of several band-path batches: the first passes of every
