@@ -374,17 +374,20 @@ int mpd_get_band_schedule(int L, int *k_first, int *k_next);
 int mpd_set_band_driver(int L, int driver);
 int mpd_get_band_driver(int L, int *driver);
 
-/* First steps of a plain seeded L = 256 batch in the bit-sliced kernel.
- * During the first ten decoder steps every emission time is at most 30, so
- * the registers fit in 5-bit planes and a whole L = 256 torus fits in one
- * workgroup (no halo, no HBM state); a sample leaves as soon as it has no
- * anyon, and the others continue on the band path from the state it hands
- * over.  k_bits in [0, 10]: the number of such steps (0: the band path's
- * first pass instead).  Applies to mpd_decode_batch, mpd_decode_mixed and
- * the one-group learned decode at L = 256 with the plain rule (Def.
- * "message passing automaton, general dimensions"); results never depend on
- * it.  L = 0 sets the default and every per-L setting (default 10).
- * Process-wide, guarded by a mutex; MPD_ERR_TMAX outside [0, 10]. */
+/* First steps of a plain seeded batch at L = 64, 128 or 256 in the
+ * bit-sliced kernel.  During the first ten decoder steps every emission time
+ * is at most 30, so the registers fit in 5-bit planes and a whole torus fits
+ * in one workgroup (L/64 waves; no halo, no HBM state); a sample leaves as
+ * soon as it has no anyon.  At L = 256 the others continue on the band path
+ * from the state the kernel hands over; at L = 64 and 128 the whole-lattice
+ * kernel decodes them again from their seeds (no workspace).  k_bits in
+ * [0, 10]: the number of such steps (0: the band path's first pass, or the
+ * whole-lattice kernel alone).  Applies to mpd_decode_batch,
+ * mpd_decode_batch_static, mpd_decode_mixed and, at L = 256, the one-group
+ * learned decode, with the plain rule (Def. "message passing automaton,
+ * general dimensions"); results never depend on it.  L = 0 sets the default
+ * and every per-L setting (default 10).  Process-wide, guarded by a mutex;
+ * MPD_ERR_TMAX outside [0, 10]. */
 int mpd_set_band_bits(int L, int k_bits);
 int mpd_get_band_bits(int L, int *k_bits);
 
@@ -429,9 +432,11 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
  * events on the launch stream around every kernel launch of the library;
  * mpd_profile(0) stops recording (records are kept).  Names: "k_band_noise"
  * (noise and initial syndrome of a band-path batch), "k_band" (one pass of k
- * decoder steps over the bands of L >= 256), "k_resident" (whole decode of
- * small lattices), "k_cnn_forward" and "k_cnn_backward" (decode-time
- * predictor).  Records from several host threads are kept together. */
+ * decoder steps over the bands of L >= 256), "k_bits" (noise and the first
+ * steps of an L = 256 batch, bit-sliced), "k_bits_small" (the same at L = 64
+ * and 128), "k_torus" (whole decode at L = 64 and 128), "k_resident" (whole
+ * decode of other small lattices), "k_cnn_forward" and "k_cnn_backward"
+ * (decode-time predictor).  Records from several host threads are kept together. */
 int mpd_profile(int enable);
 
 /* Sum of the recorded durations (ms) and number of launches of `kernel`;

@@ -479,9 +479,10 @@ def get_band_driver(L: int = 0) -> int:
 
 
 def set_band_bits(k_bits: int, L: int = 0):
-    """Decoder steps of a plain L = 256 batch that run in the bit-sliced
-    whole-lattice kernel before the band passes (0..10; 0: the band path's
-    first pass instead); L = 0 sets the default and every per-L setting."""
+    """Decoder steps of a plain batch at L = 64, 128 or 256 that run in the
+    bit-sliced whole-lattice kernel first (0..10; 0: the band path's first
+    pass, or at L = 64 and 128 the whole-lattice kernel alone); L = 0 sets the
+    default and every per-L setting."""
     _check(lib().mpd_set_band_bits(int(L), int(k_bits)), "mpd_set_band_bits")
 
 

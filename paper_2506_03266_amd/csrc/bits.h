@@ -1,5 +1,5 @@
 // bits.h -- bit-sliced whole-lattice kernel for the first decoder steps at
-// L = 256 (gfx950).
+// L = 64, 128 and 256 (gfx950).
 //
 // Registers hold emission times (see engine.h), and during the first ten
 // decoder steps every emission time is at most 3 * 10 = 30: a register fits
@@ -25,30 +25,40 @@
 //  * The feedback of eq. (ddfeedback) (a link flips iff one endpoint moves
 //    across it) and the syndrome update are bitwise on the masks.
 //
-// Layout: wave v holds rows 64v .. 64v + 63, lane i columns 4i .. 4i + 3;
+// Layout: wave v holds rows 64v .. 64v + 63, lane i columns CPL i .. CPL i + CPL - 1;
 // word w of a column covers rows 64v + 32w .. + 31 (bit r = row 64v + 32w + r).
 // Vertical neighbours inside a lane are funnel shifts (v_alignbit); across
 // waves the edge rows travel through LDS packed up to 20 to a word, once per
 // sub-step (one barrier).  Horizontal neighbours are in the lane or one
 // wave-wide DPP rotation away (the wrap in x).
 //
-// A sample that still holds anyons after its steps leaves its state in the
-// band path's HBM layout (packed u16 emission times, 16-row syndrome masks),
-// from which the band kernels continue exactly.
+// Smaller tori take fewer waves and columns per lane (L = 64: one wave, one
+// column per lane; L = 128: two waves, two columns per lane).
+//
+// At L = 256 a sample that still holds anyons after its steps leaves its
+// state in the band path's HBM layout (packed u16 emission times, 16-row
+// syndrome masks), from which the band kernels continue exactly.  At L = 64
+// and 128 a decode that ends inside the steps writes its results here; the
+// others are marked (T_dec = -1) and decoded again from their seeds by the
+// whole-lattice kernel, which needs no workspace.
 #pragma once
 
 #include "band.h"
 
 namespace mpd {
 
+// A sample of side L = 64 CPL takes NW = CPL waves of 64 rows, each lane CPL
+// columns: CPL = 1, 2, 4 for L = 64, 128, 256.
 constexpr int BITS_L = 256;
-constexpr int BITS_CPL = 4;          // columns per lane
-constexpr int BITS_NW = 4;           // waves (64 rows each)
 constexpr int BITS_PLANES = 5;       // bit planes per register
 constexpr int BITS_MAX_STEPS = 10;   // emission times <= 30 fit in 5 bits
 
 struct BitsArgs {
   const uint64_t *seeds;
+  int T_max;             // L = 64, 128: the decode's step budget
+  int32_t *T_dec;        // L = 64, 128: outputs of decodes that end inside the steps
+  uint8_t *flags;
+  uint32_t *syn;         // final syndrome bitmaps (may be null)
   uint64_t thr;          // flip threshold floor(p 2^32) when p_arr == nullptr
   const double *p_arr;   // per-sample noise strength or nullptr
   int k;                 // decoder steps at most (<= BITS_MAX_STEPS and <= T_max)
@@ -119,9 +129,15 @@ __device__ __forceinline__ void shift_in_below(uint32_t &m, uint32_t x, uint32_t
   asm("v_cmp_gt_u32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc" : "+v"(m) : "v"(x), "s"(t) : "vcc");
 }
 
+// The value of lane i ^ 1 (DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ uint32_t swap_pair(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+}
+
+template <int CPL>
 struct BitsLane {
-  uint32_t E[4][BITS_PLANES][BITS_CPL][2];  // [register: +x, -x, +y, -y][bit][column][word]
-  uint32_t S[BITS_CPL][2];        // syndrome (anyon = 1)
+  uint32_t E[4][BITS_PLANES][CPL][2];  // [register: +x, -x, +y, -y][bit][column][word]
+  uint32_t S[CPL][2];        // syndrome (anyon = 1)
 };
 
 // Edge rows of other waves, packed one bit per (register, plane, column) in
@@ -144,8 +160,8 @@ struct Carry {
 // Vertical maximum over rows y - 1, y, y + 1 of register d, column c (B
 // planes): r0/r1 for words 0/1.  The row below word 0 and the row above word
 // 1 come from the neighbour waves through `cr`.
-template <int B>
-__device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, Carry &cr, V4 &r0, V4 &r1) {
+template <int B, int CPL>
+__device__ __forceinline__ void bits_vmax(const BitsLane<CPL> &s, int d, int c, Carry &cr, V4 &r0, V4 &r1) {
   V4 x0, x1, dn, up;
 #pragma unroll
   for (int q = 0; q < BITS_PLANES; ++q) {
@@ -173,10 +189,10 @@ __device__ __forceinline__ void bits_vmax(const BitsLane &s, int d, int c, Carry
 // (+x, -x, -y row maxima).  Each word holds its items in the order the
 // receiving wave uses them: +x columns 3 .. 0 and -x columns 0 .. 3 (the
 // order of the vertical maxima), ±y columns inside planes.
-template <int B>
-__device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS, int v, int vdn, int vup,
+template <int B, int CPL>
+__device__ __forceinline__ void bits_substep(BitsLane<CPL> &s, uint32_t ss, uint4 *XS, int v, int vdn, int vup,
                                              int lane) {
-  constexpr int N = B * BITS_CPL;  // items per word
+  constexpr int N = B * CPL;  // items per word
   // anyon sites emit now: their registers read ss
 #pragma unroll
   for (int q = 0; q < B; ++q) {
@@ -184,7 +200,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
 #pragma unroll
     for (int d = 0; d < 4; ++d)
 #pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c)
+      for (int c = 0; c < CPL; ++c)
 #pragma unroll
         for (int w = 0; w < 2; ++w)  // S ? M : E (one v_bitop3; M is uniform)
           s.E[d][q][c][w] = __builtin_amdgcn_bitop3_b32(M, s.E[d][q][c][w], s.S[c][w], 0xE4);
@@ -194,8 +210,8 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   // a word shifted in at bit 0 (top rows) or at bit 31 (bottom rows)
   uint32_t upx = 0u, dpx = 0u, umx = 0u, dmx = 0u, upy = 0u, dmy = 0u;
 #pragma unroll
-  for (int k = 0; k < BITS_CPL; ++k) {
-    const int cp = BITS_CPL - 1 - k, cm = k;
+  for (int k = 0; k < CPL; ++k) {
+    const int cp = CPL - 1 - k, cm = k;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       upx = fshr(upx, s.E[0][q][cp][1], 31);
@@ -214,17 +230,17 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
       V4 left, right, prev;
 #pragma unroll
       for (int q = 0; q < BITS_PLANES; ++q) {
-        left.p[q] = q < B ? from_left<true>(s.E[d][q][BITS_CPL - 1][w]) : 0u;  // lane i - 1, last column
+        left.p[q] = q < B ? from_left<true>(s.E[d][q][CPL - 1][w]) : 0u;  // lane i - 1, last column
         right.p[q] = q < B ? from_right<true>(s.E[d][q][0][w]) : 0u;           // lane i + 1, first column
       }
       prev = left;
 #pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c) {
+      for (int c = 0; c < CPL; ++c) {
         V4 cur, nxt;
 #pragma unroll
         for (int q = 0; q < BITS_PLANES; ++q) {
           cur.p[q] = s.E[d][q][c][w];
-          nxt.p[q] = c + 1 < BITS_CPL ? s.E[d][q][c + 1][w] : right.p[q];
+          nxt.p[q] = c + 1 < CPL ? s.E[d][q][c + 1][w] : right.p[q];
         }
         const V4 h = max3v<B>(prev, cur, nxt);
 #pragma unroll
@@ -236,7 +252,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
 #pragma unroll
     for (int q = 0; q < B; ++q)
 #pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c) {
+      for (int c = 0; c < CPL; ++c) {
         const uint32_t h0 = s.E[d][q][c][0], h1 = s.E[d][q][c][1];
         if (d == 2) {  // +y reads the row below: word 1 now, word 0 after the exchange
           upy = fshr(upy, h1, 31);
@@ -260,7 +276,7 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
 #pragma unroll
   for (int q = 0; q < B; ++q)
 #pragma unroll
-    for (int c = 0; c < BITS_CPL; ++c) {
+    for (int c = 0; c < CPL; ++c) {
       s.E[2][q][c][0] = fshr(s.E[2][q][c][0], cy.take_top(), 31);
       s.E[3][q][c][1] = fshr(cy.take_bot(), s.E[3][q][c][1], 1);
     }
@@ -269,15 +285,15 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   {
     V4 r0, r1, h0, h1;
     constexpr int d = 0;
-    bits_vmax<B>(s, d, BITS_CPL - 1, cpx, r0, r1);
+    bits_vmax<B, CPL>(s, d, CPL - 1, cpx, r0, r1);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       h0.p[q] = from_left<true>(r0.p[q]);
       h1.p[q] = from_left<true>(r1.p[q]);
     }
 #pragma unroll
-    for (int c = BITS_CPL - 1; c >= 1; --c) {
-      bits_vmax<B>(s, d, c - 1, cpx, r0, r1);
+    for (int c = CPL - 1; c >= 1; --c) {
+      bits_vmax<B, CPL>(s, d, c - 1, cpx, r0, r1);
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         s.E[d][q][c][0] = r0.p[q];
@@ -295,15 +311,15 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
   {
     V4 r0, r1, h0, h1;
     constexpr int d = 1;
-    bits_vmax<B>(s, d, 0, cmx, r0, r1);
+    bits_vmax<B, CPL>(s, d, 0, cmx, r0, r1);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       h0.p[q] = from_right<true>(r0.p[q]);
       h1.p[q] = from_right<true>(r1.p[q]);
     }
 #pragma unroll
-    for (int c = 0; c + 1 < BITS_CPL; ++c) {
-      bits_vmax<B>(s, d, c + 1, cmx, r0, r1);
+    for (int c = 0; c + 1 < CPL; ++c) {
+      bits_vmax<B, CPL>(s, d, c + 1, cmx, r0, r1);
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         s.E[d][q][c][0] = r0.p[q];
@@ -313,16 +329,16 @@ __device__ __forceinline__ void bits_substep(BitsLane &s, uint32_t ss, uint4 *XS
     }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      s.E[d][q][BITS_CPL - 1][0] = h0.p[q];
-      s.E[d][q][BITS_CPL - 1][1] = h1.p[q];
+      s.E[d][q][CPL - 1][0] = h0.p[q];
+      s.E[d][q][CPL - 1][1] = h1.p[q];
     }
   }
 }
 
 // Moves of the anyons of one column word from the registers after the last
 // sub-step of a step (see decide_site in band.h), every emission time below 2^B.
-template <int B>
-__device__ __forceinline__ void bits_decide(const BitsLane &s, int c, int w, uint32_t &px, uint32_t &mx,
+template <int B, int CPL>
+__device__ __forceinline__ void bits_decide(const BitsLane<CPL> &s, int c, int w, uint32_t &px, uint32_t &mx,
                                             uint32_t &py, uint32_t &my) {
   uint32_t k[4];
   uint32_t m = s.E[0][B - 1][c][w] | s.E[1][B - 1][c][w] | s.E[2][B - 1][c][w] | s.E[3][B - 1][c][w];
@@ -350,18 +366,18 @@ __device__ __forceinline__ void bits_decide(const BitsLane &s, int c, int w, uin
 // leaving row L - 1: bit 3).  Columns are decided one at a time, so that only
 // one column's moves are live; the y-links across a wave boundary need one
 // bit per column from each neighbour wave (MX: exchange area [wave][64]).
-template <int B>
-__device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int vdn, int vup, int lane,
+template <int B, int CPL>
+__device__ __forceinline__ void bits_feedback(BitsLane<CPL> &s, uint2 *MX, int v, int vdn, int vup, int lane,
                                               uint32_t &wind) {
   uint32_t upw = 0u, dnw = 0u;  // bit c: top-row +y move / bottom-row -y move of column c
   uint32_t ytop = 0u;           // bit c: y-link above the top row flips by this wave's own moves
   uint32_t pxl[2], mx0[2];      // previous column's +x moves; column 0's -x moves
   uint32_t xs[2];               // x-links of the last column
 #pragma unroll
-  for (int c = 0; c < BITS_CPL; ++c) {
+  for (int c = 0; c < CPL; ++c) {
     uint32_t px[2], mx[2], py[2], my[2];
 #pragma unroll
-    for (int w = 0; w < 2; ++w) bits_decide<B>(s, c, w, px[w], mx[w], py[w], my[w]);
+    for (int w = 0; w < 2; ++w) bits_decide<B, CPL>(s, c, w, px[w], mx[w], py[w], my[w]);
     // y-link above row y flips iff row y moves +y or row y + 1 moves -y; the
     // link above the top row also flips if the wave above moves -y there, the
     // link below the bottom row if the wave below moves +y there (after the
@@ -390,7 +406,7 @@ __device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int
 #pragma unroll
   for (int w = 0; w < 2; ++w) {  // the x-link from the last column to lane i + 1's first
     xs[w] = pxl[w] | from_right<true>(mx0[w]);
-    s.S[BITS_CPL - 1][w] ^= xs[w];
+    s.S[CPL - 1][w] ^= xs[w];
     s.S[0][w] ^= from_left<true>(xs[w]);
   }
   MX[v * 64 + lane] = make_uint2(upw, dnw);
@@ -401,23 +417,23 @@ __device__ __forceinline__ void bits_feedback(BitsLane &s, uint2 *MX, int v, int
   // moves -y; the link above the top row iff the top row moves +y (applied
   // above) or row 64v + 64 moves -y
 #pragma unroll
-  for (int c = 0; c < BITS_CPL; ++c) {
+  for (int c = 0; c < CPL; ++c) {
     s.S[c][0] ^= ((pyb | dnw) >> c) & 1u;
     s.S[c][1] ^= (((mya & ~upw) >> c) & 1u) << 31;
   }
   const uint32_t yflip = ytop | mya;
   if (lane == 63) wind ^= ((__popc(xs[0]) + __popc(xs[1])) & 1u) << 2;
-  if (v == BITS_NW - 1) wind ^= (__popc(yflip & full_mask<BITS_CPL>()) & 1u) << 3;
+  if (v == CPL - 1) wind ^= (__popc(yflip & full_mask<CPL>()) & 1u) << 3;  // the top wave
 }
 
 // One decoder step (sub-steps t3 + 1 .. t3 + 3, then the feedback) with
 // every emission time below 2^B.
-template <int B>
-__device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[BITS_NW * 2 * 64], uint2 *MX, int v,
+template <int B, int CPL>
+__device__ __forceinline__ void bits_step(BitsLane<CPL> &s, uint32_t t3, uint4 (*XS)[CPL * 2 * 64], uint2 *MX, int v,
                                        int vdn, int vup, int lane, uint32_t &wind) {
 #pragma unroll 1
-  for (uint32_t j = 1; j <= 3; ++j) bits_substep<B>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
-  bits_feedback<B>(s, MX, v, vdn, vup, lane, wind);
+  for (uint32_t j = 1; j <= 3; ++j) bits_substep<B, CPL>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
+  bits_feedback<B, CPL>(s, MX, v, vdn, vup, lane, wind);
 }
 
 // One workgroup per sample (DRAWN: the syndrome and error windings come from
@@ -425,22 +441,23 @@ __device__ __forceinline__ void bits_step(BitsLane &s, uint32_t t3, uint4 (*XS)[
 // a.k decoder steps, stopping after the first step that leaves no anyon.
 // Writes the per-step anyon bits and the windings for k_finalize, and for a
 // sample that still holds anyons its state in the band layout.
-template <bool DRAWN>
-__global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
-  constexpr int L = BITS_L;
-  __shared__ uint4 XS[2][BITS_NW * 2 * 64];
-  __shared__ uint2 MX[BITS_NW * 64];
+template <bool DRAWN, int CPL>
+__global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
+  constexpr int L = 64 * CPL, NW = CPL;
+  __shared__ uint4 XS[2][NW * 2 * 64];
+  __shared__ uint2 MX[NW * 64];
   __shared__ uint32_t red;
   const int lane = threadIdx.x & 63;
   const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int vdn = v == 0 ? BITS_NW - 1 : v - 1, vup = v == BITS_NW - 1 ? 0 : v + 1;
+  const int vdn = v == 0 ? NW - 1 : v - 1, vup = v == NW - 1 ? 0 : v + 1;
   const int64_t sample = a.order != nullptr ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
   if (a.zero_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_count = 0;
   if (threadIdx.x == 0) red = 0u;
 
-  BitsLane s;
+  BitsLane<CPL> s;
   uint32_t wind = 0u;
-  if (DRAWN) {
+  if constexpr (DRAWN) {
+    static_assert(CPL == 4, "drawn syndromes come from the L = 256 noise kernel");
     // the noise kernel's 16-row masks of column pairs: strips 4v + 2w and
     // 4v + 2w + 1 make word w; pairs 2i and 2i + 1 are this lane's columns
     const uint2 *Sp = a.S_in + (size_t)sample * (L / TILE_H) * (L / 2);
@@ -462,67 +479,88 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
     // noise: one Philox4x32-10 block (key = seed, counter = site index / 2)
     // per site pair, words 0 and 1 the x- and y-link of the even site, words
     // 2 and 3 those of the odd site; a link flips iff its word is below
-    // thr.  Site pairs (4i, 4i + 1) and (4i + 2, 4i + 3) of row y are
-    // blocks y L/2 + 2i and + 1
-    uint32_t ex[BITS_CPL][2], ey[BITS_CPL][2];
+    // thr.
+    uint32_t ex[CPL][2], ey[CPL][2];
 #pragma unroll
-    for (int c = 0; c < BITS_CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = 0u;
+    for (int c = 0; c < CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = 0u;
     // Rows from the top of each word down: a mask shifts left and takes the
     // new row's bit at bit 0 (m = 2 m + [word < thr] through the carry of
     // one v_addc), so row r ends at bit r.  thr = 2^32 (p = 1) flips every
     // link; below that the 32-bit comparison is exact.
     const uint32_t thr32 = thr > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)thr;
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-#pragma unroll 2
+    if constexpr (CPL == 1) {
+      // Lanes 2j and 2j + 1 (columns 2j, 2j + 1) share the blocks of site
+      // pair j: the even lane draws the rows of word 0, the odd lane those
+      // of word 1, each for both columns, and they swap the other column's half.
+      const uint32_t par = (uint32_t)lane & 1u;
+      uint32_t ax = 0u, ay = 0u, bx = 0u, by = 0u;  // columns 2j (a) and 2j + 1 (b), word par
+#pragma unroll 4
       for (int r = 31; r >= 0; --r) {
-        const uint32_t y = (uint32_t)(64 * v + 32 * w + r);
-        const uint32_t blk = y * (L / 2) + 2u * (uint32_t)lane;
-        const Words4 A = philox4x32_10(blk, k0, k1);
-        const Words4 B = philox4x32_10(blk + 1u, k0, k1);
-        shift_in_below(ex[0][w], A.w0, thr32);
-        shift_in_below(ey[0][w], A.w1, thr32);
-        shift_in_below(ex[1][w], A.w2, thr32);
-        shift_in_below(ey[1][w], A.w3, thr32);
-        shift_in_below(ex[2][w], B.w0, thr32);
-        shift_in_below(ey[2][w], B.w1, thr32);
-        shift_in_below(ex[3][w], B.w2, thr32);
-        shift_in_below(ey[3][w], B.w3, thr32);
+        const uint32_t y = 32u * par + (uint32_t)r;
+        const Words4 A = philox4x32_10(y * (L / 2) + ((uint32_t)lane >> 1), k0, k1);
+        shift_in_below(ax, A.w0, thr32);
+        shift_in_below(ay, A.w1, thr32);
+        shift_in_below(bx, A.w2, thr32);
+        shift_in_below(by, A.w3, thr32);
+      }
+      const uint32_t sax = swap_pair(ax), say = swap_pair(ay), sbx = swap_pair(bx), sby = swap_pair(by);
+      ex[0][0] = par ? sbx : ax;
+      ey[0][0] = par ? sby : ay;
+      ex[0][1] = par ? bx : sax;
+      ey[0][1] = par ? by : say;
+    } else {
+      // site pairs (CPL i + 2b, CPL i + 2b + 1), b < CPL / 2, of row y are
+      // blocks y L/2 + (CPL/2) i + b
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+#pragma unroll 2
+        for (int r = 31; r >= 0; --r) {
+          const uint32_t y = (uint32_t)(64 * v + 32 * w + r);
+          const uint32_t blk = y * (L / 2) + (uint32_t)(CPL / 2) * (uint32_t)lane;
+#pragma unroll
+          for (int b = 0; b < CPL / 2; ++b) {
+            const Words4 A = philox4x32_10(blk + (uint32_t)b, k0, k1);
+            shift_in_below(ex[2 * b][w], A.w0, thr32);
+            shift_in_below(ey[2 * b][w], A.w1, thr32);
+            shift_in_below(ex[2 * b + 1][w], A.w2, thr32);
+            shift_in_below(ey[2 * b + 1][w], A.w3, thr32);
+          }
+        }
       }
     }
     if (thr > 0xFFFFFFFFull) {
 #pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = ~0u;
+      for (int c = 0; c < CPL; ++c) ex[c][0] = ex[c][1] = ey[c][0] = ey[c][1] = ~0u;
     }
     uint32_t upw = 0u;
 #pragma unroll
-    for (int c = 0; c < BITS_CPL; ++c) upw |= (ey[c][1] >> 31) << c;
+    for (int c = 0; c < CPL; ++c) upw |= (ey[c][1] >> 31) << c;
     MX[v * 64 + lane] = make_uint2(upw, 0u);
     __syncthreads();
     const uint32_t eyb = MX[vdn * 64 + lane].x;  // y-links above the top row of the wave below
     uint32_t wy = 0u;
 #pragma unroll
-    for (int c = 0; c < BITS_CPL; ++c) {
-      const uint32_t xl0 = c > 0 ? ex[c - 1][0] : from_left<true>(ex[BITS_CPL - 1][0]);
-      const uint32_t xl1 = c > 0 ? ex[c - 1][1] : from_left<true>(ex[BITS_CPL - 1][1]);
+    for (int c = 0; c < CPL; ++c) {
+      const uint32_t xl0 = c > 0 ? ex[c - 1][0] : from_left<true>(ex[CPL - 1][0]);
+      const uint32_t xl1 = c > 0 ? ex[c - 1][1] : from_left<true>(ex[CPL - 1][1]);
       s.S[c][0] = ex[c][0] ^ xl0 ^ ey[c][0] ^ ((ey[c][0] << 1) | ((eyb >> c) & 1u));
       s.S[c][1] = ex[c][1] ^ xl1 ^ ey[c][1] ^ fshr(ey[c][1], ey[c][0], 31);
       wy ^= ey[c][1] >> 31;
     }
-    if (lane == 63) wind ^= (__popc(ex[BITS_CPL - 1][0]) + __popc(ex[BITS_CPL - 1][1])) & 1u;
-    if (v == BITS_NW - 1) wind ^= wy << 1;
+    if (lane == 63) wind ^= (__popc(ex[CPL - 1][0]) + __popc(ex[CPL - 1][1])) & 1u;
+    if (v == NW - 1) wind ^= wy << 1;
   }
 #pragma unroll
   for (int d = 0; d < 4; ++d)
 #pragma unroll
     for (int q = 0; q < BITS_PLANES; ++q)
 #pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c) s.E[d][q][c][0] = s.E[d][q][c][1] = 0u;
+      for (int c = 0; c < CPL; ++c) s.E[d][q][c][0] = s.E[d][q][c][1] = 0u;
 
   auto any_anyon = [&]() {
     uint32_t o = 0u;
 #pragma unroll
-    for (int c = 0; c < BITS_CPL; ++c) o |= s.S[c][0] | s.S[c][1];
+    for (int c = 0; c < CPL; ++c) o |= s.S[c][0] | s.S[c][1];
     return o != 0u;
   };
   bool alive = __syncthreads_or(any_anyon()) != 0;
@@ -537,19 +575,19 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
     if (alive) bits |= 1u << t;
   };
   if (alive && t < a.k) {
-    bits_step<2>(s, 0u, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<2, CPL>(s, 0u, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
   if (alive && t < a.k) {
-    bits_step<3>(s, 3u, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<3, CPL>(s, 3u, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
   while (alive && t < a.k && t < 5) {
-    bits_step<4>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<4, CPL>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
   while (alive && t < a.k) {
-    bits_step<5>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<5, CPL>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
 
@@ -560,43 +598,82 @@ __global__ __launch_bounds__(BITS_NW * 64) void k_bits(BitsArgs a) {
   // across the steps
   const int64_t smp = a.order != nullptr ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[opaque_s(blockIdx.x)])
                                          : (int64_t)blockIdx.x;
-  if (threadIdx.x == 0) {
-    a.alive[smp] = bits;
-    a.wind[smp] = DRAWN ? (a.wind[smp] ^ red) : red;  // the noise kernel left Wx(E), Wy(E)
-  }
-  if (!alive) return;
-  // anyons left: the state in the band layout, emission times as packed u16
-  // (P = e^{+x} | e^{-x} << 16, Q = e^{+y} | e^{-y} << 16) and 16-row syndrome masks
-  constexpr size_t half_row = L / 2;
-  const int ln = lane_here();
-  uint4 *E = a.E + (size_t)smp * L * half_row;
-#pragma unroll
-  for (int w = 0; w < 2; ++w) {
-#pragma unroll 1
-    for (int r = 0; r < 32; ++r) {
-      uint32_t P[BITS_CPL], Q[BITS_CPL];
-      const uint32_t rr = opaque((uint32_t)r);  // no shifted copies of the planes carried across rows
-#pragma unroll
-      for (int c = 0; c < BITS_CPL; ++c) {
-        uint32_t e[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          e[d] = 0u;
-#pragma unroll
-          for (int q = 0; q < BITS_PLANES; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
-        }
-        P[c] = e[0] | (e[1] << 16);
-        Q[c] = e[2] | (e[3] << 16);
+  if constexpr (CPL < 4) {
+    // L = 64, 128: the decode's results when it ended inside these steps (no
+    // anyon left, or T_max reached); else T_dec = -1 and the whole-lattice
+    // kernel decodes the sample again from its seed
+    (void)bits;
+    const bool done = !alive || t >= a.T_max;
+    if (threadIdx.x == 0) {
+      if (done) {
+        const uint32_t W = red;
+        const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
+        const uint32_t timeout = alive ? 1u : 0u;
+        a.T_dec[smp] = t;
+        a.flags[smp] = (uint8_t)((fail | timeout) | (timeout << 1));
+      } else {
+        a.T_dec[smp] = -1;
       }
-      const size_t y = (size_t)(64 * v + 32 * w + r);
-      E[y * half_row + 2 * ln] = make_uint4(P[0], Q[0], P[1], Q[1]);
-      E[y * half_row + 2 * ln + 1] = make_uint4(P[2], Q[2], P[3], Q[3]);
     }
-    const size_t strip = (size_t)smp * (L / TILE_H) + (size_t)(4 * v + 2 * w);
-    a.S[strip * half_row + 2 * ln] = make_uint2(s.S[0][w] & 0xFFFFu, s.S[1][w] & 0xFFFFu);
-    a.S[strip * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
-    a.S[(strip + 1) * half_row + 2 * ln] = make_uint2(s.S[0][w] >> 16, s.S[1][w] >> 16);
-    a.S[(strip + 1) * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] >> 16, s.S[3][w] >> 16);
+    if (!done || a.syn == nullptr) return;
+    // final syndrome, bit y L + x of the sample's row-major bitmap
+    constexpr int NWORD = L * L / 32;
+    uint32_t *out = a.syn + (size_t)smp * NWORD;
+    if (!alive) {
+      for (int i = threadIdx.x; i < NWORD; i += NW * 64) out[i] = 0u;
+      return;
+    }
+    uint32_t *SW = reinterpret_cast<uint32_t *>(&XS[0][0]);  // free after the last step's barriers
+    for (int i = threadIdx.x; i < NWORD; i += NW * 64) SW[i] = 0u;
+    __syncthreads();
+    for (int w = 0; w < 2; ++w)
+      for (int c = 0; c < CPL; ++c)
+        for (uint32_t m = s.S[c][w]; m != 0u; m &= m - 1u) {
+          const uint32_t y = (uint32_t)(64 * v + 32 * w) + (uint32_t)__builtin_ctz(m);
+          const uint32_t i = y * (uint32_t)L + (uint32_t)(CPL * lane + c);
+          atomicOr(&SW[i >> 5], 1u << (i & 31u));
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NWORD; i += NW * 64) out[i] = SW[i];
+  } else {
+    if (threadIdx.x == 0) {
+      a.alive[smp] = bits;
+      a.wind[smp] = DRAWN ? (a.wind[smp] ^ red) : red;  // the noise kernel left Wx(E), Wy(E)
+    }
+    if (!alive) return;
+    // anyons left: the state in the band layout, emission times as packed u16
+    // (P = e^{+x} | e^{-x} << 16, Q = e^{+y} | e^{-y} << 16) and 16-row syndrome masks
+    constexpr size_t half_row = L / 2;
+    const int ln = lane_here();
+    uint4 *E = a.E + (size_t)smp * L * half_row;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll 1
+      for (int r = 0; r < 32; ++r) {
+        uint32_t P[CPL], Q[CPL];
+        const uint32_t rr = opaque((uint32_t)r);  // no shifted copies of the planes carried across rows
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          uint32_t e[4];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            e[d] = 0u;
+#pragma unroll
+            for (int q = 0; q < BITS_PLANES; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
+          }
+          P[c] = e[0] | (e[1] << 16);
+          Q[c] = e[2] | (e[3] << 16);
+        }
+        const size_t y = (size_t)(64 * v + 32 * w + r);
+        E[y * half_row + 2 * ln] = make_uint4(P[0], Q[0], P[1], Q[1]);
+        E[y * half_row + 2 * ln + 1] = make_uint4(P[2], Q[2], P[3], Q[3]);
+      }
+      const size_t strip = (size_t)smp * (L / TILE_H) + (size_t)(4 * v + 2 * w);
+      a.S[strip * half_row + 2 * ln] = make_uint2(s.S[0][w] & 0xFFFFu, s.S[1][w] & 0xFFFFu);
+      a.S[strip * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
+      a.S[(strip + 1) * half_row + 2 * ln] = make_uint2(s.S[0][w] >> 16, s.S[1][w] >> 16);
+      a.S[(strip + 1) * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] >> 16, s.S[3][w] >> 16);
+    }
   }
 }
 

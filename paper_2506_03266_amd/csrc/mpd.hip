@@ -3,7 +3,8 @@
 // Two execution shapes share the device engine of engine.h:
 //  * resident: one workgroup holds a whole L x L sample in LDS/VGPRs and runs
 //    it from noise to termination with no HBM traffic for the state
-//    (L <= 128 with a strip height dividing L);
+//    (L <= 128 with a strip height dividing L; at L = 64 and 128 the
+//    bit-sliced kernel of bits.h runs the first ten steps before it);
 //  * band (L >= 256, multiples of 16): each workgroup holds a region of 128
 //    columns x 256 rows in VGPRs (band.h), of which all but a halo of 4k
 //    columns (and 4k rows rounded up to 16, unless the region spans the
@@ -266,6 +267,7 @@ struct TorusArgs {
   int32_t *T_dec;
   uint8_t *flags;
   uint32_t *syn;         // final syndrome bits (may be null)
+  int resume = 0;        // nonzero: only samples with T_dec[sample] < 0 (left by k_bits)
 };
 
 // One workgroup per sample, the whole L x L torus in registers: NW waves of
@@ -291,6 +293,7 @@ __global__ __launch_bounds__(NW * 64) void k_torus(TorusArgs a) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wdn = w == 0 ? NW - 1 : w - 1, wup = w == NW - 1 ? 0 : w + 1;
   const int64_t sample = blockIdx.x;
+  if (a.resume && a.T_dec[sample] >= 0) return;  // decoded by the bit-sliced kernel
   const uint64_t seed = a.seeds[sample];
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
@@ -1185,6 +1188,8 @@ int launch_torus(int L, const TorusArgs &a, hipStream_t stream) {
   return MPD_OK;
 }
 
+int bits_steps_for(int L);  // bit-sliced steps of the schedule for L (below)
+
 // A seeded plain-rule decode of a small lattice (one workgroup per sample):
 // the whole-lattice band kernel where it applies, else the resident kernel.
 int launch_small(int L, int64_t n, const uint64_t *seeds, uint64_t thr, const double *p_arr, int T_max,
@@ -1199,6 +1204,30 @@ int launch_small(int L, int64_t n, const uint64_t *seeds, uint64_t thr, const do
     t.T_dec = T_dec;
     t.flags = flags;
     t.syn = syn;
+    const int kb = std::min(bits_steps_for(L), T_max);
+    if (bits_steps_for(L) > 0) {
+      // noise and the first kb steps bit-sliced; the whole-lattice kernel
+      // takes the samples that are still decoding after them
+      BitsArgs b = {};
+      b.seeds = seeds;
+      b.thr = thr;
+      b.p_arr = p_arr;
+      b.k = kb;
+      b.T_max = T_max;
+      b.T_dec = T_dec;
+      b.flags = flags;
+      b.syn = syn;
+      {
+        ProfScope ps("k_bits_small", stream);
+        if (L == 64)
+          hipLaunchKernelGGL((k_bits<false, 1>), dim3((unsigned)n), dim3(64), 0, stream, b);
+        else
+          hipLaunchKernelGGL((k_bits<false, 2>), dim3((unsigned)n), dim3(128), 0, stream, b);
+      }
+      HIP_TRY(hipGetLastError());
+      if (T_max <= kb) return MPD_OK;
+      t.resume = 1;
+    }
     return launch_torus(L, t, stream);
   }
   ResidentArgs a = {};
@@ -1277,6 +1306,7 @@ BandSchedule schedule_for(int L) {
   auto it = g_sched_by_L.find(L);
   return it == g_sched_by_L.end() ? g_sched_default : it->second;
 }
+int bits_steps_for(int L) { return schedule_for(L).k_bits; }
 
 // Launch shape of k_band_noise: whole rows of column pairs when they fit in
 // one workgroup, else the widest divisor of L/2 (a multiple of 4, so that
@@ -1679,7 +1709,7 @@ int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, 
                        w.status, w.t_done, w.active[0], &w.count[2]);
     HIP_TRY(hipGetLastError());
   }
-  BitsArgs a;
+  BitsArgs a = {};
   a.order = order;
   a.S_in = drawn ? w.S[0] : nullptr;
   a.seeds = d_seeds;
@@ -1694,9 +1724,9 @@ int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, 
   {
     ProfScope ps("k_bits", stream);
     if (drawn)
-      hipLaunchKernelGGL(k_bits<true>, dim3((unsigned)n), dim3(BITS_NW * 64), 0, stream, a);
+      hipLaunchKernelGGL((k_bits<true, 4>), dim3((unsigned)n), dim3(256), 0, stream, a);
     else
-      hipLaunchKernelGGL(k_bits<false>, dim3((unsigned)n), dim3(BITS_NW * 64), 0, stream, a);
+      hipLaunchKernelGGL((k_bits<false, 4>), dim3((unsigned)n), dim3(256), 0, stream, a);
   }
   HIP_TRY(hipGetLastError());
   (void)L;
