@@ -292,133 +292,137 @@ __global__ __launch_bounds__(NW * 64) void k_torus(TorusArgs a) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wdn = w == 0 ? NW - 1 : w - 1, wup = w == NW - 1 ? 0 : w + 1;
-  const int64_t sample = blockIdx.x;
-  if (a.resume && a.T_dec[sample] >= 0) return;  // decoded by the bit-sliced kernel
-  const uint64_t seed = a.seeds[sample];
-  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
-  const int y0 = w * H;
-  if (threadIdx.x == 0) red = 0u;
-  uint32_t wind = 0u;  // bit0 Wx(E), bit1 Wy(E), bit2 Wx(C), bit3 Wy(C)
-  int t = 0, alive;
-  uint32_t s0 = 0u, s1 = 0u;  // syndrome masks (s1: second column, CPL = 2)
+  // one sample per workgroup, or (resume) a grid of resident workgroups
+  // stepping over the samples that the bit-sliced kernel left
+  for (int64_t sample = blockIdx.x; sample < a.n; sample += gridDim.x) {
+    if (a.resume && a.T_dec[sample] >= 0) continue;  // decoded by the bit-sliced kernel
+    __syncthreads();  // the previous sample's last reads of LDS are done
+    const uint64_t seed = a.seeds[sample];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint64_t thr = a.p_arr ? device_threshold(a.p_arr[sample]) : a.thr;
+    const int y0 = w * H;
+    if (threadIdx.x == 0) red = 0u;
+    uint32_t wind = 0u;  // bit0 Wx(E), bit1 Wy(E), bit2 Wx(C), bit3 Wy(C)
+    int t = 0, alive;
+    uint32_t s0 = 0u, s1 = 0u;  // syndrome masks (s1: second column, CPL = 2)
 
-  if constexpr (CPL == 2) {
-    BandLane<H> b;
+    if constexpr (CPL == 2) {
+      BandLane<H> b;
 #pragma unroll
-    for (int h = 0; h < H; ++h) b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
-    // noise: columns 2 lane, 2 lane + 1 of rows y0 .. y0 + 15 (one generator block per site pair)
-    uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
+      for (int h = 0; h < H; ++h) b.P0[h] = b.Q0[h] = b.P1[h] = b.Q1[h] = 0u;
+      // noise: columns 2 lane, 2 lane + 1 of rows y0 .. y0 + 15 (one generator block per site pair)
+      uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
 #pragma unroll 4
-    for (int h = 0; h < H; ++h) {
-      const Words4 r = philox4x32_10((uint32_t)((y0 + h) * (L / 2) + lane), k0, k1);
-      ex0 |= (uint32_t)((uint64_t)r.w0 < thr) << h;
-      ey0 |= (uint32_t)((uint64_t)r.w1 < thr) << h;
-      ex1 |= (uint32_t)((uint64_t)r.w2 < thr) << h;
-      ey1 |= (uint32_t)((uint64_t)r.w3 < thr) << h;
-    }
-    MB[w * 64 + lane] = make_uint2((ey0 >> (H - 1)) & 1u, (ey1 >> (H - 1)) & 1u);  // top-row y-links
-    __syncthreads();
-    const uint2 eyd = MB[wdn * 64 + lane];  // y-links of the row below the strip
-    const uint32_t exl = from_left<true>(ex1);
-    b.s0 = (ex0 ^ exl ^ ey0 ^ ((ey0 << 1) | eyd.x)) & F;
-    b.s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | eyd.y)) & F;
-    if (lane == 63) wind ^= __popc(ex1) & 1u;                           // x-links leaving column L-1
-    if (w == NW - 1) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;      // y-links leaving row L-1
-    alive = __syncthreads_or((b.s0 | b.s1) != 0u);
-    while (t < a.T_max && alive) {
-      const uint32_t t3 = 3u * (uint32_t)t;
-      const uint32_t rows = wave_rows<H>(b.s0, b.s1);
-      Moves mv = {0u, 0u, 0u, 0u};
-      uint4 *sa = (t & 1) ? BND1 : BND0, *sb = (t & 1) ? BND0 : BND1;
-      if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16), rows);
-      band_substep<H, false, true>(b, sa, w, wdn, wup, lane, rows, 1u, mv);
-      if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), rows);
-      band_substep<H, false, true>(b, sb, w, wdn, wup, lane, rows, 1u, mv);
-      if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), rows);
-      band_substep<H, true, true>(b, sa, w, wdn, wup, lane, rows, 1u, mv);
-      uint32_t xo[2], yo[2];
-      band_feedback<H, true>(b, mv, MB, w, wdn, wup, lane, xo, yo);
-      if (lane == 63) wind ^= (__popc(xo[1]) & 1u) << 2;
-      if (w == NW - 1) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
-      ++t;
+      for (int h = 0; h < H; ++h) {
+        const Words4 r = philox4x32_10((uint32_t)((y0 + h) * (L / 2) + lane), k0, k1);
+        ex0 |= (uint32_t)((uint64_t)r.w0 < thr) << h;
+        ey0 |= (uint32_t)((uint64_t)r.w1 < thr) << h;
+        ex1 |= (uint32_t)((uint64_t)r.w2 < thr) << h;
+        ey1 |= (uint32_t)((uint64_t)r.w3 < thr) << h;
+      }
+      MB[w * 64 + lane] = make_uint2((ey0 >> (H - 1)) & 1u, (ey1 >> (H - 1)) & 1u);  // top-row y-links
+      __syncthreads();
+      const uint2 eyd = MB[wdn * 64 + lane];  // y-links of the row below the strip
+      const uint32_t exl = from_left<true>(ex1);
+      b.s0 = (ex0 ^ exl ^ ey0 ^ ((ey0 << 1) | eyd.x)) & F;
+      b.s1 = (ex1 ^ ex0 ^ ey1 ^ ((ey1 << 1) | eyd.y)) & F;
+      if (lane == 63) wind ^= __popc(ex1) & 1u;                           // x-links leaving column L-1
+      if (w == NW - 1) wind ^= (((ey0 ^ ey1) >> (H - 1)) & 1u) << 1;      // y-links leaving row L-1
       alive = __syncthreads_or((b.s0 | b.s1) != 0u);
-    }
-    s0 = b.s0;
-    s1 = b.s1;
-  } else {
-    uint32_t P[H], Q[H];
+      while (t < a.T_max && alive) {
+        const uint32_t t3 = 3u * (uint32_t)t;
+        const uint32_t rows = wave_rows<H>(b.s0, b.s1);
+        Moves mv = {0u, 0u, 0u, 0u};
+        uint4 *sa = (t & 1) ? BND1 : BND0, *sb = (t & 1) ? BND0 : BND1;
+        if (rows) band_fold<H>(b, (t3 + 1u) | ((t3 + 1u) << 16), rows);
+        band_substep<H, false, true>(b, sa, w, wdn, wup, lane, rows, 1u, mv);
+        if (rows) band_fold<H>(b, (t3 + 2u) | ((t3 + 2u) << 16), rows);
+        band_substep<H, false, true>(b, sb, w, wdn, wup, lane, rows, 1u, mv);
+        if (rows) band_fold<H>(b, (t3 + 3u) | ((t3 + 3u) << 16), rows);
+        band_substep<H, true, true>(b, sa, w, wdn, wup, lane, rows, 1u, mv);
+        uint32_t xo[2], yo[2];
+        band_feedback<H, true>(b, mv, MB, w, wdn, wup, lane, xo, yo);
+        if (lane == 63) wind ^= (__popc(xo[1]) & 1u) << 2;
+        if (w == NW - 1) wind ^= (((yo[0] ^ yo[1]) >> (H - 1)) & 1u) << 3;
+        ++t;
+        alive = __syncthreads_or((b.s0 | b.s1) != 0u);
+      }
+      s0 = b.s0;
+      s1 = b.s1;
+    } else {
+      uint32_t P[H], Q[H];
 #pragma unroll
-    for (int h = 0; h < H; ++h) P[h] = Q[h] = 0u;
-    // noise: column x = lane of rows y0 .. y0 + 15.  The two lanes of a site
-    // pair share generator blocks: for each row pair (h, h + 1) the even lane
-    // draws row h's block and the odd lane row h + 1's, and they swap the
-    // words of the other site (DPP quad_perm [1, 0, 3, 2]).
-    uint32_t ex = 0u, ey = 0u;
-    const uint32_t q = (uint32_t)lane & 1u;
+      for (int h = 0; h < H; ++h) P[h] = Q[h] = 0u;
+      // noise: column x = lane of rows y0 .. y0 + 15.  The two lanes of a site
+      // pair share generator blocks: for each row pair (h, h + 1) the even lane
+      // draws row h's block and the odd lane row h + 1's, and they swap the
+      // words of the other site (DPP quad_perm [1, 0, 3, 2]).
+      uint32_t ex = 0u, ey = 0u;
+      const uint32_t q = (uint32_t)lane & 1u;
 #pragma unroll 2
-    for (int h = 0; h < H; h += 2) {
-      const Words4 r = philox4x32_10((uint32_t)((y0 + h + (int)q) * (L / 2) + (lane >> 1)), k0, k1);
-      const uint32_t ownx = q ? r.w2 : r.w0, owny = q ? r.w3 : r.w1;  // this lane's site in row h + q
-      const uint32_t sendx = q ? r.w0 : r.w2, sendy = q ? r.w1 : r.w3;  // the partner's site in that row
-      const uint32_t gotx = (uint32_t)__builtin_amdgcn_mov_dpp((int)sendx, 0xB1, 0xF, 0xF, false);
-      const uint32_t goty = (uint32_t)__builtin_amdgcn_mov_dpp((int)sendy, 0xB1, 0xF, 0xF, false);
-      const uint32_t x0 = q ? gotx : ownx, y0w = q ? goty : owny;  // row h
-      const uint32_t x1 = q ? ownx : gotx, y1w = q ? owny : goty;  // row h + 1
-      ex |= ((uint32_t)((uint64_t)x0 < thr) << h) | ((uint32_t)((uint64_t)x1 < thr) << (h + 1));
-      ey |= ((uint32_t)((uint64_t)y0w < thr) << h) | ((uint32_t)((uint64_t)y1w < thr) << (h + 1));
-    }
-    MB[w * 64 + lane] = make_uint2((ey >> (H - 1)) & 1u, 0u);
-    __syncthreads();
-    const uint32_t eyd = MB[wdn * 64 + lane].x;
-    s0 = (ex ^ from_left<true>(ex) ^ ey ^ ((ey << 1) | eyd)) & F;
-    if (lane == 63) wind ^= __popc(ex) & 1u;
-    if (w == NW - 1) wind ^= ((ey >> (H - 1)) & 1u) << 1;
-    alive = __syncthreads_or(s0 != 0u);
-    while (t < a.T_max && alive) {
-      const uint32_t t3 = 3u * (uint32_t)t;
-      const uint32_t rows = wave_rows<H>(s0, 0u);
-      Moves mv = {0u, 0u, 0u, 0u};
-      uint2 *sa = (t & 1) ? BND1 : BND0, *sb = (t & 1) ? BND0 : BND1;
-      if (rows) col_fold<H>(P, Q, s0, (t3 + 1u) | ((t3 + 1u) << 16), rows);
-      col_substep<H, false>(P, Q, s0, sa, w, wdn, wup, lane, rows, 1u, mv);
-      if (rows) col_fold<H>(P, Q, s0, (t3 + 2u) | ((t3 + 2u) << 16), rows);
-      col_substep<H, false>(P, Q, s0, sb, w, wdn, wup, lane, rows, 1u, mv);
-      if (rows) col_fold<H>(P, Q, s0, (t3 + 3u) | ((t3 + 3u) << 16), rows);
-      col_substep<H, true>(P, Q, s0, sa, w, wdn, wup, lane, rows, 1u, mv);
-      uint32_t xo, yo;
-      s0 = col_feedback<H>(s0, mv, MB, w, wdn, wup, lane, xo, yo);
-      if (lane == 63) wind ^= (__popc(xo) & 1u) << 2;
-      if (w == NW - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
-      ++t;
+      for (int h = 0; h < H; h += 2) {
+        const Words4 r = philox4x32_10((uint32_t)((y0 + h + (int)q) * (L / 2) + (lane >> 1)), k0, k1);
+        const uint32_t ownx = q ? r.w2 : r.w0, owny = q ? r.w3 : r.w1;  // this lane's site in row h + q
+        const uint32_t sendx = q ? r.w0 : r.w2, sendy = q ? r.w1 : r.w3;  // the partner's site in that row
+        const uint32_t gotx = (uint32_t)__builtin_amdgcn_mov_dpp((int)sendx, 0xB1, 0xF, 0xF, false);
+        const uint32_t goty = (uint32_t)__builtin_amdgcn_mov_dpp((int)sendy, 0xB1, 0xF, 0xF, false);
+        const uint32_t x0 = q ? gotx : ownx, y0w = q ? goty : owny;  // row h
+        const uint32_t x1 = q ? ownx : gotx, y1w = q ? owny : goty;  // row h + 1
+        ex |= ((uint32_t)((uint64_t)x0 < thr) << h) | ((uint32_t)((uint64_t)x1 < thr) << (h + 1));
+        ey |= ((uint32_t)((uint64_t)y0w < thr) << h) | ((uint32_t)((uint64_t)y1w < thr) << (h + 1));
+      }
+      MB[w * 64 + lane] = make_uint2((ey >> (H - 1)) & 1u, 0u);
+      __syncthreads();
+      const uint32_t eyd = MB[wdn * 64 + lane].x;
+      s0 = (ex ^ from_left<true>(ex) ^ ey ^ ((ey << 1) | eyd)) & F;
+      if (lane == 63) wind ^= __popc(ex) & 1u;
+      if (w == NW - 1) wind ^= ((ey >> (H - 1)) & 1u) << 1;
       alive = __syncthreads_or(s0 != 0u);
+      while (t < a.T_max && alive) {
+        const uint32_t t3 = 3u * (uint32_t)t;
+        const uint32_t rows = wave_rows<H>(s0, 0u);
+        Moves mv = {0u, 0u, 0u, 0u};
+        uint2 *sa = (t & 1) ? BND1 : BND0, *sb = (t & 1) ? BND0 : BND1;
+        if (rows) col_fold<H>(P, Q, s0, (t3 + 1u) | ((t3 + 1u) << 16), rows);
+        col_substep<H, false>(P, Q, s0, sa, w, wdn, wup, lane, rows, 1u, mv);
+        if (rows) col_fold<H>(P, Q, s0, (t3 + 2u) | ((t3 + 2u) << 16), rows);
+        col_substep<H, false>(P, Q, s0, sb, w, wdn, wup, lane, rows, 1u, mv);
+        if (rows) col_fold<H>(P, Q, s0, (t3 + 3u) | ((t3 + 3u) << 16), rows);
+        col_substep<H, true>(P, Q, s0, sa, w, wdn, wup, lane, rows, 1u, mv);
+        uint32_t xo, yo;
+        s0 = col_feedback<H>(s0, mv, MB, w, wdn, wup, lane, xo, yo);
+        if (lane == 63) wind ^= (__popc(xo) & 1u) << 2;
+        if (w == NW - 1) wind ^= ((yo >> (H - 1)) & 1u) << 3;
+        ++t;
+        alive = __syncthreads_or(s0 != 0u);
+      }
     }
-  }
 
-  // winding bits of the block, classification, final syndrome
-  if (wind) atomicXor(&red, wind);
-  __syncthreads();
-  const uint32_t W = red;
-  if (a.syn != nullptr) {
-    constexpr int NWORD = L * L / 32;
-    uint32_t *SW = reinterpret_cast<uint32_t *>(smem);  // the sub-step slots are free now
-    for (int i = threadIdx.x; i < NWORD; i += blockDim.x) SW[i] = 0u;
+    // winding bits of the block, classification, final syndrome
+    if (wind) atomicXor(&red, wind);
     __syncthreads();
-    if (s0 | s1)
-      for (int h = 0; h < H; ++h)
-        for (int c = 0; c < CPL; ++c)
-          if ((((c ? s1 : s0) >> h) & 1u)) {
-            const uint32_t i = (uint32_t)((y0 + h) * L + CPL * lane + c);
-            atomicOr(&SW[i >> 5], 1u << (i & 31u));
-          }
-    __syncthreads();
-    for (int i = threadIdx.x; i < NWORD; i += blockDim.x) a.syn[sample * NWORD + i] = SW[i];
-  }
-  if (threadIdx.x == 0) {
-    const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
-    const uint32_t timeout = alive ? 1u : 0u;
-    a.T_dec[sample] = t;
-    a.flags[sample] = (uint8_t)((fail | timeout) | (timeout << 1));
+    const uint32_t W = red;
+    if (a.syn != nullptr) {
+      constexpr int NWORD = L * L / 32;
+      uint32_t *SW = reinterpret_cast<uint32_t *>(smem);  // the sub-step slots are free now
+      for (int i = threadIdx.x; i < NWORD; i += blockDim.x) SW[i] = 0u;
+      __syncthreads();
+      if (s0 | s1)
+        for (int h = 0; h < H; ++h)
+          for (int c = 0; c < CPL; ++c)
+            if ((((c ? s1 : s0) >> h) & 1u)) {
+              const uint32_t i = (uint32_t)((y0 + h) * L + CPL * lane + c);
+              atomicOr(&SW[i >> 5], 1u << (i & 31u));
+            }
+      __syncthreads();
+      for (int i = threadIdx.x; i < NWORD; i += blockDim.x) a.syn[sample * NWORD + i] = SW[i];
+    }
+    if (threadIdx.x == 0) {
+      const uint32_t fail = ((W ^ (W >> 2)) & 3u) != 0u;
+      const uint32_t timeout = alive ? 1u : 0u;
+      a.T_dec[sample] = t;
+      a.flags[sample] = (uint8_t)((fail | timeout) | (timeout << 1));
+    }
   }
 }
 
@@ -1175,14 +1179,30 @@ int launch_resident(const ResidentArgs &a, hipStream_t stream) {
 // rule variants use k_resident.
 bool torus_ok(int L) { return L == 64 || L == 128; }
 
+// Workgroups of k_torus that fit on the device at once (CUs x occupancy).
+int torus_resident_groups(const void *kernel, int threads, size_t lds) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess)
+    return 0;
+  return std::max(cus * per_cu, 0);
+}
+
 int launch_torus(int L, const TorusArgs &a, hipStream_t stream) {
   ProfScope ps("k_torus", stream);
+  // a resumed launch only has the samples the bit-sliced kernel left: one
+  // resident grid steps over the batch instead of a workgroup per sample
   if (L == 64) {
     const size_t lds = (size_t)2 * 4 * 2 * 64 * sizeof(uint2) + (size_t)4 * 64 * sizeof(uint2);
-    hipLaunchKernelGGL((k_torus<1, 4>), dim3((unsigned)a.n), dim3(4 * 64), lds, stream, a);
+    static const int cap64 = torus_resident_groups((const void *)k_torus<1, 4>, 4 * 64, lds);
+    const int64_t g = a.resume && cap64 > 0 ? std::min<int64_t>(a.n, cap64) : a.n;
+    hipLaunchKernelGGL((k_torus<1, 4>), dim3((unsigned)g), dim3(4 * 64), lds, stream, a);
   } else {
     const size_t lds = (size_t)2 * 8 * 2 * 64 * sizeof(uint4) + (size_t)8 * 64 * sizeof(uint2);
-    hipLaunchKernelGGL((k_torus<2, 8>), dim3((unsigned)a.n), dim3(8 * 64), lds, stream, a);
+    static const int cap128 = torus_resident_groups((const void *)k_torus<2, 8>, 8 * 64, lds);
+    const int64_t g = a.resume && cap128 > 0 ? std::min<int64_t>(a.n, cap128) : a.n;
+    hipLaunchKernelGGL((k_torus<2, 8>), dim3((unsigned)g), dim3(8 * 64), lds, stream, a);
   }
   HIP_TRY(hipGetLastError());
   return MPD_OK;
