@@ -427,12 +427,18 @@ __device__ __forceinline__ void bits_feedback(BitsLane<CPL> &s, uint2 *MX, int v
 }
 
 // One decoder step (sub-steps t3 + 1 .. t3 + 3, then the feedback) with
-// every emission time below 2^B.
-template <int B, int CPL>
+// every emission time below 2^B, and below 2^B1 during its first sub-step
+// (sub-step s needs the bit length of s: 1 at s = 1, 3 at s = 7).
+template <int B, int CPL, int B1 = B>
 __device__ __forceinline__ void bits_step(BitsLane<CPL> &s, uint32_t t3, uint4 (*XS)[CPL * 2 * 64], uint2 *MX, int v,
                                        int vdn, int vup, int lane, uint32_t &wind) {
+  uint32_t j = 1;
+  if constexpr (B1 != B) {
+    bits_substep<B1, CPL>(s, t3 + 1u, XS[(t3 + 1u) & 1u], v, vdn, vup, lane);
+    j = 2;
+  }
 #pragma unroll 1
-  for (uint32_t j = 1; j <= 3; ++j) bits_substep<B, CPL>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
+  for (; j <= 3; ++j) bits_substep<B, CPL>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
   bits_feedback<B, CPL>(s, MX, v, vdn, vup, lane, wind);
 }
 
@@ -567,19 +573,24 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
   uint32_t bits = alive ? 1u : 0u;
   int t = 0;
   // step t + 1 ends at sub-step 3 (t + 1): emission times below 4 in the
-  // first step, below 8 in the second, below 16 up to the fifth, below 32
-  // up to the tenth
+  // first step (below 2 in its first sub-step), below 8 in the second (and
+  // the first sub-step of the third), below 16 up to the fifth, below 32 up
+  // to the tenth
   auto after_step = [&]() {
     ++t;
     alive = __syncthreads_or(any_anyon()) != 0;
     if (alive) bits |= 1u << t;
   };
   if (alive && t < a.k) {
-    bits_step<2, CPL>(s, 0u, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<2, CPL, 1>(s, 0u, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
   if (alive && t < a.k) {
     bits_step<3, CPL>(s, 3u, XS, MX, v, vdn, vup, lane, wind);
+    after_step();
+  }
+  if (alive && t < a.k) {
+    bits_step<4, CPL, 3>(s, 6u, XS, MX, v, vdn, vup, lane, wind);
     after_step();
   }
   while (alive && t < a.k && t < 5) {
