@@ -374,29 +374,32 @@ int mpd_get_band_schedule(int L, int *k_first, int *k_next);
 int mpd_set_band_driver(int L, int driver);
 int mpd_get_band_driver(int L, int *driver);
 
-/* First steps of a plain seeded batch at L = 64, 128 or 256 in the
- * bit-sliced kernel.  During the first ten decoder steps every emission time
- * is at most 30, so the registers fit in 5-bit planes and a whole torus fits
+/* First steps of a plain seeded batch in the bit-sliced kernel.  During the
+ * first ten decoder steps every emission time is at most 30, so the
+ * registers fit in 5-bit planes and a whole torus of L = 64, 128 or 256 fits
  * in one workgroup (L/64 waves; no halo, no HBM state); a sample leaves as
  * soon as it has no anyon.  At L = 256 the others continue on the band path
  * from the state the kernel hands over; at L = 64 and 128 the whole-lattice
- * kernel decodes them again from their seeds (no workspace).  k_bits in
- * [0, 10]: the number of such steps (0: the band path's first pass, or the
+ * kernel decodes them again from their seeds (no workspace).  Larger
+ * lattices run min(k_bits, 4) steps in 256 x 256 regions with a halo of 16
+ * (the tiled kernel), then continue on the band path.  k_bits in [0, 10]:
+ * the number of such steps (0: the band path's first pass, or the
  * whole-lattice kernel alone).  Applies to mpd_decode_batch,
- * mpd_decode_batch_static, mpd_decode_mixed and, at L = 256, the one-group
- * learned decode, with the plain rule (Def. "message passing automaton,
- * general dimensions"); results never depend on it.  L = 0 sets the default
- * and every per-L setting (default 10).  Process-wide, guarded by a mutex;
- * MPD_ERR_TMAX outside [0, 10]. */
+ * mpd_decode_batch_static, mpd_decode_mixed and the learned decode, with the
+ * plain rule (Def. "message passing automaton, general dimensions"); results
+ * never depend on it.  L = 0 sets the default and every per-L setting
+ * (default 10).  Process-wide, guarded by a mutex; MPD_ERR_TMAX outside
+ * [0, 10]. */
 int mpd_set_band_bits(int L, int k_bits);
 int mpd_get_band_bits(int L, int *k_bits);
 
 /* Autotuner for the band path: decodes the probe batch (same arguments as
  * mpd_decode_batch, outputs overwritten) once per candidate schedule --
- * driver (host, device) x k_first in [1, 8] x k_next in [1, 8], and at
- * L = 256 also the steps of the bit-sliced first kernel (0, 3, 5, 8, 10;
- * with it on, k_first is not searched, since the band passes start after
- * it) -- timing each with HIP events on `stream`, and keeps the fastest for
+ * driver (host, device) x k_first in [1, 8] x k_next in [1, 8], and also
+ * the steps of the bit-sliced first kernel (0, 3, 5, 8, 10 at L = 256; 0,
+ * 2, 4 of the tiled one above; with it on, k_first is not searched, since
+ * the band passes start after it) -- timing each with HIP events on
+ * `stream`, and keeps the fastest for
  * this L (mpd_get_band_schedule, mpd_get_band_driver and mpd_get_band_bits
  * then return it).  *k_first, *k_next and *best_ms receive the choice.
  * Synchronizes `stream`. */
@@ -434,9 +437,10 @@ int mpd_decode_mixed(int n_classes, const int32_t *h_L, const int64_t *h_count, 
  * (noise and initial syndrome of a band-path batch), "k_band" (one pass of k
  * decoder steps over the bands of L >= 256), "k_bits" (noise and the first
  * steps of an L = 256 batch, bit-sliced), "k_bits_small" (the same at L = 64
- * and 128), "k_torus" (whole decode at L = 64 and 128), "k_resident" (whole
- * decode of other small lattices), "k_cnn_forward" and "k_cnn_backward"
- * (decode-time predictor).  Records from several host threads are kept together. */
+ * and 128), "k_bits_tile" (the tiled first steps above L = 256), "k_torus"
+ * (whole decode at L = 64 and 128), "k_resident" (whole decode of other
+ * small lattices), "k_cnn_forward" and "k_cnn_backward" (decode-time
+ * predictor).  Records from several host threads are kept together. */
 int mpd_profile(int enable);
 
 /* Sum of the recorded durations (ms) and number of launches of `kernel`;
@@ -516,11 +520,12 @@ int mpd_cnn_adam_step(float *d_params, const float *d_grad, float *d_m, float *d
  * mpd_decode_mixed with the one class (L, n).  Outputs as mpd_decode_batch,
  * plus d_pred [n] if not NULL.  With one group and d_pred NULL the network
  * is not evaluated: the call is the plain decode with first-pass depth
- * h_depth[0] (the FIFO fallback; d_params is still checked).  At L = 256
- * with the bit-sliced first kernel on (mpd_set_band_bits), which stops each
- * sample as soon as it has no anyon, the groups set the order in which that
- * kernel takes the samples instead -- the group with the longest predicted
- * decoding time first -- and the depths only have to be valid.  L: a multiple
+ * h_depth[0] (the FIFO fallback; d_params is still checked).  With the
+ * bit-sliced first kernel on (mpd_set_band_bits), which at L = 256 stops
+ * each sample as soon as it has no anyon and above runs the same tiled steps
+ * on every sample, the groups set the order in which that kernel takes the
+ * samples instead -- the group with the longest predicted decoding time
+ * first -- and the depths only have to be valid.  L: a multiple
  * of 16 in [256, 16384], at most 65535 samples.  Workspace:
  * mpd_learned_workspace_bytes(L, n) bytes, 256-byte aligned.  The group
  * sizes stay on the device (each group's first pass is sized there), so

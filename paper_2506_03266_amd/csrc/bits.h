@@ -129,6 +129,15 @@ __device__ __forceinline__ void shift_in_below(uint32_t &m, uint32_t x, uint32_t
   asm("v_cmp_gt_u32 vcc, %2, %1\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc" : "+v"(m) : "v"(x), "s"(t) : "vcc");
 }
 
+// Parity over the wave's lanes of each of the low four bits of x (uniform:
+// the winding bits are kept per wave, not per lane).
+__device__ __forceinline__ uint32_t wave_parity4(uint32_t x) {
+  uint32_t r = 0u;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) r |= ((uint32_t)__popcll(__ballot((x >> b) & 1u)) & 1u) << b;
+  return r;
+}
+
 // The value of lane i ^ 1 (DPP quad permutation 1, 0, 3, 2).
 __device__ __forceinline__ uint32_t swap_pair(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
@@ -189,7 +198,7 @@ __device__ __forceinline__ void bits_vmax(const BitsLane<CPL> &s, int d, int c, 
 // (+x, -x, -y row maxima).  Each word holds its items in the order the
 // receiving wave uses them: +x columns 3 .. 0 and -x columns 0 .. 3 (the
 // order of the vertical maxima), ±y columns inside planes.
-template <int B, int CPL>
+template <int B, int CPL, bool TORUS>
 __device__ __forceinline__ void bits_substep(BitsLane<CPL> &s, uint32_t ss, uint4 *XS, int v, int vdn, int vup,
                                              int lane) {
   constexpr int N = B * CPL;  // items per word
@@ -230,8 +239,8 @@ __device__ __forceinline__ void bits_substep(BitsLane<CPL> &s, uint32_t ss, uint
       V4 left, right, prev;
 #pragma unroll
       for (int q = 0; q < BITS_PLANES; ++q) {
-        left.p[q] = q < B ? from_left<true>(s.E[d][q][CPL - 1][w]) : 0u;  // lane i - 1, last column
-        right.p[q] = q < B ? from_right<true>(s.E[d][q][0][w]) : 0u;           // lane i + 1, first column
+        left.p[q] = q < B ? from_left<TORUS>(s.E[d][q][CPL - 1][w]) : 0u;  // lane i - 1, last column
+        right.p[q] = q < B ? from_right<TORUS>(s.E[d][q][0][w]) : 0u;           // lane i + 1, first column
       }
       prev = left;
 #pragma unroll
@@ -267,8 +276,10 @@ __device__ __forceinline__ void bits_substep(BitsLane<CPL> &s, uint32_t ss, uint
   XS[(v * 2 + 0) * 64 + lane] = make_uint4(upx, umx, upy, 0u);
   XS[(v * 2 + 1) * 64 + lane] = make_uint4(dpx, dmx, dmy, 0u);
   __syncthreads();
-  const uint4 Bw = XS[(vdn * 2 + 0) * 64 + lane];  // top row of the wave below
-  const uint4 Aw = XS[(vup * 2 + 1) * 64 + lane];  // bottom row of the wave above
+  // top row of the wave below, bottom row of the wave above (nothing beyond
+  // the edges of a region that is not the whole torus: its halo absorbs that)
+  const uint4 Bw = (!TORUS && v == 0) ? make_uint4(0u, 0u, 0u, 0u) : XS[(vdn * 2 + 0) * 64 + lane];
+  const uint4 Aw = (!TORUS && v == CPL - 1) ? make_uint4(0u, 0u, 0u, 0u) : XS[(vup * 2 + 1) * 64 + lane];
   Carry cpx = {Bw.x << (32 - N), Aw.x >> (32 - N)};
   Carry cmx = {Bw.y << (32 - N), Aw.y >> (32 - N)};
   Carry cy = {Bw.z << (32 - N), Aw.z >> (32 - N)};
@@ -288,8 +299,8 @@ __device__ __forceinline__ void bits_substep(BitsLane<CPL> &s, uint32_t ss, uint
     bits_vmax<B, CPL>(s, d, CPL - 1, cpx, r0, r1);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      h0.p[q] = from_left<true>(r0.p[q]);
-      h1.p[q] = from_left<true>(r1.p[q]);
+      h0.p[q] = from_left<TORUS>(r0.p[q]);
+      h1.p[q] = from_left<TORUS>(r1.p[q]);
     }
 #pragma unroll
     for (int c = CPL - 1; c >= 1; --c) {
@@ -314,8 +325,8 @@ __device__ __forceinline__ void bits_substep(BitsLane<CPL> &s, uint32_t ss, uint
     bits_vmax<B, CPL>(s, d, 0, cmx, r0, r1);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      h0.p[q] = from_right<true>(r0.p[q]);
-      h1.p[q] = from_right<true>(r1.p[q]);
+      h0.p[q] = from_right<TORUS>(r0.p[q]);
+      h1.p[q] = from_right<TORUS>(r1.p[q]);
     }
 #pragma unroll
     for (int c = 0; c + 1 < CPL; ++c) {
@@ -366,11 +377,24 @@ __device__ __forceinline__ void bits_decide(const BitsLane<CPL> &s, int c, int w
 // leaving row L - 1: bit 3).  Columns are decided one at a time, so that only
 // one column's moves are live; the y-links across a wave boundary need one
 // bit per column from each neighbour wave (MX: exchange area [wave][64]).
-template <int B, int CPL>
+// Where the cuts of the winding parities lie in the workgroup's region: the
+// x-links leaving column L - 1 are those of lane xlane's last column (-1:
+// not in this region), counted on the rows of xrows; the y-links leaving row
+// L - 1 are those above bit yb of word yw of wave yv (yv = -1: not in this
+// region), counted on lanes [ylo, yhi).  On the whole torus: lane 63 on
+// every row, and the top row of the top wave on every lane.
+struct Cut {
+  int xlane;
+  uint32_t xrows[2];
+  int yv, yw, yb, ylo, yhi;
+};
+
+template <int B, int CPL, bool TORUS>
 __device__ __forceinline__ void bits_feedback(BitsLane<CPL> &s, uint2 *MX, int v, int vdn, int vup, int lane,
-                                              uint32_t &wind) {
+                                              uint32_t &wind, const Cut &cut) {
+  // wind: the wave's winding bits (uniform)
   uint32_t upw = 0u, dnw = 0u;  // bit c: top-row +y move / bottom-row -y move of column c
-  uint32_t ytop = 0u;           // bit c: y-link above the top row flips by this wave's own moves
+  uint32_t ycut = 0u;           // parity of the cut's y-links flipped by this wave's own moves
   uint32_t pxl[2], mx0[2];      // previous column's +x moves; column 0's -x moves
   uint32_t xs[2];               // x-links of the last column
 #pragma unroll
@@ -388,7 +412,7 @@ __device__ __forceinline__ void bits_feedback(BitsLane<CPL> &s, uint2 *MX, int v
     s.S[c][1] ^= Y1 ^ fshr(Y1, Y0, 31);
     upw |= (py[1] >> 31) << c;
     dnw |= (my[0] & 1u) << c;
-    ytop |= (Y1 >> 31) << c;
+    ycut ^= ((cut.yw ? Y1 : Y0) >> cut.yb) & 1u;
     if (c == 0) {
       mx0[0] = mx[0];
       mx0[1] = mx[1];
@@ -405,14 +429,14 @@ __device__ __forceinline__ void bits_feedback(BitsLane<CPL> &s, uint2 *MX, int v
   }
 #pragma unroll
   for (int w = 0; w < 2; ++w) {  // the x-link from the last column to lane i + 1's first
-    xs[w] = pxl[w] | from_right<true>(mx0[w]);
+    xs[w] = pxl[w] | from_right<TORUS>(mx0[w]);
     s.S[CPL - 1][w] ^= xs[w];
-    s.S[0][w] ^= from_left<true>(xs[w]);
+    s.S[0][w] ^= from_left<TORUS>(xs[w]);
   }
   MX[v * 64 + lane] = make_uint2(upw, dnw);
   __syncthreads();
-  const uint32_t pyb = MX[vdn * 64 + lane].x;  // wave below: its top row moves +y
-  const uint32_t mya = MX[vup * 64 + lane].y;  // wave above: its bottom row moves -y
+  const uint32_t pyb = (!TORUS && v == 0) ? 0u : MX[vdn * 64 + lane].x;        // wave below: its top row moves +y
+  const uint32_t mya = (!TORUS && v == CPL - 1) ? 0u : MX[vup * 64 + lane].y;  // wave above: its bottom row moves -y
   // the link below the bottom row flips iff row 64v - 1 moves +y or row 64v
   // moves -y; the link above the top row iff the top row moves +y (applied
   // above) or row 64v + 64 moves -y
@@ -421,25 +445,31 @@ __device__ __forceinline__ void bits_feedback(BitsLane<CPL> &s, uint2 *MX, int v
     s.S[c][0] ^= ((pyb | dnw) >> c) & 1u;
     s.S[c][1] ^= (((mya & ~upw) >> c) & 1u) << 31;
   }
-  const uint32_t yflip = ytop | mya;
-  if (lane == 63) wind ^= ((__popc(xs[0]) + __popc(xs[1])) & 1u) << 2;
-  if (v == CPL - 1) wind ^= (__popc(yflip & full_mask<CPL>()) & 1u) << 3;  // the top wave
+  uint32_t xb = 0u, yb = 0u;
+  if (lane == cut.xlane) xb = (uint32_t)(__popc(xs[0] & cut.xrows[0]) + __popc(xs[1] & cut.xrows[1])) & 1u;
+  if (v == cut.yv && lane >= cut.ylo && lane < cut.yhi) {
+    // a link above a wave's top row also flips if the wave above moves -y into it
+    const uint32_t above =
+        (cut.yw == 1 && cut.yb == 31) ? (uint32_t)__popc(mya & ~upw & full_mask<CPL>()) : 0u;
+    yb = (ycut ^ above) & 1u;
+  }
+  wind ^= wave_parity4((xb << 2) | (yb << 3));
 }
 
 // One decoder step (sub-steps t3 + 1 .. t3 + 3, then the feedback) with
 // every emission time below 2^B, and below 2^B1 during its first sub-step
 // (sub-step s needs the bit length of s: 1 at s = 1, 3 at s = 7).
-template <int B, int CPL, int B1 = B>
+template <int B, int CPL, int B1 = B, bool TORUS = true>
 __device__ __forceinline__ void bits_step(BitsLane<CPL> &s, uint32_t t3, uint4 (*XS)[CPL * 2 * 64], uint2 *MX, int v,
-                                       int vdn, int vup, int lane, uint32_t &wind) {
+                                       int vdn, int vup, int lane, uint32_t &wind, const Cut &cut) {
   uint32_t j = 1;
   if constexpr (B1 != B) {
-    bits_substep<B1, CPL>(s, t3 + 1u, XS[(t3 + 1u) & 1u], v, vdn, vup, lane);
+    bits_substep<B1, CPL, TORUS>(s, t3 + 1u, XS[(t3 + 1u) & 1u], v, vdn, vup, lane);
     j = 2;
   }
 #pragma unroll 1
-  for (; j <= 3; ++j) bits_substep<B, CPL>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
-  bits_feedback<B, CPL>(s, MX, v, vdn, vup, lane, wind);
+  for (; j <= 3; ++j) bits_substep<B, CPL, TORUS>(s, t3 + j, XS[(t3 + j) & 1u], v, vdn, vup, lane);
+  bits_feedback<B, CPL, TORUS>(s, MX, v, vdn, vup, lane, wind, cut);
 }
 
 // One workgroup per sample (DRAWN: the syndrome and error windings come from
@@ -553,8 +583,10 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
       s.S[c][1] = ex[c][1] ^ xl1 ^ ey[c][1] ^ fshr(ey[c][1], ey[c][0], 31);
       wy ^= ey[c][1] >> 31;
     }
-    if (lane == 63) wind ^= (__popc(ex[CPL - 1][0]) + __popc(ex[CPL - 1][1])) & 1u;
-    if (v == NW - 1) wind ^= wy << 1;
+    uint32_t wl = 0u;
+    if (lane == 63) wl ^= (__popc(ex[CPL - 1][0]) + __popc(ex[CPL - 1][1])) & 1u;
+    if (v == NW - 1) wl ^= wy << 1;
+    wind = wave_parity4(wl);
   }
 #pragma unroll
   for (int d = 0; d < 4; ++d)
@@ -576,34 +608,35 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
   // first step (below 2 in its first sub-step), below 8 in the second (and
   // the first sub-step of the third), below 16 up to the fifth, below 32 up
   // to the tenth
+  const Cut cut = {63, {~0u, ~0u}, NW - 1, 1, 31, 0, 64};  // the whole torus
   auto after_step = [&]() {
     ++t;
     alive = __syncthreads_or(any_anyon()) != 0;
     if (alive) bits |= 1u << t;
   };
   if (alive && t < a.k) {
-    bits_step<2, CPL, 1>(s, 0u, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<2, CPL, 1>(s, 0u, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
   if (alive && t < a.k) {
-    bits_step<3, CPL>(s, 3u, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<3, CPL>(s, 3u, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
   if (alive && t < a.k) {
-    bits_step<4, CPL, 3>(s, 6u, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<4, CPL, 3>(s, 6u, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
   while (alive && t < a.k && t < 5) {
-    bits_step<4, CPL>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<4, CPL>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
   while (alive && t < a.k) {
-    bits_step<5, CPL>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind);
+    bits_step<5, CPL>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
 
 
-  if (wind) atomicXor(&red, wind);
+  if (wind && lane_here() == 0) atomicXor(&red, wind);
   __syncthreads();
   // the sample index again (a scalar reload) rather than a value kept live
   // across the steps
@@ -684,6 +717,202 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
       a.S[strip * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
       a.S[(strip + 1) * half_row + 2 * ln] = make_uint2(s.S[0][w] >> 16, s.S[1][w] >> 16);
       a.S[(strip + 1) * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] >> 16, s.S[3][w] >> 16);
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Tiled first pass for L > 256: each workgroup runs the same bit-sliced steps
+// on a 256 x 256 region of one sample (four waves, four columns per lane),
+// whose edges read nothing beyond it.  A decoder step moves information by
+// at most 3 + 1 sites (three sub-steps of A^{(D)}, then the feedback), so
+// after k steps the state is exact at least 4k sites inside the region's
+// edges: the region keeps a halo of h = 16 ceil(k / 4) rows and columns
+// before its own part and at least as many after it.  The own parts (whole
+// 16-row strips, the L/16 strips of a side split as evenly as possible over
+// the tiles) cover the lattice once; every region runs all k steps (no
+// early exit: its neighbours' anyons are not visible to it) and writes its
+// own part of the state in the band layout.  Per-step anyon bits are OR'd
+// and the correction windings XOR'd into the sample's words across tiles.
+
+// Own part [o, o + w) of tile i of n along a side of L sites.
+__device__ __forceinline__ void tile_owned(int L, int n, int i, int &o, int &w) {
+  const int strips = L / 16, q = strips / n, r = strips % n;
+  o = 16 * (i * q + (i < r ? i : r));
+  w = 16 * (q + (i < r ? 1 : 0));
+}
+
+constexpr int BITS_TILE_MAX_STEPS = 4;  // halo 16; emission times below 16 (4 planes)
+
+struct BitsTileArgs {
+  int L;
+  int k;                 // decoder steps (<= BITS_TILE_MAX_STEPS and <= T_max)
+  int halo;              // 16 ceil(k / 4)
+  int nt;                // tiles per side (nt x nt per sample)
+  const int32_t *order;  // sample of grid row b: order[b] (nullptr: b)
+  const uint2 *S_in;     // band layout [n][L/16][L/2] syndrome from the noise kernel (windings in wind)
+  uint4 *E;              // band layout [n][L][L/2]: the state after the k steps
+  uint2 *S;              // band layout [n][L/16][L/2]
+  uint32_t *alive;       // per sample (zeroed before): bit j anyons after step j, OR over tiles
+  uint32_t *wind;        // per sample: error windings in, correction windings XOR'd over tiles
+  int *zero_count;       // survivor counter of the following compaction (cleared here)
+};
+
+__global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
+  constexpr int CPL = 4, NW = 4;
+  __shared__ uint4 XS[2][NW * 2 * 64];
+  __shared__ uint2 MX[NW * 64];
+  __shared__ uint32_t red;
+  const int L = a.L, P = L / 2, NS = L / TILE_H, h = a.halo;
+  const int lane = threadIdx.x & 63;
+  const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int vdn = v == 0 ? NW - 1 : v - 1, vup = v == NW - 1 ? 0 : v + 1;
+  const int64_t smp = a.order != nullptr ? (int64_t)a.order[blockIdx.y] : (int64_t)blockIdx.y;
+  int ox, owx, oy, owy;
+  tile_owned(L, a.nt, (int)(blockIdx.x % (unsigned)a.nt), ox, owx);
+  tile_owned(L, a.nt, (int)(blockIdx.x / (unsigned)a.nt), oy, owy);
+  const int X0 = ox >= h ? ox - h : ox - h + L, Y0 = oy >= h ? oy - h : oy - h + L;  // region origin (multiples of 16)
+  if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
+  if (threadIdx.x == 0) red = 0u;
+
+  // own part: rows [h, h + owy) and lanes [h/4, (h + owx)/4) of the region
+  uint32_t own_rows[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const int r0 = 64 * v + 32 * w;
+    const int lo = min(max(h - r0, 0), 32), hi = min(max(h + owy - r0, 0), 32);
+    own_rows[w] = (hi > lo ? (hi - lo == 32 ? ~0u : ((1u << (hi - lo)) - 1u)) : 0u) << (lo & 31);
+  }
+  const int own_lo = h / 4, own_hi = (h + owx) / 4;  // own lanes
+  const uint64_t own_mask = (own_hi == 64 ? ~0ull : ((1ull << own_hi) - 1ull)) & ~((1ull << own_lo) - 1ull);
+
+  // the noise kernel's 16-row masks: strips (Y0 + 64v + 32w)/16 and the next
+  // make word w, column pairs (X0 + 4i)/2 and the next this lane's columns
+  BitsLane<CPL> s;
+  // (indices below twice their range wrap by one subtraction)
+  auto wrap = [](int i, int n) { return i >= n ? i - n : i; };
+  const int p0 = wrap(X0 / 2 + 2 * lane, P), p1 = wrap(p0 + 1, P);
+  {
+    const uint2 *Sp = a.S_in + (size_t)smp * NS * P;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int j0 = wrap((Y0 + 64 * v + 32 * w) / TILE_H, NS), j1 = wrap(j0 + 1, NS);
+      const uint2 a0 = Sp[(size_t)j0 * P + p0], a1 = Sp[(size_t)j0 * P + p1];
+      const uint2 b0 = Sp[(size_t)j1 * P + p0], b1 = Sp[(size_t)j1 * P + p1];
+      s.S[0][w] = (a0.x & 0xFFFFu) | (b0.x << 16);
+      s.S[1][w] = (a0.y & 0xFFFFu) | (b0.y << 16);
+      s.S[2][w] = (a1.x & 0xFFFFu) | (b1.x << 16);
+      s.S[3][w] = (a1.y & 0xFFFFu) | (b1.y << 16);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int q = 0; q < BITS_PLANES; ++q)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) s.E[d][q][c][0] = s.E[d][q][c][1] = 0u;
+
+  auto own_anyon = [&]() {
+    uint32_t o = 0u;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) o |= (s.S[c][0] & own_rows[0]) | (s.S[c][1] & own_rows[1]);
+    return (__ballot(o != 0u) & own_mask) != 0ull;  // uniform in the wave
+  };
+  // the cuts of the winding parities, where this tile owns them
+  Cut cut;
+  cut.xlane = ox + owx == L ? (h + owx) / 4 - 1 : -1;
+  cut.xrows[0] = own_rows[0];
+  cut.xrows[1] = own_rows[1];
+  const int ry = h + owy - 1;  // region row of lattice row L - 1 (if owned)
+  cut.yv = oy + owy == L ? ry / 64 : -1;
+  cut.yw = (ry % 64) / 32;
+  cut.yb = ry % 32;
+  cut.ylo = own_lo;
+  cut.yhi = own_hi;
+
+  uint32_t wind = 0u;
+  // anyons in the whole own part: each wave's flag through LDS (every lane
+  // writes the same value), one barrier
+  __shared__ uint32_t AF[NW];
+  auto group_any = [&]() {
+    AF[v] = own_anyon() ? 1u : 0u;
+    __syncthreads();
+    uint32_t o = 0u;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) o |= AF[i];
+    return __builtin_amdgcn_readfirstlane(o) != 0u;
+  };
+  uint32_t bits = group_any() ? 1u : 0u;
+  int t = 0;
+  auto after_step = [&]() {
+    ++t;
+    if (group_any()) bits |= 1u << t;
+  };
+  if (t < a.k) {
+    bits_step<2, CPL, 1, false>(s, 0u, XS, MX, v, vdn, vup, lane, wind, cut);
+    after_step();
+  }
+  if (t < a.k) {
+    bits_step<3, CPL, 3, false>(s, 3u, XS, MX, v, vdn, vup, lane, wind, cut);
+    after_step();
+  }
+  if (t < a.k) {
+    bits_step<4, CPL, 3, false>(s, 6u, XS, MX, v, vdn, vup, lane, wind, cut);
+    after_step();
+  }
+  if (t < a.k) {
+    bits_step<4, CPL, 4, false>(s, 9u, XS, MX, v, vdn, vup, lane, wind, cut);
+    after_step();
+  }
+
+  if (wind && lane_here() == 0) atomicXor(&red, wind);
+  __syncthreads();
+  const int64_t sm2 = a.order != nullptr ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[opaque_s(blockIdx.y)])
+                                         : (int64_t)blockIdx.y;
+  if (threadIdx.x == 0) {
+    if (red) atomicXor(&a.wind[sm2], red);
+    atomicOr(&a.alive[sm2], bits);
+  }
+  // own part of the state in the band layout
+  const int ln = lane_here();
+  const bool own = ln >= own_lo && ln < own_hi;
+  const int q0 = wrap(X0 / 2 + 2 * ln, P), q1 = wrap(q0 + 1, P);
+  uint4 *E = a.E + (size_t)sm2 * L * P;
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const int r0 = 64 * v + 32 * w;
+#pragma unroll 1
+    for (int r = 0; r < 32; ++r) {
+      if (r0 + r < h || r0 + r >= h + owy) continue;
+      uint32_t Pw[CPL], Qw[CPL];
+      const uint32_t rr = opaque((uint32_t)r);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        uint32_t e[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          e[d] = 0u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
+        }
+        Pw[c] = e[0] | (e[1] << 16);
+        Qw[c] = e[2] | (e[3] << 16);
+      }
+      const size_t y = (size_t)wrap(Y0 + r0 + r, L);
+      if (own) {
+        E[y * P + q0] = make_uint4(Pw[0], Qw[0], Pw[1], Qw[1]);
+        E[y * P + q1] = make_uint4(Pw[2], Qw[2], Pw[3], Qw[3]);
+      }
+    }
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int rs = r0 + 16 * half;  // region row of the strip's first row
+      if (rs < h || rs >= h + owy || !own) continue;
+      const size_t strip = (size_t)sm2 * NS + (size_t)wrap((Y0 + rs) / TILE_H, NS);
+      const int sh = 16 * half;
+      a.S[strip * P + q0] = make_uint2((s.S[0][w] >> sh) & 0xFFFFu, (s.S[1][w] >> sh) & 0xFFFFu);
+      a.S[strip * P + q1] = make_uint2((s.S[2][w] >> sh) & 0xFFFFu, (s.S[3][w] >> sh) & 0xFFFFu);
     }
   }
 }

@@ -1756,6 +1756,52 @@ int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, 
   return MPD_OK;
 }
 
+// The tiled bit-sliced first pass (L > 256) of k steps: the halo they need,
+// and tiles per side so that every own part (at most 256 - 2 halo sites)
+// is made of whole 16-row strips.
+struct TilePlan {
+  int k, halo, nt;
+};
+TilePlan tile_plan(int L, int k) {
+  TilePlan t;
+  t.k = k;
+  t.halo = TILE_H * ((k + 3) / 4);
+  const int own_strips = (256 - 2 * t.halo) / TILE_H;
+  t.nt = (L / TILE_H + own_strips - 1) / own_strips;
+  return t;
+}
+
+// Noise already drawn into buffer 0 (band_start): the first k steps of every
+// sample in the tiled bit-sliced kernel, leaving the state in buffer 1 as a
+// band first pass would, then T_dec of the finished samples and the list of
+// the others in active[1].  With `order` the grid rows take the samples in
+// that order.
+int bits_tile_start(int L, int64_t n, int T_max, int k, const BandWorkspace &w, int32_t *d_T_dec,
+                    hipStream_t stream, const int32_t *order = nullptr) {
+  const TilePlan tp = tile_plan(L, k);
+  BitsTileArgs a;
+  a.L = L;
+  a.k = k;
+  a.halo = tp.halo;
+  a.nt = tp.nt;
+  a.order = order;
+  a.S_in = w.S[0];
+  a.E = w.E[1];
+  a.S = w.S[1];
+  a.alive = w.alive;
+  a.wind = w.wind;
+  a.zero_count = &w.count[1];
+  {
+    ProfScope ps("k_bits_tile", stream);
+    hipLaunchKernelGGL(k_bits_tile, dim3((unsigned)(tp.nt * tp.nt), (unsigned)n), dim3(256), 0, stream, a);
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, k, T_max, 1, w.active[0],
+                     (int)n, (const int *)nullptr, w.t_done, w.alive, d_T_dec, w.status, w.active[1], &w.count[1]);
+  HIP_TRY(hipGetLastError());
+  return MPD_OK;
+}
+
 // Noise (or explicit errors) and first-pass setup of a plain (single-group) band batch.
 int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, int64_t n, int T_max,
                int32_t *d_T_dec, uint8_t *d_flags, uint32_t *d_syn, void *ws, hipStream_t stream,
@@ -1775,6 +1821,14 @@ int band_setup(BandRun &r, int L, uint64_t thr, const double *d_p, const uint64_
     r.fp.nb = 0;
     r.first_bound = n;
     return bits_start(L, thr, d_p, d_seeds, n, T_max, std::min(kb, T_max), r.w, d_T_dec, stream);
+  }
+  if (L > BITS_L && kb > 0 && T_max > 0 && d_links == nullptr && r.rule.mode() == BAND_PLAIN) {
+    // noise, then the first min(k_bits, T_max) steps in the tiled bit-sliced kernel
+    const int rc = band_start(L, thr, d_p, d_seeds, n, r.w, nullptr, stream);
+    if (rc != MPD_OK) return rc;
+    r.fp.nb = 0;
+    r.first_bound = n;
+    return bits_tile_start(L, n, T_max, std::min(std::min(kb, T_max), BITS_TILE_MAX_STEPS), r.w, d_T_dec, stream);
   }
   r.fp.nb = 1;
   r.fp.list[0] = r.w.active[0];
@@ -2188,10 +2242,12 @@ int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_see
   HIP_TRY(hipGetLastError());
   if (d_pred != nullptr) HIP_TRY(hipMemcpyAsync(d_pred, l.pred, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
   const int kb = schedule_for(L).k_bits;
-  if (L == BITS_L && kb > 0) {
+  if (kb > 0 && (L == BITS_L || T_max > 0)) {
     // the bit-sliced kernel stops each sample when it has no anyon, so the
     // groups set the order in which it takes them (longest predicted first),
-    // not a depth; it reads the syndrome the noise kernel drew
+    // not a depth; it reads the syndrome the noise kernel drew.  (The tiled
+    // kernel for L > 256 runs the same number of steps on every sample: the
+    // order only sets which samples its grid takes first.)
     hipLaunchKernelGGL(k_order, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, l.lists, l.bin_count, n_bins,
                        n, l.order);
     HIP_TRY(hipGetLastError());
@@ -2206,7 +2262,11 @@ int mpd_decode_learned(int L, double p, const double *d_p, const uint64_t *d_see
     r.stream = st;
     r.fp.nb = 0;
     r.first_bound = n;
-    rc = bits_start(L, 0, nullptr, d_seeds, n, T_max, std::min(kb, T_max), r.w, d_T_dec, st, l.order, true);
+    if (L == BITS_L)
+      rc = bits_start(L, 0, nullptr, d_seeds, n, T_max, std::min(kb, T_max), r.w, d_T_dec, st, l.order, true);
+    else
+      rc = bits_tile_start(L, n, T_max, std::min(std::min(kb, T_max), BITS_TILE_MAX_STEPS), r.w, d_T_dec, st,
+                           l.order);
     if (rc != MPD_OK) return rc;
     return band_passes(&r, 1);
   }
@@ -2361,14 +2421,15 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
   float best = 1e30f;
   BandSchedule pick = saved;
   int rc = MPD_OK;
-  // candidates: driver x (steps of the bit-sliced first kernel where it
-  // applies: 0, 3, 5, 8, 10) x first-pass depth 1..8 (only without the
-  // bit-sliced kernel: with it the band passes start later) x later depth 1..8
+  // candidates: driver x (steps of the bit-sliced first kernel: 0, 3, 5, 8,
+  // 10 at L = 256; of the tiled one, 0, 2, 4, above) x first-pass depth 1..8
+  // (only without a bit-sliced kernel: with it the band passes start later)
+  // x later depth 1..8
   std::vector<BandSchedule> cand;
-  const bool bits_here = L == BITS_L;
+  const bool bits_here = L == BITS_L, tiles_here = L > BITS_L;
   for (int drv = MPD_BAND_DRIVER_HOST; drv <= MPD_BAND_DRIVER_DEVICE; ++drv)
-    for (int kb : {0, 3, 5, 8, 10}) {
-      if (!bits_here && kb != 0) continue;
+    for (int kb : {0, 2, 3, 4, 5, 8, 10}) {
+      if (bits_here ? (kb == 2 || kb == 4) : tiles_here ? (kb != 0 && kb != 2 && kb != 4) : kb != 0) continue;
       for (int kf = 1; kf <= 8; ++kf) {
         if (kb > 0 && kf != saved.k_first) continue;
         for (int kn = 1; kn <= 8; ++kn) {
@@ -2376,7 +2437,7 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
           c.k_first = kf;
           c.k_next = kn;
           c.driver = drv;
-          c.k_bits = bits_here ? kb : saved.k_bits;
+          c.k_bits = (bits_here || tiles_here) ? kb : saved.k_bits;
           cand.push_back(c);
         }
       }

@@ -141,10 +141,10 @@ def predict(counts, params, chunk: int = 16384):
 
 
 def ordering_applies(L: int) -> bool:
-    """At L = 256 the bit-sliced first kernel stops every sample on its own,
-    so groups order the samples (longest predicted first) instead of giving
-    them first-pass depths."""
-    return L == 256 and b.get_band_bits(L) > 0
+    """Where a bit-sliced first kernel runs (every band-path size: the whole
+    lattice at L = 256, tiles above), the first pass has no depth to choose,
+    so groups order the samples (longest predicted first) instead."""
+    return L >= 256 and b.get_band_bits(L) > 0
 
 
 def candidate_policies(pred: np.ndarray, k_first: int, wide: bool = False, order_only: bool = False):
