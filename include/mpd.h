@@ -381,8 +381,8 @@ int mpd_get_band_driver(int L, int *driver);
  * soon as it has no anyon.  At L = 256 the others continue on the band path
  * from the state the kernel hands over; at L = 64 and 128 the whole-lattice
  * kernel decodes them again from their seeds (no workspace).  Larger
- * lattices run min(k_bits, 4) steps in 256 x 256 regions with a halo of 16
- * (the tiled kernel), then continue on the band path.  k_bits in [0, 10]:
+ * lattices run k = min(k_bits, 6) steps in 256 x 256 regions with a halo of
+ * 4k (the tiled kernel), then continue on the band path.  k_bits in [0, 10]:
  * the number of such steps (0: the band path's first pass, or the
  * whole-lattice kernel alone).  Applies to mpd_decode_batch,
  * mpd_decode_batch_static, mpd_decode_mixed and the learned decode, with the
@@ -397,7 +397,7 @@ int mpd_get_band_bits(int L, int *k_bits);
  * mpd_decode_batch, outputs overwritten) once per candidate schedule --
  * driver (host, device) x k_first in [1, 8] x k_next in [1, 8], and also
  * the steps of the bit-sliced first kernel (0, 3, 5, 8, 10 at L = 256; 0,
- * 2, 4 of the tiled one above; with it on, k_first is not searched, since
+ * 4, 5, 6 of the tiled one above; with it on, k_first is not searched, since
  * the band passes start after it) -- timing each with HIP events on
  * `stream`, and keeps the fastest for
  * this L (mpd_get_band_schedule, mpd_get_band_driver and mpd_get_band_bits

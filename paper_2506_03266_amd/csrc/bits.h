@@ -728,32 +728,34 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
 // whose edges read nothing beyond it.  A decoder step moves information by
 // at most 3 + 1 sites (three sub-steps of A^{(D)}, then the feedback), so
 // after k steps the state is exact at least 4k sites inside the region's
-// edges: the region keeps a halo of h = 16 ceil(k / 4) rows and columns
-// before its own part and at least as many after it.  The own parts (whole
-// 16-row strips, the L/16 strips of a side split as evenly as possible over
-// the tiles) cover the lattice once; every region runs all k steps (no
-// early exit: its neighbours' anyons are not visible to it) and writes its
-// own part of the state in the band layout.  Per-step anyon bits are OR'd
-// and the correction windings XOR'd into the sample's words across tiles.
+// edges: the region keeps a halo of h = 4k rows and columns before its own
+// part and at least as many after it.  The own parts (the L/4 groups of four
+// rows or columns of a side split as evenly as possible over the tiles)
+// cover the lattice once; every region runs all k steps (no early exit: its
+// neighbours' anyons are not visible to it) and writes its own part of the
+// state in the band layout -- the emission times row by row, the syndrome
+// OR'd into 16-row masks that were cleared before (an own part need not
+// start on a mask boundary).  Per-step anyon bits are OR'd and the
+// correction windings XOR'd into the sample's words across tiles.
 
 // Own part [o, o + w) of tile i of n along a side of L sites.
 __device__ __forceinline__ void tile_owned(int L, int n, int i, int &o, int &w) {
-  const int strips = L / 16, q = strips / n, r = strips % n;
-  o = 16 * (i * q + (i < r ? i : r));
-  w = 16 * (q + (i < r ? 1 : 0));
+  const int quads = L / 4, q = quads / n, r = quads % n;
+  o = 4 * (i * q + (i < r ? i : r));
+  w = 4 * (q + (i < r ? 1 : 0));
 }
 
-constexpr int BITS_TILE_MAX_STEPS = 4;  // halo 16; emission times below 16 (4 planes)
+constexpr int BITS_TILE_MAX_STEPS = 6;  // halo 24; emission times up to 18 (5 planes)
 
 struct BitsTileArgs {
   int L;
   int k;                 // decoder steps (<= BITS_TILE_MAX_STEPS and <= T_max)
-  int halo;              // 16 ceil(k / 4)
+  int halo;              // 4k
   int nt;                // tiles per side (nt x nt per sample)
   const int32_t *order;  // sample of grid row b: order[b] (nullptr: b)
   const uint2 *S_in;     // band layout [n][L/16][L/2] syndrome from the noise kernel (windings in wind)
   uint4 *E;              // band layout [n][L][L/2]: the state after the k steps
-  uint2 *S;              // band layout [n][L/16][L/2]
+  uint2 *S;              // band layout [n][L/16][L/2], cleared before
   uint32_t *alive;       // per sample (zeroed before): bit j anyons after step j, OR over tiles
   uint32_t *wind;        // per sample: error windings in, correction windings XOR'd over tiles
   int *zero_count;       // survivor counter of the following compaction (cleared here)
@@ -764,6 +766,7 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
   __shared__ uint4 XS[2][NW * 2 * 64];
   __shared__ uint2 MX[NW * 64];
   __shared__ uint32_t red;
+  __shared__ uint32_t AF[NW];
   const int L = a.L, P = L / 2, NS = L / TILE_H, h = a.halo;
   const int lane = threadIdx.x & 63;
   const int v = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -772,7 +775,9 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
   int ox, owx, oy, owy;
   tile_owned(L, a.nt, (int)(blockIdx.x % (unsigned)a.nt), ox, owx);
   tile_owned(L, a.nt, (int)(blockIdx.x / (unsigned)a.nt), oy, owy);
-  const int X0 = ox >= h ? ox - h : ox - h + L, Y0 = oy >= h ? oy - h : oy - h + L;  // region origin (multiples of 16)
+  // (indices below twice their range wrap by one subtraction)
+  auto wrap = [](int i, int n) { return i >= n ? i - n : i; };
+  const int X0 = wrap(ox - h + L, L), Y0 = wrap(oy - h + L, L);  // region origin (multiples of 4)
   if (a.zero_count != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.zero_count = 0;
   if (threadIdx.x == 0) red = 0u;
 
@@ -787,23 +792,29 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
   const int own_lo = h / 4, own_hi = (h + owx) / 4;  // own lanes
   const uint64_t own_mask = (own_hi == 64 ? ~0ull : ((1ull << own_hi) - 1ull)) & ~((1ull << own_lo) - 1ull);
 
-  // the noise kernel's 16-row masks: strips (Y0 + 64v + 32w)/16 and the next
-  // make word w, column pairs (X0 + 4i)/2 and the next this lane's columns
+  // the noise kernel's 16-row masks: word w starts at lattice row
+  // Y0 + 64v + 32w, `off` rows into a mask, and spans that mask and the next
+  // two; column pairs (X0 + 4i)/2 and the next are this lane's columns
   BitsLane<CPL> s;
-  // (indices below twice their range wrap by one subtraction)
-  auto wrap = [](int i, int n) { return i >= n ? i - n : i; };
   const int p0 = wrap(X0 / 2 + 2 * lane, P), p1 = wrap(p0 + 1, P);
   {
     const uint2 *Sp = a.S_in + (size_t)smp * NS * P;
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-      const int j0 = wrap((Y0 + 64 * v + 32 * w) / TILE_H, NS), j1 = wrap(j0 + 1, NS);
-      const uint2 a0 = Sp[(size_t)j0 * P + p0], a1 = Sp[(size_t)j0 * P + p1];
-      const uint2 b0 = Sp[(size_t)j1 * P + p0], b1 = Sp[(size_t)j1 * P + p1];
-      s.S[0][w] = (a0.x & 0xFFFFu) | (b0.x << 16);
-      s.S[1][w] = (a0.y & 0xFFFFu) | (b0.y << 16);
-      s.S[2][w] = (a1.x & 0xFFFFu) | (b1.x << 16);
-      s.S[3][w] = (a1.y & 0xFFFFu) | (b1.y << 16);
+      const int R = wrap(Y0 + 64 * v + 32 * w, L), off = R % TILE_H;
+      const int j0 = R / TILE_H, j1 = wrap(j0 + 1, NS), j2 = wrap(j0 + 2, NS);
+      uint64_t m[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int j = i == 0 ? j0 : (i == 1 ? j1 : j2);
+        const uint2 u0 = Sp[(size_t)j * P + p0], u1 = Sp[(size_t)j * P + p1];
+        m[0] |= (uint64_t)(u0.x & 0xFFFFu) << (16 * i);
+        m[1] |= (uint64_t)(u0.y & 0xFFFFu) << (16 * i);
+        m[2] |= (uint64_t)(u1.x & 0xFFFFu) << (16 * i);
+        m[3] |= (uint64_t)(u1.y & 0xFFFFu) << (16 * i);
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) s.S[c][w] = (uint32_t)(m[c] >> off);
     }
   }
 #pragma unroll
@@ -819,6 +830,16 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
     for (int c = 0; c < CPL; ++c) o |= (s.S[c][0] & own_rows[0]) | (s.S[c][1] & own_rows[1]);
     return (__ballot(o != 0u) & own_mask) != 0ull;  // uniform in the wave
   };
+  // anyons in the whole own part: each wave's flag through LDS (every lane
+  // writes the same value), one barrier
+  auto group_any = [&]() {
+    AF[v] = own_anyon() ? 1u : 0u;
+    __syncthreads();
+    uint32_t o = 0u;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) o |= AF[i];
+    return __builtin_amdgcn_readfirstlane(o) != 0u;
+  };
   // the cuts of the winding parities, where this tile owns them
   Cut cut;
   cut.xlane = ox + owx == L ? (h + owx) / 4 - 1 : -1;
@@ -832,17 +853,6 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
   cut.yhi = own_hi;
 
   uint32_t wind = 0u;
-  // anyons in the whole own part: each wave's flag through LDS (every lane
-  // writes the same value), one barrier
-  __shared__ uint32_t AF[NW];
-  auto group_any = [&]() {
-    AF[v] = own_anyon() ? 1u : 0u;
-    __syncthreads();
-    uint32_t o = 0u;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) o |= AF[i];
-    return __builtin_amdgcn_readfirstlane(o) != 0u;
-  };
   uint32_t bits = group_any() ? 1u : 0u;
   int t = 0;
   auto after_step = [&]() {
@@ -861,8 +871,12 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
     bits_step<4, CPL, 3, false>(s, 6u, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
+  while (t < a.k && t < 5) {
+    bits_step<4, CPL, 4, false>(s, 3u * (uint32_t)t, XS, MX, v, vdn, vup, lane, wind, cut);
+    after_step();
+  }
   if (t < a.k) {
-    bits_step<4, CPL, 4, false>(s, 9u, XS, MX, v, vdn, vup, lane, wind, cut);
+    bits_step<5, CPL, 5, false>(s, 15u, XS, MX, v, vdn, vup, lane, wind, cut);
     after_step();
   }
 
@@ -894,7 +908,7 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
         for (int d = 0; d < 4; ++d) {
           e[d] = 0u;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
+          for (int q = 0; q < BITS_PLANES; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
         }
         Pw[c] = e[0] | (e[1] << 16);
         Qw[c] = e[2] | (e[3] << 16);
@@ -905,14 +919,22 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
         E[y * P + q1] = make_uint4(Pw[2], Qw[2], Pw[3], Qw[3]);
       }
     }
+    // syndrome: the word's own rows, shifted to their place in the masks
+    // (anyons only: the masks were cleared)
+    const int R = wrap(Y0 + r0, L), off = R % TILE_H, j0 = R / TILE_H;
+    uint2 *Sd = a.S + (size_t)sm2 * NS * P;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int rs = r0 + 16 * half;  // region row of the strip's first row
-      if (rs < h || rs >= h + owy || !own) continue;
-      const size_t strip = (size_t)sm2 * NS + (size_t)wrap((Y0 + rs) / TILE_H, NS);
-      const int sh = 16 * half;
-      a.S[strip * P + q0] = make_uint2((s.S[0][w] >> sh) & 0xFFFFu, (s.S[1][w] >> sh) & 0xFFFFu);
-      a.S[strip * P + q1] = make_uint2((s.S[2][w] >> sh) & 0xFFFFu, (s.S[3][w] >> sh) & 0xFFFFu);
+    for (int c = 0; c < CPL; ++c) {
+      const uint64_t m = own ? (uint64_t)(s.S[c][w] & own_rows[w]) << off : 0ull;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const uint32_t part = (uint32_t)(m >> (16 * i)) & 0xFFFFu;
+        if (part != 0u) {
+          const int j = wrap(j0 + i, NS);
+          uint32_t *dst = reinterpret_cast<uint32_t *>(&Sd[(size_t)j * P + (c < 2 ? q0 : q1)]) + (c & 1);
+          atomicOr(dst, part);
+        }
+      }
     }
   }
 }

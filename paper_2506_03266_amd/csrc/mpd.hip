@@ -1756,19 +1756,24 @@ int bits_start(int L, uint64_t thr, const double *d_p, const uint64_t *d_seeds, 
   return MPD_OK;
 }
 
-// The tiled bit-sliced first pass (L > 256) of k steps: the halo they need,
-// and tiles per side so that every own part (at most 256 - 2 halo sites)
-// is made of whole 16-row strips.
+// The tiled bit-sliced first pass (L > 256) of k steps: the halo they need
+// (4k), and tiles per side so that every own part (groups of four rows or
+// columns) has at most 256 - 8k sites.
 struct TilePlan {
   int k, halo, nt;
 };
 TilePlan tile_plan(int L, int k) {
   TilePlan t;
   t.k = k;
-  t.halo = TILE_H * ((k + 3) / 4);
-  const int own_strips = (256 - 2 * t.halo) / TILE_H;
-  t.nt = (L / TILE_H + own_strips - 1) / own_strips;
+  t.halo = 4 * k;
+  const int own_quads = (256 - 2 * t.halo) / 4;
+  t.nt = (L / 4 + own_quads - 1) / own_quads;
   return t;
+}
+
+__global__ void k_zero_u2(uint2 *p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint2(0u, 0u);
 }
 
 // Noise already drawn into buffer 0 (band_start): the first k steps of every
@@ -1791,6 +1796,11 @@ int bits_tile_start(int L, int64_t n, int T_max, int k, const BandWorkspace &w, 
   a.alive = w.alive;
   a.wind = w.wind;
   a.zero_count = &w.count[1];
+  // the tiles OR their own rows into the syndrome masks
+  const int64_t words = n * (int64_t)(L / TILE_H) * (L / 2);
+  hipLaunchKernelGGL(k_zero_u2, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 8192)), dim3(256), 0, stream,
+                     w.S[1], words);
+  HIP_TRY(hipGetLastError());
   {
     ProfScope ps("k_bits_tile", stream);
     hipLaunchKernelGGL(k_bits_tile, dim3((unsigned)(tp.nt * tp.nt), (unsigned)n), dim3(256), 0, stream, a);
@@ -2422,14 +2432,14 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
   BandSchedule pick = saved;
   int rc = MPD_OK;
   // candidates: driver x (steps of the bit-sliced first kernel: 0, 3, 5, 8,
-  // 10 at L = 256; of the tiled one, 0, 2, 4, above) x first-pass depth 1..8
+  // 10 at L = 256; of the tiled one, 0, 4, 5, 6, above) x first-pass depth 1..8
   // (only without a bit-sliced kernel: with it the band passes start later)
   // x later depth 1..8
   std::vector<BandSchedule> cand;
   const bool bits_here = L == BITS_L, tiles_here = L > BITS_L;
   for (int drv = MPD_BAND_DRIVER_HOST; drv <= MPD_BAND_DRIVER_DEVICE; ++drv)
-    for (int kb : {0, 2, 3, 4, 5, 8, 10}) {
-      if (bits_here ? (kb == 2 || kb == 4) : tiles_here ? (kb != 0 && kb != 2 && kb != 4) : kb != 0) continue;
+    for (int kb : {0, 3, 4, 5, 6, 8, 10}) {
+      if (bits_here ? (kb == 4 || kb == 6) : tiles_here ? (kb == 3 || kb > 6) : kb != 0) continue;
       for (int kf = 1; kf <= 8; ++kf) {
         if (kb > 0 && kf != saved.k_first) continue;
         for (int kn = 1; kn <= 8; ++kn) {

@@ -1,5 +1,5 @@
 """The tiled bit-sliced first pass for L > 256 (256 x 256 regions with a
-halo of 16, up to four decoder steps, then the band path), against the CPU
+halo of 4k for k <= 6 decoder steps, then the band path), against the CPU
 oracle bit for bit (T_dec, flags and final syndrome): every number of tiled
 steps, lattice sizes whose strips split unevenly over the tiles, budgets that
 end inside the tiled steps, noise strengths from none to every link (high p
@@ -44,10 +44,10 @@ def with_bits(gpu, L, k, fn):
 
 
 @pytest.mark.parametrize("L", [272, 512])
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 10])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 10])
 @pytest.mark.parametrize("p", [0.01, 0.05, 0.09])
 def test_steps_against_oracle(gpu, orc, L, k, p):
-    """k = 10 runs the tiled kernel's four steps; p = 0.09 (above the
+    """k = 10 runs the tiled kernel's six steps; p = 0.09 (above the
     threshold) gives logical failures whose corrections cross the cuts."""
     n, T_max = 8, (1024 if p < 0.09 else 128)
     s = seeds(81, L * 100 + int(p * 1000) * 8 + k, n)
@@ -58,7 +58,8 @@ def test_steps_against_oracle(gpu, orc, L, k, p):
 
 @pytest.mark.parametrize("L", [288, 1024])
 def test_other_sizes_against_oracle(gpu, orc, L):
-    """288 = 18 strips (tiles of 9 strips each); 1024 = 64 strips over 5 tiles."""
+    """288 = 72 groups of four rows (two tiles of 36 at six steps); 1024 over
+    five tiles of 204 or 208 rows, whose edges fall inside 16-row masks."""
     n, p, T_max = 4, 0.03, 2048
     s = seeds(82, L, n)
     ref = orc.decode_seeds(L, p, s, T_max, threads=16)
@@ -66,7 +67,7 @@ def test_other_sizes_against_oracle(gpu, orc, L):
     compare(f"L={L}", T, F, S, ref)
 
 
-@pytest.mark.parametrize("T_max", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("T_max", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_budgets_inside_the_tiled_steps(gpu, orc, T_max):
     L, p, n = 272, 0.07, 8
     s = seeds(83, T_max, n)
@@ -99,7 +100,7 @@ def test_same_as_band_path_on_a_larger_batch(gpu, L):
     for p in (0.02, 0.08):
         s = seeds(86, L + int(p * 100), n)
         base = [x.cpu().numpy() for x in with_bits(gpu, L, 0, lambda: gpu.decode_batch(L, p, s, T_max))]
-        for k in (1, 2, 3, 4):
+        for k in (1, 2, 3, 4, 5, 6):
             got = [x.cpu().numpy() for x in with_bits(gpu, L, k, lambda: gpu.decode_batch(L, p, s, T_max))]
             for a, b, name in zip(got, base, ("T_dec", "flags", "syndrome")):
                 assert np.array_equal(a, b), f"L={L} p={p} k_bits={k}: {name} differs from the band path"
