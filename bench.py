@@ -774,6 +774,25 @@ def learned_c5(args, b, seeds, torch, np, runner):
     dev = torch.device("cuda")
     K, W = args.steps, args.warmup
     S = len(runner.streams)
+    if args.no_learned:  # the plain (FIFO) decode of both sizes only
+        for Lc, n, pidx in ((256, 4096, 0), (1024, 1024, 1)):
+            batches = [torch.from_numpy(seeds(5, 100 + pidx, n, start=i * n).view(np.int64)).to(dev)
+                       for i in range(W + K)]
+            wss = [b.alloc_workspace(Lc, n) for _ in range(S)]
+            outs = [(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
+                     None) for _ in range(W + K)]
+
+            def fifo(i, j, stream):
+                b.decode_batch(Lc, P, batches[i], T_MAX, want_syndrome=False, workspace=wss[j], out=outs[i],
+                               stream=stream)
+
+            runner.run(fifo, range(W))
+            dt = runner.run(fifo, range(W, W + K))
+            T = torch.cat([outs[i][0] for i in range(W, W + K)]).cpu().numpy().astype(np.int64)
+            print(json.dumps({"workload": f"config 5: L={Lc} p={P} {n} samples, plain decode",
+                              "fifo_samples_per_s": K * n / dt, "ms_per_batch": dt / K * 1e3,
+                              "mean_T_dec": float(T.mean()), "concurrent_batches": S}), flush=True)
+        return
     counts, target, _, _ = learned.make_dataset(200000)
     params, _ = learned.train(counts, target, epochs=6)
     for Lc, n, pidx in ((256, 4096, 0), (1024, 1024, 1)):
