@@ -472,6 +472,54 @@ __device__ __forceinline__ void bits_step(BitsLane<CPL> &s, uint32_t t3, uint4 (
   bits_feedback<B, CPL, TORUS>(s, MX, v, vdn, vup, lane, wind, cut);
 }
 
+// The emission times of word w (rows 4g_lo .. 4g_hi - 1 of the word) of a
+// lane's four columns in the band layout: row y of the word (ybase + 4g + j,
+// wrapped at L) goes to E[y P + q0] (columns 0, 1) and E[y P + q1] (columns
+// 2, 3) as packed u16 pairs (e^{+x} | e^{-x} << 16, e^{+y} | e^{-y} << 16).
+// Rows go four at a time: a plane's four bits of the group are spread to
+// bit 0 of four bytes (a product with 2^0 + 2^7 + 2^14 + 2^21 places bit j at
+// bit 8j, and the copies do not overlap; 24-bit products, one instruction),
+// and the planes OR'd at bits q of those bytes, so byte j holds row 4g + j's
+// emission time; one byte permutation then makes each 16-bit pair.
+__device__ __forceinline__ void bits_store_rows(const BitsLane<4> &s, int w, int g_lo, int g_hi, int ybase, int L,
+                                                int P, int q0, int q1, bool store, uint4 *E) {
+  constexpr int CPL = 4;
+#pragma unroll 1
+  for (int g = g_lo; g < g_hi; ++g) {
+    const uint32_t sh = opaque(4u * (uint32_t)g);
+    uint32_t Z[4][CPL];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        uint32_t z = 0u;
+#pragma unroll
+        for (int q = 0; q < BITS_PLANES; ++q)
+          z |= q < 3 ? __umul24(__builtin_amdgcn_ubfe(s.E[d][q][c][w], sh, 4u), 0x00204081u << q) & (0x01010101u << q)
+                     : (opaque(__umul24(__builtin_amdgcn_ubfe(s.E[d][q][c][w], sh, 4u), 0x00204081u)) & 0x01010101u)
+                           << q;
+        Z[d][c] = z;
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // byte 0: first operand's byte j, byte 2: second operand's byte j, bytes 1 and 3 zero
+      const uint32_t sel = (uint32_t)j | 0x0C00u | ((uint32_t)(4 + j) << 16) | 0x0C000000u;
+      uint32_t Pw[CPL], Qw[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        Pw[c] = __builtin_amdgcn_perm(Z[1][c], Z[0][c], sel);
+        Qw[c] = __builtin_amdgcn_perm(Z[3][c], Z[2][c], sel);
+      }
+      int y = ybase + 4 * g + j;
+      if (y >= L) y -= L;
+      if (store) {
+        E[(size_t)y * P + q0] = make_uint4(Pw[0], Qw[0], Pw[1], Qw[1]);
+        E[(size_t)y * P + q1] = make_uint4(Pw[2], Qw[2], Pw[3], Qw[3]);
+      }
+    }
+  }
+}
+
 // One workgroup per sample (DRAWN: the syndrome and error windings come from
 // the noise kernel, in a.S_in and a.wind): noise, initial syndrome and windings, then up to
 // a.k decoder steps, stopping after the first step that leaves no anyon.
@@ -692,26 +740,7 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
     uint4 *E = a.E + (size_t)smp * L * half_row;
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-#pragma unroll 1
-      for (int r = 0; r < 32; ++r) {
-        uint32_t P[CPL], Q[CPL];
-        const uint32_t rr = opaque((uint32_t)r);  // no shifted copies of the planes carried across rows
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          uint32_t e[4];
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            e[d] = 0u;
-#pragma unroll
-            for (int q = 0; q < BITS_PLANES; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
-          }
-          P[c] = e[0] | (e[1] << 16);
-          Q[c] = e[2] | (e[3] << 16);
-        }
-        const size_t y = (size_t)(64 * v + 32 * w + r);
-        E[y * half_row + 2 * ln] = make_uint4(P[0], Q[0], P[1], Q[1]);
-        E[y * half_row + 2 * ln + 1] = make_uint4(P[2], Q[2], P[3], Q[3]);
-      }
+      bits_store_rows(s, w, 0, 8, 64 * v + 32 * w, L, (int)half_row, 2 * ln, 2 * ln + 1, true, E);
       const size_t strip = (size_t)smp * (L / TILE_H) + (size_t)(4 * v + 2 * w);
       a.S[strip * half_row + 2 * ln] = make_uint2(s.S[0][w] & 0xFFFFu, s.S[1][w] & 0xFFFFu);
       a.S[strip * half_row + 2 * ln + 1] = make_uint2(s.S[2][w] & 0xFFFFu, s.S[3][w] & 0xFFFFu);
@@ -888,7 +917,7 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
     if (red) atomicXor(&a.wind[sm2], red);
     atomicOr(&a.alive[sm2], bits);
   }
-  // own part of the state in the band layout
+  // own part of the state in the band layout (own rows come in groups of four)
   const int ln = lane_here();
   const bool own = ln >= own_lo && ln < own_hi;
   const int q0 = wrap(X0 / 2 + 2 * ln, P), q1 = wrap(q0 + 1, P);
@@ -896,29 +925,8 @@ __global__ __launch_bounds__(256) void k_bits_tile(BitsTileArgs a) {
 #pragma unroll
   for (int w = 0; w < 2; ++w) {
     const int r0 = 64 * v + 32 * w;
-#pragma unroll 1
-    for (int r = 0; r < 32; ++r) {
-      if (r0 + r < h || r0 + r >= h + owy) continue;
-      uint32_t Pw[CPL], Qw[CPL];
-      const uint32_t rr = opaque((uint32_t)r);
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        uint32_t e[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          e[d] = 0u;
-#pragma unroll
-          for (int q = 0; q < BITS_PLANES; ++q) e[d] |= __builtin_amdgcn_ubfe(s.E[d][q][c][w], rr, 1u) << q;
-        }
-        Pw[c] = e[0] | (e[1] << 16);
-        Qw[c] = e[2] | (e[3] << 16);
-      }
-      const size_t y = (size_t)wrap(Y0 + r0 + r, L);
-      if (own) {
-        E[y * P + q0] = make_uint4(Pw[0], Qw[0], Pw[1], Qw[1]);
-        E[y * P + q1] = make_uint4(Pw[2], Qw[2], Pw[3], Qw[3]);
-      }
-    }
+    const int g_lo = min(max(h - r0, 0), 32) / 4, g_hi = min(max(h + owy - r0, 0), 32) / 4;
+    bits_store_rows(s, w, g_lo, g_hi, wrap(Y0 + r0, L), L, P, q0, q1, own, E);
     // syndrome: the word's own rows, shifted to their place in the masks
     // (anyons only: the masks were cleared)
     const int R = wrap(Y0 + r0, L), off = R % TILE_H, j0 = R / TILE_H;
