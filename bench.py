@@ -296,51 +296,63 @@ class Runner:
         return dt
 
 
-def device_driven(b, batches, outs, W, K, n, ws, torch):
+def device_driven(b, batches, outs, W, K, n, ws, torch, rounds=5):
     """The same K batches, one stream: with the later passes driven from the
     host (a survivor-count readback per pass) and on the device (no host
-    wait in a decode), then as replays of one captured HIP graph (the seeds
-    copied into the graph's input before each replay).  Checks that every
-    output equals the plain run's."""
+    wait in a decode), and as replays of one captured HIP graph (the seeds
+    copied into the graph's input before each replay), timed in alternating
+    rounds so that drift of the device clock falls on all alike.  Checks
+    that every output equals the plain run's."""
     dev = torch.device("cuda")
     st = torch.cuda.current_stream()
     o = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.uint8, device=dev),
          torch.empty((n, b.syndrome_words(L)), dtype=torch.int32, device=dev))
     same = True
-    el = {}
-    for name, drv in (("host", b.BAND_DRIVER_HOST), ("device", b.BAND_DRIVER_DEVICE)):
-        b.set_band_driver(drv)
-        try:
-            for i in range(W):
-                b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for i in range(W, W + K):
-                b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
-            torch.cuda.synchronize()
-            el[name] = time.perf_counter() - t0
-            same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
-        finally:
-            b.set_band_driver(b.BAND_DRIVER_AUTO)
     s_in = batches[0].clone()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         b.decode_batch(L, P, s_in, T_MAX, workspace=ws, out=o)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(W, W + K):
+    for i in range(W, min(W + 2, W + K)):  # a couple of replays checked against the plain run (untimed)
         s_in.copy_(batches[i])
         g.replay()
-        if i < W + 2:  # a couple of replays checked against the plain run as they go
+        torch.cuda.synchronize()
+        same = same and all(torch.equal(x, y) for x, y in zip(o, outs[i]))
+
+    def run(mode):
+        if mode == "graph":
+            for i in range(W, W + K):
+                s_in.copy_(batches[i])
+                g.replay()
+            return
+        b.set_band_driver(b.BAND_DRIVER_HOST if mode == "host" else b.BAND_DRIVER_DEVICE)
+        try:
+            for i in range(W, W + K):
+                b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
+        finally:
+            b.set_band_driver(b.BAND_DRIVER_AUTO)
+
+    for mode in ("host", "device"):  # warm-up
+        b.set_band_driver(b.BAND_DRIVER_HOST if mode == "host" else b.BAND_DRIVER_DEVICE)
+        try:
+            for i in range(W):
+                b.decode_batch(L, P, batches[i], T_MAX, workspace=ws, out=o, stream=st)
+        finally:
+            b.set_band_driver(b.BAND_DRIVER_AUTO)
+    el = {"host": 0.0, "device": 0.0, "graph": 0.0}
+    for _ in range(rounds):
+        for mode in el:
             torch.cuda.synchronize()
-            same = same and all(torch.equal(x, y) for x, y in zip(o, outs[i]))
-    torch.cuda.synchronize()
-    el_graph = time.perf_counter() - t0
-    same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
-    return {"samples_per_s": K * n / el["device"], "ms_per_step": el["device"] / K * 1e3,
-            "host_driver_samples_per_s": K * n / el["host"], "host_driver_ms_per_step": el["host"] / K * 1e3,
-            "graph_replay_samples_per_s": K * n / el_graph, "graph_replay_ms_per_step": el_graph / K * 1e3,
-            "identical_results": bool(same)}
+            t0 = time.perf_counter()
+            run(mode)
+            torch.cuda.synchronize()
+            el[mode] += time.perf_counter() - t0
+            same = same and all(torch.equal(x, y) for x, y in zip(o, outs[W + K - 1]))
+    R = rounds * K
+    return {"samples_per_s": R * n / el["device"], "ms_per_step": el["device"] / R * 1e3,
+            "host_driver_samples_per_s": R * n / el["host"], "host_driver_ms_per_step": el["host"] / R * 1e3,
+            "graph_replay_samples_per_s": R * n / el["graph"], "graph_replay_ms_per_step": el["graph"] / R * 1e3,
+            "rounds": rounds, "identical_results": bool(same)}
 
 
 def learned_scheduling(b, batches, outs, W, K, n, torch, np, runner, L_eval=L):
