@@ -39,10 +39,17 @@ CSRC = os.path.join(ROOT, "paper_2506_03266_amd", "csrc")
 
 def kernel_source_sha():
     """sha256[:16] of the bit-sliced kernel's device code: engine.h, band.h
-    (lane shifts) and bits.h."""
+    (lane shifts) and bits.h, without // comments, trailing blanks and empty
+    lines (so that editing a comment keeps a profile valid)."""
     import hashlib
-    parts = [open(os.path.join(CSRC, f), "rb").read() for f in ("engine.h", "band.h", "bits.h")]
-    return hashlib.sha256(b"".join(parts)).hexdigest()[:16]
+    import re
+    lines = []
+    for f in ("engine.h", "band.h", "bits.h"):
+        for line in open(os.path.join(CSRC, f), encoding="utf-8"):
+            line = re.sub(r"//.*$", "", line.rstrip("\n")).rstrip()
+            if line:
+                lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
 def profile_summary():

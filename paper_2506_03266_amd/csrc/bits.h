@@ -1,5 +1,6 @@
-// bits.h -- bit-sliced whole-lattice kernel for the first decoder steps at
-// L = 64, 128 and 256 (gfx950).
+// bits.h -- bit-sliced kernels for the first decoder steps (gfx950): the
+// whole lattice in one workgroup at L = 64, 128 and 256 (k_bits), and
+// 256 x 256 regions with halos above 256 (k_bits_tile, at the end).
 //
 // Registers hold emission times (see engine.h), and during the first ten
 // decoder steps every emission time is at most 3 * 10 = 30: a register fits
