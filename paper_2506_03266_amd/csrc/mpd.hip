@@ -799,15 +799,20 @@ __global__ __launch_bounds__(1024) void k_band_noise(int L, int CP, int S, const
   const uint64_t seed = seeds[sample];
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const uint64_t t = p_arr ? device_threshold(p_arr[sample]) : thr;
+  // rows from the top down, each flip bit shifted in at bit 0 through the
+  // carry of one add (shift_in_below), so row h ends at bit h; t = 2^32
+  // (p = 1) flips every link, below that the 32-bit comparison is exact
+  const uint32_t t32 = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
   uint32_t ex0 = 0u, ey0 = 0u, ex1 = 0u, ey1 = 0u;
 #pragma unroll 4
-  for (int h = 0; h < TILE_H; ++h) {
+  for (int h = TILE_H - 1; h >= 0; --h) {
     const Words4 r = philox4x32_10((uint32_t)((y0 + h) * L + gx) >> 1, k0, k1);
-    ex0 |= (uint32_t)((uint64_t)r.w0 < t) << h;
-    ey0 |= (uint32_t)((uint64_t)r.w1 < t) << h;
-    ex1 |= (uint32_t)((uint64_t)r.w2 < t) << h;
-    ey1 |= (uint32_t)((uint64_t)r.w3 < t) << h;
+    shift_in_below(ex0, r.w0, t32);
+    shift_in_below(ey0, r.w1, t32);
+    shift_in_below(ex1, r.w2, t32);
+    shift_in_below(ey1, r.w3, t32);
   }
+  if (t > 0xFFFFFFFFull) ex0 = ey0 = ex1 = ey1 = full_mask<TILE_H>();
   if (open) {
     if (q == P - 1) ex1 = 0u;                       // x-links leaving column L-1
     if (q == 0) ey0 = 0u;                           // column 0 is the boundary
