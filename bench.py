@@ -52,6 +52,24 @@ def kernel_source_sha():
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
+def library_source_sha():
+    """sha256[:16] of the library's sources (csrc/*.hip, csrc/*.h, include/mpd.h)
+    and the git commit if the tree is a checkout: which code a bench line ran."""
+    import glob
+    import hashlib
+    import subprocess
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")))
+    for f in files + [os.path.join(ROOT, "include", "mpd.h")]:
+        h.update(open(f, "rb").read())
+    try:
+        commit = subprocess.run(["git", "rev-parse", "--short=12", "HEAD"], cwd=ROOT, capture_output=True,
+                                text=True, timeout=10).stdout.strip() or None
+    except Exception:
+        commit = None
+    return h.hexdigest()[:16], commit
+
+
 def profile_summary():
     """The committed rocprofv3 summary of k_bits on the benchmark batches
     (VALU instructions per launch from SQ_INSTS_VALU, HBM bytes per launch
@@ -181,6 +199,7 @@ def main():
     samples_per_s = K * n / elapsed
     su_per_s = site_updates / elapsed
     summ = profile_summary()
+    lib_sha, git_commit = library_source_sha()
     avg_launch_s = bits_ms / 1e3 / max(bits_launches, 1)
     valu = summ.get("valu_insts_per_launch")
     achieved = valu * 64 / avg_launch_s / 1e12 if (valu and bits_launches) else None
@@ -249,6 +268,8 @@ def main():
                      "band_passes": {"k_bits_steps": k_bits, "samples_beyond": int((T_all > k_bits).sum()),
                                      "launches": band_launches, "total_ms": band_ms}},
         "kernel_source_sha16": kernel_source_sha(),
+        "library_source_sha16": lib_sha,
+        "git_commit": git_commit,
         "cpu_baseline": cpu,
         "device_driver": device_leg,
         "learned_sched": learned_leg,

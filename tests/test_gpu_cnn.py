@@ -288,6 +288,23 @@ def trained(gpu):
     return params, target
 
 
+def test_training_labels_relabelled_by_oracle(gpu, orc, trained):
+    """2% of the 200000 training labels (every 50th sample of the data set
+    the predictor is trained on) decoded again by the CPU oracle: the same
+    T_dec for every one."""
+    from paper_2506_03266_amd import learned
+    _, target = trained
+    n = target.numel()
+    p = np.random.default_rng(5).uniform(learned.P_RANGE[0], learned.P_RANGE[1], n)  # make_dataset's draw
+    s = learned.make_seeds(learned.TRAIN_CONFIG, 1, n)
+    pick = np.arange(0, n, 50)
+    T = np.rint(np.expm1(target.cpu().numpy().astype(np.float64))).astype(np.int64)[pick]
+    ref = orc.decode_seeds(256, p[pick], s[pick], 4096, threads=16)
+    assert pick.size == n // 50
+    bad = np.nonzero(T != ref["T_dec"])[0]
+    assert bad.size == 0, f"{bad.size} labels differ, first at sample {pick[bad[:5]]}: {T[bad[:5]]} vs {ref['T_dec'][bad[:5]]}"
+
+
 def _time_batches(batches, fn):
     import time
     fn(*batches[0])
