@@ -1229,8 +1229,8 @@ int launch_small(int L, int64_t n, const uint64_t *seeds, uint64_t thr, const do
     t.T_dec = T_dec;
     t.flags = flags;
     t.syn = syn;
-    const int kb = std::min(bits_steps_for(L), T_max);
-    if (bits_steps_for(L) > 0) {
+    const int kb_set = bits_steps_for(L), kb = std::min(kb_set, T_max);
+    if (kb_set > 0) {
       // noise and the first kb steps bit-sliced; the whole-lattice kernel
       // takes the samples that are still decoding after them
       BitsArgs b = {};
