@@ -56,11 +56,12 @@ def test_steps_against_oracle(gpu, orc, L, k, p):
     compare(f"L={L} k_bits={k} p={p}", T, F, S, ref)
 
 
-@pytest.mark.parametrize("L", [288, 1024])
+@pytest.mark.parametrize("L", [288, 1024, 2048])
 def test_other_sizes_against_oracle(gpu, orc, L):
     """288 = 72 groups of four rows (two tiles of 36 at six steps); 1024 over
-    five tiles of 204 or 208 rows, whose edges fall inside 16-row masks."""
-    n, p, T_max = 4, 0.03, 2048
+    five tiles of 204 or 208 rows, whose edges fall inside 16-row masks;
+    2048 over ten tiles per side."""
+    n, p, T_max = (4, 0.03, 2048) if L < 2048 else (2, 0.02, 256)
     s = seeds(82, L, n)
     ref = orc.decode_seeds(L, p, s, T_max, threads=16)
     T, F, S = gpu.decode_batch(L, p, s, T_max)
