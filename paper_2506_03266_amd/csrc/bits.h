@@ -644,13 +644,27 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
 #pragma unroll
       for (int c = 0; c < CPL; ++c) s.E[d][q][c][0] = s.E[d][q][c][1] = 0u;
 
+  // anyons anywhere in the sample: a wave ballot, then (several waves) each
+  // wave's flag through LDS -- every lane writes the same value -- and one
+  // barrier (a block-wide OR intrinsic takes three)
+  __shared__ uint32_t AF[NW];
   auto any_anyon = [&]() {
     uint32_t o = 0u;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) o |= s.S[c][0] | s.S[c][1];
-    return o != 0u;
+    const bool wave_any = __ballot(o != 0u) != 0ull;
+    if constexpr (NW == 1) {
+      return wave_any;
+    } else {
+      AF[v] = wave_any ? 1u : 0u;
+      __syncthreads();
+      uint32_t r = 0u;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) r |= AF[i];
+      return __builtin_amdgcn_readfirstlane(r) != 0u;
+    }
   };
-  bool alive = __syncthreads_or(any_anyon()) != 0;
+  bool alive = any_anyon();
   uint32_t bits = alive ? 1u : 0u;
   int t = 0;
   // step t + 1 ends at sub-step 3 (t + 1): emission times below 4 in the
@@ -660,7 +674,7 @@ __global__ __launch_bounds__(CPL * 64) void k_bits(BitsArgs a) {
   const Cut cut = {63, {~0u, ~0u}, NW - 1, 1, 31, 0, 64};  // the whole torus
   auto after_step = [&]() {
     ++t;
-    alive = __syncthreads_or(any_anyon()) != 0;
+    alive = any_anyon();
     if (alive) bits |= 1u << t;
   };
   if (alive && t < a.k) {
