@@ -380,7 +380,9 @@ int mpd_get_band_driver(int L, int *driver);
  * in one workgroup (L/64 waves; no halo, no HBM state); a sample leaves as
  * soon as it has no anyon.  At L = 256 the others continue on the band path
  * from the state the kernel hands over; at L = 64 and 128 the whole-lattice
- * kernel decodes them again from their seeds (no workspace).  Larger
+ * kernel decodes them again from their seeds (no workspace), so there a
+ * batch with one p >= 0.045 (nearly every sample outlives the ten steps)
+ * skips the bit-sliced steps; per-sample p always runs them.  Larger
  * lattices run k = min(k_bits, 6) steps in 256 x 256 regions with a halo of
  * 4k (the tiled kernel), then continue on the band path.  k_bits in [0, 10]:
  * the number of such steps (0: the band path's first pass, or the

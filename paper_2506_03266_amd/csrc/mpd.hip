@@ -1194,19 +1194,23 @@ int torus_resident_groups(const void *kernel, int threads, size_t lds) {
   return std::max(cus * per_cu, 0);
 }
 
-int launch_torus(int L, const TorusArgs &a, hipStream_t stream) {
+// resident_grid: the launch resumes a batch of which the bit-sliced kernel
+// is expected to have decoded nearly every sample, so one grid of resident
+// workgroups steps over it instead of a workgroup per sample.  A fixed share
+// of samples per workgroup balances badly once many are left (decode times
+// have a long tail near the threshold), so every other launch leaves the
+// balancing to the hardware, one workgroup per sample.
+int launch_torus(int L, const TorusArgs &a, bool resident_grid, hipStream_t stream) {
   ProfScope ps("k_torus", stream);
-  // a resumed launch only has the samples the bit-sliced kernel left: one
-  // resident grid steps over the batch instead of a workgroup per sample
   if (L == 64) {
     const size_t lds = (size_t)2 * 4 * 2 * 64 * sizeof(uint2) + (size_t)4 * 64 * sizeof(uint2);
     static const int cap64 = torus_resident_groups((const void *)k_torus<1, 4>, 4 * 64, lds);
-    const int64_t g = a.resume && cap64 > 0 ? std::min<int64_t>(a.n, cap64) : a.n;
+    const int64_t g = a.resume && resident_grid && cap64 > 0 ? std::min<int64_t>(a.n, cap64) : a.n;
     hipLaunchKernelGGL((k_torus<1, 4>), dim3((unsigned)g), dim3(4 * 64), lds, stream, a);
   } else {
     const size_t lds = (size_t)2 * 8 * 2 * 64 * sizeof(uint4) + (size_t)8 * 64 * sizeof(uint2);
     static const int cap128 = torus_resident_groups((const void *)k_torus<2, 8>, 8 * 64, lds);
-    const int64_t g = a.resume && cap128 > 0 ? std::min<int64_t>(a.n, cap128) : a.n;
+    const int64_t g = a.resume && resident_grid && cap128 > 0 ? std::min<int64_t>(a.n, cap128) : a.n;
     hipLaunchKernelGGL((k_torus<2, 8>), dim3((unsigned)g), dim3(8 * 64), lds, stream, a);
   }
   HIP_TRY(hipGetLastError());
@@ -1229,7 +1233,15 @@ int launch_small(int L, int64_t n, const uint64_t *seeds, uint64_t thr, const do
     t.T_dec = T_dec;
     t.flags = flags;
     t.syn = syn;
-    const int kb_set = bits_steps_for(L), kb = std::min(kb_set, T_max);
+    // With one p for the batch (p_arr null), the share of samples left after
+    // the bit-sliced steps follows from p.  Measured at L = 64 (10000
+    // samples) and 128 (4096): up to p = 0.02 so few are left that a
+    // resident grid resumes them fastest; from p = 0.045 on nearly every
+    // sample is left, and the bit-sliced steps only add their own time to a
+    // decode the whole-lattice kernel does again, so they are skipped.
+    // Per-sample p keeps the steps and resumes one workgroup per sample.
+    const bool one_p = p_arr == nullptr;
+    const int kb_set = one_p && thr >= threshold_of(0.045) ? 0 : bits_steps_for(L), kb = std::min(kb_set, T_max);
     if (kb_set > 0) {
       // noise and the first kb steps bit-sliced; the whole-lattice kernel
       // takes the samples that are still decoding after them
@@ -1253,7 +1265,7 @@ int launch_small(int L, int64_t n, const uint64_t *seeds, uint64_t thr, const do
       if (T_max <= kb) return MPD_OK;
       t.resume = 1;
     }
-    return launch_torus(L, t, stream);
+    return launch_torus(L, t, one_p && thr <= threshold_of(0.02), stream);
   }
   ResidentArgs a = {};
   a.L = L;

@@ -4,8 +4,11 @@ bit for bit (T_dec, flags and final syndrome): every number of bit-sliced
 steps, budgets that end inside them (the final syndrome then comes from the
 bit-sliced kernel), noise strengths from none to every link, per-sample
 noise strength, and samples still decoding after the bit-sliced steps (the
-whole-lattice kernel decodes them again from their seeds).  Every setting
-must give the whole-lattice kernel's results."""
+whole-lattice kernel decodes them again from their seeds, on a resident grid
+at low p and one workgroup per sample otherwise).  A batch with one p >=
+0.045 skips the bit-sliced steps, so each case above that also runs as
+per-sample p, which keeps them.  Every setting must give the whole-lattice
+kernel's results."""
 import numpy as np
 import pytest
 
@@ -36,6 +39,14 @@ def compare(tag, T, F, S, ref):
     assert rows.size == 0, f"{tag}: final syndrome differs for samples {rows[:5]}"
 
 
+def both_forms(gpu, L, p, s, T_max):
+    """The decode with one p for the batch and with the same p per sample."""
+    n = len(s)
+    one = gpu.decode_batch(L, p, s, T_max)
+    per = gpu.decode_mixed([(L, n)], np.full(n, p), s, T_max)
+    return (("one p", one), ("per-sample p", per))
+
+
 def with_bits(gpu, L, k, fn):
     old = gpu.get_band_bits(L)
     gpu.set_band_bits(k, L)
@@ -59,8 +70,8 @@ def test_steps_against_oracle(gpu, orc, L, k, p):
     n, T_max = 48, 512
     s = seeds(71, L * 100 + int(p * 1000) * 8 + k, n)
     ref = orc.decode_seeds(L, p, s, T_max, threads=16)
-    T, F, S = with_bits(gpu, L, k, lambda: gpu.decode_batch(L, p, s, T_max))
-    compare(f"L={L} k_bits={k} p={p}", T, F, S, ref)
+    for form, (T, F, S) in with_bits(gpu, L, k, lambda: both_forms(gpu, L, p, s, T_max)):
+        compare(f"L={L} k_bits={k} p={p} {form}", T, F, S, ref)
 
 
 @pytest.mark.parametrize("L", SIZES)
@@ -71,8 +82,8 @@ def test_budgets_inside_the_bit_sliced_steps(gpu, orc, L, T_max):
     p, n = 0.08, 32
     s = seeds(72, L * 100 + T_max, n)
     ref = orc.decode_seeds(L, p, s, T_max, threads=16)
-    T, F, S = gpu.decode_batch(L, p, s, T_max)
-    compare(f"L={L} T_max={T_max}", T, F, S, ref)
+    for form, (T, F, S) in both_forms(gpu, L, p, s, T_max):
+        compare(f"L={L} T_max={T_max} {form}", T, F, S, ref)
 
 
 @pytest.mark.parametrize("L", SIZES)
@@ -97,16 +108,46 @@ def test_per_sample_noise_strength(gpu, orc, L):
 
 @pytest.mark.parametrize("L", SIZES)
 def test_same_as_whole_lattice_kernel_on_a_large_batch(gpu, L):
-    """4096 samples at p = 0.03 and 0.07: every setting of the bit-sliced
-    steps gives the whole-lattice kernel's results."""
+    """4096 samples at p = 0.01 (survivors resumed on a resident grid), 0.03
+    (one workgroup per survivor) and 0.07 as per-sample p (nearly every
+    sample resumed): every setting of the bit-sliced steps gives the
+    whole-lattice kernel's results."""
     n, T_max = 4096, 4096
-    for p in (0.03, 0.07):
+    for p, per_sample in ((0.01, False), (0.03, False), (0.07, True)):
         s = seeds(75, L + int(p * 100), n)
-        base = [x.cpu().numpy() for x in with_bits(gpu, L, 0, lambda: gpu.decode_batch(L, p, s, T_max))]
+
+        def run():
+            if per_sample:
+                return gpu.decode_mixed([(L, n)], np.full(n, p), s, T_max)
+            return gpu.decode_batch(L, p, s, T_max)
+        base = [x.cpu().numpy() for x in with_bits(gpu, L, 0, run)]
         for k in (1, 4, 7, 10):
-            got = [x.cpu().numpy() for x in with_bits(gpu, L, k, lambda: gpu.decode_batch(L, p, s, T_max))]
+            got = [x.cpu().numpy() for x in with_bits(gpu, L, k, run)]
             for a, b, name in zip(got, base, ("T_dec", "flags", "syndrome")):
                 assert np.array_equal(a, b), f"L={L} p={p} k_bits={k}: {name} differs from the whole-lattice kernel"
+
+
+@pytest.mark.parametrize("L", SIZES)
+def test_bit_sliced_steps_skipped_at_high_one_p(gpu, L):
+    """With one p for the batch the bit-sliced kernel runs below p = 0.045
+    and not from there on; per-sample p always runs it."""
+    n, T_max = 256, 4096
+    s = seeds(77, L, n)
+
+    def launches(fn):  # launches of the bit-sliced kernel during fn()
+        import torch
+        torch.cuda.synchronize()
+        gpu.profile(True)
+        try:
+            fn()
+            torch.cuda.synchronize()
+        finally:
+            gpu.profile(False)
+        return gpu.profile_read("k_bits_small")[1]
+    assert launches(lambda: gpu.decode_batch(L, 0.044, s, T_max)) == 1
+    assert launches(lambda: gpu.decode_batch(L, 0.045, s, T_max)) == 0
+    assert launches(lambda: gpu.decode_batch(L, 0.08, s, T_max)) == 0
+    assert launches(lambda: gpu.decode_mixed([(L, n)], np.full(n, 0.08), s, T_max)) == 1
 
 
 def test_mixed_classes_against_oracle(gpu, orc):
