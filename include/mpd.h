@@ -401,10 +401,11 @@ int mpd_get_band_bits(int L, int *k_bits);
  * the steps of the bit-sliced first kernel (0, 3, 5, 8, 10 at L = 256; 0,
  * 4, 5, 6 of the tiled one above; with it on, k_first is not searched, since
  * the band passes start after it) -- timing each with HIP events on
- * `stream`, and keeps the fastest for
- * this L (mpd_get_band_schedule, mpd_get_band_driver and mpd_get_band_bits
- * then return it).  *k_first, *k_next and *best_ms receive the choice.
- * Synchronizes `stream`. */
+ * `stream` (a warm-up decode, then a timed one).  The eight fastest are
+ * timed again in five interleaved rounds, and the one with the lowest
+ * median is kept for this L (mpd_get_band_schedule, mpd_get_band_driver
+ * and mpd_get_band_bits then return it).  *k_first, *k_next and *best_ms
+ * (that median) receive the choice.  Synchronizes `stream`. */
 int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T_max, int32_t *d_T_dec,
                       uint8_t *d_flags, void *d_workspace, size_t ws_bytes, void *stream, int *k_first,
                       int *k_next, float *best_ms);

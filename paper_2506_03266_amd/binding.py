@@ -528,8 +528,10 @@ def load_band_tuning(path: str) -> dict:
 def autotune_band(L: int, p: float, seeds, T_max: int = 4096, stream=None):
     """Time the band-path schedules (driver x k_first x k_next, and the steps
     of the bit-sliced first kernel: 0, 3, 5, 8, 10 at L = 256, 0, 4, 5, 6 of
-    the tiled one above) on a probe batch and keep the fastest for L.  Returns (k_first, k_next, best_ms); get_band_driver(L)
-    and get_band_bits(L) give the chosen driver and bit-sliced steps."""
+    the tiled one above) on a probe batch, time the eight fastest again in
+    five interleaved rounds and keep the lowest median for L.  Returns
+    (k_first, k_next, median ms); get_band_driver(L) and get_band_bits(L)
+    give the chosen driver and bit-sliced steps."""
     dev = torch.device("cuda")
     s = _seeds_tensor(seeds, dev)
     n = s.numel()

@@ -2469,30 +2469,49 @@ int mpd_autotune_band(int L, double p, const uint64_t *d_seeds, int64_t n, int T
         }
       }
     }
-  for (size_t ci = 0; ci < cand.size() && rc == MPD_OK; ++ci) {
-    const BandSchedule c = cand[ci];
+  // one probe decode under schedule c, after a warm-up decode under it
+  auto time_one = [&](const BandSchedule &c, float &ms) -> int {
     {
-      {
-        {
-          std::lock_guard<std::mutex> lk(g_sched_mu);
-          g_sched_by_L[L] = c;
-        }
-        // warm-up run, then a timed run
-        rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
-        if (rc) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail_with(MPD_ERR_HIP, "event record"); break; }
-        rc = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
-        if (rc) break;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          rc = fail_with(MPD_ERR_HIP, "event timing");
-          break;
-        }
+      std::lock_guard<std::mutex> lk(g_sched_mu);
+      g_sched_by_L[L] = c;
+    }
+    int r = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
+    if (r) return r;
+    if (hipEventRecord(e0, st) != hipSuccess) return fail_with(MPD_ERR_HIP, "event record");
+    r = mpd_decode_batch(L, p, d_seeds, n, T_max, d_T_dec, d_flags, nullptr, d_workspace, ws_bytes, stream);
+    if (r) return r;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail_with(MPD_ERR_HIP, "event timing");
+    ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return MPD_OK;
+  };
+  // Screening: one timed decode per candidate.  The minimum of many single
+  // timings of a short probe favours whichever candidate met a quiet moment,
+  // so the fastest few are timed again in interleaved rounds and the pick is
+  // the lowest median.
+  constexpr int FINALISTS = 8, ROUNDS = 5;
+  std::vector<float> first(cand.size(), 1e30f);
+  for (size_t ci = 0; ci < cand.size() && rc == MPD_OK; ++ci) rc = time_one(cand[ci], first[ci]);
+  if (rc == MPD_OK) {
+    std::vector<size_t> order(cand.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return first[x] < first[y]; });
+    order.resize(std::min<size_t>(order.size(), FINALISTS));
+    std::vector<std::vector<float>> again(order.size());
+    for (int r = 0; r < ROUNDS && rc == MPD_OK; ++r)
+      for (size_t f = 0; f < order.size() && rc == MPD_OK; ++f) {
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-          best = ms;
-          pick = c;
-        }
+        rc = time_one(cand[order[f]], ms);
+        again[f].push_back(ms);
+      }
+    for (size_t f = 0; f < order.size() && rc == MPD_OK; ++f) {
+      std::vector<float> v = again[f];
+      std::sort(v.begin(), v.end());
+      const float med = v[v.size() / 2];
+      if (med < best) {
+        best = med;
+        pick = cand[order[f]];
       }
     }
   }
