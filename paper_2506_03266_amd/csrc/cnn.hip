@@ -277,68 +277,118 @@ __device__ __forceinline__ void conv_layer(const uint16_t *__restrict__ in, uint
   }
 }
 
-// A 16 -> 16 layer of a whole 32 x 32 map (bordered input and output
-// buffers [34^2][16]), streamed by rows: wave w computes the 16 columns
-// x0 = 16 (w & 1) of output rows y0 .. y0 + 7, y0 = 8 (w >> 1).  It walks
-// the bordered input rows R = y0 .. y0 + 9 once; the operand fragment of a
-// row (the taps dx = -1, 0 in one K block, dx = +1 in a second) serves the
-// three output rows R, R - 1, R - 2 that read it (with the weights of
-// dy = -1, 0, +1), which keep three accumulators in flight.  So each input
-// fragment is read from LDS once for three output rows.  A holds the six
-// blocks of Arow for this layer.  LAST folds the outputs into the pooling
-// state (a lane meets its positions in increasing order).
-template <bool LAST>
-__device__ __forceinline__ void conv_rows32(const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
-                                            const bf16x8 *A, const float *__restrict__ b, Pool &pool) {
-  constexpr int M = 32, S = M + 2, RPW = 8;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Activations of a whole 32 x 32 map in LDS: [32 rows][33 columns][16
+// channels] bfloat16.  Rows and columns wrap by address (no border copies);
+// column 32 stays zero and is what the lanes whose second K block holds no
+// tap read, so that every lane issues the same loads.
+constexpr int M32 = 32, RS32 = (M32 + 1) * CH;  // row stride in bfloat16
+constexpr int BUF32 = M32 * RS32;               // one buffer, in bfloat16
+
+// A lane's LDS addresses in the first buffer, fixed for the kernel: wave w
+// computes the 16 columns x0 = 16 (w & 1) of output rows y0 .. y0 + 7, y0 =
+// 8 (w >> 1), from input rows y0 - 1 .. y0 + 8 (mod 32).  rd[k][b] is the
+// lane's K slice of block b in input row y0 - 1 (k = 0), y0 (k = 1; rows up
+// to y0 + 7 follow at multiples of RS32) and y0 + 8 (k = 2); block 0 holds
+// the tap dx = -1 (lane groups 0, 1) or 0 (groups 2, 3), block 1 dx = +1
+// (groups 0, 1) or the zero column.  wr is the lane's output (4 channels)
+// in row y0.  The second buffer is the same plus BUF32.
+struct Lane32 {
+  const uint16_t *rd[3][2];
+  uint16_t *wr;
+};
+__device__ __forceinline__ Lane32 lane32(uint16_t *bufA) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = lane & 15, g = lane >> 4;
-  const int x0 = (wave & 1) * 16, y0 = (wave >> 1) * RPW;
-  float bias[4];
+  const int x = (wave & 1) * 16 + j, y0 = (wave >> 1) * 8;
+  const int col[2] = {(x + M32 - 1 + (g >> 1)) & (M32 - 1), g < 2 ? (x + 1) & (M32 - 1) : M32};
+  const int row[3] = {(y0 + M32 - 1) & (M32 - 1), y0, (y0 + 8) & (M32 - 1)};
+  Lane32 l;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) bias[r] = b[4 * g + r];
-  // bordered columns of this lane's K slices: block 0 dx = -1 (groups 0, 1)
-  // or 0 (groups 2, 3); block 1 dx = +1 (groups 0, 1 only)
-  const uint16_t *p0 = in + (y0 * S + x0 + j + (g >> 1)) * CH + 8 * (g & 1);
-  const uint16_t *p1 = in + (y0 * S + x0 + j + 2) * CH + 8 * (g & 1);
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) l.rd[k][b] = bufA + row[k] * RS32 + col[b] * CH + 8 * (g & 1);
+  l.wr = bufA + y0 * RS32 + x * CH + 4 * g;
+  return l;
+}
+
+// K slice of block b in input row y0 - 1 + t (t = 0 .. 9) of the buffer at
+// offset IN (0 or BUF32).
+template <int IN>
+__device__ __forceinline__ uint4 row_slice(const Lane32 &l, int t, int b) {
+  const uint16_t *p = t == 0 ? l.rd[0][b] : t == 9 ? l.rd[2][b] : l.rd[1][b] + (t - 1) * RS32;
+  return *reinterpret_cast<const uint4 *>(p + IN);
+}
+
+// ReLU of two packed bfloat16: a bfloat16's sign is the sign of the same
+// bits read as int16, so the maximum with 0 as two int16 (one v_pk_max_i16)
+// zeroes the negative ones.  Taken after the rounding, which keeps signs,
+// it gives the rounded ReLU; a NaN keeps its bits unless its sign is set.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), s16x2{0, 0}));
+}
+
+// Zero column of one buffer (2 x 16 bytes per row).
+__device__ __forceinline__ void zero_column32(uint16_t *buf) {
+  if (threadIdx.x < 2 * M32)
+    reinterpret_cast<uint4 *>(buf + (threadIdx.x >> 1) * RS32 + M32 * CH)[threadIdx.x & 1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// A 16 -> 16 layer of a whole 32 x 32 map, streamed by rows: the wave walks
+// its input rows once; the operand fragment of a row (the taps dx = -1, 0
+// in one K block, dx = +1 in a second) serves the three output rows that
+// read it (with the weights of dy = -1, 0, +1), which keep three
+// accumulators in flight, so each input fragment is read from LDS once for
+// three output rows.  The bias is the first instruction's accumulator.  A
+// holds the six blocks of Arow for this layer.  IN / OUT: buffer offsets.
+// LAST folds the outputs into the pooling state (a lane meets its positions
+// in increasing order and starts it at value 0 at its first position: the
+// largest ReLU output with the lowest position, found without taking the
+// ReLU, since relu(v) > m <=> v > m for m >= 0).
+template <bool LAST, int IN, int OUT>
+__device__ __forceinline__ void conv_rows32(const Lane32 &l, const bf16x8 *A, const f32x4 &bias, Pool &pool) {
+  constexpr int RPW = 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = (wave & 1) * 16 + (lane & 15), y0 = (wave >> 1) * RPW;
+  if (LAST)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      pool.best[r] = 0.f;
+      pool.idx[r] = y0 * M32 + x;
+    }
   f32x4 acc[3];
   // fragments of the next input row are loaded one row ahead
-  uint4 n0 = *reinterpret_cast<const uint4 *>(p0), n1 = make_uint4(0u, 0u, 0u, 0u);
-  if (g < 2) n1 = *reinterpret_cast<const uint4 *>(p1);
+  uint4 n0 = row_slice<IN>(l, 0, 0), n1 = row_slice<IN>(l, 0, 1);
 #pragma unroll
-  for (int t = 0; t < RPW + 2; ++t) {  // bordered input row y0 + t
+  for (int t = 0; t < RPW + 2; ++t) {  // input row y0 - 1 + t
     const bf16x8 B0 = __builtin_bit_cast(bf16x8, n0), B1 = __builtin_bit_cast(bf16x8, n1);
     if (t + 1 < RPW + 2) {
-      n0 = *reinterpret_cast<const uint4 *>(p0 + (t + 1) * S * CH);
-      if (g < 2) n1 = *reinterpret_cast<const uint4 *>(p1 + (t + 1) * S * CH);
+      n0 = row_slice<IN>(l, t + 1, 0);
+      n1 = row_slice<IN>(l, t + 1, 1);
     }
     // output row u = t - 1 - dy reads this row with the weights of dy
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
       const int u = t - 1 - dy;
       if (u < 0 || u >= RPW) continue;
-      f32x4 c = acc[u % 3];
-      if (dy == -1) c = f32x4{0.f, 0.f, 0.f, 0.f};  // first contribution to row u
+      f32x4 c = dy == -1 ? bias : acc[u % 3];  // bias: first contribution to row u
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2 * (dy + 1)], B0, c, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2 * (dy + 1) + 1], B1, c, 0, 0, 0);
       acc[u % 3] = c;
     }
-    // row u = t - 2 is complete: bias, ReLU, store or pool
+    // row u = t - 2 is complete: ReLU and store, or pool
     if (t >= 2) {
-      const int u = t - 2, y = y0 + u, x = x0 + j;
+      const int u = t - 2;
       const f32x4 c = acc[u % 3];
-      float v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = relu(c[r] + bias[r]);
       if (!LAST) {
-        *reinterpret_cast<uint2 *>(out + ((y + 1) * S + x + 1) * CH + 4 * g) =
-            make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+        *reinterpret_cast<uint2 *>(l.wr + OUT + u * RS32) =
+            make_uint2(relu_bf16x2(pack_bf16(c[0], c[1])), relu_bf16x2(pack_bf16(c[2], c[3])));
       } else {
-        const int gi = y * M + x;
+        const int gi = (y0 + u) * M32 + x;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const bool gt = v[r] > pool.best[r];
-          pool.best[r] = gt ? v[r] : pool.best[r];
+          const bool gt = c[r] > pool.best[r];
+          pool.best[r] = gt ? c[r] : pool.best[r];
           pool.idx[r] = gt ? gi : pool.idx[r];
           // update the pooling state here, not after the loop (which would
           // keep every row's accumulators alive)
@@ -351,48 +401,41 @@ __device__ __forceinline__ void conv_rows32(const uint16_t *__restrict__ in, uin
 }
 
 // Layer 1 (one input channel) of a whole 32 x 32 map, streamed by rows as
-// conv_rows32: wave w computes columns x0 = 16 (w & 1) of output rows
-// y0 .. y0 + 7, y0 = 8 (w >> 1).  T[R][c] (R = 0..33 bordered rows, c =
-// 0..31) holds the inputs at bordered columns c, c + 1, c + 2 of row R as
-// four bfloat16 (the last zero).  A lane keeps the triplets of the last
-// three rows and assembles the 3 x 3 window of its output position as K =
-// tap = 3 (dy + 1) + (dx + 1): K 0..7 in lane group 0, K 8 in group 1 (the
-// operand layout of the layer-1 block of Aop), so one instruction per
-// output row and position group.
-__device__ __forceinline__ void conv1_rows32(const uint2 *__restrict__ T, uint16_t *__restrict__ out,
-                                             const bf16x8 &A1, const float *__restrict__ b) {
-  constexpr int M = 32, S = M + 2, RPW = 8;
+// conv_rows32, into the first buffer.  T[R][c] (R = 0..33 rows y = R - 1
+// mod 32, c = 0..31) holds the inputs at columns c - 1, c, c + 1 (mod 32)
+// of that row as four bfloat16 (the last zero).  A lane keeps the triplets
+// of the last three rows and assembles the 3 x 3 window of its output
+// position as K = tap = 3 (dy + 1) + (dx + 1): K 0..7 in lane group 0, K 8
+// in group 1 (the operand layout of the layer-1 block of Aop), so one
+// instruction per output row and position group; the bias is its
+// accumulator.  Each 32-bit word of the K slice is one byte permutation of
+// two triplet words, with per-lane selectors (byte code 12 gives a zero
+// byte: the words a lane group does not hold).
+__device__ __forceinline__ void conv1_rows32(const uint2 *__restrict__ T, const Lane32 &l, const bf16x8 &A1,
+                                             const f32x4 &bias) {
+  constexpr int RPW = 8;
+  constexpr uint32_t Z = 0x0C0C0C0Cu;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int x0 = (wave & 1) * 16, y0 = (wave >> 1) * RPW;
-  float bias[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) bias[r] = b[4 * g + r];
-  const uint2 *p = T + y0 * M + x0 + j;
-  uint2 r0 = make_uint2(0u, 0u), r1 = r0, r2 = r0;  // triplets of rows t - 2, t - 1, t
-  if (g < 2) {
-    r1 = p[0];
-    r2 = p[M];
-  }
+  // __builtin_amdgcn_perm(hi, lo, sel): byte codes 0..3 pick lo's bytes, 4..7 hi's
+  const uint32_t sx = g == 0 ? 0x07060504u : g == 1 ? 0x0C0C0100u : Z;  // r0.x | r2.y low half
+  const uint32_t sy = g == 0 ? 0x05040100u : Z;                        // r0.y low half, r1.x low half
+  const uint32_t sz = g == 0 ? 0x05040302u : Z;                        // r1.x high half, r1.y low half
+  const uint32_t sw = g == 0 ? 0x03020100u : Z;                        // r2.x
+  const uint2 *p = T + y0 * M32 + x0 + j;
+  uint2 r0, r1 = p[0], r2 = p[M32];  // triplets of rows t - 2, t - 1, t
 #pragma unroll
   for (int t = 2; t < RPW + 2; ++t) {
     r0 = r1;
     r1 = r2;
-    if (g < 2) r2 = p[t * M];
+    r2 = p[t * M32];
     // window of output row y0 + t - 2: rows r0 (dy = -1), r1 (0), r2 (+1)
-    uint4 k = make_uint4(0u, 0u, 0u, 0u);
-    if (g == 0)
-      k = make_uint4(r0.x, (r0.y & 0xFFFFu) | (r1.x << 16), (r1.x >> 16) | (r1.y << 16), r2.x);
-    else if (g == 1)
-      k.x = r2.y & 0xFFFFu;
-    const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, __builtin_bit_cast(bf16x8, k),
-                                                           f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    const int y = y0 + t - 2, x = x0 + j;
-    float v[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = relu(c[r] + bias[r]);
-    *reinterpret_cast<uint2 *>(out + ((y + 1) * S + x + 1) * CH + 4 * g) =
-        make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+    const uint4 k = make_uint4(__builtin_amdgcn_perm(r0.x, r2.y, sx), __builtin_amdgcn_perm(r1.x, r0.y, sy),
+                               __builtin_amdgcn_perm(r1.y, r1.x, sz), __builtin_amdgcn_perm(r2.x, r2.x, sw));
+    const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, __builtin_bit_cast(bf16x8, k), bias, 0, 0, 0);
+    *reinterpret_cast<uint2 *>(l.wr + (t - 2) * RS32) =
+        make_uint2(relu_bf16x2(pack_bf16(c[0], c[1])), relu_bf16x2(pack_bf16(c[2], c[3])));
   }
 }
 
@@ -492,6 +535,15 @@ __device__ __forceinline__ void store_interior(const uint16_t *src, uint16_t *ds
   for (int i = threadIdx.x; i < 2 * M * M; i += blockDim.x) {
     const int pos = i >> 1, y = pos / M, x = pos - y * M;
     d[i] = s[((y + 1) * (M + 2) + x + 1) * 2 + (i & 1)];
+  }
+}
+
+// A [32][33][16] buffer's 32 x 32 positions to [M*M][16] in HBM.
+__device__ __forceinline__ void store_rows32(const uint16_t *src, uint16_t *dst) {
+  uint4 *d = reinterpret_cast<uint4 *>(dst);
+  for (int i = threadIdx.x; i < 2 * M32 * M32; i += blockDim.x) {
+    const int pos = i >> 1, y = pos / M32, x = pos - y * M32;
+    d[i] = reinterpret_cast<const uint4 *>(src + y * RS32 + x * CH)[i & 1];
   }
 }
 
@@ -617,34 +669,43 @@ __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4)
 
 // Whole 32 x 32 maps (L = 256): one workgroup of 8 waves per map, two
 // workgroups per CU, a fixed grid walking the maps.  Every layer is
-// streamed by rows (conv1_rows32, conv_rows32); the wrapped borders are
-// refreshed after each layer.  The next map's counts are fetched into registers while the
-// current map's last layer runs.  LDS: A, B [34^2][16] bfloat16 (layer 1's
-// tap triplets and the staged counts live in B until layer 2 writes it) |
+// streamed by rows (conv1_rows32, conv_rows32) over [32][33][16] buffers
+// that wrap by address.  The next map's counts are fetched into registers
+// while the current map's last layer runs.  LDS: A, B [32][33][16]
+// bfloat16 (layer 1's tap triplets and the staged counts live in B until
+// layer 2 writes it; B's zero column is cleared again after layer 1) |
 // per-wave pooling keys.
 __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4))) void k_cnn_forward32(FwdArgs a) {
-  constexpr int M = 32, S = M + 2, SS = S * S;
+  constexpr int M = M32, S = M + 2;
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t *bufA = reinterpret_cast<uint16_t *>(smem);
-  uint16_t *bufB = bufA + SS * CH;
+  uint16_t *bufB = bufA + BUF32;
   uint2 *T = reinterpret_cast<uint2 *>(bufB);                        // [34][32] layer-1 tap triplets
   uint16_t *stage = reinterpret_cast<uint16_t *>(T + S * M);         // [M*M/2] staged counts (2 per entry)
-  unsigned long long *pool_keys = reinterpret_cast<unsigned long long *>(bufB + SS * CH);  // [NW][16]
+  unsigned long long *pool_keys = reinterpret_cast<unsigned long long *>(bufB + BUF32);  // [NW][16]
   __shared__ float feat_s[CH];
   __shared__ float bias_s[4 * CH];
   __shared__ float head_s[CH + 1];
   const float *P = a.params;
   load_biases(P, bias_s);
   if (threadIdx.x <= CH) head_s[threadIdx.x] = P[OFF_WL + threadIdx.x];  // Wl[16], then bl
+  zero_column32(bufA);  // B's is cleared per map, after its tap triplets are used
   const int lane = threadIdx.x & 63;
+  const Lane32 l = lane32(bufA);
   const size_t act = (size_t)M * M * CH;
   // this thread's two counts of the first map (M*M/2 = THREADS_WRAP pairs)
   uint16_t nxt = 0;
   if ((int64_t)blockIdx.x < a.n) nxt = reinterpret_cast<const uint16_t *>(a.counts + blockIdx.x * M * M)[threadIdx.x];
+  __syncthreads();  // biases
+  f32x4 bias[4];  // per layer: this lane's four output channels
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    bias[k] = f32x4{bias_s[k * CH + 4 * (lane >> 4)], bias_s[k * CH + 4 * (lane >> 4) + 1],
+                    bias_s[k * CH + 4 * (lane >> 4) + 2], bias_s[k * CH + 4 * (lane >> 4) + 3]};
   for (int64_t s = blockIdx.x; s < a.n; s += gridDim.x) {
     stage[threadIdx.x] = nxt;
     __syncthreads();
-    {  // tap triplets of layer 1: T[R][c] = x at bordered columns c .. c + 2 of bordered row R
+    {  // tap triplets of layer 1: T[R][c] = x at columns c - 1 .. c + 1 of row R - 1 (mod M)
       const uint8_t *cs = reinterpret_cast<const uint8_t *>(stage);
       for (int i = threadIdx.x; i < S * M; i += blockDim.x) {
         const int R = i / M, c = i - R * M, y = (R + M - 1) % M;
@@ -661,28 +722,22 @@ __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4)
     asm volatile("" : "+s"(Aop));
     const uint4 *Arow = Aop + AOP_UINT4;
     LayerRow Wr;
-    conv1_rows32(T, bufA, __builtin_bit_cast(bf16x8, Aop[lane]), bias_s);
-    Pool pool;
-    pool_init(pool);
+    conv1_rows32(T, l, __builtin_bit_cast(bf16x8, Aop[lane]), bias[0]);
+    Pool pool;  // set by the last layer
     load_layer_rows(Arow, 1, Wr);
     __syncthreads();
-    fill_border(bufA, M);
-    if (a.store) store_interior(bufA, a.store + (size_t)s * act, M);
-    __syncthreads();
-    conv_rows32<false>(bufA, bufB, Wr.A, bias_s + CH, pool);
+    zero_column32(bufB);  // read first by layer 3, after the next barrier
+    if (a.store) store_rows32(bufA, a.store + (size_t)s * act);
+    conv_rows32<false, 0, BUF32>(l, Wr.A, bias[1], pool);
     load_layer_rows(Arow, 2, Wr);
     __syncthreads();
-    fill_border(bufB, M);
-    if (a.store) store_interior(bufB, a.store + ((size_t)a.n + s) * act, M);
-    __syncthreads();
-    conv_rows32<false>(bufB, bufA, Wr.A, bias_s + 2 * CH, pool);
+    if (a.store) store_rows32(bufB, a.store + ((size_t)a.n + s) * act);
+    conv_rows32<false, BUF32, 0>(l, Wr.A, bias[2], pool);
     load_layer_rows(Arow, 3, Wr);
     __syncthreads();
-    fill_border(bufA, M);
-    if (a.store) store_interior(bufA, a.store + ((size_t)2 * a.n + s) * act, M);
-    __syncthreads();
+    if (a.store) store_rows32(bufA, a.store + ((size_t)2 * a.n + s) * act);
     if (s + gridDim.x < a.n) nxt = reinterpret_cast<const uint16_t *>(a.counts + (s + gridDim.x) * M * M)[threadIdx.x];
-    conv_rows32<true>(bufA, nullptr, Wr.A, bias_s + 3 * CH, pool);
+    conv_rows32<true, 0, 0>(l, Wr.A, bias[3], pool);
     float best;
     int bi;
     pool_keys_reduce(pool, pool_keys, best, bi);
@@ -1029,8 +1084,8 @@ size_t wrap_lds(int M, int threads) {
   const size_t SS = (size_t)(M + 2) * (M + 2);
   return ((SS + 7) & ~(size_t)7) * 2 + 2 * SS * CH * 2 + (size_t)(threads / 64) * CH * 8;
 }
-size_t fwd32_lds() {  // A, B [34^2][16] bfloat16, per-wave pooling results
-  return (size_t)2 * 34 * 34 * CH * 2 + (size_t)(THREADS_WRAP / 64) * CH * 8;
+size_t fwd32_lds() {  // A, B [32][33][16] bfloat16, per-wave pooling results
+  return (size_t)2 * BUF32 * 2 + (size_t)(THREADS_WRAP / 64) * CH * 8;
 }
 size_t tile_lds(int threads) {
   constexpr size_t R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4;
