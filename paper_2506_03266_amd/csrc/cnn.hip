@@ -18,6 +18,9 @@
 // Precision: conv weights and the activations of layers 1-3 are bfloat16
 // (round to nearest even); products accumulate in float32 on the matrix
 // cores; biases, layer-4 activations, the pooling and the head are float32.
+// Only non-finite parameters make NaN activations: the 32 x 32 kernel's ReLU
+// (on the bfloat16 bit pattern) passes them on and its pooling skips them,
+// the other kernels' ReLU zeroes them; no decode result depends on either.
 //
 // Forward: positions form the N dimension of v_mfma_f32_16x16x32_bf16 (16
 // positions per instruction), output channels the M dimension and (tap,
