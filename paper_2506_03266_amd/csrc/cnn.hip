@@ -18,9 +18,9 @@
 // Precision: conv weights and the activations of layers 1-3 are bfloat16
 // (round to nearest even); products accumulate in float32 on the matrix
 // cores; biases, layer-4 activations, the pooling and the head are float32.
-// Only non-finite parameters make NaN activations: the 32 x 32 kernel's ReLU
-// (on the bfloat16 bit pattern) passes them on and its pooling skips them,
-// the other kernels' ReLU zeroes them; no decode result depends on either.
+// Only non-finite parameters make NaN activations: the row-streamed kernels'
+// ReLU (on the bfloat16 bit pattern) passes them on, the whole-map kernel of
+// maps below 32 x 32 zeroes them; no decode result depends on either.
 //
 // Forward: positions form the N dimension of v_mfma_f32_16x16x32_bf16 (16
 // positions per instruction), output channels the M dimension and (tap,
@@ -28,10 +28,10 @@
 // instruction, five instructions per 3x3 layer).  Activations live in LDS as
 // [position][16 channels] bfloat16, so a lane's K slice is one 16-byte read
 // and its result (4 channels of one position) one 8-byte write.  Maps up to
-// 32 x 32 are processed whole by one workgroup with wrapped indexing; wider
-// maps in 32 x 32 output tiles with a 4-position halo (valid convolutions
-// shrinking the region by one position per layer and side), the per-channel
-// maxima meeting in a 64-bit atomic max.
+// 32 x 32 are processed whole by one workgroup with wrapped indexing (32 x
+// 32 maps streamed by rows); wider maps in 32 x 32 output tiles from frames
+// with a 4-position halo, also streamed by rows, the per-channel maxima
+// meeting in a 64-bit atomic max.
 //
 // Backward (training, maps up to 32 x 32): the global max routes each
 // channel's gradient to a single layer-4 position, so the gradient of a
@@ -66,7 +66,7 @@ constexpr int NPARAM = MPD_CNN_PARAMS;
 constexpr uint32_t INIT_TAG = 0x636E6E31u;  // second counter word of the initializer
 constexpr int WRAP_MAX = 32;                // largest map held whole by one workgroup
 constexpr int TILE = 32;                    // output tile of wider maps
-constexpr int THREADS_WRAP = 512, THREADS_TILE = 1024;
+constexpr int THREADS_WRAP = 512;
 constexpr int BWD_THREADS = 256;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -758,50 +758,202 @@ __global__ __launch_bounds__(THREADS_WRAP) __attribute__((amdgpu_waves_per_eu(4)
   }
 }
 
-// 32 x 32 output tiles; each layer shrinks the region by one position per
-// side.  LDS: x [40^2] | A [38^2][16] | B [36^2][16] | pooling.
-__global__ __launch_bounds__(THREADS_TILE) void k_cnn_forward_tile(FwdArgs a) {
+// Wider maps (M > 32), row-streamed like k_cnn_forward32: 32 x 32 output
+// tiles, each from a frame of map rows ty0 - 5 .. ty0 + 36 and columns
+// tx0 - 4 .. tx0 + 45 (wrapping mod M).  12 waves: three 16-column groups x
+// four bands of 10 rows.  Layers 1-3 compute frame rows 0..39 and columns
+// 1..48 into [42 rows][51 columns][16] buffers (row index = frame row + 1;
+// column 50 stays zero for the lanes with no second K block); layer 4
+// computes frame rows and columns 4..35 (8 waves: two column groups x four
+// bands of 8 rows).  Outputs a layer computes outside its valid region
+// (layer 1: all of its rows and columns, layer l >= 2: frame rows l - 1 ..
+// 40 - l, columns l .. 49 - l) read buffer rows or columns nobody wrote; they
+// only feed outputs that are outside the valid region too, so layer 4's
+// outputs are those of the whole map at the tile's positions.
+constexpr int RT_NW = 12;                 // waves per workgroup
+constexpr int RT_BR = 10;                 // output rows per wave (layers 1-3)
+constexpr int RT_COLS = 51;               // activation columns: frame columns 0..49, zero column 50
+constexpr int RT_Z = 50;                  // the zero column
+constexpr int RT_RS = RT_COLS * CH;       // row stride in bfloat16
+constexpr int RT_ROWS = TILE + 10;        // activation rows: frame rows -1..40
+constexpr int RT_BUF = RT_ROWS * RT_RS;   // one buffer, in bfloat16
+constexpr int RT_TC = 48;                 // tap-triplet columns (frame columns 1..48)
+constexpr int RT_XC = RT_TC + 2;          // staged count columns (frame columns 0..49)
+
+size_t rtile_lds() {  // A, B, per-wave pooling results (floats and indices)
+  return (size_t)2 * RT_BUF * 2 + (size_t)RT_NW * CH * 8;
+}
+
+// Zero column of one [RT_ROWS][RT_COLS][16] buffer.
+__device__ __forceinline__ void zero_column_rt(uint16_t *buf) {
+  for (int i = threadIdx.x; i < 2 * RT_ROWS; i += blockDim.x)
+    reinterpret_cast<uint4 *>(buf + (i >> 1) * RT_RS + RT_Z * CH)[i & 1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// One row-streamed 16 -> 16 layer over NR output rows of one wave (see
+// conv_rows32).  rd[b]: the lane's K slice of block b in the input row above
+// its first output row; wr: its output (4 channels) in its first output
+// row.  LAST folds the outputs into the pooling state instead: the output
+// in row u is at map position ((my0 + u) mod M, mx).
+template <int NR, bool LAST>
+__device__ __forceinline__ void conv_rows_rt(const uint16_t *rd0, const uint16_t *rd1, uint16_t *wr,
+                                             const bf16x8 *A, const f32x4 &bias, Pool &pool, int my0, int mx,
+                                             int M) {
+  f32x4 acc[3];
+  uint4 n0 = *reinterpret_cast<const uint4 *>(rd0), n1 = *reinterpret_cast<const uint4 *>(rd1);
+  int my = my0;
+#pragma unroll
+  for (int t = 0; t < NR + 2; ++t) {  // input row t - 1 relative to the first output row
+    const bf16x8 B0 = __builtin_bit_cast(bf16x8, n0), B1 = __builtin_bit_cast(bf16x8, n1);
+    if (t + 1 < NR + 2) {
+      n0 = *reinterpret_cast<const uint4 *>(rd0 + (t + 1) * RT_RS);
+      n1 = *reinterpret_cast<const uint4 *>(rd1 + (t + 1) * RT_RS);
+    }
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int u = t - 1 - dy;
+      if (u < 0 || u >= NR) continue;
+      f32x4 c = dy == -1 ? bias : acc[u % 3];  // bias: first contribution to row u
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2 * (dy + 1)], B0, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2 * (dy + 1) + 1], B1, c, 0, 0, 0);
+      acc[u % 3] = c;
+    }
+    if (t >= 2) {
+      const int u = t - 2;
+      const f32x4 c = acc[u % 3];
+      if (!LAST) {
+        *reinterpret_cast<uint2 *>(wr + u * RT_RS) =
+            make_uint2(relu_bf16x2(pack_bf16(c[0], c[1])), relu_bf16x2(pack_bf16(c[2], c[3])));
+      } else {
+        const int gi = my * M + mx;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          keep_max(relu(c[r]), gi, pool.best[r], pool.idx[r]);
+          asm volatile("" : "+v"(pool.best[r]), "+v"(pool.idx[r]));
+        }
+        my = my + 1 == M ? 0 : my + 1;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads one row ahead, not all hoisted
+  }
+}
+
+__global__ __launch_bounds__(RT_NW * 64) void k_cnn_forward_rtile(FwdArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4, R3 = TILE + 2;
   const int M = a.M;
-  uint16_t *xin = reinterpret_cast<uint16_t *>(smem);
-  uint16_t *bufA = xin + R0 * R0;
-  uint16_t *bufB = bufA + R1 * R1 * CH;
-  float *red_v = reinterpret_cast<float *>(bufB + R2 * R2 * CH);
-  int *red_i = reinterpret_cast<int *>(red_v + (blockDim.x >> 6) * CH);
+  uint16_t *bufA = reinterpret_cast<uint16_t *>(smem);
+  uint16_t *bufB = bufA + RT_BUF;
+  uint2 *T = reinterpret_cast<uint2 *>(bufB);                         // [RT_ROWS][RT_TC] layer-1 tap triplets
+  uint8_t *xs = reinterpret_cast<uint8_t *>(T + RT_ROWS * RT_TC);     // [RT_ROWS][RT_XC] staged counts
+  float *red_v = reinterpret_cast<float *>(bufB + RT_BUF);
+  int *red_i = reinterpret_cast<int *>(red_v + RT_NW * CH);
   __shared__ float bias_s[4 * CH];
   load_biases(a.params, bias_s);
-  LayerA Wc, Wn;  // current and next layer's operands
-  load_layer(a.Aop, 0, Wc);
+  zero_column_rt(bufA);  // B's is cleared per item, after its tap triplets are used
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = lane & 15, g = lane >> 4;
+  // layers 1-3: column group gc, rows RT_BR b .. RT_BR b + RT_BR - 1 (frame)
+  const int gc = wave % 3, b = wave / 3;
+  const int fc = 1 + 16 * gc + j, fr0 = RT_BR * b;
+  const int c0 = fc - 1 + (g >> 1), c1 = g < 2 ? fc + 1 : RT_Z;
+  const int rdo0 = fr0 * RT_RS + c0 * CH + 8 * (g & 1), rdo1 = fr0 * RT_RS + c1 * CH + 8 * (g & 1);
+  const int wro = (fr0 + 1) * RT_RS + fc * CH + 4 * g;
+  __syncthreads();  // biases
+  // this lane's four output channels of layer l's bias (read per layer: few registers stay live)
+  auto bias = [&](int l) { return *reinterpret_cast<const f32x4 *>(bias_s + l * CH + 4 * g); };
   const int nt = a.ntile;
-  // a fixed grid walks the (sample, tile) items: weights stay in registers
-  for (int64_t it = blockIdx.x; it < a.n * nt * nt; it += gridDim.x) {
+  const int64_t items = a.n * nt * nt;
+  const uint4 *Arow = a.Aop + AOP_UINT4;
+  // This thread's counts of an item's frame (rows -1..40, i.e. map rows
+  // ty0 - 5 .., and columns 0..49): entries threadIdx.x + k blockDim.x.
+  // The next item's are fetched while the current one's last layer runs.
+  constexpr int XPT = (RT_ROWS * RT_XC + RT_NW * 64 - 1) / (RT_NW * 64);
+  uint8_t pre[XPT];
+  auto fetch = [&](int64_t item) {
+    const int tt = (int)(item % (nt * nt));
+    const int ty0 = (tt / nt) * TILE, tx0 = (tt % nt) * TILE;
+    const uint8_t *cnt = a.counts + (item / (nt * nt)) * M * M;
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int i = threadIdx.x + k * RT_NW * 64;
+      if (i < RT_ROWS * RT_XC) {
+        const int R = i / RT_XC, C = i - R * RT_XC;
+        int y = ty0 - 5 + R, x = tx0 - 4 + C;  // in [-5, M + 45): at most two wraps for M >= 34
+        y += y < 0 ? M : 0;
+        x += x < 0 ? M : 0;
+        y -= y >= M ? M : 0;
+        x -= x >= M ? M : 0;
+        y -= y >= M ? M : 0;
+        x -= x >= M ? M : 0;
+        pre[k] = cnt[y * M + x];
+      }
+    }
+  };
+  if ((int64_t)blockIdx.x < items) fetch(blockIdx.x);
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
     const int64_t s = it / (nt * nt);
     const int t = (int)(it % (nt * nt));
     const int ty0 = (t / nt) * TILE, tx0 = (t % nt) * TILE;
-    const uint8_t *cnt = a.counts + s * M * M;
-    for (int i = threadIdx.x; i < R0 * R0; i += blockDim.x) {
-      const int y = (ty0 - 4 + i / R0 + M) % M, x = (tx0 - 4 + i % R0 + M) % M;
-      xin[i] = to_bf16((float)cnt[y * M + x] * 0.125f);
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int i = threadIdx.x + k * RT_NW * 64;
+      if (i < RT_ROWS * RT_XC) xs[i] = pre[k];
     }
     __syncthreads();
+    // tap triplets: T[R][k] = x at frame columns k, k + 1, k + 2 of frame row R - 1
+    for (int i = threadIdx.x; i < RT_ROWS * RT_TC; i += blockDim.x) {
+      const int R = i / RT_TC, k = i - R * RT_TC;
+      const uint8_t *q = xs + R * RT_XC + k;
+      T[i] = make_uint2(pack_bf16((float)q[0] * 0.125f, (float)q[1] * 0.125f), pack_bf16((float)q[2] * 0.125f, 0.f));
+    }
+    __syncthreads();
+    {  // layer 1: output rows fr0 .. fr0 + RT_BR - 1, column fc; K = tap as in conv1_rows32
+      constexpr uint32_t Z = 0x0C0C0C0Cu;
+      const uint32_t sx = g == 0 ? 0x07060504u : g == 1 ? 0x0C0C0100u : Z;
+      const uint32_t sy = g == 0 ? 0x05040100u : Z;
+      const uint32_t sz = g == 0 ? 0x05040302u : Z;
+      const uint32_t sw = g == 0 ? 0x03020100u : Z;
+      const bf16x8 A1 = __builtin_bit_cast(bf16x8, a.Aop[lane]);
+      const uint2 *p = T + fr0 * RT_TC + fc - 1;
+      uint16_t *w1 = bufA + wro;
+      uint2 r0, r1 = p[0], r2 = p[RT_TC];
+#pragma unroll
+      for (int tt = 2; tt < RT_BR + 2; ++tt) {
+        r0 = r1;
+        r1 = r2;
+        r2 = p[tt * RT_TC];
+        const uint4 k = make_uint4(__builtin_amdgcn_perm(r0.x, r2.y, sx), __builtin_amdgcn_perm(r1.x, r0.y, sy),
+                                   __builtin_amdgcn_perm(r1.y, r1.x, sz), __builtin_amdgcn_perm(r2.x, r2.x, sw));
+        const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, __builtin_bit_cast(bf16x8, k), bias(0), 0, 0, 0);
+        *reinterpret_cast<uint2 *>(w1 + (tt - 2) * RT_RS) =
+            make_uint2(relu_bf16x2(pack_bf16(c[0], c[1])), relu_bf16x2(pack_bf16(c[2], c[3])));
+      }
+    }
+    LayerRow Wr;
+    load_layer_rows(Arow, 1, Wr);
     Pool pool;
     pool_init(pool);
-    load_layer(a.Aop, 1, Wn);
-    conv_layer<true, false>(xin, bufA, CtGeom<R0, R1, R1, 0>{}, Wc.A, bias_s, M, 0, 0, pool);
-    Wc = Wn;
-    load_layer(a.Aop, 2, Wn);
     __syncthreads();
-    conv_layer<false, false>(bufA, bufB, CtGeom<R1, R2, R2, 0>{}, Wc.A, bias_s + CH, M, 0, 0, pool);
-    Wc = Wn;
-    load_layer(a.Aop, 3, Wn);
+    zero_column_rt(bufB);  // read first by layer 3, after the next barrier
+    conv_rows_rt<RT_BR, false>(bufA + rdo0, bufA + rdo1, bufB + wro, Wr.A, bias(1), pool, 0, 0, M);
+    load_layer_rows(Arow, 2, Wr);
     __syncthreads();
-    conv_layer<false, false>(bufB, bufA, CtGeom<R2, R3, R3, 0>{}, Wc.A, bias_s + 2 * CH, M, 0, 0, pool);
-    Wc = Wn;
-    load_layer(a.Aop, 0, Wn);
+    conv_rows_rt<RT_BR, false>(bufB + rdo0, bufB + rdo1, bufA + wro, Wr.A, bias(2), pool, 0, 0, M);
+    load_layer_rows(Arow, 3, Wr);
     __syncthreads();
-    conv_layer<false, true>(bufA, nullptr, CtGeom<R3, TILE, 0, 0>{}, Wc.A, bias_s + 3 * CH, M, ty0, tx0, pool);
-    Wc = Wn;
+    if (it + gridDim.x < items) fetch(it + gridDim.x);  // after the last weight load: no wait on it before
+    if (wave < 8) {  // layer 4: column group gc4, rows 4 + 8 b4 .. 11 + 8 b4 (frame)
+      const int gc4 = wave & 1, b4 = wave >> 1;
+      const int fc4 = 4 + 16 * gc4 + j, fr4 = 4 + 8 * b4;
+      const int c04 = fc4 - 1 + (g >> 1), c14 = g < 2 ? fc4 + 1 : RT_Z;
+      const int rd4o0 = fr4 * RT_RS + c04 * CH + 8 * (g & 1), rd4o1 = fr4 * RT_RS + c14 * CH + 8 * (g & 1);
+      int my0 = ty0 - 4 + fr4, mx = tx0 - 4 + fc4;  // in [0, M + 36): at most two wraps
+      my0 -= my0 >= M ? M : 0;
+      mx -= mx >= M ? M : 0;
+      my0 -= my0 >= M ? M : 0;
+      mx -= mx >= M ? M : 0;
+      conv_rows_rt<8, true>(bufA + rd4o0, bufA + rd4o1, nullptr, Wr.A, bias(3), pool, my0, mx, M);
+    }
     float best;
     int bi;
     pool_reduce(pool, red_v, red_i, best, bi);
@@ -1090,10 +1242,6 @@ size_t wrap_lds(int M, int threads) {
 size_t fwd32_lds() {  // A, B [32][33][16] bfloat16, per-wave pooling results
   return (size_t)2 * BUF32 * 2 + (size_t)(THREADS_WRAP / 64) * CH * 8;
 }
-size_t tile_lds(int threads) {
-  constexpr size_t R0 = TILE + 8, R1 = TILE + 6, R2 = TILE + 4;
-  return R0 * R0 * 2 + (R1 * R1 + R2 * R2) * CH * 2 + (size_t)(threads / 64) * CH * 8;
-}
 
 // Workspace of the training step: stored activations, feat, argmax, pred,
 // per-sample gradients.
@@ -1172,7 +1320,7 @@ int cnn_forward_run(const uint8_t *counts, int M, int64_t n, const float *params
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, a.pool, cnt);
   HIP_TRY(hipGetLastError());
   const unsigned tgrid = (unsigned)std::min<int64_t>(n * a.ntile * a.ntile, cu_count());
-  hipLaunchKernelGGL(k_cnn_forward_tile, dim3(tgrid), dim3(THREADS_TILE), tile_lds(THREADS_TILE), stream, a);
+  hipLaunchKernelGGL(k_cnn_forward_rtile, dim3(tgrid), dim3(RT_NW * 64), rtile_lds(), stream, a);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_cnn_head, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   HIP_TRY(hipGetLastError());
