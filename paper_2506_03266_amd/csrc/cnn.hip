@@ -153,10 +153,10 @@ __device__ __forceinline__ int row_of(int p, int R) {
 
 // Running maximum with the lowest index on ties.
 __device__ __forceinline__ void keep_max(float v, int i, float &best, int &bi) {
-  if (v > best || (v == best && i < bi)) {
-    best = v;
-    bi = i;
-  }
+  // both comparisons evaluated (no short circuit): selects instead of a branch per value
+  const bool take = (v > best) | ((v == best) & (i < bi));
+  best = take ? v : best;
+  bi = take ? i : bi;
 }
 
 struct Pool {
