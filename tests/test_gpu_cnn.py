@@ -109,6 +109,22 @@ def test_forward_translation_invariance(gpu):
     assert np.allclose(got, base, rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("M", [64, 34])
+def test_forward_translation_invariance_tiled(gpu, M):
+    """Wider maps run in 32 x 32 tiles from frames with a halo: a circular
+    shift moves content across tile edges and the wrap seam (ragged at
+    M = 34, where the last tile wraps onto the first), yet every position's
+    value is computed from the same neighbourhood in the same order, so
+    the predictions agree to float32 rounding."""
+    counts = realistic_counts(11 + M, 3, M)
+    params = torch.from_numpy(trained_like_params(5)).cuda()
+    base = gpu.cnn_forward(torch.from_numpy(counts).cuda(), params).cpu().numpy()
+    for dy, dx in ((5, 11), (17, 3), (M - 1, 29)):
+        sh = np.ascontiguousarray(np.roll(counts, (dy, dx), axis=(1, 2)))
+        got = gpu.cnn_forward(torch.from_numpy(sh).cuda(), params).cpu().numpy()
+        assert np.allclose(got, base, rtol=1e-5, atol=1e-5), (dy, dx, got, base)
+
+
 @pytest.mark.parametrize("M,n", [(32, 16), (8, 32), (8, 21)])
 def test_gradient_matches_oracle(gpu, M, n):
     counts = realistic_counts(M + 1, n, M)
